@@ -1,0 +1,160 @@
+"""Stochastic Lanczos quadrature (Sec. III, Algorithm 1) and its error bar
+(Sec. VIII).
+
+Oracle, test infrastructure only.
+
+Steps, in Algorithm 1's order and notation, per probe n:
+  phi <- random probe;  beta_1 = ||phi||;  phi_0 = 0;  phi_1 = phi / beta_1
+  for k = 1..K_max:
+      v       = X phi_k - beta_k phi_{k-1}
+      alpha_k = Re <phi_k | v>          (the operator is Hermitian)
+      v       = v - alpha_k phi_k
+      [optional: full reorthogonalisation against phi_1..phi_k, twice]
+      beta_{k+1} = ||v||
+      phi_{k+1}  = v / beta_{k+1}
+      T_k = tridiag(alpha_1..alpha_k; beta_2..beta_k)
+      (theta_j, w_j) = eig(T_k);  tau_j = <e_1|w_j>
+      F_k = sum_j tau_j^2 f(theta_j)
+  G_n = ||phi||^2 F_m
+then mean, standard error sqrt(Var/N), and E = log2(mean G).
+
+Readings where the paper is silent (each also listed in the design notes):
+  * Algorithm 1's F_k estimates <phi_1|f|phi_1> for the *normalised* start
+    vector; Hutchinson's sum needs <phi|f|phi>, hence the factor
+    beta_1^2 = ||phi||^2 in G_n.
+  * lanczos_estimate is F_m after a fixed number m of steps (no early exit).
+  * Breakdown: a probe stops when beta_{k+1} <= 1e-12 * s_k with
+    s_k = max_{i<=k} |alpha_i| + max_{2<=i<=k} beta_i; the quadrature of
+    T_k is then exact and later F values repeat F_k.
+  * Reorthogonalisation (when asked for) is classical Gram-Schmidt applied
+    twice against every earlier Lanczos vector of the same probe.
+  * Error on the mean uses the sample variance with N-1 in the denominator;
+    the error of E follows by the delta method, dE = SE / (mean * ln 2).
+"""
+from __future__ import annotations
+
+from typing import Callable, Dict, Optional
+
+import numpy as np
+import scipy.linalg
+
+from . import exact, probes
+
+BREAKDOWN_TOL = 1e-12
+
+
+def lanczos(matvec: Callable[[np.ndarray], np.ndarray], phi: np.ndarray, m: int,
+            reorth: bool = False):
+    """Lanczos recurrence of Algorithm 1 for one probe.
+
+    Returns (alpha[m], beta[m+1], steps): beta[0] = beta_1 = ||phi||,
+    beta[k] = beta_{k+1}; entries past a breakdown are zero.
+    """
+    phi = np.asarray(phi, dtype=np.complex128)
+    alpha = np.zeros(m)
+    beta = np.zeros(m + 1)
+    beta[0] = np.linalg.norm(phi)
+    q_prev = np.zeros_like(phi)
+    q = phi / beta[0]
+    basis = [q]
+    amax = 0.0
+    bmax = 0.0
+    steps = 0
+    for k in range(m):
+        v = matvec(q) - beta[k] * q_prev if k > 0 else matvec(q)
+        alpha[k] = np.real(np.vdot(q, v))
+        v = v - alpha[k] * q
+        if reorth:
+            Q = np.array(basis)
+            for _ in range(2):
+                v = v - Q.T @ (Q.conj() @ v)
+        beta[k + 1] = np.linalg.norm(v)
+        steps = k + 1
+        amax = max(amax, abs(alpha[k]))
+        if k > 0:
+            bmax = max(bmax, beta[k])
+        if beta[k + 1] <= BREAKDOWN_TOL * (amax + bmax):
+            break
+        q_prev, q = q, v / beta[k + 1]
+        basis.append(q)
+    return alpha, beta, steps
+
+
+def gauss_quadrature(alpha: np.ndarray, beta_off: np.ndarray,
+                     f: Callable[[np.ndarray], np.ndarray] = np.abs) -> float:
+    """F = sum_j tau_j^2 f(theta_j) for T = tridiag(alpha; beta_off)
+    (Algorithm 1, the quadrature block): theta, w from the eigensystem of T,
+    tau_j the first component of w_j."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    if alpha.size == 1:
+        return float(f(alpha)[0])
+    theta, w = scipy.linalg.eigh_tridiagonal(alpha, np.asarray(beta_off, dtype=np.float64))
+    tau = w[0, :]
+    return float(np.sum(tau * tau * f(theta)))
+
+
+def quadrature_trajectory(alpha: np.ndarray, beta: np.ndarray, steps: int,
+                          f: Callable[[np.ndarray], np.ndarray] = np.abs) -> np.ndarray:
+    """[F_1, ..., F_m] for one probe; F_k for k > steps repeats F_steps."""
+    m = alpha.size
+    out = np.zeros(m)
+    for k in range(1, m + 1):
+        kk = min(k, steps)
+        out[k - 1] = gauss_quadrature(alpha[:kk], beta[1:kk], f)
+    return out
+
+
+def hutchinson_stats(G: np.ndarray) -> Dict[str, float]:
+    """Mean, standard error sqrt(Var/N) (Sec. VIII), E = log2(mean) (Eq. 2)
+    and its delta-method error."""
+    G = np.asarray(G, dtype=np.float64)
+    n = G.size
+    mean = float(np.mean(G))
+    se = float(np.std(G, ddof=1) / np.sqrt(n)) if n > 1 else float("nan")
+    e = float(np.log2(mean))
+    de = se / (mean * np.log(2.0)) if n > 1 else float("nan")
+    return {"trace_norm": mean, "trace_norm_se": se, "logneg": e, "logneg_se": de}
+
+
+def slq(matvec: Callable[[np.ndarray], np.ndarray], probe_block: np.ndarray, m: int,
+        reorth: bool = False, f: Callable[[np.ndarray], np.ndarray] = np.abs) -> Dict[str, object]:
+    """Algorithm 1 with fixed N = len(probe_block) and K_max = m."""
+    K, n = probe_block.shape
+    alpha = np.zeros((K, m))
+    beta = np.zeros((K, m + 1))
+    steps = np.zeros(K, dtype=np.int64)
+    F = np.zeros((K, m))
+    G = np.zeros(K)
+    for k in range(K):
+        a, b, s = lanczos(matvec, probe_block[k], m, reorth)
+        alpha[k], beta[k], steps[k] = a, b, s
+        F[k] = quadrature_trajectory(a, b, s, f)
+        G[k] = b[0] ** 2 * F[k, -1]
+    out = {"alpha": alpha, "beta": beta, "steps": steps, "F": F, "G": G}
+    out.update(hutchinson_stats(G))
+    return out
+
+
+def slq_logneg(psi: np.ndarray, n_qubits: int, a, b, n_probes: int, n_steps: int, seed: int,
+               probe_offset: int = 0, reorth: bool = False, matvec: str = "explicit",
+               ) -> Dict[str, object]:
+    """SLQ estimate of log2 Tr|rho_AB^{T_B}| on the seeded probes of ``probes``."""
+    P = exact.regroup(psi, n_qubits, a, b)
+    d_a, d_b, _ = P.shape
+    if matvec == "explicit":
+        R = exact.rho_pt(P)
+        mv = lambda v: R @ v  # noqa: E731
+    else:
+        mv = lambda v: exact.pt_matvec_lazy(P, v[None, :])[0]  # noqa: E731
+    X = probes.rademacher_probes(seed, n_probes, d_a * d_b, probe_offset)
+    return slq(mv, X, n_steps, reorth)
+
+
+def lanczos_block_features(alpha: np.ndarray, beta: np.ndarray, d_a: int, d_b: int, d_e: int,
+                           n_early: int = 8) -> np.ndarray:
+    """The surrogate's 19 inputs: probe means of N*alpha_1..8 and
+    N*beta_2..9 (N = d_A d_B), then log2 d_A, log2 d_B, log2 d_E."""
+    n = float(d_a * d_b)
+    fa = n * np.mean(alpha[:, :n_early], axis=0)
+    fb = n * np.mean(beta[:, 1:n_early + 1], axis=0)
+    return np.concatenate([fa, fb, [np.log2(d_a), np.log2(d_b), np.log2(d_e)]])

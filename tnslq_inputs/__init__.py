@@ -1,0 +1,268 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module holds state and partition generators only: none of the
+logarithmic-negativity arithmetic (regrouping, partial transpose, Lanczos,
+quadrature) lives here.  Both the CPU oracle and the HIP path take their
+inputs from these functions so that they see bit-identical states.
+
+Workloads follow the paper's experiments (Sec. VII):
+  * Haar-random pure states (Sec. VII.A): i.i.d. complex Gaussian amplitudes,
+    normalised in FP64.
+  * A scrambling stand-in for the Heisenberg quench of Sec. VII.B: a brickwork
+    circuit of Haar-random two-qubit gates applied to |0...0>.
+
+Qubit 0 is the most significant bit of the flat amplitude index (the order of
+``numpy.kron``), so a state of L qubits reshaped to ``[2]*L`` has qubit q on
+axis q.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "haar_state",
+    "haar_state_torch",
+    "haar_unitary",
+    "brickwork_gates",
+    "brickwork_state",
+    "brickwork_state_torch",
+    "basis_product_state",
+    "bell_pair_state",
+    "random_contiguous_partition",
+    "Workload",
+    "WORKLOADS",
+]
+
+
+# --------------------------------------------------------------------------
+# Haar-random pure states (Sec. VII.A)
+# --------------------------------------------------------------------------
+def haar_state(n_qubits: int, seed: int, dtype=np.complex128) -> np.ndarray:
+    """Haar-random pure state: Re and Im i.i.d. N(0,1), normalised in FP64.
+
+    The amplitudes are drawn with ``numpy.random.default_rng(seed)``: first all
+    real parts, then all imaginary parts.  Normalisation happens in complex128
+    before any cast to ``dtype``.
+    """
+    n = 1 << n_qubits
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal(n)
+    im = rng.standard_normal(n)
+    psi = re + 1j * im
+    psi /= np.linalg.norm(psi)
+    return psi.astype(dtype, copy=False)
+
+
+def haar_state_torch(n_qubits: int, seed: int, device, dtype=None):
+    """Haar-random pure state generated on a torch device.
+
+    Used for states too large to generate on the host in reasonable time
+    (26 qubits and up).  The generator is torch's, seeded with ``seed``; the
+    values differ from :func:`haar_state` for the same seed.  Normalisation is
+    done in FP64 on the device, then the state is cast to ``dtype``.
+    """
+    import torch
+
+    dtype = dtype or torch.complex64
+    n = 1 << n_qubits
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty(n, dtype=dtype, device=device)
+    real_dtype = torch.float32 if dtype == torch.complex64 else torch.float64
+    view = torch.view_as_real(out)
+    chunk = 1 << 26
+    norm2 = torch.zeros((), dtype=torch.float64, device=device)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        x = torch.randn((e - s, 2), generator=g, device=device, dtype=torch.float64)
+        norm2 += (x * x).sum()
+        view[s:e] = x.to(real_dtype)
+    scale = (1.0 / torch.sqrt(norm2)).to(real_dtype)
+    view.mul_(scale)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Brickwork circuits of Haar two-qubit gates (stand-in for Sec. VII.B)
+# --------------------------------------------------------------------------
+def haar_unitary(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed n x n unitary (Mezzadri 2007: QR of a complex
+    Ginibre matrix with the phases of R's diagonal divided out)."""
+    z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    ph = d / np.abs(d)
+    return q * ph[None, :]
+
+
+def brickwork_gates(n_qubits: int, depth: int, seed: int) -> List[Tuple[int, np.ndarray]]:
+    """Gate list ``[(i, U), ...]`` of a brickwork circuit.
+
+    Layer t = 1..depth acts on pairs (i, i+1) with i = t-1 (mod 2) and
+    i+1 < n_qubits (open boundary).  Gates are drawn from one
+    ``default_rng(seed)`` in (layer, pair) order.  Qubit i is the most
+    significant bit of each 4 x 4 gate's index.
+    """
+    rng = np.random.default_rng(seed)
+    gates = []
+    for t in range(1, depth + 1):
+        for i in range((t - 1) % 2, n_qubits - 1, 2):
+            gates.append((i, haar_unitary(4, rng)))
+    return gates
+
+
+def brickwork_state(n_qubits: int, depth: int, seed: int, dtype=np.complex128) -> np.ndarray:
+    """|0...0> evolved by :func:`brickwork_gates` (host, complex128)."""
+    n = 1 << n_qubits
+    psi = np.zeros(n, dtype=np.complex128)
+    psi[0] = 1.0
+    for i, u in brickwork_gates(n_qubits, depth, seed):
+        v = psi.reshape(1 << i, 4, 1 << (n_qubits - i - 2))
+        psi = np.einsum("ij,ajb->aib", u, v).reshape(n)
+    return psi.astype(dtype, copy=False)
+
+
+def brickwork_state_torch(n_qubits: int, depth: int, seed: int, device, dtype=None):
+    """Same circuit as :func:`brickwork_state`, applied on a torch device.
+
+    The gates are the host-drawn ones from :func:`brickwork_gates`; only the
+    application runs on the device (in complex128, cast at the end).
+    """
+    import torch
+
+    dtype = dtype or torch.complex64
+    n = 1 << n_qubits
+    psi = torch.zeros(n, dtype=torch.complex128, device=device)
+    psi[0] = 1.0
+    for i, u in brickwork_gates(n_qubits, depth, seed):
+        ut = torch.from_numpy(np.ascontiguousarray(u)).to(device)
+        v = psi.view(1 << i, 4, 1 << (n_qubits - i - 2))
+        psi = torch.matmul(ut, v).reshape(n)
+    return psi.to(dtype)
+
+
+# --------------------------------------------------------------------------
+# Small closed-form fixtures
+# --------------------------------------------------------------------------
+def basis_product_state(n_qubits: int, bits: Sequence[int], dtype=np.complex128) -> np.ndarray:
+    """Computational-basis product state |bits>, bits[q] for qubit q."""
+    idx = 0
+    for q in range(n_qubits):
+        idx = (idx << 1) | (int(bits[q]) & 1)
+    psi = np.zeros(1 << n_qubits, dtype=dtype)
+    psi[idx] = 1.0
+    return psi
+
+
+def bell_pair_state(n_qubits: int, i: int, j: int, background_seed: int | None = None,
+                    dtype=np.complex128) -> np.ndarray:
+    """(|00> + |11>)/sqrt(2) on qubits (i, j), every other qubit in a product
+    state: |0> when ``background_seed`` is None, else a seeded random
+    single-qubit state per qubit."""
+    rng = np.random.default_rng(background_seed) if background_seed is not None else None
+    t = np.zeros([2] * n_qubits, dtype=np.complex128)
+    # Build as a tensor product over qubits other than (i, j).
+    others = [q for q in range(n_qubits) if q not in (i, j)]
+    singles = {}
+    for q in others:
+        if rng is None:
+            v = np.array([1.0, 0.0], dtype=np.complex128)
+        else:
+            v = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+            v /= np.linalg.norm(v)
+        singles[q] = v
+    for bit in (0, 1):
+        vec = np.array([1.0], dtype=np.complex128)
+        for q in range(n_qubits):
+            if q == i or q == j:
+                e = np.zeros(2, dtype=np.complex128)
+                e[bit] = 1.0
+                vec = np.kron(vec, e)
+            else:
+                vec = np.kron(vec, singles[q])
+        t += vec.reshape([2] * n_qubits) / np.sqrt(2.0)
+    return t.reshape(-1).astype(dtype, copy=False)
+
+
+# --------------------------------------------------------------------------
+# Partitions
+# --------------------------------------------------------------------------
+def random_contiguous_partition(n_qubits: int, rng: np.random.Generator) -> Tuple[List[int], List[int]]:
+    """Contiguous blocks A then B (|A|, |B| >= 1, gap >= 0) at a random
+    offset, as used for the surrogate's training instances."""
+    while True:
+        na = int(rng.integers(1, n_qubits))
+        nb = int(rng.integers(1, n_qubits))
+        gap = int(rng.integers(0, n_qubits))
+        span = na + gap + nb
+        if span <= n_qubits:
+            break
+    start = int(rng.integers(0, n_qubits - span + 1))
+    a = list(range(start, start + na))
+    b = list(range(start + na + gap, start + na + gap + nb))
+    return a, b
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """A named workload: state recipe, partition and SLQ sizes."""
+    name: str
+    n_qubits: int
+    a: Tuple[int, ...]
+    b: Tuple[int, ...]
+    n_probes: int
+    n_steps: int
+    state: str            # "haar" or "brickwork"
+    dtype: str            # "c64" or "c128"
+    precision: str        # "fp64", "fp32", "bf16x3", "bf16x6"
+    reorth: bool
+    depth: int = 0
+
+    @property
+    def e(self) -> Tuple[int, ...]:
+        s = set(self.a) | set(self.b)
+        return tuple(q for q in range(self.n_qubits) if q not in s)
+
+
+WORKLOADS = {
+    # 10-qubit Haar state, A = 0-2, B = 3-5, E = 6-9; exact 64 x 64 eigensolve
+    # against SLQ with 16 probes and 20 steps.
+    "haar10": Workload("haar10", 10, (0, 1, 2), (3, 4, 5), 16, 20, "haar", "c128", "fp64", False),
+    # 20-qubit Haar state, |A| = |B| = 6 separated by 2 qubits, E = 8 qubits;
+    # 32 probes, 40 steps, full reorthogonalisation.
+    "haar20": Workload("haar20", 20, tuple(range(0, 6)), tuple(range(8, 14)), 32, 40, "haar", "c64",
+                       "fp32", True),
+    # 30-qubit Haar state in complex64 (8 GiB), E = 0-3, A = 4-16, B = 17-29:
+    # a 26-qubit rho_AB; 8 probes, 50 steps, split-BF16 contractions.
+    "haar30": Workload("haar30", 30, tuple(range(4, 17)), tuple(range(17, 30)), 8, 50, "haar", "c64",
+                       "bf16x3", False),
+    # 24-qubit brickwork state, A = 4-11, B = 13-20, E = rest; 32 probes,
+    # 40 steps, split-BF16.
+    "brick24": Workload("brick24", 24, tuple(range(4, 12)), tuple(range(13, 21)), 32, 40, "brickwork",
+                        "c64", "bf16x3", True, depth=12),
+}
+
+
+# --------------------------------------------------------------------------
+# Surrogate network initial weights
+# --------------------------------------------------------------------------
+MLP_SHAPES = [((256, 19), True), ((256,), False), ((256, 256), True), ((256,), False),
+              ((2, 256), True), ((2,), False)]
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Flat float32 initial parameters of the 19-256-256-2 surrogate network
+    (W1, b1, W2, b2, W3, b3): He-uniform weights from ``default_rng(seed)``,
+    zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, is_weight in MLP_SHAPES:
+        if is_weight:
+            lim = np.sqrt(6.0 / shape[1])
+            parts.append(rng.uniform(-lim, lim, size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
