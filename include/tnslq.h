@@ -1,0 +1,268 @@
+/*
+ * tnslq.h -- C ABI of libtnslq: tensor-network stochastic Lanczos quadrature
+ * (TNSLQ) for the logarithmic negativity of a densely represented pure state,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Gray, "Fast Computation of Many-Body Entanglement"):
+ *   given a pure state psi of L qubits and two disjoint qubit sets A and B
+ *   (the environment C = E is every other qubit), estimate
+ *       E(rho_AB) = log2 || rho_AB^{T_B} ||_Tr = log2 Tr | rho_AB^{T_B} |
+ *   (Sec. II Eq. 1 and Sec. III Eq. 2) with stochastic Lanczos quadrature
+ *   (Sec. III, Algorithm 1), acting with rho_AB^{T_B} lazily through two
+ *   contractions against psi (Sec. V Eq. 4, intermediary (i)), and report the
+ *   error on the mean (Sec. VIII).
+ *
+ * Conventions shared by every entry point
+ *   - Qubit 0 is the most significant bit of psi's flat index.
+ *   - A and B are listed in the order that defines the composite indices a and
+ *     b: the first listed qubit is the most significant bit.  An element of a
+ *     vector on AB has flat index a * d_B + b.
+ *   - Complex data are interleaved (re, im): TNSLQ_C64 = 2 x float,
+ *     TNSLQ_C128 = 2 x double.
+ *   - Device pointers ("dev") are HIP device allocations owned by the caller;
+ *     host pointers ("host") are ordinary host memory owned by the caller.
+ *     The library allocates no device memory and keeps none between calls:
+ *     every scratch buffer lives in the caller's workspace.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  All device work is
+ *     ordered on it.  Calls that fill host outputs synchronise that stream
+ *     before returning; calls without host outputs return without waiting.
+ *   - Errors: every argument is validated before any launch; the call then
+ *     returns a negative status and launches nothing.  A failing HIP call
+ *     returns TNSLQ_E_DEVICE.  Nothing aborts or throws across the ABI.
+ *     tnslq_last_error() gives a one-line description of the last failure on
+ *     the calling thread.
+ *   - Calls that share one workspace must not overlap in time.
+ */
+#ifndef TNSLQ_H
+#define TNSLQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    TNSLQ_OK = 0,
+    TNSLQ_E_ARG = -1,        /* null pointer, size or enum out of range       */
+    TNSLQ_E_PARTITION = -2,  /* qubit out of range, repeated, or in A and B    */
+    TNSLQ_E_DTYPE = -3,      /* unknown storage type                           */
+    TNSLQ_E_WORKSPACE = -4,  /* workspace smaller than the query returned      */
+    TNSLQ_E_DEVICE = -5,     /* a HIP runtime call failed                      */
+    TNSLQ_E_NONFINITE = -6   /* the estimate came out NaN or infinite          */
+};
+
+/* State storage. */
+enum { TNSLQ_C64 = 0, TNSLQ_C128 = 1 };
+
+/* Arithmetic of the two contractions (Sec. V Eq. 4).  The Lanczos recurrence,
+ * reorthogonalisation, tridiagonal eigensolve and statistics are FP64 in every
+ * mode.
+ *   FP64    complex FP64 products and sums.
+ *   FP32    complex FP32 products, FP32 sums in blocks, blocks summed in FP64.
+ *   BF16X3  each FP32 operand split as hi + lo (two BF16 values); products
+ *           hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32 accumulation.
+ *   BF16X6  hi + mid + lo split, six BF16 products per real product.        */
+enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
+
+#define TNSLQ_MAX_QUBITS 36
+#define TNSLQ_MAX_STEPS 128
+
+/* Subsystems A and B (Sec. V: group psi's indices into A, B and C).  `a` and
+ * `b` are host arrays of qubit indices in [0, n_qubits), pairwise distinct and
+ * disjoint.  n_a == 0 or n_b == 0 is allowed: the negativity is then exactly 0
+ * and no device work is done. */
+typedef struct {
+    int n_qubits;
+    const int *a;
+    int n_a;
+    const int *b;
+    int n_b;
+} tnslq_partition;
+
+/* Algorithm 1's inputs (Sec. III): N = n_probes repeats, K_max = n_steps.
+ *   reorth       0: the three-vector recurrence of Algorithm 1;
+ *                1: full reorthogonalisation (classical Gram-Schmidt, twice)
+ *                   against every earlier Lanczos vector of the same probe.
+ *   precision    TNSLQ_FP64 ... TNSLQ_BF16X6.
+ *   seed, probe_offset
+ *                probe k uses SplitMix64 outputs (probe_offset + k) * d_A d_B + i
+ *                of the generator seeded with `seed`; element i takes
+ *                1j ** (output >> 62).  Runs with disjoint offsets are
+ *                independent Hutchinson samples and can be merged.
+ *   stop_tol     0: run exactly n_steps steps.  > 0: after step j >= 6, stop
+ *                once sqrt(dE^2 + (E_j - E_{j-5})^2) <= stop_tol * max(|E_j|, 1)
+ *                with E_j the estimate from T_j and dE its error on the mean
+ *                (the "target precision" reading of Sec. VII.B / Sec. VIII).
+ */
+typedef struct {
+    int n_probes;
+    int n_steps;
+    int reorth;
+    int precision;
+    uint64_t seed;
+    uint64_t probe_offset;
+    double stop_tol;
+} tnslq_options;
+
+typedef struct {
+    double logneg;          /* log2 of the mean of G_n                        */
+    double logneg_se;       /* trace_norm_se / (trace_norm ln 2); NaN if N = 1 */
+    double trace_norm;      /* mean of G_n = ||phi_n||^2 F_{m}                */
+    double trace_norm_se;   /* sqrt(Var(G) / N), sample variance (N - 1)       */
+    int steps_done;         /* Lanczos steps run on the probe block            */
+    int steps_min;          /* fewest steps of any probe (breakdown stops one) */
+    int swapped_ab;         /* 1 if the roles of A and B were exchanged so that
+                               the transposed side is the smaller one          */
+    int n_matvecs;          /* block matvecs performed                          */
+    int n_contract_launches;/* launches of each contraction kernel             */
+    double t_layout_ms;     /* psi regrouping + operand preparation (device)   */
+    double t_matvec_ms;     /* both contractions + split-K merge (device)      */
+    double t_contract1_ms;  /* first contraction (over a'), all launches       */
+    double t_contract2_ms;  /* second contraction (over b', c), all launches   */
+    double t_lanczos_ms;    /* recurrence, reorthogonalisation (device)        */
+    double t_total_ms;      /* whole call, host clock                          */
+} tnslq_result;
+
+/* ------------------------------------------------------------ utilities */
+const char *tnslq_status_str(int status);
+/* Description of the last failure on the calling thread ("" if none). */
+const char *tnslq_last_error(void);
+/* ABI version, currently 1. */
+int tnslq_version(void);
+
+/* -------------------------------------------------- logarithmic negativity */
+
+/* Bytes of device workspace tnslq_logneg needs for this problem (host call,
+ * no device work).  Writes *bytes; returns a status. */
+int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt,
+                          size_t *bytes);
+
+/* SLQ estimate of E(rho_AB) (Sec. III Algorithm 1 with the lazy operator of
+ * Sec. V Eq. 4).
+ *   psi_dev    device, 2^n_qubits complex elements of `dtype`, read only.
+ *   ws_dev     device workspace of at least tnslq_workspace_bytes() bytes,
+ *              256-byte aligned; contents on entry are ignored.
+ *   res        host, filled on success.
+ * Optional host outputs (NULL to skip), with N = n_probes, m = n_steps:
+ *   G_host     N doubles: the per-probe estimates G_n.
+ *   alpha_host N*m doubles, row n = alpha_1..alpha_m of probe n (0 past a stop).
+ *   beta_host  N*(m+1) doubles, row n = beta_1 (= ||phi_n||) .. beta_{m+1}.
+ *   F_host     N*m doubles, row n = F_1..F_m (Algorithm 1's quadrature values
+ *              for the normalised probe; values past a stop repeat the last).
+ *   steps_host N ints: Lanczos steps each probe ran before stopping.
+ * A probe stops early (Lanczos breakdown, not an error) when
+ * beta_{j+1} <= 1e-12 * (max_{i<=j} |alpha_i| + max_{2<=i<=j} beta_i); its
+ * quadrature is then exact.  Synchronises `stream`. */
+int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part,
+                 const tnslq_options *opt, void *ws_dev, size_t ws_bytes, void *stream,
+                 tnslq_result *res, double *G_host, double *alpha_host, double *beta_host,
+                 double *F_host, int *steps_host);
+
+/* ------------------------------------------------ partial-transpose matvec */
+
+/* Workspace bytes for tnslq_ptmatvec with n_vectors vectors. */
+int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n_vectors,
+                                   int precision, size_t *bytes);
+
+/* Y = rho_AB^{T_B} X for a block of n_vectors vectors (Sec. V Eq. 4:
+ * (rho^{T_B} phi)_{ab} = sum_{a',b',c} psi_{ab'c} psi*_{a'bc} phi_{a'b'}),
+ * contracted lazily through intermediary (i) in the given precision.
+ *   X_dev  device, n_vectors x (d_A d_B) complex128, row n = vector n.
+ *   Y_dev  device, same shape, overwritten (must not alias X_dev).
+ * Does not synchronise. */
+int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors,
+                   const void *X_dev, void *Y_dev, int precision, void *ws_dev, size_t ws_bytes,
+                   void *stream);
+
+/* ----------------------------------------------------- Gauss quadrature */
+
+/* For each probe n and each k = 1..n_steps, F[n][k-1] = sum_j tau_j^2 |theta_j|
+ * where theta_j, w_j are the eigenpairs of T_k = tridiag(alpha_1..alpha_k;
+ * beta_2..beta_k) and tau_j the first component of w_j (Sec. III,
+ * Algorithm 1's quadrature block), with k capped at steps[n].
+ *   alpha_dev  device, n_probes x n_steps doubles.
+ *   beta_dev   device, n_probes x (n_steps+1) doubles (beta_1 first).
+ *   steps_dev  device, n_probes ints in [1, n_steps].
+ *   F_dev      device, n_probes x n_steps doubles, written.
+ * Does not synchronise. */
+int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev,
+                     int n_probes, int n_steps, double *F_dev, void *stream);
+
+/* The probe block itself: X[n][i] = 1j ** (SplitMix64(seed) output
+ * ((probe_offset + n) * d + i) >> 62), written as complex128 to the device
+ * array X_dev (n_probes x d).  Does not synchronise. */
+int tnslq_probes(uint64_t seed, uint64_t probe_offset, int n_probes, int64_t d, void *X_dev,
+                 void *stream);
+
+/* ------------------------------------------ learned early stopping (MLP) */
+/* A 19 -> 256 -> 256 -> 2 perceptron with ReLU (the project's addition; the
+ * paper has no learned part).  Parameters are one float array of
+ * TNSLQ_MLP_NPARAMS values, W1 (256 x 19, row = output unit), b1, W2 (256 x
+ * 256), b2, W3 (2 x 256), b3.  Weights enter every product rounded to BF16
+ * (nearest, ties to even); sums are FP32.  `norm` holds 38 floats: the 19
+ * feature means then the 19 feature scales; inputs are standardised as
+ * (x - mean) / scale.  Output row = (u0, u1): predicted residual mean and log
+ * variance. */
+#define TNSLQ_MLP_NIN 19
+#define TNSLQ_MLP_NHID 256
+#define TNSLQ_MLP_NOUT 2
+#define TNSLQ_MLP_NPARAMS 71426
+
+/* Workspace bytes for a batch of `batch` rows (forward and gradient). */
+int tnslq_mlp_workspace_bytes(int batch, size_t *bytes);
+
+/* out_dev[batch x 2] = network(x_dev[batch x 19]).  All pointers device.
+ * Does not synchronise. */
+int tnslq_mlp_forward(const float *params_dev, const float *norm_dev, const float *x_dev,
+                      int batch, float *out_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Gaussian negative log-likelihood of targets r_dev[batch],
+ * L = (1/B) sum 0.5 (u1 + (r - u0)^2 exp(-u1)), and its gradient with
+ * respect to the parameters (BF16 rounding treated as the identity).
+ * loss_dev: 1 float; grad_dev: TNSLQ_MLP_NPARAMS floats, overwritten.
+ * Does not synchronise. */
+int tnslq_mlp_loss_grad(const float *params_dev, const float *norm_dev, const float *x_dev,
+                        const float *r_dev, int batch, float *loss_dev, float *grad_dev,
+                        void *ws_dev, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba) on FP32 master parameters in place, t >= 1,
+ * beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  m_dev, v_dev: moment buffers.
+ * Does not synchronise. */
+int tnslq_mlp_adam(float *params_dev, float *m_dev, float *v_dev, const float *grad_dev, int t,
+                   float lr, void *stream);
+
+/* Minibatch training: for s = 0..n_batches-1, gather rows idx_dev[s*batch ..
+ * (s+1)*batch) of (x_dev, r_dev), compute the gradient and take Adam step
+ * t0 + s.  losses_dev (device, n_batches floats, may be NULL) receives each
+ * step's loss.  Does not synchronise. */
+int tnslq_mlp_train(float *params_dev, float *m_dev, float *v_dev, const float *norm_dev,
+                    const float *x_dev, const float *r_dev, const int *idx_dev, int batch,
+                    int n_batches, int t0, float lr, float *losses_dev, void *ws_dev,
+                    size_t ws_bytes, void *stream);
+
+/* Early-stopping surrogate run.  Runs `early_steps` Lanczos steps of
+ * tnslq_logneg, forms the 19 features (probe means of d_A d_B alpha_1..8 and
+ * d_A d_B beta_2..9, then log2 d_A, log2 d_B, log2 d_E), and evaluates the
+ * network: mu = E_early + y_scale * u0, sigma = y_scale * exp(u1 / 2), with
+ * E_early the SLQ estimate from T_{early_steps}.  If sigma <= tol *
+ * max(|mu|, 1) the result is (mu, sigma); otherwise the same Lanczos state
+ * continues to opt->n_steps (the fallback) and the result is full SLQ's.
+ *   early_steps  8 (the network's input width fixes it).
+ *   res          as tnslq_logneg; when the surrogate is accepted, logneg =
+ *                mu and logneg_se = sigma.
+ *   info_host    host, 5 doubles: mu, sigma, E_early, used_fallback (0/1),
+ *                E_full (NaN when not run).
+ * Synchronises `stream`. */
+int tnslq_logneg_surrogate(const void *psi_dev, int dtype, const tnslq_partition *part,
+                           const tnslq_options *opt, const float *params_dev,
+                           const float *norm_dev, float y_scale, int early_steps, double tol,
+                           void *ws_dev, size_t ws_bytes, void *stream, tnslq_result *res,
+                           double *info_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNSLQ_H */

@@ -1,0 +1,314 @@
+"""Python binding of libtnslq (TNSLQ logarithmic negativity on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libtnslq.so`` behind the C ABI declared in ``include/tnslq.h``.
+torch supplies device memory and the current stream.  The functions keep the
+C names; importing works without a GPU (the library is loaded on first use),
+and a missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, Optional, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtnslq.so")
+
+TNSLQ_OK = 0
+TNSLQ_C64, TNSLQ_C128 = 0, 1
+TNSLQ_FP64, TNSLQ_FP32, TNSLQ_BF16X3, TNSLQ_BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "bf16x6": TNSLQ_BF16X6}
+MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS = 19, 256, 2, 71426
+
+
+class TnslqError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class Partition(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_int)), ("n_a", ctypes.c_int),
+                ("b", ctypes.POINTER(ctypes.c_int)), ("n_b", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
+                ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
+                ("stop_tol", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("logneg", ctypes.c_double), ("logneg_se", ctypes.c_double), ("trace_norm", ctypes.c_double),
+                ("trace_norm_se", ctypes.c_double), ("steps_done", ctypes.c_int), ("steps_min", ctypes.c_int),
+                ("swapped_ab", ctypes.c_int), ("n_matvecs", ctypes.c_int), ("n_contract_launches", ctypes.c_int),
+                ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
+                ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
+                ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self) -> Dict[str, float]:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+_VP, _SZ, _I, _D, _F, _U64, _I64 = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_float, ctypes.c_uint64, ctypes.c_int64)
+_SIGS = {
+    "tnslq_status_str": (ctypes.c_char_p, [_I]),
+    "tnslq_last_error": (ctypes.c_char_p, []),
+    "tnslq_version": (_I, []),
+    "tnslq_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(Options), ctypes.POINTER(_SZ)]),
+    "tnslq_logneg": (_I, [_VP, _I, ctypes.POINTER(Partition), ctypes.POINTER(Options), _VP, _SZ, _VP,
+                          ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
+    "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, ctypes.POINTER(_SZ)]),
+    "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _VP, _SZ, _VP]),
+    "tnslq_quadrature": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
+    "tnslq_probes": (_I, [_U64, _U64, _I, _I64, _VP, _VP]),
+    "tnslq_mlp_workspace_bytes": (_I, [_I, ctypes.POINTER(_SZ)]),
+    "tnslq_mlp_forward": (_I, [_VP, _VP, _VP, _I, _VP, _VP, _SZ, _VP]),
+    "tnslq_mlp_loss_grad": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]),
+    "tnslq_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _I, _F, _VP]),
+    "tnslq_mlp_train": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _F, _VP, _VP, _SZ, _VP]),
+    "tnslq_logneg_surrogate": (_I, [_VP, _I, ctypes.POINTER(Partition), ctypes.POINTER(Options), _VP, _VP, _F, _I,
+                                    _D, _VP, _SZ, _VP, ctypes.POINTER(Result), _VP]),
+}
+
+
+def lib():
+    """Load libtnslq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1809_01685_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != TNSLQ_OK:
+        detail = lib().tnslq_last_error().decode()
+        raise TnslqError(rc, where, detail or lib().tnslq_status_str(rc).decode())
+
+
+def _partition(n_qubits: int, a: Sequence[int], b: Sequence[int]):
+    aa = (ctypes.c_int * max(1, len(a)))(*a)
+    bb = (ctypes.c_int * max(1, len(b)))(*b)
+    p = Partition(n_qubits, aa, len(a), bb, len(b))
+    p._keep = (aa, bb)  # keep the arrays alive with the struct
+    return p
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.complex64:
+        return TNSLQ_C64
+    if t.dtype == torch.complex128:
+        return TNSLQ_C128
+    raise TypeError(f"psi must be complex64 or complex128, got {t.dtype}")
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _workspace(nbytes: int, device, ws=None):
+    import torch
+    if ws is not None and ws.numel() >= nbytes:
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _check_device_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+# ----------------------------------------------------------------- utilities
+def tnslq_version() -> int:
+    return lib().tnslq_version()
+
+
+def tnslq_status_str(status: int) -> str:
+    return lib().tnslq_status_str(status).decode()
+
+
+def tnslq_last_error() -> str:
+    return lib().tnslq_last_error().decode()
+
+
+def make_options(n_probes: int, n_steps: int, reorth: bool = False, precision="fp32", seed: int = 0,
+                 probe_offset: int = 0, stop_tol: float = 0.0) -> Options:
+    return Options(int(n_probes), int(n_steps), int(bool(reorth)), _prec(precision), int(seed) & (2**64 - 1),
+                   int(probe_offset), float(stop_tol))
+
+
+def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int:
+    n = ctypes.c_size_t(0)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_workspace_bytes(int(dtype), ctypes.byref(p), ctypes.byref(opts), ctypes.byref(n)),
+           "tnslq_workspace_bytes")
+    return n.value
+
+
+# ------------------------------------------------------------- logneg
+def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
+                 seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
+                 want_arrays: bool = True) -> Dict[str, object]:
+    """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``."""
+    import numpy as np
+    _check_device_tensor(psi, "psi")
+    if psi.numel() != 1 << n_qubits:
+        raise ValueError("psi has the wrong length")
+    dt = _dtype_code(psi)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol)
+    p = _partition(n_qubits, a, b)
+    need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
+    ws = _workspace(need, psi.device, workspace)
+    res = Result()
+    K, m = n_probes, n_steps
+    G = np.zeros(K)
+    al = np.zeros((K, m))
+    be = np.zeros((K, m + 1))
+    F = np.zeros((K, m))
+    st = np.zeros(K, dtype=np.int32)
+    host = (lambda x: x.ctypes.data_as(ctypes.c_void_p)) if want_arrays else (lambda x: ctypes.c_void_p(0))
+    rc = lib().tnslq_logneg(_ptr(psi), dt, ctypes.byref(p), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                            _stream(stream), ctypes.byref(res), host(G), host(al), host(be), host(F), host(st))
+    _check(rc, "tnslq_logneg")
+    out: Dict[str, object] = res.as_dict()
+    if want_arrays:
+        out.update({"G": G, "alpha": al, "beta": be, "F": F, "steps": st})
+    out["workspace_bytes"] = need
+    return out
+
+
+# ------------------------------------------------------------- matvec
+def tnslq_ptmatvec_workspace_bytes(dtype: int, n_qubits: int, a, b, n_vectors: int, precision="fp32") -> int:
+    n = ctypes.c_size_t(0)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_ptmatvec_workspace_bytes(int(dtype), ctypes.byref(p), int(n_vectors), _prec(precision),
+                                                ctypes.byref(n)), "tnslq_ptmatvec_workspace_bytes")
+    return n.value
+
+
+def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None, stream=None, Y=None):
+    """Y = rho_AB^{T_B} X for device complex128 X of shape (K, d_A d_B)."""
+    import torch
+    _check_device_tensor(psi, "psi")
+    _check_device_tensor(X, "X")
+    if X.dtype != torch.complex128 or X.dim() != 2:
+        raise TypeError("X must be a 2-D complex128 device tensor")
+    dt = _dtype_code(psi)
+    K = X.shape[0]
+    need = tnslq_ptmatvec_workspace_bytes(dt, n_qubits, a, b, K, precision)
+    ws = _workspace(need, psi.device, workspace)
+    if Y is None:
+        Y = torch.empty_like(X)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision), _ptr(ws),
+                                ws.numel(), _stream(stream)), "tnslq_ptmatvec")
+    return Y
+
+
+def tnslq_quadrature(alpha, beta, steps=None, stream=None):
+    """Device FP64 (K, m) alpha, (K, m+1) beta -> (K, m) quadrature values."""
+    import torch
+    K, m = alpha.shape
+    F = torch.empty((K, m), dtype=torch.float64, device=alpha.device)
+    _check(lib().tnslq_quadrature(_ptr(alpha), _ptr(beta), _ptr(steps), K, m, _ptr(F), _stream(stream)),
+           "tnslq_quadrature")
+    return F
+
+
+def tnslq_probes(seed: int, probe_offset: int, n_probes: int, d: int, device="cuda", stream=None):
+    import torch
+    X = torch.empty((n_probes, d), dtype=torch.complex128, device=device)
+    _check(lib().tnslq_probes(int(seed) & (2**64 - 1), int(probe_offset), int(n_probes), int(d), _ptr(X),
+                              _stream(stream)), "tnslq_probes")
+    return X
+
+
+# ------------------------------------------------------------- MLP
+def tnslq_mlp_workspace_bytes(batch: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().tnslq_mlp_workspace_bytes(int(batch), ctypes.byref(n)), "tnslq_mlp_workspace_bytes")
+    return n.value
+
+
+def tnslq_mlp_forward(params, norm, x, workspace=None, stream=None):
+    import torch
+    B = x.shape[0]
+    out = torch.empty((B, MLP_NOUT), dtype=torch.float32, device=x.device)
+    ws = _workspace(tnslq_mlp_workspace_bytes(B), x.device, workspace)
+    _check(lib().tnslq_mlp_forward(_ptr(params), _ptr(norm), _ptr(x), B, _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(stream)), "tnslq_mlp_forward")
+    return out
+
+
+def tnslq_mlp_loss_grad(params, norm, x, r, workspace=None, stream=None):
+    import torch
+    B = x.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+    ws = _workspace(tnslq_mlp_workspace_bytes(B), x.device, workspace)
+    _check(lib().tnslq_mlp_loss_grad(_ptr(params), _ptr(norm), _ptr(x), _ptr(r), B, _ptr(loss), _ptr(grad),
+                                     _ptr(ws), ws.numel(), _stream(stream)), "tnslq_mlp_loss_grad")
+    return loss, grad
+
+
+def tnslq_mlp_adam(params, m, v, grad, t: int, lr: float, stream=None):
+    _check(lib().tnslq_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(t), float(lr), _stream(stream)),
+           "tnslq_mlp_adam")
+
+
+def tnslq_mlp_train(params, m, v, norm, x, r, idx, batch: int, t0: int, lr: float, losses=None, workspace=None,
+                    stream=None):
+    n_batches = idx.numel() // batch
+    need = tnslq_mlp_workspace_bytes(batch) + MLP_NPARAMS * 4 + 512
+    ws = _workspace(need, x.device, workspace)
+    _check(lib().tnslq_mlp_train(_ptr(params), _ptr(m), _ptr(v), _ptr(norm), _ptr(x), _ptr(r), _ptr(idx), int(batch),
+                                 int(n_batches), int(t0), float(lr), _ptr(losses), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "tnslq_mlp_train")
+    return t0 + n_batches
+
+
+def tnslq_logneg_surrogate(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, params, norm, y_scale: float,
+                           tol: float = 0.01, early_steps: int = 8, reorth: bool = False, precision="fp32",
+                           seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None,
+                           stream=None) -> Dict[str, object]:
+    import numpy as np
+    _check_device_tensor(psi, "psi")
+    dt = _dtype_code(psi)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol)
+    p = _partition(n_qubits, a, b)
+    need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
+    ws = _workspace(need, psi.device, workspace)
+    res = Result()
+    info = np.zeros(5)
+    rc = lib().tnslq_logneg_surrogate(_ptr(psi), dt, ctypes.byref(p), ctypes.byref(opts), _ptr(params), _ptr(norm),
+                                      float(y_scale), int(early_steps), float(tol), _ptr(ws), ws.numel(),
+                                      _stream(stream), ctypes.byref(res), info.ctypes.data_as(ctypes.c_void_p))
+    _check(rc, "tnslq_logneg_surrogate")
+    out: Dict[str, object] = res.as_dict()
+    out.update({"mu": info[0], "sigma": info[1], "e_early": info[2], "used_fallback": bool(info[3]),
+                "e_full": info[4] if not math.isnan(info[4]) else None})
+    return out

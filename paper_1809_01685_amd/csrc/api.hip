@@ -1,0 +1,700 @@
+// C ABI and host orchestration of libtnslq.
+//
+// The host side validates arguments, plans the layout and the workspace
+// carve-up, and drives the device loop of Algorithm 1 (Sec. III): one block
+// matvec (both contractions of Sec. V Eq. 4) per Lanczos step for all probes
+// at once, the FP64 recurrence, and at the end the Gauss quadrature and the
+// Hutchinson statistics.  No device memory is allocated here.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "tnslq_internal.h"
+
+using namespace tnslq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define TNSLQ_HIP(x)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) return fail(TNSLQ_E_DEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Largest intermediary (Ups) chunk the planner allows, in bytes.
+constexpr size_t UPS_BUDGET = size_t(16) << 30;
+
+int check_partition(const tnslq_partition *p) {
+    if (!p) return fail(TNSLQ_E_ARG, "partition is NULL");
+    if (p->n_qubits < 1 || p->n_qubits > TNSLQ_MAX_QUBITS)
+        return fail(TNSLQ_E_PARTITION, "n_qubits %d outside [1, %d]", p->n_qubits, TNSLQ_MAX_QUBITS);
+    if (p->n_a < 0 || p->n_b < 0 || p->n_a + p->n_b > p->n_qubits)
+        return fail(TNSLQ_E_PARTITION, "bad subsystem sizes n_a=%d n_b=%d", p->n_a, p->n_b);
+    if ((p->n_a > 0 && !p->a) || (p->n_b > 0 && !p->b)) return fail(TNSLQ_E_ARG, "qubit list is NULL");
+    std::vector<int> seen(p->n_qubits, 0);
+    for (int i = 0; i < p->n_a + p->n_b; ++i) {
+        const int q = i < p->n_a ? p->a[i] : p->b[i - p->n_a];
+        if (q < 0 || q >= p->n_qubits) return fail(TNSLQ_E_PARTITION, "qubit %d out of range", q);
+        if (seen[q]) return fail(TNSLQ_E_PARTITION, "qubit %d listed twice", q);
+        seen[q] = 1;
+    }
+    return TNSLQ_OK;
+}
+
+int check_prec(int prec) {
+    if (prec < TNSLQ_FP64 || prec > TNSLQ_BF16X6) return fail(TNSLQ_E_ARG, "precision %d unknown", prec);
+    return TNSLQ_OK;
+}
+int check_dtype(int dtype) {
+    if (dtype != TNSLQ_C64 && dtype != TNSLQ_C128) return fail(TNSLQ_E_DTYPE, "dtype %d unknown", dtype);
+    return TNSLQ_OK;
+}
+
+// Build the plan: roles (A and B exchanged when B is larger, so that the
+// contraction cost D * min(d_A, d_B) per probe is the smaller one), chunking
+// and the workspace carve-up.  `lanczos` = 0 plans a bare matvec.
+int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int prec, int lanczos, Plan &pl) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(p)) || (rc = check_prec(prec))) return rc;
+    if (K < 1 || K > 65535) return fail(TNSLQ_E_ARG, "n_probes %d outside [1, 65535]", K);
+    if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
+        return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
+    pl = Plan();
+    pl.L = p->n_qubits;
+    pl.dtype = dtype;
+    pl.prec = prec;
+    pl.K = K;
+    pl.m = lanczos ? m : 1;
+    pl.reorth = lanczos ? (reorth ? 1 : 0) : 0;
+    pl.swapped = p->n_b > p->n_a;
+    const int *qa = pl.swapped ? p->b : p->a;
+    const int *qb = pl.swapped ? p->a : p->b;
+    pl.nA = pl.swapped ? p->n_b : p->n_a;
+    pl.nB = pl.swapped ? p->n_a : p->n_b;
+    for (int i = 0; i < pl.nA; ++i) pl.qa[i] = qa[i];
+    for (int i = 0; i < pl.nB; ++i) pl.qb[i] = qb[i];
+    std::vector<int> used(pl.L, 0);
+    for (int i = 0; i < p->n_a; ++i) used[p->a[i]] = 1;
+    for (int i = 0; i < p->n_b; ++i) used[p->b[i]] = 1;
+    pl.nE = 0;
+    for (int q = 0; q < pl.L; ++q)
+        if (!used[q]) pl.qe[pl.nE++] = q;
+    pl.dA = int64_t(1) << pl.nA;
+    pl.dB = int64_t(1) << pl.nB;
+    pl.dE = int64_t(1) << pl.nE;
+    pl.dAB = pl.dA * pl.dB;
+    pl.D = int64_t(1) << pl.L;
+
+    const int np = planes_of(prec);
+    const size_t pb = piece_bytes(prec);
+    const size_t acc = prec == TNSLQ_FP64 ? 16 : 8;
+    // intermediary per probe: d_B * d_E * d_B elements
+    const int64_t ups_per = pl.dB * pl.dE * pl.dB;
+    const size_t ups_bytes_per = (size_t)np * pb * (size_t)ups_per;
+    pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
+    // split-K of the second contraction: enough blocks to fill the chip
+    const int64_t kr2 = pl.dE * pl.dB;
+    const int64_t tiles = ((pl.dA + 63) / 64) * ((pl.kc * pl.dB + 63) / 64);
+    pl.S = 1;
+    while (tiles * pl.S < 2048 && kr2 / (2 * pl.S) >= 256 && kr2 % (2 * pl.S) == 0) pl.S *= 2;
+    const int64_t n = pl.dAB;
+    pl.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 4096));
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += up(bytes);
+        return r;
+    };
+    pl.off_Paeb = take((size_t)np * pb * plane_stride(pl.D));
+    pl.off_Pbea = take((size_t)np * pb * plane_stride(pl.D));
+    pl.off_Xt = take((size_t)np * pb * plane_stride((int64_t)K * n));
+    pl.off_Ups = take((size_t)np * pb * plane_stride((int64_t)pl.kc * ups_per));
+    pl.off_Ypart = take((size_t)pl.S * pl.kc * n * acc);
+    if (lanczos) {
+        pl.nQ = pl.reorth ? pl.m + 1 : 3;
+        pl.off_Q = take((size_t)pl.nQ * K * n * 16);
+        pl.off_w = take((size_t)K * n * 16);
+        pl.off_alpha = take((size_t)K * pl.m * 8);
+        pl.off_beta = take((size_t)K * (pl.m + 1) * 8);
+        pl.off_F = take((size_t)K * pl.m * 8);
+        pl.off_G = take((size_t)K * 8);
+        pl.off_stats = take((size_t)pl.m * 4 * 8);
+        pl.off_red = take((size_t)2 * K * pl.nblk * 8);
+        pl.off_h = take((size_t)K * (pl.m + 1) * pl.nblk * 16 + (size_t)K * (pl.m + 1) * 16);
+        pl.off_steps = take((size_t)K * 4);
+        pl.off_feat = take(64 * 4);
+        pl.off_mlp = take(mlp_ws_bytes(1) + 64);
+    }
+    pl.total = o;
+    return TNSLQ_OK;
+}
+
+// Output bit t of the regrouped index <- input bit of psi's flat index.
+// `order` lists the three groups from most to least significant.
+PermDesc perm_for(const Plan &pl, const int *g0, int n0, const int *g1, int n1, const int *g2, int n2) {
+    PermDesc pd{};
+    pd.L = pl.L;
+    int t = 0;
+    const int *groups[3] = {g2, g1, g0};
+    const int sizes[3] = {n2, n1, n0};
+    for (int gi = 0; gi < 3; ++gi)
+        for (int i = sizes[gi] - 1; i >= 0; --i) pd.map[t++] = pl.L - 1 - groups[gi][i];
+    return pd;
+}
+
+struct Ctx {
+    Plan pl;
+    char *ws;
+    hipStream_t st;
+    LzDims z;
+    void *Paeb, *Pbea, *Xt, *Ups, *Ypart;
+    int64_t psP, psX, psU;
+    double2 *Q, *w;
+    double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
+    double2 *h;
+    int *steps;
+    float *feat;
+    void *mlpws;
+    std::vector<hipEvent_t> ev;
+    int n_launch = 0;
+    ~Ctx() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipEvent_t event() {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    }
+};
+
+void bind(Ctx &c, void *ws, hipStream_t st) {
+    Plan &pl = c.pl;
+    c.ws = (char *)ws;
+    c.st = st;
+    c.Paeb = c.ws + pl.off_Paeb;
+    c.Pbea = c.ws + pl.off_Pbea;
+    c.Xt = c.ws + pl.off_Xt;
+    c.Ups = c.ws + pl.off_Ups;
+    c.Ypart = c.ws + pl.off_Ypart;
+    c.psP = plane_stride(pl.D);
+    c.psX = plane_stride((int64_t)pl.K * pl.dAB);
+    c.psU = plane_stride((int64_t)pl.kc * pl.dB * pl.dE * pl.dB);
+    c.Q = (double2 *)(c.ws + pl.off_Q);
+    c.w = (double2 *)(c.ws + pl.off_w);
+    c.alpha = (double *)(c.ws + pl.off_alpha);
+    c.beta = (double *)(c.ws + pl.off_beta);
+    c.F = (double *)(c.ws + pl.off_F);
+    c.G = (double *)(c.ws + pl.off_G);
+    c.stats = (double *)(c.ws + pl.off_stats);
+    c.dotpart = (double *)(c.ws + pl.off_red);
+    c.nrmpart = c.dotpart + (size_t)pl.K * pl.nblk;
+    c.hpart = (double *)(c.ws + pl.off_h);
+    c.h = (double2 *)(c.ws + pl.off_h + (size_t)pl.K * (pl.m + 1) * pl.nblk * 16);
+    c.steps = (int *)(c.ws + pl.off_steps);
+    c.feat = (float *)(c.ws + pl.off_feat);
+    c.mlpws = c.ws + pl.off_mlp;
+    c.z = LzDims{pl.dA, pl.dB, pl.dAB, pl.K, pl.m, pl.nblk};
+}
+
+int do_layout(Ctx &c, const void *psi) {
+    const Plan &pl = c.pl;
+    PermDesc aeb = perm_for(pl, pl.qa, pl.nA, pl.qe, pl.nE, pl.qb, pl.nB);
+    PermDesc bea = perm_for(pl, pl.qb, pl.nB, pl.qe, pl.nE, pl.qa, pl.nA);
+    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Paeb, c.psP, pl.D, aeb, 0, c.st));
+    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Pbea, c.psP, pl.D, bea, 1, c.st));
+    return TNSLQ_OK;
+}
+
+// Both contractions for probes [k0, k0 + kcur): Xt -> Ups -> Ypart.
+int contract_chunk(Ctx &c, int k0, int kcur, hipEvent_t e1, hipEvent_t e2) {
+    const Plan &pl = c.pl;
+    const size_t pb = piece_bytes(pl.prec);
+    GemmDesc g1{};
+    g1.A = c.Pbea;
+    g1.lda = pl.dA;
+    g1.a_ps = c.psP;
+    g1.B = (const char *)c.Xt + (size_t)k0 * pl.dAB * pb;
+    g1.ldb = pl.dA;
+    g1.b_ps = c.psX;
+    g1.C = c.Ups;
+    g1.c_ps = c.psU;
+    g1.M = pl.dB * pl.dE;
+    g1.N = (int64_t)kcur * pl.dB;
+    g1.Kr = pl.dA;
+    g1.ldc = pl.dB;
+    g1.cnb = pl.dB;
+    g1.cbs = pl.dB * pl.dE * pl.dB;
+    g1.S = 1;
+    g1.c_split = 0;
+    g1.out_mode = 0;
+    GemmDesc g2{};
+    g2.A = c.Paeb;
+    g2.lda = pl.dE * pl.dB;
+    g2.a_ps = c.psP;
+    g2.B = c.Ups;
+    g2.ldb = pl.dE * pl.dB;
+    g2.b_ps = c.psU;
+    g2.C = c.Ypart;
+    g2.c_ps = 0;
+    g2.M = pl.dA;
+    g2.N = (int64_t)kcur * pl.dB;
+    g2.Kr = pl.dE * pl.dB;
+    g2.ldc = pl.dB;
+    g2.cnb = pl.dB;
+    g2.cbs = pl.dAB;
+    g2.S = pl.S;
+    g2.c_split = (int64_t)pl.kc * pl.dAB;
+    g2.out_mode = 1;
+    TNSLQ_HIP(launch_gemm(pl.prec, g1, c.st));
+    if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+    TNSLQ_HIP(launch_gemm(pl.prec, g2, c.st));
+    if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+    c.n_launch++;
+    return TNSLQ_OK;
+}
+
+// Events of one Lanczos step: mv0, then per probe chunk (after contraction 1,
+// after contraction 2, after the merge), then mv1 (matvec done), lz1.
+struct StepEvents {
+    std::vector<hipEvent_t> e;
+    int nchunk = 0;
+    hipEvent_t mv0() const { return e[0]; }
+    hipEvent_t c1(int ch) const { return e[1 + 3 * ch]; }
+    hipEvent_t c2(int ch) const { return e[2 + 3 * ch]; }
+    hipEvent_t pa(int ch) const { return e[3 + 3 * ch]; }
+    hipEvent_t mv1() const { return e[1 + 3 * nchunk]; }
+    hipEvent_t lz1() const { return e[2 + 3 * nchunk]; }
+};
+
+int lanczos_step(Ctx &c, int j, StepEvents *se) {
+    const Plan &pl = c.pl;
+    const int64_t n = pl.dAB;
+    const int64_t slot = (int64_t)pl.K * n;
+    auto slot_of = [&](int jj) { return pl.reorth ? jj : jj % 3; };   // q_{jj+1} lives in slot slot_of(jj)
+    double2 *q_cur = c.Q + slot_of(j - 1) * slot;
+    double2 *q_prev = j > 1 ? c.Q + slot_of(j - 2) * slot : q_cur;
+    double2 *q_next = c.Q + slot_of(j) * slot;
+    const int accfp64 = pl.prec == TNSLQ_FP64;
+    int rc;
+    TNSLQ_HIP(hipEventRecord(se->mv0(), c.st));
+    for (int k0 = 0, ch = 0; k0 < pl.K; k0 += pl.kc, ++ch) {
+        const int kcur = std::min(pl.kc, pl.K - k0);
+        if ((rc = contract_chunk(c, k0, kcur, se->c1(ch), se->c2(ch)))) return rc;
+        TNSLQ_HIP(launch_passA(accfp64, c.z, c.Ypart, pl.S, (int64_t)pl.kc * n, k0, kcur, q_prev, q_cur, c.w,
+                               c.alpha, c.beta, j, c.dotpart, c.st));
+        TNSLQ_HIP(hipEventRecord(se->pa(ch), c.st));
+    }
+    TNSLQ_HIP(hipEventRecord(se->mv1(), c.st));
+    TNSLQ_HIP(launch_passB(c.z, c.dotpart, q_cur, c.w, c.alpha, c.beta, j, c.nrmpart, pl.reorth ? 0 : 1, c.st));
+    if (pl.reorth)
+        TNSLQ_HIP(launch_reorth(c.z, c.Q, j, slot, c.w, c.hpart, c.h, c.alpha, c.beta, j, c.nrmpart, c.st));
+    TNSLQ_HIP(launch_passC(pl.prec, c.z, c.nrmpart, c.w, q_next, c.Xt, c.psX, c.alpha, c.beta, j, c.st));
+    TNSLQ_HIP(hipEventRecord(se->lz1(), c.st));
+    return TNSLQ_OK;
+}
+
+int slq_setup(Ctx &c, const void *psi, uint64_t seed, uint64_t offset) {
+    const Plan &pl = c.pl;
+    int rc;
+    if ((rc = do_layout(c, psi))) return rc;
+    TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)pl.K * pl.m * 8, c.st));
+    TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)pl.K * (pl.m + 1) * 8, c.st));
+    TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)pl.K * pl.m * 8, c.st));
+    TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, c.Xt, c.psX, c.alpha, c.beta, c.st));
+    return TNSLQ_OK;
+}
+
+// Quadrature for steps [jlo, jhi] and the statistics of step `jstat`.
+int quad_stats(Ctx &c, int jdone, int jlo, int jhi, int jstat, double *G) {
+    const Plan &pl = c.pl;
+    TNSLQ_HIP(launch_steps(c.alpha, c.beta, pl.K, pl.m, jdone, c.steps, c.st));
+    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, pl.K, pl.m, jlo, jhi, c.F, c.st));
+    TNSLQ_HIP(launch_stats(c.beta, c.F, pl.K, pl.m, jstat, G, c.stats, c.st));
+    return TNSLQ_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (a && b && hipEventElapsedTime(&ms, a, b) == hipSuccess) return ms;
+    return 0.f;
+}
+
+void zero_result(tnslq_result *res) {
+    memset(res, 0, sizeof *res);
+}
+
+// Trivial partitions (empty A or B): rho^{T_B} then has the spectrum of a
+// density matrix, so the trace norm is 1 and E = 0 exactly.
+int trivial(const tnslq_options *opt, tnslq_result *res, double *G, double *alpha, double *beta, double *F,
+            int *steps) {
+    zero_result(res);
+    res->trace_norm = 1.0;
+    const int K = opt->n_probes, m = opt->n_steps;
+    if (G) std::fill(G, G + K, 1.0);
+    if (alpha) std::fill(alpha, alpha + (size_t)K * m, 0.0);
+    if (beta) std::fill(beta, beta + (size_t)K * (m + 1), 0.0);
+    if (F) std::fill(F, F + (size_t)K * m, 1.0);
+    if (steps) std::fill(steps, steps + K, 0);
+    return TNSLQ_OK;
+}
+
+int check_options(const tnslq_options *opt) {
+    if (!opt) return fail(TNSLQ_E_ARG, "options is NULL");
+    if (opt->n_probes < 1) return fail(TNSLQ_E_ARG, "n_probes must be >= 1");
+    if (opt->n_steps < 1 || opt->n_steps > TNSLQ_MAX_STEPS)
+        return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", opt->n_steps, TNSLQ_MAX_STEPS);
+    if (opt->reorth != 0 && opt->reorth != 1) return fail(TNSLQ_E_ARG, "reorth must be 0 or 1");
+    if (!(opt->stop_tol >= 0.0)) return fail(TNSLQ_E_ARG, "stop_tol must be >= 0");
+    return check_prec(opt->precision);
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// Shared body of tnslq_logneg and tnslq_logneg_surrogate.
+struct Run {
+    Ctx c;
+    std::vector<StepEvents> se;
+    hipEvent_t e_start = nullptr, e_layout = nullptr;
+    int jdone = 0;
+};
+
+int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_options *opt, const void *psi, void *ws,
+              size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1, r.c.pl))) return rc;
+    if (!psi) return fail(TNSLQ_E_ARG, "psi is NULL");
+    if (!ws) return fail(TNSLQ_E_ARG, "workspace is NULL");
+    if ((uintptr_t)ws % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < r.c.pl.total)
+        return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, r.c.pl.total);
+    bind(r.c, ws, (hipStream_t)stream);
+    r.e_start = r.c.event();
+    r.e_layout = r.c.event();
+    r.se.resize(opt->n_steps + 1);
+    const int nchunk = (r.c.pl.K + r.c.pl.kc - 1) / r.c.pl.kc;
+    for (auto &s : r.se) {
+        s.nchunk = nchunk;
+        s.e.resize(3 + 3 * nchunk);
+        for (auto &e : s.e)
+            if (!(e = r.c.event())) return fail(TNSLQ_E_DEVICE, "hipEventCreate failed");
+    }
+    TNSLQ_HIP(hipEventRecord(r.e_start, r.c.st));
+    if ((rc = slq_setup(r.c, psi, opt->seed, opt->probe_offset))) return rc;
+    TNSLQ_HIP(hipEventRecord(r.e_layout, r.c.st));
+    return TNSLQ_OK;
+}
+
+// Steps jdone+1 .. jmax; with stop_tol > 0 stops at the first step meeting the
+// precision target.
+int run_steps(Run &r, int jmax, double stop_tol) {
+    int rc;
+    for (int j = r.jdone + 1; j <= jmax; ++j) {
+        if ((rc = lanczos_step(r.c, j, &r.se[j]))) return rc;
+        r.jdone = j;
+        if (stop_tol > 0.0 && j >= 6) {
+            if ((rc = quad_stats(r.c, j, j - 5, j, j - 5, nullptr))) return rc;
+            TNSLQ_HIP(launch_stats(r.c.beta, r.c.F, r.c.pl.K, r.c.pl.m, j, nullptr, r.c.stats, r.c.st));
+            double s[8];
+            TNSLQ_HIP(hipMemcpyAsync(s, r.c.stats + (size_t)(j - 6) * 4, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                                     r.c.st));
+            TNSLQ_HIP(hipMemcpyAsync(s + 4, r.c.stats + (size_t)(j - 1) * 4, 4 * sizeof(double),
+                                     hipMemcpyDeviceToHost, r.c.st));
+            TNSLQ_HIP(hipStreamSynchronize(r.c.st));
+            const double e_now = s[6], de = s[7], e_old = s[2];
+            const double dl = e_now - e_old;
+            const double err = std::sqrt((std::isnan(de) ? 0.0 : de * de) + dl * dl);
+            if (std::isfinite(e_now) && err <= stop_tol * std::max(std::fabs(e_now), 1.0)) break;
+        }
+    }
+    return TNSLQ_OK;
+}
+
+int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta, double *F, int *steps,
+               const Timer &tm) {
+    Ctx &c = r.c;
+    const Plan &pl = c.pl;
+    int rc;
+    if ((rc = quad_stats(c, r.jdone, 1, r.jdone, r.jdone, c.G))) return rc;
+    double s[4];
+    TNSLQ_HIP(hipMemcpyAsync(s, c.stats + (size_t)(r.jdone - 1) * 4, sizeof s, hipMemcpyDeviceToHost, c.st));
+    std::vector<int> hsteps(pl.K);
+    TNSLQ_HIP(hipMemcpyAsync(hsteps.data(), c.steps, sizeof(int) * pl.K, hipMemcpyDeviceToHost, c.st));
+    if (G) TNSLQ_HIP(hipMemcpyAsync(G, c.G, sizeof(double) * pl.K, hipMemcpyDeviceToHost, c.st));
+    if (alpha) TNSLQ_HIP(hipMemcpyAsync(alpha, c.alpha, sizeof(double) * pl.K * pl.m, hipMemcpyDeviceToHost, c.st));
+    if (beta)
+        TNSLQ_HIP(hipMemcpyAsync(beta, c.beta, sizeof(double) * pl.K * (pl.m + 1), hipMemcpyDeviceToHost, c.st));
+    if (F) TNSLQ_HIP(hipMemcpyAsync(F, c.F, sizeof(double) * pl.K * pl.m, hipMemcpyDeviceToHost, c.st));
+    TNSLQ_HIP(hipStreamSynchronize(c.st));
+    if (steps) std::copy(hsteps.begin(), hsteps.end(), steps);
+    zero_result(res);
+    res->trace_norm = s[0];
+    res->trace_norm_se = s[1];
+    res->logneg = s[2];
+    res->logneg_se = s[3];
+    res->steps_done = r.jdone;
+    res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
+    res->swapped_ab = pl.swapped;
+    res->n_matvecs = r.jdone;
+    res->n_contract_launches = c.n_launch;
+    res->t_layout_ms = elapsed(r.e_start, r.e_layout);
+    for (int j = 1; j <= r.jdone; ++j) {
+        const StepEvents &e = r.se[j];
+        res->t_matvec_ms += elapsed(e.mv0(), e.mv1());
+        for (int ch = 0; ch < e.nchunk; ++ch) {
+            res->t_contract1_ms += elapsed(ch == 0 ? e.mv0() : e.pa(ch - 1), e.c1(ch));
+            res->t_contract2_ms += elapsed(e.c1(ch), e.c2(ch));
+        }
+        res->t_lanczos_ms += elapsed(e.mv1(), e.lz1());
+    }
+    res->t_total_ms = tm.ms();
+    if (!std::isfinite(res->logneg)) return fail(TNSLQ_E_NONFINITE, "estimate is not finite (trace norm %g)", s[0]);
+    return TNSLQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tnslq_status_str(int s) {
+    switch (s) {
+        case TNSLQ_OK: return "ok";
+        case TNSLQ_E_ARG: return "invalid argument";
+        case TNSLQ_E_PARTITION: return "invalid partition";
+        case TNSLQ_E_DTYPE: return "invalid dtype";
+        case TNSLQ_E_WORKSPACE: return "workspace too small";
+        case TNSLQ_E_DEVICE: return "device error";
+        case TNSLQ_E_NONFINITE: return "non-finite result";
+        default: return "unknown status";
+    }
+}
+
+const char *tnslq_last_error(void) { return g_err.c_str(); }
+
+int tnslq_version(void) { return 1; }
+
+int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt, size_t *bytes) {
+    int rc;
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    if ((rc = check_options(opt))) return rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) {
+        *bytes = 0;
+        return TNSLQ_OK;
+    }
+    Plan pl;
+    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1, pl))) return rc;
+    *bytes = pl.total;
+    return TNSLQ_OK;
+}
+
+int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part, const tnslq_options *opt, void *ws_dev,
+                 size_t ws_bytes, void *stream, tnslq_result *res, double *G_host, double *alpha_host,
+                 double *beta_host, double *F_host, int *steps_host) {
+    Timer tm;
+    int rc;
+    g_err.clear();
+    if (!res) return fail(TNSLQ_E_ARG, "result is NULL");
+    if ((rc = check_options(opt))) return rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return trivial(opt, res, G_host, alpha_host, beta_host, F_host, steps_host);
+    Run r;
+    if ((rc = run_begin(r, dtype, part, opt, psi_dev, ws_dev, ws_bytes, stream))) return rc;
+    if ((rc = run_steps(r, opt->n_steps, opt->stop_tol))) return rc;
+    return run_finish(r, res, G_host, alpha_host, beta_host, F_host, steps_host, tm);
+}
+
+int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n_vectors, int precision,
+                                   size_t *bytes) {
+    int rc;
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
+    Plan pl;
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, pl))) return rc;
+    *bytes = pl.total;
+    return TNSLQ_OK;
+}
+
+int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors, const void *X_dev,
+                   void *Y_dev, int precision, void *ws_dev, size_t ws_bytes, void *stream) {
+    int rc;
+    g_err.clear();
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
+    Ctx c;
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, c.pl))) return rc;
+    if (!psi_dev || !X_dev || !Y_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (X_dev == Y_dev) return fail(TNSLQ_E_ARG, "X and Y alias");
+    if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < c.pl.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, c.pl.total);
+    bind(c, ws_dev, (hipStream_t)stream);
+    const Plan &pl = c.pl;
+    if ((rc = do_layout(c, psi_dev))) return rc;
+    TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.psX, c.st));
+    for (int k0 = 0; k0 < pl.K; k0 += pl.kc) {
+        const int kcur = std::min(pl.kc, pl.K - k0);
+        if ((rc = contract_chunk(c, k0, kcur, nullptr, nullptr))) return rc;
+        TNSLQ_HIP(launch_reduce_partials(pl.prec == TNSLQ_FP64, c.Ypart, pl.S, (int64_t)pl.kc * pl.dAB, pl.dA, pl.dB,
+                                         kcur, pl.swapped, (double2 *)Y_dev + (size_t)k0 * pl.dAB, c.st));
+    }
+    return TNSLQ_OK;
+}
+
+int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev, int n_probes, int n_steps,
+                     double *F_dev, void *stream) {
+    g_err.clear();
+    if (!alpha_dev || !beta_dev || !F_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (n_probes < 1 || n_steps < 1 || n_steps > TNSLQ_MAX_STEPS) return fail(TNSLQ_E_ARG, "bad sizes");
+    TNSLQ_HIP(launch_quadrature(alpha_dev, beta_dev, steps_dev, n_probes, n_steps, 1, n_steps, F_dev,
+                                (hipStream_t)stream));
+    return TNSLQ_OK;
+}
+
+int tnslq_probes(uint64_t seed, uint64_t probe_offset, int n_probes, int64_t d, void *X_dev, void *stream) {
+    g_err.clear();
+    if (!X_dev) return fail(TNSLQ_E_ARG, "X is NULL");
+    if (n_probes < 1 || n_probes > 65535 || d < 1) return fail(TNSLQ_E_ARG, "bad sizes");
+    TNSLQ_HIP(launch_probes_plain(seed, probe_offset, n_probes, d, (double2 *)X_dev, (hipStream_t)stream));
+    return TNSLQ_OK;
+}
+
+int tnslq_mlp_workspace_bytes(int batch, size_t *bytes) {
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    if (batch < 1) return fail(TNSLQ_E_ARG, "batch must be >= 1");
+    *bytes = mlp_ws_bytes(batch);
+    return TNSLQ_OK;
+}
+
+int tnslq_mlp_forward(const float *params, const float *norm, const float *x, int batch, float *out, void *ws,
+                      size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!params || !norm || !x || !out || !ws) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (batch < 1 || batch > (1 << 20)) return fail(TNSLQ_E_ARG, "batch %d outside [1, 2^20]", batch);
+    if (ws_bytes < mlp_ws_bytes(batch)) return fail(TNSLQ_E_WORKSPACE, "workspace too small");
+    TNSLQ_HIP(mlp_forward(params, norm, x, batch, out, ws, (hipStream_t)stream));
+    return TNSLQ_OK;
+}
+
+int tnslq_mlp_loss_grad(const float *params, const float *norm, const float *x, const float *r, int batch,
+                        float *loss, float *grad, void *ws, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!params || !norm || !x || !r || !grad || !ws) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (batch < 1 || batch > (1 << 20)) return fail(TNSLQ_E_ARG, "batch %d outside [1, 2^20]", batch);
+    if (ws_bytes < mlp_ws_bytes(batch)) return fail(TNSLQ_E_WORKSPACE, "workspace too small");
+    TNSLQ_HIP(mlp_loss_grad(params, norm, x, r, nullptr, batch, loss, grad, ws, (hipStream_t)stream));
+    return TNSLQ_OK;
+}
+
+int tnslq_mlp_adam(float *params, float *m, float *v, const float *grad, int t, float lr, void *stream) {
+    g_err.clear();
+    if (!params || !m || !v || !grad) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (t < 1) return fail(TNSLQ_E_ARG, "t must be >= 1");
+    TNSLQ_HIP(mlp_adam(params, m, v, grad, TNSLQ_MLP_NPARAMS, t, lr, (hipStream_t)stream));
+    return TNSLQ_OK;
+}
+
+int tnslq_mlp_train(float *params, float *m, float *v, const float *norm, const float *x, const float *r,
+                    const int *idx, int batch, int n_batches, int t0, float lr, float *losses, void *ws,
+                    size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!params || !m || !v || !norm || !x || !r || !idx || !ws) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (batch < 1 || batch > (1 << 20) || n_batches < 0 || t0 < 1) return fail(TNSLQ_E_ARG, "bad sizes");
+    const size_t need = mlp_ws_bytes(batch) + (size_t)TNSLQ_MLP_NPARAMS * 4 + 256;
+    if (ws_bytes < need) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    float *grad = (float *)((char *)ws + (mlp_ws_bytes(batch) + 255) / 256 * 256);
+    for (int s = 0; s < n_batches; ++s) {
+        TNSLQ_HIP(mlp_loss_grad(params, norm, x, r, idx + (size_t)s * batch, batch, losses ? losses + s : nullptr,
+                                grad, ws, st));
+        TNSLQ_HIP(mlp_adam(params, m, v, grad, TNSLQ_MLP_NPARAMS, t0 + s, lr, st));
+    }
+    return TNSLQ_OK;
+}
+
+int tnslq_logneg_surrogate(const void *psi_dev, int dtype, const tnslq_partition *part, const tnslq_options *opt,
+                           const float *params, const float *norm, float y_scale, int early_steps, double tol,
+                           void *ws_dev, size_t ws_bytes, void *stream, tnslq_result *res, double *info) {
+    Timer tm;
+    int rc;
+    g_err.clear();
+    if (!res || !info || !params || !norm) return fail(TNSLQ_E_ARG, "NULL pointer");
+    if ((rc = check_options(opt))) return rc;
+    if (early_steps != 8) return fail(TNSLQ_E_ARG, "early_steps must be 8 (network input width)");
+    if (opt->n_steps < early_steps) return fail(TNSLQ_E_ARG, "n_steps must be >= early_steps");
+    if (!(tol > 0.0)) return fail(TNSLQ_E_ARG, "tol must be > 0");
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) {
+        info[0] = 0.0;
+        info[1] = 0.0;
+        info[2] = 0.0;
+        info[3] = 0.0;
+        info[4] = 0.0;
+        return trivial(opt, res, nullptr, nullptr, nullptr, nullptr, nullptr);
+    }
+    Run r;
+    if ((rc = run_begin(r, dtype, part, opt, psi_dev, ws_dev, ws_bytes, stream))) return rc;
+    if ((rc = run_steps(r, early_steps, 0.0))) return rc;
+    Ctx &c = r.c;
+    const Plan &pl = c.pl;
+    if ((rc = quad_stats(c, r.jdone, r.jdone, r.jdone, r.jdone, nullptr))) return rc;
+    // features in the caller's roles (log2 d_A, log2 d_B as given)
+    const double dA = double(int64_t(1) << part->n_a), dB = double(int64_t(1) << part->n_b);
+    TNSLQ_HIP(launch_features(c.alpha, c.beta, pl.K, pl.m, early_steps, double(pl.dAB), dA, dB, double(pl.dE), c.feat,
+                              c.st));
+    float *out = c.feat + 32;
+    TNSLQ_HIP(mlp_forward(params, norm, c.feat, 1, out, c.mlpws, c.st));
+    float u[2];
+    double s[4];
+    TNSLQ_HIP(hipMemcpyAsync(u, out, sizeof u, hipMemcpyDeviceToHost, c.st));
+    TNSLQ_HIP(hipMemcpyAsync(s, c.stats + (size_t)(r.jdone - 1) * 4, sizeof s, hipMemcpyDeviceToHost, c.st));
+    TNSLQ_HIP(hipStreamSynchronize(c.st));
+    const double e_early = s[2];
+    const double mu = e_early + (double)y_scale * u[0];
+    const double sigma = (double)y_scale * std::exp(0.5 * (double)u[1]);
+    info[0] = mu;
+    info[1] = sigma;
+    info[2] = e_early;
+    if (std::isfinite(mu) && std::isfinite(sigma) && sigma <= tol * std::max(std::fabs(mu), 1.0)) {
+        if ((rc = run_finish(r, res, nullptr, nullptr, nullptr, nullptr, nullptr, tm))) return rc;
+        res->logneg = mu;
+        res->logneg_se = sigma;
+        info[3] = 0.0;
+        info[4] = std::nan("");
+        return TNSLQ_OK;
+    }
+    if ((rc = run_steps(r, opt->n_steps, opt->stop_tol))) return rc;
+    if ((rc = run_finish(r, res, nullptr, nullptr, nullptr, nullptr, nullptr, tm))) return rc;
+    info[3] = 1.0;
+    info[4] = res->logneg;
+    return TNSLQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Operand preparation: regrouping psi into the two contraction layouts
+// (Sec. IV: grouping indices turns the network into matrix products; Sec. V:
+// psi_{1..L} -> psi_{abc}), the Hutchinson probe block (Sec. III,
+// Algorithm 1), and the conversions between caller vectors and the
+// contraction operands.
+#include "tnslq_internal.h"
+
+namespace tnslq {
+namespace {
+
+// ---------------------------------------------------------------- psi
+template <int DTYPE>
+__device__ inline double2 load_psi(const void *psi, int64_t i) {
+    if constexpr (DTYPE == TNSLQ_C128) {
+        return ((const double2 *)psi)[i];
+    } else {
+        float2 v = ((const float2 *)psi)[i];
+        return make_double2(v.x, v.y);
+    }
+}
+
+// out[o] = psi[in(o)] (conjugated if asked) where bit t of o is bit map[t]
+// of in.  One output element per thread step, consecutive threads write
+// consecutive elements.
+template <int PREC, int DTYPE>
+__global__ void __launch_bounds__(256) k_permute(const void *__restrict__ psi, void *__restrict__ out,
+                                                 int64_t ps, int64_t D, PermDesc pd, int conj) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < D; o += stride) {
+        int64_t in = 0;
+        for (int t = 0; t < pd.L; ++t) in |= ((o >> t) & 1) << pd.map[t];
+        double2 v = load_psi<DTYPE>(psi, in);
+        if (conj) v.y = -v.y;
+        store_planes<PREC>(out, ps, o, v.x, v.y);
+    }
+}
+
+// ---------------------------------------------------------------- probes
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t n) {
+    // n-th output of SplitMix64 seeded with `seed` (state advances by the
+    // golden gamma before each output).
+    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Probe k's value at layout position (a, b).  Without the role swap the flat
+// index is a * dB + b; with it, layout (a, b) is the caller's (b, a) and the
+// value is conjugated (the operator on the swapped layout is the complex
+// conjugate of rho^{T_B}, so the conjugated probe reproduces the same Krylov
+// coefficients).
+__device__ inline double2 probe_value(uint64_t seed, uint64_t offset, int k, int64_t a, int64_t b,
+                                      int64_t dA, int64_t dB, int swapped) {
+    const int64_t n = dA * dB;
+    const int64_t i = swapped ? (b * dA + a) : (a * dB + b);
+    const uint64_t r = splitmix64(seed, (offset + (uint64_t)k) * (uint64_t)n + (uint64_t)i) >> 62;
+    double re = (r == 0) ? 1.0 : (r == 2 ? -1.0 : 0.0);
+    double im = (r == 1) ? 1.0 : (r == 3 ? -1.0 : 0.0);
+    if (swapped) im = -im;
+    return make_double2(re, im);
+}
+
+// q_1 = phi / beta_1 with beta_1 = ||phi|| = sqrt(d_A d_B) (unit-modulus
+// entries), in [k][a][b] order, and its transposed low-precision copy Xt.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_probe_init(uint64_t seed, uint64_t offset, int swapped,
+                                                    int64_t dA, int64_t dB, double2 *__restrict__ q,
+                                                    void *__restrict__ Xt, int64_t xt_ps,
+                                                    double *__restrict__ beta, int m) {
+    const int k = blockIdx.y;
+    const int64_t n = dA * dB;
+    const double b1 = sqrt((double)n);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        // q in [a][b] order, b fastest
+        const int64_t a = e / dB, b = e % dB;
+        double2 v = probe_value(seed, offset, k, a, b, dA, dB, swapped);
+        q[(int64_t)k * n + e] = make_double2(v.x / b1, v.y / b1);
+        // Xt in [b][a] order, a fastest
+        const int64_t b2 = e / dA, a2 = e % dA;
+        double2 u = probe_value(seed, offset, k, a2, b2, dA, dB, swapped);
+        store_planes<PREC>(Xt, xt_ps, (int64_t)k * n + e, u.x / b1, u.y / b1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta[(int64_t)k * (m + 1)] = b1;
+}
+
+// Plain probe block for the caller (complex128, caller's index order).
+__global__ void k_probes(uint64_t seed, uint64_t offset, int64_t d, double2 *__restrict__ X) {
+    const int k = blockIdx.y;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d; i += stride)
+        X[(int64_t)k * d + i] = probe_value(seed, offset, k, i / d, i % d, 1, d, 0);
+}
+
+// Caller vectors X[k][a_o][b_o] -> transposed contraction operand Xt[k][b][a]
+// in layout roles (conjugated and index-swapped when the roles are swapped).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_load_vectors(const double2 *__restrict__ X, int64_t dA,
+                                                      int64_t dB, int swapped, void *__restrict__ Xt,
+                                                      int64_t xt_ps) {
+    const int k = blockIdx.y;
+    const int64_t n = dA * dB;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int64_t b = e / dA, a = e % dA;   // Xt position [b][a]
+        double2 v;
+        if (swapped) {
+            v = X[(int64_t)k * n + b * dA + a];  // caller (a_o, b_o) = (b, a)
+            v.y = -v.y;
+        } else {
+            v = X[(int64_t)k * n + a * dB + b];
+        }
+        store_planes<PREC>(Xt, xt_ps, (int64_t)k * n + e, v.x, v.y);
+    }
+}
+
+// Y = sum over split-K partials, written in the caller's index order.
+template <typename AccT>
+__global__ void __launch_bounds__(256) k_reduce_partials(const AccT *__restrict__ part, int S,
+                                                         int64_t split_stride, int64_t dA, int64_t dB,
+                                                         int swapped, double2 *__restrict__ Y) {
+    const int k = blockIdx.y;
+    const int64_t n = dA * dB;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        // e indexes the caller's order
+        int64_t src;
+        if (swapped) {
+            // caller (a_o, b_o) = layout (b, a): e = a_o * dB_o + b_o, dB_o = dA
+            const int64_t ao = e / dA, bo = e % dA;
+            src = bo * dB + ao;
+        } else {
+            src = e;
+        }
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < S; ++s) {
+            AccT v = part[s * split_stride + (int64_t)k * n + src];
+            re += (double)v.x;
+            im += (double)v.y;
+        }
+        Y[(int64_t)k * n + e] = make_double2(re, swapped ? -im : im);
+    }
+}
+
+inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t ps, int64_t D,
+                          const PermDesc &pd, int conj, hipStream_t st) {
+    dim3 grid(grid_for(D, 256 * 4, 65535 * 8)), block(256);
+#define TNSLQ_PERM(P, T) hipLaunchKernelGGL((k_permute<P, T>), grid, block, 0, st, psi, out, ps, D, pd, conj)
+    if (dtype == TNSLQ_C128) {
+        switch (prec) {
+            case TNSLQ_FP64: TNSLQ_PERM(TNSLQ_FP64, TNSLQ_C128); break;
+            case TNSLQ_FP32: TNSLQ_PERM(TNSLQ_FP32, TNSLQ_C128); break;
+            case TNSLQ_BF16X3: TNSLQ_PERM(TNSLQ_BF16X3, TNSLQ_C128); break;
+            default: TNSLQ_PERM(TNSLQ_BF16X6, TNSLQ_C128); break;
+        }
+    } else {
+        switch (prec) {
+            case TNSLQ_FP64: TNSLQ_PERM(TNSLQ_FP64, TNSLQ_C64); break;
+            case TNSLQ_FP32: TNSLQ_PERM(TNSLQ_FP32, TNSLQ_C64); break;
+            case TNSLQ_BF16X3: TNSLQ_PERM(TNSLQ_BF16X3, TNSLQ_C64); break;
+            default: TNSLQ_PERM(TNSLQ_BF16X6, TNSLQ_C64); break;
+        }
+    }
+#undef TNSLQ_PERM
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_init(int prec, const LzDims &z, uint64_t seed, uint64_t offset, int swapped,
+                             double2 *q, void *Xt, int64_t xt_ps, double *alpha, double *beta,
+                             hipStream_t st) {
+    (void)alpha;
+    dim3 grid(grid_for(z.n, 256 * 8, 4096), z.K), block(256);
+#define TNSLQ_PI(P) \
+    hipLaunchKernelGGL((k_probe_init<P>), grid, block, 0, st, seed, offset, swapped, z.dA, z.dB, q, Xt, xt_ps, beta, z.m)
+    switch (prec) {
+        case TNSLQ_FP64: TNSLQ_PI(TNSLQ_FP64); break;
+        case TNSLQ_FP32: TNSLQ_PI(TNSLQ_FP32); break;
+        case TNSLQ_BF16X3: TNSLQ_PI(TNSLQ_BF16X3); break;
+        default: TNSLQ_PI(TNSLQ_BF16X6); break;
+    }
+#undef TNSLQ_PI
+    return hipGetLastError();
+}
+
+hipError_t launch_probes_plain(uint64_t seed, uint64_t offset, int K, int64_t d, double2 *X,
+                               hipStream_t st) {
+    dim3 grid(grid_for(d, 256 * 8, 4096), K), block(256);
+    hipLaunchKernelGGL(k_probes, grid, block, 0, st, seed, offset, d, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_vectors(int prec, const double2 *X, int64_t dA, int64_t dB, int K, int swapped,
+                               void *Xt, int64_t xt_ps, hipStream_t st) {
+    dim3 grid(grid_for(dA * dB, 256 * 8, 4096), K), block(256);
+#define TNSLQ_LV(P) hipLaunchKernelGGL((k_load_vectors<P>), grid, block, 0, st, X, dA, dB, swapped, Xt, xt_ps)
+    switch (prec) {
+        case TNSLQ_FP64: TNSLQ_LV(TNSLQ_FP64); break;
+        case TNSLQ_FP32: TNSLQ_LV(TNSLQ_FP32); break;
+        case TNSLQ_BF16X3: TNSLQ_LV(TNSLQ_BF16X3); break;
+        default: TNSLQ_LV(TNSLQ_BF16X6); break;
+    }
+#undef TNSLQ_LV
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(int accfp64, const void *part, int S, int64_t split_stride, int64_t dA,
+                                  int64_t dB, int K, int swapped, double2 *Y, hipStream_t st) {
+    dim3 grid(grid_for(dA * dB, 256 * 8, 4096), K), block(256);
+    if (accfp64)
+        hipLaunchKernelGGL((k_reduce_partials<double2>), grid, block, 0, st, (const double2 *)part, S,
+                           split_stride, dA, dB, swapped, Y);
+    else
+        hipLaunchKernelGGL((k_reduce_partials<float2>), grid, block, 0, st, (const float2 *)part, S,
+                           split_stride, dA, dB, swapped, Y);
+    return hipGetLastError();
+}
+
+}  // namespace tnslq

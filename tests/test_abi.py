@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and validates arguments without touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1809_01685_amd as T
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tnslq.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnslq_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libtnslq.so not built")
+    return T.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(T._SIGS), "binding and header disagree"
+
+
+def test_version_and_status_strings(L):
+    assert T.tnslq_version() == 1
+    assert T.tnslq_status_str(0) == "ok"
+    assert T.tnslq_status_str(-2) == "invalid partition"
+    assert T.tnslq_status_str(-4) == "workspace too small"
+
+
+def test_workspace_query_and_plan(L):
+    o = T.make_options(32, 40, reorth=True, precision="fp32")
+    n = T.tnslq_workspace_bytes(T.TNSLQ_C64, 20, list(range(6)), list(range(8, 14)), o)
+    # at least the two regrouped copies of psi (2 planes x 4 bytes x 2^20 each)
+    assert n >= 2 * 2 * 4 * (1 << 20)
+    # the Lanczos basis with reorthogonalisation: 41 slots x 32 probes x 4096 x 16 bytes
+    assert n >= 41 * 32 * 4096 * 16
+    o2 = T.make_options(32, 40, reorth=False, precision="fp32")
+    assert T.tnslq_workspace_bytes(T.TNSLQ_C64, 20, list(range(6)), list(range(8, 14)), o2) < n
+
+
+@pytest.mark.parametrize("a,b,code", [
+    ([0, 1], [1, 2], -2),      # overlap
+    ([0, 0], [2], -2),         # repeat
+    ([0, 10], [2], -2),        # out of range
+])
+def test_bad_partitions_rejected(L, a, b, code):
+    o = T.make_options(4, 4)
+    with pytest.raises(T.TnslqError) as ei:
+        T.tnslq_workspace_bytes(T.TNSLQ_C64, 6, a, b, o)
+    assert ei.value.status == code
+
+
+def test_bad_options_rejected(L):
+    p = T._partition(6, [0], [1])
+    n = ctypes.c_size_t(0)
+    for o in (T.make_options(0, 4), T.make_options(4, 0), T.make_options(4, 500), T.make_options(4, 4, precision=9)):
+        rc = L.tnslq_workspace_bytes(0, ctypes.byref(p), ctypes.byref(o), ctypes.byref(n))
+        assert rc == -1
+    assert L.tnslq_workspace_bytes(7, ctypes.byref(p), ctypes.byref(T.make_options(4, 4)), ctypes.byref(n)) == -3
+
+
+def test_logneg_validates_before_device_work(L):
+    p = T._partition(6, [0], [1])
+    o = T.make_options(4, 4)
+    res = T.Result()
+    # NULL psi with a non-trivial partition: argument error, no launch
+    rc = L.tnslq_logneg(None, 0, ctypes.byref(p), ctypes.byref(o), None, 0, None, ctypes.byref(res),
+                        None, None, None, None, None)
+    assert rc == -1
+    assert "NULL" in T.tnslq_last_error()
+
+
+def test_empty_subsystem_is_exactly_zero_without_device(L):
+    p = T._partition(6, [0, 1], [])
+    o = T.make_options(3, 5)
+    res = T.Result()
+    G = np.full(3, -1.0)
+    rc = L.tnslq_logneg(None, 0, ctypes.byref(p), ctypes.byref(o), None, 0, None, ctypes.byref(res),
+                        G.ctypes.data_as(ctypes.c_void_p), None, None, None, None)
+    assert rc == 0
+    assert res.logneg == 0.0 and res.trace_norm == 1.0
+    assert np.all(G == 1.0)
+
+
+def test_mlp_argument_checks(L):
+    n = ctypes.c_size_t(0)
+    assert L.tnslq_mlp_workspace_bytes(0, ctypes.byref(n)) == -1
+    assert L.tnslq_mlp_workspace_bytes(64, ctypes.byref(n)) == 0 and n.value > 64 * 256 * 4
+    assert L.tnslq_mlp_adam(None, None, None, None, 1, 1e-3, None) == -1

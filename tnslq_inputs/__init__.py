@@ -266,3 +266,10 @@ def mlp_init_params(seed: int) -> np.ndarray:
         else:
             parts.append(np.zeros(shape))
     return np.concatenate(parts).astype(np.float32)
+
+
+def random_vectors(n_vectors: int, dim: int, seed: int) -> np.ndarray:
+    """(n_vectors, dim) complex128 vectors with i.i.d. N(0,1) real and
+    imaginary parts, from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n_vectors, dim)) + 1j * rng.standard_normal((n_vectors, dim))
