@@ -20,7 +20,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
-#include "../../include/tnslq.h"
+#include "tnslq.h"
 
 namespace tnslq {
 
