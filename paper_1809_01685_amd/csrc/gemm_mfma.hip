@@ -1,0 +1,411 @@
+// Complex "NT" contraction C = A * B^T on the matrix cores (gfx950), for the
+// two contractions of Sec. V Eq. 4, in three arithmetics:
+//   BF16X3  operands split as hi + lo BF16 pieces, three real products per
+//           real product (hi*hi + hi*lo + lo*hi), v_mfma_f32_16x16x32_bf16,
+//           FP32 accumulation;
+//   FP32    v_mfma_f32_16x16x4_f32 with FP32 accumulation, the matrix-core
+//           sums flushed every 64 reduction terms into a second accumulator
+//           so that no FP32 running sum grows past 64 terms;
+//   FP64    v_mfma_f64_16x16x4_f64.
+//
+// Complex products use four real MFMA chains:
+//   Re C += Re A Re B + (-Im A) Im B,   Im C += Re A Im B + Im A Re B,
+// the sign of Im A applied by flipping sign bits in registers.
+//
+// Tiling (wave64): a block of 8 waves computes a 128 x 128 complex output
+// tile, each wave 64 x 32 (4 x 2 MFMA tiles of 16 x 16), two waves per SIMD
+// so that one wave's LDS waits overlap the other's matrix instructions.  A
+// reduction step stages 64 bytes of every row of each operand plane in LDS
+// (32 BF16, 16 FP32 or 8 FP64 reduction terms), double buffered: while the
+// waves multiply step i out of one buffer, step i+1 (loaded from global memory
+// one step earlier) is written to the other and step i+2 is loaded into
+// registers, one barrier per step.  The four 16-byte units of a staged row are
+// XOR-swizzled by ((row >> 1) ^ (row >> 2)) & 3 so that the fragment reads of
+// 8 or 16 consecutive rows hit distinct banks.  Each lane's 16-byte fragment
+// feeds one BF16 MFMA (8 terms), four FP32 MFMAs or two FP64 MFMAs; A and B
+// fragments pair the same reduction terms, so the order in which the terms of
+// a unit enter the sum does not matter.
+//
+// Block order: the hardware deals blocks to the eight XCDs round robin, so
+// block b is renumbered to give XCD b % 8 a contiguous range of output tiles,
+// walked in groups of 4 tile rows; the ~32 blocks resident on one XCD then
+// cover a compact 4 x 8 patch of tiles and share their A and B tiles in that
+// XCD's L2.
+#include "tnslq_internal.h"
+
+namespace tnslq {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+constexpr int BM = 128, BN = 128;
+constexpr int ROWB = 64;                 // LDS bytes per staged row
+constexpr int TILEB = BM * ROWB;         // LDS bytes per plane tile
+constexpr int GROUP_M = 4;
+constexpr int WAVES_M = 2, WAVES_N = 4;
+constexpr int TM = BM / (16 * WAVES_M), TN = BN / (16 * WAVES_N);
+constexpr int NT = 64 * WAVES_M * WAVES_N;
+constexpr int UPT = BM * 4 / NT;         // 16-byte staging units per thread per plane
+
+template <int PREC> struct MP;
+template <> struct MP<TNSLQ_BF16X3> {
+    static constexpr int NPL = 4;        // re_hi, re_lo, im_hi, im_lo
+    static constexpr int BK = 32;        // reduction terms per stage
+    static constexpr int EB = 2;         // bytes per stored piece
+    using acc = f32x4;
+};
+template <> struct MP<TNSLQ_FP32> {
+    static constexpr int NPL = 2;
+    static constexpr int BK = 16;
+    static constexpr int EB = 4;
+    using acc = f32x4;
+};
+template <> struct MP<TNSLQ_FP64> {
+    static constexpr int NPL = 2;
+    static constexpr int BK = 8;
+    static constexpr int EB = 8;
+    using acc = f64x4;
+};
+
+template <int PREC> constexpr int stage_bytes() { return 2 * MP<PREC>::NPL * TILEB; }
+template <int PREC> constexpr int lds_bytes() { return 2 * stage_bytes<PREC>(); }
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ inline uint4 neg_bf16x8(uint4 v) {
+    return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+}
+__device__ inline uint4 neg_f32x4(uint4 v) {
+    return make_uint4(v.x ^ 0x80000000u, v.y ^ 0x80000000u, v.z ^ 0x80000000u, v.w ^ 0x80000000u);
+}
+__device__ inline uint4 neg_f64x2(uint4 v) { return make_uint4(v.x, v.y ^ 0x80000000u, v.z, v.w ^ 0x80000000u); }
+__device__ inline float f32_at(uint4 v, int t) {
+    return __uint_as_float(t == 0 ? v.x : (t == 1 ? v.y : (t == 2 ? v.z : v.w)));
+}
+__device__ inline double f64_at(uint4 v, int t) {
+    return t == 0 ? __hiloint2double((int)v.y, (int)v.x) : __hiloint2double((int)v.w, (int)v.z);
+}
+
+// byte offset of 16-byte unit `u` of staged row `row` within a plane tile
+__device__ inline int loff(int row, int u) { return row * ROWB + 16 * (u ^ (((row >> 1) ^ (row >> 2)) & 3)); }
+
+// One reduction stage of the complex product for the wave's TM x TN tiles.
+template <int PREC>
+__device__ __forceinline__ void stage_mfma(const uint4 (&fa)[TM][MP<PREC>::NPL], const uint4 (&fb)[TN][MP<PREC>::NPL],
+                                           typename MP<PREC>::acc (&accr)[TM][TN],
+                                           typename MP<PREC>::acc (&acci)[TM][TN]) {
+    if constexpr (PREC == TNSLQ_BF16X3) {
+        uint4 nai[TM][2];
+#pragma unroll
+        for (int x = 0; x < TM; ++x) {
+            nai[x][0] = neg_bf16x8(fa[x][2]);
+            nai[x][1] = neg_bf16x8(fa[x][3]);
+        }
+        // split terms (p, q) in {(hi,hi), (hi,lo), (lo,hi)}
+#pragma unroll
+        for (int term = 0; term < 3; ++term) {
+            const int p = term == 2 ? 1 : 0;
+            const int q = term == 1 ? 1 : 0;
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]), as_bf16x8(fb[b][q]),
+                                                                          accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]),
+                                                                          as_bf16x8(fb[b][2 + q]), acci[a][b], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(nai[a][p]),
+                                                                          as_bf16x8(fb[b][2 + q]), accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][2 + p]),
+                                                                          as_bf16x8(fb[b][q]), acci[a][b], 0, 0, 0);
+                }
+        }
+    } else if constexpr (PREC == TNSLQ_FP32) {
+        uint4 nai[TM];
+#pragma unroll
+        for (int x = 0; x < TM; ++x) nai[x] = neg_f32x4(fa[x][1]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    const float ar = f32_at(fa[a][0], t), ai = f32_at(fa[a][1], t), nai_t = f32_at(nai[a], t);
+                    const float br = f32_at(fb[b][0], t), bi = f32_at(fb[b][1], t);
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, accr[a][b], 0, 0, 0);
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai_t, bi, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, acci[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, acci[a][b], 0, 0, 0);
+                }
+    } else {
+        uint4 nai[TM];
+#pragma unroll
+        for (int x = 0; x < TM; ++x) nai[x] = neg_f64x2(fa[x][1]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) {
+                    const double ar = f64_at(fa[a][0], t), ai = f64_at(fa[a][1], t), nai_t = f64_at(nai[a], t);
+                    const double br = f64_at(fb[b][0], t), bi = f64_at(fb[b][1], t);
+                    accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr[a][b], 0, 0, 0);
+                    accr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai_t, bi, accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci[a][b], 0, 0, 0);
+                }
+    }
+}
+
+// Main reduction loop over [kbeg, kend) for the block's output tile at
+// (i0, j0), accumulating into (outr, outi).  FULL = the tile lies inside C, so
+// no operand row needs zeroing.
+template <int PREC, bool FULL>
+__device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i0, int64_t j0, int64_t kbeg,
+                                         int64_t kend, typename MP<PREC>::acc (&outr)[TM][TN],
+                                         typename MP<PREC>::acc (&outi)[TM][TN]) {
+    using P = MP<PREC>;
+    using Acc = typename P::acc;
+    constexpr int NPL = P::NPL, BK = P::BK, EPU = 16 / P::EB;   // elements per 16-byte unit
+    constexpr int STAGEB = stage_bytes<PREC>();
+    // FP32 keeps a second accumulator: the matrix-core sums restart every
+    // FLUSH stages (64 terms) and are added into (outr, outi).
+    constexpr bool TWO_LEVEL = PREC == TNSLQ_FP32;
+    constexpr int FLUSH = 4;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WAVES_N, wn = wid % WAVES_N;
+    const char *A = (const char *)g.A;
+    const char *B = (const char *)g.B;
+
+    // global -> register staging: per plane, UPT 16-byte units of A and of B.
+    // Rows past the edge of A or B read a clamped in-range row and are zeroed.
+    uint4 ra[NPL][UPT], rb[NPL][UPT];
+    const int urow0 = tid >> 2, ucol = tid & 3;   // unit u = tid + NT t: row = u / 4, unit = u % 4
+    const char *arow[UPT], *brow[UPT];
+    bool aok[UPT], bok[UPT];
+#pragma unroll
+    for (int tt = 0; tt < UPT; ++tt) {
+        const int row = urow0 + (NT / 4) * tt;
+        const int64_t gi = i0 + row, gj = j0 + row;
+        aok[tt] = FULL || gi < g.M;
+        bok[tt] = FULL || gj < g.N;
+        arow[tt] = A + ((gi < g.M ? gi : g.M - 1) * g.lda + EPU * ucol) * P::EB;
+        brow[tt] = B + ((gj < g.N ? gj : g.N - 1) * g.ldb + EPU * ucol) * P::EB;
+    }
+    auto gload = [&](int64_t l0) {
+#pragma unroll
+        for (int tt = 0; tt < UPT; ++tt) {
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                uint4 va = *(const uint4 *)(arow[tt] + (p * g.a_ps + l0) * P::EB);
+                uint4 vb = *(const uint4 *)(brow[tt] + (p * g.b_ps + l0) * P::EB);
+                if constexpr (FULL) {
+                    ra[p][tt] = va;
+                    rb[p][tt] = vb;
+                } else {
+                    ra[p][tt] = aok[tt] ? va : make_uint4(0, 0, 0, 0);
+                    rb[p][tt] = bok[tt] ? vb : make_uint4(0, 0, 0, 0);
+                }
+            }
+        }
+    };
+    auto lstore = [&](int buf) {
+        char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
+#pragma unroll
+        for (int tt = 0; tt < UPT; ++tt) {
+            const int off = loff(urow0 + (NT / 4) * tt, ucol);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                *(uint4 *)(As + p * TILEB + off) = ra[p][tt];
+                *(uint4 *)(Bs + p * TILEB + off) = rb[p][tt];
+            }
+        }
+    };
+
+    Acc accr[TM][TN], acci[TM][TN];
+    auto zero = [&]() {
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                accr[a][b] = Acc{0, 0, 0, 0};
+                acci[a][b] = Acc{0, 0, 0, 0};
+            }
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                outr[a][b] += accr[a][b];
+                outi[a][b] += acci[a][b];
+            }
+    };
+    zero();
+
+    const int frow = lane & 15, fk = lane >> 4;   // fragment row within a 16-row tile, k-unit
+    gload(kbeg);
+    lstore(0);
+    if (kbeg + BK < kend) gload(kbeg + BK);
+    __syncthreads();
+    int buf = 0, nstage = 0;
+    for (int64_t l0 = kbeg; l0 < kend; l0 += BK, buf ^= 1) {
+        const char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
+        uint4 fa[TM][NPL], fb[TN][NPL];
+#pragma unroll
+        for (int x = 0; x < TM; ++x) {
+            const int oa = loff(wm * TM * 16 + x * 16 + frow, fk);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) fa[x][p] = *(const uint4 *)(As + p * TILEB + oa);
+        }
+#pragma unroll
+        for (int x = 0; x < TN; ++x) {
+            const int ob = loff(wn * TN * 16 + x * 16 + frow, fk);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
+        }
+        if (l0 + BK < kend) {
+            lstore(buf ^ 1);
+            if (l0 + 2 * BK < kend) gload(l0 + 2 * BK);
+        }
+        stage_mfma<PREC>(fa, fb, accr, acci);
+        if constexpr (TWO_LEVEL) {
+            if (++nstage == FLUSH) {
+                flush();
+                zero();
+                nstage = 0;
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (TWO_LEVEL) {
+        if (nstage) flush();
+    } else {
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                outr[a][b] = accr[a][b];
+                outi[a][b] = acci[a][b];
+            }
+    }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
+    using Acc = typename MP<PREC>::acc;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wm = wid / WAVES_N, wn = wid % WAVES_N;
+
+    const int64_t ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    const int64_t per_split = ntm * ntn;
+    int64_t bid = blockIdx.x;
+    if (gridDim.x % 8 == 0) bid = (bid % 8) * (gridDim.x / 8) + bid / 8;
+    const int s = (int)(bid / per_split);
+    const int64_t t = bid % per_split;
+    const int64_t group = t / (GROUP_M * ntn);
+    const int64_t first_m = group * GROUP_M;
+    const int64_t gsize = (ntm - first_m) < GROUP_M ? (ntm - first_m) : GROUP_M;
+    const int64_t tm = first_m + (t % (GROUP_M * ntn)) % gsize;
+    const int64_t tn = (t % (GROUP_M * ntn)) / gsize;
+    const int64_t i0 = tm * BM, j0 = tn * BN;
+
+    const int64_t klen = g.Kr / g.S;
+    const int64_t kbeg = (int64_t)s * klen, kend = kbeg + klen;
+
+    Acc accr[TM][TN], acci[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            accr[a][b] = Acc{0, 0, 0, 0};
+            acci[a][b] = Acc{0, 0, 0, 0};
+        }
+    if (i0 + BM <= g.M && j0 + BN <= g.N)
+        mainloop<PREC, true>(g, lds, i0, j0, kbeg, kend, accr, acci);
+    else
+        mainloop<PREC, false>(g, lds, i0, j0, kbeg, kend, accr, acci);
+
+    // epilogue: output register r of lane l holds column l % 16 and row
+    // 4 * (l / 16) + r (FP32 accumulators) or row 4 * r + l / 16 (FP64)
+    const int frow = lane & 15, fk = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int orow = PREC == TNSLQ_FP64 ? 4 * r + fk : 4 * fk + r;
+                const int64_t i = i0 + wm * TM * 16 + a * 16 + orow;
+                const int64_t j = j0 + wn * TN * 16 + b * 16 + frow;
+                if (i >= g.M || j >= g.N) continue;
+                const int64_t addr = (j / g.cnb) * g.cbs + i * g.ldc + (j % g.cnb);
+                if constexpr (PREC == TNSLQ_FP64) {
+                    const double vr = accr[a][b][r], vi = acci[a][b][r];
+                    if (g.out_mode == 0)
+                        store_planes<PREC>(g.C, g.c_ps, addr, vr, vi);
+                    else
+                        ((double2 *)g.C)[s * g.c_split + addr] = make_double2(vr, vi);
+                } else {
+                    const float vr = accr[a][b][r], vi = acci[a][b][r];
+                    if (g.out_mode == 0)
+                        store_planes_f<PREC>(g.C, g.c_ps, addr, vr, vi);
+                    else
+                        ((float2 *)g.C)[s * g.c_split + addr] = make_float2(vr, vi);
+                }
+            }
+}
+
+template <int PREC>
+hipError_t launch(const GemmDesc &g, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_cgemm_nt_mfma<PREC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t nblocks = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.S;
+    if (nblocks < 1 || nblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_cgemm_nt_mfma<PREC>, dim3((unsigned)nblocks), dim3(NT), lds_bytes<PREC>(), st, g);
+    return hipGetLastError();
+}
+
+template <int PREC>
+bool supported(const GemmDesc &g) {
+    constexpr int EPU = 16 / MP<PREC>::EB;
+    const int64_t klen = g.Kr / g.S;
+    return g.Kr % g.S == 0 && klen % MP<PREC>::BK == 0 && g.lda % EPU == 0 && g.ldb % EPU == 0 &&
+           g.a_ps % EPU == 0 && g.b_ps % EPU == 0 && ((uintptr_t)g.A % 16) == 0 && ((uintptr_t)g.B % 16) == 0;
+}
+
+}  // namespace
+
+// Whether the matrix-core kernel takes this shape in this precision: the
+// reduction per split a multiple of one stage, 16-byte aligned rows.
+bool gemm_mfma_supported(int prec, const GemmDesc &g) {
+    switch (prec) {
+        case TNSLQ_BF16X3: return supported<TNSLQ_BF16X3>(g);
+        case TNSLQ_FP32: return supported<TNSLQ_FP32>(g);
+        case TNSLQ_FP64: return supported<TNSLQ_FP64>(g);
+        default: return false;
+    }
+}
+
+hipError_t launch_gemm_mfma(int prec, const GemmDesc &g, hipStream_t st) {
+    switch (prec) {
+        case TNSLQ_BF16X3: return launch<TNSLQ_BF16X3>(g, st);
+        case TNSLQ_FP32: return launch<TNSLQ_FP32>(g, st);
+        case TNSLQ_FP64: return launch<TNSLQ_FP64>(g, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tnslq

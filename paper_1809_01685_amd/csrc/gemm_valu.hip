@@ -167,7 +167,7 @@ hipError_t launch_gemm_valu(int prec, const GemmDesc &g, hipStream_t st) {
 }
 
 hipError_t launch_gemm(int prec, const GemmDesc &g, hipStream_t st) {
-    if (prec == TNSLQ_BF16X3 && gemm_bf16x3_supported(g)) return launch_gemm_bf16x3(g, st);
+    if (gemm_mfma_supported(prec, g)) return launch_gemm_mfma(prec, g, st);
     return launch_gemm_valu(prec, g, st);
 }
 

@@ -164,8 +164,8 @@ struct GemmDesc {
 
 hipError_t launch_gemm(int prec, const GemmDesc &g, hipStream_t st);
 hipError_t launch_gemm_valu(int prec, const GemmDesc &g, hipStream_t st);
-bool gemm_bf16x3_supported(const GemmDesc &g);
-hipError_t launch_gemm_bf16x3(const GemmDesc &g, hipStream_t st);
+bool gemm_mfma_supported(int prec, const GemmDesc &g);
+hipError_t launch_gemm_mfma(int prec, const GemmDesc &g, hipStream_t st);
 
 // ------------------------------------------------------------ layout
 struct PermDesc {
