@@ -120,3 +120,23 @@ def purity_from_environment(P: np.ndarray) -> float:
     m = P.reshape(d_a * d_b, d_c)
     rho_c = m.T @ m.conj()
     return float(np.real(np.sum(rho_c * rho_c.T)))
+
+
+def pt_matvec_entries_from_slabs(slab, d_c: int, x: np.ndarray, entries) -> np.ndarray:
+    """Selected outputs y[a, b] of Eq. 4 for one vector x (d_A x d_B), for a
+    state whose environment qubits are the leading ones, so that environment
+    slab c is the d_A x d_B matrix slab(c) = psi[c, :, :] (A rows, B columns).
+
+    For each c and each requested column b: u[b'] = sum_a' conj(M_c[a', b]) x[a', b'],
+    then y[a, b] += sum_b' M_c[a, b'] u[b'].
+    """
+    x = np.asarray(x, dtype=np.complex128)
+    entries = [(int(a), int(b)) for a, b in entries]
+    cols = sorted({b for _, b in entries})
+    y = np.zeros(len(entries), dtype=np.complex128)
+    for c in range(d_c):
+        m_c = slab(c)
+        u = {b: np.conj(np.asarray(m_c[:, b], dtype=np.complex128)) @ x for b in cols}
+        for t, (a, b) in enumerate(entries):
+            y[t] += np.asarray(m_c[a, :], dtype=np.complex128) @ u[b]
+    return y

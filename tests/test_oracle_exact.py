@@ -134,3 +134,17 @@ def test_random_state_formula_eq6():
     e = _le(psi, L, list(range(5)), list(range(5, 10)))
     want = analytic.random_state_logneg(32, 32, 64)
     assert abs(e - want) < 0.02 * want
+
+
+def test_sampled_entries_match_explicit_matvec():
+    # environment = the leading qubits, so slab c is psi[c] as a d_A x d_B matrix
+    L = 8
+    psi = ti.haar_state(L, 12)
+    a, b = [2, 3, 4], [5, 6, 7]
+    P = exact.regroup(psi, L, a, b)
+    x = ti.random_vectors(1, 64, seed=2)
+    y = exact.pt_matvec_explicit(P, x)[0].reshape(8, 8)
+    slab = lambda c: psi.reshape(4, 8, 8)[c]  # noqa: E731
+    entries = [(0, 3), (5, 3), (7, 0), (2, 6)]
+    got = exact.pt_matvec_entries_from_slabs(slab, 4, x[0].reshape(8, 8), entries)
+    assert np.allclose(got, [y[i, j] for i, j in entries], atol=1e-15)
