@@ -88,6 +88,51 @@ def cpu_baseline(psi, w, m_used, budget_s=30.0):
             "sample": f"{sample_desc}: {t:.2f} s, scaled x{n_slab} slabs x{K} probes x{m_used} Lanczos steps"}
 
 
+def run_forms(args, w, psi, L, a, b, m, ws):
+    """Each requested form on the same state and probes: seconds to the +-1%
+    target, the estimate, and its difference from the FP64 form both at the
+    stopping point and at a common step count (E_j from the quadrature values)."""
+    import numpy as np
+    import torch
+    import paper_1809_01685_amd as T
+    res = {}
+    traj = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if form == "surrogate":
+            from paper_1809_01685_amd import surrogate as S
+            model = S.Model.load()
+            r = S.surrogate_logneg(model, psi, L, a, b, w["n_probes"], m, tol=0.01, precision=w["precision"],
+                                   seed=args.seed, stop_tol=args.stop_tol, workspace=ws)
+        else:
+            r = T.tnslq_logneg(psi, L, a, b, w["n_probes"], m, reorth=w["reorth"], precision=form, seed=args.seed,
+                               stop_tol=args.stop_tol, workspace=None if form in ("fp64", "fp32") else ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+        entry = {"seconds": dt, "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_steps": r["steps_done"]}
+        if form == "surrogate":
+            entry.update({"mu": r["mu"], "sigma": r["sigma"], "e_early": r["e_early"],
+                          "used_fallback": r["used_fallback"]})
+        else:
+            G = r["beta"][:, :1] ** 2 * r["F"][:, :r["steps_done"]]
+            traj[form] = np.log2(G.mean(axis=0))
+        res[form] = entry
+        print(f"[bench] form {form}: {dt:.2f} s, E = {r['logneg']:.6f} after {r['steps_done']} steps",
+              file=sys.stderr, flush=True)
+    if "fp64" in traj:
+        j = min(len(t) for t in traj.values())
+        for form, t in traj.items():
+            res[form]["logneg_at_common_step"] = float(t[j - 1])
+            res[form]["error_vs_fp64_at_common_step"] = float(t[j - 1] - traj["fp64"][j - 1])
+        res["common_step"] = j
+        for form, e in res.items():
+            if isinstance(e, dict):
+                e["error_vs_fp64"] = float(e["logneg"] - res["fp64"]["logneg"])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +145,10 @@ def main():
     ap.add_argument("--probes", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="",
+                    help="comma list of extra forms to time on the same state and probes "
+                         "(fp64, fp32, bf16x3, surrogate); adds a 'forms' object with each form's "
+                         "time, estimate and error against the FP64 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
@@ -191,6 +240,8 @@ def main():
                      "frac": achieved / peak, "mfma_issue_frac": achieved * MFMA_PER_ALGO[w["precision"]] / peak,
                      "flops_per_launch": flops_per_launch, "avg_launch_ms": tdom, "traffic": None},
     }
+    if args.forms:
+        out["forms"] = run_forms(args, w, psi, L, a, b, m, ws)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(psi, w, last["steps_done"])

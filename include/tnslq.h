@@ -204,8 +204,9 @@ int tnslq_probes(uint64_t seed, uint64_t probe_offset, int n_probes, int64_t d, 
  * 256), b2, W3 (2 x 256), b3.  Weights enter every product rounded to BF16
  * (nearest, ties to even); sums are FP32.  `norm` holds 38 floats: the 19
  * feature means then the 19 feature scales; inputs are standardised as
- * (x - mean) / scale.  Output row = (u0, u1): predicted residual mean and log
- * variance. */
+ * (t(x) - mean) / scale, where t is asinh for the 16 Lanczos-coefficient
+ * features and the identity for the three log2 sizes.  Output row = (u0, u1):
+ * predicted residual mean and log variance. */
 #define TNSLQ_MLP_NIN 19
 #define TNSLQ_MLP_NHID 256
 #define TNSLQ_MLP_NOUT 2

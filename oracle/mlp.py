@@ -9,6 +9,10 @@ weights), trained with a Gaussian negative log-likelihood and Adam
 Flat parameter order (71,426 values): W1 (256 x 19, row = output unit),
 b1 (256), W2 (256 x 256), b2 (256), W3 (2 x 256), b3 (2).
 
+Inputs: the 19 features are mapped by t (asinh on the 16 Lanczos-coefficient
+features, identity on the three log2 sizes) and standardised with fixed
+per-feature means and scales.
+
 Forward, with Wb = bf16(W) and xhat the standardised features:
     z1 = xhat Wb1^T + b1,  h1 = relu(z1)
     z2 = h1 Wb2^T + b2,    h2 = relu(z2)
@@ -52,8 +56,20 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+N_COEF = 16
+
+
+def input_transform(x: np.ndarray) -> np.ndarray:
+    """asinh on the 16 Lanczos-coefficient features, identity on the three
+    log2 subsystem sizes."""
+    x = np.array(x, dtype=np.float64)
+    x[..., :N_COEF] = np.arcsinh(x[..., :N_COEF])
+    return x
+
+
 def standardise(x: np.ndarray, mu: np.ndarray, sd: np.ndarray) -> np.ndarray:
-    return (np.asarray(x, dtype=np.float64) - mu) / sd
+    """xhat = (t(x) - mean) / scale with t = input_transform."""
+    return (input_transform(x) - mu) / sd
 
 
 def forward(theta: np.ndarray, xhat: np.ndarray, quantise: bool = True):

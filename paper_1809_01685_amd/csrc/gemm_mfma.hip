@@ -19,7 +19,11 @@
 // (32 BF16, 16 FP32 or 8 FP64 reduction terms), double buffered: while the
 // waves multiply step i out of one buffer, step i+1 (loaded from global memory
 // one step earlier) is written to the other and step i+2 is loaded into
-// registers, one barrier per step.  The four 16-byte units of a staged row are
+// registers, one barrier per step.  For interior BF16 tiles the LDS writes and
+// global loads of a step are placed between its matrix instructions
+// (scheduling groups: the 24 fragment reads, then two MFMAs per LDS write and
+// per global load, then the remaining MFMAs) and the barrier is pinned after
+// the last MFMA, so that the two waves of a SIMD do not idle together on LDS.  The four 16-byte units of a staged row are
 // XOR-swizzled by ((row >> 1) ^ (row >> 2)) & 3 so that the fragment reads of
 // 8 or 16 consecutive rows hit distinct banks.  Each lane's 16-byte fragment
 // feeds one BF16 MFMA (8 terms), four FP32 MFMAs or two FP64 MFMAs; A and B
@@ -270,11 +274,29 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
 #pragma unroll
             for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
         }
-        if (l0 + BK < kend) {
+        if constexpr (PREC == TNSLQ_BF16X3 && FULL) {
+            // unconditional (clamped) so that the stage is one basic block
+            lstore(buf ^ 1);
+            gload(l0 + 2 * BK < kend ? l0 + 2 * BK : kend - BK);
+        } else if (l0 + BK < kend) {
             lstore(buf ^ 1);
             if (l0 + 2 * BK < kend) gload(l0 + 2 * BK);
         }
         stage_mfma<PREC>(fa, fb, accr, acci);
+        if constexpr (PREC == TNSLQ_BF16X3 && FULL) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
+        }
         if constexpr (TWO_LEVEL) {
             if (++nstage == FLUSH) {
                 flush();
@@ -282,6 +304,7 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
                 nstage = 0;
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
     }
     if constexpr (TWO_LEVEL) {

@@ -70,14 +70,18 @@ __global__ void __launch_bounds__(256) k_mm(MM p) {
     }
 }
 
-// xhat = (x[gather] - mean) / scale
+// xhat = (t(x[gather]) - mean) / scale, t = asinh on the 16 Lanczos-coefficient
+// features (which span many decades) and the identity on the three log2 sizes.
+constexpr int N_COEF = 16;
 __global__ void k_standardise(const float *__restrict__ x, const int *__restrict__ gather,
                               const float *__restrict__ norm, int B, float *__restrict__ xh) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= B * NIN) return;
     const int b = t / NIN, f = t % NIN;
     const int64_t row = gather ? gather[b] : b;
-    xh[t] = (x[row * NIN + f] - norm[f]) / norm[NIN + f];
+    float v = x[row * NIN + f];
+    if (f < N_COEF) v = asinhf(v);
+    xh[t] = (v - norm[f]) / norm[NIN + f];
 }
 
 // Loss and dL/du for L = (1/B) sum 0.5 (u1 + (r - u0)^2 exp(-u1)).

@@ -48,6 +48,17 @@ def features_from_coefficients(alpha: np.ndarray, beta: np.ndarray, d_a: int, d_
     return np.concatenate([fa, fb, [math.log2(d_a), math.log2(d_b), math.log2(d_e)]])
 
 
+def input_transform(X: np.ndarray) -> np.ndarray:
+    """The fixed map applied before standardisation (the kernel applies the
+    same): asinh on the 16 Lanczos-coefficient features, which span many
+    decades (nearly pure rho_AB has d_A d_B alpha ~ d_A d_B), identity on the
+    three log2 sizes.  Used here only to compute the standardisation
+    constants."""
+    X = np.array(X, dtype=np.float64)
+    X[..., :16] = np.arcsinh(X[..., :16])
+    return X
+
+
 def estimate_at(beta: np.ndarray, F: np.ndarray, j: int) -> float:
     """SLQ estimate log2 mean(beta_1^2 F_j) after j steps."""
     return float(np.log2(np.mean(beta[:, 0] ** 2 * F[:, j - 1])))
@@ -147,7 +158,7 @@ class Model:
                 torch.from_numpy(np.ascontiguousarray(self.norm)).to(device))
 
 
-def train(data: Dict[str, np.ndarray], device, seed=0, epochs=200, batch=256, lr=1e-3, val_frac=0.1,
+def train(data: Dict[str, np.ndarray], device, seed=0, epochs=150, batch=256, lr=1e-3, val_frac=0.1,
           log=True) -> Model:
     """Fit the network to (E_full - E_8) / y_scale with the library's kernels;
     the validation split is by instance (the last val_frac of a seeded
@@ -162,8 +173,9 @@ def train(data: Dict[str, np.ndarray], device, seed=0, epochs=200, batch=256, lr
     tr, va = perm[:-n_val], perm[-n_val:]
     resid = ef - e8
     y_scale = float(np.std(resid[tr])) or 1.0
-    mu = X[tr].mean(axis=0)
-    sd = X[tr].std(axis=0)
+    Xt = input_transform(X)
+    mu = Xt[tr].mean(axis=0)
+    sd = Xt[tr].std(axis=0)
     sd[sd < 1e-6] = 1.0
     norm = np.concatenate([mu, sd]).astype(np.float32)
     r = (resid / y_scale).astype(np.float32)
@@ -223,7 +235,7 @@ def _main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)
     t.add_argument("--out", default=WEIGHTS_DIR)
-    t.add_argument("--epochs", type=int, default=200)
+    t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
@@ -233,7 +245,8 @@ def _main(argv=None):
         np.savez(os.path.join(args.out, "dataset.npz"), **d)
         print(f"[surrogate] wrote {args.n} instances to {args.out}")
     else:
-        with np.load(os.path.join(args.data, "dataset.npz")) as f:
+        path = args.data if args.data.endswith(".npz") else os.path.join(args.data, "dataset.npz")
+        with np.load(path) as f:
             d = {k: f[k] for k in f.files}
         model = train(d, dev, seed=args.seed, epochs=args.epochs)
         model.save(args.out)

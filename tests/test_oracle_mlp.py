@@ -80,3 +80,14 @@ def test_nll_gradient_at_optimum_is_zero_for_mean():
     # b3[0]'s gradient is the sum of mean-gradients
     assert abs(g[-2]) < 1e-15
     assert g[-1] == pytest.approx(0.5, rel=1e-12)
+
+
+def test_input_transform_compresses_only_the_lanczos_features():
+    rng = np.random.default_rng(3)
+    y = rng.uniform(-15, 15, size=(5, 19))
+    x = y.copy()
+    x[:, :16] = np.sinh(y[:, :16])            # values spanning ~1e-6 .. 1e6
+    t = mlp.input_transform(x)
+    assert np.allclose(t[:, :16], y[:, :16], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(t[:, 16:], x[:, 16:])
+    assert np.allclose(mlp.standardise(x, 1.0, 2.0), (t - 1.0) / 2.0)
