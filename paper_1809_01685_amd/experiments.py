@@ -1,0 +1,131 @@
+"""Experiment drivers on the library (the paper's Sec. VII set-ups, adapted).
+
+    python -m paper_1809_01685_amd.experiments scrambling [--depths 1-12]
+        24-qubit brickwork states of Haar two-qubit gates from |0...0>, A = 4-11,
+        B = 13-20, E = rest: logarithmic negativity against circuit depth
+        (a seeded stand-in for the quench of Sec. VII.B).
+
+    python -m paper_1809_01685_amd.experiments heldout26
+        The early-stopping surrogate on 26-qubit rho_AB it never saw: the
+        30-qubit Haar state (E = 0-3) and 28-qubit brickwork states (A = 1-13,
+        B = 14-26, E = {0, 27}) at depths 4, 8, 12.  Each is judged against
+        50-step split-BF16 SLQ on the same probes; the +-1% adaptive stop is
+        read off the same run's trajectory.
+
+Both print one JSON object.  All arithmetic runs in libtnslq.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import tnslq_logneg
+
+
+def _trajectory(r):
+    """E_j and its error on the mean for every step j of a run."""
+    G = r["beta"][:, :1] ** 2 * r["F"][:, :r["steps_done"]]
+    mean = G.mean(axis=0)
+    K = G.shape[0]
+    se = G.std(axis=0, ddof=1) / math.sqrt(K) if K > 1 else np.full(mean.shape, np.nan)
+    return np.log2(mean), se / (mean * math.log(2.0))
+
+
+def _adaptive_stop(E, dE, tol=0.01):
+    """First step j >= 6 with sqrt(dE_j^2 + (E_j - E_{j-5})^2) <= tol max(|E_j|, 1)."""
+    for j in range(6, len(E) + 1):
+        err = math.sqrt((0.0 if np.isnan(dE[j - 1]) else dE[j - 1] ** 2) + (E[j - 1] - E[j - 6]) ** 2)
+        if err <= tol * max(abs(E[j - 1]), 1.0):
+            return j
+    return len(E)
+
+
+def run_scrambling(depths, seed=0, n_probes=32, n_steps=40, precision="bf16x3"):
+    import torch
+    import tnslq_inputs as ti
+    w = ti.WORKLOADS["brick24"]
+    dev = torch.device("cuda:0")
+    rows = []
+    for depth in depths:
+        psi = ti.brickwork_state_torch(w.n_qubits, depth, seed, dev, torch.complex64)
+        t0 = time.perf_counter()
+        r = tnslq_logneg(psi, w.n_qubits, list(w.a), list(w.b), n_probes, n_steps, reorth=w.reorth,
+                         precision=precision, seed=seed)
+        rows.append({"depth": depth, "logneg": r["logneg"], "logneg_se": r["logneg_se"],
+                     "steps_min": r["steps_min"], "seconds": time.perf_counter() - t0})
+        print(f"[scrambling] depth {depth}: E = {r['logneg']:.4f} +- {r['logneg_se']:.4f}", file=sys.stderr,
+              flush=True)
+    return {"workload": "brick24: 24-qubit brickwork, A = 4-11, B = 13-20", "probes": n_probes, "steps": n_steps,
+            "precision": precision, "rows": rows}
+
+
+def run_heldout26(n_probes=8, n_steps=50, precision="bf16x3", seed=0, tol=0.01):
+    import torch
+    import tnslq_inputs as ti
+    from .surrogate import Model, surrogate_logneg
+    dev = torch.device("cuda:0")
+    model = Model.load()
+    cases = [("haar30", 30, list(range(4, 17)), list(range(17, 30)), "haar", 0)]
+    for depth in (4, 8, 12):
+        cases.append((f"brick28_d{depth}", 28, list(range(1, 14)), list(range(14, 27)), "brickwork", depth))
+    rows = []
+    for name, L, a, b, kind, depth in cases:
+        if kind == "haar":
+            psi = ti.haar_state_torch(L, seed, dev, torch.complex64)
+        else:
+            psi = ti.brickwork_state_torch(L, depth, seed, dev, torch.complex64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        full = tnslq_logneg(psi, L, a, b, n_probes, n_steps, precision=precision, seed=seed)
+        t_full = time.perf_counter() - t0
+        E, dE = _trajectory(full)
+        j_stop = _adaptive_stop(E, dE, tol)
+        t0 = time.perf_counter()
+        s = surrogate_logneg(model, psi, L, a, b, n_probes, n_steps, tol=tol, precision=precision, seed=seed)
+        t_sur = time.perf_counter() - t0
+        ref = full["logneg"]
+        row = {"case": name, "E_full": ref, "E_full_se": full["logneg_se"], "t_full_s": t_full,
+               "steps_full": full["steps_done"], "E8": float(E[7]), "err_E8": float(E[7] - ref),
+               "adaptive_stop_step": j_stop, "E_adaptive": float(E[j_stop - 1]),
+               "err_adaptive": float(E[j_stop - 1] - ref),
+               "t_adaptive_s_est": t_full * j_stop / full["steps_done"],
+               "mu": s["mu"], "sigma": s["sigma"], "accepted": not s["used_fallback"],
+               "E_surrogate": s["logneg"], "err_surrogate": s["logneg"] - ref, "t_surrogate_s": t_sur}
+        rows.append(row)
+        print(f"[heldout26] {name}: full {ref:.5f}, E8 {E[7]:.5f}, adaptive@{j_stop} {E[j_stop - 1]:.5f}, "
+              f"surrogate {s['logneg']:.5f} (sigma {s['sigma']:.4f}, accepted {not s['used_fallback']})",
+              file=sys.stderr, flush=True)
+        del psi
+        torch.cuda.empty_cache()
+    return {"probes": n_probes, "steps": n_steps, "precision": precision, "tol": tol, "rows": rows}
+
+
+def _parse_range(s):
+    if "-" in s:
+        lo, hi = s.split("-")
+        return list(range(int(lo), int(hi) + 1))
+    return [int(x) for x in s.split(",")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sc = sub.add_parser("scrambling")
+    sc.add_argument("--depths", default="1-12")
+    sc.add_argument("--precision", default="bf16x3")
+    sub.add_parser("heldout26")
+    args = ap.parse_args(argv)
+    if args.cmd == "scrambling":
+        out = run_scrambling(_parse_range(args.depths), precision=args.precision)
+    else:
+        out = run_heldout26()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
