@@ -106,18 +106,22 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     pl.dAB = pl.dA * pl.dB;
     pl.D = int64_t(1) << pl.L;
 
-    const int np = planes_of(prec);
-    const size_t pb = piece_bytes(prec);
     const size_t acc = prec == TNSLQ_FP64 ? 16 : 8;
-    // intermediary per probe: d_B * d_E * d_B elements
-    const int64_t ups_per = pl.dB * pl.dE * pl.dB;
-    const size_t ups_bytes_per = (size_t)np * pb * (size_t)ups_per;
+    pl.nst1 = brick_stages(prec, pl.dA);
+    pl.nst2 = brick_stages(prec, pl.dE * pl.dB);
+    // intermediary per probe: d_B rows (b) by d_E d_B reduction terms (c, b')
+    const size_t ups_bytes_per = brick_bytes(prec, pl.dB, pl.dE * pl.dB);
     pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
-    // split-K of the second contraction: enough blocks to fill the chip
-    const int64_t kr2 = pl.dE * pl.dB;
-    const int64_t tiles = ((pl.dA + 63) / 64) * ((pl.kc * pl.dB + 63) / 64);
+    // every chunk must start on a block of 128 rows (k, b') of Xt
+    if (pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
+        const int q = (int)(BRICK_ROWS / pl.dB);
+        pl.kc = std::min(K, (pl.kc + q - 1) / q * q);
+    }
+    // split-K of the second contraction: enough blocks to fill the chip,
+    // at least 8 bricks per split
+    const int64_t tiles = ((pl.dA + 127) / 128) * ((pl.kc * pl.dB + 127) / 128);
     pl.S = 1;
-    while (tiles * pl.S < 2048 && kr2 / (2 * pl.S) >= 256 && kr2 % (2 * pl.S) == 0) pl.S *= 2;
+    while (tiles * pl.S < 2048 && pl.nst2 % (2 * pl.S) == 0 && pl.nst2 / (2 * pl.S) >= 8) pl.S *= 2;
     const int64_t n = pl.dAB;
     pl.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 4096));
 
@@ -127,10 +131,10 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         o += up(bytes);
         return r;
     };
-    pl.off_Paeb = take((size_t)np * pb * plane_stride(pl.D));
-    pl.off_Pbea = take((size_t)np * pb * plane_stride(pl.D));
-    pl.off_Xt = take((size_t)np * pb * plane_stride((int64_t)K * n));
-    pl.off_Ups = take((size_t)np * pb * plane_stride((int64_t)pl.kc * ups_per));
+    pl.off_Paeb = take(brick_bytes(prec, pl.dA, pl.dE * pl.dB));
+    pl.off_Pbea = take(brick_bytes(prec, pl.dB * pl.dE, pl.dA));
+    pl.off_Xt = take(brick_bytes(prec, (int64_t)K * pl.dB, pl.dA));
+    pl.off_Ups = take(brick_bytes(prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB));
     pl.off_Ypart = take((size_t)pl.S * pl.kc * n * acc);
     if (lanczos) {
         pl.nQ = pl.reorth ? pl.m + 1 : 3;
@@ -170,7 +174,6 @@ struct Ctx {
     hipStream_t st;
     LzDims z;
     void *Paeb, *Pbea, *Xt, *Ups, *Ypart;
-    int64_t psP, psX, psU;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -199,9 +202,6 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Xt = c.ws + pl.off_Xt;
     c.Ups = c.ws + pl.off_Ups;
     c.Ypart = c.ws + pl.off_Ypart;
-    c.psP = plane_stride(pl.D);
-    c.psX = plane_stride((int64_t)pl.K * pl.dAB);
-    c.psU = plane_stride((int64_t)pl.kc * pl.dB * pl.dE * pl.dB);
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
     c.alpha = (double *)(c.ws + pl.off_alpha);
@@ -219,55 +219,59 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.z = LzDims{pl.dA, pl.dB, pl.dAB, pl.K, pl.m, pl.nblk};
 }
 
+// Regroup psi into both contraction layouts, and zero the padding of Xt and
+// Ups along their reduction index (written nowhere else; padded rows need no
+// clearing, their products land outside C).
 int do_layout(Ctx &c, const void *psi) {
     const Plan &pl = c.pl;
     PermDesc aeb = perm_for(pl, pl.qa, pl.nA, pl.qe, pl.nE, pl.qb, pl.nB);
     PermDesc bea = perm_for(pl, pl.qb, pl.nB, pl.qe, pl.nE, pl.qa, pl.nA);
-    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Paeb, c.psP, pl.D, aeb, 0, c.st));
-    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Pbea, c.psP, pl.D, bea, 1, c.st));
+    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Paeb, pl.dA, pl.dE * pl.dB, aeb, 0, c.st));
+    TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Pbea, pl.dB * pl.dE, pl.dA, bea, 1, c.st));
+    const int64_t epr = brick_epr(pl.prec);
+    if (pl.dA % epr)
+        TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, (int64_t)pl.K * pl.dB, pl.dA), c.st));
+    if ((pl.dE * pl.dB) % epr)
+        TNSLQ_HIP(hipMemsetAsync(c.Ups, 0, brick_bytes(pl.prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB), c.st));
     return TNSLQ_OK;
 }
 
 // Both contractions for probes [k0, k0 + kcur): Xt -> Ups -> Ypart.
 int contract_chunk(Ctx &c, int k0, int kcur, hipEvent_t e1, hipEvent_t e2) {
     const Plan &pl = c.pl;
-    const size_t pb = piece_bytes(pl.prec);
+    // contraction 1: Ups[(k, b)][(c, b')] = sum_a' conj psi[a', b, c] Xt[(k, b')][a'];
+    // output (i, j) = ((b, c), (k, b')) -> row k d_B + b, index c d_B + b'
     GemmDesc g1{};
     g1.A = c.Pbea;
-    g1.lda = pl.dA;
-    g1.a_ps = c.psP;
-    g1.B = (const char *)c.Xt + (size_t)k0 * pl.dAB * pb;
-    g1.ldb = pl.dA;
-    g1.b_ps = c.psX;
+    g1.B = (const char *)c.Xt + (size_t)((int64_t)k0 * pl.dB / BRICK_ROWS) * brick_block_bytes(pl.prec, pl.nst1);
     g1.C = c.Ups;
-    g1.c_ps = c.psU;
     g1.M = pl.dB * pl.dE;
     g1.N = (int64_t)kcur * pl.dB;
     g1.Kr = pl.dA;
-    g1.ldc = pl.dB;
-    g1.cnb = pl.dB;
-    g1.cbs = pl.dB * pl.dE * pl.dB;
+    g1.nst = pl.nst1;
     g1.S = 1;
-    g1.c_split = 0;
     g1.out_mode = 0;
+    g1.cnb_log2 = pl.nB;
+    g1.cni_log2 = pl.nE;
+    g1.crs = pl.dB;
+    g1.c_nst = pl.nst2;
+    // contraction 2: Y[k][a][b] = sum_(c, b') psi[a, c, b'] Ups[(k, b)][(c, b')],
+    // split-K partials at s * kc d_A d_B + k d_A d_B + a d_B + b
     GemmDesc g2{};
     g2.A = c.Paeb;
-    g2.lda = pl.dE * pl.dB;
-    g2.a_ps = c.psP;
     g2.B = c.Ups;
-    g2.ldb = pl.dE * pl.dB;
-    g2.b_ps = c.psU;
     g2.C = c.Ypart;
-    g2.c_ps = 0;
     g2.M = pl.dA;
     g2.N = (int64_t)kcur * pl.dB;
     g2.Kr = pl.dE * pl.dB;
-    g2.ldc = pl.dB;
-    g2.cnb = pl.dB;
-    g2.cbs = pl.dAB;
+    g2.nst = pl.nst2;
     g2.S = pl.S;
-    g2.c_split = (int64_t)pl.kc * pl.dAB;
     g2.out_mode = 1;
+    g2.cnb_log2 = pl.nB;
+    g2.cni_log2 = 0;
+    g2.ldc = pl.dB;
+    g2.cbs = pl.dAB;
+    g2.c_split = (int64_t)pl.kc * pl.dAB;
     TNSLQ_HIP(launch_gemm(pl.prec, g1, c.st));
     if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
     TNSLQ_HIP(launch_gemm(pl.prec, g2, c.st));
@@ -311,7 +315,7 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     TNSLQ_HIP(launch_passB(c.z, c.dotpart, q_cur, c.w, c.alpha, c.beta, j, c.nrmpart, pl.reorth ? 0 : 1, c.st));
     if (pl.reorth)
         TNSLQ_HIP(launch_reorth(c.z, c.Q, j, slot, c.w, c.hpart, c.h, c.alpha, c.beta, j, c.nrmpart, c.st));
-    TNSLQ_HIP(launch_passC(pl.prec, c.z, c.nrmpart, c.w, q_next, c.Xt, c.psX, c.alpha, c.beta, j, c.st));
+    TNSLQ_HIP(launch_passC(pl.prec, c.z, c.nrmpart, c.w, q_next, c.Xt, c.pl.nst1, c.alpha, c.beta, j, c.st));
     TNSLQ_HIP(hipEventRecord(se->lz1(), c.st));
     return TNSLQ_OK;
 }
@@ -323,7 +327,7 @@ int slq_setup(Ctx &c, const void *psi, uint64_t seed, uint64_t offset) {
     TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)pl.K * pl.m * 8, c.st));
     TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)pl.K * (pl.m + 1) * 8, c.st));
     TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)pl.K * pl.m * 8, c.st));
-    TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, c.Xt, c.psX, c.alpha, c.beta, c.st));
+    TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, c.Xt, c.pl.nst1, c.alpha, c.beta, c.st));
     return TNSLQ_OK;
 }
 
@@ -558,7 +562,7 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
     bind(c, ws_dev, (hipStream_t)stream);
     const Plan &pl = c.pl;
     if ((rc = do_layout(c, psi_dev))) return rc;
-    TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.psX, c.st));
+    TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.pl.nst1, c.st));
     for (int k0 = 0; k0 < pl.K; k0 += pl.kc) {
         const int kcur = std::min(pl.kc, pl.K - k0);
         if ((rc = contract_chunk(c, k0, kcur, nullptr, nullptr))) return rc;

@@ -15,17 +15,22 @@
 // Tiling (wave64): a block of 8 waves computes a 128 x 128 complex output
 // tile, each wave 64 x 32 (4 x 2 MFMA tiles of 16 x 16), two waves per SIMD
 // so that one wave's LDS waits overlap the other's matrix instructions.  A
-// reduction step stages 64 bytes of every row of each operand plane in LDS
-// (32 BF16, 16 FP32 or 8 FP64 reduction terms), double buffered: while the
-// waves multiply step i out of one buffer, step i+1 (loaded from global memory
-// one step earlier) is written to the other and step i+2 is loaded into
-// registers, one barrier per step.  For interior BF16 tiles the LDS writes and
-// global loads of a step are placed between its matrix instructions
-// (scheduling groups: the 24 fragment reads, then two MFMAs per LDS write and
-// per global load, then the remaining MFMAs) and the barrier is pinned after
-// the last MFMA, so that the two waves of a SIMD do not idle together on LDS.  The four 16-byte units of a staged row are
-// XOR-swizzled by ((row >> 1) ^ (row >> 2)) & 3 so that the fragment reads of
-// 8 or 16 consecutive rows hit distinct banks.  Each lane's 16-byte fragment
+// reduction step stages one brick of each operand (128 rows x 64 bytes per
+// plane: 32 BF16, 16 FP32 or 8 FP64 reduction terms) in LDS: thread t copies
+// bytes [16 t, 16 t + 16) of every plane, so each load instruction of the
+// block reads 8 KiB of contiguous memory and lands at the same offset in LDS.
+// Double buffered: while the waves multiply step i out of one buffer, step
+// i+1 (loaded from global memory one step earlier) is written to the other
+// and step i+2 is loaded into registers, one barrier per step.  For BF16 the
+// LDS writes and global loads of a step are placed between its matrix
+// instructions (scheduling groups: the 24 fragment reads, then two MFMAs per
+// LDS write and per global load, then the remaining MFMAs) and the barrier is
+// pinned after the last MFMA, so that the two waves of a SIMD do not idle
+// together on LDS.  Bricks store the four 16-byte units of a row XOR-swizzled
+// by ((row >> 1) ^ (row >> 2)) & 3, so the fragment reads of 8 or 16
+// consecutive rows hit distinct banks.  Rows past the edge of C come from the
+// bricks' row padding and their results are dropped; the reduction padding
+// holds zeros.  Each lane's 16-byte fragment
 // feeds one BF16 MFMA (8 terms), four FP32 MFMAs or two FP64 MFMAs; A and B
 // fragments pair the same reduction terms, so the order in which the terms of
 // a unit enter the sum does not matter.
@@ -51,27 +56,29 @@ constexpr int GROUP_M = 4;
 constexpr int WAVES_M = 2, WAVES_N = 4;
 constexpr int TM = BM / (16 * WAVES_M), TN = BN / (16 * WAVES_N);
 constexpr int NT = 64 * WAVES_M * WAVES_N;
-constexpr int UPT = BM * 4 / NT;         // 16-byte staging units per thread per plane
+static_assert(BM == BRICK_ROWS && BN == BRICK_ROWS && ROWB == BRICK_ROW_BYTES, "one brick per operand per step");
+static_assert(BM * ROWB / 16 == NT, "one 16-byte unit of every brick plane per thread");
 
 template <int PREC> struct MP;
 template <> struct MP<TNSLQ_BF16X3> {
     static constexpr int NPL = 4;        // re_hi, re_lo, im_hi, im_lo
-    static constexpr int BK = 32;        // reduction terms per stage
-    static constexpr int EB = 2;         // bytes per stored piece
     using acc = f32x4;
 };
 template <> struct MP<TNSLQ_FP32> {
     static constexpr int NPL = 2;
-    static constexpr int BK = 16;
-    static constexpr int EB = 4;
     using acc = f32x4;
 };
 template <> struct MP<TNSLQ_FP64> {
     static constexpr int NPL = 2;
-    static constexpr int BK = 8;
-    static constexpr int EB = 8;
     using acc = f64x4;
 };
+// a 16-byte unit of a brick row feeds one 16x16x32 BF16 MFMA, four 16x16x4
+// FP32 MFMAs or two 16x16x4 FP64 MFMAs per lane
+static_assert(brick_epr(TNSLQ_BF16X3) == 32 && brick_epr(TNSLQ_FP32) == 16 && brick_epr(TNSLQ_FP64) == 8,
+              "brick rows of 64 bytes");
+static_assert(MP<TNSLQ_BF16X3>::NPL == planes_of(TNSLQ_BF16X3) && MP<TNSLQ_FP32>::NPL == planes_of(TNSLQ_FP32) &&
+                  MP<TNSLQ_FP64>::NPL == planes_of(TNSLQ_FP64),
+              "planes per brick");
 
 template <int PREC> constexpr int stage_bytes() { return 2 * MP<PREC>::NPL * TILEB; }
 template <int PREC> constexpr int lds_bytes() { return 2 * stage_bytes<PREC>(); }
@@ -92,7 +99,7 @@ __device__ inline double f64_at(uint4 v, int t) {
 }
 
 // byte offset of 16-byte unit `u` of staged row `row` within a plane tile
-__device__ inline int loff(int row, int u) { return row * ROWB + 16 * (u ^ (((row >> 1) ^ (row >> 2)) & 3)); }
+__device__ inline int loff(int row, int u) { return row * ROWB + 16 * (u ^ brick_swizzle(row)); }
 
 // One reduction stage of the complex product for the wave's TM x TN tiles.
 template <int PREC>
@@ -167,73 +174,50 @@ __device__ __forceinline__ void stage_mfma(const uint4 (&fa)[TM][MP<PREC>::NPL],
     }
 }
 
-// Main reduction loop over [kbeg, kend) for the block's output tile at
-// (i0, j0), accumulating into (outr, outi).  FULL = the tile lies inside C, so
-// no operand row needs zeroing.
-template <int PREC, bool FULL>
-__device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i0, int64_t j0, int64_t kbeg,
-                                         int64_t kend, typename MP<PREC>::acc (&outr)[TM][TN],
+// Main reduction loop over bricks [sbeg, send) for the block's output tile at
+// (i0, j0), accumulating into (outr, outi).
+template <int PREC>
+__device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i0, int64_t j0, int64_t sbeg,
+                                         int64_t send, typename MP<PREC>::acc (&outr)[TM][TN],
                                          typename MP<PREC>::acc (&outi)[TM][TN]) {
     using P = MP<PREC>;
     using Acc = typename P::acc;
-    constexpr int NPL = P::NPL, BK = P::BK, EPU = 16 / P::EB;   // elements per 16-byte unit
+    constexpr int NPL = P::NPL;
     constexpr int STAGEB = stage_bytes<PREC>();
+    constexpr int BRICKB = NPL * TILEB;   // one brick, all planes
     // FP32 keeps a second accumulator: the matrix-core sums restart every
     // FLUSH stages (64 terms) and are added into (outr, outi).
     constexpr bool TWO_LEVEL = PREC == TNSLQ_FP32;
     constexpr int FLUSH = 4;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WAVES_N, wn = wid % WAVES_N;
-    const char *A = (const char *)g.A;
-    const char *B = (const char *)g.B;
+    const size_t blk = brick_block_bytes(PREC, g.nst);
+    const char *ga = (const char *)g.A + (size_t)(i0 / BM) * blk + 16 * tid;
+    const char *gb = (const char *)g.B + (size_t)(j0 / BN) * blk + 16 * tid;
 
-    // global -> register staging: per plane, UPT 16-byte units of A and of B.
-    // Rows past the edge of A or B read a clamped in-range row and are zeroed.
-    uint4 ra[NPL][UPT], rb[NPL][UPT];
-    const int urow0 = tid >> 2, ucol = tid & 3;   // unit u = tid + NT t: row = u / 4, unit = u % 4
-    const char *arow[UPT], *brow[UPT];
-    bool aok[UPT], bok[UPT];
+    // global -> register staging: one 16-byte unit of A and of B per plane
+    uint4 ra[NPL], rb[NPL];
+    auto gload = [&](int64_t st) __attribute__((always_inline)) {
+        const char *pa = ga + st * BRICKB, *pb = gb + st * BRICKB;
 #pragma unroll
-    for (int tt = 0; tt < UPT; ++tt) {
-        const int row = urow0 + (NT / 4) * tt;
-        const int64_t gi = i0 + row, gj = j0 + row;
-        aok[tt] = FULL || gi < g.M;
-        bok[tt] = FULL || gj < g.N;
-        arow[tt] = A + ((gi < g.M ? gi : g.M - 1) * g.lda + EPU * ucol) * P::EB;
-        brow[tt] = B + ((gj < g.N ? gj : g.N - 1) * g.ldb + EPU * ucol) * P::EB;
-    }
-    auto gload = [&](int64_t l0) {
-#pragma unroll
-        for (int tt = 0; tt < UPT; ++tt) {
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                uint4 va = *(const uint4 *)(arow[tt] + (p * g.a_ps + l0) * P::EB);
-                uint4 vb = *(const uint4 *)(brow[tt] + (p * g.b_ps + l0) * P::EB);
-                if constexpr (FULL) {
-                    ra[p][tt] = va;
-                    rb[p][tt] = vb;
-                } else {
-                    ra[p][tt] = aok[tt] ? va : make_uint4(0, 0, 0, 0);
-                    rb[p][tt] = bok[tt] ? vb : make_uint4(0, 0, 0, 0);
-                }
-            }
+        for (int p = 0; p < NPL; ++p) {
+            const uint4 va = *(const uint4 *)(pa + p * TILEB);
+            const uint4 vb = *(const uint4 *)(pb + p * TILEB);
+            ra[p] = va;
+            rb[p] = vb;
         }
     };
-    auto lstore = [&](int buf) {
-        char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
+    auto lstore = [&](int buf) __attribute__((always_inline)) {
+        char *As = lds + buf * STAGEB + 16 * tid, *Bs = As + NPL * TILEB;
 #pragma unroll
-        for (int tt = 0; tt < UPT; ++tt) {
-            const int off = loff(urow0 + (NT / 4) * tt, ucol);
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                *(uint4 *)(As + p * TILEB + off) = ra[p][tt];
-                *(uint4 *)(Bs + p * TILEB + off) = rb[p][tt];
-            }
+        for (int p = 0; p < NPL; ++p) {
+            *(uint4 *)(As + p * TILEB) = ra[p];
+            *(uint4 *)(Bs + p * TILEB) = rb[p];
         }
     };
 
     Acc accr[TM][TN], acci[TM][TN];
-    auto zero = [&]() {
+    auto zero = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -242,7 +226,7 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
                 acci[a][b] = Acc{0, 0, 0, 0};
             }
     };
-    auto flush = [&]() {
+    auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -254,12 +238,12 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
     zero();
 
     const int frow = lane & 15, fk = lane >> 4;   // fragment row within a 16-row tile, k-unit
-    gload(kbeg);
+    gload(sbeg);
     lstore(0);
-    if (kbeg + BK < kend) gload(kbeg + BK);
+    if (sbeg + 1 < send) gload(sbeg + 1);
     __syncthreads();
     int buf = 0, nstage = 0;
-    for (int64_t l0 = kbeg; l0 < kend; l0 += BK, buf ^= 1) {
+    for (int64_t st = sbeg; st < send; ++st, buf ^= 1) {
         const char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
         uint4 fa[TM][NPL], fb[TN][NPL];
 #pragma unroll
@@ -274,16 +258,17 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
 #pragma unroll
             for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
         }
-        if constexpr (PREC == TNSLQ_BF16X3 && FULL) {
-            // unconditional (clamped) so that the stage is one basic block
+        if constexpr (PREC == TNSLQ_BF16X3) {
+            // unconditional (clamped) so that the stage is one basic block;
+            // the extra store and load of the last step are never read
             lstore(buf ^ 1);
-            gload(l0 + 2 * BK < kend ? l0 + 2 * BK : kend - BK);
-        } else if (l0 + BK < kend) {
+            gload(st + 2 < send ? st + 2 : send - 1);
+        } else if (st + 1 < send) {
             lstore(buf ^ 1);
-            if (l0 + 2 * BK < kend) gload(l0 + 2 * BK);
+            if (st + 2 < send) gload(st + 2);
         }
         stage_mfma<PREC>(fa, fb, accr, acci);
-        if constexpr (PREC == TNSLQ_BF16X3 && FULL) {
+        if constexpr (PREC == TNSLQ_BF16X3) {
             __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -340,8 +325,8 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
     const int64_t tn = (t % (GROUP_M * ntn)) / gsize;
     const int64_t i0 = tm * BM, j0 = tn * BN;
 
-    const int64_t klen = g.Kr / g.S;
-    const int64_t kbeg = (int64_t)s * klen, kend = kbeg + klen;
+    const int64_t per = g.nst / g.S;
+    const int64_t sbeg = (int64_t)s * per, send = sbeg + per;
 
     Acc accr[TM][TN], acci[TM][TN];
 #pragma unroll
@@ -351,14 +336,12 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
             accr[a][b] = Acc{0, 0, 0, 0};
             acci[a][b] = Acc{0, 0, 0, 0};
         }
-    if (i0 + BM <= g.M && j0 + BN <= g.N)
-        mainloop<PREC, true>(g, lds, i0, j0, kbeg, kend, accr, acci);
-    else
-        mainloop<PREC, false>(g, lds, i0, j0, kbeg, kend, accr, acci);
+    mainloop<PREC>(g, lds, i0, j0, sbeg, send, accr, acci);
 
     // epilogue: output register r of lane l holds column l % 16 and row
     // 4 * (l / 16) + r (FP32 accumulators) or row 4 * r + l / 16 (FP64)
     const int frow = lane & 15, fk = lane >> 4;
+    const int64_t cnb_mask = ((int64_t)1 << g.cnb_log2) - 1, cni_mask = ((int64_t)1 << g.cni_log2) - 1;
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -369,19 +352,22 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
                 const int64_t i = i0 + wm * TM * 16 + a * 16 + orow;
                 const int64_t j = j0 + wn * TN * 16 + b * 16 + frow;
                 if (i >= g.M || j >= g.N) continue;
-                const int64_t addr = (j / g.cnb) * g.cbs + i * g.ldc + (j % g.cnb);
-                if constexpr (PREC == TNSLQ_FP64) {
-                    const double vr = accr[a][b][r], vi = acci[a][b][r];
-                    if (g.out_mode == 0)
-                        store_planes<PREC>(g.C, g.c_ps, addr, vr, vi);
+                const int64_t jq = j >> g.cnb_log2, jr = j & cnb_mask;
+                const auto vr = accr[a][b][r], vi = acci[a][b][r];
+                if (g.out_mode == 0) {
+                    const int64_t row = jq * g.crs + (i >> g.cni_log2);
+                    const int64_t col = ((i & cni_mask) << g.cnb_log2) + jr;
+                    const int64_t idx = brick_index(PREC, g.c_nst, row, col);
+                    if constexpr (PREC == TNSLQ_FP64)
+                        store_planes<PREC>(g.C, brick_ps(PREC), idx, vr, vi);
                     else
-                        ((double2 *)g.C)[s * g.c_split + addr] = make_double2(vr, vi);
+                        store_planes_f<PREC>(g.C, brick_ps(PREC), idx, vr, vi);
                 } else {
-                    const float vr = accr[a][b][r], vi = acci[a][b][r];
-                    if (g.out_mode == 0)
-                        store_planes_f<PREC>(g.C, g.c_ps, addr, vr, vi);
+                    const int64_t addr = s * g.c_split + jq * g.cbs + i * g.ldc + jr;
+                    if constexpr (PREC == TNSLQ_FP64)
+                        ((double2 *)g.C)[addr] = make_double2(vr, vi);
                     else
-                        ((float2 *)g.C)[s * g.c_split + addr] = make_float2(vr, vi);
+                        ((float2 *)g.C)[addr] = make_float2(vr, vi);
                 }
             }
 }
@@ -403,16 +389,13 @@ hipError_t launch(const GemmDesc &g, hipStream_t st) {
 
 template <int PREC>
 bool supported(const GemmDesc &g) {
-    constexpr int EPU = 16 / MP<PREC>::EB;
-    const int64_t klen = g.Kr / g.S;
-    return g.Kr % g.S == 0 && klen % MP<PREC>::BK == 0 && g.lda % EPU == 0 && g.ldb % EPU == 0 &&
-           g.a_ps % EPU == 0 && g.b_ps % EPU == 0 && ((uintptr_t)g.A % 16) == 0 && ((uintptr_t)g.B % 16) == 0;
+    return g.S >= 1 && g.nst % g.S == 0 && ((uintptr_t)g.A % 16) == 0 && ((uintptr_t)g.B % 16) == 0;
 }
 
 }  // namespace
 
-// Whether the matrix-core kernel takes this shape in this precision: the
-// reduction per split a multiple of one stage, 16-byte aligned rows.
+// Whether the matrix-core kernel takes this contraction: BF16X3, FP32 or FP64
+// bricks, the bricks divided evenly between the splits.
 bool gemm_mfma_supported(int prec, const GemmDesc &g) {
     switch (prec) {
         case TNSLQ_BF16X3: return supported<TNSLQ_BF16X3>(g);

@@ -1,11 +1,10 @@
-// Complex "NT" contraction C = A * B^T on the vector ALUs.
+// Complex "NT" contraction C = A * B^T on the vector ALUs, over the same
+// brick operands as the matrix-core kernel.
 //
-// Serves the shapes too small or too narrow for the matrix-core kernels
-// (reduction length or output width below one MFMA tile) and every
-// precision: FP64 and FP32 operands, and the BF16 hi/lo(/mid) splits whose
-// products are formed in FP32 exactly as the matrix cores form them.
-// Sums run in blocks of one LDS tile (16 terms), blocks added into a second
-// accumulator.
+// Serves the six-piece BF16 split (hi/mid/lo, the products with p + q < 3
+// formed in FP32), which has no matrix-core kernel, and works for every
+// precision.  Sums run in blocks of one LDS tile (16 terms), blocks added into
+// a second accumulator.
 #include "tnslq_internal.h"
 
 namespace tnslq {
@@ -79,8 +78,11 @@ __global__ void __launch_bounds__(256) k_cgemm_nt_valu(GemmDesc g) {
     const int s = (int)(bid / (ntn * ntm));
     const int64_t i0 = tm * BM;
     const int64_t j0 = tn * BN;
-    const int64_t klen = g.Kr / g.S;
-    const int64_t kbeg = s * klen, kend = kbeg + klen;
+    // split s covers bricks [s nst / S, (s + 1) nst / S) of the reduction
+    constexpr int EPR = brick_epr(PREC);
+    const int64_t per = g.nst / g.S;
+    const int64_t kbeg = s * per * EPR;
+    const int64_t kend = (kbeg + per * EPR) < g.Kr ? (kbeg + per * EPR) : g.Kr;
 
     T tot_re[4][4], tot_im[4][4];
 #pragma unroll
@@ -95,9 +97,9 @@ __global__ void __launch_bounds__(256) k_cgemm_nt_valu(GemmDesc g) {
             const int e = tid + t * 256;
             const int row = e / BK, l = e % BK;
             const int64_t gi = i0 + row, gl = l0 + l;
-            As[l][row] = load_elem<PREC>(g.A, g.a_ps, gi * g.lda + gl, gi < g.M && gl < kend);
+            As[l][row] = load_elem<PREC>(g.A, brick_ps(PREC), brick_index(PREC, g.nst, gi, gl), gi < g.M && gl < kend);
             const int64_t gj = j0 + row;
-            Bs[l][row] = load_elem<PREC>(g.B, g.b_ps, gj * g.ldb + gl, gj < g.N && gl < kend);
+            Bs[l][row] = load_elem<PREC>(g.B, brick_ps(PREC), brick_index(PREC, g.nst, gj, gl), gj < g.N && gl < kend);
         }
         __syncthreads();
         T blk_re[4][4], blk_im[4][4];
@@ -135,17 +137,21 @@ __global__ void __launch_bounds__(256) k_cgemm_nt_valu(GemmDesc g) {
         for (int c = 0; c < 4; ++c) {
             const int64_t j = j0 + tx + 16 * c;
             if (j >= g.N) continue;
-            const int64_t addr = (j / g.cnb) * g.cbs + i * g.ldc + (j % g.cnb);
+            const int64_t jq = j >> g.cnb_log2, jr = j & (((int64_t)1 << g.cnb_log2) - 1);
             if (g.out_mode == 0) {
+                const int64_t row = jq * g.crs + (i >> g.cni_log2);
+                const int64_t col = ((i & (((int64_t)1 << g.cni_log2) - 1)) << g.cnb_log2) + jr;
+                const int64_t idx = brick_index(PREC, g.c_nst, row, col);
                 if constexpr (PREC == TNSLQ_FP64)
-                    store_planes<PREC>(g.C, g.c_ps, addr, tot_re[r][c], tot_im[r][c]);
+                    store_planes<PREC>(g.C, brick_ps(PREC), idx, tot_re[r][c], tot_im[r][c]);
                 else
-                    store_planes_f<PREC>(g.C, g.c_ps, addr, tot_re[r][c], tot_im[r][c]);
+                    store_planes_f<PREC>(g.C, brick_ps(PREC), idx, tot_re[r][c], tot_im[r][c]);
             } else {
+                const int64_t addr = s * g.c_split + jq * g.cbs + i * g.ldc + jr;
                 if constexpr (PREC == TNSLQ_FP64)
-                    ((double2 *)g.C)[s * g.c_split + addr] = make_double2(tot_re[r][c], tot_im[r][c]);
+                    ((double2 *)g.C)[addr] = make_double2(tot_re[r][c], tot_im[r][c]);
                 else
-                    ((float2 *)g.C)[s * g.c_split + addr] = make_float2(tot_re[r][c], tot_im[r][c]);
+                    ((float2 *)g.C)[addr] = make_float2(tot_re[r][c], tot_im[r][c]);
             }
         }
     }

@@ -200,7 +200,7 @@ template <int PREC>
 __global__ void __launch_bounds__(256) k_passC(const double *__restrict__ nrmpart, int64_t n, int64_t dA,
                                                int64_t dB, const double2 *__restrict__ w,
                                                double2 *__restrict__ q_next, void *__restrict__ Xt,
-                                               int64_t xt_ps, const double *__restrict__ alpha,
+                                               int64_t xt_nst, const double *__restrict__ alpha,
                                                double *__restrict__ beta, int m, int j, int nblk) {
     __shared__ double sh[16];
     const int k = blockIdx.y;
@@ -224,11 +224,11 @@ __global__ void __launch_bounds__(256) k_passC(const double *__restrict__ nrmpar
         double2 v = w[base + e];
         double2 q = cont ? make_double2(v.x / b, v.y / b) : make_double2(0.0, 0.0);
         q_next[base + e] = q;
-        // Xt position e = (b', a') reads w at a' * dB + b'
+        // Xt entry (row (k, b'), reduction index a') reads w at a' * dB + b'
         const int64_t bb = e / dA, aa = e % dA;
         double2 u = w[base + aa * dB + bb];
         double2 qt = cont ? make_double2(u.x / b, u.y / b) : make_double2(0.0, 0.0);
-        store_planes<PREC>(Xt, xt_ps, base + e, qt.x, qt.y);
+        store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + bb, aa), qt.x, qt.y);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) bk[j] = b;
 }
@@ -406,10 +406,10 @@ hipError_t launch_reorth(const LzDims &z, const double2 *Q, int nvec, int64_t sl
 }
 
 hipError_t launch_passC(int prec, const LzDims &z, const double *nrmpart, const double2 *w, double2 *q_next,
-                        void *Xt, int64_t xt_ps, const double *alpha, double *beta, int j, hipStream_t st) {
+                        void *Xt, int64_t xt_nst, const double *alpha, double *beta, int j, hipStream_t st) {
     dim3 grid(z.nblk, z.K), block(256);
 #define TNSLQ_PC(P)                                                                                         \
-    hipLaunchKernelGGL((k_passC<P>), grid, block, 0, st, nrmpart, z.n, z.dA, z.dB, w, q_next, Xt, xt_ps, \
+    hipLaunchKernelGGL((k_passC<P>), grid, block, 0, st, nrmpart, z.n, z.dA, z.dB, w, q_next, Xt, xt_nst, \
                        alpha, beta, z.m, j, z.nblk)
     switch (prec) {
         case TNSLQ_FP64: TNSLQ_PC(TNSLQ_FP64); break;

@@ -19,19 +19,33 @@ __device__ inline double2 load_psi(const void *psi, int64_t i) {
     }
 }
 
-// out[o] = psi[in(o)] (conjugated if asked) where bit t of o is bit map[t]
-// of in.  One output element per thread step, consecutive threads write
-// consecutive elements.
+// Brick operand of R x Kr entries from psi: entry (r, l) = psi[in(r Kr + l)]
+// (conjugated if asked), where bit t of the regrouped index is bit map[t] of
+// in, and zeros in the padding.  Threads step over the plane-0 entries of the
+// bricks in memory order, so consecutive threads write consecutive elements of
+// every plane.
 template <int PREC, int DTYPE>
-__global__ void __launch_bounds__(256) k_permute(const void *__restrict__ psi, void *__restrict__ out,
-                                                 int64_t ps, int64_t D, PermDesc pd, int conj) {
+__global__ void __launch_bounds__(256) k_permute(const void *__restrict__ psi, void *__restrict__ out, int64_t R,
+                                                 int64_t Kr, int64_t nst, PermDesc pd, int conj) {
+    constexpr int EPR = brick_epr(PREC), EPU = EPR / 4, NPL = planes_of(PREC);
+    constexpr int64_t PER_BRICK = (int64_t)BRICK_ROWS * EPR;
+    const int64_t total = brick_rows(R) * nst * EPR;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < D; o += stride) {
-        int64_t in = 0;
-        for (int t = 0; t < pd.L; ++t) in |= ((o >> t) & 1) << pd.map[t];
-        double2 v = load_psi<DTYPE>(psi, in);
-        if (conj) v.y = -v.y;
-        store_planes<PREC>(out, ps, o, v.x, v.y);
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
+        const int64_t b = x / PER_BRICK, w = x % PER_BRICK;
+        const int64_t rr = w / EPR, pos = w % EPR;
+        // stored unit pos / EPU holds logical unit (pos / EPU) ^ swizzle(rr)
+        const int64_t ll = (((pos / EPU) ^ brick_swizzle(rr)) * EPU) + pos % EPU;
+        const int64_t r = (b / nst) * BRICK_ROWS + rr, l = (b % nst) * EPR + ll;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < R && l < Kr) {
+            const int64_t o = r * Kr + l;
+            int64_t in = 0;
+            for (int t = 0; t < pd.L; ++t) in |= ((o >> t) & 1) << pd.map[t];
+            v = load_psi<DTYPE>(psi, in);
+            if (conj) v.y = -v.y;
+        }
+        store_planes<PREC>(out, brick_ps(PREC), (b * NPL * BRICK_ROWS + rr) * EPR + pos, v.x, v.y);
     }
 }
 
@@ -66,7 +80,7 @@ __device__ inline double2 probe_value(uint64_t seed, uint64_t offset, int k, int
 template <int PREC>
 __global__ void __launch_bounds__(256) k_probe_init(uint64_t seed, uint64_t offset, int swapped,
                                                     int64_t dA, int64_t dB, double2 *__restrict__ q,
-                                                    void *__restrict__ Xt, int64_t xt_ps,
+                                                    void *__restrict__ Xt, int64_t xt_nst,
                                                     double *__restrict__ beta, int m) {
     const int k = blockIdx.y;
     const int64_t n = dA * dB;
@@ -77,10 +91,11 @@ __global__ void __launch_bounds__(256) k_probe_init(uint64_t seed, uint64_t offs
         const int64_t a = e / dB, b = e % dB;
         double2 v = probe_value(seed, offset, k, a, b, dA, dB, swapped);
         q[(int64_t)k * n + e] = make_double2(v.x / b1, v.y / b1);
-        // Xt in [b][a] order, a fastest
+        // Xt row (k, b'), reduction index a'
         const int64_t b2 = e / dA, a2 = e % dA;
         double2 u = probe_value(seed, offset, k, a2, b2, dA, dB, swapped);
-        store_planes<PREC>(Xt, xt_ps, (int64_t)k * n + e, u.x / b1, u.y / b1);
+        store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + b2, a2), u.x / b1,
+                           u.y / b1);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) beta[(int64_t)k * (m + 1)] = b1;
 }
@@ -93,12 +108,13 @@ __global__ void k_probes(uint64_t seed, uint64_t offset, int64_t d, double2 *__r
         X[(int64_t)k * d + i] = probe_value(seed, offset, k, i / d, i % d, 1, d, 0);
 }
 
-// Caller vectors X[k][a_o][b_o] -> transposed contraction operand Xt[k][b][a]
-// in layout roles (conjugated and index-swapped when the roles are swapped).
+// Caller vectors X[k][a_o][b_o] -> contraction operand Xt, row (k, b),
+// reduction index a, in layout roles (conjugated and index-swapped when the
+// roles are swapped).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_load_vectors(const double2 *__restrict__ X, int64_t dA,
                                                       int64_t dB, int swapped, void *__restrict__ Xt,
-                                                      int64_t xt_ps) {
+                                                      int64_t xt_nst) {
     const int k = blockIdx.y;
     const int64_t n = dA * dB;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -111,7 +127,7 @@ __global__ void __launch_bounds__(256) k_load_vectors(const double2 *__restrict_
         } else {
             v = X[(int64_t)k * n + a * dB + b];
         }
-        store_planes<PREC>(Xt, xt_ps, (int64_t)k * n + e, v.x, v.y);
+        store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + b, a), v.x, v.y);
     }
 }
 
@@ -152,10 +168,12 @@ inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
 
 }  // namespace
 
-hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t ps, int64_t D,
+hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t R, int64_t Kr,
                           const PermDesc &pd, int conj, hipStream_t st) {
-    dim3 grid(grid_for(D, 256 * 4, 65535 * 8)), block(256);
-#define TNSLQ_PERM(P, T) hipLaunchKernelGGL((k_permute<P, T>), grid, block, 0, st, psi, out, ps, D, pd, conj)
+    const int64_t nst = brick_stages(prec, Kr);
+    dim3 grid(grid_for(brick_rows(R) * nst * brick_epr(prec), 256 * 4, 65535 * 8)), block(256);
+#define TNSLQ_PERM(P, T) \
+    hipLaunchKernelGGL((k_permute<P, T>), grid, block, 0, st, psi, out, R, Kr, nst, pd, conj)
     if (dtype == TNSLQ_C128) {
         switch (prec) {
             case TNSLQ_FP64: TNSLQ_PERM(TNSLQ_FP64, TNSLQ_C128); break;
@@ -176,12 +194,12 @@ hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64
 }
 
 hipError_t launch_probe_init(int prec, const LzDims &z, uint64_t seed, uint64_t offset, int swapped,
-                             double2 *q, void *Xt, int64_t xt_ps, double *alpha, double *beta,
+                             double2 *q, void *Xt, int64_t xt_nst, double *alpha, double *beta,
                              hipStream_t st) {
     (void)alpha;
     dim3 grid(grid_for(z.n, 256 * 8, 4096), z.K), block(256);
 #define TNSLQ_PI(P) \
-    hipLaunchKernelGGL((k_probe_init<P>), grid, block, 0, st, seed, offset, swapped, z.dA, z.dB, q, Xt, xt_ps, beta, z.m)
+    hipLaunchKernelGGL((k_probe_init<P>), grid, block, 0, st, seed, offset, swapped, z.dA, z.dB, q, Xt, xt_nst, beta, z.m)
     switch (prec) {
         case TNSLQ_FP64: TNSLQ_PI(TNSLQ_FP64); break;
         case TNSLQ_FP32: TNSLQ_PI(TNSLQ_FP32); break;
@@ -200,9 +218,9 @@ hipError_t launch_probes_plain(uint64_t seed, uint64_t offset, int K, int64_t d,
 }
 
 hipError_t launch_load_vectors(int prec, const double2 *X, int64_t dA, int64_t dB, int K, int swapped,
-                               void *Xt, int64_t xt_ps, hipStream_t st) {
+                               void *Xt, int64_t xt_nst, hipStream_t st) {
     dim3 grid(grid_for(dA * dB, 256 * 8, 4096), K), block(256);
-#define TNSLQ_LV(P) hipLaunchKernelGGL((k_load_vectors<P>), grid, block, 0, st, X, dA, dB, swapped, Xt, xt_ps)
+#define TNSLQ_LV(P) hipLaunchKernelGGL((k_load_vectors<P>), grid, block, 0, st, X, dA, dB, swapped, Xt, xt_nst)
     switch (prec) {
         case TNSLQ_FP64: TNSLQ_LV(TNSLQ_FP64); break;
         case TNSLQ_FP32: TNSLQ_LV(TNSLQ_FP32); break;

@@ -1,19 +1,18 @@
 // Internal declarations shared by the libtnslq translation units.
 //
-// Data layout in HBM (all complex operands of the contractions are stored as
-// separate planes, one real array per component piece):
-//   P_aeb   psi regrouped as (A, E, B), b fastest: a d_A x (d_E d_B) matrix.
-//           Row a holds psi[a, c, b'] over the reduction index (c, b') of the
-//           second contraction.
-//   P_bea   psi regrouped as (B, E, A), a fastest and conjugated: a
-//           (d_B d_E) x d_A matrix whose rows (b, c) hold conj psi[a', b, c]
-//           over the reduction index a' of the first contraction.
-//   Xt      the current Lanczos vectors, transposed to [k][b'][a'] (a' fastest).
-//   Ups     intermediary (i) of Sec. V, Ups[k][(b, c)][b'], which read as
-//           [k][b][(c, b')] is the B operand of the second contraction.
-//   Ypart   FP32 or FP64 split-K partial sums of Y[k][a][b].
-// Both contractions are therefore "NT" products C = A * B^T in which both
-// operands are contiguous along the reduction index.
+// Data layout in HBM.  The four operands of the two contractions are complex
+// matrices of R rows by Kr reduction terms, stored in bricks (below):
+//   P_aeb   psi regrouped as (A, E, B): d_A rows a, reduction index (c, b')
+//           (b' fastest) of the second contraction.
+//   P_bea   psi regrouped as (B, E, A) and conjugated: d_B d_E rows (b, c),
+//           reduction index a' of the first contraction.
+//   Xt      the current Lanczos vectors: rows (k, b'), reduction index a'.
+//   Ups     intermediary (i) of Sec. V: rows (k, b), reduction index (c, b'),
+//           the B operand of the second contraction.
+//   Ypart   FP32 or FP64 split-K partial sums of Y[k][a][b], interleaved
+//           complex, row-major.
+// Both contractions are therefore "NT" products C = A * B^T whose operands are
+// bricked along the reduction index.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,10 +32,6 @@ __host__ __device__ constexpr int piece_bytes(int prec) {
     return prec == TNSLQ_FP64 ? 8 : (prec == TNSLQ_FP32 ? 4 : 2);
 }
 __host__ __device__ constexpr int planes_of(int prec) { return 2 * pieces_of(prec); }
-
-// Plane stride in elements for an array of n complex elements (256-byte
-// aligned planes for every piece size).
-__host__ __device__ inline int64_t plane_stride(int64_t n) { return (n + 127) / 128 * 128; }
 
 // ------------------------------------------------------------ BF16 helpers
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs; NaN stays NaN).
@@ -134,6 +129,7 @@ struct Plan {
     int kc = 1;                      // probes per contraction chunk
     int S = 1;                       // split-K factor of the second contraction
     int nblk = 1;                    // reduction blocks per probe vector
+    int64_t nst1 = 1, nst2 = 1;      // bricks along the reduction index of contraction 1, 2
     // workspace carve-up (byte offsets)
     size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
@@ -142,24 +138,67 @@ struct Plan {
     int nQ = 3;                      // Lanczos vector slots
 };
 
+// ------------------------------------------------------------ bricks
+// An R x Kr operand is cut into bricks of 128 rows by 64 bytes of the
+// reduction index (32 BF16, 16 FP32 or 8 FP64 terms) per plane; a brick holds
+// all planes of its piece of the matrix one after the other (8 KiB each), and
+// bricks run along the reduction index first, then over blocks of 128 rows.
+// Within a brick row the four 16-byte units are stored XOR-swizzled by
+// ((row >> 1) ^ (row >> 2)) & 3, the order in which the contraction kernel
+// keeps them in LDS.  Rows are padded to a multiple of 128 and the reduction
+// index to a whole brick; padding along the reduction index must hold zeros.
+// One brick is what the contraction kernel stages per reduction step, so its
+// loads are contiguous 8 KiB blocks.
+constexpr int BRICK_ROWS = 128;
+constexpr int BRICK_ROW_BYTES = 64;
+constexpr int BRICK_PLANE_BYTES = BRICK_ROWS * BRICK_ROW_BYTES;
+
+// reduction terms per brick row
+__host__ __device__ constexpr int brick_epr(int prec) { return BRICK_ROW_BYTES / piece_bytes(prec); }
+// distance between the planes of one brick, in elements
+__host__ __device__ constexpr int64_t brick_ps(int prec) { return (int64_t)BRICK_ROWS * brick_epr(prec); }
+// bricks along the reduction index
+__host__ __device__ inline int64_t brick_stages(int prec, int64_t Kr) {
+    return (Kr + brick_epr(prec) - 1) / brick_epr(prec);
+}
+__host__ __device__ inline int64_t brick_rows(int64_t R) { return (R + BRICK_ROWS - 1) / BRICK_ROWS * BRICK_ROWS; }
+// bytes of one block of 128 rows, and of a whole R x Kr operand
+__host__ __device__ inline size_t brick_block_bytes(int prec, int64_t nst) {
+    return (size_t)nst * planes_of(prec) * BRICK_PLANE_BYTES;
+}
+__host__ __device__ inline size_t brick_bytes(int prec, int64_t R, int64_t Kr) {
+    return (size_t)(brick_rows(R) / BRICK_ROWS) * brick_block_bytes(prec, brick_stages(prec, Kr));
+}
+__host__ __device__ inline int brick_swizzle(int64_t row) { return (int)(((row >> 1) ^ (row >> 2)) & 3); }
+// Element index (plane 0) of entry (r, l) of an operand with nst bricks along
+// the reduction index; plane p of the entry is at + p * brick_ps(prec).
+__host__ __device__ inline int64_t brick_index(int prec, int64_t nst, int64_t r, int64_t l) {
+    const int epr = brick_epr(prec), epu = epr / 4;
+    const int64_t rr = r % BRICK_ROWS, st = l / epr, ll = l % epr;
+    const int64_t u = (ll / epu) ^ brick_swizzle(rr);
+    return (((r / BRICK_ROWS) * nst + st) * planes_of(prec) * BRICK_ROWS + rr) * epr + u * epu + ll % epu;
+}
+
 // ------------------------------------------------------------ GEMM
-// C = A * B^T over complex planes; A is M x Kr (row stride lda), B is N x Kr
-// (row stride ldb), both contiguous along the reduction index.  Output
-// element (i, j) goes to (j / cnb) * cbs + i * ldc + (j % cnb), either as
-// low-precision planes (out_mode 0) or as interleaved accumulator-type
-// complex values of split s at offset s * c_split (out_mode 1).
+// C = A * B^T over complex brick operands: A is M x Kr, B is N x Kr, both with
+// nst bricks along the reduction index and A, B pointing at their first block
+// of rows.  The reduction is split into S equal runs of bricks.  With
+// cnb = 2^cnb_log2 and cni = 2^cni_log2, output element (i, j) of split s goes
+//   out_mode 0: into a brick operand with c_nst bricks along its reduction
+//               index, at row (j / cnb) * crs + i / cni and reduction index
+//               (i % cni) * cnb + j % cnb (S = 1);
+//   out_mode 1: to interleaved accumulator-type complex values at
+//               s * c_split + (j / cnb) * cbs + i * ldc + j % cnb.
 struct GemmDesc {
     const void *A;
-    int64_t lda, a_ps;
     const void *B;
-    int64_t ldb, b_ps;
     void *C;
-    int64_t c_ps;
-    int64_t M, N, Kr;
-    int64_t ldc, cnb, cbs;
+    int64_t M, N, Kr, nst;
     int S;
-    int64_t c_split;
     int out_mode;
+    int cnb_log2, cni_log2;
+    int64_t crs, c_nst;
+    int64_t ldc, cbs, c_split;
 };
 
 hipError_t launch_gemm(int prec, const GemmDesc &g, hipStream_t st);
@@ -172,7 +211,9 @@ struct PermDesc {
     int L;
     int map[TNSLQ_MAX_QUBITS];   // output bit t <- input bit map[t]
 };
-hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t ps, int64_t D,
+// Regroup psi into an R x Kr brick operand (output flat index r * Kr + l),
+// writing every brick entry including the zero padding.
+hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t R, int64_t Kr,
                           const PermDesc &pd, int conj, hipStream_t st);
 
 // ------------------------------------------------------------ Lanczos etc.
@@ -180,8 +221,10 @@ struct LzDims {
     int64_t dA, dB, n;   // n = dA * dB per probe
     int K, m, nblk;
 };
+// Xt arguments below are the brick operand of K d_B rows (k, b') by d_A
+// reduction terms a', with xt_nst = brick_stages(prec, d_A).
 hipError_t launch_probe_init(int prec, const LzDims &z, uint64_t seed, uint64_t offset, int swapped,
-                             double2 *q, void *Xt, int64_t xt_ps, double *alpha, double *beta,
+                             double2 *q, void *Xt, int64_t xt_nst, double *alpha, double *beta,
                              hipStream_t st);
 hipError_t launch_passA(int accfp64, const LzDims &z, const void *part, int S, int64_t split_stride,
                         int k0, int kc, const double2 *q_prev, const double2 *q_cur, double2 *w,
@@ -194,7 +237,7 @@ hipError_t launch_reorth(const LzDims &z, const double2 *Q, int nvec, int64_t q_
                          double2 *w, double *hpart, double2 *h, const double *alpha,
                          const double *beta, int j, double *nrmpart, hipStream_t st);
 hipError_t launch_passC(int prec, const LzDims &z, const double *nrmpart, const double2 *w,
-                        double2 *q_next, void *Xt, int64_t xt_ps, const double *alpha,
+                        double2 *q_next, void *Xt, int64_t xt_nst, const double *alpha,
                         double *beta, int j, hipStream_t st);
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int *steps, int K,
                              int m, int jlo, int jhi, double *F, hipStream_t st);
@@ -208,7 +251,7 @@ hipError_t launch_reduce_partials(int accfp64, const void *part, int S, int64_t 
 hipError_t launch_probes_plain(uint64_t seed, uint64_t offset, int K, int64_t d, double2 *X,
                                hipStream_t st);
 hipError_t launch_load_vectors(int prec, const double2 *X, int64_t dA, int64_t dB, int K,
-                               int swapped, void *Xt, int64_t xt_ps, hipStream_t st);
+                               int swapped, void *Xt, int64_t xt_nst, hipStream_t st);
 hipError_t launch_features(const double *alpha, const double *beta, int K, int m, int n_early,
                            double dAB, double dA, double dB, double dE, float *feat,
                            hipStream_t st);
