@@ -25,6 +25,50 @@ METRIC = "s per ±1% logneg estimate @26-qubit ρ_AB; ρ^T_B matvec GB/s or MFMA
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "fp32": 157.3, "fp64": 78.6}
 # real matrix-core products per complex product of each split
 MFMA_PER_ALGO = {"bf16x3": 3.0, "bf16x6": 6.0, "fp32": 1.0, "fp64": 1.0}
+# rocprofv3 counter summary of the split-BF16 contraction kernel at the default workload
+COUNTERS = os.path.join(ROOT, "profiles", "gemm_bf16x3_haar30_counters.txt")
+
+
+def read_counters(path=COUNTERS):
+    """key = value lines of a counter summary ('#' lines are comments)."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def kernel_source_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in files:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_figures(workload_name, precision, kernel):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE passes, each scaled by the
+    same counter's reading for a 1 GiB device copy) and the matrix-core busy
+    fraction of `kernel`, from the committed counter summary; None when the
+    summary is for another workload or precision, or the kernel's sources have
+    changed since the counters were taken."""
+    c = read_counters()
+    if not c or workload_name != "haar30" or precision != "bf16x3":
+        return None
+    try:
+        if kernel_source_sha256(c["kernel_sources"].split()) != c["kernel_source_sha256"]:
+            return None
+        return {"hbm_bytes": float(c[f"{kernel}_hbm_bytes"]),
+                "mfma_busy_frac": float(c[f"{kernel}_mfma_busy_frac"]),
+                "avg_clock_ghz": float(c[f"{kernel}_avg_clock_ghz"])}
+    except (KeyError, ValueError, OSError):
+        return None
 
 EXTRA = {
     # 26-qubit Haar state with the same block structure (E = 4 qubits) but
@@ -214,6 +258,7 @@ def main():
     dom, tdom = ("contraction2", t2) if t2 >= t1 else ("contraction1", t1)
     achieved = flops_per_launch / (tdom * 1e-3) / 1e12
     peak = PEAK_TFLOPS[w["precision"]]
+    counters = counter_figures(args.workload, w["precision"], dom)
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1e3,
@@ -238,8 +283,13 @@ def main():
                    "t_lanczos_ms": last["t_lanczos_ms"]},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "mfma_issue_frac": achieved * MFMA_PER_ALGO[w["precision"]] / peak,
-                     "flops_per_launch": flops_per_launch, "avg_launch_ms": tdom, "traffic": None},
+                     "flops_per_launch": flops_per_launch, "avg_launch_ms": tdom,
+                     "traffic": counters["hbm_bytes"] if counters else None},
     }
+    if counters:
+        out["roofline"]["counters"] = {"source": os.path.relpath(COUNTERS, ROOT),
+                                       "mfma_busy_frac": counters["mfma_busy_frac"],
+                                       "avg_clock_ghz": counters["avg_clock_ghz"]}
     if args.forms:
         out["forms"] = run_forms(args, w, psi, L, a, b, m, ws)
     if not args.no_cpu_baseline:
