@@ -29,8 +29,9 @@ MFMA_PER_ALGO = {"bf16x3": 3.0, "bf16x6": 6.0, "fp32": 1.0, "fp64": 1.0}
 COUNTERS = os.path.join(ROOT, "profiles", "gemm_bf16x3_haar30_counters.txt")
 
 
-def read_counters(path=COUNTERS):
+def read_counters(path=None):
     """key = value lines of a counter summary ('#' lines are comments)."""
+    path = path or COUNTERS
     out = {}
     if not os.path.exists(path):
         return out
