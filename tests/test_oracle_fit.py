@@ -1,0 +1,126 @@
+"""Pins for the exponential-fit stopping rule of the oracle (Sec. III)."""
+import numpy as np
+import pytest
+import scipy.optimize
+
+import tnslq_inputs as ti
+from oracle import exact, lanczos_fit as lf, probes, slq
+
+
+@pytest.mark.parametrize("r", [0.85, 0.4, -0.3, -0.75, -0.95])
+def test_noise_free_exponential_is_recovered_exactly(r):
+    t = np.arange(8, dtype=float)
+    y = 0.37 - 0.21 * r ** t
+    f = lf.exponential_fit(y)
+    assert f["f_inf"] == pytest.approx(0.37, abs=1e-12)
+    assert f["r"] == pytest.approx(r, abs=1e-9)
+    assert f["a"] == pytest.approx(-0.21, abs=1e-9)
+    assert f["sigma"] < 1e-12
+
+
+def test_constant_sequence_has_zero_uncertainty():
+    f = lf.exponential_fit(np.full(6, 2.5))
+    assert f["f_inf"] == pytest.approx(2.5, rel=1e-15)
+    assert f["sigma"] < 1e-14
+
+
+def _model(t, f_inf, a, r):
+    return f_inf + a * r ** t
+
+
+@pytest.mark.parametrize("seed,r_true", [(0, 0.6), (1, -0.7), (2, -0.4), (3, 0.8)])
+def test_agrees_with_levenberg_marquardt(seed, r_true):
+    # noisy data: the grid + bounded search and scipy's curve_fit (started from
+    # several guesses, best residual kept) find the same optimum, and the
+    # uncertainty matches curve_fit's sqrt(pcov[0, 0])
+    rng = np.random.default_rng(seed)
+    t = np.arange(8, dtype=float)
+    y = 1.0 + 0.5 * r_true ** t + 1e-3 * rng.standard_normal(8)
+    best = None
+    for r0 in (-0.9, -0.5, -0.1, 0.1, 0.5, 0.9):
+        try:
+            p, cov = scipy.optimize.curve_fit(_model, t, y, p0=[y[-1], y[0] - y[-1], r0],
+                                              bounds=([-np.inf, -np.inf, -0.99], [np.inf, np.inf, 0.99]))
+        except RuntimeError:
+            continue
+        rss = float(np.sum((y - _model(t, *p)) ** 2))
+        if best is None or rss < best[0]:
+            best = (rss, p, cov)
+    rss, p, cov = best
+    f = lf.exponential_fit(y)
+    assert f["rss"] <= rss * (1 + 1e-9)
+    assert f["f_inf"] == pytest.approx(p[0], abs=1e-7)
+    assert f["sigma"] == pytest.approx(np.sqrt(cov[0, 0]), rel=1e-3)
+
+
+def test_sign_alternating_ratio_tracks_oscillating_convergence():
+    # F_t = 1 + (-0.8)^t / (t + 1): geometric with a slowly varying amplitude,
+    # the shape of |x| quadrature; the fit's limit is closer than the last value
+    t = np.arange(8, dtype=float)
+    y = 1.0 + (-0.8) ** (t + 6) / (t + 7)
+    f = lf.exponential_fit(y)
+    assert f["r"] < 0
+    assert abs(f["f_inf"] - 1.0) < 0.2 * abs(y[-1] - 1.0)
+
+
+def test_breakdown_makes_the_estimate_exact():
+    # Bell pair between A and B in a product background: the Krylov space of
+    # rho^T_B has dimension <= 3, every probe breaks down early and the
+    # estimate is the exact quadrature value
+    L = 4
+    psi = ti.bell_pair_state(L, 0, 2)
+    P = exact.regroup(psi, L, [0, 1], [2, 3])
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(3, 4, 16, 0)
+    r = slq.slq(lambda v: R @ v, X, 10)
+    for n in range(4):
+        s = lf.breakdown_step(r["alpha"][n], r["beta"][n])
+        assert 0 < s <= 3
+        est = lf.lanczos_estimate(r["F"][n], 10, s)
+        assert est["sigma"] == 0.0 and est["f_inf"] == r["F"][n, s - 1]
+    st = lf.fit_stats(r["F"], r["alpha"], r["beta"], 10)
+    assert st["lanczos_err"] == 0.0
+    assert st["trace_norm"] == pytest.approx(np.mean(r["G"]), rel=1e-14)
+
+
+def test_fit_beats_the_last_quadrature_value_on_a_haar_state():
+    # 14-qubit Haar state, A = 4-8, B = 9-13 (E = 4 qubits): the spectrum of
+    # rho^T_B straddles 0, the quadrature of |x| converges with alternating
+    # sign; at 10 steps the fitted limit is closer to the 40-step value than
+    # F_10 for every probe, and the block error covers the true error
+    L = 14
+    psi = ti.haar_state(L, 1)
+    a, b = list(range(4, 9)), list(range(9, 14))
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(5, 6, 1024, 0)
+    r = slq.slq(lambda v: R @ v, X, 40)
+    for n in range(6):
+        est = lf.lanczos_estimate(r["F"][n], 10, 0)
+        ref = r["F"][n, -1]
+        assert abs(est["f_inf"] - ref) < abs(r["F"][n, 9] - ref)
+    st = lf.fit_stats(r["F"], r["alpha"], r["beta"], 10)
+    assert abs(st["logneg"] - r["logneg"]) < 3 * st["logneg_err"]
+
+
+def test_stop_step_meets_its_target_against_the_long_run():
+    L = 14
+    psi = ti.haar_state(L, 2)
+    a, b = list(range(4, 9)), list(range(9, 14))
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(7, 8, 1024, 0)
+    r = slq.slq(lambda v: R @ v, X, 40)
+    k = lf.fit_stop_step(r["F"], r["alpha"], r["beta"], 0.01)
+    assert lf.FIT_MIN_POINTS <= k < 40
+    st = lf.fit_stats(r["F"], r["alpha"], r["beta"], k)
+    assert abs(st["logneg"] - r["logneg"]) <= 0.01 * max(abs(r["logneg"]), 1.0)
+    # the step before did not meet the target
+    if k > lf.FIT_MIN_POINTS:
+        prev = lf.fit_stats(r["F"], r["alpha"], r["beta"], k - 1)
+        assert prev["logneg_err"] > 0.01 * max(abs(prev["logneg"]), 1.0)
+
+
+def test_too_few_points_is_an_error():
+    with pytest.raises(ValueError):
+        lf.exponential_fit(np.ones(4))
