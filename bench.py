@@ -143,21 +143,26 @@ def run_forms(args, w, psi, L, a, b, m, ws):
     res = {}
     traj = {}
     for form in [f for f in args.forms.split(",") if f]:
+        # "precision" or "precision:rule" (rule: fit or diff; default the run's)
+        prec, _, rule = form.partition(":")
+        rule = rule or args.stop_rule
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if form == "surrogate":
+        if prec == "surrogate":
             from paper_1809_01685_amd import surrogate as S
             model = S.Model.load()
             r = S.surrogate_logneg(model, psi, L, a, b, w["n_probes"], m, tol=0.01, precision=w["precision"],
-                                   seed=args.seed, stop_tol=args.stop_tol, workspace=ws)
+                                   seed=args.seed, stop_tol=args.stop_tol, workspace=ws, stop_rule=rule)
         else:
-            r = T.tnslq_logneg(psi, L, a, b, w["n_probes"], m, reorth=w["reorth"], precision=form, seed=args.seed,
-                               stop_tol=args.stop_tol, workspace=None if form in ("fp64", "fp32") else ws)
+            r = T.tnslq_logneg(psi, L, a, b, w["n_probes"], m, reorth=w["reorth"], precision=prec, seed=args.seed,
+                               stop_tol=args.stop_tol, workspace=None if prec in ("fp64", "fp32") else ws,
+                               stop_rule=rule)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         torch.cuda.empty_cache()
-        entry = {"seconds": dt, "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_steps": r["steps_done"]}
-        if form == "surrogate":
+        entry = {"seconds": dt, "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_err": r["lanczos_err"],
+                 "lanczos_steps": r["steps_done"], "stop_rule": rule}
+        if prec == "surrogate":
             entry.update({"mu": r["mu"], "sigma": r["sigma"], "e_early": r["e_early"],
                           "used_fallback": r["used_fallback"]})
         else:
@@ -166,15 +171,16 @@ def run_forms(args, w, psi, L, a, b, m, ws):
         res[form] = entry
         print(f"[bench] form {form}: {dt:.2f} s, E = {r['logneg']:.6f} after {r['steps_done']} steps",
               file=sys.stderr, flush=True)
-    if "fp64" in traj:
+    ref = next((f for f in traj if f.partition(":")[0] == "fp64"), None)
+    if ref is not None:
         j = min(len(t) for t in traj.values())
         for form, t in traj.items():
             res[form]["logneg_at_common_step"] = float(t[j - 1])
-            res[form]["error_vs_fp64_at_common_step"] = float(t[j - 1] - traj["fp64"][j - 1])
+            res[form]["error_vs_fp64_at_common_step"] = float(t[j - 1] - traj[ref][j - 1])
         res["common_step"] = j
         for form, e in res.items():
             if isinstance(e, dict):
-                e["error_vs_fp64"] = float(e["logneg"] - res["fp64"]["logneg"])
+                e["error_vs_fp64"] = float(e["logneg"] - res[ref]["logneg"])
     return res
 
 
@@ -186,6 +192,12 @@ def main():
     ap.add_argument("--workload", default="haar30")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--stop-tol", type=float, default=0.01)
+    ap.add_argument("--stop-rule", default="fit", choices=["fit", "diff"],
+                    help="fit: Algorithm 1's lanczos_estimate by the exponential fit of Sec. III; "
+                         "diff: quadrature E_j with |E_j - E_{j-5}| as the Lanczos error")
+    ap.add_argument("--check-steps", type=int, default=0, metavar="M",
+                    help="also run M fixed steps on the same probes and report the estimate's error against "
+                         "that run's value (post-hoc check of the +-tol target)")
     ap.add_argument("--max-steps", type=int, default=None)
     ap.add_argument("--probes", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
@@ -223,7 +235,8 @@ def main():
           f"{w['precision']} stop_tol={args.stop_tol}", file=sys.stderr, flush=True)
     psi = make_state(w, args.seed, dev)
     dtc = T.TNSLQ_C64 if psi.dtype == torch.complex64 else T.TNSLQ_C128
-    opts = T.make_options(w["n_probes"], m, w["reorth"], w["precision"], args.seed, 0, args.stop_tol)
+    opts = T.make_options(w["n_probes"], max(m, args.check_steps), w["reorth"], w["precision"], args.seed, 0,
+                          args.stop_tol, args.stop_rule)
     nbytes = T.tnslq_workspace_bytes(dtc, L, a, b, opts)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
@@ -231,7 +244,8 @@ def main():
 
     def step():
         return T.tnslq_logneg(psi, L, a, b, w["n_probes"], m, reorth=w["reorth"], precision=w["precision"],
-                              seed=args.seed, stop_tol=args.stop_tol, workspace=ws, want_arrays=False)
+                              seed=args.seed, stop_tol=args.stop_tol, workspace=ws, want_arrays=False,
+                              stop_rule=args.stop_rule)
 
     for i in range(args.warmup):
         step()
@@ -277,9 +291,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {L}-qubit {w['state']} state {w['dtype']}, A={a[0]}-{a[-1]}, "
                                f"B={b[0]}-{b[-1]}, {len(a) + len(b)}-qubit rho_AB, K={w['n_probes']} probes, "
-                               f"<= {m} Lanczos steps, stop at +-{args.stop_tol * 100:g}%",
+                               f"<= {m} Lanczos steps, stop at +-{args.stop_tol * 100:g}% "
+                               f"({'exponential-fit' if args.stop_rule == 'fit' else 'step-difference'} rule)",
                    "precision": w["precision"], "reorth": bool(w["reorth"])},
-        "result": {"logneg": last["logneg"], "logneg_se": last["logneg_se"], "lanczos_steps": last["steps_done"],
+        "result": {"logneg": last["logneg"], "logneg_se": last["logneg_se"], "lanczos_err": last["lanczos_err"],
+                   "lanczos_steps": last["steps_done"], "stop_rule": args.stop_rule,
                    "t_layout_ms": last["t_layout_ms"], "t_matvec_ms": last["t_matvec_ms"],
                    "t_lanczos_ms": last["t_lanczos_ms"]},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -291,6 +307,16 @@ def main():
         out["roofline"]["counters"] = {"source": os.path.relpath(COUNTERS, ROOT),
                                        "mfma_busy_frac": counters["mfma_busy_frac"],
                                        "avg_clock_ghz": counters["avg_clock_ghz"]}
+    if args.check_steps:
+        # the plain M-step estimate (Gauss quadrature of T_M) on the same probes
+        ref = T.tnslq_logneg(psi, L, a, b, w["n_probes"], args.check_steps, reorth=w["reorth"],
+                             precision=w["precision"], seed=args.seed, stop_tol=0.0, workspace=ws, want_arrays=False,
+                             stop_rule="diff")
+        out["accuracy_check"] = {"reference_steps": args.check_steps, "reference_logneg": ref["logneg"],
+                                 "error": last["logneg"] - ref["logneg"],
+                                 "target": args.stop_tol * max(abs(ref["logneg"]), 1.0)}
+        print(f"[bench] check: {args.check_steps}-step value {ref['logneg']:.6f}, error of the estimate "
+              f"{last['logneg'] - ref['logneg']:+.4f}", file=sys.stderr, flush=True)
     if args.forms:
         out["forms"] = run_forms(args, w, psi, L, a, b, m, ws)
     if not args.no_cpu_baseline:

@@ -70,6 +70,11 @@ enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
 #define TNSLQ_MAX_QUBITS 36
 #define TNSLQ_MAX_STEPS 128
 
+/* Stopping rules of tnslq_options.stop_rule. */
+enum { TNSLQ_STOP_DIFF = 0, TNSLQ_STOP_FIT = 1 };
+#define TNSLQ_FIT_WINDOW 8
+#define TNSLQ_FIT_MIN_POINTS 5
+
 /* Subsystems A and B (Sec. V: group psi's indices into A, B and C).  `a` and
  * `b` are host arrays of qubit indices in [0, n_qubits), pairwise distinct and
  * disjoint.  n_a == 0 or n_b == 0 is allowed: the negativity is then exactly 0
@@ -92,10 +97,27 @@ typedef struct {
  *                of the generator seeded with `seed`; element i takes
  *                1j ** (output >> 62).  Runs with disjoint offsets are
  *                independent Hutchinson samples and can be merged.
- *   stop_tol     0: run exactly n_steps steps.  > 0: after step j >= 6, stop
- *                once sqrt(dE^2 + (E_j - E_{j-5})^2) <= stop_tol * max(|E_j|, 1)
- *                with E_j the estimate from T_j and dE its error on the mean
- *                (the "target precision" reading of Sec. VII.B / Sec. VIII).
+ *   stop_tol     0: run exactly n_steps steps.  > 0: stop at the first step j
+ *                whose estimate E_j and combined error e_j meet
+ *                e_j <= stop_tol * max(|E_j|, 1) (the "target precision" of
+ *                Sec. VII.B / Sec. VIII, relative, in bits), where e_j depends
+ *                on stop_rule.
+ *   stop_rule    TNSLQ_STOP_DIFF: E_j from the quadrature of T_j, checked from
+ *                j >= 6 with e_j = sqrt(dE^2 + (E_j - E_{j-5})^2), dE the
+ *                Hutchinson error of the mean.
+ *                TNSLQ_STOP_FIT: Algorithm 1's lanczos_estimate by the
+ *                exponential fit of Sec. III.  After step
+ *                j >= TNSLQ_FIT_MIN_POINTS + 1 each probe's quadrature values
+ *                F_{max(2, j-TNSLQ_FIT_WINDOW+1)..j} (F_1, the one-node rule, is
+ *                never fitted) are fitted by least squares with F_inf + a r^t,
+ *                r in [-0.99, 0.99] (t = 0 at the window's first point);
+ *                G_n = ||phi_n||^2 F_inf,n, sigma_n its uncertainty from the
+ *                fit's linearised covariance (0 after a breakdown).
+ *                E_j = log2 mean G_n and e_j = sqrt(SE^2 + eps_L^2) / (T ln 2)
+ *                with SE the Hutchinson error of the mean T and eps_L the mean
+ *                of ||phi_n||^2 sigma_n.  The result is the fitted estimate,
+ *                also with stop_tol = 0 (then after n_steps steps, which must
+ *                be > TNSLQ_FIT_MIN_POINTS).
  */
 typedef struct {
     int n_probes;
@@ -105,12 +127,14 @@ typedef struct {
     uint64_t seed;
     uint64_t probe_offset;
     double stop_tol;
+    int stop_rule;
 } tnslq_options;
 
 typedef struct {
     double logneg;          /* log2 of the mean of G_n                        */
     double logneg_se;       /* trace_norm_se / (trace_norm ln 2); NaN if N = 1 */
-    double trace_norm;      /* mean of G_n = ||phi_n||^2 F_{m}                */
+    double trace_norm;      /* mean of G_n = ||phi_n||^2 F_{m} (TNSLQ_STOP_FIT:
+                               ||phi_n||^2 F_inf,n)                           */
     double trace_norm_se;   /* sqrt(Var(G) / N), sample variance (N - 1)       */
     int steps_done;         /* Lanczos steps run on the probe block            */
     int steps_min;          /* fewest steps of any probe (breakdown stops one) */
@@ -124,13 +148,16 @@ typedef struct {
     double t_contract2_ms;  /* second contraction (over b', c), all launches   */
     double t_lanczos_ms;    /* recurrence, reorthogonalisation (device)        */
     double t_total_ms;      /* whole call, host clock                          */
+    double lanczos_err;     /* Lanczos part of the error of logneg, in bits:
+                               |E_j - E_{j-5}| (TNSLQ_STOP_DIFF, NaN for j < 6)
+                               or eps_L / (T ln 2) (TNSLQ_STOP_FIT)            */
 } tnslq_result;
 
 /* ------------------------------------------------------------ utilities */
 const char *tnslq_status_str(int status);
 /* Description of the last failure on the calling thread ("" if none). */
 const char *tnslq_last_error(void);
-/* ABI version, currently 1. */
+/* ABI version, currently 2. */
 int tnslq_version(void);
 
 /* -------------------------------------------------- logarithmic negativity */

@@ -11,12 +11,14 @@ paper fixes neither the points, the weights nor the form of the exponential;
 the readings taken here (each also listed in the design notes):
 
   * model F_t = F_inf + a r^t over the last FIT_WINDOW quadrature values
-    (fewer while k < FIT_WINDOW), t = 0, 1, ... counted from the first point of
-    the window, unweighted.  The ratio r = +-exp(-b) ranges over
+    (fewer early on), t = 0, 1, ... counted from the first point of the window,
+    unweighted.  F_1, the one-node rule (|alpha_1|, far from every later
+    value), is never fitted, so the window holds F_max(2, k-FIT_WINDOW+1)..F_k;  The ratio r = +-exp(-b) ranges over
     [-FIT_R_MAX, FIT_R_MAX]: for |x| the quadrature values of successive
     Lanczos steps fall on alternate sides of the limit, an exponential approach
     with sign-alternating ratio;
-  * at least FIT_MIN_POINTS points (two degrees of freedom for the residual);
+  * at least FIT_MIN_POINTS points (two degrees of freedom for the residual),
+    so the first fit comes after step FIT_MIN_POINTS + 1;
   * uncertainty of F_inf = sqrt(C_00) of the linearised covariance
     C = s^2 (J^T J)^-1, s^2 = RSS / (n - 3), J the Jacobian of the model in
     (F_inf, a, r) at the optimum; an exact fit (RSS = 0) has uncertainty 0, a
@@ -105,7 +107,7 @@ def lanczos_estimate(F_traj, k: int, broke: int = 0) -> Dict[str, float]:
     F_traj = np.asarray(F_traj, dtype=np.float64)
     if 0 < broke <= k:
         return {"f_inf": float(F_traj[broke - 1]), "sigma": 0.0}
-    lo = max(0, k - FIT_WINDOW)
+    lo = max(1, k - FIT_WINDOW)
     fit = exponential_fit(F_traj[lo:k])
     return {"f_inf": fit["f_inf"], "sigma": fit["sigma"]}
 
@@ -133,11 +135,11 @@ def fit_stats(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, k: int) -> Dic
 
 
 def fit_stop_step(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float) -> int:
-    """First step k >= FIT_MIN_POINTS whose combined error meets
+    """First step k >= FIT_MIN_POINTS + 1 whose combined error meets
     dE <= tol max(|E|, 1) (the +-tol target in bits, relative), else the last
     step."""
     m = F.shape[1]
-    for k in range(FIT_MIN_POINTS, m + 1):
+    for k in range(FIT_MIN_POINTS + 1, m + 1):
         s = fit_stats(F, alpha, beta, k)
         if np.isfinite(s["logneg_err"]) and s["logneg_err"] <= tol * max(abs(s["logneg"]), 1.0):
             return k

@@ -20,6 +20,9 @@ TNSLQ_OK = 0
 TNSLQ_C64, TNSLQ_C128 = 0, 1
 TNSLQ_FP64, TNSLQ_FP32, TNSLQ_BF16X3, TNSLQ_BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "bf16x6": TNSLQ_BF16X6}
+TNSLQ_STOP_DIFF, TNSLQ_STOP_FIT = 0, 1
+STOP_RULES = {"diff": TNSLQ_STOP_DIFF, "fit": TNSLQ_STOP_FIT}
+TNSLQ_FIT_WINDOW, TNSLQ_FIT_MIN_POINTS = 8, 5
 MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS = 19, 256, 2, 71426
 
 
@@ -37,7 +40,7 @@ class Partition(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
-                ("stop_tol", ctypes.c_double)]
+                ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -46,7 +49,8 @@ class Result(ctypes.Structure):
                 ("swapped_ab", ctypes.c_int), ("n_matvecs", ctypes.c_int), ("n_contract_launches", ctypes.c_int),
                 ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
                 ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
-                ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("lanczos_err", ctypes.c_double)]
 
     def as_dict(self) -> Dict[str, float]:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -155,10 +159,16 @@ def tnslq_last_error() -> str:
     return lib().tnslq_last_error().decode()
 
 
+def _rule(stop_rule) -> int:
+    if isinstance(stop_rule, str):
+        return STOP_RULES[stop_rule]
+    return int(stop_rule)
+
+
 def make_options(n_probes: int, n_steps: int, reorth: bool = False, precision="fp32", seed: int = 0,
-                 probe_offset: int = 0, stop_tol: float = 0.0) -> Options:
+                 probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff") -> Options:
     return Options(int(n_probes), int(n_steps), int(bool(reorth)), _prec(precision), int(seed) & (2**64 - 1),
-                   int(probe_offset), float(stop_tol))
+                   int(probe_offset), float(stop_tol), _rule(stop_rule))
 
 
 def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int:
@@ -172,14 +182,14 @@ def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int
 # ------------------------------------------------------------- logneg
 def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
                  seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
-                 want_arrays: bool = True) -> Dict[str, object]:
+                 want_arrays: bool = True, stop_rule="diff") -> Dict[str, object]:
     """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``."""
     import numpy as np
     _check_device_tensor(psi, "psi")
     if psi.numel() != 1 << n_qubits:
         raise ValueError("psi has the wrong length")
     dt = _dtype_code(psi)
-    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule)
     p = _partition(n_qubits, a, b)
     need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
     ws = _workspace(need, psi.device, workspace)
@@ -294,11 +304,11 @@ def tnslq_mlp_train(params, m, v, norm, x, r, idx, batch: int, t0: int, lr: floa
 def tnslq_logneg_surrogate(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, params, norm, y_scale: float,
                            tol: float = 0.01, early_steps: int = 8, reorth: bool = False, precision="fp32",
                            seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None,
-                           stream=None) -> Dict[str, object]:
+                           stream=None, stop_rule="diff") -> Dict[str, object]:
     import numpy as np
     _check_device_tensor(psi, "psi")
     dt = _dtype_code(psi)
-    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule)
     p = _partition(n_qubits, a, b)
     need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
     ws = _workspace(need, psi.device, workspace)

@@ -148,6 +148,7 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         pl.off_red = take((size_t)2 * K * pl.nblk * 8);
         pl.off_h = take((size_t)K * (pl.m + 1) * pl.nblk * 16 + (size_t)K * (pl.m + 1) * 16);
         pl.off_steps = take((size_t)K * 4);
+        pl.off_fit = take((size_t)2 * K * 8 + 8 * 8);
         pl.off_feat = take(64 * 4);
         pl.off_mlp = take(mlp_ws_bytes(1) + 64);
     }
@@ -178,6 +179,7 @@ struct Ctx {
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
     int *steps;
+    double *finf, *fsig, *fitout;
     float *feat;
     void *mlpws;
     std::vector<hipEvent_t> ev;
@@ -214,6 +216,9 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.hpart = (double *)(c.ws + pl.off_h);
     c.h = (double2 *)(c.ws + pl.off_h + (size_t)pl.K * (pl.m + 1) * pl.nblk * 16);
     c.steps = (int *)(c.ws + pl.off_steps);
+    c.finf = (double *)(c.ws + pl.off_fit);
+    c.fsig = c.finf + pl.K;
+    c.fitout = c.fsig + pl.K;
     c.feat = (float *)(c.ws + pl.off_feat);
     c.mlpws = c.ws + pl.off_mlp;
     c.z = LzDims{pl.dA, pl.dB, pl.dAB, pl.K, pl.m, pl.nblk};
@@ -372,6 +377,10 @@ int check_options(const tnslq_options *opt) {
         return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", opt->n_steps, TNSLQ_MAX_STEPS);
     if (opt->reorth != 0 && opt->reorth != 1) return fail(TNSLQ_E_ARG, "reorth must be 0 or 1");
     if (!(opt->stop_tol >= 0.0)) return fail(TNSLQ_E_ARG, "stop_tol must be >= 0");
+    if (opt->stop_rule != TNSLQ_STOP_DIFF && opt->stop_rule != TNSLQ_STOP_FIT)
+        return fail(TNSLQ_E_ARG, "stop_rule %d unknown", opt->stop_rule);
+    if (opt->stop_rule == TNSLQ_STOP_FIT && opt->n_steps < TNSLQ_FIT_MIN_POINTS + 1)
+        return fail(TNSLQ_E_ARG, "the fit rule needs n_steps >= %d", TNSLQ_FIT_MIN_POINTS + 1);
     return check_prec(opt->precision);
 }
 
@@ -388,6 +397,8 @@ struct Run {
     std::vector<StepEvents> se;
     hipEvent_t e_start = nullptr, e_layout = nullptr;
     int jdone = 0;
+    int rule = TNSLQ_STOP_DIFF;
+    double lanczos_err = 0.0;   // of the last stop check
 };
 
 int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_options *opt, const void *psi, void *ws,
@@ -400,6 +411,7 @@ int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_option
     if (ws_bytes < r.c.pl.total)
         return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, r.c.pl.total);
     bind(r.c, ws, (hipStream_t)stream);
+    r.rule = opt->stop_rule;
     r.e_start = r.c.event();
     r.e_layout = r.c.event();
     r.se.resize(opt->n_steps + 1);
@@ -416,14 +428,32 @@ int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_option
     return TNSLQ_OK;
 }
 
+// Fitted estimate of every probe after step j (exponential fit, Sec. III):
+// quadrature of the window's steps, the fits and their block statistics.
+int fit_step(Run &r, int j, double *G) {
+    Ctx &c = r.c;
+    const int lo = std::max(2, j - TNSLQ_FIT_WINDOW + 1);
+    TNSLQ_HIP(launch_steps(c.alpha, c.beta, c.pl.K, c.pl.m, j, c.steps, c.st));
+    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, c.pl.K, c.pl.m, lo, j, c.F, c.st));
+    TNSLQ_HIP(launch_fit(c.alpha, c.beta, c.F, c.pl.K, c.pl.m, j, c.finf, c.fsig, G, c.fitout, c.st));
+    return TNSLQ_OK;
+}
+
 // Steps jdone+1 .. jmax; with stop_tol > 0 stops at the first step meeting the
-// precision target.
+// precision target under the run's stopping rule.
 int run_steps(Run &r, int jmax, double stop_tol) {
     int rc;
     for (int j = r.jdone + 1; j <= jmax; ++j) {
         if ((rc = lanczos_step(r.c, j, &r.se[j]))) return rc;
         r.jdone = j;
-        if (stop_tol > 0.0 && j >= 6) {
+        if (stop_tol <= 0.0) continue;
+        if (r.rule == TNSLQ_STOP_FIT && j >= TNSLQ_FIT_MIN_POINTS + 1) {
+            if ((rc = fit_step(r, j, nullptr))) return rc;
+            double o[6];
+            TNSLQ_HIP(hipMemcpyAsync(o, r.c.fitout, sizeof o, hipMemcpyDeviceToHost, r.c.st));
+            TNSLQ_HIP(hipStreamSynchronize(r.c.st));
+            if (std::isfinite(o[3]) && std::isfinite(o[4]) && o[4] <= stop_tol * std::max(std::fabs(o[3]), 1.0)) break;
+        } else if (r.rule == TNSLQ_STOP_DIFF && j >= 6) {
             if ((rc = quad_stats(r.c, j, j - 5, j, j - 5, nullptr))) return rc;
             TNSLQ_HIP(launch_stats(r.c.beta, r.c.F, r.c.pl.K, r.c.pl.m, j, nullptr, r.c.stats, r.c.st));
             double s[8];
@@ -446,9 +476,19 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     Ctx &c = r.c;
     const Plan &pl = c.pl;
     int rc;
-    if ((rc = quad_stats(c, r.jdone, 1, r.jdone, r.jdone, c.G))) return rc;
-    double s[4];
+    const bool fit = r.rule == TNSLQ_STOP_FIT && r.jdone >= TNSLQ_FIT_MIN_POINTS + 1;
+    // quadrature of every step and the plain statistics of each step (G at the
+    // last step unless the fit supplies it)
+    if ((rc = quad_stats(c, r.jdone, 1, r.jdone, r.jdone, fit ? nullptr : c.G))) return rc;
+    if (fit && (rc = fit_step(r, r.jdone, c.G))) return rc;
+    double s[4], o[6], e_old = std::nan("");
     TNSLQ_HIP(hipMemcpyAsync(s, c.stats + (size_t)(r.jdone - 1) * 4, sizeof s, hipMemcpyDeviceToHost, c.st));
+    if (fit) TNSLQ_HIP(hipMemcpyAsync(o, c.fitout, sizeof o, hipMemcpyDeviceToHost, c.st));
+    if (!fit && r.jdone >= 6) {
+        TNSLQ_HIP(launch_stats(c.beta, c.F, pl.K, pl.m, r.jdone - 5, nullptr, c.stats, c.st));
+        TNSLQ_HIP(hipMemcpyAsync(&e_old, c.stats + (size_t)(r.jdone - 6) * 4 + 2, sizeof(double),
+                                 hipMemcpyDeviceToHost, c.st));
+    }
     std::vector<int> hsteps(pl.K);
     TNSLQ_HIP(hipMemcpyAsync(hsteps.data(), c.steps, sizeof(int) * pl.K, hipMemcpyDeviceToHost, c.st));
     if (G) TNSLQ_HIP(hipMemcpyAsync(G, c.G, sizeof(double) * pl.K, hipMemcpyDeviceToHost, c.st));
@@ -459,10 +499,20 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     TNSLQ_HIP(hipStreamSynchronize(c.st));
     if (steps) std::copy(hsteps.begin(), hsteps.end(), steps);
     zero_result(res);
-    res->trace_norm = s[0];
-    res->trace_norm_se = s[1];
-    res->logneg = s[2];
-    res->logneg_se = s[3];
+    if (fit) {
+        const double ln2 = std::log(2.0);
+        res->trace_norm = o[0];
+        res->trace_norm_se = pl.K > 1 ? o[1] : std::nan("");
+        res->logneg = o[3];
+        res->logneg_se = o[5];
+        res->lanczos_err = o[2] / (o[0] * ln2);
+    } else {
+        res->trace_norm = s[0];
+        res->trace_norm_se = s[1];
+        res->logneg = s[2];
+        res->logneg_se = s[3];
+        res->lanczos_err = r.jdone >= 6 ? std::fabs(s[2] - e_old) : std::nan("");
+    }
     res->steps_done = r.jdone;
     res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
     res->swapped_ab = pl.swapped;
@@ -479,7 +529,8 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
         res->t_lanczos_ms += elapsed(e.mv1(), e.lz1());
     }
     res->t_total_ms = tm.ms();
-    if (!std::isfinite(res->logneg)) return fail(TNSLQ_E_NONFINITE, "estimate is not finite (trace norm %g)", s[0]);
+    if (!std::isfinite(res->logneg))
+        return fail(TNSLQ_E_NONFINITE, "estimate is not finite (trace norm %g)", res->trace_norm);
     return TNSLQ_OK;
 }
 
@@ -502,7 +553,7 @@ const char *tnslq_status_str(int s) {
 
 const char *tnslq_last_error(void) { return g_err.c_str(); }
 
-int tnslq_version(void) { return 1; }
+int tnslq_version(void) { return 2; }
 
 int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt, size_t *bytes) {
     int rc;

@@ -40,7 +40,7 @@
 // walked in groups of 4 tile rows; the ~32 blocks resident on one XCD then
 // cover a compact 4 x 8 patch of tiles and share their A and B tiles in that
 // XCD's L2.
-#include "tnslq_internal.h"
+#include "operands.h"
 
 namespace tnslq {
 namespace {

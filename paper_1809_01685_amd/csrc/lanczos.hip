@@ -344,6 +344,164 @@ __global__ void __launch_bounds__(256) k_stats(const double *__restrict__ beta, 
     }
 }
 
+// ---------------------------------------------------------------- fit
+// lanczos_estimate of Sec. III: a least-squares fit of F_inf + a r^t to the
+// last FIT_WINDOW quadrature values of a probe, leaving out F_1 (the one-node
+// rule) (t = 0 at the first point of the window), r in [-FIT_R_MAX, FIT_R_MAX] so that the sign-alternating approach
+// of the |x| quadrature is an exponential too.  For fixed r the fit is the
+// linear regression of the values on r^t; r is chosen on an even grid of
+// FIT_GRID points and refined by golden-section search between the best grid
+// point's neighbours.  The uncertainty of F_inf is sqrt(C_00) of
+// C = RSS / (n - 3) (J^T J)^-1, J the model's Jacobian in (F_inf, a, r); an
+// exact fit has uncertainty 0, a singular J^T J with RSS > 0 infinity.  A probe
+// whose recurrence broke down by step j is exact: F_s, uncertainty 0.
+constexpr int FIT_WINDOW = TNSLQ_FIT_WINDOW;
+constexpr int FIT_MIN_POINTS = TNSLQ_FIT_MIN_POINTS;
+constexpr int FIT_GRID = 397;
+constexpr double FIT_R_MAX = 0.99;
+
+// RSS of the regression y_t ~ f + a r^t (t = 0..n-1), with f, a.
+__device__ inline double fit_linear(const double *y, int n, double r, double &f, double &a) {
+    double x[FIT_WINDOW];
+    double p = 1.0, mx = 0.0, my = 0.0;
+    for (int t = 0; t < n; ++t) {
+        x[t] = p;
+        p *= r;
+        mx += x[t];
+        my += y[t];
+    }
+    mx /= n;
+    my /= n;
+    double sxx = 0.0, sxy = 0.0;
+    for (int t = 0; t < n; ++t) {
+        sxx += (x[t] - mx) * (x[t] - mx);
+        sxy += (x[t] - mx) * (y[t] - my);
+    }
+    a = sxx > 0.0 ? sxy / sxx : 0.0;
+    f = my - a * mx;
+    double rss = 0.0;
+    for (int t = 0; t < n; ++t) {
+        const double e = y[t] - f - a * x[t];
+        rss += e * e;
+    }
+    return rss;
+}
+
+__device__ inline double fit_grid_r(int i) { return -FIT_R_MAX + (2.0 * FIT_R_MAX) * i / (FIT_GRID - 1); }
+
+// Per probe k (one thread each): F_inf and its uncertainty after step j >= FIT_MIN_POINTS + 1.
+__global__ void k_fit(const double *__restrict__ alpha, const double *__restrict__ beta, const double *__restrict__ F,
+                      int K, int m, int j, double *__restrict__ finf, double *__restrict__ fsig) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const double *ak = alpha + (int64_t)k * m, *bk = beta + (int64_t)k * (m + 1), *Fk = F + (int64_t)k * m;
+    const int s = first_break(ak, bk, j);
+    if (s > 0) {
+        finf[k] = Fk[s - 1];
+        fsig[k] = 0.0;
+        return;
+    }
+    const int lo = j - FIT_WINDOW > 1 ? j - FIT_WINDOW : 1;   // F_1 is never fitted
+    const int n = j - lo;
+    double y[FIT_WINDOW];
+    for (int t = 0; t < n; ++t) y[t] = Fk[lo + t];
+    double f, a, best = INFINITY;
+    int ib = 0;
+    for (int i = 0; i < FIT_GRID; ++i) {
+        const double rss = fit_linear(y, n, fit_grid_r(i), f, a);
+        if (rss < best) {
+            best = rss;
+            ib = i;
+        }
+    }
+    double lo_r = fit_grid_r(ib > 0 ? ib - 1 : 0), hi_r = fit_grid_r(ib < FIT_GRID - 1 ? ib + 1 : FIT_GRID - 1);
+    const double g = 0.61803398874989484820;   // (sqrt(5) - 1) / 2
+    double x1 = hi_r - g * (hi_r - lo_r), x2 = lo_r + g * (hi_r - lo_r);
+    double f1 = fit_linear(y, n, x1, f, a), f2 = fit_linear(y, n, x2, f, a);
+    for (int it = 0; it < 200 && hi_r - lo_r > 1e-13; ++it) {
+        if (f1 <= f2) {
+            hi_r = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = hi_r - g * (hi_r - lo_r);
+            f1 = fit_linear(y, n, x1, f, a);
+        } else {
+            lo_r = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = lo_r + g * (hi_r - lo_r);
+            f2 = fit_linear(y, n, x2, f, a);
+        }
+    }
+    double r = 0.5 * (lo_r + hi_r);
+    double rss = fit_linear(y, n, r, f, a);
+    if (!(rss <= best)) {
+        r = fit_grid_r(ib);
+        rss = fit_linear(y, n, r, f, a);
+    }
+    double sig;
+    if (rss == 0.0) {
+        sig = 0.0;
+    } else {
+        // J^T J for the columns 1, r^t, a t r^(t-1)
+        double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+        double p = 1.0, pm = 1.0;   // r^t, r^(t-1) (taken as 1 at t = 0, where the column is 0)
+        for (int t = 0; t < n; ++t) {
+            const double c1 = p, c2 = t > 0 ? a * t * pm : 0.0;
+            m00 += 1.0;
+            m01 += c1;
+            m02 += c2;
+            m11 += c1 * c1;
+            m12 += c1 * c2;
+            m22 += c2 * c2;
+            pm = p;
+            p *= r;
+        }
+        const double cof00 = m11 * m22 - m12 * m12;
+        const double det = m00 * cof00 - m01 * (m01 * m22 - m12 * m02) + m02 * (m01 * m12 - m11 * m02);
+        const double c00 = rss / (n - 3) * cof00 / det;
+        sig = (det > 0.0 && isfinite(c00) && c00 >= 0.0) ? sqrt(c00) : INFINITY;
+    }
+    finf[k] = f;
+    fsig[k] = sig;
+}
+
+// Block statistics of the fitted estimates: G_n = beta_1^2 F_inf,n;
+// out = {mean T, SE (N - 1), eps_L = mean beta_1^2 sigma_n, E = log2 T,
+//        dE = sqrt(SE^2 + eps_L^2) / (T ln 2), SE / (T ln 2)}.
+__global__ void __launch_bounds__(256) k_fit_stats(const double *__restrict__ beta, const double *__restrict__ finf,
+                                                   const double *__restrict__ fsig, int K, int m,
+                                                   double *__restrict__ G, double *__restrict__ out) {
+    __shared__ double sh[16];
+    double s = 0.0, e = 0.0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const double b1 = beta[(int64_t)k * (m + 1)];
+        const double g = b1 * b1 * finf[k];
+        if (G) G[k] = g;
+        s += g;
+        e += b1 * b1 * fsig[k];
+    }
+    const double mean = block_sum(s, sh) / K;
+    const double eps = block_sum(e, sh) / K;
+    double v = 0.0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        const double b1 = beta[(int64_t)k * (m + 1)];
+        const double g = b1 * b1 * finf[k];
+        v += (g - mean) * (g - mean);
+    }
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        const double ln2 = 0.69314718055994530942;
+        const double se = K > 1 ? sqrt(v / (K - 1) / K) : 0.0;
+        out[0] = mean;
+        out[1] = se;
+        out[2] = eps;
+        out[3] = log2(mean);
+        out[4] = sqrt(se * se + eps * eps) / (mean * ln2);
+        out[5] = K > 1 ? se / (mean * ln2) : __longlong_as_double(0x7ff8000000000000ll);
+    }
+}
+
 // Surrogate inputs: probe means of dAB alpha_1..n_early and dAB beta_2..n_early+1,
 // then log2 dA, log2 dB, log2 dE.
 __global__ void k_features(const double *__restrict__ alpha, const double *__restrict__ beta, int K, int m,
@@ -437,6 +595,15 @@ hipError_t launch_quadrature(const double *alpha, const double *beta, const int 
 hipError_t launch_stats(const double *beta, const double *F, int K, int m, int j, double *G, double *stats,
                         hipStream_t st) {
     hipLaunchKernelGGL(k_stats, dim3(1), dim3(256), 0, st, beta, F, K, m, j, G, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit(const double *alpha, const double *beta, const double *F, int K, int m, int j, double *finf,
+                      double *fsig, double *G, double *out, hipStream_t st) {
+    if (j < FIT_MIN_POINTS + 1 || j > m) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fit, dim3((K + 63) / 64), dim3(64), 0, st, alpha, beta, F, K, m, j, finf, fsig);
+    hipLaunchKernelGGL(k_fit_stats, dim3(1), dim3(256), 0, st, beta, (const double *)finf, (const double *)fsig, K, m,
+                       G, out);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert T.tnslq_version() == 1
+    assert T.tnslq_version() == 2
     assert T.tnslq_status_str(0) == "ok"
     assert T.tnslq_status_str(-2) == "invalid partition"
     assert T.tnslq_status_str(-4) == "workspace too small"
@@ -66,7 +66,8 @@ def test_bad_partitions_rejected(L, a, b, code):
 def test_bad_options_rejected(L):
     p = T._partition(6, [0], [1])
     n = ctypes.c_size_t(0)
-    for o in (T.make_options(0, 4), T.make_options(4, 0), T.make_options(4, 500), T.make_options(4, 4, precision=9)):
+    for o in (T.make_options(0, 4), T.make_options(4, 0), T.make_options(4, 500), T.make_options(4, 4, precision=9),
+              T.make_options(4, 4, stop_rule=7), T.make_options(4, 5, stop_rule="fit")):
         rc = L.tnslq_workspace_bytes(0, ctypes.byref(p), ctypes.byref(o), ctypes.byref(n))
         assert rc == -1
     assert L.tnslq_workspace_bytes(7, ctypes.byref(p), ctypes.byref(T.make_options(4, 4)), ctypes.byref(n)) == -3
@@ -100,3 +101,30 @@ def test_mlp_argument_checks(L):
     assert L.tnslq_mlp_workspace_bytes(0, ctypes.byref(n)) == -1
     assert L.tnslq_mlp_workspace_bytes(64, ctypes.byref(n)) == 0 and n.value > 64 * 256 * 4
     assert L.tnslq_mlp_adam(None, None, None, None, 1, 1e-3, None) == -1
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # the ctypes mirrors must have the C layout: compile a probe of the header
+    # with the host compiler and compare sizes and field offsets
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"tnslq_partition": T.Partition, "tnslq_options": T.Options, "tnslq_result": T.Result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tnslq.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -11,14 +11,14 @@ import bench  # noqa: E402
 def _write(path, sha):
     path.write_text("# comment = ignored\n"
                     f"kernel_source_sha256 = {sha}\n"
-                    "kernel_sources = paper_1809_01685_amd/csrc/gemm_mfma.hip paper_1809_01685_amd/csrc/tnslq_internal.h\n"
+                    "kernel_sources = paper_1809_01685_amd/csrc/gemm_mfma.hip paper_1809_01685_amd/csrc/operands.h\n"
                     "contraction2_hbm_bytes = 1.5e+11\n"
                     "contraction2_mfma_busy_frac = 0.7\n"
                     "contraction2_avg_clock_ghz = 2.0\n")
 
 
 def test_counter_summary_parses_and_checks_kernel_sources(tmp_path, monkeypatch):
-    srcs = ["paper_1809_01685_amd/csrc/gemm_mfma.hip", "paper_1809_01685_amd/csrc/tnslq_internal.h"]
+    srcs = ["paper_1809_01685_amd/csrc/gemm_mfma.hip", "paper_1809_01685_amd/csrc/operands.h"]
     p = tmp_path / "c.txt"
     _write(p, bench.kernel_source_sha256(srcs))
     monkeypatch.setattr(bench, "COUNTERS", str(p))

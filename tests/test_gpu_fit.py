@@ -1,0 +1,85 @@
+"""GPU parity of the exponential-fit stopping rule (Sec. III) against the
+oracle, through the C ABI.
+
+The GPU runs in FP64, where its Lanczos coefficients match the oracle's on
+the same probes to ~1e-12; both sides then fit their own quadrature values.
+The fit's optimum is found by different searches (golden section on the
+device, bounded Brent in the oracle) that agree to ~1e-9 in the ratio r, so
+the fitted limits agree to 1e-7 relative and their uncertainties to 1e-4.
+"""
+import numpy as np
+import pytest
+
+import tnslq_inputs as ti
+from oracle import exact, lanczos_fit as lf, probes, slq
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_1809_01685_amd")
+
+
+def _oracle_run(psi, L, a, b, K, m, seed):
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(seed, K, P.shape[0] * P.shape[1], 0)
+    return slq.slq(lambda v: R @ v, X, m)
+
+
+@pytest.mark.parametrize("L,a,b,m", [(12, [0, 1, 2, 3], [6, 7, 8, 9], 12),
+                                     (14, list(range(4, 9)), list(range(9, 14)), 10),
+                                     (10, [0, 1, 2], [3, 4, 5], 6),
+                                     (11, [1, 5], [0, 3, 6, 8], 16)])
+def test_fitted_estimate_matches_oracle(dev, L, a, b, m):
+    import torch
+    psi = ti.haar_state(L, L + 1)
+    psi_t = torch.from_numpy(psi).to(dev)
+    K = 6
+    g = T.tnslq_logneg(psi_t, L, a, b, K, m, precision="fp64", seed=4, stop_rule="fit")
+    o = _oracle_run(psi, L, a, b, K, m, 4)
+    # swapped roles (|B| > |A|) give the same Krylov coefficients, so the same F
+    assert np.allclose(g["F"], o["F"], rtol=1e-10, atol=1e-14)
+    st = lf.fit_stats(o["F"], o["alpha"], o["beta"], m)
+    assert g["steps_done"] == m
+    assert np.allclose(g["G"], st["G"], rtol=1e-7, atol=0)
+    assert g["trace_norm"] == pytest.approx(st["trace_norm"], rel=1e-7)
+    assert g["logneg"] == pytest.approx(st["logneg"], rel=1e-7, abs=1e-9)
+    assert g["trace_norm_se"] == pytest.approx(st["trace_norm_se"], rel=1e-5)
+    lanczos_bits = st["lanczos_err"] / (st["trace_norm"] * np.log(2.0))
+    assert g["lanczos_err"] == pytest.approx(lanczos_bits, rel=1e-4)
+
+
+def test_fit_stop_step_matches_oracle_and_meets_target(dev):
+    import torch
+    L, a, b = 14, list(range(4, 9)), list(range(9, 14))
+    psi = ti.haar_state(L, 2)
+    psi_t = torch.from_numpy(psi).to(dev)
+    K, m = 8, 40
+    g = T.tnslq_logneg(psi_t, L, a, b, K, m, precision="fp64", seed=7, stop_tol=0.01, stop_rule="fit")
+    o = _oracle_run(psi, L, a, b, K, m, 7)
+    k = lf.fit_stop_step(o["F"], o["alpha"], o["beta"], 0.01)
+    assert g["steps_done"] == k < m
+    st = lf.fit_stats(o["F"], o["alpha"], o["beta"], k)
+    assert g["logneg"] == pytest.approx(st["logneg"], rel=1e-7)
+    # the estimate at the stop is within its +-1% target of the 40-step value
+    assert abs(g["logneg"] - o["logneg"]) <= 0.01 * max(abs(o["logneg"]), 1.0)
+
+
+def test_fit_rule_stops_no_later_than_the_difference_rule(dev):
+    import torch
+    L, a, b = 14, list(range(4, 9)), list(range(9, 14))
+    psi_t = torch.from_numpy(ti.haar_state(L, 3).astype(np.complex64)).to(dev)
+    d = T.tnslq_logneg(psi_t, L, a, b, 8, 40, precision="bf16x3", seed=2, stop_tol=0.01, stop_rule="diff")
+    f = T.tnslq_logneg(psi_t, L, a, b, 8, 40, precision="bf16x3", seed=2, stop_tol=0.01, stop_rule="fit")
+    assert T.TNSLQ_FIT_MIN_POINTS + 1 <= f["steps_done"] <= d["steps_done"]
+    assert abs(f["logneg"] - d["logneg"]) <= 0.01 * max(abs(d["logneg"]), 1.0)
+
+
+def test_breakdown_gives_exact_fit(dev):
+    import torch
+    # Bell pair between A and B in a |0> background: every probe breaks down by
+    # step 3, the fitted estimate is the exact quadrature and E = 1 exactly
+    L = 8
+    psi_t = torch.from_numpy(ti.bell_pair_state(L, 1, 6)).to(dev)
+    r = T.tnslq_logneg(psi_t, L, [0, 1, 2], [5, 6, 7], 4, 8, precision="fp64", seed=0, stop_rule="fit")
+    assert r["logneg"] == pytest.approx(1.0, abs=1e-12)
+    assert r["lanczos_err"] == 0.0

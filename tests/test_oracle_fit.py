@@ -112,13 +112,28 @@ def test_stop_step_meets_its_target_against_the_long_run():
     X = probes.rademacher_probes(7, 8, 1024, 0)
     r = slq.slq(lambda v: R @ v, X, 40)
     k = lf.fit_stop_step(r["F"], r["alpha"], r["beta"], 0.01)
-    assert lf.FIT_MIN_POINTS <= k < 40
+    assert lf.FIT_MIN_POINTS + 1 <= k < 40
     st = lf.fit_stats(r["F"], r["alpha"], r["beta"], k)
     assert abs(st["logneg"] - r["logneg"]) <= 0.01 * max(abs(r["logneg"]), 1.0)
     # the step before did not meet the target
-    if k > lf.FIT_MIN_POINTS:
+    if k > lf.FIT_MIN_POINTS + 1:
         prev = lf.fit_stats(r["F"], r["alpha"], r["beta"], k - 1)
         assert prev["logneg_err"] > 0.01 * max(abs(prev["logneg"]), 1.0)
+
+
+def test_window_leaves_out_the_one_node_rule():
+    # F_1 is never fitted: changing it changes no estimate
+    rng = np.random.default_rng(4)
+    F = 1.0 + (-0.7) ** np.arange(12) * 0.3 + 1e-4 * rng.standard_normal(12)
+    G = F.copy()
+    G[0] = 123.0
+    for k in (6, 7, 9, 12):
+        assert lf.lanczos_estimate(F, k)["f_inf"] == lf.lanczos_estimate(G, k)["f_inf"]
+    # the window is F_2..F_k up to 8 points, then the last 8
+    assert lf.lanczos_estimate(F, 9)["f_inf"] == lf.exponential_fit(F[1:9])["f_inf"]
+    assert lf.lanczos_estimate(F, 12)["f_inf"] == lf.exponential_fit(F[4:12])["f_inf"]
+    with pytest.raises(ValueError):
+        lf.lanczos_estimate(F, 5)
 
 
 def test_too_few_points_is_an_error():
