@@ -204,6 +204,65 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
                    const void *X_dev, void *Y_dev, int precision, void *ws_dev, size_t ws_bytes,
                    void *stream);
 
+/* ------------------------------------------- other spectral sums (entropy) */
+
+/* The same stochastic Lanczos quadrature with the partial transpose dropped
+ * (the paper's closing section: von Neumann entropy, mutual information and
+ * other functions of reduced density matrices).  For a subsystem S of the
+ * pure state psi, rho_S = Tr_R |psi><psi| = Psi Psi^dagger with Psi = psi
+ * regrouped as a d_S x d_R matrix (S's qubits in the given order, most
+ * significant first; R the other qubits in increasing order).  The Krylov
+ * space is built on the smaller of S and R (rho_S and rho_R share their
+ * non-zero spectrum), and rho is applied lazily, rho X = Psi (Psi^dagger X),
+ * by two passes over psi with FP64 products and sums.  The estimate of
+ * Tr f(rho) is the Hutchinson mean of G_n = ||phi_n||^2 F_m (no logarithm). */
+enum { TNSLQ_F_ABS = 0,       /* f(x) = |x|: the trace norm (tnslq_logneg)   */
+       TNSLQ_F_ENTROPY = 1,   /* f(x) = -x log2 x (0 for x <= 0): S in bits */
+       TNSLQ_F_PURITY = 2 };  /* f(x) = x^2: Tr rho^2                       */
+
+typedef struct {
+    double value;           /* mean of G_n, the estimate of Tr f(rho_S)       */
+    double value_se;        /* sqrt(Var(G) / N), sample variance (N - 1)       */
+    int steps_done;         /* Lanczos steps run                               */
+    int steps_min;          /* fewest steps of any probe (breakdown stops one) */
+    int complement;         /* 1 if the Krylov space is that of rho_R          */
+    int n_qubits_side;      /* qubits of the side the Krylov space lives on    */
+    double t_layout_ms;     /* regrouping psi (device)                         */
+    double t_matvec_ms;     /* both passes over psi, all steps (device)        */
+    double t_lanczos_ms;    /* recurrence, reorthogonalisation (device)        */
+    double t_total_ms;      /* whole call, host clock                          */
+} tnslq_spectral_result;
+
+/* Workspace bytes for tnslq_spectral_sum on subsystem s[0..n_s) (host call). */
+int tnslq_spectral_workspace_bytes(int dtype, int n_qubits, const int *s, int n_s, const tnslq_options *opt,
+                                   size_t *bytes);
+
+/* Tr f(rho_S) by Algorithm 1 with opt->n_probes probes and exactly
+ * opt->n_steps Lanczos steps (opt->precision must be TNSLQ_FP64; stop_tol must
+ * be 0; reorth, seed and probe_offset as for tnslq_logneg, with d = the side's
+ * dimension in place of d_A d_B).  n_s == 0 or n_s == n_qubits is exact
+ * without device work (a pure state: entropy 0, purity 1).  Host arrays as
+ * for tnslq_logneg, may be NULL.  Synchronises the stream before returning. */
+int tnslq_spectral_sum(const void *psi_dev, int dtype, int n_qubits, const int *s, int n_s, int fn,
+                       const tnslq_options *opt, void *ws_dev, size_t ws_bytes, void *stream,
+                       tnslq_spectral_result *res, double *G_host, double *alpha_host, double *beta_host,
+                       double *F_host, int *steps_host);
+
+/* Workspace bytes for tnslq_mutual_information: the largest of its three
+ * spectral sums. */
+int tnslq_mutual_information_workspace_bytes(int dtype, const tnslq_partition *part,
+                                             const tnslq_options *opt, size_t *bytes);
+
+/* Mutual information I(A:B) = S(A) + S(B) - S(AB) of the pure state psi, each
+ * entropy by tnslq_spectral_sum (S(AB) through the smaller of AB and E), with
+ * the probe offsets probe_offset, +n_probes, +2 n_probes so that the three
+ * estimates are independent.  out[8] = {I, I_se, S_A, S_A_se, S_B, S_B_se,
+ * S_AB, S_AB_se} (host); the errors of I add in quadrature.  Synchronises the
+ * stream before returning. */
+int tnslq_mutual_information(const void *psi_dev, int dtype, const tnslq_partition *part,
+                             const tnslq_options *opt, void *ws_dev, size_t ws_bytes, void *stream,
+                             double *out);
+
 /* ----------------------------------------------------- Gauss quadrature */
 
 /* For each probe n and each k = 1..n_steps, F[n][k-1] = sum_j tau_j^2 |theta_j|

@@ -23,6 +23,8 @@ PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "b
 TNSLQ_STOP_DIFF, TNSLQ_STOP_FIT = 0, 1
 STOP_RULES = {"diff": TNSLQ_STOP_DIFF, "fit": TNSLQ_STOP_FIT}
 TNSLQ_FIT_WINDOW, TNSLQ_FIT_MIN_POINTS = 8, 5
+TNSLQ_F_ABS, TNSLQ_F_ENTROPY, TNSLQ_F_PURITY = 0, 1, 2
+FUNCTIONS = {"entropy": TNSLQ_F_ENTROPY, "purity": TNSLQ_F_PURITY}
 MLP_NIN, MLP_NHID, MLP_NOUT, MLP_NPARAMS = 19, 256, 2, 71426
 
 
@@ -41,6 +43,16 @@ class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
                 ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int)]
+
+
+class SpectralResult(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("value_se", ctypes.c_double), ("steps_done", ctypes.c_int),
+                ("steps_min", ctypes.c_int), ("complement", ctypes.c_int), ("n_qubits_side", ctypes.c_int),
+                ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
+                ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Result(ctypes.Structure):
@@ -77,6 +89,13 @@ _SIGS = {
     "tnslq_mlp_train": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _F, _VP, _VP, _SZ, _VP]),
     "tnslq_logneg_surrogate": (_I, [_VP, _I, ctypes.POINTER(Partition), ctypes.POINTER(Options), _VP, _VP, _F, _I,
                                     _D, _VP, _SZ, _VP, ctypes.POINTER(Result), _VP]),
+    "tnslq_spectral_workspace_bytes": (_I, [_I, _I, _VP, _I, ctypes.POINTER(Options), ctypes.POINTER(_SZ)]),
+    "tnslq_spectral_sum": (_I, [_VP, _I, _I, _VP, _I, _I, ctypes.POINTER(Options), _VP, _SZ, _VP,
+                                ctypes.POINTER(SpectralResult), _VP, _VP, _VP, _VP, _VP]),
+    "tnslq_mutual_information_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(Options),
+                                                      ctypes.POINTER(_SZ)]),
+    "tnslq_mutual_information": (_I, [_VP, _I, ctypes.POINTER(Partition), ctypes.POINTER(Options), _VP, _SZ, _VP,
+                                      _VP]),
 }
 
 
@@ -322,3 +341,69 @@ def tnslq_logneg_surrogate(psi, n_qubits: int, a, b, n_probes: int, n_steps: int
     out.update({"mu": info[0], "sigma": info[1], "e_early": info[2], "used_fallback": bool(info[3]),
                 "e_full": info[4] if not math.isnan(info[4]) else None})
     return out
+
+
+# ------------------------------------------------------------- entropy
+def _qubits(s: Sequence[int]):
+    arr = (ctypes.c_int * max(1, len(s)))(*s)
+    return arr
+
+
+def tnslq_spectral_workspace_bytes(dtype: int, n_qubits: int, s, opts: Options) -> int:
+    n = ctypes.c_size_t(0)
+    arr = _qubits(s)
+    _check(lib().tnslq_spectral_workspace_bytes(int(dtype), int(n_qubits), ctypes.cast(arr, ctypes.c_void_p), len(s),
+                                                ctypes.byref(opts), ctypes.byref(n)), "tnslq_spectral_workspace_bytes")
+    return n.value
+
+
+def tnslq_spectral_sum(psi, n_qubits: int, s, fn="entropy", n_probes: int = 8, n_steps: int = 40,
+                       reorth: bool = False, seed: int = 0, probe_offset: int = 0, workspace=None, stream=None,
+                       want_arrays: bool = True) -> Dict[str, object]:
+    """Tr f(rho_S) of the device state ``psi`` for f = -x log2 x ("entropy") or x^2 ("purity")."""
+    import numpy as np
+    _check_device_tensor(psi, "psi")
+    if psi.numel() != 1 << n_qubits:
+        raise ValueError("psi has the wrong length")
+    dt = _dtype_code(psi)
+    code = FUNCTIONS[fn] if isinstance(fn, str) else int(fn)
+    opts = make_options(n_probes, n_steps, reorth, "fp64", seed, probe_offset, 0.0)
+    need = tnslq_spectral_workspace_bytes(dt, n_qubits, s, opts)
+    ws = _workspace(max(need, 256), psi.device, workspace)
+    res = SpectralResult()
+    K, m = n_probes, n_steps
+    G = np.zeros(K)
+    al = np.zeros((K, m))
+    be = np.zeros((K, m + 1))
+    F = np.zeros((K, m))
+    st = np.zeros(K, dtype=np.int32)
+    host = (lambda x: x.ctypes.data_as(ctypes.c_void_p)) if want_arrays else (lambda x: ctypes.c_void_p(0))
+    arr = _qubits(s)
+    rc = lib().tnslq_spectral_sum(_ptr(psi), dt, int(n_qubits), ctypes.cast(arr, ctypes.c_void_p), len(s), code,
+                                  ctypes.byref(opts), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(res),
+                                  host(G), host(al), host(be), host(F), host(st))
+    _check(rc, "tnslq_spectral_sum")
+    out: Dict[str, object] = res.as_dict()
+    if want_arrays:
+        out.update({"G": G, "alpha": al, "beta": be, "F": F, "steps": st})
+    return out
+
+
+def tnslq_mutual_information(psi, n_qubits: int, a, b, n_probes: int = 8, n_steps: int = 40, reorth: bool = False,
+                             seed: int = 0, probe_offset: int = 0, workspace=None, stream=None) -> Dict[str, float]:
+    """I(A:B) = S(A) + S(B) - S(AB) of the device state ``psi``, in bits."""
+    import numpy as np
+    _check_device_tensor(psi, "psi")
+    dt = _dtype_code(psi)
+    opts = make_options(n_probes, n_steps, reorth, "fp64", seed, probe_offset, 0.0)
+    p = _partition(n_qubits, a, b)
+    n = ctypes.c_size_t(0)
+    _check(lib().tnslq_mutual_information_workspace_bytes(dt, ctypes.byref(p), ctypes.byref(opts), ctypes.byref(n)),
+           "tnslq_mutual_information_workspace_bytes")
+    ws = _workspace(max(n.value, 256), psi.device, workspace)
+    out = np.zeros(8)
+    _check(lib().tnslq_mutual_information(_ptr(psi), dt, ctypes.byref(p), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                          _stream(stream), out.ctypes.data_as(ctypes.c_void_p)),
+           "tnslq_mutual_information")
+    keys = ("mutual_information", "mutual_information_se", "S_A", "S_A_se", "S_B", "S_B_se", "S_AB", "S_AB_se")
+    return {k: float(v) for k, v in zip(keys, out)}

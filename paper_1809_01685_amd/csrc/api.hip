@@ -340,7 +340,7 @@ int slq_setup(Ctx &c, const void *psi, uint64_t seed, uint64_t offset) {
 int quad_stats(Ctx &c, int jdone, int jlo, int jhi, int jstat, double *G) {
     const Plan &pl = c.pl;
     TNSLQ_HIP(launch_steps(c.alpha, c.beta, pl.K, pl.m, jdone, c.steps, c.st));
-    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, pl.K, pl.m, jlo, jhi, c.F, c.st));
+    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, pl.K, pl.m, jlo, jhi, TNSLQ_F_ABS, c.F, c.st));
     TNSLQ_HIP(launch_stats(c.beta, c.F, pl.K, pl.m, jstat, G, c.stats, c.st));
     return TNSLQ_OK;
 }
@@ -434,7 +434,7 @@ int fit_step(Run &r, int j, double *G) {
     Ctx &c = r.c;
     const int lo = std::max(2, j - TNSLQ_FIT_WINDOW + 1);
     TNSLQ_HIP(launch_steps(c.alpha, c.beta, c.pl.K, c.pl.m, j, c.steps, c.st));
-    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, c.pl.K, c.pl.m, lo, j, c.F, c.st));
+    TNSLQ_HIP(launch_quadrature(c.alpha, c.beta, c.steps, c.pl.K, c.pl.m, lo, j, TNSLQ_F_ABS, c.F, c.st));
     TNSLQ_HIP(launch_fit(c.alpha, c.beta, c.F, c.pl.K, c.pl.m, j, c.finf, c.fsig, G, c.fitout, c.st));
     return TNSLQ_OK;
 }
@@ -534,6 +534,255 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     return TNSLQ_OK;
 }
 
+
+// ------------------------------------------------------------ spectral sums
+// Tr f(rho_S) for f = -x log2 x or x^2 by Algorithm 1 on the reduced density
+// matrix of the smaller side, applied as two passes over psi (entropy.hip).
+struct SPlan {
+    int L = 0, dtype = TNSLQ_C64, fn = TNSLQ_F_ENTROPY;
+    int n_side = 0, n_rest = 0, complement = 0;
+    int side[TNSLQ_MAX_QUBITS], rest[TNSLQ_MAX_QUBITS];
+    int64_t d = 1, dR = 1, D = 1;
+    int K = 1, m = 1, reorth = 0;
+    int S1 = 1, S2 = 1, nblk = 1, nQ = 3;
+    size_t off_P1 = 0, off_P2 = 0, off_Zp = 0, off_Yp = 0, off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0;
+    size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, total = 0;
+};
+
+int check_subsystem(int L, const int *s, int n_s) {
+    if (L < 1 || L > TNSLQ_MAX_QUBITS) return fail(TNSLQ_E_PARTITION, "n_qubits %d outside [1, %d]", L, TNSLQ_MAX_QUBITS);
+    if (n_s < 0 || n_s > L) return fail(TNSLQ_E_PARTITION, "subsystem size %d outside [0, %d]", n_s, L);
+    if (n_s > 0 && !s) return fail(TNSLQ_E_ARG, "qubit list is NULL");
+    std::vector<int> seen(L, 0);
+    for (int i = 0; i < n_s; ++i) {
+        if (s[i] < 0 || s[i] >= L) return fail(TNSLQ_E_PARTITION, "qubit %d out of range", s[i]);
+        if (seen[s[i]]) return fail(TNSLQ_E_PARTITION, "qubit %d repeated", s[i]);
+        seen[s[i]] = 1;
+    }
+    return TNSLQ_OK;
+}
+
+int check_spectral_options(const tnslq_options *opt, int fn) {
+    int rc;
+    if ((rc = check_options(opt))) return rc;
+    if (fn != TNSLQ_F_ENTROPY && fn != TNSLQ_F_PURITY) return fail(TNSLQ_E_ARG, "function %d unknown", fn);
+    if (opt->precision != TNSLQ_FP64) return fail(TNSLQ_E_ARG, "spectral sums compute in FP64 only");
+    if (opt->stop_tol != 0.0) return fail(TNSLQ_E_ARG, "spectral sums run a fixed number of steps (stop_tol 0)");
+    return TNSLQ_OK;
+}
+
+// Output bit t <- input bit, for psi regrouped with group `hi` most
+// significant and group `lo` least significant.
+PermDesc perm_two(int L, const int *hi, int n_hi, const int *lo, int n_lo) {
+    PermDesc pd{};
+    pd.L = L;
+    int t = 0;
+    for (int i = n_lo - 1; i >= 0; --i) pd.map[t++] = L - 1 - lo[i];
+    for (int i = n_hi - 1; i >= 0; --i) pd.map[t++] = L - 1 - hi[i];
+    return pd;
+}
+
+int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt, int fn, SPlan &sp) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_subsystem(L, s, n_s)) || (rc = check_spectral_options(opt, fn)))
+        return rc;
+    sp = SPlan();
+    sp.L = L;
+    sp.dtype = dtype;
+    sp.fn = fn;
+    std::vector<int> in_s(L, 0), comp;
+    for (int i = 0; i < n_s; ++i) in_s[s[i]] = 1;
+    for (int q = 0; q < L; ++q)
+        if (!in_s[q]) comp.push_back(q);
+    sp.complement = n_s > L - n_s;
+    const int *side = sp.complement ? comp.data() : s;
+    const int *rest = sp.complement ? s : comp.data();
+    sp.n_side = sp.complement ? L - n_s : n_s;
+    sp.n_rest = L - sp.n_side;
+    for (int i = 0; i < sp.n_side; ++i) sp.side[i] = side[i];
+    for (int i = 0; i < sp.n_rest; ++i) sp.rest[i] = rest[i];
+    sp.d = int64_t(1) << sp.n_side;
+    sp.dR = int64_t(1) << sp.n_rest;
+    sp.D = int64_t(1) << L;
+    sp.K = opt->n_probes;
+    sp.m = opt->n_steps;
+    sp.reorth = opt->reorth;
+    // row splits of the two passes: about 2048 blocks, at least 64 rows each
+    const int64_t kg = (sp.K + 7) / 8;
+    const int64_t cb1 = (sp.dR + 255) / 256 * kg, cb2 = (sp.d + 255) / 256 * kg;
+    while (cb1 * sp.S1 < 2048 && sp.d / (2 * sp.S1) >= 64 && sp.S1 < 1024) sp.S1 *= 2;
+    while (cb2 * sp.S2 < 2048 && sp.dR / (2 * sp.S2) >= 64 && sp.S2 < 1024) sp.S2 *= 2;
+    sp.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, sp.d / 4096));
+    sp.nQ = sp.reorth ? sp.m + 1 : 3;
+    const size_t esz = dtype == TNSLQ_C128 ? 16 : 8;
+    const int K = sp.K, m = sp.m;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += up(bytes);
+        return r;
+    };
+    sp.off_P1 = take(esz * (size_t)sp.D);
+    sp.off_P2 = take(esz * (size_t)sp.D);
+    sp.off_Zp = take((size_t)sp.S1 * K * sp.dR * 16);
+    sp.off_Yp = take((size_t)sp.S2 * K * sp.d * 16);
+    sp.off_Q = take((size_t)sp.nQ * K * sp.d * 16);
+    sp.off_w = take((size_t)K * sp.d * 16);
+    sp.off_alpha = take((size_t)K * m * 8);
+    sp.off_beta = take((size_t)K * (m + 1) * 8);
+    sp.off_F = take((size_t)K * m * 8);
+    sp.off_G = take((size_t)K * 8);
+    sp.off_stats = take((size_t)m * 4 * 8);
+    sp.off_red = take((size_t)2 * K * sp.nblk * 8);
+    sp.off_h = take((size_t)K * (m + 1) * sp.nblk * 16 + (size_t)K * (m + 1) * 16);
+    sp.off_steps = take((size_t)K * 4);
+    sp.total = o;
+    return TNSLQ_OK;
+}
+
+void spectral_trivial(const SPlan *sp, int fn, const tnslq_options *opt, tnslq_spectral_result *res, double *G,
+                      double *alpha, double *beta, double *F, int *steps) {
+    memset(res, 0, sizeof *res);
+    const double v = fn == TNSLQ_F_ENTROPY ? 0.0 : 1.0;
+    res->value = v;
+    (void)sp;
+    const int K = opt->n_probes, m = opt->n_steps;
+    if (G) std::fill(G, G + K, v);
+    if (alpha) std::fill(alpha, alpha + (size_t)K * m, 0.0);
+    if (beta) std::fill(beta, beta + (size_t)K * (m + 1), 0.0);
+    if (F) std::fill(F, F + (size_t)K * m, v);
+    if (steps) std::fill(steps, steps + K, 0);
+}
+
+// The whole spectral sum with a validated plan, on the caller's workspace.
+int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uint64_t offset, void *ws,
+                 hipStream_t st, tnslq_spectral_result *res, double *Gh, double *alh, double *beh, double *Fh,
+                 int *sth, const Timer &tm) {
+    char *base = (char *)ws;
+    void *P1 = base + sp.off_P1, *P2 = base + sp.off_P2;
+    double2 *Zp = (double2 *)(base + sp.off_Zp), *Yp = (double2 *)(base + sp.off_Yp);
+    double2 *Q = (double2 *)(base + sp.off_Q), *w = (double2 *)(base + sp.off_w);
+    double *alpha = (double *)(base + sp.off_alpha), *beta = (double *)(base + sp.off_beta);
+    double *F = (double *)(base + sp.off_F), *G = (double *)(base + sp.off_G);
+    double *stats = (double *)(base + sp.off_stats);
+    double *dotpart = (double *)(base + sp.off_red), *nrmpart = dotpart + (size_t)sp.K * sp.nblk;
+    double *hpart = (double *)(base + sp.off_h);
+    double2 *h = (double2 *)(base + sp.off_h + (size_t)sp.K * (sp.m + 1) * sp.nblk * 16);
+    int *steps = (int *)(base + sp.off_steps);
+    const LzDims z{sp.d, 1, sp.d, sp.K, sp.m, sp.nblk};
+    const int64_t n = sp.d, slot = (int64_t)sp.K * n;
+    std::vector<hipEvent_t> ev;
+    struct Guard {
+        std::vector<hipEvent_t> &e;
+        ~Guard() {
+            for (auto x : e) (void)hipEventDestroy(x);
+        }
+    } guard{ev};
+    auto event = [&]() {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) == hipSuccess) ev.push_back(e);
+        return e;
+    };
+    hipEvent_t e0 = event(), e1 = event();
+    std::vector<hipEvent_t> mv0(sp.m + 1), mv1(sp.m + 1), lz1(sp.m + 1);
+    for (int j = 1; j <= sp.m; ++j) {
+        mv0[j] = event();
+        mv1[j] = event();
+        lz1[j] = event();
+    }
+    if ((int)ev.size() != 2 + 3 * sp.m) return fail(TNSLQ_E_DEVICE, "hipEventCreate failed");
+    TNSLQ_HIP(hipEventRecord(e0, st));
+    const PermDesc p1 = perm_two(sp.L, sp.side, sp.n_side, sp.rest, sp.n_rest);
+    const PermDesc p2 = perm_two(sp.L, sp.rest, sp.n_rest, sp.side, sp.n_side);
+    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P1, sp.D, p1, st));
+    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P2, sp.D, p2, st));
+    TNSLQ_HIP(hipMemsetAsync(alpha, 0, (size_t)sp.K * sp.m * 8, st));
+    TNSLQ_HIP(hipMemsetAsync(beta, 0, (size_t)sp.K * (sp.m + 1) * 8, st));
+    TNSLQ_HIP(hipMemsetAsync(F, 0, (size_t)sp.K * sp.m * 8, st));
+    TNSLQ_HIP(launch_probe_init(TNSLQ_FP64, z, opt->seed, offset, 0, Q, nullptr, 0, alpha, beta, st));
+    TNSLQ_HIP(hipEventRecord(e1, st));
+    auto slot_of = [&](int jj) { return sp.reorth ? jj : jj % 3; };
+    for (int j = 1; j <= sp.m; ++j) {
+        double2 *q_cur = Q + slot_of(j - 1) * slot;
+        double2 *q_prev = j > 1 ? Q + slot_of(j - 2) * slot : q_cur;
+        double2 *q_next = Q + slot_of(j) * slot;
+        TNSLQ_HIP(hipEventRecord(mv0[j], st));
+        // Z = Psi^dagger q over P1 (d x d_R); Y = Psi Z over P2 = Psi^T (d_R x d)
+        TNSLQ_HIP(launch_colmac(sp.dtype, 1, P1, sp.d, sp.dR, q_cur, 1, 0, sp.K, Zp, sp.S1, st));
+        TNSLQ_HIP(launch_colmac(sp.dtype, 0, P2, sp.dR, sp.d, Zp, sp.S1, (int64_t)sp.K * sp.dR, sp.K, Yp, sp.S2, st));
+        TNSLQ_HIP(hipEventRecord(mv1[j], st));
+        TNSLQ_HIP(launch_passA(1, z, Yp, sp.S2, slot, 0, sp.K, q_prev, q_cur, w, alpha, beta, j, dotpart, st));
+        TNSLQ_HIP(launch_passB(z, dotpart, q_cur, w, alpha, beta, j, nrmpart, sp.reorth ? 0 : 1, st));
+        if (sp.reorth) TNSLQ_HIP(launch_reorth(z, Q, j, slot, w, hpart, h, alpha, beta, j, nrmpart, st));
+        TNSLQ_HIP(launch_passC(TNSLQ_FP64, z, nrmpart, w, q_next, nullptr, 0, alpha, beta, j, st));
+        TNSLQ_HIP(hipEventRecord(lz1[j], st));
+    }
+    TNSLQ_HIP(launch_steps(alpha, beta, sp.K, sp.m, sp.m, steps, st));
+    TNSLQ_HIP(launch_quadrature(alpha, beta, steps, sp.K, sp.m, 1, sp.m, sp.fn, F, st));
+    TNSLQ_HIP(launch_stats(beta, F, sp.K, sp.m, sp.m, G, stats, st));
+    double sv[4];
+    std::vector<int> hsteps(sp.K);
+    TNSLQ_HIP(hipMemcpyAsync(sv, stats + (size_t)(sp.m - 1) * 4, sizeof sv, hipMemcpyDeviceToHost, st));
+    TNSLQ_HIP(hipMemcpyAsync(hsteps.data(), steps, sizeof(int) * sp.K, hipMemcpyDeviceToHost, st));
+    if (Gh) TNSLQ_HIP(hipMemcpyAsync(Gh, G, sizeof(double) * sp.K, hipMemcpyDeviceToHost, st));
+    if (alh) TNSLQ_HIP(hipMemcpyAsync(alh, alpha, sizeof(double) * sp.K * sp.m, hipMemcpyDeviceToHost, st));
+    if (beh) TNSLQ_HIP(hipMemcpyAsync(beh, beta, sizeof(double) * sp.K * (sp.m + 1), hipMemcpyDeviceToHost, st));
+    if (Fh) TNSLQ_HIP(hipMemcpyAsync(Fh, F, sizeof(double) * sp.K * sp.m, hipMemcpyDeviceToHost, st));
+    TNSLQ_HIP(hipStreamSynchronize(st));
+    if (sth) std::copy(hsteps.begin(), hsteps.end(), sth);
+    memset(res, 0, sizeof *res);
+    res->value = sv[0];
+    res->value_se = sv[1];
+    res->steps_done = sp.m;
+    res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
+    res->complement = sp.complement;
+    res->n_qubits_side = sp.n_side;
+    res->t_layout_ms = elapsed(e0, e1);
+    for (int j = 1; j <= sp.m; ++j) {
+        res->t_matvec_ms += elapsed(mv0[j], mv1[j]);
+        res->t_lanczos_ms += elapsed(mv1[j], lz1[j]);
+    }
+    res->t_total_ms = tm.ms();
+    if (!std::isfinite(res->value)) return fail(TNSLQ_E_NONFINITE, "estimate is not finite");
+    return TNSLQ_OK;
+}
+
+int spectral_sum(const void *psi, int dtype, int L, const int *s, int n_s, int fn, const tnslq_options *opt,
+                 uint64_t offset, void *ws, size_t ws_bytes, void *stream, tnslq_spectral_result *res, double *Gh,
+                 double *alh, double *beh, double *Fh, int *sth) {
+    Timer tm;
+    int rc;
+    if (!res) return fail(TNSLQ_E_ARG, "result is NULL");
+    if ((rc = check_dtype(dtype)) || (rc = check_subsystem(L, s, n_s)) || (rc = check_spectral_options(opt, fn)))
+        return rc;
+    if (n_s == 0 || n_s == L) {
+        spectral_trivial(nullptr, fn, opt, res, Gh, alh, beh, Fh, sth);
+        res->t_total_ms = tm.ms();
+        return TNSLQ_OK;
+    }
+    SPlan sp;
+    if ((rc = make_splan(dtype, L, s, n_s, opt, fn, sp))) return rc;
+    if (!psi) return fail(TNSLQ_E_ARG, "psi is NULL");
+    if (!ws) return fail(TNSLQ_E_ARG, "workspace is NULL");
+    if ((uintptr_t)ws % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < sp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, sp.total);
+    return spectral_run(sp, psi, opt, offset, ws, (hipStream_t)stream, res, Gh, alh, beh, Fh, sth, tm);
+}
+
+int spectral_bytes(int dtype, int L, const int *s, int n_s, const tnslq_options *opt, int fn, size_t *bytes) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_subsystem(L, s, n_s)) || (rc = check_spectral_options(opt, fn)))
+        return rc;
+    if (n_s == 0 || n_s == L) {
+        *bytes = 0;
+        return TNSLQ_OK;
+    }
+    SPlan sp;
+    if ((rc = make_splan(dtype, L, s, n_s, opt, fn, sp))) return rc;
+    *bytes = sp.total;
+    return TNSLQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -623,12 +872,79 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
     return TNSLQ_OK;
 }
 
+int tnslq_spectral_workspace_bytes(int dtype, int n_qubits, const int *s, int n_s, const tnslq_options *opt,
+                                   size_t *bytes) {
+    g_err.clear();
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    // the function does not change the workspace; entropy stands for both
+    return spectral_bytes(dtype, n_qubits, s, n_s, opt, TNSLQ_F_ENTROPY, bytes);
+}
+
+int tnslq_spectral_sum(const void *psi_dev, int dtype, int n_qubits, const int *s, int n_s, int fn,
+                       const tnslq_options *opt, void *ws_dev, size_t ws_bytes, void *stream,
+                       tnslq_spectral_result *res, double *G_host, double *alpha_host, double *beta_host,
+                       double *F_host, int *steps_host) {
+    g_err.clear();
+    if (!opt) return fail(TNSLQ_E_ARG, "options is NULL");
+    return spectral_sum(psi_dev, dtype, n_qubits, s, n_s, fn, opt, opt->probe_offset, ws_dev, ws_bytes, stream, res,
+                        G_host, alpha_host, beta_host, F_host, steps_host);
+}
+
+int tnslq_mutual_information_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt,
+                                             size_t *bytes) {
+    int rc;
+    g_err.clear();
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    if ((rc = check_partition(part))) return rc;
+    std::vector<int> ab(part->a, part->a + part->n_a);
+    ab.insert(ab.end(), part->b, part->b + part->n_b);
+    size_t best = 0, b = 0;
+    const int *sets[3] = {part->a, part->b, ab.data()};
+    const int sizes[3] = {part->n_a, part->n_b, (int)ab.size()};
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = spectral_bytes(dtype, part->n_qubits, sets[i], sizes[i], opt, TNSLQ_F_ENTROPY, &b))) return rc;
+        best = std::max(best, b);
+    }
+    *bytes = best;
+    return TNSLQ_OK;
+}
+
+int tnslq_mutual_information(const void *psi_dev, int dtype, const tnslq_partition *part, const tnslq_options *opt,
+                             void *ws_dev, size_t ws_bytes, void *stream, double *out) {
+    int rc;
+    g_err.clear();
+    if (!out) return fail(TNSLQ_E_ARG, "out is NULL");
+    if (!opt) return fail(TNSLQ_E_ARG, "options is NULL");
+    if ((rc = check_partition(part))) return rc;
+    std::vector<int> ab(part->a, part->a + part->n_a);
+    ab.insert(ab.end(), part->b, part->b + part->n_b);
+    const int *sets[3] = {part->a, part->b, ab.data()};
+    const int sizes[3] = {part->n_a, part->n_b, (int)ab.size()};
+    double v[3], e[3];
+    for (int i = 0; i < 3; ++i) {
+        tnslq_spectral_result r;
+        const uint64_t off = opt->probe_offset + (uint64_t)i * (uint64_t)opt->n_probes;
+        if ((rc = spectral_sum(psi_dev, dtype, part->n_qubits, sets[i], sizes[i], TNSLQ_F_ENTROPY, opt, off, ws_dev,
+                               ws_bytes, stream, &r, nullptr, nullptr, nullptr, nullptr, nullptr)))
+            return rc;
+        v[i] = r.value;
+        e[i] = (sizes[i] == 0 || sizes[i] == part->n_qubits) ? 0.0 : r.value_se;
+    }
+    out[0] = v[0] + v[1] - v[2];
+    out[1] = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    for (int i = 0; i < 3; ++i) {
+        out[2 + 2 * i] = v[i];
+        out[3 + 2 * i] = e[i];
+    }
+    return TNSLQ_OK;
+}
+
 int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev, int n_probes, int n_steps,
                      double *F_dev, void *stream) {
     g_err.clear();
     if (!alpha_dev || !beta_dev || !F_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
     if (n_probes < 1 || n_steps < 1 || n_steps > TNSLQ_MAX_STEPS) return fail(TNSLQ_E_ARG, "bad sizes");
-    TNSLQ_HIP(launch_quadrature(alpha_dev, beta_dev, steps_dev, n_probes, n_steps, 1, n_steps, F_dev,
+    TNSLQ_HIP(launch_quadrature(alpha_dev, beta_dev, steps_dev, n_probes, n_steps, 1, n_steps, TNSLQ_F_ABS, F_dev,
                                 (hipStream_t)stream));
     return TNSLQ_OK;
 }

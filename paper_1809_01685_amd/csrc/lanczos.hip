@@ -225,10 +225,13 @@ __global__ void __launch_bounds__(256) k_passC(const double *__restrict__ nrmpar
         double2 q = cont ? make_double2(v.x / b, v.y / b) : make_double2(0.0, 0.0);
         q_next[base + e] = q;
         // Xt entry (row (k, b'), reduction index a') reads w at a' * dB + b'
-        const int64_t bb = e / dA, aa = e % dA;
-        double2 u = w[base + aa * dB + bb];
-        double2 qt = cont ? make_double2(u.x / b, u.y / b) : make_double2(0.0, 0.0);
-        store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + bb, aa), qt.x, qt.y);
+        if (Xt) {
+            const int64_t bb = e / dA, aa = e % dA;
+            double2 u = w[base + aa * dB + bb];
+            double2 qt = cont ? make_double2(u.x / b, u.y / b) : make_double2(0.0, 0.0);
+            store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + bb, aa), qt.x,
+                               qt.y);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) bk[j] = b;
 }
@@ -292,8 +295,16 @@ __device__ void tridiag_ql_first_row(int n, double *d, double *e, double *z) {
 }
 
 // F[k][j-1] = sum_i tau_i^2 |theta_i| for T_j (j capped at steps[k]).
+// f of the quadrature: TNSLQ_F_ABS |x| (the negativity), TNSLQ_F_ENTROPY
+// -x log2 x (0 for x <= 0), TNSLQ_F_PURITY x^2.
+__device__ inline double quad_f(int fn, double x) {
+    if (fn == TNSLQ_F_ENTROPY) return x > 0.0 ? -x * log2(x) : 0.0;
+    if (fn == TNSLQ_F_PURITY) return x * x;
+    return fabs(x);
+}
+
 __global__ void k_quadrature(const double *__restrict__ alpha, const double *__restrict__ beta,
-                             const int *__restrict__ steps, int K, int m, int jlo, int jhi,
+                             const int *__restrict__ steps, int K, int m, int jlo, int jhi, int fn,
                              double *__restrict__ F) {
     const int nj = jhi - jlo + 1;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,7 +319,7 @@ __global__ void k_quadrature(const double *__restrict__ alpha, const double *__r
     }
     tridiag_ql_first_row(jj, d, e, z);
     double f = 0.0;
-    for (int i = 0; i < jj; ++i) f += z[i] * z[i] * fabs(d[i]);
+    for (int i = 0; i < jj; ++i) f += z[i] * z[i] * quad_f(fn, d[i]);
     F[(int64_t)k * m + (j - 1)] = f;
 }
 
@@ -586,9 +597,9 @@ hipError_t launch_steps(const double *alpha, const double *beta, int K, int m, i
 }
 
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int *steps, int K, int m, int jlo,
-                             int jhi, double *F, hipStream_t st) {
+                             int jhi, int fn, double *F, hipStream_t st) {
     const int64_t nt = (int64_t)K * (jhi - jlo + 1);
-    hipLaunchKernelGGL(k_quadrature, dim3(cdiv(nt, 64)), dim3(64), 0, st, alpha, beta, steps, K, m, jlo, jhi, F);
+    hipLaunchKernelGGL(k_quadrature, dim3(cdiv(nt, 64)), dim3(64), 0, st, alpha, beta, steps, K, m, jlo, jhi, fn, F);
     return hipGetLastError();
 }
 

@@ -91,11 +91,13 @@ __global__ void __launch_bounds__(256) k_probe_init(uint64_t seed, uint64_t offs
         const int64_t a = e / dB, b = e % dB;
         double2 v = probe_value(seed, offset, k, a, b, dA, dB, swapped);
         q[(int64_t)k * n + e] = make_double2(v.x / b1, v.y / b1);
-        // Xt row (k, b'), reduction index a'
-        const int64_t b2 = e / dA, a2 = e % dA;
-        double2 u = probe_value(seed, offset, k, a2, b2, dA, dB, swapped);
-        store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + b2, a2), u.x / b1,
-                           u.y / b1);
+        // Xt row (k, b'), reduction index a' (when the caller contracts through Xt)
+        if (Xt) {
+            const int64_t b2 = e / dA, a2 = e % dA;
+            double2 u = probe_value(seed, offset, k, a2, b2, dA, dB, swapped);
+            store_planes<PREC>(Xt, brick_ps(PREC), brick_index(PREC, xt_nst, (int64_t)k * dB + b2, a2), u.x / b1,
+                               u.y / b1);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) beta[(int64_t)k * (m + 1)] = b1;
 }

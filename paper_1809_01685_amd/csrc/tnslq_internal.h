@@ -79,8 +79,9 @@ hipError_t launch_reorth(const LzDims &z, const double2 *Q, int nvec, int64_t q_
 hipError_t launch_passC(int prec, const LzDims &z, const double *nrmpart, const double2 *w,
                         double2 *q_next, void *Xt, int64_t xt_nst, const double *alpha,
                         double *beta, int j, hipStream_t st);
+// fn: TNSLQ_F_ABS, TNSLQ_F_ENTROPY or TNSLQ_F_PURITY
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int *steps, int K,
-                             int m, int jlo, int jhi, double *F, hipStream_t st);
+                             int m, int jlo, int jhi, int fn, double *F, hipStream_t st);
 hipError_t launch_steps(const double *alpha, const double *beta, int K, int m, int jdone,
                         int *steps, hipStream_t st);
 hipError_t launch_stats(const double *beta, const double *F, int K, int m, int j, double *G,
@@ -100,6 +101,15 @@ hipError_t launch_load_vectors(int prec, const double2 *X, int64_t dA, int64_t d
 hipError_t launch_features(const double *alpha, const double *beta, int K, int m, int n_early,
                            double dAB, double dA, double dB, double dE, float *feat,
                            hipStream_t st);
+
+// ------------------------------------------------------------ entropy
+// Plain regrouping (same dtype, interleaved complex) and the column MAC
+// out[s][k][c] = sum_{i in split s} op(M[i][c]) V[k][i] over a row-major R x C
+// matrix M, V the sum of v_splits partial K x R arrays (stride v_split_stride),
+// out S x K x C, rows split evenly (R % S == 0).
+hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t D, const PermDesc &pd, hipStream_t st);
+hipError_t launch_colmac(int dtype, int conj, const void *M, int64_t R, int64_t C, const double2 *V, int v_splits,
+                         int64_t v_split_stride, int K, double2 *out, int S, hipStream_t st);
 
 // ------------------------------------------------------------ MLP
 size_t mlp_ws_bytes(int batch);

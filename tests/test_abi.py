@@ -111,7 +111,8 @@ def test_binding_structs_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    structs = {"tnslq_partition": T.Partition, "tnslq_options": T.Options, "tnslq_result": T.Result}
+    structs = {"tnslq_partition": T.Partition, "tnslq_options": T.Options, "tnslq_result": T.Result,
+               "tnslq_spectral_result": T.SpectralResult}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tnslq.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -128,3 +129,37 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_spectral_sum_validates_and_handles_trivial_subsystems_without_device(L):
+    import ctypes as C
+    o = T.make_options(3, 5, precision="fp64")
+    res = T.SpectralResult()
+    G = np.full(3, -1.0)
+    for fn, want in ((T.TNSLQ_F_ENTROPY, 0.0), (T.TNSLQ_F_PURITY, 1.0)):
+        for s in ([], [0, 1, 2, 3]):
+            arr = (C.c_int * 4)(*s) if s else None
+            rc = L.tnslq_spectral_sum(None, 0, 4, C.cast(arr, C.c_void_p) if arr else None, len(s), fn,
+                                      C.byref(o), None, 0, None, C.byref(res), G.ctypes.data_as(C.c_void_p),
+                                      None, None, None, None)
+            assert rc == 0 and res.value == want and np.all(G == want)
+    arr = (C.c_int * 2)(0, 1)
+    bad = [(o, 7), (T.make_options(3, 5, precision="fp32"), 1), (T.make_options(3, 5, precision="fp64", stop_tol=0.1), 1)]
+    for oo, fn in bad:
+        rc = L.tnslq_spectral_sum(None, 0, 4, C.cast(arr, C.c_void_p), 2, fn, C.byref(oo), None, 0, None,
+                                  C.byref(res), None, None, None, None, None)
+        assert rc == -1, (fn, oo.precision)
+    # NULL psi on a real subsystem: argument error before any launch
+    rc = L.tnslq_spectral_sum(None, 0, 4, C.cast(arr, C.c_void_p), 2, 1, C.byref(o), None, 0, None,
+                              C.byref(res), None, None, None, None, None)
+    assert rc == -1 and "NULL" in T.tnslq_last_error()
+    rep = (C.c_int * 2)(1, 1)
+    n = C.c_size_t(0)
+    assert L.tnslq_spectral_workspace_bytes(0, 4, C.cast(rep, C.c_void_p), 2, C.byref(o), C.byref(n)) == -2
+
+
+def test_spectral_workspace_uses_the_smaller_side(L):
+    o = T.make_options(4, 10, precision="fp64")
+    small = T.tnslq_spectral_workspace_bytes(T.TNSLQ_C64, 16, [0, 1, 2], o)
+    large = T.tnslq_spectral_workspace_bytes(T.TNSLQ_C64, 16, list(range(3, 16)), o)
+    assert small == large > 2 * 8 * (1 << 16)

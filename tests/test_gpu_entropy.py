@@ -1,0 +1,123 @@
+"""GPU parity of the other spectral sums (von Neumann entropy, purity, mutual
+information) against the oracle, through the C ABI.
+
+The device computes rho X = Psi (Psi^dagger X) with FP64 products and sums and
+runs the FP64 Lanczos recurrence; on the same probes its coefficients match
+the oracle's to rounding (tolerances 1e-10 relative on the Lanczos
+coefficients and 1e-9 on the probe values G_n, which pass through a
+tridiagonal eigensolve of up to 30 steps).
+"""
+import numpy as np
+import pytest
+
+import tnslq_inputs as ti
+from oracle import entropy as en
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_1809_01685_amd")
+
+
+def _dev(psi_np, dtype, dev):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(psi_np.astype(dtype))).to(dev)
+    return t, t.cpu().numpy().astype(np.complex128)
+
+
+CASES = [
+    (10, [0, 1, 2], 8),                   # d = 8: m = d exhausts the Krylov space
+    (12, [1, 5, 7, 9], 16),               # non-contiguous subsystem
+    (11, list(range(4, 11)), 16),         # the complement is the smaller side
+    (13, list(range(6)), 20),
+    (14, [13, 0, 6, 2, 9, 4, 11], 24),    # d = d_R = 128, unordered qubits
+]
+
+
+@pytest.mark.parametrize("fn", ["entropy", "purity"])
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+@pytest.mark.parametrize("L,s,m", CASES)
+def test_spectral_sum_matches_oracle_on_same_probes(dev, L, s, m, fn, dtype):
+    psi_t, psi_np = _dev(ti.haar_state(L, L + 3), dtype, dev)
+    K = 6
+    g = T.tnslq_spectral_sum(psi_t, L, s, fn, K, m, seed=3)
+    o = en.slq_spectral_sum(psi_np, L, s, fn, K, m, seed=3)
+    assert g["complement"] == (o["side"] != list(s))
+    # m <= d: beta_{d+1} (when m = d) is a rounding residual on both sides and
+    # enters no quadrature; every other coefficient is determined
+    d = 1 << min(len(s), L - len(s))
+    assert m <= d
+    nb = min(m, d - 1)
+    assert np.allclose(g["alpha"], o["alpha"], rtol=1e-10, atol=1e-12 * np.abs(o["alpha"]).max())
+    assert np.allclose(g["beta"][:, 1:nb + 1], o["beta"][:, 1:nb + 1], rtol=1e-10, atol=0)
+    assert np.array_equal(g["beta"][:, 0], o["beta"][:, 0])
+    assert np.allclose(g["G"], o["G"], rtol=1e-9, atol=0)
+    assert g["value"] == pytest.approx(o["value"], rel=1e-9)
+    assert g["value_se"] == pytest.approx(o["value_se"], rel=1e-6)
+
+
+def test_reorthogonalised_entropy_matches_oracle_and_exact(dev):
+    import torch
+    L, s = 12, list(range(5))
+    psi = ti.haar_state(L, 9)
+    psi_t = torch.from_numpy(psi).to(dev)
+    g = T.tnslq_spectral_sum(psi_t, L, s, "entropy", 32, 30, reorth=True, seed=1)
+    o = en.slq_spectral_sum(psi, L, s, "entropy", 32, 30, seed=1, reorth=True)
+    assert np.allclose(g["G"], o["G"], rtol=1e-8, atol=0)
+    ex = en.entropy_exact(psi, L, s)
+    assert abs(g["value"] - ex) < 4 * g["value_se"] + 1e-3
+
+
+def test_low_rank_states_are_exact(dev):
+    import torch
+    # Bell pair across the cut: Schmidt rank 2, every probe breaks down by step 2
+    psi_t = torch.from_numpy(ti.bell_pair_state(8, 2, 6)).to(dev)
+    r = T.tnslq_spectral_sum(psi_t, 8, [0, 1, 2, 3], "entropy", 4, 8, seed=0)
+    assert r["steps_min"] <= 2
+    assert r["value"] == pytest.approx(1.0, abs=1e-12)
+    p = T.tnslq_spectral_sum(psi_t, 8, [0, 1, 2, 3], "purity", 4, 8, seed=0)
+    assert p["value"] == pytest.approx(0.5, abs=1e-12)
+    # product state: rank 1
+    psi_t = torch.from_numpy(ti.basis_product_state(8, [1, 0, 0, 1, 1, 0, 1, 0])).to(dev)
+    r = T.tnslq_spectral_sum(psi_t, 8, [2, 3, 4], "entropy", 4, 8, seed=0)
+    assert r["value"] == pytest.approx(0.0, abs=1e-12)
+
+
+def test_mutual_information(dev):
+    import torch
+    L = 6
+    t = np.zeros([2] * L, dtype=np.complex128)
+    for x in (0, 1):
+        for y in (0, 1):
+            idx = [0] * L
+            idx[0] = idx[3] = x
+            idx[1] = idx[5] = y
+            t[tuple(idx)] = 0.5
+    psi_t = torch.from_numpy(t.reshape(-1)).to(dev)
+    r = T.tnslq_mutual_information(psi_t, L, [0, 1], [2, 3], 4, 6, seed=2)
+    assert r["mutual_information"] == pytest.approx(2.0, abs=1e-12)
+    assert r["S_A"] == pytest.approx(2.0, abs=1e-12) and r["S_B"] == pytest.approx(1.0, abs=1e-12)
+    # Haar state: the estimate is within its error of the exact value
+    L, a, b = 12, [0, 1, 2, 3], [4, 5, 6]
+    psi = ti.haar_state(L, 4)
+    r = T.tnslq_mutual_information(torch.from_numpy(psi).to(dev), L, a, b, 16, 30, reorth=True, seed=5)
+    ex = en.mutual_information_exact(psi, L, a, b)
+    assert abs(r["mutual_information"] - ex) < 4 * r["mutual_information_se"] + 2e-3
+
+
+def test_30_qubit_half_chain_entropy_is_pages_value(dev):
+    import torch
+    # full size: 30-qubit Haar state (complex64, 8 GiB), S = 15 qubits
+    # (d = d_R = 2^15): the entropy concentrates at Page's value
+    # 15 - 1 / (2 ln 2) + O(2^-15).  The quadrature has converged by ~10 steps
+    # (a 20-qubit analogue moves by 1e-3 between 10 and 80 steps); the
+    # Hutchinson error dominates, ~0.16 / sqrt(32 K) bits here
+    L = 30
+    psi = ti.haar_state_torch(L, 0, dev, torch.complex64)
+    r = T.tnslq_spectral_sum(psi, L, list(range(15)), "entropy", 16, 20, seed=0, want_arrays=False)
+    page = en.page_entropy(1 << 15, 1 << 15)
+    assert 0 < r["value_se"] < 0.03
+    assert abs(r["value"] - page) < 4 * r["value_se"] + 2e-3
+    p = T.tnslq_spectral_sum(psi, L, list(range(15)), "purity", 4, 4, seed=0, want_arrays=False)
+    assert p["value"] == pytest.approx(en.haar_mean_purity(1 << 15, 1 << 15), rel=0.02)
+    del psi
+    torch.cuda.empty_cache()
