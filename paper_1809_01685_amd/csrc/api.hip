@@ -545,7 +545,7 @@ struct SPlan {
     int64_t d = 1, dR = 1, D = 1;
     int K = 1, m = 1, reorth = 0;
     int S1 = 1, S2 = 1, nblk = 1, nQ = 3;
-    size_t off_P1 = 0, off_P2 = 0, off_Zp = 0, off_Yp = 0, off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0;
+    size_t off_P1 = 0, off_P2 = 0, off_Zp = 0, off_Z = 0, off_Yp = 0, off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0;
     size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, total = 0;
 };
 
@@ -609,7 +609,7 @@ int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt
     sp.reorth = opt->reorth;
     // row splits of the two passes: about 2048 blocks, at least 64 rows each
     const int64_t kg = (sp.K + 7) / 8;
-    const int64_t cb1 = (sp.dR + 255) / 256 * kg, cb2 = (sp.d + 255) / 256 * kg;
+    const int64_t cb1 = (sp.dR + 511) / 512 * kg, cb2 = (sp.d + 511) / 512 * kg;
     while (cb1 * sp.S1 < 2048 && sp.d / (2 * sp.S1) >= 64 && sp.S1 < 1024) sp.S1 *= 2;
     while (cb2 * sp.S2 < 2048 && sp.dR / (2 * sp.S2) >= 64 && sp.S2 < 1024) sp.S2 *= 2;
     sp.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, sp.d / 4096));
@@ -625,6 +625,7 @@ int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt
     sp.off_P1 = take(esz * (size_t)sp.D);
     sp.off_P2 = take(esz * (size_t)sp.D);
     sp.off_Zp = take((size_t)sp.S1 * K * sp.dR * 16);
+    sp.off_Z = take((size_t)K * sp.dR * 16);
     sp.off_Yp = take((size_t)sp.S2 * K * sp.d * 16);
     sp.off_Q = take((size_t)sp.nQ * K * sp.d * 16);
     sp.off_w = take((size_t)K * sp.d * 16);
@@ -660,7 +661,8 @@ int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uin
                  int *sth, const Timer &tm) {
     char *base = (char *)ws;
     void *P1 = base + sp.off_P1, *P2 = base + sp.off_P2;
-    double2 *Zp = (double2 *)(base + sp.off_Zp), *Yp = (double2 *)(base + sp.off_Yp);
+    double2 *Zp = (double2 *)(base + sp.off_Zp), *Z = (double2 *)(base + sp.off_Z);
+    double2 *Yp = (double2 *)(base + sp.off_Yp);
     double2 *Q = (double2 *)(base + sp.off_Q), *w = (double2 *)(base + sp.off_w);
     double *alpha = (double *)(base + sp.off_alpha), *beta = (double *)(base + sp.off_beta);
     double *F = (double *)(base + sp.off_F), *G = (double *)(base + sp.off_G);
@@ -694,8 +696,8 @@ int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uin
     TNSLQ_HIP(hipEventRecord(e0, st));
     const PermDesc p1 = perm_two(sp.L, sp.side, sp.n_side, sp.rest, sp.n_rest);
     const PermDesc p2 = perm_two(sp.L, sp.rest, sp.n_rest, sp.side, sp.n_side);
-    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P1, sp.D, p1, st));
-    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P2, sp.D, p2, st));
+    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P1, sp.d, sp.dR, p1, st));
+    TNSLQ_HIP(launch_regroup(sp.dtype, psi, P2, sp.dR, sp.d, p2, st));
     TNSLQ_HIP(hipMemsetAsync(alpha, 0, (size_t)sp.K * sp.m * 8, st));
     TNSLQ_HIP(hipMemsetAsync(beta, 0, (size_t)sp.K * (sp.m + 1) * 8, st));
     TNSLQ_HIP(hipMemsetAsync(F, 0, (size_t)sp.K * sp.m * 8, st));
@@ -708,8 +710,9 @@ int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uin
         double2 *q_next = Q + slot_of(j) * slot;
         TNSLQ_HIP(hipEventRecord(mv0[j], st));
         // Z = Psi^dagger q over P1 (d x d_R); Y = Psi Z over P2 = Psi^T (d_R x d)
-        TNSLQ_HIP(launch_colmac(sp.dtype, 1, P1, sp.d, sp.dR, q_cur, 1, 0, sp.K, Zp, sp.S1, st));
-        TNSLQ_HIP(launch_colmac(sp.dtype, 0, P2, sp.dR, sp.d, Zp, sp.S1, (int64_t)sp.K * sp.dR, sp.K, Yp, sp.S2, st));
+        TNSLQ_HIP(launch_colmac(sp.dtype, 1, P1, sp.d, sp.dR, q_cur, sp.K, Zp, sp.S1, st));
+        TNSLQ_HIP(launch_sum_splits(Zp, sp.S1, (int64_t)sp.K * sp.dR, Z, st));
+        TNSLQ_HIP(launch_colmac(sp.dtype, 0, P2, sp.dR, sp.d, Z, sp.K, Yp, sp.S2, st));
         TNSLQ_HIP(hipEventRecord(mv1[j], st));
         TNSLQ_HIP(launch_passA(1, z, Yp, sp.S2, slot, 0, sp.K, q_prev, q_cur, w, alpha, beta, j, dotpart, st));
         TNSLQ_HIP(launch_passB(z, dotpart, q_cur, w, alpha, beta, j, nrmpart, sp.reorth ? 0 : 1, st));

@@ -103,13 +103,16 @@ hipError_t launch_features(const double *alpha, const double *beta, int K, int m
                            hipStream_t st);
 
 // ------------------------------------------------------------ entropy
-// Plain regrouping (same dtype, interleaved complex) and the column MAC
-// out[s][k][c] = sum_{i in split s} op(M[i][c]) V[k][i] over a row-major R x C
-// matrix M, V the sum of v_splits partial K x R arrays (stride v_split_stride),
-// out S x K x C, rows split evenly (R % S == 0).
-hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t D, const PermDesc &pd, hipStream_t st);
-hipError_t launch_colmac(int dtype, int conj, const void *M, int64_t R, int64_t C, const double2 *V, int v_splits,
-                         int64_t v_split_stride, int K, double2 *out, int S, hipStream_t st);
+// psi regrouped as an R x C matrix in column panels 512 wide (same dtype,
+// interleaved complex); the column MAC out[s][k][c] = sum_{i in split s}
+// op(M[i][c]) V[k][i] over such a matrix M and K x R vectors V, out S x K x C,
+// rows split evenly (R % S == 0), C even; and the sum of S partial arrays of n
+// elements.
+hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int64_t C, const PermDesc &pd,
+                          hipStream_t st);
+hipError_t launch_colmac(int dtype, int conj, const void *M, int64_t R, int64_t C, const double2 *V, int K,
+                         double2 *out, int S, hipStream_t st);
+hipError_t launch_sum_splits(const double2 *part, int S, int64_t n, double2 *Z, hipStream_t st);
 
 // ------------------------------------------------------------ MLP
 size_t mlp_ws_bytes(int batch);
