@@ -122,6 +122,12 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     const int64_t tiles = ((pl.dA + 127) / 128) * ((pl.kc * pl.dB + 127) / 128);
     pl.S = 1;
     while (tiles * pl.S < 2048 && pl.nst2 % (2 * pl.S) == 0 && pl.nst2 / (2 * pl.S) >= 8) pl.S *= 2;
+    // the first contraction too, when its output (d_B d_E x kc d_B) has few
+    // tiles: partial sums in the accumulator type, merged into Ups afterwards
+    const int64_t tiles1 = ((pl.dB * pl.dE + 127) / 128) * ((pl.kc * pl.dB + 127) / 128);
+    pl.S1 = 1;
+    if (tiles1 < 1024)
+        while (tiles1 * pl.S1 < 2048 && pl.nst1 % (2 * pl.S1) == 0 && pl.nst1 / (2 * pl.S1) >= 8) pl.S1 *= 2;
     const int64_t n = pl.dAB;
     pl.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 4096));
 
@@ -136,6 +142,7 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     pl.off_Xt = take(brick_bytes(prec, (int64_t)K * pl.dB, pl.dA));
     pl.off_Ups = take(brick_bytes(prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB));
     pl.off_Ypart = take((size_t)pl.S * pl.kc * n * acc);
+    if (pl.S1 > 1) pl.off_U1part = take((size_t)pl.S1 * pl.kc * pl.dB * pl.dE * pl.dB * acc);
     if (lanczos) {
         pl.nQ = pl.reorth ? pl.m + 1 : 3;
         pl.off_Q = take((size_t)pl.nQ * K * n * 16);
@@ -174,7 +181,7 @@ struct Ctx {
     char *ws;
     hipStream_t st;
     LzDims z;
-    void *Paeb, *Pbea, *Xt, *Ups, *Ypart;
+    void *Paeb, *Pbea, *Xt, *Ups, *Ypart, *U1part;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -204,6 +211,7 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Xt = c.ws + pl.off_Xt;
     c.Ups = c.ws + pl.off_Ups;
     c.Ypart = c.ws + pl.off_Ypart;
+    c.U1part = pl.S1 > 1 ? c.ws + pl.off_U1part : nullptr;
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
     c.alpha = (double *)(c.ws + pl.off_alpha);
@@ -260,6 +268,16 @@ int contract_chunk(Ctx &c, int k0, int kcur, hipEvent_t e1, hipEvent_t e2) {
     g1.cni_log2 = pl.nE;
     g1.crs = pl.dB;
     g1.c_nst = pl.nst2;
+    const int64_t u1n = (int64_t)kcur * pl.dB * pl.dE * pl.dB;
+    if (pl.S1 > 1) {
+        // split along a': partials at s * split + k (d_B d_E d_B) + (b d_E + c) d_B + b'
+        g1.C = c.U1part;
+        g1.S = pl.S1;
+        g1.out_mode = 1;
+        g1.ldc = pl.dB;
+        g1.cbs = pl.dB * pl.dE * pl.dB;
+        g1.c_split = (int64_t)pl.kc * pl.dB * pl.dE * pl.dB;
+    }
     // contraction 2: Y[k][a][b] = sum_(c, b') psi[a, c, b'] Ups[(k, b)][(c, b')],
     // split-K partials at s * kc d_A d_B + k d_A d_B + a d_B + b
     GemmDesc g2{};
@@ -278,6 +296,9 @@ int contract_chunk(Ctx &c, int k0, int kcur, hipEvent_t e1, hipEvent_t e2) {
     g2.cbs = pl.dAB;
     g2.c_split = (int64_t)pl.kc * pl.dAB;
     TNSLQ_HIP(launch_gemm(pl.prec, g1, c.st));
+    if (pl.S1 > 1)
+        TNSLQ_HIP(launch_partials_to_bricks(pl.prec, c.U1part, pl.S1, g1.c_split, u1n, pl.nB, pl.nE, c.Ups, pl.nst2,
+                                            c.st));
     if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
     TNSLQ_HIP(launch_gemm(pl.prec, g2, c.st));
     if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));

@@ -161,6 +161,29 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const AccT *__restrict_
     }
 }
 
+// The first contraction split along its reduction: the S partial sums of
+// Ups[k][(b, c)][b'] (accumulator type, at s * split + k * M dB + (b dE + c) dB
+// + b' with M = dB dE) added in FP64 and stored into the Ups brick operand,
+// row k dB + b, reduction index c dB + b'.
+template <int PREC, typename AccT>
+__global__ void __launch_bounds__(256) k_partials_to_bricks(const AccT *__restrict__ part, int S, int64_t split,
+                                                            int64_t n, int nB, int nE, void *__restrict__ ups,
+                                                            int64_t ups_nst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t dB = int64_t(1) << nB, dE = int64_t(1) << nE;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double re = 0.0, im = 0.0;
+        for (int s = 0; s < S; ++s) {
+            const AccT v = part[s * split + e];
+            re += (double)v.x;
+            im += (double)v.y;
+        }
+        const int64_t bp = e & (dB - 1), i = (e >> nB) % (dB * dE), k = (e >> nB) / (dB * dE);
+        const int64_t b = i >> nE, c = i & (dE - 1);
+        store_planes<PREC>(ups, brick_ps(PREC), brick_index(PREC, ups_nst, k * dB + b, (c << nB) + bp), re, im);
+    }
+}
+
 inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -242,6 +265,21 @@ hipError_t launch_reduce_partials(int accfp64, const void *part, int S, int64_t 
     else
         hipLaunchKernelGGL((k_reduce_partials<float2>), grid, block, 0, st, (const float2 *)part, S,
                            split_stride, dA, dB, swapped, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_partials_to_bricks(int prec, const void *part, int S, int64_t split, int64_t n, int nB, int nE,
+                                     void *ups, int64_t ups_nst, hipStream_t st) {
+    dim3 grid(grid_for(n, 256 * 4, 65535 * 4)), block(256);
+#define TNSLQ_P2B(P, A) \
+    hipLaunchKernelGGL((k_partials_to_bricks<P, A>), grid, block, 0, st, (const A *)part, S, split, n, nB, nE, ups, ups_nst)
+    switch (prec) {
+        case TNSLQ_FP64: TNSLQ_P2B(TNSLQ_FP64, double2); break;
+        case TNSLQ_FP32: TNSLQ_P2B(TNSLQ_FP32, float2); break;
+        case TNSLQ_BF16X3: TNSLQ_P2B(TNSLQ_BF16X3, float2); break;
+        default: TNSLQ_P2B(TNSLQ_BF16X6, float2); break;
+    }
+#undef TNSLQ_P2B
     return hipGetLastError();
 }
 

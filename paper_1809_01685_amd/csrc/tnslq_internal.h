@@ -36,10 +36,11 @@ struct Plan {
     int K = 1, m = 1, reorth = 0;
     int kc = 1;                      // probes per contraction chunk
     int S = 1;                       // split-K factor of the second contraction
+    int S1 = 1;                      // split-K factor of the first contraction
     int nblk = 1;                    // reduction blocks per probe vector
     int64_t nst1 = 1, nst2 = 1;      // bricks along the reduction index of contraction 1, 2
     // workspace carve-up (byte offsets)
-    size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0;
+    size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0, off_U1part = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -94,6 +95,11 @@ hipError_t launch_fit(const double *alpha, const double *beta, const double *F, 
 hipError_t launch_reduce_partials(int accfp64, const void *part, int S, int64_t split_stride,
                                   int64_t dA, int64_t dB, int K, int swapped, double2 *Y,
                                   hipStream_t st);
+// Sum of the S split partials of the first contraction (n = kc dB dE dB
+// elements, accumulator type: FP64 for TNSLQ_FP64, else FP32) into the Ups
+// brick operand.
+hipError_t launch_partials_to_bricks(int prec, const void *part, int S, int64_t split, int64_t n, int nB, int nE,
+                                     void *ups, int64_t ups_nst, hipStream_t st);
 hipError_t launch_probes_plain(uint64_t seed, uint64_t offset, int K, int64_t d, double2 *X,
                                hipStream_t st);
 hipError_t launch_load_vectors(int prec, const double2 *X, int64_t dA, int64_t dB, int K,

@@ -49,6 +49,7 @@ PARTS = [
     (12, [7], [2]),                     # d_A = d_B = 2, d_E = 1024
     (11, [0, 1, 2, 3, 4], [6, 7, 8, 9, 10]),
     (14, list(range(6)), list(range(8, 14))),
+    (13, list(range(9)), [10, 11]),     # d_B d_E = 16: the first contraction splits along a'
 ]
 
 
