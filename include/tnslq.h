@@ -57,9 +57,12 @@ enum {
 /* State storage. */
 enum { TNSLQ_C64 = 0, TNSLQ_C128 = 1 };
 
-/* Arithmetic of the two contractions (Sec. V Eq. 4).  The Lanczos recurrence,
- * reorthogonalisation, tridiagonal eigensolve and statistics are FP64 in every
- * mode.
+/* Arithmetic of the two contractions (Sec. V Eq. 4) on the matrix cores.  The
+ * Lanczos recurrence, reorthogonalisation, tridiagonal eigensolve and
+ * statistics are FP64 in every mode.  With K d_B <= 4 (d_B the smaller side)
+ * the contractions are bound by HBM, not by arithmetic, and run instead as two
+ * streaming passes over psi in its own dtype with FP64 products and sums,
+ * whatever the precision (tnslq_result.streamed).
  *   FP64    complex FP64 products and sums.
  *   FP32    complex FP32 products, FP32 sums in blocks, blocks summed in FP64.
  *   BF16X3  each FP32 operand split as hi + lo (two BF16 values); products
@@ -151,6 +154,10 @@ typedef struct {
     double lanczos_err;     /* Lanczos part of the error of logneg, in bits:
                                |E_j - E_{j-5}| (TNSLQ_STOP_DIFF, NaN for j < 6)
                                or eps_L / (T ln 2) (TNSLQ_STOP_FIT)            */
+    int streamed;           /* 1 if the contractions ran as two streaming
+                               passes over psi with FP64 arithmetic (K d_B <= 4
+                               after the role choice), 0 on the matrix cores
+                               in `precision`                                  */
 } tnslq_result;
 
 /* ------------------------------------------------------------ utilities */

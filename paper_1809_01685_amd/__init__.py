@@ -62,7 +62,7 @@ class Result(ctypes.Structure):
                 ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
                 ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
                 ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
-                ("lanczos_err", ctypes.c_double)]
+                ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int)]
 
     def as_dict(self) -> Dict[str, float]:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -130,6 +130,23 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         while (tiles1 * pl.S1 < 2048 && pl.nst1 % (2 * pl.S1) == 0 && pl.nst1 / (2 * pl.S1) >= 8) pl.S1 *= 2;
     const int64_t n = pl.dAB;
     pl.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 4096));
+    // HBM regime: with K d_B <= 4 vectors the contractions do at most 4 complex
+    // multiply-adds per element of psi and the 128 x 128 matrix-core tiles
+    // would be mostly padding; they run instead as two streaming passes over
+    // psi in its own dtype with FP64 products and sums.
+    pl.stream = (int64_t)K * pl.dB <= 4;
+    if (pl.stream) {
+        pl.kc = K;
+        pl.S1 = 1;
+        // pass 1: d_A rows, d_E d_B columns (one block per 512); pass 2: d_E d_B
+        // rows, d_A columns
+        const int64_t gx1 = (pl.dE * pl.dB + 511) / 512, gx2 = (pl.dA + 511) / 512;
+        pl.S1s = 1;
+        while (gx1 * pl.S1s < 2048 && pl.dA / (2 * pl.S1s) >= 256) pl.S1s *= 2;
+        pl.S2s = 1;
+        while (gx2 * pl.S2s < 2048 && pl.dE * pl.dB / (2 * pl.S2s) >= 64) pl.S2s *= 2;
+        pl.S = pl.S2s;
+    }
 
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -137,12 +154,23 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         o += up(bytes);
         return r;
     };
-    pl.off_Paeb = take(brick_bytes(prec, pl.dA, pl.dE * pl.dB));
-    pl.off_Pbea = take(brick_bytes(prec, pl.dB * pl.dE, pl.dA));
-    pl.off_Xt = take(brick_bytes(prec, (int64_t)K * pl.dB, pl.dA));
-    pl.off_Ups = take(brick_bytes(prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB));
-    pl.off_Ypart = take((size_t)pl.S * pl.kc * n * acc);
-    if (pl.S1 > 1) pl.off_U1part = take((size_t)pl.S1 * pl.kc * pl.dB * pl.dE * pl.dB * acc);
+    if (pl.stream) {
+        const size_t esz = dtype == TNSLQ_C128 ? 16 : 8;
+        const int64_t nv = (int64_t)K * pl.dB, ncol = pl.dE * pl.dB;
+        pl.off_P1s = take(esz * (size_t)pl.D);
+        pl.off_P2s = take(esz * (size_t)pl.D);
+        pl.off_Up = take((size_t)pl.S1s * nv * ncol * 16);
+        pl.off_U2 = take((size_t)nv * ncol * 16);
+        pl.off_Ypart = take((size_t)pl.S2s * K * n * 16);
+        if (!lanczos) pl.off_Xs = take((size_t)K * n * 16);
+    } else {
+        pl.off_Paeb = take(brick_bytes(prec, pl.dA, pl.dE * pl.dB));
+        pl.off_Pbea = take(brick_bytes(prec, pl.dB * pl.dE, pl.dA));
+        pl.off_Xt = take(brick_bytes(prec, (int64_t)K * pl.dB, pl.dA));
+        pl.off_Ups = take(brick_bytes(prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB));
+        pl.off_Ypart = take((size_t)pl.S * pl.kc * n * acc);
+        if (pl.S1 > 1) pl.off_U1part = take((size_t)pl.S1 * pl.kc * pl.dB * pl.dE * pl.dB * acc);
+    }
     if (lanczos) {
         pl.nQ = pl.reorth ? pl.m + 1 : 3;
         pl.off_Q = take((size_t)pl.nQ * K * n * 16);
@@ -176,12 +204,25 @@ PermDesc perm_for(const Plan &pl, const int *g0, int n0, const int *g1, int n1, 
     return pd;
 }
 
+// Output bit t <- input bit, for psi regrouped with group `hi` most
+// significant and group `lo` least significant.
+PermDesc perm_two(int L, const int *hi, int n_hi, const int *lo, int n_lo) {
+    PermDesc pd{};
+    pd.L = L;
+    int t = 0;
+    for (int i = n_lo - 1; i >= 0; --i) pd.map[t++] = L - 1 - lo[i];
+    for (int i = n_hi - 1; i >= 0; --i) pd.map[t++] = L - 1 - hi[i];
+    return pd;
+}
+
 struct Ctx {
     Plan pl;
     char *ws;
     hipStream_t st;
     LzDims z;
     void *Paeb, *Pbea, *Xt, *Ups, *Ypart, *U1part;
+    void *P1s, *P2s;
+    double2 *Up, *U2, *Xs;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -212,6 +253,12 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Ups = c.ws + pl.off_Ups;
     c.Ypart = c.ws + pl.off_Ypart;
     c.U1part = pl.S1 > 1 ? c.ws + pl.off_U1part : nullptr;
+    c.P1s = c.ws + pl.off_P1s;
+    c.P2s = c.ws + pl.off_P2s;
+    c.Up = (double2 *)(c.ws + pl.off_Up);
+    c.U2 = (double2 *)(c.ws + pl.off_U2);
+    c.Xs = (double2 *)(c.ws + pl.off_Xs);
+    if (pl.stream) c.Paeb = c.Pbea = c.Xt = c.Ups = nullptr;
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
     c.alpha = (double *)(c.ws + pl.off_alpha);
@@ -237,6 +284,17 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
 // clearing, their products land outside C).
 int do_layout(Ctx &c, const void *psi) {
     const Plan &pl = c.pl;
+    if (pl.stream) {
+        // (A; E, B): rows a', columns (c, b); (E, B; A): rows (c, b'), columns a
+        int eb[TNSLQ_MAX_QUBITS];
+        for (int i = 0; i < pl.nE; ++i) eb[i] = pl.qe[i];
+        for (int i = 0; i < pl.nB; ++i) eb[pl.nE + i] = pl.qb[i];
+        const PermDesc p1 = perm_two(pl.L, pl.qa, pl.nA, eb, pl.nE + pl.nB);
+        const PermDesc p2 = perm_two(pl.L, eb, pl.nE + pl.nB, pl.qa, pl.nA);
+        TNSLQ_HIP(launch_regroup(pl.dtype, psi, c.P1s, pl.dA, pl.dE * pl.dB, p1, c.st));
+        TNSLQ_HIP(launch_regroup(pl.dtype, psi, c.P2s, pl.dE * pl.dB, pl.dA, p2, c.st));
+        return TNSLQ_OK;
+    }
     PermDesc aeb = perm_for(pl, pl.qa, pl.nA, pl.qe, pl.nE, pl.qb, pl.nB);
     PermDesc bea = perm_for(pl, pl.qb, pl.nB, pl.qe, pl.nE, pl.qa, pl.nA);
     TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Paeb, pl.dA, pl.dE * pl.dB, aeb, 0, c.st));
@@ -246,6 +304,58 @@ int do_layout(Ctx &c, const void *psi) {
         TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, (int64_t)pl.K * pl.dB, pl.dA), c.st));
     if ((pl.dE * pl.dB) % epr)
         TNSLQ_HIP(hipMemsetAsync(c.Ups, 0, brick_bytes(pl.prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB), c.st));
+    return TNSLQ_OK;
+}
+
+// The streaming form of both contractions for all K probes (Sec. V Eq. 4,
+// intermediary (i)), from FP64 vectors xq[k][a dB + b]:
+//   Up[s][(k, b')][(c, b)] = sum_{a' in split s} conj psi[a', c, b] xq[k][a' dB + b']
+//   U2[(k, b)][(c, b')]    = sum_s Up[s][(k, b')][(c, b)]
+//   Ypart[s][k][a dB + b]  = sum_{(c, b') in split s} psi[a, c, b'] U2[(k, b)][(c, b')]
+int stream_contract(Ctx &c, const double2 *xq, hipEvent_t e1, hipEvent_t e2) {
+    const Plan &pl = c.pl;
+    const int64_t n = pl.dAB, ncol = pl.dE * pl.dB;
+    const int nv = pl.K * (int)pl.dB;
+    ColmacDesc g1{};
+    g1.M = c.P1s;
+    g1.R = pl.dA;
+    g1.C = ncol;
+    g1.V = xq;
+    g1.NV = nv;
+    g1.vdiv = pl.dB;
+    g1.vs1 = n;
+    g1.vs2 = 1;
+    g1.vsi = pl.dB;
+    g1.out = c.Up;
+    g1.osplit = (int64_t)nv * ncol;
+    g1.odiv = 1;
+    g1.os1 = ncol;
+    g1.os2 = 0;
+    g1.osc = 1;
+    g1.S = pl.S1s;
+    TNSLQ_HIP(launch_colmac(pl.dtype, 1, g1, c.st));
+    TNSLQ_HIP(launch_sum_transpose_ups(c.Up, pl.S1s, pl.K, pl.nB, pl.nE, c.U2, c.st));
+    if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+    ColmacDesc g2{};
+    g2.M = c.P2s;
+    g2.R = ncol;
+    g2.C = pl.dA;
+    g2.V = c.U2;
+    g2.NV = nv;
+    g2.vdiv = 1;
+    g2.vs1 = ncol;
+    g2.vs2 = 0;
+    g2.vsi = 1;
+    g2.out = (double2 *)c.Ypart;
+    g2.osplit = (int64_t)pl.K * n;
+    g2.odiv = pl.dB;
+    g2.os1 = n;
+    g2.os2 = 1;
+    g2.osc = pl.dB;
+    g2.S = pl.S2s;
+    TNSLQ_HIP(launch_colmac(pl.dtype, 0, g2, c.st));
+    if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+    c.n_launch++;
     return TNSLQ_OK;
 }
 
@@ -327,12 +437,16 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     double2 *q_cur = c.Q + slot_of(j - 1) * slot;
     double2 *q_prev = j > 1 ? c.Q + slot_of(j - 2) * slot : q_cur;
     double2 *q_next = c.Q + slot_of(j) * slot;
-    const int accfp64 = pl.prec == TNSLQ_FP64;
+    const int accfp64 = pl.prec == TNSLQ_FP64 || pl.stream;
     int rc;
     TNSLQ_HIP(hipEventRecord(se->mv0(), c.st));
     for (int k0 = 0, ch = 0; k0 < pl.K; k0 += pl.kc, ++ch) {
         const int kcur = std::min(pl.kc, pl.K - k0);
-        if ((rc = contract_chunk(c, k0, kcur, se->c1(ch), se->c2(ch)))) return rc;
+        if (pl.stream) {
+            if ((rc = stream_contract(c, q_cur, se->c1(ch), se->c2(ch)))) return rc;
+        } else if ((rc = contract_chunk(c, k0, kcur, se->c1(ch), se->c2(ch)))) {
+            return rc;
+        }
         TNSLQ_HIP(launch_passA(accfp64, c.z, c.Ypart, pl.S, (int64_t)pl.kc * n, k0, kcur, q_prev, q_cur, c.w,
                                c.alpha, c.beta, j, c.dotpart, c.st));
         TNSLQ_HIP(hipEventRecord(se->pa(ch), c.st));
@@ -341,7 +455,8 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     TNSLQ_HIP(launch_passB(c.z, c.dotpart, q_cur, c.w, c.alpha, c.beta, j, c.nrmpart, pl.reorth ? 0 : 1, c.st));
     if (pl.reorth)
         TNSLQ_HIP(launch_reorth(c.z, c.Q, j, slot, c.w, c.hpart, c.h, c.alpha, c.beta, j, c.nrmpart, c.st));
-    TNSLQ_HIP(launch_passC(pl.prec, c.z, c.nrmpart, c.w, q_next, c.Xt, c.pl.nst1, c.alpha, c.beta, j, c.st));
+    TNSLQ_HIP(launch_passC(pl.prec, c.z, c.nrmpart, c.w, q_next, pl.stream ? nullptr : c.Xt, pl.nst1, c.alpha,
+                           c.beta, j, c.st));
     TNSLQ_HIP(hipEventRecord(se->lz1(), c.st));
     return TNSLQ_OK;
 }
@@ -353,7 +468,8 @@ int slq_setup(Ctx &c, const void *psi, uint64_t seed, uint64_t offset) {
     TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)pl.K * pl.m * 8, c.st));
     TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)pl.K * (pl.m + 1) * 8, c.st));
     TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)pl.K * pl.m * 8, c.st));
-    TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, c.Xt, c.pl.nst1, c.alpha, c.beta, c.st));
+    TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, pl.stream ? nullptr : c.Xt, pl.nst1,
+                                c.alpha, c.beta, c.st));
     return TNSLQ_OK;
 }
 
@@ -537,6 +653,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     res->steps_done = r.jdone;
     res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
     res->swapped_ab = pl.swapped;
+    res->streamed = pl.stream;
     res->n_matvecs = r.jdone;
     res->n_contract_launches = c.n_launch;
     res->t_layout_ms = elapsed(r.e_start, r.e_layout);
@@ -570,6 +687,29 @@ struct SPlan {
     size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, total = 0;
 };
 
+// Column MAC over an R x C matrix with K plain vectors V[k][i] and output
+// out[s][k][c].
+ColmacDesc plain_colmac(const void *M, int64_t R, int64_t C, const double2 *V, int K, double2 *out, int S) {
+    ColmacDesc g{};
+    g.M = M;
+    g.R = R;
+    g.C = C;
+    g.V = V;
+    g.NV = K;
+    g.vdiv = 1;
+    g.vs1 = R;
+    g.vs2 = 0;
+    g.vsi = 1;
+    g.out = out;
+    g.osplit = (int64_t)K * C;
+    g.odiv = 1;
+    g.os1 = C;
+    g.os2 = 0;
+    g.osc = 1;
+    g.S = S;
+    return g;
+}
+
 int check_subsystem(int L, const int *s, int n_s) {
     if (L < 1 || L > TNSLQ_MAX_QUBITS) return fail(TNSLQ_E_PARTITION, "n_qubits %d outside [1, %d]", L, TNSLQ_MAX_QUBITS);
     if (n_s < 0 || n_s > L) return fail(TNSLQ_E_PARTITION, "subsystem size %d outside [0, %d]", n_s, L);
@@ -590,17 +730,6 @@ int check_spectral_options(const tnslq_options *opt, int fn) {
     if (opt->precision != TNSLQ_FP64) return fail(TNSLQ_E_ARG, "spectral sums compute in FP64 only");
     if (opt->stop_tol != 0.0) return fail(TNSLQ_E_ARG, "spectral sums run a fixed number of steps (stop_tol 0)");
     return TNSLQ_OK;
-}
-
-// Output bit t <- input bit, for psi regrouped with group `hi` most
-// significant and group `lo` least significant.
-PermDesc perm_two(int L, const int *hi, int n_hi, const int *lo, int n_lo) {
-    PermDesc pd{};
-    pd.L = L;
-    int t = 0;
-    for (int i = n_lo - 1; i >= 0; --i) pd.map[t++] = L - 1 - lo[i];
-    for (int i = n_hi - 1; i >= 0; --i) pd.map[t++] = L - 1 - hi[i];
-    return pd;
 }
 
 int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt, int fn, SPlan &sp) {
@@ -731,9 +860,9 @@ int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uin
         double2 *q_next = Q + slot_of(j) * slot;
         TNSLQ_HIP(hipEventRecord(mv0[j], st));
         // Z = Psi^dagger q over P1 (d x d_R); Y = Psi Z over P2 = Psi^T (d_R x d)
-        TNSLQ_HIP(launch_colmac(sp.dtype, 1, P1, sp.d, sp.dR, q_cur, sp.K, Zp, sp.S1, st));
+        TNSLQ_HIP(launch_colmac(sp.dtype, 1, plain_colmac(P1, sp.d, sp.dR, q_cur, sp.K, Zp, sp.S1), st));
         TNSLQ_HIP(launch_sum_splits(Zp, sp.S1, (int64_t)sp.K * sp.dR, Z, st));
-        TNSLQ_HIP(launch_colmac(sp.dtype, 0, P2, sp.dR, sp.d, Z, sp.K, Yp, sp.S2, st));
+        TNSLQ_HIP(launch_colmac(sp.dtype, 0, plain_colmac(P2, sp.dR, sp.d, Z, sp.K, Yp, sp.S2), st));
         TNSLQ_HIP(hipEventRecord(mv1[j], st));
         TNSLQ_HIP(launch_passA(1, z, Yp, sp.S2, slot, 0, sp.K, q_prev, q_cur, w, alpha, beta, j, dotpart, st));
         TNSLQ_HIP(launch_passB(z, dotpart, q_cur, w, alpha, beta, j, nrmpart, sp.reorth ? 0 : 1, st));
@@ -886,6 +1015,13 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
     bind(c, ws_dev, (hipStream_t)stream);
     const Plan &pl = c.pl;
     if ((rc = do_layout(c, psi_dev))) return rc;
+    if (pl.stream) {
+        TNSLQ_HIP(launch_load_vectors_plain((const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xs, c.st));
+        if ((rc = stream_contract(c, c.Xs, nullptr, nullptr))) return rc;
+        TNSLQ_HIP(launch_reduce_partials(1, c.Ypart, pl.S2s, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
+                                         (double2 *)Y_dev, c.st));
+        return TNSLQ_OK;
+    }
     TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.pl.nst1, c.st));
     for (int k0 = 0; k0 < pl.K; k0 += pl.kc) {
         const int kcur = std::min(pl.kc, pl.K - k0);

@@ -37,7 +37,6 @@ __device__ inline double2 load_c(const void *p, int64_t i) {
 constexpr int CM_THREADS = 256;   // threads per block
 constexpr int CM_CPT = 2;         // adjacent columns per thread
 constexpr int CM_COLS = CM_THREADS * CM_CPT;   // columns per block = panel width
-constexpr int CM_CH = 64;         // rows staged per LDS chunk
 
 // Panel layout of an R x C matrix: column panels of w = min(C, CM_COLS)
 // columns, each stored row after row, so that the rows of one block's panel
@@ -65,38 +64,46 @@ __global__ void __launch_bounds__(256) k_regroup(const void *__restrict__ psi, v
     }
 }
 
-// The two adjacent elements (i, c), (i, c + 1) at panel offset e of M.
+// The two adjacent elements (i, c), (i, c + 1) at panel offset e of M, read
+// as a stream (nontemporal: psi is not re-read within a pass).
 template <int DTYPE>
 __device__ inline void load_pair(const void *M, int64_t e, double2 &a, double2 &b) {
+    typedef __attribute__((ext_vector_type(4))) float f4;
+    typedef __attribute__((ext_vector_type(2))) double d2;
     if constexpr (DTYPE == TNSLQ_C128) {
-        a = ((const double2 *)M)[e];
-        b = ((const double2 *)M)[e + 1];
+        const d2 x = __builtin_nontemporal_load((const d2 *)M + e);
+        const d2 y = __builtin_nontemporal_load((const d2 *)M + e + 1);
+        a = make_double2(x.x, x.y);
+        b = make_double2(y.x, y.y);
     } else {
-        const float4 f = *(const float4 *)((const float2 *)M + e);
+        const f4 f = __builtin_nontemporal_load((const f4 *)((const float2 *)M + e));
         a = make_double2(f.x, f.y);
         b = make_double2(f.z, f.w);
     }
 }
 
-// out[s][k][c] = sum over rows i of split s of op(M[i][c]) V[k][i] for the KG
-// vectors k0 = blockIdx.z KG ..; op = conj if CONJ; M in panel layout, block x
-// owning panel x, thread t its columns 2t, 2t + 1.  The vector entries of a
-// row are staged in LDS and broadcast; each serves two columns.
-template <int DTYPE, bool CONJ, int KG>
-__global__ void __launch_bounds__(CM_THREADS) k_colmac(const void *__restrict__ M, int64_t R, int64_t C,
-                                                       const double2 *__restrict__ V, int K,
-                                                       double2 *__restrict__ out, int64_t out_split_stride,
-                                                       int64_t rows_per_split) {
+// out(s, v, c) = sum over rows i of split s of op(M[i][c]) V(v, i) for the KG
+// vectors v = blockIdx.z KG ..; op = conj if CONJ; M in panel layout.  A block
+// covers one panel: its threads take column pairs (2 cp, 2 cp + 1), and when
+// the panel is narrower than 512 columns the threads left over walk
+// interleaved rows (phase ph of nph) and their sums meet in LDS at the end.
+// The vector entries of a chunk of rows are staged in LDS and broadcast, each
+// read serving two columns.
+template <int DTYPE, bool CONJ, int KG, int CM_CH>
+__global__ void __launch_bounds__(CM_THREADS) k_colmac(ColmacDesc g) {
     constexpr int U = 8;   // rows whose loads are issued together
-    __shared__ double2 vs[KG][CM_CH];
+    __shared__ double2 vs[KG][CM_CH];   // CM_CH rows of vector entries per chunk
+    __shared__ double2 red[CM_THREADS][CM_CPT];
     const int t = threadIdx.x;
-    const int64_t c = ((int64_t)blockIdx.x * CM_THREADS + t) * CM_CPT;
+    const int64_t w = g.C < CM_COLS ? g.C : CM_COLS;
+    const int cpairs = (int)(w / CM_CPT), nph = CM_THREADS / cpairs;
+    const int cp = t % cpairs, ph = t / cpairs;
+    const int64_t c = (int64_t)blockIdx.x * CM_COLS + CM_CPT * cp;
     const int s = blockIdx.y;
-    const int kg0 = blockIdx.z * KG;
-    const int kn = K - kg0 < KG ? K - kg0 : KG;
-    const int64_t i0 = (int64_t)s * rows_per_split;
-    const int64_t i1 = i0 + rows_per_split < R ? i0 + rows_per_split : R;
-    const int64_t w = C < CM_COLS ? C : CM_COLS;
+    const int v0 = blockIdx.z * KG;
+    const int kn = g.NV - v0 < KG ? g.NV - v0 : KG;
+    const int64_t i0 = (int64_t)s * g.rows_per_split;
+    const int64_t i1 = i0 + g.rows_per_split < g.R ? i0 + g.rows_per_split : g.R;
     double ar[CM_CPT][KG], ai[CM_CPT][KG];
 #pragma unroll
     for (int j = 0; j < CM_CPT; ++j)
@@ -107,18 +114,24 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(const void *__restrict__ 
         __syncthreads();
         for (int e = t; e < KG * CM_CH; e += CM_THREADS) {
             const int k = e / CM_CH, ii = e % CM_CH;
-            vs[k][ii] = (k < kn && ii < nrow) ? V[(int64_t)(kg0 + k) * R + ib + ii] : make_double2(0.0, 0.0);
+            double2 v = make_double2(0.0, 0.0);
+            if (k < kn && ii < nrow) {
+                const int64_t vv = v0 + k;
+                v = g.V[(vv / g.vdiv) * g.vs1 + (vv % g.vdiv) * g.vs2 + (ib + ii) * g.vsi];
+            }
+            vs[k][ii] = v;
         }
         __syncthreads();
-        if (c < C) {
-            const int64_t base = panel_index(ib, c, R, C);
-            for (int u0 = 0; u0 < nrow; u0 += U) {
+        if (c < g.C) {
+            const int64_t base = panel_index(ib, c, g.R, g.C);
+            for (int u0 = ph; u0 < nrow; u0 += U * nph) {
                 // the U row loads of a batch are issued before any is used
                 double2 ma[U], mb[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (u0 + u < nrow) {
-                        load_pair<DTYPE>(M, base + (int64_t)(u0 + u) * w, ma[u], mb[u]);
+                    const int ii = u0 + u * nph;
+                    if (ii < nrow) {
+                        load_pair<DTYPE>(g.M, base + (int64_t)ii * w, ma[u], mb[u]);
                     } else {
                         ma[u] = make_double2(0.0, 0.0);
                         mb[u] = ma[u];
@@ -126,11 +139,13 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(const void *__restrict__ 
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
+                    const int ii = u0 + u * nph;
                     const double ax = ma[u].x, ay = CONJ ? -ma[u].y : ma[u].y;
                     const double bx = mb[u].x, by = CONJ ? -mb[u].y : mb[u].y;
 #pragma unroll
                     for (int k = 0; k < KG; ++k) {
-                        const double2 v = vs[k][(u0 + u) & (CM_CH - 1)];
+                        // rows past the chunk load zeros; any staged entry will do
+                        const double2 v = vs[k][ii < CM_CH ? ii : 0];
                         ar[0][k] = fma(ax, v.x, fma(-ay, v.y, ar[0][k]));
                         ai[0][k] = fma(ax, v.y, fma(ay, v.x, ai[0][k]));
                         ar[1][k] = fma(bx, v.x, fma(-by, v.y, ar[1][k]));
@@ -140,14 +155,31 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(const void *__restrict__ 
             }
         }
     }
-    if (c < C) {
+    // phases of one column pair add up (one vector at a time through LDS)
 #pragma unroll
-        for (int k = 0; k < KG; ++k)
-            if (k < kn) {
-                double2 *o = out + s * out_split_stride + (int64_t)(kg0 + k) * C + c;
-                o[0] = make_double2(ar[0][k], ai[0][k]);
-                o[1] = make_double2(ar[1][k], ai[1][k]);
+    for (int k = 0; k < KG; ++k) {
+        double2 r0 = make_double2(ar[0][k], ai[0][k]), r1 = make_double2(ar[1][k], ai[1][k]);
+        if (nph > 1) {
+            __syncthreads();
+            red[t][0] = r0;
+            red[t][1] = r1;
+            __syncthreads();
+            if (ph == 0) {
+                for (int p = 1; p < nph; ++p) {
+                    const double2 x0 = red[p * cpairs + cp][0], x1 = red[p * cpairs + cp][1];
+                    r0.x += x0.x;
+                    r0.y += x0.y;
+                    r1.x += x1.x;
+                    r1.y += x1.y;
+                }
             }
+        }
+        if (ph == 0 && c < g.C && k < kn) {
+            const int64_t vv = v0 + k;
+            double2 *o = g.out + s * g.osplit + (vv / g.odiv) * g.os1 + (vv % g.odiv) * g.os2;
+            o[c * g.osc] = r0;
+            o[(c + 1) * g.osc] = r1;
+        }
     }
 }
 
@@ -166,6 +198,28 @@ __global__ void __launch_bounds__(256) k_sum_splits(const double2 *__restrict__ 
     }
 }
 
+// The streaming form of the partial-transpose matvec: the first pass leaves
+// Up[s][(k, b')][(c, b)] (split partials over a'); the second pass wants
+// U2[(k, b)][(c, b')] as its vectors over the reduction index (c, b').
+__global__ void __launch_bounds__(256) k_sum_transpose_ups(const double2 *__restrict__ Up, int S, int64_t n, int nB,
+                                                           int nE, double2 *__restrict__ U2) {
+    const int64_t dB = int64_t(1) << nB, dE = int64_t(1) << nE;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        // e = ((k dB + b) dE + c) dB + b'
+        const int64_t bp = e & (dB - 1), c = (e >> nB) & (dE - 1), b = (e >> (nB + nE)) & (dB - 1);
+        const int64_t k = e >> (2 * nB + nE);
+        const int64_t src = ((k << nB) + bp) * (dE * dB) + (c << nB) + b;
+        double x = 0.0, y = 0.0;
+        for (int p = 0; p < S; ++p) {
+            const double2 v = Up[p * n + src];
+            x += v.x;
+            y += v.y;
+        }
+        U2[e] = make_double2(x, y);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int64_t C, const PermDesc &pd,
@@ -180,11 +234,9 @@ hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int6
     return hipGetLastError();
 }
 
-template <int KG>
-void colmac_kg(int dtype, int conj, dim3 grid, hipStream_t st, const void *M, int64_t R, int64_t C,
-               const double2 *V, int K, double2 *out, int64_t ostride, int64_t rps) {
-#define TNSLQ_CM(T, CJ) \
-    hipLaunchKernelGGL((k_colmac<T, CJ, KG>), grid, dim3(CM_THREADS), 0, st, M, R, C, V, K, out, ostride, rps)
+template <int KG, int CH>
+void colmac_kg(int dtype, int conj, dim3 grid, hipStream_t st, const ColmacDesc &g) {
+#define TNSLQ_CM(T, CJ) hipLaunchKernelGGL((k_colmac<T, CJ, KG, CH>), grid, dim3(CM_THREADS), 0, st, g)
     if (dtype == TNSLQ_C128) {
         if (conj) TNSLQ_CM(TNSLQ_C128, true);
         else TNSLQ_CM(TNSLQ_C128, false);
@@ -195,22 +247,25 @@ void colmac_kg(int dtype, int conj, dim3 grid, hipStream_t st, const void *M, in
 #undef TNSLQ_CM
 }
 
-hipError_t launch_colmac(int dtype, int conj, const void *M, int64_t R, int64_t C, const double2 *V, int K,
-                         double2 *out, int S, hipStream_t st) {
-    if (R < 1 || C < 1 || K < 1 || S < 1 || R % S != 0) return hipErrorInvalidValue;
-    // vectors per pass over M: the smallest of 1, 2, 4, 8 covering K (8 and
-    // several passes beyond: 16 would leave one wave per SIMD)
-    const int kg = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : 8;
-    if (C % CM_CPT != 0) return hipErrorInvalidValue;
-    const int64_t gx = (C + CM_COLS - 1) / CM_COLS, gz = (K + kg - 1) / kg;
-    if (gx > 0x7fffffff || S > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)gx, (unsigned)S, (unsigned)gz);
-    const int64_t rps = R / S, ostride = (int64_t)K * C;
+hipError_t launch_colmac(int dtype, int conj, ColmacDesc g, hipStream_t st) {
+    if (g.R < 1 || g.C < CM_CPT || g.NV < 1 || g.S < 1 || g.R % g.S != 0 || g.C % CM_CPT != 0) return hipErrorInvalidValue;
+    if (g.C < CM_COLS && CM_COLS % g.C != 0) return hipErrorInvalidValue;   // narrow panels: C divides 512
+    if (g.vdiv < 1 || g.odiv < 1) return hipErrorInvalidValue;
+    g.rows_per_split = g.R / g.S;
+    // vectors per pass over M: the smallest of 1, 2, 4, 8 covering NV (8 and
+    // several passes beyond)
+    const int kg = g.NV <= 1 ? 1 : g.NV <= 2 ? 2 : g.NV <= 4 ? 4 : 8;
+    const int64_t gx = (g.C + CM_COLS - 1) / CM_COLS, gz = (g.NV + kg - 1) / kg;
+    if (gx > 0x7fffffff || g.S > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)gx, (unsigned)g.S, (unsigned)gz);
+    // rows staged per chunk: 64 for full panels, 256 when narrow panels split
+    // the block into row phases
+    const bool wide = g.C >= CM_COLS;
     switch (kg) {
-        case 1: colmac_kg<1>(dtype, conj, grid, st, M, R, C, V, K, out, ostride, rps); break;
-        case 2: colmac_kg<2>(dtype, conj, grid, st, M, R, C, V, K, out, ostride, rps); break;
-        case 4: colmac_kg<4>(dtype, conj, grid, st, M, R, C, V, K, out, ostride, rps); break;
-        default: colmac_kg<8>(dtype, conj, grid, st, M, R, C, V, K, out, ostride, rps); break;
+        case 1: wide ? colmac_kg<1, 64>(dtype, conj, grid, st, g) : colmac_kg<1, 256>(dtype, conj, grid, st, g); break;
+        case 2: wide ? colmac_kg<2, 64>(dtype, conj, grid, st, g) : colmac_kg<2, 256>(dtype, conj, grid, st, g); break;
+        case 4: wide ? colmac_kg<4, 64>(dtype, conj, grid, st, g) : colmac_kg<4, 256>(dtype, conj, grid, st, g); break;
+        default: wide ? colmac_kg<8, 64>(dtype, conj, grid, st, g) : colmac_kg<8, 256>(dtype, conj, grid, st, g); break;
     }
     return hipGetLastError();
 }
@@ -220,6 +275,15 @@ hipError_t launch_sum_splits(const double2 *part, int S, int64_t n, double2 *Z, 
     if (g > 65535 * 4) g = 65535 * 4;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)g), dim3(256), 0, st, part, S, n, Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_transpose_ups(const double2 *Up, int S, int K, int nB, int nE, double2 *U2, hipStream_t st) {
+    const int64_t n = (int64_t)K << (2 * nB + nE);
+    int64_t g = (n + 255) / 256;
+    if (g > 65535 * 4) g = 65535 * 4;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_sum_transpose_ups, dim3((unsigned)g), dim3(256), 0, st, Up, S, n, nB, nE, U2);
     return hipGetLastError();
 }
 

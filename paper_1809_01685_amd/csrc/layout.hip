@@ -133,6 +133,27 @@ __global__ void __launch_bounds__(256) k_load_vectors(const double2 *__restrict_
     }
 }
 
+// Caller vectors X[k][a_o][b_o] -> FP64 vectors in layout order, Xs[k][a dB + b]
+// (conjugated and index-swapped when the roles are swapped), for the
+// streaming form of the contractions.
+__global__ void __launch_bounds__(256) k_load_vectors_plain(const double2 *__restrict__ X, int64_t dA, int64_t dB,
+                                                            int swapped, double2 *__restrict__ Xs) {
+    const int k = blockIdx.y;
+    const int64_t n = dA * dB;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int64_t a = e / dB, b = e % dB;
+        double2 v;
+        if (swapped) {
+            v = X[(int64_t)k * n + b * dA + a];
+            v.y = -v.y;
+        } else {
+            v = X[(int64_t)k * n + e];
+        }
+        Xs[(int64_t)k * n + e] = v;
+    }
+}
+
 // Y = sum over split-K partials, written in the caller's index order.
 template <typename AccT>
 __global__ void __launch_bounds__(256) k_reduce_partials(const AccT *__restrict__ part, int S,
@@ -280,6 +301,13 @@ hipError_t launch_partials_to_bricks(int prec, const void *part, int S, int64_t 
         default: TNSLQ_P2B(TNSLQ_BF16X6, float2); break;
     }
 #undef TNSLQ_P2B
+    return hipGetLastError();
+}
+
+hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, int K, int swapped, double2 *Xs,
+                                     hipStream_t st) {
+    dim3 grid(grid_for(dA * dB, 256 * 8, 4096), K), block(256);
+    hipLaunchKernelGGL(k_load_vectors_plain, grid, block, 0, st, X, dA, dB, swapped, Xs);
     return hipGetLastError();
 }
 

@@ -37,10 +37,13 @@ struct Plan {
     int kc = 1;                      // probes per contraction chunk
     int S = 1;                       // split-K factor of the second contraction
     int S1 = 1;                      // split-K factor of the first contraction
+    int stream = 0;                  // contractions as two streaming passes over psi (K d_B <= 4)
+    int S1s = 1, S2s = 1;            // row splits of the two streaming passes
     int nblk = 1;                    // reduction blocks per probe vector
     int64_t nst1 = 1, nst2 = 1;      // bricks along the reduction index of contraction 1, 2
     // workspace carve-up (byte offsets)
     size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0, off_U1part = 0;
+    size_t off_P1s = 0, off_P2s = 0, off_Up = 0, off_U2 = 0, off_Xs = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -110,15 +113,34 @@ hipError_t launch_features(const double *alpha, const double *beta, int K, int m
 
 // ------------------------------------------------------------ entropy
 // psi regrouped as an R x C matrix in column panels 512 wide (same dtype,
-// interleaved complex); the column MAC out[s][k][c] = sum_{i in split s}
-// op(M[i][c]) V[k][i] over such a matrix M and K x R vectors V, out S x K x C,
-// rows split evenly (R % S == 0), C even; and the sum of S partial arrays of n
-// elements.
+// interleaved complex), and the sum of S partial arrays of n elements.
 hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int64_t C, const PermDesc &pd,
                           hipStream_t st);
-hipError_t launch_colmac(int dtype, int conj, const void *M, int64_t R, int64_t C, const double2 *V, int K,
-                         double2 *out, int S, hipStream_t st);
+// The column MAC: out(s, v, c) = sum_{i in split s} op(M[i][c]) V(v, i) over
+// an R x C panel-layout matrix M (C even, and dividing 512 when below it) for
+// vectors v < NV, with
+//   V(v, i)      at V[(v / vdiv) vs1 + (v % vdiv) vs2 + i vsi],
+//   out(s, v, c) at out[s osplit + (v / odiv) os1 + (v % odiv) os2 + c osc],
+// the R rows cut into S equal splits.
+struct ColmacDesc {
+    const void *M;
+    int64_t R, C;
+    const double2 *V;
+    int NV;
+    int64_t vdiv, vs1, vs2, vsi;
+    double2 *out;
+    int64_t osplit, odiv, os1, os2, osc;
+    int S;
+    int64_t rows_per_split;   // set by the launcher
+};
+hipError_t launch_colmac(int dtype, int conj, ColmacDesc g, hipStream_t st);
 hipError_t launch_sum_splits(const double2 *part, int S, int64_t n, double2 *Z, hipStream_t st);
+// U2[(k, b)][(c, b')] = sum_s Up[s][(k, b')][(c, b)] for the streaming
+// partial-transpose matvec (K probes, dB = 2^nB, dE = 2^nE).
+hipError_t launch_sum_transpose_ups(const double2 *Up, int S, int K, int nB, int nE, double2 *U2, hipStream_t st);
+// Caller vectors into FP64 layout order Xs[k][a dB + b].
+hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, int K, int swapped, double2 *Xs,
+                                     hipStream_t st);
 
 // ------------------------------------------------------------ MLP
 size_t mlp_ws_bytes(int batch);

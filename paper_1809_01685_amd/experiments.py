@@ -18,6 +18,12 @@
         per Lanczos step and the HBM throughput of the two streaming passes
         over psi that apply the reduced density matrix.
 
+    python -m paper_1809_01685_amd.experiments hbm_sweep
+        The HBM-bound end of the negativity: the 30-qubit Haar state with
+        A = 4-16 and |B| = 1, 2, 3 qubits (B = 17, 18, 19 ...), K = 1, 2, 4
+        probes, 10 Lanczos steps; time per block matvec against the minimum
+        bytes (psi once, the probe block in and out) at 8 TB/s.
+
 All print one JSON object.  All arithmetic runs in libtnslq.
 """
 from __future__ import annotations
@@ -150,6 +156,37 @@ def run_entropy30(n_steps=20, seed=0):
     return {"workload": "30-qubit Haar state c64, S = first n qubits", "rows": rows}
 
 
+def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3"):
+    import torch
+    import tnslq_inputs as ti
+    dev = torch.device("cuda:0")
+    L = 30
+    psi = ti.haar_state_torch(L, seed, dev, torch.complex64)
+    D = 1 << L
+    rows = []
+    a = list(range(4, 17))
+    for nb in (1, 2, 3):
+        b = list(range(17, 17 + nb))
+        for K in (1, 2, 4):
+            tnslq_logneg(psi, L, a, b, K, 2, precision=precision, seed=seed, want_arrays=False)   # warm-up
+            r = tnslq_logneg(psi, L, a, b, K, n_steps, precision=precision, seed=seed, want_arrays=False)
+            d_ab = 1 << (len(a) + nb)
+            ms = r["t_matvec_ms"] / r["steps_done"]
+            min_bytes = 8 * D + 2 * 8 * d_ab * K
+            rows.append({"b_qubits": nb, "probes": K, "streamed": bool(r["streamed"]), "logneg": r["logneg"],
+                         "logneg_se": r["logneg_se"], "matvec_ms": ms, "min_bytes": min_bytes,
+                         "algorithmic_GBps": min_bytes / (ms * 1e-3) / 1e9,
+                         "frac_of_8TBps": min_bytes / (ms * 1e-3) / 8e12,
+                         "two_pass_frac_of_8TBps": 2 * 8 * D / (ms * 1e-3) / 8e12 if r["streamed"] else None})
+            print(f"[hbm_sweep] |B| = {nb}, K = {K}: {'stream' if r['streamed'] else 'mfma'} {ms:.3f} ms per matvec, "
+                  f"{rows[-1]['algorithmic_GBps']:.0f} GB/s of minimum bytes, E = {r['logneg']:.4f}",
+                  file=sys.stderr, flush=True)
+    del psi
+    torch.cuda.empty_cache()
+    return {"workload": "30-qubit Haar state c64, A = 4-16, B = 17.. (1-3 qubits)", "precision": precision,
+            "steps": n_steps, "rows": rows}
+
+
 def _parse_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -164,11 +201,14 @@ def main(argv=None):
     sc.add_argument("--depths", default="1-12")
     sc.add_argument("--precision", default="bf16x3")
     sub.add_parser("heldout26")
+    sub.add_parser("hbm_sweep")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
+    elif args.cmd == "hbm_sweep":
+        out = run_hbm_sweep()
     elif args.cmd == "entropy30":
         out = run_entropy30(n_steps=args.steps)
     else:
