@@ -322,13 +322,13 @@ int stream_contract(Ctx &c, const double2 *xq, hipEvent_t e1, hipEvent_t e2) {
     g1.C = ncol;
     g1.V = xq;
     g1.NV = nv;
-    g1.vdiv = pl.dB;
+    g1.vsh = pl.nB;
     g1.vs1 = n;
     g1.vs2 = 1;
     g1.vsi = pl.dB;
     g1.out = c.Up;
     g1.osplit = (int64_t)nv * ncol;
-    g1.odiv = 1;
+    g1.osh = 0;
     g1.os1 = ncol;
     g1.os2 = 0;
     g1.osc = 1;
@@ -342,13 +342,13 @@ int stream_contract(Ctx &c, const double2 *xq, hipEvent_t e1, hipEvent_t e2) {
     g2.C = pl.dA;
     g2.V = c.U2;
     g2.NV = nv;
-    g2.vdiv = 1;
+    g2.vsh = 0;
     g2.vs1 = ncol;
     g2.vs2 = 0;
     g2.vsi = 1;
     g2.out = (double2 *)c.Ypart;
     g2.osplit = (int64_t)pl.K * n;
-    g2.odiv = pl.dB;
+    g2.osh = pl.nB;
     g2.os1 = n;
     g2.os2 = 1;
     g2.osc = pl.dB;
@@ -696,13 +696,13 @@ ColmacDesc plain_colmac(const void *M, int64_t R, int64_t C, const double2 *V, i
     g.C = C;
     g.V = V;
     g.NV = K;
-    g.vdiv = 1;
+    g.vsh = 0;
     g.vs1 = R;
     g.vs2 = 0;
     g.vsi = 1;
     g.out = out;
     g.osplit = (int64_t)K * C;
-    g.odiv = 1;
+    g.osh = 0;
     g.os1 = C;
     g.os2 = 0;
     g.osc = 1;

@@ -89,15 +89,17 @@ __device__ inline void load_pair(const void *M, int64_t e, double2 &a, double2 &
 // interleaved rows (phase ph of nph) and their sums meet in LDS at the end.
 // The vector entries of a chunk of rows are staged in LDS and broadcast, each
 // read serving two columns.
-template <int DTYPE, bool CONJ, int KG, int CM_CH>
+template <int DTYPE, bool CONJ, int KG, bool WIDE>
 __global__ void __launch_bounds__(CM_THREADS) k_colmac(ColmacDesc g) {
-    constexpr int U = 8;   // rows whose loads are issued together
-    __shared__ double2 vs[KG][CM_CH];   // CM_CH rows of vector entries per chunk
-    __shared__ double2 red[CM_THREADS][CM_CPT];
+    constexpr int U = 8;                      // rows whose loads are issued together
+    constexpr int CM_CH = WIDE ? 64 : 256;    // rows of vector entries staged per chunk
+    __shared__ double2 vs[KG][CM_CH];
+    __shared__ double2 red[WIDE ? 1 : CM_THREADS][CM_CPT];
     const int t = threadIdx.x;
-    const int64_t w = g.C < CM_COLS ? g.C : CM_COLS;
-    const int cpairs = (int)(w / CM_CPT), nph = CM_THREADS / cpairs;
-    const int cp = t % cpairs, ph = t / cpairs;
+    // WIDE: the panel is 512 columns wide, one row phase
+    const int64_t w = WIDE ? CM_COLS : g.C;
+    const int cpairs = WIDE ? CM_THREADS : (int)(w / CM_CPT), nph = WIDE ? 1 : CM_THREADS / cpairs;
+    const int cp = WIDE ? t : t % cpairs, ph = WIDE ? 0 : t / cpairs;
     const int64_t c = (int64_t)blockIdx.x * CM_COLS + CM_CPT * cp;
     const int s = blockIdx.y;
     const int v0 = blockIdx.z * KG;
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(ColmacDesc g) {
             double2 v = make_double2(0.0, 0.0);
             if (k < kn && ii < nrow) {
                 const int64_t vv = v0 + k;
-                v = g.V[(vv / g.vdiv) * g.vs1 + (vv % g.vdiv) * g.vs2 + (ib + ii) * g.vsi];
+                v = g.V[(vv >> g.vsh) * g.vs1 + (vv & ((1 << g.vsh) - 1)) * g.vs2 + (ib + ii) * g.vsi];
             }
             vs[k][ii] = v;
         }
@@ -159,7 +161,7 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(ColmacDesc g) {
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
         double2 r0 = make_double2(ar[0][k], ai[0][k]), r1 = make_double2(ar[1][k], ai[1][k]);
-        if (nph > 1) {
+        if (!WIDE && nph > 1) {
             __syncthreads();
             red[t][0] = r0;
             red[t][1] = r1;
@@ -176,11 +178,75 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac(ColmacDesc g) {
         }
         if (ph == 0 && c < g.C && k < kn) {
             const int64_t vv = v0 + k;
-            double2 *o = g.out + s * g.osplit + (vv / g.odiv) * g.os1 + (vv % g.odiv) * g.os2;
+            double2 *o = g.out + s * g.osplit + (vv >> g.osh) * g.os1 + (vv & ((1 << g.osh) - 1)) * g.os2;
             o[c * g.osc] = r0;
             o[(c + 1) * g.osc] = r1;
         }
     }
+}
+
+// The plain case of the column MAC: full 512-column panels, vectors
+// V[v][i] = V[v R + i] and output out[s][v][c] (the entropy's two passes).
+// The same sums with simpler addressing, which keeps the kernel at 4 waves
+// per SIMD with 8 vectors.
+template <int DTYPE, bool CONJ, int KG>
+__global__ void __launch_bounds__(CM_THREADS) k_colmac_plain(ColmacDesc g) {
+    constexpr int U = 8, CH = 64;
+    __shared__ double2 vs[KG][CH];
+    const int t = threadIdx.x;
+    const int64_t c = ((int64_t)blockIdx.x * CM_THREADS + t) * CM_CPT;
+    const int s = blockIdx.y;
+    const int v0 = blockIdx.z * KG;
+    const int kn = g.NV - v0 < KG ? g.NV - v0 : KG;
+    const int64_t i0 = (int64_t)s * g.rows_per_split;
+    const int64_t i1 = i0 + g.rows_per_split < g.R ? i0 + g.rows_per_split : g.R;
+    double ar[CM_CPT][KG], ai[CM_CPT][KG];
+#pragma unroll
+    for (int j = 0; j < CM_CPT; ++j)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) ar[j][k] = ai[j][k] = 0.0;
+    for (int64_t ib = i0; ib < i1; ib += CH) {
+        const int nrow = (int)(i1 - ib < CH ? i1 - ib : CH);
+        __syncthreads();
+        for (int e = t; e < KG * CH; e += CM_THREADS) {
+            const int k = e / CH, ii = e % CH;
+            vs[k][ii] = (k < kn && ii < nrow) ? g.V[(int64_t)(v0 + k) * g.R + ib + ii] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        const int64_t base = panel_index(ib, c, g.R, g.C);
+        for (int u0 = 0; u0 < nrow; u0 += U) {
+            double2 ma[U], mb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (u0 + u < nrow) {
+                    load_pair<DTYPE>(g.M, base + (int64_t)(u0 + u) * CM_COLS, ma[u], mb[u]);
+                } else {
+                    ma[u] = make_double2(0.0, 0.0);
+                    mb[u] = ma[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double ax = ma[u].x, ay = CONJ ? -ma[u].y : ma[u].y;
+                const double bx = mb[u].x, by = CONJ ? -mb[u].y : mb[u].y;
+#pragma unroll
+                for (int k = 0; k < KG; ++k) {
+                    const double2 v = vs[k][(u0 + u) & (CH - 1)];
+                    ar[0][k] = fma(ax, v.x, fma(-ay, v.y, ar[0][k]));
+                    ai[0][k] = fma(ax, v.y, fma(ay, v.x, ai[0][k]));
+                    ar[1][k] = fma(bx, v.x, fma(-by, v.y, ar[1][k]));
+                    ai[1][k] = fma(bx, v.y, fma(by, v.x, ai[1][k]));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KG; ++k)
+        if (k < kn) {
+            double2 *o = g.out + s * g.osplit + (int64_t)(v0 + k) * g.C + c;
+            o[0] = make_double2(ar[0][k], ai[0][k]);
+            o[1] = make_double2(ar[1][k], ai[1][k]);
+        }
 }
 
 // Z[k][i] = sum_s Zp[s][k][i], n = K x n_i elements.
@@ -234,9 +300,16 @@ hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int6
     return hipGetLastError();
 }
 
-template <int KG, int CH>
+template <int KG, bool WIDE>
 void colmac_kg(int dtype, int conj, dim3 grid, hipStream_t st, const ColmacDesc &g) {
-#define TNSLQ_CM(T, CJ) hipLaunchKernelGGL((k_colmac<T, CJ, KG, CH>), grid, dim3(CM_THREADS), 0, st, g)
+    const bool plain = WIDE && g.vsh == 0 && g.vs1 == g.R && g.vsi == 1 && g.osh == 0 && g.os1 == g.C && g.osc == 1;
+#define TNSLQ_CM(T, CJ)                                                                                   \
+    do {                                                                                                  \
+        if (plain)                                                                                        \
+            hipLaunchKernelGGL((k_colmac_plain<T, CJ, KG>), grid, dim3(CM_THREADS), 0, st, g);           \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_colmac<T, CJ, KG, WIDE>), grid, dim3(CM_THREADS), 0, st, g);           \
+    } while (0)
     if (dtype == TNSLQ_C128) {
         if (conj) TNSLQ_CM(TNSLQ_C128, true);
         else TNSLQ_CM(TNSLQ_C128, false);
@@ -250,7 +323,7 @@ void colmac_kg(int dtype, int conj, dim3 grid, hipStream_t st, const ColmacDesc 
 hipError_t launch_colmac(int dtype, int conj, ColmacDesc g, hipStream_t st) {
     if (g.R < 1 || g.C < CM_CPT || g.NV < 1 || g.S < 1 || g.R % g.S != 0 || g.C % CM_CPT != 0) return hipErrorInvalidValue;
     if (g.C < CM_COLS && CM_COLS % g.C != 0) return hipErrorInvalidValue;   // narrow panels: C divides 512
-    if (g.vdiv < 1 || g.odiv < 1) return hipErrorInvalidValue;
+    if (g.vsh < 0 || g.vsh > 30 || g.osh < 0 || g.osh > 30) return hipErrorInvalidValue;
     g.rows_per_split = g.R / g.S;
     // vectors per pass over M: the smallest of 1, 2, 4, 8 covering NV (8 and
     // several passes beyond)
@@ -258,14 +331,13 @@ hipError_t launch_colmac(int dtype, int conj, ColmacDesc g, hipStream_t st) {
     const int64_t gx = (g.C + CM_COLS - 1) / CM_COLS, gz = (g.NV + kg - 1) / kg;
     if (gx > 0x7fffffff || g.S > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)gx, (unsigned)g.S, (unsigned)gz);
-    // rows staged per chunk: 64 for full panels, 256 when narrow panels split
-    // the block into row phases
+    // full panels (C a multiple of 512) compile without the row phases
     const bool wide = g.C >= CM_COLS;
     switch (kg) {
-        case 1: wide ? colmac_kg<1, 64>(dtype, conj, grid, st, g) : colmac_kg<1, 256>(dtype, conj, grid, st, g); break;
-        case 2: wide ? colmac_kg<2, 64>(dtype, conj, grid, st, g) : colmac_kg<2, 256>(dtype, conj, grid, st, g); break;
-        case 4: wide ? colmac_kg<4, 64>(dtype, conj, grid, st, g) : colmac_kg<4, 256>(dtype, conj, grid, st, g); break;
-        default: wide ? colmac_kg<8, 64>(dtype, conj, grid, st, g) : colmac_kg<8, 256>(dtype, conj, grid, st, g); break;
+        case 1: wide ? colmac_kg<1, true>(dtype, conj, grid, st, g) : colmac_kg<1, false>(dtype, conj, grid, st, g); break;
+        case 2: wide ? colmac_kg<2, true>(dtype, conj, grid, st, g) : colmac_kg<2, false>(dtype, conj, grid, st, g); break;
+        case 4: wide ? colmac_kg<4, true>(dtype, conj, grid, st, g) : colmac_kg<4, false>(dtype, conj, grid, st, g); break;
+        default: wide ? colmac_kg<8, true>(dtype, conj, grid, st, g) : colmac_kg<8, false>(dtype, conj, grid, st, g); break;
     }
     return hipGetLastError();
 }

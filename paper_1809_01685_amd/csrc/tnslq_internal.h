@@ -118,7 +118,7 @@ hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int6
                           hipStream_t st);
 // The column MAC: out(s, v, c) = sum_{i in split s} op(M[i][c]) V(v, i) over
 // an R x C panel-layout matrix M (C even, and dividing 512 when below it) for
-// vectors v < NV, with
+// vectors v < NV, with vdiv = 2^vsh and odiv = 2^osh,
 //   V(v, i)      at V[(v / vdiv) vs1 + (v % vdiv) vs2 + i vsi],
 //   out(s, v, c) at out[s osplit + (v / odiv) os1 + (v % odiv) os2 + c osc],
 // the R rows cut into S equal splits.
@@ -127,9 +127,11 @@ struct ColmacDesc {
     int64_t R, C;
     const double2 *V;
     int NV;
-    int64_t vdiv, vs1, vs2, vsi;
+    int vsh;
+    int64_t vs1, vs2, vsi;
     double2 *out;
-    int64_t osplit, odiv, os1, os2, osc;
+    int osh;
+    int64_t osplit, os1, os2, osc;
     int S;
     int64_t rows_per_split;   // set by the launcher
 };
