@@ -174,7 +174,7 @@ def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3"):
             ms = r["t_matvec_ms"] / r["steps_done"]
             min_bytes = 8 * D + 2 * 8 * d_ab * K
             rows.append({"b_qubits": nb, "probes": K, "streamed": bool(r["streamed"]), "logneg": r["logneg"],
-                         "logneg_se": r["logneg_se"], "matvec_ms": ms, "min_bytes": min_bytes,
+                         "logneg_se": None if K == 1 else r["logneg_se"], "matvec_ms": ms, "min_bytes": min_bytes,
                          "algorithmic_GBps": min_bytes / (ms * 1e-3) / 1e9,
                          "frac_of_8TBps": min_bytes / (ms * 1e-3) / 8e12,
                          "two_pass_frac_of_8TBps": 2 * 8 * D / (ms * 1e-3) / 8e12 if r["streamed"] else None})
