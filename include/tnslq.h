@@ -73,6 +73,25 @@ enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
 #define TNSLQ_MAX_QUBITS 36
 #define TNSLQ_MAX_STEPS 128
 
+/* Forms of the operator rho_AB^{T_B} (tnslq_options.operator_form).  Sec. V
+ * lists three intermediaries for (rho^{T_B} phi)_{ab}; the subsystem sizes
+ * decide which is cheapest.
+ *   TNSLQ_OPERATOR_LAZY      intermediary (i) (or (ii), by exchanging the
+ *                            roles of A and B): every matvec contracts psi,
+ *                            16 D min(d_A, d_B) flops per vector.
+ *   TNSLQ_OPERATOR_EXPLICIT  intermediary (iii): rho^{T_B} is formed once as a
+ *                            d_A d_B x d_A d_B matrix (8 (d_A d_B)^2 d_E
+ *                            flops, rho = P P^dagger with P = psi regrouped as
+ *                            (A B) x E, then B's indices exchanged), and every
+ *                            matvec is a dense product, 8 (d_A d_B)^2 flops
+ *                            per vector.  Needs the matrix in the workspace
+ *                            (at most 4 GiB of it).
+ *   TNSLQ_OPERATOR_AUTO      the explicit form when it fits and its padded
+ *                            flop count over n_steps matvecs is the smaller,
+ *                            else the lazy form (always lazy when K d_B <= 4,
+ *                            the streaming regime). */
+enum { TNSLQ_OPERATOR_AUTO = 0, TNSLQ_OPERATOR_LAZY = 1, TNSLQ_OPERATOR_EXPLICIT = 2 };
+
 /* Stopping rules of tnslq_options.stop_rule. */
 enum { TNSLQ_STOP_DIFF = 0, TNSLQ_STOP_FIT = 1 };
 #define TNSLQ_FIT_WINDOW 8
@@ -121,6 +140,8 @@ typedef struct {
  *                of ||phi_n||^2 sigma_n.  The result is the fitted estimate,
  *                also with stop_tol = 0 (then after n_steps steps, which must
  *                be > TNSLQ_FIT_MIN_POINTS).
+ *   operator_form
+ *                how rho^{T_B} is applied (TNSLQ_OPERATOR_*, above).
  */
 typedef struct {
     int n_probes;
@@ -131,6 +152,7 @@ typedef struct {
     uint64_t probe_offset;
     double stop_tol;
     int stop_rule;
+    int operator_form;      /* TNSLQ_OPERATOR_AUTO / _LAZY / _EXPLICIT        */
 } tnslq_options;
 
 typedef struct {
@@ -158,13 +180,18 @@ typedef struct {
                                passes over psi with FP64 arithmetic (K d_B <= 4
                                after the role choice), 0 on the matrix cores
                                in `precision`                                  */
+    int explicit_operator;  /* 1 if rho^{T_B} was formed explicitly
+                               (intermediary (iii)); the roles of A and B are
+                               then never exchanged, t_contract1_ms is 0 and
+                               t_contract2_ms times the dense products; the
+                               forming is part of t_layout_ms                  */
 } tnslq_result;
 
 /* ------------------------------------------------------------ utilities */
 const char *tnslq_status_str(int status);
 /* Description of the last failure on the calling thread ("" if none). */
 const char *tnslq_last_error(void);
-/* ABI version, currently 2. */
+/* ABI version, currently 3. */
 int tnslq_version(void);
 
 /* -------------------------------------------------- logarithmic negativity */
@@ -210,6 +237,21 @@ int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n
 int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors,
                    const void *X_dev, void *Y_dev, int precision, void *ws_dev, size_t ws_bytes,
                    void *stream);
+
+/* ------------------------------------------- explicit partial transpose */
+
+/* Workspace bytes for tnslq_rho_pt. */
+int tnslq_rho_pt_workspace_bytes(int dtype, const tnslq_partition *part, size_t *bytes);
+
+/* The partially traced, partially transposed density matrix of Sec. V's
+ * intermediary (iii), formed on the device in FP64:
+ *   rho_out[(a, b)][(a', b')] = sum_c psi_{a b' c} psi*_{a' b c},
+ * rows and columns (a, b) with a = A's qubits in the order given (most
+ * significant first), b likewise, b fastest; c runs over the other qubits.
+ *   rho_dev  device, (d_A d_B)^2 complex128, row-major, overwritten.
+ * At most d_A d_B = 16384.  Needs non-empty A and B.  Does not synchronise. */
+int tnslq_rho_pt(const void *psi_dev, int dtype, const tnslq_partition *part, void *rho_dev, void *ws_dev,
+                 size_t ws_bytes, void *stream);
 
 /* ------------------------------------------- other spectral sums (entropy) */
 

@@ -22,6 +22,8 @@ TNSLQ_FP64, TNSLQ_FP32, TNSLQ_BF16X3, TNSLQ_BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "bf16x6": TNSLQ_BF16X6}
 TNSLQ_STOP_DIFF, TNSLQ_STOP_FIT = 0, 1
 STOP_RULES = {"diff": TNSLQ_STOP_DIFF, "fit": TNSLQ_STOP_FIT}
+TNSLQ_OPERATOR_AUTO, TNSLQ_OPERATOR_LAZY, TNSLQ_OPERATOR_EXPLICIT = 0, 1, 2
+OPERATORS = {"auto": TNSLQ_OPERATOR_AUTO, "lazy": TNSLQ_OPERATOR_LAZY, "explicit": TNSLQ_OPERATOR_EXPLICIT}
 TNSLQ_FIT_WINDOW, TNSLQ_FIT_MIN_POINTS = 8, 5
 TNSLQ_F_ABS, TNSLQ_F_ENTROPY, TNSLQ_F_PURITY = 0, 1, 2
 FUNCTIONS = {"entropy": TNSLQ_F_ENTROPY, "purity": TNSLQ_F_PURITY}
@@ -42,7 +44,7 @@ class Partition(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
-                ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int)]
+                ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int), ("operator_form", ctypes.c_int)]
 
 
 class SpectralResult(ctypes.Structure):
@@ -62,7 +64,7 @@ class Result(ctypes.Structure):
                 ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
                 ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
                 ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
-                ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int)]
+                ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int), ("explicit_operator", ctypes.c_int)]
 
     def as_dict(self) -> Dict[str, float]:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -80,6 +82,8 @@ _SIGS = {
                           ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
     "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, ctypes.POINTER(_SZ)]),
     "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _VP, _SZ, _VP]),
+    "tnslq_rho_pt_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(_SZ)]),
+    "tnslq_rho_pt": (_I, [_VP, _I, ctypes.POINTER(Partition), _VP, _VP, _SZ, _VP]),
     "tnslq_quadrature": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
     "tnslq_probes": (_I, [_U64, _U64, _I, _I64, _VP, _VP]),
     "tnslq_mlp_workspace_bytes": (_I, [_I, ctypes.POINTER(_SZ)]),
@@ -184,10 +188,16 @@ def _rule(stop_rule) -> int:
     return int(stop_rule)
 
 
+def _operator(operator) -> int:
+    if isinstance(operator, str):
+        return OPERATORS[operator]
+    return int(operator)
+
+
 def make_options(n_probes: int, n_steps: int, reorth: bool = False, precision="fp32", seed: int = 0,
-                 probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff") -> Options:
+                 probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff", operator="auto") -> Options:
     return Options(int(n_probes), int(n_steps), int(bool(reorth)), _prec(precision), int(seed) & (2**64 - 1),
-                   int(probe_offset), float(stop_tol), _rule(stop_rule))
+                   int(probe_offset), float(stop_tol), _rule(stop_rule), _operator(operator))
 
 
 def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int:
@@ -201,14 +211,14 @@ def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int
 # ------------------------------------------------------------- logneg
 def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
                  seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
-                 want_arrays: bool = True, stop_rule="diff") -> Dict[str, object]:
+                 want_arrays: bool = True, stop_rule="diff", operator="auto") -> Dict[str, object]:
     """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``."""
     import numpy as np
     _check_device_tensor(psi, "psi")
     if psi.numel() != 1 << n_qubits:
         raise ValueError("psi has the wrong length")
     dt = _dtype_code(psi)
-    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator)
     p = _partition(n_qubits, a, b)
     need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
     ws = _workspace(need, psi.device, workspace)
@@ -256,6 +266,31 @@ def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None
     _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision), _ptr(ws),
                                 ws.numel(), _stream(stream)), "tnslq_ptmatvec")
     return Y
+
+
+def tnslq_rho_pt_workspace_bytes(dtype: int, n_qubits: int, a, b) -> int:
+    n = ctypes.c_size_t(0)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_rho_pt_workspace_bytes(int(dtype), ctypes.byref(p), ctypes.byref(n)),
+           "tnslq_rho_pt_workspace_bytes")
+    return n.value
+
+
+def tnslq_rho_pt(psi, n_qubits: int, a, b, workspace=None, stream=None, out=None):
+    """rho_AB^{T_B} formed explicitly in FP64 (intermediary (iii)) as a device
+    complex128 (d_A d_B, d_A d_B) matrix, rows and columns (a, b), b fastest."""
+    import torch
+    _check_device_tensor(psi, "psi")
+    dt = _dtype_code(psi)
+    n = 1 << (len(a) + len(b))
+    need = tnslq_rho_pt_workspace_bytes(dt, n_qubits, a, b)
+    ws = _workspace(need, psi.device, workspace)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.complex128, device=psi.device)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_rho_pt(_ptr(psi), dt, ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "tnslq_rho_pt")
+    return out
 
 
 def tnslq_quadrature(alpha, beta, steps=None, stream=None):
@@ -323,11 +358,11 @@ def tnslq_mlp_train(params, m, v, norm, x, r, idx, batch: int, t0: int, lr: floa
 def tnslq_logneg_surrogate(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, params, norm, y_scale: float,
                            tol: float = 0.01, early_steps: int = 8, reorth: bool = False, precision="fp32",
                            seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None,
-                           stream=None, stop_rule="diff") -> Dict[str, object]:
+                           stream=None, stop_rule="diff", operator="auto") -> Dict[str, object]:
     import numpy as np
     _check_device_tensor(psi, "psi")
     dt = _dtype_code(psi)
-    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator)
     p = _partition(n_qubits, a, b)
     need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
     ws = _workspace(need, psi.device, workspace)

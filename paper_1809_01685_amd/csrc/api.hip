@@ -44,6 +44,10 @@ inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Largest intermediary (Ups) chunk the planner allows, in bytes.
 constexpr size_t UPS_BUDGET = size_t(16) << 30;
+// Largest explicit operator (intermediary (iii)): d_A d_B, and bytes of the
+// operator and of its dense FP32/FP64 precursor.
+constexpr int64_t EXPLICIT_MAX_N = 16384;
+constexpr size_t EXPLICIT_BUDGET = size_t(4) << 30;
 
 int check_partition(const tnslq_partition *p) {
     if (!p) return fail(TNSLQ_E_ARG, "partition is NULL");
@@ -71,12 +75,34 @@ int check_dtype(int dtype) {
     return TNSLQ_OK;
 }
 
-// Build the plan: roles (A and B exchanged when B is larger, so that the
-// contraction cost D * min(d_A, d_B) per probe is the smaller one), chunking
-// and the workspace carve-up.  `lanczos` = 0 plans a bare matvec.
-int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int prec, int lanczos, Plan &pl) {
+inline int64_t up128(int64_t x) { return (x + 127) / 128 * 128; }
+
+// Padded complex multiply-adds of one lazy block matvec (both contractions
+// over all probe chunks; matrix-core tiles are 128 x 128) and of the explicit
+// form (forming rho^{T_B} once, then one dense product per matvec), for the
+// operator-form choice.
+double lazy_macs(const Plan &pl) {
+    const int64_t chunks = (pl.K + pl.kc - 1) / pl.kc, N = up128((int64_t)pl.kc * pl.dB);
+    return (double)chunks * ((double)up128(pl.dB * pl.dE) * N * pl.dA + (double)up128(pl.dA) * N * pl.dE * pl.dB);
+}
+double explicit_macs(int64_t n, int64_t dE, int K, int m) {
+    return (double)up128(n) * up128(n) * dE + (double)m * up128(n) * up128(K) * n;
+}
+size_t explicit_bytes(int prec, int64_t n) {
+    return std::max(brick_bytes(prec, n, n), (size_t)(n * n) * (prec == TNSLQ_FP64 ? 16 : 8));
+}
+
+// Build the plan: the operator form (Sec. V: the subsystem sizes decide
+// between the lazy intermediaries and the explicit operator), roles (for the
+// lazy form A and B are exchanged when B is larger, so that the contraction
+// cost D * min(d_A, d_B) per probe is the smaller one), chunking and the
+// workspace carve-up.  `lanczos` = 0 plans a bare lazy matvec.
+int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int prec, int lanczos, int opform,
+              Plan &pl) {
     int rc;
     if ((rc = check_dtype(dtype)) || (rc = check_partition(p)) || (rc = check_prec(prec))) return rc;
+    if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_EXPLICIT)
+        return fail(TNSLQ_E_ARG, "operator_form %d unknown", opform);
     if (K < 1 || K > 65535) return fail(TNSLQ_E_ARG, "n_probes %d outside [1, 65535]", K);
     if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
         return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
@@ -88,6 +114,24 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     pl.m = lanczos ? m : 1;
     pl.reorth = lanczos ? (reorth ? 1 : 0) : 0;
     pl.swapped = p->n_b > p->n_a;
+    // the explicit form keeps the caller's roles
+    {
+        const int64_t n0 = int64_t(1) << (p->n_a + p->n_b);
+        const int64_t dE0 = int64_t(1) << (p->n_qubits - p->n_a - p->n_b);
+        const bool fits = n0 <= EXPLICIT_MAX_N && explicit_bytes(prec, n0) <= EXPLICIT_BUDGET;
+        if (lanczos && opform == TNSLQ_OPERATOR_EXPLICIT) {
+            if (!fits)
+                return fail(TNSLQ_E_ARG, "explicit operator: d_A d_B = %lld exceeds %lld", (long long)n0,
+                            (long long)EXPLICIT_MAX_N);
+            pl.expl = 1;
+        } else if (lanczos && opform == TNSLQ_OPERATOR_AUTO && fits) {
+            // cost of the lazy plan (roles as above, chunking as below)
+            Plan lz;
+            if ((rc = make_plan(dtype, p, K, m, reorth, prec, lanczos, TNSLQ_OPERATOR_LAZY, lz))) return rc;
+            if (!lz.stream && explicit_macs(n0, dE0, K, lz.m) < lz.m * lazy_macs(lz)) pl.expl = 1;
+        }
+        if (pl.expl) pl.swapped = 0;
+    }
     const int *qa = pl.swapped ? p->b : p->a;
     const int *qb = pl.swapped ? p->a : p->b;
     pl.nA = pl.swapped ? p->n_b : p->n_a;
@@ -134,7 +178,18 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     // multiply-adds per element of psi and the 128 x 128 matrix-core tiles
     // would be mostly padding; they run instead as two streaming passes over
     // psi in its own dtype with FP64 products and sums.
-    pl.stream = (int64_t)K * pl.dB <= 4;
+    pl.stream = !pl.expl && (int64_t)K * pl.dB <= 4;
+    if (pl.expl) {
+        // one dense product per matvec: rho^{T_B} (n rows, reduction n) with
+        // the K vectors (rows k, reduction n), split-K to fill the chip
+        pl.kc = K;
+        pl.S1 = 1;
+        pl.nst1 = pl.nst_rho = brick_stages(prec, n);
+        pl.nst_e = brick_stages(prec, pl.dE);
+        const int64_t tl = (up128(n) / 128) * (up128(K) / 128);
+        pl.S = 1;
+        while (tl * pl.S < 2048 && pl.nst_rho % (2 * pl.S) == 0 && pl.nst_rho / (2 * pl.S) >= 8) pl.S *= 2;
+    }
     if (pl.stream) {
         pl.kc = K;
         pl.S1 = 1;
@@ -154,7 +209,14 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         o += up(bytes);
         return r;
     };
-    if (pl.stream) {
+    if (pl.expl) {
+        pl.off_Pabe = take(brick_bytes(prec, n, pl.dE));
+        pl.off_Pabc = take(brick_bytes(prec, n, pl.dE));
+        pl.off_Cd = take((size_t)(n * n) * acc);
+        pl.off_rho = take(brick_bytes(prec, n, n));
+        pl.off_Xt = take(brick_bytes(prec, K, n));
+        pl.off_Ypart = take((size_t)pl.S * K * n * acc);
+    } else if (pl.stream) {
         const size_t esz = dtype == TNSLQ_C128 ? 16 : 8;
         const int64_t nv = (int64_t)K * pl.dB, ncol = pl.dE * pl.dB;
         pl.off_P1s = take(esz * (size_t)pl.D);
@@ -222,6 +284,7 @@ struct Ctx {
     LzDims z;
     void *Paeb, *Pbea, *Xt, *Ups, *Ypart, *U1part;
     void *P1s, *P2s;
+    void *Pabe, *Pabc, *Cd, *rho;
     double2 *Up, *U2, *Xs;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
@@ -259,6 +322,11 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.U2 = (double2 *)(c.ws + pl.off_U2);
     c.Xs = (double2 *)(c.ws + pl.off_Xs);
     if (pl.stream) c.Paeb = c.Pbea = c.Xt = c.Ups = nullptr;
+    c.Pabe = pl.expl ? c.ws + pl.off_Pabe : nullptr;
+    c.Pabc = pl.expl ? c.ws + pl.off_Pabc : nullptr;
+    c.Cd = pl.expl ? c.ws + pl.off_Cd : nullptr;
+    c.rho = pl.expl ? c.ws + pl.off_rho : nullptr;
+    if (pl.expl) c.Paeb = c.Pbea = c.Ups = nullptr;
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
     c.alpha = (double *)(c.ws + pl.off_alpha);
@@ -276,14 +344,53 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.fitout = c.fsig + pl.K;
     c.feat = (float *)(c.ws + pl.off_feat);
     c.mlpws = c.ws + pl.off_mlp;
-    c.z = LzDims{pl.dA, pl.dB, pl.dAB, pl.K, pl.m, pl.nblk};
+    // the explicit form contracts the vectors over the whole index (a, b): its
+    // transposed copy Xt has rows k and reduction index a d_B + b
+    c.z = pl.expl ? LzDims{pl.dAB, 1, pl.dAB, pl.K, pl.m, pl.nblk} : LzDims{pl.dA, pl.dB, pl.dAB, pl.K, pl.m, pl.nblk};
 }
 
 // Regroup psi into both contraction layouts, and zero the padding of Xt and
 // Ups along their reduction index (written nowhere else; padded rows need no
 // clearing, their products land outside C).
+// rho_AB = P P^dagger (Sec. V: the partial trace over E) as a dense n x n
+// product in the accumulator type, from P[(a, b)][c] = psi regrouped as
+// (A, B, E) and its conjugate, both as brick operands of precision `prec`.
+int form_rho(int prec, int dtype, const void *psi, const PermDesc &abe, int64_t n, int64_t dE, void *Pabe,
+             void *Pabc, void *Cd, hipStream_t st) {
+    TNSLQ_HIP(launch_permute(prec, dtype, psi, Pabe, n, dE, abe, 0, st));
+    TNSLQ_HIP(launch_permute(prec, dtype, psi, Pabc, n, dE, abe, 1, st));
+    GemmDesc g{};
+    g.A = Pabe;
+    g.B = Pabc;
+    g.C = Cd;
+    g.M = n;
+    g.N = n;
+    g.Kr = dE;
+    g.nst = brick_stages(prec, dE);
+    g.S = 1;
+    g.out_mode = 1;   // C[i][j] at i n + j
+    g.cnb_log2 = 0;
+    g.cni_log2 = 0;
+    g.ldc = n;
+    g.cbs = 1;
+    g.c_split = 0;
+    TNSLQ_HIP(launch_gemm(prec, g, st));
+    return TNSLQ_OK;
+}
+
 int do_layout(Ctx &c, const void *psi) {
     const Plan &pl = c.pl;
+    if (pl.expl) {
+        // intermediary (iii): rho^{T_B} formed once, as the brick operand of
+        // every later matvec
+        const PermDesc abe = perm_for(pl, pl.qa, pl.nA, pl.qb, pl.nB, pl.qe, pl.nE);
+        int rc;
+        if ((rc = form_rho(pl.prec, pl.dtype, psi, abe, pl.dAB, pl.dE, c.Pabe, c.Pabc, c.Cd, c.st))) return rc;
+        TNSLQ_HIP(launch_pt_bricks(pl.prec, pl.prec == TNSLQ_FP64, c.Cd, pl.dAB, pl.nB, c.rho, pl.nst_rho, c.st));
+        if (pl.dAB % brick_epr(pl.prec))
+            TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, pl.K, pl.dAB), c.st));
+        return TNSLQ_OK;
+    }
     if (pl.stream) {
         // (A; E, B): rows a', columns (c, b); (E, B; A): rows (c, b'), columns a
         int eb[TNSLQ_MAX_QUBITS];
@@ -416,6 +523,33 @@ int contract_chunk(Ctx &c, int k0, int kcur, hipEvent_t e1, hipEvent_t e2) {
     return TNSLQ_OK;
 }
 
+// Intermediary (iii): Y[k][i] = sum_l rho^{T_B}[i][l] Xt[k][l] for all K
+// probes, split-K partials at s K n + k n + i.
+int explicit_matvec(Ctx &c, hipEvent_t e1, hipEvent_t e2) {
+    const Plan &pl = c.pl;
+    const int64_t n = pl.dAB;
+    if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+    GemmDesc g{};
+    g.A = c.rho;
+    g.B = c.Xt;
+    g.C = c.Ypart;
+    g.M = n;
+    g.N = pl.K;
+    g.Kr = n;
+    g.nst = pl.nst_rho;
+    g.S = pl.S;
+    g.out_mode = 1;
+    g.cnb_log2 = 0;
+    g.cni_log2 = 0;
+    g.ldc = 1;
+    g.cbs = n;
+    g.c_split = (int64_t)pl.K * n;
+    TNSLQ_HIP(launch_gemm(pl.prec, g, c.st));
+    if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+    c.n_launch++;
+    return TNSLQ_OK;
+}
+
 // Events of one Lanczos step: mv0, then per probe chunk (after contraction 1,
 // after contraction 2, after the merge), then mv1 (matvec done), lz1.
 struct StepEvents {
@@ -442,7 +576,9 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     TNSLQ_HIP(hipEventRecord(se->mv0(), c.st));
     for (int k0 = 0, ch = 0; k0 < pl.K; k0 += pl.kc, ++ch) {
         const int kcur = std::min(pl.kc, pl.K - k0);
-        if (pl.stream) {
+        if (pl.expl) {
+            if ((rc = explicit_matvec(c, se->c1(ch), se->c2(ch)))) return rc;
+        } else if (pl.stream) {
             if ((rc = stream_contract(c, q_cur, se->c1(ch), se->c2(ch)))) return rc;
         } else if ((rc = contract_chunk(c, k0, kcur, se->c1(ch), se->c2(ch)))) {
             return rc;
@@ -516,6 +652,8 @@ int check_options(const tnslq_options *opt) {
     if (!(opt->stop_tol >= 0.0)) return fail(TNSLQ_E_ARG, "stop_tol must be >= 0");
     if (opt->stop_rule != TNSLQ_STOP_DIFF && opt->stop_rule != TNSLQ_STOP_FIT)
         return fail(TNSLQ_E_ARG, "stop_rule %d unknown", opt->stop_rule);
+    if (opt->operator_form < TNSLQ_OPERATOR_AUTO || opt->operator_form > TNSLQ_OPERATOR_EXPLICIT)
+        return fail(TNSLQ_E_ARG, "operator_form %d unknown", opt->operator_form);
     if (opt->stop_rule == TNSLQ_STOP_FIT && opt->n_steps < TNSLQ_FIT_MIN_POINTS + 1)
         return fail(TNSLQ_E_ARG, "the fit rule needs n_steps >= %d", TNSLQ_FIT_MIN_POINTS + 1);
     return check_prec(opt->precision);
@@ -541,7 +679,9 @@ struct Run {
 int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_options *opt, const void *psi, void *ws,
               size_t ws_bytes, void *stream) {
     int rc;
-    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1, r.c.pl))) return rc;
+    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
+                         opt->operator_form, r.c.pl)))
+        return rc;
     if (!psi) return fail(TNSLQ_E_ARG, "psi is NULL");
     if (!ws) return fail(TNSLQ_E_ARG, "workspace is NULL");
     if ((uintptr_t)ws % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
@@ -654,6 +794,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
     res->swapped_ab = pl.swapped;
     res->streamed = pl.stream;
+    res->explicit_operator = pl.expl;
     res->n_matvecs = r.jdone;
     res->n_contract_launches = c.n_launch;
     res->t_layout_ms = elapsed(r.e_start, r.e_layout);
@@ -955,7 +1096,7 @@ const char *tnslq_status_str(int s) {
 
 const char *tnslq_last_error(void) { return g_err.c_str(); }
 
-int tnslq_version(void) { return 2; }
+int tnslq_version(void) { return 3; }
 
 int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt, size_t *bytes) {
     int rc;
@@ -967,7 +1108,9 @@ int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_op
         return TNSLQ_OK;
     }
     Plan pl;
-    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1, pl))) return rc;
+    if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
+                         opt->operator_form, pl)))
+        return rc;
     *bytes = pl.total;
     return TNSLQ_OK;
 }
@@ -995,7 +1138,7 @@ int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
     if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
     Plan pl;
-    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, pl))) return rc;
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, pl))) return rc;
     *bytes = pl.total;
     return TNSLQ_OK;
 }
@@ -1007,7 +1150,7 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
     if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
     Ctx c;
-    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, c.pl))) return rc;
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, c.pl))) return rc;
     if (!psi_dev || !X_dev || !Y_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
     if (X_dev == Y_dev) return fail(TNSLQ_E_ARG, "X and Y alias");
     if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
@@ -1096,6 +1239,60 @@ int tnslq_mutual_information(const void *psi_dev, int dtype, const tnslq_partiti
         out[2 + 2 * i] = v[i];
         out[3 + 2 * i] = e[i];
     }
+    return TNSLQ_OK;
+}
+
+namespace {
+// Roles, sizes and workspace of tnslq_rho_pt: P and its conjugate as FP64
+// bricks, then the dense FP64 product.
+struct PtPlan {
+    Plan pl;
+    size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, total = 0;
+};
+int make_pt_plan(int dtype, const tnslq_partition *part, PtPlan &pp) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "rho_pt needs non-empty A and B");
+    if (part->n_a + part->n_b > 14)
+        return fail(TNSLQ_E_ARG, "rho_pt: d_A d_B = 2^%d exceeds %lld", part->n_a + part->n_b,
+                    (long long)EXPLICIT_MAX_N);
+    if ((rc = make_plan(dtype, part, 1, 1, 0, TNSLQ_FP64, 1, TNSLQ_OPERATOR_EXPLICIT, pp.pl))) return rc;
+    const Plan &pl = pp.pl;
+    const size_t pb = up(brick_bytes(TNSLQ_FP64, pl.dAB, pl.dE));
+    pp.off_Pabe = 0;
+    pp.off_Pabc = pb;
+    pp.off_Cd = 2 * pb;
+    pp.total = pp.off_Cd + up((size_t)(pl.dAB * pl.dAB) * 16);
+    return TNSLQ_OK;
+}
+}  // namespace
+
+int tnslq_rho_pt_workspace_bytes(int dtype, const tnslq_partition *part, size_t *bytes) {
+    int rc;
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    PtPlan pp;
+    if ((rc = make_pt_plan(dtype, part, pp))) return rc;
+    *bytes = pp.total;
+    return TNSLQ_OK;
+}
+
+int tnslq_rho_pt(const void *psi_dev, int dtype, const tnslq_partition *part, void *rho_dev, void *ws_dev,
+                 size_t ws_bytes, void *stream) {
+    int rc;
+    g_err.clear();
+    PtPlan pp;
+    if ((rc = make_pt_plan(dtype, part, pp))) return rc;
+    if (!psi_dev || !rho_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < pp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, pp.total);
+    const Plan &pl = pp.pl;
+    char *ws = (char *)ws_dev;
+    hipStream_t st = (hipStream_t)stream;
+    const PermDesc abe = perm_for(pl, pl.qa, pl.nA, pl.qb, pl.nB, pl.qe, pl.nE);
+    if ((rc = form_rho(TNSLQ_FP64, pl.dtype, psi_dev, abe, pl.dAB, pl.dE, ws + pp.off_Pabe, ws + pp.off_Pabc,
+                       ws + pp.off_Cd, st)))
+        return rc;
+    TNSLQ_HIP(launch_pt_dense((const double2 *)(ws + pp.off_Cd), pl.dAB, pl.nB, (double2 *)rho_dev, st));
     return TNSLQ_OK;
 }
 

@@ -205,6 +205,47 @@ __global__ void __launch_bounds__(256) k_partials_to_bricks(const AccT *__restri
     }
 }
 
+// ---------------------------------------------------------- explicit operator
+// Intermediary (iii) of Sec. V from the dense product C = rho_AB (row-major
+// n x n, accumulator type AccT): exchanging B's bra and ket indices,
+//   rho^{T_B}[(a, b)][(a', b')] = C[(a, b')][(a', b)],
+// written as an n x n brick operand (rows (a, b), reduction index (a', b')),
+// zeros in the reduction padding.  Threads step over the plane-0 entries of
+// the bricks in memory order, as in k_permute.
+template <int PREC, typename AccT>
+__global__ void __launch_bounds__(256) k_pt_bricks(const AccT *__restrict__ C, int64_t n, int nB,
+                                                   void *__restrict__ rho, int64_t nst) {
+    constexpr int EPR = brick_epr(PREC), EPU = EPR / 4, NPL = planes_of(PREC);
+    constexpr int64_t PER_BRICK = (int64_t)BRICK_ROWS * EPR;
+    const int64_t mB = (int64_t(1) << nB) - 1;
+    const int64_t total = brick_rows(n) * nst * EPR;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
+        const int64_t b = x / PER_BRICK, w = x % PER_BRICK;
+        const int64_t rr = w / EPR, pos = w % EPR;
+        const int64_t ll = (((pos / EPU) ^ brick_swizzle(rr)) * EPU) + pos % EPU;
+        const int64_t r = (b / nst) * BRICK_ROWS + rr, l = (b % nst) * EPR + ll;
+        double re = 0.0, im = 0.0;
+        if (r < n && l < n) {
+            const AccT v = C[((r & ~mB) | (l & mB)) * n + ((l & ~mB) | (r & mB))];
+            re = (double)v.x;
+            im = (double)v.y;
+        }
+        store_planes<PREC>(rho, brick_ps(PREC), (b * NPL * BRICK_ROWS + rr) * EPR + pos, re, im);
+    }
+}
+
+// The same as a dense complex128 matrix, one thread per output element.
+__global__ void __launch_bounds__(256) k_pt_dense(const double2 *__restrict__ C, int64_t n, int nB,
+                                                  double2 *__restrict__ out) {
+    const int64_t mB = (int64_t(1) << nB) - 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n * n; x += stride) {
+        const int64_t r = x / n, l = x % n;
+        out[x] = C[((r & ~mB) | (l & mB)) * n + ((l & ~mB) | (r & mB))];
+    }
+}
+
 inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -301,6 +342,28 @@ hipError_t launch_partials_to_bricks(int prec, const void *part, int S, int64_t 
         default: TNSLQ_P2B(TNSLQ_BF16X6, float2); break;
     }
 #undef TNSLQ_P2B
+    return hipGetLastError();
+}
+
+hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int nB, void *rho, int64_t rho_nst,
+                            hipStream_t st) {
+    if ((prec == TNSLQ_FP64) != (accfp64 != 0)) return hipErrorInvalidValue;
+    dim3 grid(grid_for(brick_rows(n) * rho_nst * brick_epr(prec), 256 * 4, 65535 * 8)), block(256);
+#define TNSLQ_PTB(P, A) \
+    hipLaunchKernelGGL((k_pt_bricks<P, A>), grid, block, 0, st, (const A *)C, n, nB, rho, rho_nst)
+    switch (prec) {
+        case TNSLQ_FP64: TNSLQ_PTB(TNSLQ_FP64, double2); break;
+        case TNSLQ_FP32: TNSLQ_PTB(TNSLQ_FP32, float2); break;
+        case TNSLQ_BF16X3: TNSLQ_PTB(TNSLQ_BF16X3, float2); break;
+        default: TNSLQ_PTB(TNSLQ_BF16X6, float2); break;
+    }
+#undef TNSLQ_PTB
+    return hipGetLastError();
+}
+
+hipError_t launch_pt_dense(const double2 *C, int64_t n, int nB, double2 *out, hipStream_t st) {
+    dim3 grid(grid_for(n * n, 256 * 4, 65535 * 4)), block(256);
+    hipLaunchKernelGGL(k_pt_dense, grid, block, 0, st, C, n, nB, out);
     return hipGetLastError();
 }
 

@@ -39,11 +39,15 @@ struct Plan {
     int S1 = 1;                      // split-K factor of the first contraction
     int stream = 0;                  // contractions as two streaming passes over psi (K d_B <= 4)
     int S1s = 1, S2s = 1;            // row splits of the two streaming passes
+    int expl = 0;                    // rho^{T_B} formed explicitly (intermediary (iii))
+    int64_t nst_rho = 1;             // bricks along the reduction index of the explicit matvec
+    int64_t nst_e = 1;               // bricks along E of the forming product
     int nblk = 1;                    // reduction blocks per probe vector
     int64_t nst1 = 1, nst2 = 1;      // bricks along the reduction index of contraction 1, 2
     // workspace carve-up (byte offsets)
     size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0, off_U1part = 0;
     size_t off_P1s = 0, off_P2s = 0, off_Up = 0, off_U2 = 0, off_Xs = 0;
+    size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, off_rho = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -59,6 +63,16 @@ struct PermDesc {
 // writing every brick entry including the zero padding.
 hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t R, int64_t Kr,
                           const PermDesc &pd, int conj, hipStream_t st);
+
+// Explicit rho^{T_B} (intermediary (iii) of Sec. V) from the dense product
+// C[i][j] = rho_AB[i][j] (n x n, row-major, accumulator type: FP64 when
+// accfp64, else FP32), d_B = 2^nB:
+//   rho^{T_B}[(a, b)][(a', b')] = C[(a, b')][(a', b)].
+// As an n x n brick operand of precision `prec` (reduction padding zeroed):
+hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int nB, void *rho, int64_t rho_nst,
+                            hipStream_t st);
+// As a dense complex128 row-major matrix (from an FP64 product):
+hipError_t launch_pt_dense(const double2 *C, int64_t n, int nB, double2 *out, hipStream_t st);
 
 // ------------------------------------------------------------ Lanczos etc.
 struct LzDims {

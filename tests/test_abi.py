@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert T.tnslq_version() == 2
+    assert T.tnslq_version() == 3
     assert T.tnslq_status_str(0) == "ok"
     assert T.tnslq_status_str(-2) == "invalid partition"
     assert T.tnslq_status_str(-4) == "workspace too small"
@@ -49,6 +49,48 @@ def test_workspace_query_and_plan(L):
     assert n >= 41 * 32 * 4096 * 16
     o2 = T.make_options(32, 40, reorth=False, precision="fp32")
     assert T.tnslq_workspace_bytes(T.TNSLQ_C64, 20, list(range(6)), list(range(8, 14)), o2) < n
+
+
+def test_operator_form_choice_and_limits(L):
+    a20, b20 = list(range(6)), list(range(8, 14))
+    ws = {}
+    for form in ("auto", "lazy", "explicit"):
+        o = T.make_options(32, 40, reorth=True, precision="fp32", operator=form)
+        ws[form] = T.tnslq_workspace_bytes(T.TNSLQ_C64, 20, a20, b20, o)
+    # the explicit form holds rho^{T_B} (4096^2 complex, FP32 planes) and its
+    # dense FP32 precursor
+    assert ws["explicit"] >= 2 * 4096 * 4096 * 8
+    # at the 20-qubit workload (d_A = d_B = 64, d_E = 256, K = 32, 40 steps)
+    # the explicit form does ~3x fewer padded multiply-adds: auto takes it
+    assert ws["auto"] == ws["explicit"] != ws["lazy"]
+    # d_A d_B = 2^26: only the lazy form
+    o = T.make_options(8, 10, precision="bf16x3")
+    a30, b30 = list(range(4, 17)), list(range(17, 30))
+    assert T.tnslq_workspace_bytes(T.TNSLQ_C64, 30, a30, b30, o) == T.tnslq_workspace_bytes(
+        T.TNSLQ_C64, 30, a30, b30, T.make_options(8, 10, precision="bf16x3", operator="lazy"))
+    with pytest.raises(T.TnslqError, match="explicit operator"):
+        T.tnslq_workspace_bytes(T.TNSLQ_C64, 30, a30, b30, T.make_options(8, 10, precision="bf16x3",
+                                                                         operator="explicit"))
+    # K d_B <= 4 (streaming regime): auto stays lazy
+    o1 = T.make_options(1, 10, operator="auto")
+    assert T.tnslq_workspace_bytes(T.TNSLQ_C64, 16, list(range(8)), [8, 9], o1) == T.tnslq_workspace_bytes(
+        T.TNSLQ_C64, 16, list(range(8)), [8, 9], T.make_options(1, 10, operator="lazy"))
+    p = T._partition(6, [0], [1])
+    n = ctypes.c_size_t(0)
+    assert L.tnslq_workspace_bytes(0, ctypes.byref(p), ctypes.byref(T.make_options(4, 4, operator=5)),
+                                   ctypes.byref(n)) == -1
+
+
+def test_rho_pt_validates_without_device(L):
+    assert T.tnslq_rho_pt_workspace_bytes(T.TNSLQ_C128, 10, [0, 1, 2], [5, 6, 7]) >= 64 * 64 * 16
+    with pytest.raises(T.TnslqError) as ei:
+        T.tnslq_rho_pt_workspace_bytes(T.TNSLQ_C64, 20, list(range(8)), list(range(8, 15)))
+    assert ei.value.status == -1
+    with pytest.raises(T.TnslqError) as ei:
+        T.tnslq_rho_pt_workspace_bytes(T.TNSLQ_C64, 8, [0, 1], [])
+    assert ei.value.status == -2
+    p = T._partition(8, [0, 1], [2, 3])
+    assert L.tnslq_rho_pt(None, 0, ctypes.byref(p), None, None, 0, None) == -1
 
 
 @pytest.mark.parametrize("a,b,code", [

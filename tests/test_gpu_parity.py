@@ -70,18 +70,21 @@ def test_ptmatvec_matches_explicit_operator(dev, L, a, b, prec, dtype):
         assert err <= MATVEC_TOL[prec], (K, err)
 
 
-def _logneg_case(dev, psi_np, L, a, b, K, m, prec, dtype, reorth, seed):
+def _logneg_case(dev, psi_np, L, a, b, K, m, prec, dtype, reorth, seed, operator="lazy"):
     psi_t, psi_o = _dev_state(psi_np, dtype, dev)
-    g = T.tnslq_logneg(psi_t, L, a, b, K, m, reorth=reorth, precision=prec, seed=seed)
+    g = T.tnslq_logneg(psi_t, L, a, b, K, m, reorth=reorth, precision=prec, seed=seed, operator=operator)
+    assert g["explicit_operator"] == (operator == "explicit")
     o = slq.slq_logneg(psi_o, L, a, b, K, m, seed=seed, reorth=reorth)
     return g, o
 
 
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_logneg_matches_oracle_small_haar(dev, prec):
+def test_logneg_matches_oracle_small_haar(dev, prec, operator):
     # 10-qubit Haar state, A = 0-2, B = 3-5; 16 probes, 20 steps.
     dtype = np.complex128 if prec == "fp64" else np.complex64
-    g, o = _logneg_case(dev, ti.haar_state(10, 0), 10, [0, 1, 2], [3, 4, 5], 16, 20, prec, dtype, False, 0)
+    g, o = _logneg_case(dev, ti.haar_state(10, 0), 10, [0, 1, 2], [3, 4, 5], 16, 20, prec, dtype, False, 0,
+                        operator)
     tol = LOGNEG_TOL[prec] * max(abs(o["logneg"]), 1.0)
     print(prec, g["logneg"], o["logneg"], g["logneg"] - o["logneg"])
     assert abs(g["logneg"] - o["logneg"]) <= tol
@@ -108,32 +111,36 @@ def test_logneg_swapped_roles_match_oracle(dev):
     assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-10)
 
 
-def test_logneg_reorth_matches_oracle(dev):
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
+def test_logneg_reorth_matches_oracle(dev, operator):
     L, a, b = 12, [0, 1, 2, 3], [6, 7, 8]
-    g, o = _logneg_case(dev, ti.haar_state(L, 5), L, a, b, 4, 24, "fp64", np.complex128, True, 2)
+    g, o = _logneg_case(dev, ti.haar_state(L, 5), L, a, b, 4, 24, "fp64", np.complex128, True, 2, operator)
     assert np.allclose(g["alpha"], o["alpha"], rtol=0, atol=1e-10 * np.max(np.abs(o["alpha"])))
     assert np.allclose(g["beta"], o["beta"], rtol=0, atol=1e-10 * np.max(np.abs(o["alpha"])))
     assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-9)
 
 
-def test_bell_pair_and_product_state(dev):
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
+def test_bell_pair_and_product_state(dev, operator):
     L = 6
-    g, _ = _logneg_case(dev, ti.bell_pair_state(L, 1, 4), L, [0, 1], [3, 4], 6, 10, "fp64", np.complex128, False, 2)
+    g, _ = _logneg_case(dev, ti.bell_pair_state(L, 1, 4), L, [0, 1], [3, 4], 6, 10, "fp64", np.complex128, False, 2,
+                        operator)
     assert g["logneg"] == pytest.approx(1.0, abs=1e-12)
     assert np.all(g["steps"] <= 3)
     assert np.allclose(g["G"], 2.0, atol=1e-12)
     g, _ = _logneg_case(dev, ti.basis_product_state(L, [0, 1, 1, 0, 1, 0]), L, [0, 2], [3, 5], 4, 6, "fp32",
-                        np.complex64, False, 0)
+                        np.complex64, False, 0, operator)
     assert g["logneg"] == pytest.approx(0.0, abs=1e-6)
 
 
-def test_pure_state_schmidt_formula(dev):
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
+def test_pure_state_schmidt_formula(dev, operator):
     # empty environment: E = 2 log2 sum of singular values of psi as d_A x d_B
     L, a, b = 8, [0, 1, 2, 3], [4, 5, 6, 7]
     psi = ti.haar_state(L, 9)
     s = np.linalg.svd(psi.reshape(16, 16), compute_uv=False)
     want = 2 * np.log2(np.sum(s))
-    g, o = _logneg_case(dev, psi, L, a, b, 64, 40, "fp64", np.complex128, True, 4)
+    g, o = _logneg_case(dev, psi, L, a, b, 64, 40, "fp64", np.complex128, True, 4, operator)
     assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-9)
     assert abs(g["logneg"] - want) <= 4 * g["logneg_se"] + 1e-3
 
@@ -169,11 +176,12 @@ def test_probe_offset_merges_as_independent_samples(dev):
     assert np.allclose(np.concatenate([r1["G"], r2["G"]]), r["G"], rtol=1e-13, atol=0)
 
 
-def test_deterministic_rerun(dev):
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
+def test_deterministic_rerun(dev, operator):
     import torch
     L, a, b = 12, [0, 1, 2, 3], [6, 7, 8, 9]
     psi_t = torch.from_numpy(ti.haar_state(L, 8).astype(np.complex64)).to(dev)
-    r1 = T.tnslq_logneg(psi_t, L, a, b, 8, 16, precision="bf16x3", seed=1)
-    r2 = T.tnslq_logneg(psi_t, L, a, b, 8, 16, precision="bf16x3", seed=1)
+    r1 = T.tnslq_logneg(psi_t, L, a, b, 8, 16, precision="bf16x3", seed=1, operator=operator)
+    r2 = T.tnslq_logneg(psi_t, L, a, b, 8, 16, precision="bf16x3", seed=1, operator=operator)
     assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
     assert r1["logneg"] == r2["logneg"]

@@ -27,12 +27,14 @@ def haar20():
     return ti.haar_state(L20, 0)
 
 
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
 @pytest.mark.parametrize("prec,dtype", [("fp32", np.complex64), ("fp64", np.complex128)])
-def test_haar20_matches_oracle_on_same_probes(dev, haar20, prec, dtype):
+def test_haar20_matches_oracle_on_same_probes(dev, haar20, prec, dtype, operator):
     import torch
     psi = haar20.astype(dtype)
     psi_t = torch.from_numpy(psi).to(dev)
-    g = T.tnslq_logneg(psi_t, L20, A20, B20, 32, 40, reorth=True, precision=prec, seed=7)
+    g = T.tnslq_logneg(psi_t, L20, A20, B20, 32, 40, reorth=True, precision=prec, seed=7, operator=operator)
+    assert g["explicit_operator"] == (operator == "explicit")
     P = exact.regroup(psi.astype(np.complex128), L20, A20, B20)
     R = exact.rho_pt(P)
     X = probes.rademacher_probes(7, 32, 4096)
