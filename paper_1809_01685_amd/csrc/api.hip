@@ -44,6 +44,15 @@ inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Largest intermediary (Ups) chunk the planner allows, in bytes.
 constexpr size_t UPS_BUDGET = size_t(16) << 30;
+// Blocks per probe vector of the Lanczos kernels' two-stage reductions: at
+// least 4096 elements per block for long vectors, but enough blocks over the
+// K probes to fill the chip (about 2048) down to 128 elements per block.
+int reduction_blocks(int64_t n, int K) {
+    const int64_t want = std::max<int64_t>(n / 4096, (2048 + K - 1) / K);
+    const int64_t cap = std::min<int64_t>(1024, std::max<int64_t>(1, n / 128));
+    return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
 // Largest explicit operator (intermediary (iii)): d_A d_B, and bytes of the
 // operator and of its dense FP32/FP64 precursor.
 constexpr int64_t EXPLICIT_MAX_N = 16384;
@@ -173,7 +182,7 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     if (tiles1 < 1024)
         while (tiles1 * pl.S1 < 2048 && pl.nst1 % (2 * pl.S1) == 0 && pl.nst1 / (2 * pl.S1) >= 8) pl.S1 *= 2;
     const int64_t n = pl.dAB;
-    pl.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 4096));
+    pl.nblk = reduction_blocks(n, K);
     // HBM regime: with K d_B <= 4 vectors the contractions do at most 4 complex
     // multiply-adds per element of psi and the 128 x 128 matrix-core tiles
     // would be mostly padding; they run instead as two streaming passes over
@@ -903,7 +912,7 @@ int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt
     const int64_t cb1 = (sp.dR + 511) / 512 * kg, cb2 = (sp.d + 511) / 512 * kg;
     while (cb1 * sp.S1 < 2048 && sp.d / (2 * sp.S1) >= 64 && sp.S1 < 1024) sp.S1 *= 2;
     while (cb2 * sp.S2 < 2048 && sp.dR / (2 * sp.S2) >= 64 && sp.S2 < 1024) sp.S2 *= 2;
-    sp.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, sp.d / 4096));
+    sp.nblk = reduction_blocks(sp.d, sp.K);
     sp.nQ = sp.reorth ? sp.m + 1 : 3;
     const size_t esz = dtype == TNSLQ_C128 ? 16 : 8;
     const int K = sp.K, m = sp.m;

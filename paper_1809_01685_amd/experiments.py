@@ -24,6 +24,14 @@
         probes, 10 Lanczos steps; time per block matvec against the minimum
         bytes (psi once, the probe block in and out) at 8 TB/s.
 
+    python -m paper_1809_01685_amd.experiments operator_forms
+        The lazy operator (intermediary (i)) against the explicit one
+        (intermediary (iii)) on Haar states where d_A d_B <= 16384: 10 qubits
+        (d_A d_B = 64), the 20-qubit workload (4096, d_E = 256, K = 32, 40
+        steps with reorthogonalisation) in three precisions, and 24 qubits
+        with A = 0-6, B = 7-13 (16384, d_E = 1024); wall time per estimate,
+        and which form the automatic choice takes.
+
 All print one JSON object.  All arithmetic runs in libtnslq.
 """
 from __future__ import annotations
@@ -187,6 +195,44 @@ def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3"):
             "steps": n_steps, "rows": rows}
 
 
+def run_operator_forms(seed=0):
+    import torch
+    from . import tnslq_logneg as lg
+    dev = torch.device("cuda:0")
+    cases = [("haar10", 10, [0, 1, 2], [3, 4, 5], 16, 20, False, ["fp64"]),
+             ("haar20", 20, list(range(6)), list(range(8, 14)), 32, 40, True, ["fp32", "fp64", "bf16x3"]),
+             ("haar24", 24, list(range(7)), list(range(7, 14)), 32, 40, False, ["fp32", "bf16x3"])]
+    from tnslq_inputs import haar_state_torch
+    rows = []
+    for name, L, a, b, K, m, reorth, precs in cases:
+        for prec in precs:
+            dtype = torch.complex128 if prec == "fp64" else torch.complex64
+            psi = haar_state_torch(L, seed, dev, dtype)
+            res = {}
+            for form in ("lazy", "explicit", "auto"):
+                lg(psi, L, a, b, K, 4, reorth=reorth, precision=prec, seed=seed, operator=form, want_arrays=False)
+                r = lg(psi, L, a, b, K, m, reorth=reorth, precision=prec, seed=seed, operator=form,
+                       want_arrays=False)
+                res[form] = r
+            row = {"case": name, "n_qubits": L, "d_AB": 1 << (len(a) + len(b)), "d_E": 1 << (L - len(a) - len(b)),
+                   "probes": K, "steps": m, "reorth": reorth, "precision": prec,
+                   "lazy_s": res["lazy"]["t_total_ms"] / 1e3, "explicit_s": res["explicit"]["t_total_ms"] / 1e3,
+                   "explicit_forming_ms": res["explicit"]["t_layout_ms"],
+                   "lazy_matvec_ms": res["lazy"]["t_matvec_ms"] / m,
+                   "explicit_matvec_ms": res["explicit"]["t_matvec_ms"] / m,
+                   "speedup": res["lazy"]["t_total_ms"] / res["explicit"]["t_total_ms"],
+                   "auto_explicit": bool(res["auto"]["explicit_operator"]),
+                   "E_lazy": res["lazy"]["logneg"], "E_explicit": res["explicit"]["logneg"],
+                   "E_difference": res["explicit"]["logneg"] - res["lazy"]["logneg"]}
+            rows.append(row)
+            print(f"[operator_forms] {name} {prec}: lazy {row['lazy_s']:.4f} s, explicit {row['explicit_s']:.4f} s "
+                  f"(forming {row['explicit_forming_ms']:.2f} ms), auto explicit = {row['auto_explicit']}, "
+                  f"dE = {row['E_difference']:.2e}", file=sys.stderr, flush=True)
+            del psi
+            torch.cuda.empty_cache()
+    return {"workload": "Haar states, lazy vs explicit rho^{T_B}", "rows": rows}
+
+
 def _parse_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -202,11 +248,14 @@ def main(argv=None):
     sc.add_argument("--precision", default="bf16x3")
     sub.add_parser("heldout26")
     sub.add_parser("hbm_sweep")
+    sub.add_parser("operator_forms")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
+    elif args.cmd == "operator_forms":
+        out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
         out = run_hbm_sweep()
     elif args.cmd == "entropy30":
