@@ -142,6 +142,21 @@ typedef struct {
  *                be > TNSLQ_FIT_MIN_POINTS).
  *   operator_form
  *                how rho^{T_B} is applied (TNSLQ_OPERATOR_*, above).
+ *   max_probes   0 or <= n_probes: one block of n_probes probes, as above.
+ *                > n_probes (needs stop_rule = TNSLQ_STOP_FIT and
+ *                stop_tol > 0): Algorithm 1's outer loop over probes, in
+ *                blocks of n_probes.  Block b uses probe offsets
+ *                probe_offset + b n_probes and runs Lanczos steps until its
+ *                own Lanczos error meets the target (lanczos_converged:
+ *                eps_L / (T ln 2) <= stop_tol max(|E|, 1) on the block's
+ *                fitted estimate, checked from step TNSLQ_FIT_MIN_POINTS + 1,
+ *                else n_steps); its fitted G_n and sigma_n join those of the
+ *                earlier blocks.  Blocks are added until the estimate over all
+ *                probes so far meets the combined target of stop_rule
+ *                TNSLQ_STOP_FIT (hutchinson_converged) or the next block would
+ *                pass max_probes.  psi is regrouped once.  Only G_host (room
+ *                for max_probes values, filled for the probes used) may be
+ *                non-NULL among the optional outputs.
  */
 typedef struct {
     int n_probes;
@@ -153,6 +168,7 @@ typedef struct {
     double stop_tol;
     int stop_rule;
     int operator_form;      /* TNSLQ_OPERATOR_AUTO / _LAZY / _EXPLICIT        */
+    int max_probes;         /* > n_probes: Algorithm 1's loop over probes     */
 } tnslq_options;
 
 typedef struct {
@@ -185,6 +201,8 @@ typedef struct {
                                then never exchanged, t_contract1_ms is 0 and
                                t_contract2_ms times the dense products; the
                                forming is part of t_layout_ms                  */
+    int n_probes_used;      /* probes behind the estimate (n_probes, or a
+                               multiple of it with max_probes)                 */
 } tnslq_result;
 
 /* ------------------------------------------------------------ utilities */

@@ -144,3 +144,59 @@ def fit_stop_step(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float
         if np.isfinite(s["logneg_err"]) and s["logneg_err"] <= tol * max(abs(s["logneg"]), 1.0):
             return k
     return m
+
+
+def block_lanczos_stop_step(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float) -> int:
+    """lanczos_converged for a block of probes: the first step k >=
+    FIT_MIN_POINTS + 1 whose Lanczos error alone meets the target,
+    eps_L / (T ln 2) <= tol max(|E|, 1), else the last step."""
+    m = F.shape[1]
+    for k in range(FIT_MIN_POINTS + 1, m + 1):
+        s = fit_stats(F, alpha, beta, k)
+        lerr = s["lanczos_err"] / (s["trace_norm"] * np.log(2.0))
+        if np.isfinite(lerr) and lerr <= tol * max(abs(s["logneg"]), 1.0):
+            return k
+    return m
+
+
+def combined_stats(G: np.ndarray, S: np.ndarray) -> Dict[str, float]:
+    """Estimate over all probes so far from their fitted G_n and Lanczos
+    errors S_n = beta_1^2 sigma_n: T = mean G, SE (N - 1 variance),
+    eps_L = mean S, E = log2 T, dE = sqrt(SE^2 + eps_L^2) / (T ln 2); with a
+    single probe the Hutchinson error is unknown and dE is infinite."""
+    G = np.asarray(G, dtype=np.float64)
+    S = np.asarray(S, dtype=np.float64)
+    N = G.size
+    T = float(np.mean(G))
+    se = float(np.std(G, ddof=1) / np.sqrt(N)) if N > 1 else float("nan")
+    eps_l = float(np.mean(S))
+    de = float(np.sqrt(se * se + eps_l * eps_l) / (T * np.log(2.0))) if N > 1 else float("inf")
+    return {"trace_norm": T, "trace_norm_se": se, "lanczos_err": eps_l, "logneg": float(np.log2(T)),
+            "logneg_err": de}
+
+
+def probe_loop(block, n_probes: int, max_probes: int, tol: float) -> Dict[str, object]:
+    """Algorithm 1's outer loop over probes, in blocks of n_probes: block b
+    (block(b) -> its quadrature trajectories F, alpha, beta, with probe
+    offsets b n_probes) runs until its own Lanczos error meets the target
+    (block_lanczos_stop_step); its fitted G_n and S_n = beta_1^2 sigma_n join
+    the earlier blocks'.  Blocks are added until the estimate over all probes
+    meets dE <= tol max(|E|, 1) (hutchinson_converged) or the next block would
+    pass max_probes."""
+    G, S, stops = [], [], []
+    b = 0
+    while True:
+        F, alpha, beta = block(b)
+        k = block_lanczos_stop_step(F, alpha, beta, tol)
+        st = fit_stats(F, alpha, beta, k)
+        G.extend(st["G"])
+        S.extend(st["sigma"])
+        stops.append(k)
+        c = combined_stats(np.array(G), np.array(S))
+        if np.isfinite(c["logneg_err"]) and c["logneg_err"] <= tol * max(abs(c["logneg"]), 1.0):
+            break
+        if (b + 2) * n_probes > max_probes:
+            break
+        b += 1
+    c.update({"G": np.array(G), "S": np.array(S), "stops": stops, "n_probes_used": len(G)})
+    return c

@@ -44,7 +44,8 @@ class Partition(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
-                ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int), ("operator_form", ctypes.c_int)]
+                ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int), ("operator_form", ctypes.c_int),
+                ("max_probes", ctypes.c_int)]
 
 
 class SpectralResult(ctypes.Structure):
@@ -64,7 +65,8 @@ class Result(ctypes.Structure):
                 ("t_layout_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
                 ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
                 ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
-                ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int), ("explicit_operator", ctypes.c_int)]
+                ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int), ("explicit_operator", ctypes.c_int),
+                ("n_probes_used", ctypes.c_int)]
 
     def as_dict(self) -> Dict[str, float]:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -195,9 +197,10 @@ def _operator(operator) -> int:
 
 
 def make_options(n_probes: int, n_steps: int, reorth: bool = False, precision="fp32", seed: int = 0,
-                 probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff", operator="auto") -> Options:
+                 probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff", operator="auto",
+                 max_probes: int = 0) -> Options:
     return Options(int(n_probes), int(n_steps), int(bool(reorth)), _prec(precision), int(seed) & (2**64 - 1),
-                   int(probe_offset), float(stop_tol), _rule(stop_rule), _operator(operator))
+                   int(probe_offset), float(stop_tol), _rule(stop_rule), _operator(operator), int(max_probes))
 
 
 def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int:
@@ -211,14 +214,32 @@ def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int
 # ------------------------------------------------------------- logneg
 def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
                  seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
-                 want_arrays: bool = True, stop_rule="diff", operator="auto") -> Dict[str, object]:
-    """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``."""
+                 want_arrays: bool = True, stop_rule="diff", operator="auto", max_probes: int = 0) -> Dict[str, object]:
+    """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``.
+
+    With ``max_probes`` > ``n_probes`` (fit rule, ``stop_tol`` > 0) blocks of
+    ``n_probes`` probes are added until the estimate meets the target; only
+    ``G`` (one value per probe used) is returned among the arrays."""
     import numpy as np
     _check_device_tensor(psi, "psi")
     if psi.numel() != 1 << n_qubits:
         raise ValueError("psi has the wrong length")
     dt = _dtype_code(psi)
-    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator,
+                        max_probes)
+    if max_probes > n_probes:
+        p = _partition(n_qubits, a, b)
+        ws = _workspace(tnslq_workspace_bytes(dt, n_qubits, a, b, opts), psi.device, workspace)
+        res = Result()
+        G = np.zeros(max_probes)
+        rc = lib().tnslq_logneg(_ptr(psi), dt, ctypes.byref(p), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                _stream(stream), ctypes.byref(res), G.ctypes.data_as(ctypes.c_void_p), None, None,
+                                None, None)
+        _check(rc, "tnslq_logneg")
+        out: Dict[str, object] = res.as_dict()
+        out["G"] = G[:res.n_probes_used].copy()
+        out["workspace_bytes"] = ws.numel()
+        return out
     p = _partition(n_qubits, a, b)
     need = tnslq_workspace_bytes(dt, n_qubits, a, b, opts)
     ws = _workspace(need, psi.device, workspace)

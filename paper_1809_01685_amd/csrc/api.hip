@@ -644,6 +644,7 @@ int trivial(const tnslq_options *opt, tnslq_result *res, double *G, double *alph
     zero_result(res);
     res->trace_norm = 1.0;
     const int K = opt->n_probes, m = opt->n_steps;
+    res->n_probes_used = K;
     if (G) std::fill(G, G + K, 1.0);
     if (alpha) std::fill(alpha, alpha + (size_t)K * m, 0.0);
     if (beta) std::fill(beta, beta + (size_t)K * (m + 1), 0.0);
@@ -663,6 +664,9 @@ int check_options(const tnslq_options *opt) {
         return fail(TNSLQ_E_ARG, "stop_rule %d unknown", opt->stop_rule);
     if (opt->operator_form < TNSLQ_OPERATOR_AUTO || opt->operator_form > TNSLQ_OPERATOR_EXPLICIT)
         return fail(TNSLQ_E_ARG, "operator_form %d unknown", opt->operator_form);
+    if (opt->max_probes < 0) return fail(TNSLQ_E_ARG, "max_probes must be >= 0");
+    if (opt->max_probes > opt->n_probes && (opt->stop_rule != TNSLQ_STOP_FIT || !(opt->stop_tol > 0.0)))
+        return fail(TNSLQ_E_ARG, "the loop over probes (max_probes > n_probes) needs the fit rule and stop_tol > 0");
     if (opt->stop_rule == TNSLQ_STOP_FIT && opt->n_steps < TNSLQ_FIT_MIN_POINTS + 1)
         return fail(TNSLQ_E_ARG, "the fit rule needs n_steps >= %d", TNSLQ_FIT_MIN_POINTS + 1);
     return check_prec(opt->precision);
@@ -726,8 +730,9 @@ int fit_step(Run &r, int j, double *G) {
 }
 
 // Steps jdone+1 .. jmax; with stop_tol > 0 stops at the first step meeting the
-// precision target under the run's stopping rule.
-int run_steps(Run &r, int jmax, double stop_tol) {
+// precision target under the run's stopping rule (for the fit rule with
+// lanczos_only, on the Lanczos part of the error alone).
+int run_steps(Run &r, int jmax, double stop_tol, bool lanczos_only = false) {
     int rc;
     for (int j = r.jdone + 1; j <= jmax; ++j) {
         if ((rc = lanczos_step(r.c, j, &r.se[j]))) return rc;
@@ -738,7 +743,9 @@ int run_steps(Run &r, int jmax, double stop_tol) {
             double o[6];
             TNSLQ_HIP(hipMemcpyAsync(o, r.c.fitout, sizeof o, hipMemcpyDeviceToHost, r.c.st));
             TNSLQ_HIP(hipStreamSynchronize(r.c.st));
-            if (std::isfinite(o[3]) && std::isfinite(o[4]) && o[4] <= stop_tol * std::max(std::fabs(o[3]), 1.0)) break;
+            // lanczos_only: the block's Lanczos error alone, eps_L / (T ln 2)
+            const double err = lanczos_only ? o[2] / (o[0] * std::log(2.0)) : o[4];
+            if (std::isfinite(o[3]) && std::isfinite(err) && err <= stop_tol * std::max(std::fabs(o[3]), 1.0)) break;
         } else if (r.rule == TNSLQ_STOP_DIFF && j >= 6) {
             if ((rc = quad_stats(r.c, j, j - 5, j, j - 5, nullptr))) return rc;
             TNSLQ_HIP(launch_stats(r.c.beta, r.c.F, r.c.pl.K, r.c.pl.m, j, nullptr, r.c.stats, r.c.st));
@@ -804,6 +811,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     res->swapped_ab = pl.swapped;
     res->streamed = pl.stream;
     res->explicit_operator = pl.expl;
+    res->n_probes_used = pl.K;
     res->n_matvecs = r.jdone;
     res->n_contract_launches = c.n_launch;
     res->t_layout_ms = elapsed(r.e_start, r.e_layout);
@@ -1124,6 +1132,104 @@ int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_op
     return TNSLQ_OK;
 }
 
+namespace {
+// Algorithm 1's outer loop over probes (Sec. III), in blocks of K probes on
+// one regrouped psi: each block runs until its Lanczos error meets the
+// target (lanczos_converged), its fitted G_n and errors beta_1^2 sigma_n join
+// those of the earlier blocks, and blocks are added until the estimate over
+// all of them meets the combined target (hutchinson_converged with the
+// Lanczos part added in quadrature) or the next block would pass max_probes.
+// The block's estimates come from the device; their mean and spread over the
+// few hundred probes at most are summed here.
+int run_probe_loop(Run &r, const tnslq_options *opt, tnslq_result *res, double *G_host, const Timer &tm) {
+    Ctx &c = r.c;
+    const Plan &pl = c.pl;
+    const int K = pl.K;
+    const double ln2 = std::log(2.0), b1sq = (double)pl.dAB;   // ||phi||^2 of a unit-modulus probe
+    std::vector<double> Gall, Sall, g(K), sg(K);
+    std::vector<int> hsteps(K);
+    int steps_min = pl.m, jmax = 0, nmv = 0;
+    double tmv = 0.0, tc1 = 0.0, tc2 = 0.0, tlz = 0.0;
+    double T = 0.0, se = std::nan(""), epsl = 0.0, E = std::nan(""), de = INFINITY;
+    int rc;
+    for (int b = 0;; ++b) {
+        if (b > 0) {
+            // the next block: fresh probes on the same regrouped psi
+            TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)K * pl.m * 8, c.st));
+            TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)K * (pl.m + 1) * 8, c.st));
+            TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)K * pl.m * 8, c.st));
+            TNSLQ_HIP(launch_probe_init(pl.prec, c.z, opt->seed, opt->probe_offset + (uint64_t)b * K, pl.swapped,
+                                        c.Q, pl.stream ? nullptr : c.Xt, pl.nst1, c.alpha, c.beta, c.st));
+            r.jdone = 0;
+        }
+        if ((rc = run_steps(r, opt->n_steps, opt->stop_tol, true))) return rc;
+        if ((rc = fit_step(r, r.jdone, c.G))) return rc;
+        TNSLQ_HIP(hipMemcpyAsync(g.data(), c.G, sizeof(double) * K, hipMemcpyDeviceToHost, c.st));
+        TNSLQ_HIP(hipMemcpyAsync(sg.data(), c.fsig, sizeof(double) * K, hipMemcpyDeviceToHost, c.st));
+        TNSLQ_HIP(hipMemcpyAsync(hsteps.data(), c.steps, sizeof(int) * K, hipMemcpyDeviceToHost, c.st));
+        TNSLQ_HIP(hipStreamSynchronize(c.st));
+        for (int j = 1; j <= r.jdone; ++j) {
+            const StepEvents &e = r.se[j];
+            tmv += elapsed(e.mv0(), e.mv1());
+            for (int ch = 0; ch < e.nchunk; ++ch) {
+                tc1 += elapsed(ch == 0 ? e.mv0() : e.pa(ch - 1), e.c1(ch));
+                tc2 += elapsed(e.c1(ch), e.c2(ch));
+            }
+            tlz += elapsed(e.mv1(), e.lz1());
+        }
+        nmv += r.jdone;
+        jmax = std::max(jmax, r.jdone);
+        for (int k = 0; k < K; ++k) {
+            Gall.push_back(g[k]);
+            Sall.push_back(b1sq * sg[k]);
+            steps_min = std::min(steps_min, hsteps[k]);
+        }
+        const double N = (double)Gall.size();
+        T = 0.0;
+        epsl = 0.0;
+        for (size_t i = 0; i < Gall.size(); ++i) {
+            T += Gall[i];
+            epsl += Sall[i];
+        }
+        T /= N;
+        epsl /= N;
+        if (Gall.size() > 1) {
+            double v = 0.0;
+            for (double x : Gall) v += (x - T) * (x - T);
+            se = std::sqrt(v / (N - 1.0) / N);
+            de = std::sqrt(se * se + epsl * epsl) / (T * ln2);
+        }
+        E = std::log2(T);
+        if (std::isfinite(E) && std::isfinite(de) && de <= opt->stop_tol * std::max(std::fabs(E), 1.0)) break;
+        if ((int64_t)(b + 2) * K > opt->max_probes) break;
+    }
+    zero_result(res);
+    res->trace_norm = T;
+    res->trace_norm_se = se;
+    res->logneg = E;
+    res->logneg_se = se / (T * ln2);
+    res->lanczos_err = epsl / (T * ln2);
+    res->steps_done = jmax;
+    res->steps_min = steps_min;
+    res->swapped_ab = pl.swapped;
+    res->streamed = pl.stream;
+    res->explicit_operator = pl.expl;
+    res->n_probes_used = (int)Gall.size();
+    res->n_matvecs = nmv;
+    res->n_contract_launches = c.n_launch;
+    res->t_layout_ms = elapsed(r.e_start, r.e_layout);
+    res->t_matvec_ms = tmv;
+    res->t_contract1_ms = tc1;
+    res->t_contract2_ms = tc2;
+    res->t_lanczos_ms = tlz;
+    if (G_host) std::copy(Gall.begin(), Gall.end(), G_host);
+    res->t_total_ms = tm.ms();
+    if (!std::isfinite(res->logneg))
+        return fail(TNSLQ_E_NONFINITE, "estimate is not finite (trace norm %g)", res->trace_norm);
+    return TNSLQ_OK;
+}
+}  // namespace
+
 int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part, const tnslq_options *opt, void *ws_dev,
                  size_t ws_bytes, void *stream, tnslq_result *res, double *G_host, double *alpha_host,
                  double *beta_host, double *F_host, int *steps_host) {
@@ -1134,8 +1240,12 @@ int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part, co
     if ((rc = check_options(opt))) return rc;
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
     if (part->n_a == 0 || part->n_b == 0) return trivial(opt, res, G_host, alpha_host, beta_host, F_host, steps_host);
+    const bool loop = opt->max_probes > opt->n_probes;
+    if (loop && (alpha_host || beta_host || F_host || steps_host))
+        return fail(TNSLQ_E_ARG, "with max_probes > n_probes only G_host may be requested");
     Run r;
     if ((rc = run_begin(r, dtype, part, opt, psi_dev, ws_dev, ws_bytes, stream))) return rc;
+    if (loop) return run_probe_loop(r, opt, res, G_host, tm);
     if ((rc = run_steps(r, opt->n_steps, opt->stop_tol))) return rc;
     return run_finish(r, res, G_host, alpha_host, beta_host, F_host, steps_host, tm);
 }
@@ -1385,6 +1495,7 @@ int tnslq_logneg_surrogate(const void *psi_dev, int dtype, const tnslq_partition
     if (!res || !info || !params || !norm) return fail(TNSLQ_E_ARG, "NULL pointer");
     if ((rc = check_options(opt))) return rc;
     if (early_steps != 8) return fail(TNSLQ_E_ARG, "early_steps must be 8 (network input width)");
+    if (opt->max_probes > opt->n_probes) return fail(TNSLQ_E_ARG, "the surrogate runs one block of probes");
     if (opt->n_steps < early_steps) return fail(TNSLQ_E_ARG, "n_steps must be >= early_steps");
     if (!(tol > 0.0)) return fail(TNSLQ_E_ARG, "tol must be > 0");
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;

@@ -109,7 +109,10 @@ def test_bad_options_rejected(L):
     p = T._partition(6, [0], [1])
     n = ctypes.c_size_t(0)
     for o in (T.make_options(0, 4), T.make_options(4, 0), T.make_options(4, 500), T.make_options(4, 4, precision=9),
-              T.make_options(4, 4, stop_rule=7), T.make_options(4, 5, stop_rule="fit")):
+              T.make_options(4, 4, stop_rule=7), T.make_options(4, 5, stop_rule="fit"),
+              T.make_options(4, 8, stop_tol=0.01, max_probes=-1),
+              T.make_options(4, 8, stop_tol=0.01, stop_rule="diff", max_probes=16),
+              T.make_options(4, 8, stop_tol=0.0, stop_rule="fit", max_probes=16)):
         rc = L.tnslq_workspace_bytes(0, ctypes.byref(p), ctypes.byref(o), ctypes.byref(n))
         assert rc == -1
     assert L.tnslq_workspace_bytes(7, ctypes.byref(p), ctypes.byref(T.make_options(4, 4)), ctypes.byref(n)) == -3

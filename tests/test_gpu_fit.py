@@ -83,3 +83,46 @@ def test_breakdown_gives_exact_fit(dev):
     r = T.tnslq_logneg(psi_t, L, [0, 1, 2], [5, 6, 7], 4, 8, precision="fp64", seed=0, stop_rule="fit")
     assert r["logneg"] == pytest.approx(1.0, abs=1e-12)
     assert r["lanczos_err"] == 0.0
+
+
+def _oracle_blocks(psi, L, a, b, K, m, seed):
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    n = P.shape[0] * P.shape[1]
+
+    def block(bi):
+        X = probes.rademacher_probes(seed, K, n, bi * K)
+        o = slq.slq(lambda v: R @ v, X, m)
+        return o["F"], o["alpha"], o["beta"]
+    return block
+
+
+@pytest.mark.parametrize("operator", ["lazy", "explicit"])
+def test_probe_loop_matches_oracle(dev, operator):
+    # Algorithm 1's outer loop in blocks of 8 probes: the device adds the same
+    # number of blocks as the oracle replaying the rule on the same probes
+    import torch
+    L, a, b = 12, [0, 1, 2, 3], [6, 7, 8, 9]
+    psi = ti.haar_state(L, 1)
+    g = T.tnslq_logneg(torch.from_numpy(psi).to(dev), L, a, b, 8, 30, precision="fp64", seed=3, stop_tol=0.01,
+                       stop_rule="fit", operator=operator, max_probes=256)
+    o = lf.probe_loop(_oracle_blocks(psi, L, a, b, 8, 30, 3), 8, 256, 0.01)
+    assert g["n_probes_used"] == o["n_probes_used"] == 16
+    assert np.allclose(g["G"], o["G"], rtol=1e-7, atol=0)
+    assert g["logneg"] == pytest.approx(o["logneg"], rel=1e-7)
+    assert g["steps_done"] == max(o["stops"])
+    dE = np.hypot(g["logneg_se"], g["lanczos_err"])
+    assert dE == pytest.approx(o["logneg_err"], rel=1e-4)
+    assert dE <= 0.01 * max(abs(g["logneg"]), 1.0)
+
+
+def test_probe_loop_keeps_to_the_budget(dev):
+    import torch
+    L, a, b = 12, [0, 1, 2, 3], [6, 7, 8, 9]
+    psi_t = torch.from_numpy(ti.haar_state(L, 1)).to(dev)
+    g = T.tnslq_logneg(psi_t, L, a, b, 8, 12, precision="fp64", seed=3, stop_tol=1e-6, stop_rule="fit",
+                       max_probes=20)
+    assert g["n_probes_used"] == 16 and len(g["G"]) == 16
+    # the same first block as a single-block run on the same probes
+    one = T.tnslq_logneg(psi_t, L, a, b, 8, 12, precision="fp64", seed=3, stop_tol=0, stop_rule="fit")
+    assert np.allclose(g["G"][:8], one["G"], rtol=1e-12, atol=0)

@@ -139,3 +139,73 @@ def test_window_leaves_out_the_one_node_rule():
 def test_too_few_points_is_an_error():
     with pytest.raises(ValueError):
         lf.exponential_fit(np.ones(4))
+
+
+# ------------------------------------------------------------ loop over probes
+def _blocks(psi, L, a, b, K, m, seed):
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    n = P.shape[0] * P.shape[1]
+    cache = {}
+
+    def block(bi):
+        if bi not in cache:
+            X = probes.rademacher_probes(seed, K, n, bi * K)
+            o = slq.slq(lambda v: R @ v, X, m)
+            cache[bi] = (o["F"], o["alpha"], o["beta"])
+        return cache[bi]
+    return block, exact.logneg_exact(P)
+
+
+def test_combined_error_is_the_standard_error_of_the_mean():
+    import scipy.stats
+    rng = np.random.default_rng(4)
+    G = 3.0 + 0.2 * rng.standard_normal(24)
+    c = lf.combined_stats(G, np.zeros(24))
+    assert c["trace_norm_se"] == pytest.approx(float(scipy.stats.sem(G)), rel=1e-12)
+    assert c["logneg"] == pytest.approx(np.log2(np.mean(G)), rel=1e-14)
+    # with a Lanczos part the errors add in quadrature
+    c2 = lf.combined_stats(G, np.full(24, 0.05))
+    assert c2["logneg_err"] == pytest.approx(np.hypot(scipy.stats.sem(G), 0.05) / (np.mean(G) * np.log(2.0)),
+                                             rel=1e-12)
+    # one probe: the Hutchinson error is unknown, never converged
+    assert lf.combined_stats(G[:1], np.zeros(1))["logneg_err"] == np.inf
+
+
+def test_block_lanczos_stop_comes_no_later_than_the_combined_rule():
+    L, a, b = 14, list(range(4, 9)), list(range(9, 14))
+    block, _ = _blocks(ti.haar_state(L, 2), L, a, b, 4, 30, 7)
+    F, al, be = block(0)
+    assert lf.block_lanczos_stop_step(F, al, be, 0.01) <= lf.fit_stop_step(F, al, be, 0.01)
+
+
+def test_probe_loop_stops_at_the_first_block_count_meeting_the_target():
+    # blocks of 8 probes (the first Hutchinson check sees 8 samples): this
+    # state needs two; replaying every prefix of blocks by brute force finds
+    # the same count
+    L, a, b = 12, [0, 1, 2, 3], [6, 7, 8, 9]
+    block, e_exact = _blocks(ti.haar_state(L, 1), L, a, b, 8, 30, 3)
+    tol = 0.01
+    r = lf.probe_loop(block, 8, 256, tol)
+    G, S, first = [], [], None
+    for bi in range(32):
+        F, al, be = block(bi)
+        st = lf.fit_stats(F, al, be, lf.block_lanczos_stop_step(F, al, be, tol))
+        G.extend(st["G"])
+        S.extend(st["sigma"])
+        c = lf.combined_stats(np.array(G), np.array(S))
+        if c["logneg_err"] <= tol * max(abs(c["logneg"]), 1.0):
+            first = bi + 1
+            break
+    assert first is not None and r["n_probes_used"] == 8 * first > 8
+    assert r["logneg"] == pytest.approx(lf.combined_stats(np.array(G), np.array(S))["logneg"], rel=1e-14)
+    # and the estimate is within its stated error of the exact value
+    assert abs(r["logneg"] - e_exact) <= 3 * r["logneg_err"]
+
+
+def test_probe_loop_respects_the_probe_budget():
+    L, a, b = 12, [0, 1, 2, 3], [6, 7, 8, 9]
+    block, _ = _blocks(ti.haar_state(L, 1), L, a, b, 4, 24, 3)
+    r = lf.probe_loop(block, 4, 11, 1e-6)   # unreachable target: 2 blocks fit in 11 probes
+    assert r["n_probes_used"] == 8 and len(r["stops"]) == 2
+    assert r["logneg_err"] > 1e-6
