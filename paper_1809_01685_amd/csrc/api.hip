@@ -233,6 +233,8 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         pl.off_Up = take((size_t)pl.S1s * nv * ncol * 16);
         pl.off_U2 = take((size_t)nv * ncol * 16);
         pl.off_Ypart = take((size_t)pl.S2s * K * n * 16);
+        pl.off_Xq = take((size_t)K * n * 16);
+        pl.off_Ym = take((size_t)K * n * 16);
         if (!lanczos) pl.off_Xs = take((size_t)K * n * 16);
     } else {
         pl.off_Paeb = take(brick_bytes(prec, pl.dA, pl.dE * pl.dB));
@@ -286,6 +288,29 @@ PermDesc perm_two(int L, const int *hi, int n_hi, const int *lo, int n_lo) {
     return pd;
 }
 
+// Column MAC over an R x C matrix with K plain vectors V[k][i] and output
+// out[s][k][c].
+ColmacDesc plain_colmac(const void *M, int64_t R, int64_t C, const double2 *V, int K, double2 *out, int S) {
+    ColmacDesc g{};
+    g.M = M;
+    g.R = R;
+    g.C = C;
+    g.V = V;
+    g.NV = K;
+    g.vsh = 0;
+    g.vs1 = R;
+    g.vs2 = 0;
+    g.vsi = 1;
+    g.out = out;
+    g.osplit = (int64_t)K * C;
+    g.osh = 0;
+    g.os1 = C;
+    g.os2 = 0;
+    g.osc = 1;
+    g.S = S;
+    return g;
+}
+
 struct Ctx {
     Plan pl;
     char *ws;
@@ -294,7 +319,7 @@ struct Ctx {
     void *Paeb, *Pbea, *Xt, *Ups, *Ypart, *U1part;
     void *P1s, *P2s;
     void *Pabe, *Pabc, *Cd, *rho;
-    double2 *Up, *U2, *Xs;
+    double2 *Up, *U2, *Xs, *Xq, *Ym;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -330,6 +355,8 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Up = (double2 *)(c.ws + pl.off_Up);
     c.U2 = (double2 *)(c.ws + pl.off_U2);
     c.Xs = (double2 *)(c.ws + pl.off_Xs);
+    c.Xq = (double2 *)(c.ws + pl.off_Xq);
+    c.Ym = (double2 *)(c.ws + pl.off_Ym);
     if (pl.stream) c.Paeb = c.Pbea = c.Xt = c.Ups = nullptr;
     c.Pabe = pl.expl ? c.ws + pl.off_Pabe : nullptr;
     c.Pabc = pl.expl ? c.ws + pl.off_Pabc : nullptr;
@@ -425,51 +452,24 @@ int do_layout(Ctx &c, const void *psi) {
 
 // The streaming form of both contractions for all K probes (Sec. V Eq. 4,
 // intermediary (i)), from FP64 vectors xq[k][a dB + b]:
-//   Up[s][(k, b')][(c, b)] = sum_{a' in split s} conj psi[a', c, b] xq[k][a' dB + b']
+//   Xq[(k, b')][a']        = xq[k][a' dB + b']
+//   Up[s][(k, b')][(c, b)] = sum_{a' in split s} conj psi[a', c, b] Xq[(k, b')][a']
 //   U2[(k, b)][(c, b')]    = sum_s Up[s][(k, b')][(c, b)]
-//   Ypart[s][k][a dB + b]  = sum_{(c, b') in split s} psi[a, c, b'] U2[(k, b)][(c, b')]
+//   Yt[s][(k, b)][a]       = sum_{(c, b') in split s} psi[a, c, b'] U2[(k, b)][(c, b')]
+//   Ym[k][a dB + b]        = sum_s Yt[s][(k, b)][a]
+// Both passes read their vectors and write their outputs contiguously, the
+// column MAC's plain form.
 int stream_contract(Ctx &c, const double2 *xq, hipEvent_t e1, hipEvent_t e2) {
     const Plan &pl = c.pl;
-    const int64_t n = pl.dAB, ncol = pl.dE * pl.dB;
+    const int64_t ncol = pl.dE * pl.dB;
     const int nv = pl.K * (int)pl.dB;
-    ColmacDesc g1{};
-    g1.M = c.P1s;
-    g1.R = pl.dA;
-    g1.C = ncol;
-    g1.V = xq;
-    g1.NV = nv;
-    g1.vsh = pl.nB;
-    g1.vs1 = n;
-    g1.vs2 = 1;
-    g1.vsi = pl.dB;
-    g1.out = c.Up;
-    g1.osplit = (int64_t)nv * ncol;
-    g1.osh = 0;
-    g1.os1 = ncol;
-    g1.os2 = 0;
-    g1.osc = 1;
-    g1.S = pl.S1s;
-    TNSLQ_HIP(launch_colmac(pl.dtype, 1, g1, c.st));
+    TNSLQ_HIP(launch_vectors_by_b(xq, pl.K, pl.dA, pl.nB, c.Xq, c.st));
+    TNSLQ_HIP(launch_colmac(pl.dtype, 1, plain_colmac(c.P1s, pl.dA, ncol, c.Xq, nv, c.Up, pl.S1s), c.st));
     TNSLQ_HIP(launch_sum_transpose_ups(c.Up, pl.S1s, pl.K, pl.nB, pl.nE, c.U2, c.st));
     if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
-    ColmacDesc g2{};
-    g2.M = c.P2s;
-    g2.R = ncol;
-    g2.C = pl.dA;
-    g2.V = c.U2;
-    g2.NV = nv;
-    g2.vsh = 0;
-    g2.vs1 = ncol;
-    g2.vs2 = 0;
-    g2.vsi = 1;
-    g2.out = (double2 *)c.Ypart;
-    g2.osplit = (int64_t)pl.K * n;
-    g2.osh = pl.nB;
-    g2.os1 = n;
-    g2.os2 = 1;
-    g2.osc = pl.dB;
-    g2.S = pl.S2s;
-    TNSLQ_HIP(launch_colmac(pl.dtype, 0, g2, c.st));
+    double2 *Yt = (double2 *)c.Ypart;
+    TNSLQ_HIP(launch_colmac(pl.dtype, 0, plain_colmac(c.P2s, ncol, pl.dA, c.U2, nv, Yt, pl.S2s), c.st));
+    TNSLQ_HIP(launch_sum_transpose_y(Yt, pl.S2s, pl.K, pl.dA, pl.nB, c.Ym, c.st));
     if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
     c.n_launch++;
     return TNSLQ_OK;
@@ -592,8 +592,10 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
         } else if ((rc = contract_chunk(c, k0, kcur, se->c1(ch), se->c2(ch)))) {
             return rc;
         }
-        TNSLQ_HIP(launch_passA(accfp64, c.z, c.Ypart, pl.S, (int64_t)pl.kc * n, k0, kcur, q_prev, q_cur, c.w,
-                               c.alpha, c.beta, j, c.dotpart, c.st));
+        // the streaming passes leave Y already summed over their splits
+        TNSLQ_HIP(launch_passA(accfp64, c.z, pl.stream ? (const void *)c.Ym : c.Ypart, pl.stream ? 1 : pl.S,
+                               (int64_t)pl.kc * n, k0, kcur, q_prev, q_cur, c.w, c.alpha, c.beta, j, c.dotpart,
+                               c.st));
         TNSLQ_HIP(hipEventRecord(se->pa(ch), c.st));
     }
     TNSLQ_HIP(hipEventRecord(se->mv1(), c.st));
@@ -844,29 +846,6 @@ struct SPlan {
     size_t off_P1 = 0, off_P2 = 0, off_Zp = 0, off_Z = 0, off_Yp = 0, off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0;
     size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, total = 0;
 };
-
-// Column MAC over an R x C matrix with K plain vectors V[k][i] and output
-// out[s][k][c].
-ColmacDesc plain_colmac(const void *M, int64_t R, int64_t C, const double2 *V, int K, double2 *out, int S) {
-    ColmacDesc g{};
-    g.M = M;
-    g.R = R;
-    g.C = C;
-    g.V = V;
-    g.NV = K;
-    g.vsh = 0;
-    g.vs1 = R;
-    g.vs2 = 0;
-    g.vsi = 1;
-    g.out = out;
-    g.osplit = (int64_t)K * C;
-    g.osh = 0;
-    g.os1 = C;
-    g.os2 = 0;
-    g.osc = 1;
-    g.S = S;
-    return g;
-}
 
 int check_subsystem(int L, const int *s, int n_s) {
     if (L < 1 || L > TNSLQ_MAX_QUBITS) return fail(TNSLQ_E_PARTITION, "n_qubits %d outside [1, %d]", L, TNSLQ_MAX_QUBITS);
@@ -1280,7 +1259,7 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
     if (pl.stream) {
         TNSLQ_HIP(launch_load_vectors_plain((const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xs, c.st));
         if ((rc = stream_contract(c, c.Xs, nullptr, nullptr))) return rc;
-        TNSLQ_HIP(launch_reduce_partials(1, c.Ypart, pl.S2s, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
+        TNSLQ_HIP(launch_reduce_partials(1, c.Ym, 1, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
                                          (double2 *)Y_dev, c.st));
         return TNSLQ_OK;
     }

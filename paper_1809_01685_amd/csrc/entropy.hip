@@ -286,7 +286,53 @@ __global__ void __launch_bounds__(256) k_sum_transpose_ups(const double2 *__rest
     }
 }
 
+// The streaming partial-transpose matvec's first pass takes its vectors over
+// a': Lanczos vectors xq[k][a dB + b] -> Xq[(k, b)][a], K dA dB elements.
+__global__ void __launch_bounds__(256) k_vectors_by_b(const double2 *__restrict__ xq, int64_t total, int64_t dA,
+                                                      int nB, double2 *__restrict__ Xq) {
+    const int64_t dB = int64_t(1) << nB, n = dA * dB;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t a = e % dA, kb = e / dA;
+        Xq[e] = xq[(kb >> nB) * n + a * dB + (kb & (dB - 1))];
+    }
+}
+
+// Its second pass leaves Yt[s][(k, b)][a]; Y[k][a dB + b] = sum_s Yt[s].
+__global__ void __launch_bounds__(256) k_sum_transpose_y(const double2 *__restrict__ Yt, int S, int64_t total,
+                                                         int64_t dA, int nB, double2 *__restrict__ Y) {
+    const int64_t dB = int64_t(1) << nB, n = dA * dB;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t k = e / n, r = e % n;
+        const int64_t src = ((k << nB) + (r & (dB - 1))) * dA + (r >> nB);
+        double x = 0.0, y = 0.0;
+        for (int p = 0; p < S; ++p) {
+            const double2 v = Yt[p * total + src];
+            x += v.x;
+            y += v.y;
+        }
+        Y[e] = make_double2(x, y);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_vectors_by_b(const double2 *xq, int K, int64_t dA, int nB, double2 *Xq, hipStream_t st) {
+    const int64_t total = (int64_t)K * dA * (int64_t(1) << nB);
+    int64_t g = (total + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_vectors_by_b, dim3((unsigned)g), dim3(256), 0, st, xq, total, dA, nB, Xq);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_transpose_y(const double2 *Yt, int S, int K, int64_t dA, int nB, double2 *Y, hipStream_t st) {
+    const int64_t total = (int64_t)K * dA * (int64_t(1) << nB);
+    int64_t g = (total + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_sum_transpose_y, dim3((unsigned)g), dim3(256), 0, st, Yt, S, total, dA, nB, Y);
+    return hipGetLastError();
+}
 
 hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int64_t C, const PermDesc &pd,
                           hipStream_t st) {

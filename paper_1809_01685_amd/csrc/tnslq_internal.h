@@ -48,6 +48,7 @@ struct Plan {
     size_t off_Paeb = 0, off_Pbea = 0, off_Xt = 0, off_Ups = 0, off_Ypart = 0, off_U1part = 0;
     size_t off_P1s = 0, off_P2s = 0, off_Up = 0, off_U2 = 0, off_Xs = 0;
     size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, off_rho = 0;
+    size_t off_Xq = 0, off_Ym = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -154,6 +155,11 @@ hipError_t launch_sum_splits(const double2 *part, int S, int64_t n, double2 *Z, 
 // U2[(k, b)][(c, b')] = sum_s Up[s][(k, b')][(c, b)] for the streaming
 // partial-transpose matvec (K probes, dB = 2^nB, dE = 2^nE).
 hipError_t launch_sum_transpose_ups(const double2 *Up, int S, int K, int nB, int nE, double2 *U2, hipStream_t st);
+// Xq[(k, b)][a] = xq[k][a dB + b] (K probes, dB = 2^nB), the first streaming
+// pass's vectors; and Y[k][a dB + b] = sum_s Yt[s][(k, b)][a], the sum of the
+// second pass's split partials.
+hipError_t launch_vectors_by_b(const double2 *xq, int K, int64_t dA, int nB, double2 *Xq, hipStream_t st);
+hipError_t launch_sum_transpose_y(const double2 *Yt, int S, int K, int64_t dA, int nB, double2 *Y, hipStream_t st);
 // Caller vectors into FP64 layout order Xs[k][a dB + b].
 hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, int K, int swapped, double2 *Xs,
                                      hipStream_t st);

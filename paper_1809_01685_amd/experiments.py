@@ -32,7 +32,14 @@
         with A = 0-6, B = 7-13 (16384, d_E = 1024); wall time per estimate,
         and which form the automatic choice takes.
 
-All print one JSON object.  All arithmetic runs in libtnslq.
+    python -m paper_1809_01685_amd.experiments hbm_peak
+        What HBM bandwidth is reachable on this GPU, as a yardstick for the
+        streaming passes: torch's device-to-device copy of 4 GiB and its sum
+        over 8 GiB of float32 (vendor kernels, timed with events), beside the
+        entropy passes over the 30-qubit state (8 GiB, complex64) at K = 1, 2, 4.
+
+All print one JSON object.  All arithmetic of the method runs in libtnslq
+(hbm_peak times torch's own copy and sum only as a reference).
 """
 from __future__ import annotations
 
@@ -233,6 +240,52 @@ def run_operator_forms(seed=0):
     return {"workload": "Haar states, lazy vs explicit rho^{T_B}", "rows": rows}
 
 
+def run_hbm_peak(reps=10, seed=0):
+    import torch
+    import tnslq_inputs as ti
+    from . import tnslq_spectral_sum
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    n = 1 << 30   # 4 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src))
+    out["copy_4GiB"] = {"ms": ms, "GBps": 2 * 4 * n / (ms * 1e-3) / 1e9}
+    del dst
+    big = torch.ones(2 * n, dtype=torch.float32, device=dev)
+    del src
+    acc = torch.empty((), dtype=torch.float32, device=dev)
+    ms = timed(lambda: torch.sum(big, dim=0, out=acc))
+    out["sum_8GiB_float32"] = {"ms": ms, "GBps": 4 * 2 * n / (ms * 1e-3) / 1e9}
+    del big, acc
+    torch.cuda.empty_cache()
+    L = 30
+    psi = ti.haar_state_torch(L, seed, dev, torch.complex64)
+    for K in (1, 2, 4):
+        tnslq_spectral_sum(psi, L, list(range(15)), "purity", K, 2, seed=seed, want_arrays=False)
+        r = tnslq_spectral_sum(psi, L, list(range(15)), "purity", K, 20, seed=seed, want_arrays=False)
+        ms = r["t_matvec_ms"] / 20
+        out[f"entropy_passes_K{K}"] = {"ms_per_step": ms, "GBps": 2 * 8 * (1 << L) / (ms * 1e-3) / 1e9}
+    del psi
+    torch.cuda.empty_cache()
+    for k, v in out.items():
+        v["frac_of_8TBps"] = v["GBps"] / 8000.0
+        print(f"[hbm_peak] {k}: {v['GBps']:.0f} GB/s ({100 * v['frac_of_8TBps']:.1f}% of 8 TB/s)", file=sys.stderr,
+              flush=True)
+    return {"workload": "HBM yardstick on one MI355X", "rows": out}
+
+
 def _parse_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -249,11 +302,14 @@ def main(argv=None):
     sub.add_parser("heldout26")
     sub.add_parser("hbm_sweep")
     sub.add_parser("operator_forms")
+    sub.add_parser("hbm_peak")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
+    elif args.cmd == "hbm_peak":
+        out = run_hbm_peak()
     elif args.cmd == "operator_forms":
         out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
