@@ -19,6 +19,8 @@
 // splits (grid.y) to fill the chip, their partial sums written separately:
 // the first pass's partials are added by a small kernel before the second
 // pass stages them, the second pass's by the Lanczos kernel that consumes Y.
+#include <type_traits>
+
 #include "tnslq_internal.h"
 
 namespace tnslq {
@@ -61,6 +63,59 @@ __global__ void __launch_bounds__(256) k_regroup(const void *__restrict__ psi, v
             ((double2 *)out)[dst] = ((const double2 *)psi)[in];
         else
             ((float2 *)out)[dst] = ((const float2 *)psi)[in];
+    }
+}
+
+// The same regrouping through LDS tiles, for D >= 2^TB: a tile is the 2^TB
+// elements that share every output bit outside td.wr.  They are read with the
+// input's lowest bits varying fastest (td.rd lists the tile's output bits in
+// that order: a wave reads runs of consecutive psi elements) and written with
+// the output's lowest bits varying fastest (td.wr: runs of consecutive panel
+// elements).  One LDS row of padding per 64 entries keeps the transposed
+// accesses off a single bank.
+struct RegroupTile {
+    int nouter;
+    int outer[TNSLQ_MAX_QUBITS];   // output bits outside the tile, from the tile index
+    int rd[12], wr[12];            // the tile's output bits in read and in write order
+    int rd2wr[12];                 // position of rd[k] in wr
+    int64_t in_rd[12];             // psi index bit of rd[k]
+};
+
+template <int DTYPE, int TB>
+__global__ void __launch_bounds__(256) k_regroup_tiled(const void *__restrict__ psi, void *__restrict__ out,
+                                                       int64_t R, int64_t C, int cl, PermDesc pd, RegroupTile td) {
+    using T = typename std::conditional<DTYPE == TNSLQ_C128, double2, float2>::type;
+    constexpr int TN = 1 << TB;
+    __shared__ T tile[TN + TN / 64];
+    const int64_t ntiles = (R * C) >> TB;
+    const int wl = cl < 9 ? cl : 9;
+    for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+        int64_t ob = 0;
+        for (int k = 0; k < td.nouter; ++k) ob |= ((tl >> k) & 1) << td.outer[k];
+        int64_t ib = 0;
+        for (int t = 0; t < pd.L; ++t) ib |= ((ob >> t) & 1) << pd.map[t];
+        for (int j = threadIdx.x; j < TN; j += 256) {
+            int64_t in = ib;
+            int slot = 0;
+#pragma unroll
+            for (int k = 0; k < TB; ++k) {
+                const int bit = (j >> k) & 1;
+                in |= (int64_t)bit << td.in_rd[k];
+                slot |= bit << td.rd2wr[k];
+            }
+            tile[slot + (slot >> 6)] = ((const T *)psi)[in];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < TN; j += 256) {
+            int64_t o = ob;
+#pragma unroll
+            for (int k = 0; k < TB; ++k) o |= (int64_t)((j >> k) & 1) << td.wr[k];
+            // panel_index with R, C, and the panel width min(C, 512) powers of two
+            const int64_t i = o >> cl, c = o & (C - 1);
+            const int64_t dst = ((c >> wl) * R << wl) + (i << wl) + (c & ((int64_t(1) << wl) - 1));
+            ((T *)out)[dst] = tile[j + (j >> 6)];
+        }
+        __syncthreads();
     }
 }
 
@@ -336,6 +391,54 @@ hipError_t launch_sum_transpose_y(const double2 *Yt, int S, int K, int64_t dA, i
 
 hipError_t launch_regroup(int dtype, const void *psi, void *out, int64_t R, int64_t C, const PermDesc &pd,
                           hipStream_t st) {
+    const int TB = dtype == TNSLQ_C128 ? 11 : 12;   // 33 KiB of LDS either way
+    if (pd.L >= TB) {
+        // the tile: the output's 6 lowest bits, the output bits of psi's
+        // lowest TB - 6 bits, then further output bits up to TB
+        RegroupTile td{};
+        int inv[TNSLQ_MAX_QUBITS];
+        for (int t = 0; t < pd.L; ++t) inv[pd.map[t]] = t;
+        int in_tile[TNSLQ_MAX_QUBITS] = {0};
+        int nu = 0, u[12];
+        auto add = [&](int b) {
+            if (nu < TB && !in_tile[b]) {
+                in_tile[b] = 1;
+                u[nu++] = b;
+            }
+        };
+        for (int b = 0; b < 6; ++b) add(b);
+        for (int b = 0; b < TB - 6; ++b) add(inv[b]);
+        for (int b = 6; b < pd.L && nu < TB; ++b) add(b);
+        // write order: ascending output bits; read order: psi's lowest bits first
+        int nw = 0, nr = 0;
+        for (int b = 0; b < pd.L; ++b)
+            if (in_tile[b]) td.wr[nw++] = b;
+        int used[TNSLQ_MAX_QUBITS] = {0};
+        for (int b = 0; b < pd.L && nr < TB; ++b) {
+            const int ob = inv[b];
+            if (in_tile[ob] && !used[ob]) {
+                used[ob] = 1;
+                td.rd[nr++] = ob;
+            }
+        }
+        for (int k = 0; k < TB; ++k) {
+            for (int w = 0; w < TB; ++w)
+                if (td.wr[w] == td.rd[k]) td.rd2wr[k] = w;
+            td.in_rd[k] = pd.map[td.rd[k]];
+        }
+        td.nouter = 0;
+        for (int b = 0; b < pd.L; ++b)
+            if (!in_tile[b]) td.outer[td.nouter++] = b;
+        int cl = 0;
+        while ((int64_t(1) << cl) < C) ++cl;
+        const int64_t ntiles = (R * C) >> TB;
+        const unsigned g = (unsigned)(ntiles < 65535 * 8 ? ntiles : 65535 * 8);
+        if (dtype == TNSLQ_C128)
+            hipLaunchKernelGGL((k_regroup_tiled<TNSLQ_C128, 11>), dim3(g), dim3(256), 0, st, psi, out, R, C, cl, pd, td);
+        else
+            hipLaunchKernelGGL((k_regroup_tiled<TNSLQ_C64, 12>), dim3(g), dim3(256), 0, st, psi, out, R, C, cl, pd, td);
+        return hipGetLastError();
+    }
     int64_t g = (R * C + 1023) / 1024;
     if (g < 1) g = 1;
     if (g > 65535 * 8) g = 65535 * 8;
