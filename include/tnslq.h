@@ -240,6 +240,35 @@ int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part,
                  tnslq_result *res, double *G_host, double *alpha_host, double *beta_host,
                  double *F_host, int *steps_host);
 
+/* ------------------------------------------ sites of any local dimension */
+
+/* Subsystems of a state on sites of general local dimension (the paper's
+ * method is stated for any d_A, d_B, d_C; Sec. V).  psi's flat index is in
+ * mixed radix over sites 0 .. n_sites-1 with site 0 most significant and
+ * dims[s] >= 2 values at site s (the product at most 2^40).  `a` and `b` list
+ * sites, pairwise distinct and disjoint; C is the other sites in increasing
+ * order.  Index (a, b) of A B runs over A's sites in the order given, then
+ * B's, b fastest. */
+typedef struct {
+    int n_sites;
+    const int *dims;
+    const int *a;
+    int n_a;
+    const int *b;
+    int n_b;
+} tnslq_partition_dims;
+
+/* tnslq_workspace_bytes / tnslq_logneg for such sites.  They use the explicit
+ * operator only (operator_form TNSLQ_OPERATOR_AUTO or _EXPLICIT; _LAZY is an
+ * argument error), so d_A d_B <= 16384; everything else, including the probe
+ * law (element i of probe k from output (probe_offset + k) d_A d_B + i) and
+ * the optional outputs, is as for qubits. */
+int tnslq_workspace_bytes_dims(int dtype, const tnslq_partition_dims *part, const tnslq_options *opt,
+                               size_t *bytes);
+int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims *part, const tnslq_options *opt,
+                      void *ws_dev, size_t ws_bytes, void *stream, tnslq_result *res, double *G_host,
+                      double *alpha_host, double *beta_host, double *F_host, int *steps_host);
+
 /* ------------------------------------------------ partial-transpose matvec */
 
 /* Workspace bytes for tnslq_ptmatvec with n_vectors vectors. */
@@ -270,6 +299,11 @@ int tnslq_rho_pt_workspace_bytes(int dtype, const tnslq_partition *part, size_t 
  * At most d_A d_B = 16384.  Needs non-empty A and B.  Does not synchronise. */
 int tnslq_rho_pt(const void *psi_dev, int dtype, const tnslq_partition *part, void *rho_dev, void *ws_dev,
                  size_t ws_bytes, void *stream);
+
+/* tnslq_rho_pt for sites of general local dimension (above). */
+int tnslq_rho_pt_dims_workspace_bytes(int dtype, const tnslq_partition_dims *part, size_t *bytes);
+int tnslq_rho_pt_dims(const void *psi_dev, int dtype, const tnslq_partition_dims *part, void *rho_dev, void *ws_dev,
+                      size_t ws_bytes, void *stream);
 
 /* ------------------------------------------- other spectral sums (entropy) */
 

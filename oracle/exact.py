@@ -36,6 +36,19 @@ def regroup(psi: np.ndarray, n_qubits: int, a: Sequence[int], b: Sequence[int]) 
     return t.reshape(1 << len(a), 1 << len(b), 1 << len(c))
 
 
+def regroup_dims(psi: np.ndarray, dims: Sequence[int], a: Sequence[int], b: Sequence[int]) -> np.ndarray:
+    """The same for sites of any local dimension: psi's flat index in mixed
+    radix over the sites (site 0 most significant, dims[s] values at site s);
+    P[a, b, c] of shape (d_A, d_B, d_C) with a, b running over the listed sites
+    in the given order and c over the other sites in increasing order."""
+    a, b = list(a), list(b)
+    c = complement(len(dims), a, b)
+    t = np.asarray(psi, dtype=np.complex128).reshape(list(dims))
+    t = np.transpose(t, a + b + c)
+    d = lambda s: int(np.prod([dims[q] for q in s], dtype=np.int64))  # noqa: E731
+    return t.reshape(d(a), d(b), d(c))
+
+
 def rho_ab(P: np.ndarray) -> np.ndarray:
     """rho_AB[(a,b),(a',b')] = sum_c P[a,b,c] conj(P[a',b',c]) (Sec. V, Fig. 2(c))."""
     d_a, d_b, d_c = P.shape

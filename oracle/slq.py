@@ -150,6 +150,15 @@ def slq_logneg(psi: np.ndarray, n_qubits: int, a, b, n_probes: int, n_steps: int
     return slq(mv, X, n_steps, reorth)
 
 
+def slq_logneg_dims(psi: np.ndarray, dims, a, b, n_probes: int, n_steps: int, seed: int, probe_offset: int = 0,
+                    reorth: bool = False) -> Dict[str, object]:
+    """slq_logneg for sites of any local dimension (explicit operator)."""
+    P = exact.regroup_dims(psi, dims, a, b)
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(seed, n_probes, P.shape[0] * P.shape[1], probe_offset)
+    return slq(lambda v: R @ v, X, n_steps, reorth)
+
+
 def lanczos_block_features(alpha: np.ndarray, beta: np.ndarray, d_a: int, d_b: int, d_e: int,
                            n_early: int = 8) -> np.ndarray:
     """The surrogate's 19 inputs: probe means of N*alpha_1..8 and

@@ -41,6 +41,11 @@ class Partition(ctypes.Structure):
                 ("b", ctypes.POINTER(ctypes.c_int)), ("n_b", ctypes.c_int)]
 
 
+class PartitionDims(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int)), ("a", ctypes.POINTER(ctypes.c_int)),
+                ("n_a", ctypes.c_int), ("b", ctypes.POINTER(ctypes.c_int)), ("n_b", ctypes.c_int)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
@@ -84,6 +89,12 @@ _SIGS = {
                           ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
     "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, ctypes.POINTER(_SZ)]),
     "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _VP, _SZ, _VP]),
+    "tnslq_workspace_bytes_dims": (_I, [_I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options),
+                                        ctypes.POINTER(_SZ)]),
+    "tnslq_logneg_dims": (_I, [_VP, _I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options), _VP, _SZ, _VP,
+                               ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
+    "tnslq_rho_pt_dims_workspace_bytes": (_I, [_I, ctypes.POINTER(PartitionDims), ctypes.POINTER(_SZ)]),
+    "tnslq_rho_pt_dims": (_I, [_VP, _I, ctypes.POINTER(PartitionDims), _VP, _VP, _SZ, _VP]),
     "tnslq_rho_pt_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(_SZ)]),
     "tnslq_rho_pt": (_I, [_VP, _I, ctypes.POINTER(Partition), _VP, _VP, _SZ, _VP]),
     "tnslq_quadrature": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
@@ -124,6 +135,15 @@ def _check(rc: int, where: str):
     if rc != TNSLQ_OK:
         detail = lib().tnslq_last_error().decode()
         raise TnslqError(rc, where, detail or lib().tnslq_status_str(rc).decode())
+
+
+def _partition_dims(dims: Sequence[int], a: Sequence[int], b: Sequence[int]):
+    dd = (ctypes.c_int * max(1, len(dims)))(*dims)
+    aa = (ctypes.c_int * max(1, len(a)))(*a)
+    bb = (ctypes.c_int * max(1, len(b)))(*b)
+    p = PartitionDims(len(dims), dd, aa, len(a), bb, len(b))
+    p._keep = (dd, aa, bb)
+    return p
 
 
 def _partition(n_qubits: int, a: Sequence[int], b: Sequence[int]):
@@ -287,6 +307,65 @@ def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None
     _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision), _ptr(ws),
                                 ws.numel(), _stream(stream)), "tnslq_ptmatvec")
     return Y
+
+
+# ------------------------------------------------- sites of any dimension
+def tnslq_workspace_bytes_dims(dtype: int, dims, a, b, opts: Options) -> int:
+    n = ctypes.c_size_t(0)
+    p = _partition_dims(dims, a, b)
+    _check(lib().tnslq_workspace_bytes_dims(int(dtype), ctypes.byref(p), ctypes.byref(opts), ctypes.byref(n)),
+           "tnslq_workspace_bytes_dims")
+    return n.value
+
+
+def tnslq_logneg_dims(psi, dims, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
+                      seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
+                      stop_rule="diff", operator="auto", max_probes: int = 0) -> Dict[str, object]:
+    """tnslq_logneg for a state on sites with dims[s] levels (explicit operator)."""
+    import numpy as np
+    _check_device_tensor(psi, "psi")
+    if psi.numel() != int(np.prod(list(dims), dtype=np.int64)):
+        raise ValueError("psi has the wrong length")
+    dt = _dtype_code(psi)
+    opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator,
+                        max_probes)
+    p = _partition_dims(dims, a, b)
+    ws = _workspace(tnslq_workspace_bytes_dims(dt, dims, a, b, opts), psi.device, workspace)
+    res = Result()
+    K, m = n_probes, n_steps
+    loop = max_probes > n_probes
+    G = np.zeros(max(K, max_probes))
+    al, be, F = np.zeros((K, m)), np.zeros((K, m + 1)), np.zeros((K, m))
+    st = np.zeros(K, dtype=np.int32)
+    host = (lambda x: ctypes.c_void_p(0)) if loop else (lambda x: x.ctypes.data_as(ctypes.c_void_p))
+    rc = lib().tnslq_logneg_dims(_ptr(psi), dt, ctypes.byref(p), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                 _stream(stream), ctypes.byref(res), G.ctypes.data_as(ctypes.c_void_p), host(al),
+                                 host(be), host(F), host(st))
+    _check(rc, "tnslq_logneg_dims")
+    out: Dict[str, object] = res.as_dict()
+    out["G"] = G[:res.n_probes_used].copy()
+    if not loop:
+        out.update({"alpha": al, "beta": be, "F": F, "steps": st})
+    return out
+
+
+def tnslq_rho_pt_dims(psi, dims, a, b, workspace=None, stream=None, out=None):
+    """rho_AB^{T_B} in FP64 for a state on sites with dims[s] levels."""
+    import numpy as np
+    import torch
+    _check_device_tensor(psi, "psi")
+    dt = _dtype_code(psi)
+    n = int(np.prod([dims[q] for q in list(a) + list(b)], dtype=np.int64))
+    p = _partition_dims(dims, a, b)
+    nb = ctypes.c_size_t(0)
+    _check(lib().tnslq_rho_pt_dims_workspace_bytes(dt, ctypes.byref(p), ctypes.byref(nb)),
+           "tnslq_rho_pt_dims_workspace_bytes")
+    ws = _workspace(nb.value, psi.device, workspace)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.complex128, device=psi.device)
+    _check(lib().tnslq_rho_pt_dims(_ptr(psi), dt, ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "tnslq_rho_pt_dims")
+    return out
 
 
 def tnslq_rho_pt_workspace_bytes(dtype: int, n_qubits: int, a, b) -> int:

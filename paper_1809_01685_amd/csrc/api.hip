@@ -85,6 +85,7 @@ int check_dtype(int dtype) {
 }
 
 inline int64_t up128(int64_t x) { return (x + 127) / 128 * 128; }
+int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos);
 
 // Padded complex multiply-adds of one lazy block matvec (both contractions
 // over all probe chunks; matrix-core tiles are 128 x 128) and of the explicit
@@ -158,15 +159,21 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     pl.dE = int64_t(1) << pl.nE;
     pl.dAB = pl.dA * pl.dB;
     pl.D = int64_t(1) << pl.L;
+    return plan_rest(pl, dtype, prec, K, lanczos);
+}
 
+// Chunking, splits and the workspace carve-up of a plan whose roles, sizes
+// and operator form are set.
+int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     const size_t acc = prec == TNSLQ_FP64 ? 16 : 8;
     pl.nst1 = brick_stages(prec, pl.dA);
     pl.nst2 = brick_stages(prec, pl.dE * pl.dB);
     // intermediary per probe: d_B rows (b) by d_E d_B reduction terms (c, b')
     const size_t ups_bytes_per = brick_bytes(prec, pl.dB, pl.dE * pl.dB);
     pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
-    // every chunk must start on a block of 128 rows (k, b') of Xt
-    if (pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
+    // every chunk must start on a block of 128 rows (k, b') of Xt (lazy form:
+    // d_B is then a power of two)
+    if (!pl.expl && pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
         const int q = (int)(BRICK_ROWS / pl.dB);
         pl.kc = std::min(K, (pl.kc + q - 1) / q * q);
     }
@@ -262,6 +269,90 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     }
     pl.total = o;
     return TNSLQ_OK;
+}
+
+// Sites of general local dimension (explicit form only): A and B in the
+// order given, E the other sites in increasing order; psi's flat index in
+// mixed radix with site 0 most significant.
+int check_partition_dims(const tnslq_partition_dims *p) {
+    if (!p) return fail(TNSLQ_E_ARG, "partition is NULL");
+    if (p->n_sites < 1 || p->n_sites > TNSLQ_MAX_QUBITS)
+        return fail(TNSLQ_E_PARTITION, "n_sites %d outside [1, %d]", p->n_sites, TNSLQ_MAX_QUBITS);
+    if (!p->dims) return fail(TNSLQ_E_ARG, "dims is NULL");
+    if (p->n_a < 0 || p->n_b < 0 || p->n_a + p->n_b > p->n_sites)
+        return fail(TNSLQ_E_PARTITION, "bad subsystem sizes n_a=%d n_b=%d", p->n_a, p->n_b);
+    if ((p->n_a > 0 && !p->a) || (p->n_b > 0 && !p->b)) return fail(TNSLQ_E_ARG, "site list is NULL");
+    int64_t D = 1;
+    for (int s = 0; s < p->n_sites; ++s) {
+        if (p->dims[s] < 2 || p->dims[s] > 65536)
+            return fail(TNSLQ_E_PARTITION, "site %d: dimension %d outside [2, 65536]", s, p->dims[s]);
+        if (D > (int64_t(1) << 40) / p->dims[s]) return fail(TNSLQ_E_PARTITION, "state dimension exceeds 2^40");
+        D *= p->dims[s];
+    }
+    std::vector<int> seen(p->n_sites, 0);
+    for (int i = 0; i < p->n_a + p->n_b; ++i) {
+        const int q = i < p->n_a ? p->a[i] : p->b[i - p->n_a];
+        if (q < 0 || q >= p->n_sites) return fail(TNSLQ_E_PARTITION, "site %d out of range", q);
+        if (seen[q]) return fail(TNSLQ_E_PARTITION, "site %d listed twice", q);
+        seen[q] = 1;
+    }
+    return TNSLQ_OK;
+}
+
+int make_plan_dims(int dtype, const tnslq_partition_dims *p, int K, int m, int reorth, int prec, int lanczos,
+                   int opform, Plan &pl) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_prec(prec)) || (rc = check_partition_dims(p))) return rc;
+    int64_t D = 1;
+    for (int s = 0; s < p->n_sites; ++s) D *= p->dims[s];
+    std::vector<int> seen(p->n_sites, 0);
+    for (int i = 0; i < p->n_a; ++i) seen[p->a[i]] = 1;
+    for (int i = 0; i < p->n_b; ++i) seen[p->b[i]] = 1;
+    if (K < 1 || K > 65535) return fail(TNSLQ_E_ARG, "n_probes %d outside [1, 65535]", K);
+    if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
+        return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
+    if (opform == TNSLQ_OPERATOR_LAZY)
+        return fail(TNSLQ_E_ARG, "sites of general dimension take the explicit operator only");
+    if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_EXPLICIT)
+        return fail(TNSLQ_E_ARG, "operator_form %d unknown", opform);
+    pl = Plan();
+    pl.L = p->n_sites;
+    pl.dtype = dtype;
+    pl.prec = prec;
+    pl.K = K;
+    pl.m = lanczos ? m : 1;
+    pl.reorth = lanczos ? (reorth ? 1 : 0) : 0;
+    pl.expl = 1;
+    pl.mixed = 1;
+    std::vector<int64_t> stride(p->n_sites);
+    int64_t acc = 1;
+    for (int s = p->n_sites - 1; s >= 0; --s) {
+        stride[s] = acc;
+        acc *= p->dims[s];
+    }
+    std::vector<int> grp[3];
+    grp[0].assign(p->a, p->a + p->n_a);
+    grp[1].assign(p->b, p->b + p->n_b);
+    for (int s = 0; s < p->n_sites; ++s)
+        if (!seen[s]) grp[2].push_back(s);
+    for (int g = 0; g < 3; ++g) {
+        pl.md.n[g] = (int)grp[g].size();
+        pl.md.d[g] = 1;
+        for (int i = 0; i < pl.md.n[g]; ++i) {
+            pl.md.dim[g][i] = p->dims[grp[g][i]];
+            pl.md.stride[g][i] = stride[grp[g][i]];
+            pl.md.d[g] *= p->dims[grp[g][i]];
+        }
+    }
+    pl.dA = pl.md.d[0];
+    pl.dB = pl.md.d[1];
+    pl.dE = pl.md.d[2];
+    pl.dAB = pl.dA * pl.dB;
+    pl.D = D;
+    if (pl.dAB > EXPLICIT_MAX_N || explicit_bytes(prec, pl.dAB) > EXPLICIT_BUDGET)
+        return fail(TNSLQ_E_ARG, "explicit operator: d_A d_B = %lld exceeds %lld", (long long)pl.dAB,
+                    (long long)EXPLICIT_MAX_N);
+    return plan_rest(pl, dtype, prec, K, lanczos);
 }
 
 // Output bit t of the regrouped index <- input bit of psi's flat index.
@@ -391,10 +482,16 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
 // rho_AB = P P^dagger (Sec. V: the partial trace over E) as a dense n x n
 // product in the accumulator type, from P[(a, b)][c] = psi regrouped as
 // (A, B, E) and its conjugate, both as brick operands of precision `prec`.
-int form_rho(int prec, int dtype, const void *psi, const PermDesc &abe, int64_t n, int64_t dE, void *Pabe,
-             void *Pabc, void *Cd, hipStream_t st) {
-    TNSLQ_HIP(launch_permute(prec, dtype, psi, Pabe, n, dE, abe, 0, st));
-    TNSLQ_HIP(launch_permute(prec, dtype, psi, Pabc, n, dE, abe, 1, st));
+int form_rho(const Plan &pl, int prec, const void *psi, void *Pabe, void *Pabc, void *Cd, hipStream_t st) {
+    const int64_t n = pl.dAB, dE = pl.dE;
+    if (pl.mixed) {
+        TNSLQ_HIP(launch_permute_mixed(prec, pl.dtype, psi, Pabe, pl.md, 0, st));
+        TNSLQ_HIP(launch_permute_mixed(prec, pl.dtype, psi, Pabc, pl.md, 1, st));
+    } else {
+        const PermDesc abe = perm_for(pl, pl.qa, pl.nA, pl.qb, pl.nB, pl.qe, pl.nE);
+        TNSLQ_HIP(launch_permute(prec, pl.dtype, psi, Pabe, n, dE, abe, 0, st));
+        TNSLQ_HIP(launch_permute(prec, pl.dtype, psi, Pabc, n, dE, abe, 1, st));
+    }
     GemmDesc g{};
     g.A = Pabe;
     g.B = Pabc;
@@ -419,10 +516,9 @@ int do_layout(Ctx &c, const void *psi) {
     if (pl.expl) {
         // intermediary (iii): rho^{T_B} formed once, as the brick operand of
         // every later matvec
-        const PermDesc abe = perm_for(pl, pl.qa, pl.nA, pl.qb, pl.nB, pl.qe, pl.nE);
         int rc;
-        if ((rc = form_rho(pl.prec, pl.dtype, psi, abe, pl.dAB, pl.dE, c.Pabe, c.Pabc, c.Cd, c.st))) return rc;
-        TNSLQ_HIP(launch_pt_bricks(pl.prec, pl.prec == TNSLQ_FP64, c.Cd, pl.dAB, pl.nB, c.rho, pl.nst_rho, c.st));
+        if ((rc = form_rho(pl, pl.prec, psi, c.Pabe, c.Pabc, c.Cd, c.st))) return rc;
+        TNSLQ_HIP(launch_pt_bricks(pl.prec, pl.prec == TNSLQ_FP64, c.Cd, pl.dAB, pl.dB, c.rho, pl.nst_rho, c.st));
         if (pl.dAB % brick_epr(pl.prec))
             TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, pl.K, pl.dAB), c.st));
         return TNSLQ_OK;
@@ -691,12 +787,20 @@ struct Run {
     double lanczos_err = 0.0;   // of the last stop check
 };
 
+int run_start(Run &r, const tnslq_options *opt, const void *psi, void *ws, size_t ws_bytes, void *stream);
+
 int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_options *opt, const void *psi, void *ws,
               size_t ws_bytes, void *stream) {
     int rc;
     if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
                          opt->operator_form, r.c.pl)))
         return rc;
+    return run_start(r, opt, psi, ws, ws_bytes, stream);
+}
+
+// Bind the workspace to a planned run, regroup psi and start the probes.
+int run_start(Run &r, const tnslq_options *opt, const void *psi, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
     if (!psi) return fail(TNSLQ_E_ARG, "psi is NULL");
     if (!ws) return fail(TNSLQ_E_ARG, "workspace is NULL");
     if ((uintptr_t)ws % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
@@ -1229,6 +1333,45 @@ int tnslq_logneg(const void *psi_dev, int dtype, const tnslq_partition *part, co
     return run_finish(r, res, G_host, alpha_host, beta_host, F_host, steps_host, tm);
 }
 
+int tnslq_workspace_bytes_dims(int dtype, const tnslq_partition_dims *part, const tnslq_options *opt,
+                               size_t *bytes) {
+    int rc;
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    if ((rc = check_options(opt)) || (rc = check_dtype(dtype)) || (rc = check_partition_dims(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) {
+        *bytes = 0;
+        return TNSLQ_OK;
+    }
+    Plan pl;
+    if ((rc = make_plan_dims(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
+                             opt->operator_form, pl)))
+        return rc;
+    *bytes = pl.total;
+    return TNSLQ_OK;
+}
+
+int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims *part, const tnslq_options *opt,
+                      void *ws_dev, size_t ws_bytes, void *stream, tnslq_result *res, double *G_host,
+                      double *alpha_host, double *beta_host, double *F_host, int *steps_host) {
+    Timer tm;
+    int rc;
+    g_err.clear();
+    if (!res) return fail(TNSLQ_E_ARG, "result is NULL");
+    if ((rc = check_options(opt)) || (rc = check_dtype(dtype)) || (rc = check_partition_dims(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return trivial(opt, res, G_host, alpha_host, beta_host, F_host, steps_host);
+    const bool loop = opt->max_probes > opt->n_probes;
+    if (loop && (alpha_host || beta_host || F_host || steps_host))
+        return fail(TNSLQ_E_ARG, "with max_probes > n_probes only G_host may be requested");
+    Run r;
+    if ((rc = make_plan_dims(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
+                             opt->operator_form, r.c.pl)))
+        return rc;
+    if ((rc = run_start(r, opt, psi_dev, ws_dev, ws_bytes, stream))) return rc;
+    if (loop) return run_probe_loop(r, opt, res, G_host, tm);
+    if ((rc = run_steps(r, opt->n_steps, opt->stop_tol))) return rc;
+    return run_finish(r, res, G_host, alpha_host, beta_host, F_host, steps_host, tm);
+}
+
 int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n_vectors, int precision,
                                    size_t *bytes) {
     int rc;
@@ -1347,6 +1490,15 @@ struct PtPlan {
     Plan pl;
     size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, total = 0;
 };
+int pt_offsets(PtPlan &pp) {
+    const Plan &pl = pp.pl;
+    const size_t pb = up(brick_bytes(TNSLQ_FP64, pl.dAB, pl.dE));
+    pp.off_Pabe = 0;
+    pp.off_Pabc = pb;
+    pp.off_Cd = 2 * pb;
+    pp.total = pp.off_Cd + up((size_t)(pl.dAB * pl.dAB) * 16);
+    return TNSLQ_OK;
+}
 int make_pt_plan(int dtype, const tnslq_partition *part, PtPlan &pp) {
     int rc;
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part))) return rc;
@@ -1355,12 +1507,25 @@ int make_pt_plan(int dtype, const tnslq_partition *part, PtPlan &pp) {
         return fail(TNSLQ_E_ARG, "rho_pt: d_A d_B = 2^%d exceeds %lld", part->n_a + part->n_b,
                     (long long)EXPLICIT_MAX_N);
     if ((rc = make_plan(dtype, part, 1, 1, 0, TNSLQ_FP64, 1, TNSLQ_OPERATOR_EXPLICIT, pp.pl))) return rc;
+    return pt_offsets(pp);
+}
+int make_pt_plan_dims(int dtype, const tnslq_partition_dims *part, PtPlan &pp) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition_dims(part))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "rho_pt needs non-empty A and B");
+    if ((rc = make_plan_dims(dtype, part, 1, 1, 0, TNSLQ_FP64, 1, TNSLQ_OPERATOR_EXPLICIT, pp.pl))) return rc;
+    return pt_offsets(pp);
+}
+int rho_pt_run(const PtPlan &pp, const void *psi_dev, void *rho_dev, void *ws_dev, size_t ws_bytes, void *stream) {
+    int rc;
+    if (!psi_dev || !rho_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < pp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, pp.total);
     const Plan &pl = pp.pl;
-    const size_t pb = up(brick_bytes(TNSLQ_FP64, pl.dAB, pl.dE));
-    pp.off_Pabe = 0;
-    pp.off_Pabc = pb;
-    pp.off_Cd = 2 * pb;
-    pp.total = pp.off_Cd + up((size_t)(pl.dAB * pl.dAB) * 16);
+    char *ws = (char *)ws_dev;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = form_rho(pl, TNSLQ_FP64, psi_dev, ws + pp.off_Pabe, ws + pp.off_Pabc, ws + pp.off_Cd, st))) return rc;
+    TNSLQ_HIP(launch_pt_dense((const double2 *)(ws + pp.off_Cd), pl.dAB, pl.dB, (double2 *)rho_dev, st));
     return TNSLQ_OK;
 }
 }  // namespace
@@ -1380,18 +1545,25 @@ int tnslq_rho_pt(const void *psi_dev, int dtype, const tnslq_partition *part, vo
     g_err.clear();
     PtPlan pp;
     if ((rc = make_pt_plan(dtype, part, pp))) return rc;
-    if (!psi_dev || !rho_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
-    if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
-    if (ws_bytes < pp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, pp.total);
-    const Plan &pl = pp.pl;
-    char *ws = (char *)ws_dev;
-    hipStream_t st = (hipStream_t)stream;
-    const PermDesc abe = perm_for(pl, pl.qa, pl.nA, pl.qb, pl.nB, pl.qe, pl.nE);
-    if ((rc = form_rho(TNSLQ_FP64, pl.dtype, psi_dev, abe, pl.dAB, pl.dE, ws + pp.off_Pabe, ws + pp.off_Pabc,
-                       ws + pp.off_Cd, st)))
-        return rc;
-    TNSLQ_HIP(launch_pt_dense((const double2 *)(ws + pp.off_Cd), pl.dAB, pl.nB, (double2 *)rho_dev, st));
+    return rho_pt_run(pp, psi_dev, rho_dev, ws_dev, ws_bytes, stream);
+}
+
+int tnslq_rho_pt_dims_workspace_bytes(int dtype, const tnslq_partition_dims *part, size_t *bytes) {
+    int rc;
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    PtPlan pp;
+    if ((rc = make_pt_plan_dims(dtype, part, pp))) return rc;
+    *bytes = pp.total;
     return TNSLQ_OK;
+}
+
+int tnslq_rho_pt_dims(const void *psi_dev, int dtype, const tnslq_partition_dims *part, void *rho_dev, void *ws_dev,
+                      size_t ws_bytes, void *stream) {
+    int rc;
+    g_err.clear();
+    PtPlan pp;
+    if ((rc = make_pt_plan_dims(dtype, part, pp))) return rc;
+    return rho_pt_run(pp, psi_dev, rho_dev, ws_dev, ws_bytes, stream);
 }
 
 int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev, int n_probes, int n_steps,

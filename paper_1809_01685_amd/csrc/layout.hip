@@ -49,6 +49,45 @@ __global__ void __launch_bounds__(256) k_permute(const void *__restrict__ psi, v
     }
 }
 
+// psi index of the digits of v in group g (most significant site first).
+__device__ inline int64_t mixed_offset(const MixedDesc &md, int g, int64_t v) {
+    int64_t in = 0;
+    for (int i = md.n[g] - 1; i >= 0; --i) {
+        const int64_t q = v / md.dim[g][i];
+        in += (v - q * md.dim[g][i]) * md.stride[g][i];
+        v = q;
+    }
+    return in;
+}
+
+// P[(a, b)][c] = psi at A's digits of a, B's of b and E's of c, as a brick
+// operand of d_A d_B rows and d_E reduction terms (conjugated if asked), zeros
+// in the padding; threads step over the bricks in memory order as in
+// k_permute.
+template <int PREC, int DTYPE>
+__global__ void __launch_bounds__(256) k_permute_mixed(const void *__restrict__ psi, void *__restrict__ out,
+                                                       MixedDesc md, int64_t nst, int conj) {
+    constexpr int EPR = brick_epr(PREC), EPU = EPR / 4, NPL = planes_of(PREC);
+    constexpr int64_t PER_BRICK = (int64_t)BRICK_ROWS * EPR;
+    const int64_t R = md.d[0] * md.d[1], Kr = md.d[2];
+    const int64_t total = brick_rows(R) * nst * EPR;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
+        const int64_t b = x / PER_BRICK, w = x % PER_BRICK;
+        const int64_t rr = w / EPR, pos = w % EPR;
+        const int64_t ll = (((pos / EPU) ^ brick_swizzle(rr)) * EPU) + pos % EPU;
+        const int64_t r = (b / nst) * BRICK_ROWS + rr, l = (b % nst) * EPR + ll;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < R && l < Kr) {
+            const int64_t in = mixed_offset(md, 0, r / md.d[1]) + mixed_offset(md, 1, r % md.d[1]) +
+                               mixed_offset(md, 2, l);
+            v = load_psi<DTYPE>(psi, in);
+            if (conj) v.y = -v.y;
+        }
+        store_planes<PREC>(out, brick_ps(PREC), (b * NPL * BRICK_ROWS + rr) * EPR + pos, v.x, v.y);
+    }
+}
+
 // ---------------------------------------------------------------- probes
 __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t n) {
     // n-th output of SplitMix64 seeded with `seed` (state advances by the
@@ -213,11 +252,10 @@ __global__ void __launch_bounds__(256) k_partials_to_bricks(const AccT *__restri
 // zeros in the reduction padding.  Threads step over the plane-0 entries of
 // the bricks in memory order, as in k_permute.
 template <int PREC, typename AccT>
-__global__ void __launch_bounds__(256) k_pt_bricks(const AccT *__restrict__ C, int64_t n, int nB,
+__global__ void __launch_bounds__(256) k_pt_bricks(const AccT *__restrict__ C, int64_t n, int64_t dB,
                                                    void *__restrict__ rho, int64_t nst) {
     constexpr int EPR = brick_epr(PREC), EPU = EPR / 4, NPL = planes_of(PREC);
     constexpr int64_t PER_BRICK = (int64_t)BRICK_ROWS * EPR;
-    const int64_t mB = (int64_t(1) << nB) - 1;
     const int64_t total = brick_rows(n) * nst * EPR;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
@@ -227,7 +265,8 @@ __global__ void __launch_bounds__(256) k_pt_bricks(const AccT *__restrict__ C, i
         const int64_t r = (b / nst) * BRICK_ROWS + rr, l = (b % nst) * EPR + ll;
         double re = 0.0, im = 0.0;
         if (r < n && l < n) {
-            const AccT v = C[((r & ~mB) | (l & mB)) * n + ((l & ~mB) | (r & mB))];
+            const int64_t rb = r % dB, lb = l % dB;
+            const AccT v = C[(r - rb + lb) * n + (l - lb + rb)];
             re = (double)v.x;
             im = (double)v.y;
         }
@@ -236,13 +275,12 @@ __global__ void __launch_bounds__(256) k_pt_bricks(const AccT *__restrict__ C, i
 }
 
 // The same as a dense complex128 matrix, one thread per output element.
-__global__ void __launch_bounds__(256) k_pt_dense(const double2 *__restrict__ C, int64_t n, int nB,
+__global__ void __launch_bounds__(256) k_pt_dense(const double2 *__restrict__ C, int64_t n, int64_t dB,
                                                   double2 *__restrict__ out) {
-    const int64_t mB = (int64_t(1) << nB) - 1;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n * n; x += stride) {
-        const int64_t r = x / n, l = x % n;
-        out[x] = C[((r & ~mB) | (l & mB)) * n + ((l & ~mB) | (r & mB))];
+        const int64_t r = x / n, l = x % n, rb = r % dB, lb = l % dB;
+        out[x] = C[(r - rb + lb) * n + (l - lb + rb)];
     }
 }
 
@@ -345,12 +383,37 @@ hipError_t launch_partials_to_bricks(int prec, const void *part, int S, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int nB, void *rho, int64_t rho_nst,
+hipError_t launch_permute_mixed(int prec, int dtype, const void *psi, void *out, const MixedDesc &md, int conj,
+                                hipStream_t st) {
+    const int64_t R = md.d[0] * md.d[1];
+    const int64_t nst = brick_stages(prec, md.d[2]);
+    dim3 grid(grid_for(brick_rows(R) * nst * brick_epr(prec), 256 * 4, 65535 * 8)), block(256);
+#define TNSLQ_PM(P, T) hipLaunchKernelGGL((k_permute_mixed<P, T>), grid, block, 0, st, psi, out, md, nst, conj)
+    if (dtype == TNSLQ_C128) {
+        switch (prec) {
+            case TNSLQ_FP64: TNSLQ_PM(TNSLQ_FP64, TNSLQ_C128); break;
+            case TNSLQ_FP32: TNSLQ_PM(TNSLQ_FP32, TNSLQ_C128); break;
+            case TNSLQ_BF16X3: TNSLQ_PM(TNSLQ_BF16X3, TNSLQ_C128); break;
+            default: TNSLQ_PM(TNSLQ_BF16X6, TNSLQ_C128); break;
+        }
+    } else {
+        switch (prec) {
+            case TNSLQ_FP64: TNSLQ_PM(TNSLQ_FP64, TNSLQ_C64); break;
+            case TNSLQ_FP32: TNSLQ_PM(TNSLQ_FP32, TNSLQ_C64); break;
+            case TNSLQ_BF16X3: TNSLQ_PM(TNSLQ_BF16X3, TNSLQ_C64); break;
+            default: TNSLQ_PM(TNSLQ_BF16X6, TNSLQ_C64); break;
+        }
+    }
+#undef TNSLQ_PM
+    return hipGetLastError();
+}
+
+hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int64_t dB, void *rho, int64_t rho_nst,
                             hipStream_t st) {
     if ((prec == TNSLQ_FP64) != (accfp64 != 0)) return hipErrorInvalidValue;
     dim3 grid(grid_for(brick_rows(n) * rho_nst * brick_epr(prec), 256 * 4, 65535 * 8)), block(256);
 #define TNSLQ_PTB(P, A) \
-    hipLaunchKernelGGL((k_pt_bricks<P, A>), grid, block, 0, st, (const A *)C, n, nB, rho, rho_nst)
+    hipLaunchKernelGGL((k_pt_bricks<P, A>), grid, block, 0, st, (const A *)C, n, dB, rho, rho_nst)
     switch (prec) {
         case TNSLQ_FP64: TNSLQ_PTB(TNSLQ_FP64, double2); break;
         case TNSLQ_FP32: TNSLQ_PTB(TNSLQ_FP32, float2); break;
@@ -361,9 +424,9 @@ hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int
     return hipGetLastError();
 }
 
-hipError_t launch_pt_dense(const double2 *C, int64_t n, int nB, double2 *out, hipStream_t st) {
+hipError_t launch_pt_dense(const double2 *C, int64_t n, int64_t dB, double2 *out, hipStream_t st) {
     dim3 grid(grid_for(n * n, 256 * 4, 65535 * 4)), block(256);
-    hipLaunchKernelGGL(k_pt_dense, grid, block, 0, st, C, n, nB, out);
+    hipLaunchKernelGGL(k_pt_dense, grid, block, 0, st, C, n, dB, out);
     return hipGetLastError();
 }
 

@@ -25,6 +25,16 @@
 namespace tnslq {
 
 // ------------------------------------------------------------ plan
+// Sites of any local dimension (flat index of psi in mixed radix, site 0 most
+// significant): groups A, B, E, each listing its sites' dimensions and psi
+// index strides, most significant first.
+struct MixedDesc {
+    int n[3];
+    int64_t d[3];
+    int dim[3][TNSLQ_MAX_QUBITS];
+    int64_t stride[3][TNSLQ_MAX_QUBITS];
+};
+
 struct Plan {
     int L = 0;
     int nA = 0, nB = 0, nE = 0;      // sizes in the roles used on the device
@@ -42,6 +52,8 @@ struct Plan {
     int expl = 0;                    // rho^{T_B} formed explicitly (intermediary (iii))
     int64_t nst_rho = 1;             // bricks along the reduction index of the explicit matvec
     int64_t nst_e = 1;               // bricks along E of the forming product
+    int mixed = 0;                   // sites of general local dimension (explicit form only)
+    MixedDesc md;                    // their regrouping
     int nblk = 1;                    // reduction blocks per probe vector
     int64_t nst1 = 1, nst2 = 1;      // bricks along the reduction index of contraction 1, 2
     // workspace carve-up (byte offsets)
@@ -67,13 +79,18 @@ hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64
 
 // Explicit rho^{T_B} (intermediary (iii) of Sec. V) from the dense product
 // C[i][j] = rho_AB[i][j] (n x n, row-major, accumulator type: FP64 when
-// accfp64, else FP32), d_B = 2^nB:
+// accfp64, else FP32), index (a, b) = a d_B + b:
 //   rho^{T_B}[(a, b)][(a', b')] = C[(a, b')][(a', b)].
 // As an n x n brick operand of precision `prec` (reduction padding zeroed):
-hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int nB, void *rho, int64_t rho_nst,
+hipError_t launch_pt_bricks(int prec, int accfp64, const void *C, int64_t n, int64_t dB, void *rho, int64_t rho_nst,
                             hipStream_t st);
 // As a dense complex128 row-major matrix (from an FP64 product):
-hipError_t launch_pt_dense(const double2 *C, int64_t n, int nB, double2 *out, hipStream_t st);
+hipError_t launch_pt_dense(const double2 *C, int64_t n, int64_t dB, double2 *out, hipStream_t st);
+
+// P[(a, b)][c] of d_A d_B rows and d_E reduction terms as a brick operand
+// (conjugated if asked), zeros in the padding.
+hipError_t launch_permute_mixed(int prec, int dtype, const void *psi, void *out, const MixedDesc &md, int conj,
+                                hipStream_t st);
 
 // ------------------------------------------------------------ Lanczos etc.
 struct LzDims {

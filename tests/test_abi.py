@@ -157,7 +157,7 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"tnslq_partition": T.Partition, "tnslq_options": T.Options, "tnslq_result": T.Result,
-               "tnslq_spectral_result": T.SpectralResult}
+               "tnslq_spectral_result": T.SpectralResult, "tnslq_partition_dims": T.PartitionDims}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tnslq.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -208,3 +208,19 @@ def test_spectral_workspace_uses_the_smaller_side(L):
     small = T.tnslq_spectral_workspace_bytes(T.TNSLQ_C64, 16, [0, 1, 2], o)
     large = T.tnslq_spectral_workspace_bytes(T.TNSLQ_C64, 16, list(range(3, 16)), o)
     assert small == large > 2 * 8 * (1 << 16)
+
+
+def test_dims_entry_points_validate_without_device(L):
+    o = T.make_options(4, 8, precision="fp64")
+    # qutrits: 3^4 = 81 amplitudes, d_A d_B = 9
+    assert T.tnslq_workspace_bytes_dims(T.TNSLQ_C128, [3, 3, 3, 3], [0], [2], o) > 0
+    with pytest.raises(T.TnslqError, match="explicit operator only"):
+        T.tnslq_workspace_bytes_dims(T.TNSLQ_C128, [3, 3, 3, 3], [0], [2], T.make_options(4, 8, operator="lazy"))
+    for dims, a, b in (([3, 1, 3], [0], [2]), ([3, 3], [0], [0]), ([3, 3], [0], [5])):
+        with pytest.raises(T.TnslqError) as ei:
+            T.tnslq_workspace_bytes_dims(T.TNSLQ_C128, dims, a, b, o)
+        assert ei.value.status == -2
+    # d_A d_B = 3^9 > 16384
+    with pytest.raises(T.TnslqError, match="exceeds"):
+        T.tnslq_workspace_bytes_dims(T.TNSLQ_C64, [3] * 10, list(range(5)), list(range(5, 9)), o)
+    assert T.tnslq_workspace_bytes_dims(T.TNSLQ_C64, [3, 3], [0], [], o) == 0

@@ -32,6 +32,8 @@ __all__ = [
     "basis_product_state",
     "bell_pair_state",
     "random_contiguous_partition",
+    "haar_state_dims",
+    "max_entangled_pair_state_dims",
     "Workload",
     "WORKLOADS",
 ]
@@ -273,3 +275,30 @@ def random_vectors(n_vectors: int, dim: int, seed: int) -> np.ndarray:
     imaginary parts, from ``default_rng(seed)``."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n_vectors, dim)) + 1j * rng.standard_normal((n_vectors, dim))
+
+
+# --------------------------------------------------------------------------
+# Sites of any local dimension (site 0 most significant in the flat index)
+# --------------------------------------------------------------------------
+def haar_state_dims(dims: Sequence[int], seed: int, dtype=np.complex128) -> np.ndarray:
+    """Haar-random pure state on sites with dims[s] levels each."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(list(dims), dtype=np.int64))
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    return v.astype(dtype)
+
+
+def max_entangled_pair_state_dims(dims: Sequence[int], i: int, j: int, dtype=np.complex128) -> np.ndarray:
+    """(1/sqrt d) sum_k |k>_i |k>_j on sites i, j (d = dims[i] = dims[j]),
+    every other site in level 0."""
+    dims = list(dims)
+    d = dims[i]
+    if dims[j] != d:
+        raise ValueError("the two sites need the same dimension")
+    t = np.zeros(dims, dtype=np.complex128)
+    for k in range(d):
+        idx = [0] * len(dims)
+        idx[i] = idx[j] = k
+        t[tuple(idx)] = 1.0 / np.sqrt(d)
+    return t.reshape(-1).astype(dtype)
