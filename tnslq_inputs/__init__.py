@@ -34,6 +34,8 @@ __all__ = [
     "random_contiguous_partition",
     "haar_state_dims",
     "max_entangled_pair_state_dims",
+    "random_mps",
+    "bell_pair_mps",
     "Workload",
     "WORKLOADS",
 ]
@@ -302,3 +304,39 @@ def max_entangled_pair_state_dims(dims: Sequence[int], i: int, j: int, dtype=np.
         idx[i] = idx[j] = k
         t[tuple(idx)] = 1.0 / np.sqrt(d)
     return t.reshape(-1).astype(dtype)
+
+
+# --------------------------------------------------------------------------
+# Open-boundary matrix product states (Sec. VI): tensors (chi_i, p, chi_{i+1})
+# --------------------------------------------------------------------------
+def random_mps(n_sites: int, p: int, chi: int, seed: int) -> List[np.ndarray]:
+    """Complex Gaussian tensors with bond dimensions min(chi, p^i, p^(L-i))
+    (the largest an open chain can use), not normalised."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_sites):
+        cl = min(chi, p ** i, p ** (n_sites - i))
+        cr = min(chi, p ** (i + 1), p ** (n_sites - i - 1))
+        out.append(rng.standard_normal((cl, p, cr)) + 1j * rng.standard_normal((cl, p, cr)))
+    return out
+
+
+def bell_pair_mps(n_sites: int, i: int, j: int) -> List[np.ndarray]:
+    """(|00> + |11>)/sqrt 2 on qubits i < j, |0> elsewhere, as an MPS of bond
+    dimension 2 between i and j (1 elsewhere)."""
+    out = []
+    for s in range(n_sites):
+        inside = i < s < j
+        cl = 2 if i < s <= j else 1
+        cr = 2 if i <= s < j else 1
+        M = np.zeros((cl, 2, cr), dtype=np.complex128)
+        if s == i:
+            M[0, 0, 0] = M[0, 1, 1] = 2 ** -0.5
+        elif s == j:
+            M[0, 0, 0] = M[1, 1, 0] = 1.0
+        elif inside:
+            M[0, 0, 0] = M[1, 0, 1] = 1.0
+        else:
+            M[0, 0, 0] = 1.0
+        out.append(M)
+    return out
