@@ -269,6 +269,56 @@ int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
                       void *ws_dev, size_t ws_bytes, void *stream, tnslq_result *res, double *G_host,
                       double *alpha_host, double *beta_host, double *F_host, int *steps_host);
 
+/* ----------------------------------------- matrix product states (Sec. VI) */
+
+/* An open-boundary matrix product state (Eq. 5 with boundary bonds of size
+ * 1): site i holds a complex128 tensor M_i[x][s][y] of shape
+ * (bond[i], phys[i], bond[i+1]), row-major, the sites' tensors one after the
+ * other in `tensors` (device, read only).  psi_{s_0 .. s_{L-1}} =
+ * M_0[0][s_0][:] M_1[:][s_1][:] ... M_{L-1}[:][s_{L-1}][0], site 0 most
+ * significant.  The state need not be normalised. */
+typedef struct {
+    int n_sites;
+    const int *phys;        /* host, n_sites entries >= 2                      */
+    const int *bond;        /* host, n_sites + 1 entries, bond[0] = bond[n] = 1 */
+    const void *tensors;    /* device, complex128                              */
+} tnslq_mps;
+
+/* Contiguous blocks A = sites [a0, a0 + n_a) and B = [b0, b0 + n_b), a0 + n_a
+ * <= b0.  Sec. VI's compressed form of rho_AB^{T_B}, reduced to a dense
+ * effective state psi_eff with the same nonzero spectrum of the partial
+ * transpose (so the same trace norm), normalised:
+ *   - the sites left of A and right of B are traced; their transfer products
+ *     E_L, E_R (positive, on the bonds entering A and leaving B) are factored
+ *     E = X X^dagger (Cholesky) and absorbed into A and B, whose outer bond
+ *     indices u, v become traced environment indices;
+ *   - vertical decomposition: a block whose physical space is larger than its
+ *     two bonds' (p^{n_a} > bond[a0] bond[a0 + n_a]) is replaced by R with
+ *     R^dagger R its Gram matrix over the physical index (Cholesky): an
+ *     isometry on the block's space, which keeps the nonzero spectrum of the
+ *     partial transpose; effective dimension <= bond^2;
+ *   - the gap between A and B (if any) is traced: its transfer matrix,
+ *     grouped as its two bonds against their conjugates, is factored W
+ *     W^dagger when the gap's physical space is the larger, and W's column
+ *     index joins the environment.
+ * psi_eff's parts A', B', E' = (u, w, v) are each zero padded to a power of
+ * two, 2^q_A, 2^q_B, 2^q_E, so that tnslq_logneg (qubits: A = [0, q_A),
+ * B = [q_A, q_A + q_B)) applies to it unchanged; the padding adds only zero
+ * eigenvalues.
+ *   tnslq_mps_effective_state_size: q[3] = (q_A, q_B, q_E) and the workspace
+ *     bytes (host only).
+ *   tnslq_mps_effective_state: writes psi_eff, 2^(q_A + q_B + q_E) complex128
+ *     (device), A' most significant.  The factorisations are Cholesky factors
+ *     of positive semidefinite matrices: where a matrix is rank deficient (a
+ *     pivot at most 1e-13 of its largest diagonal entry) the column is left
+ *     zero, which only adds zero padding to psi_eff.  Returns
+ *     TNSLQ_E_NONFINITE if a factored matrix holds non-finite values.
+ *     Synchronises `stream` (to read that outcome). */
+int tnslq_mps_effective_state_size(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, int *q,
+                                   size_t *ws_bytes);
+int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, void *psi_dev, void *ws_dev,
+                              size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------ partial-transpose matvec */
 
 /* Workspace bytes for tnslq_ptmatvec with n_vectors vectors. */

@@ -74,6 +74,22 @@ def section(tensors, i0: int, i1: int) -> np.ndarray:
     return S
 
 
+def psd_cholesky(G: np.ndarray, tol: float = 1e-13) -> np.ndarray:
+    """Lower Cholesky factor L of a positive semidefinite G (G = L L^dagger),
+    column by column; a pivot not above tol times the largest diagonal entry
+    leaves its column zero (the matrix is rank deficient there)."""
+    G = np.asarray(G, dtype=np.complex128)
+    n = G.shape[0]
+    L = np.zeros_like(G)
+    dmax = float(np.max(G.diagonal().real)) if n else 0.0
+    for j in range(n):
+        d = G[j, j].real - float(np.sum(np.abs(L[j, :j]) ** 2))
+        if d > tol * dmax:
+            L[j, j] = np.sqrt(d)
+            L[j + 1:, j] = (G[j + 1:, j] - L[j + 1:, :j] @ L[j, :j].conj()) / L[j, j]
+    return L
+
+
 def _vertical(S: np.ndarray) -> np.ndarray:
     """R[k, u, m] with R^dagger R = sum_a conj(S[u,a,m]) S[u',a,m'] (or S itself
     as R[a, u, m] when the physical space is not larger than the bond space)."""
@@ -82,19 +98,19 @@ def _vertical(S: np.ndarray) -> np.ndarray:
         return S.transpose(1, 0, 2)
     Sm = S.transpose(1, 0, 2).reshape(a, u * m)           # rows a, columns (u, m)
     G = Sm.conj().T @ Sm
-    Lc = np.linalg.cholesky(G)                            # G = L L^dagger
+    Lc = psd_cholesky(G)                                  # G = L L^dagger
     return Lc.conj().T.reshape(u * m, u, m)               # R = L^dagger
 
 
 def effective_state(tensors, a0: int, LA: int, b0: int, LB: int) -> np.ndarray:
     """psi_eff of shape (d_A', d_B', d_E'), normalised (see module docstring)."""
     a1, b1 = a0 + LA, b0 + LB
-    X = np.linalg.cholesky(environment_left(tensors, a0))
-    Y = np.linalg.cholesky(environment_right(tensors, b1))
+    X = psd_cholesky(environment_left(tensors, a0))
+    Y = psd_cholesky(environment_right(tensors, b1))
     SA = np.einsum("xu,xam->uam", X, section(tensors, a0, a1))
     SB = np.einsum("nby,yv->nbv", section(tensors, b0, b1), Y)
     RA = _vertical(SA)                                    # [kA, u, m]
-    RB = _vertical(SB.transpose(2, 1, 0)).transpose(0, 2, 1)   # [kB, n, v] from the mirrored section
+    RB = _vertical(SB)                                    # [kB, n, v]
     if b0 == a1:
         W = np.eye(RA.shape[2], dtype=np.complex128)[:, :, None]      # m = n, w of size 1
     else:
@@ -104,7 +120,7 @@ def effective_state(tensors, a0: int, LA: int, b0: int, LB: int) -> np.ndarray:
             W = SG.transpose(0, 2, 1)                     # [m, n, w = g]
         else:
             Gm = SG.transpose(0, 2, 1).reshape(m * n, g)
-            W = np.linalg.cholesky(Gm @ Gm.conj().T).reshape(m, n, m * n)
+            W = psd_cholesky(Gm @ Gm.conj().T).reshape(m, n, m * n)
     psi = np.einsum("aum,mnw,bnv->abuwv", RA, W, RB)
     dA, dB = RA.shape[0], RB.shape[0]
     psi = psi.reshape(dA, dB, -1)

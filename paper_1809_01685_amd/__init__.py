@@ -46,6 +46,11 @@ class PartitionDims(ctypes.Structure):
                 ("n_a", ctypes.c_int), ("b", ctypes.POINTER(ctypes.c_int)), ("n_b", ctypes.c_int)]
 
 
+class Mps(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int), ("phys", ctypes.POINTER(ctypes.c_int)), ("bond", ctypes.POINTER(ctypes.c_int)),
+                ("tensors", ctypes.c_void_p)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
@@ -95,6 +100,9 @@ _SIGS = {
                                ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
     "tnslq_rho_pt_dims_workspace_bytes": (_I, [_I, ctypes.POINTER(PartitionDims), ctypes.POINTER(_SZ)]),
     "tnslq_rho_pt_dims": (_I, [_VP, _I, ctypes.POINTER(PartitionDims), _VP, _VP, _SZ, _VP]),
+    "tnslq_mps_effective_state_size": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, ctypes.POINTER(_I),
+                                            ctypes.POINTER(_SZ)]),
+    "tnslq_mps_effective_state": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "tnslq_rho_pt_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(_SZ)]),
     "tnslq_rho_pt": (_I, [_VP, _I, ctypes.POINTER(Partition), _VP, _VP, _SZ, _VP]),
     "tnslq_quadrature": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
@@ -365,6 +373,53 @@ def tnslq_rho_pt_dims(psi, dims, a, b, workspace=None, stream=None, out=None):
         out = torch.empty((n, n), dtype=torch.complex128, device=psi.device)
     _check(lib().tnslq_rho_pt_dims(_ptr(psi), dt, ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
            "tnslq_rho_pt_dims")
+    return out
+
+
+# ------------------------------------------------- matrix product states
+def _mps(tensors, device):
+    """Upload an open-boundary MPS (a list of (chi_l, p, chi_r) arrays) and
+    describe it for the library."""
+    import numpy as np
+    import torch
+    phys = [int(t.shape[1]) for t in tensors]
+    bond = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
+    flat = np.concatenate([np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).ravel() for t in tensors])
+    dev = torch.from_numpy(flat).to(device)
+    pp = (ctypes.c_int * len(phys))(*phys)
+    bb = (ctypes.c_int * len(bond))(*bond)
+    m = Mps(len(tensors), pp, bb, _ptr(dev))
+    m._keep = (pp, bb, dev)
+    return m
+
+
+def tnslq_mps_effective_state(tensors, a0: int, n_a: int, b0: int, n_b: int, device="cuda", workspace=None,
+                              stream=None):
+    """Sec. VI's compressed form of rho_AB^{T_B} for blocks A = [a0, a0 + n_a),
+    B = [b0, b0 + n_b) of an open-boundary MPS, as a dense effective state:
+    returns (psi_eff, (q_A, q_B, q_E)); psi_eff is a device complex128 vector
+    of 2^(q_A + q_B + q_E) amplitudes, A' the most significant qubits."""
+    import torch
+    m = _mps(tensors, device)
+    q = (ctypes.c_int * 3)()
+    n = ctypes.c_size_t(0)
+    _check(lib().tnslq_mps_effective_state_size(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), q,
+                                                ctypes.byref(n)), "tnslq_mps_effective_state_size")
+    ws = _workspace(n.value, torch.device(device), workspace)
+    psi = torch.empty(1 << (q[0] + q[1] + q[2]), dtype=torch.complex128, device=device)
+    _check(lib().tnslq_mps_effective_state(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), _ptr(psi),
+                                           _ptr(ws), ws.numel(), _stream(stream)), "tnslq_mps_effective_state")
+    return psi, (q[0], q[1], q[2])
+
+
+def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: int, n_steps: int, device="cuda",
+                     **kw) -> Dict[str, object]:
+    """E(rho_AB) of two contiguous blocks of an open-boundary MPS: the
+    effective state of tnslq_mps_effective_state through tnslq_logneg."""
+    psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device)
+    qa, qb, qe = q
+    out = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps, **kw)
+    out["effective_qubits"] = q
     return out
 
 

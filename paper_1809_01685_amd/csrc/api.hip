@@ -1566,6 +1566,269 @@ int tnslq_rho_pt_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
     return rho_pt_run(pp, psi_dev, rho_dev, ws_dev, ws_bytes, stream);
 }
 
+// ------------------------------------------------------------ MPS blocks
+namespace {
+int64_t ceil_pow2_log(int64_t x) {
+    int q = 0;
+    while ((int64_t(1) << q) < x) ++q;
+    return q;
+}
+
+// Sizes and workspace of the effective state of two contiguous blocks of an
+// open-boundary MPS (Sec. VI); see tnslq_mps_effective_state.
+struct MpsPlan {
+    int L = 0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    std::vector<int> p, bond;
+    std::vector<int64_t> off;          // element offset of each site's tensor
+    int64_t U = 1, Mb = 1, Nb = 1, V = 1, pA = 1, pB = 1, pG = 1;
+    int compA = 0, compB = 0, compG = 0;
+    int64_t kA = 1, kB = 1, Wd = 1;
+    int q[3] = {0, 0, 0};
+    int64_t smax = 1, gmax = 1, maxb = 1;
+    size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_G, off_RA, off_RB, off_RBp, off_W, off_T1,
+        off_T, off_part, off_fail, total = 0;
+};
+
+int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp) {
+    if (!m) return fail(TNSLQ_E_ARG, "mps is NULL");
+    const int L = m->n_sites;
+    if (L < 2 || L > 100000) return fail(TNSLQ_E_ARG, "n_sites %d outside [2, 100000]", L);
+    if (!m->phys || !m->bond) return fail(TNSLQ_E_ARG, "phys or bond is NULL");
+    if (m->bond[0] != 1 || m->bond[L] != 1) return fail(TNSLQ_E_ARG, "open boundaries need bond[0] = bond[n] = 1");
+    if (a0 < 0 || na < 1 || nb < 1 || a0 + na > b0 || b0 + nb > L)
+        return fail(TNSLQ_E_PARTITION, "blocks [%d, %d) and [%d, %d) not ordered inside the chain", a0, a0 + na, b0,
+                    b0 + nb);
+    mp = MpsPlan();
+    mp.L = L;
+    mp.a0 = a0;
+    mp.a1 = a0 + na;
+    mp.b0 = b0;
+    mp.b1 = b0 + nb;
+    mp.p.assign(m->phys, m->phys + L);
+    mp.bond.assign(m->bond, m->bond + L + 1);
+    mp.off.resize(L + 1);
+    mp.off[0] = 0;
+    for (int i = 0; i < L; ++i) {
+        if (mp.p[i] < 2 || mp.p[i] > 65536) return fail(TNSLQ_E_ARG, "site %d: phys %d outside [2, 65536]", i, mp.p[i]);
+        if (mp.bond[i + 1] < 1 || mp.bond[i + 1] > 4096)
+            return fail(TNSLQ_E_ARG, "bond %d: %d outside [1, 4096]", i + 1, mp.bond[i + 1]);
+        mp.off[i + 1] = mp.off[i] + (int64_t)mp.bond[i] * mp.p[i] * mp.bond[i + 1];
+        mp.maxb = std::max<int64_t>(mp.maxb, mp.bond[i + 1]);
+    }
+    const int64_t LIM = int64_t(1) << 40;
+    auto prod = [&](int i0, int i1, int64_t &out) {
+        out = 1;
+        for (int i = i0; i < i1; ++i) {
+            if (out > LIM / mp.p[i]) return false;
+            out *= mp.p[i];
+        }
+        return true;
+    };
+    if (!prod(mp.a0, mp.a1, mp.pA) || !prod(mp.b0, mp.b1, mp.pB) || !prod(mp.a1, mp.b0, mp.pG))
+        return fail(TNSLQ_E_ARG, "a block's physical dimension exceeds 2^40");
+    mp.U = mp.bond[mp.a0];
+    mp.Mb = mp.bond[mp.a1];
+    mp.Nb = mp.bond[mp.b0];
+    mp.V = mp.bond[mp.b1];
+    mp.compA = mp.pA > mp.U * mp.Mb;
+    mp.compB = mp.pB > mp.Nb * mp.V;
+    mp.kA = mp.compA ? mp.U * mp.Mb : mp.pA;
+    mp.kB = mp.compB ? mp.Nb * mp.V : mp.pB;
+    if (mp.b0 > mp.a1) {
+        mp.compG = mp.pG > mp.Mb * mp.Nb;
+        mp.Wd = mp.compG ? mp.Mb * mp.Nb : mp.pG;
+    }
+    // section sizes while they are built (left bond x physical so far x bond)
+    auto sec_max = [&](int i0, int i1, int64_t left) {
+        int64_t f = 1, mx = 0;
+        for (int i = i0; i < i1; ++i) {
+            f *= mp.p[i];
+            mx = std::max(mx, left * f * mp.bond[i + 1]);
+        }
+        return mx;
+    };
+    mp.smax = std::max({sec_max(mp.a0, mp.a1, mp.U), sec_max(mp.b0, mp.b1, mp.Nb), mp.Nb * mp.pB * mp.V,
+                        mp.b0 > mp.a1 ? sec_max(mp.a1, mp.b0, mp.Mb) : int64_t(1)});
+    if (mp.smax > (int64_t(1) << 31)) return fail(TNSLQ_E_ARG, "a block section has more than 2^31 entries");
+    const int64_t chol = std::max({mp.compA ? mp.U * mp.Mb : 0, mp.compB ? mp.Nb * mp.V : 0,
+                                   mp.compG ? mp.Mb * mp.Nb : 0, mp.U, mp.V});
+    if (chol > 4096) return fail(TNSLQ_E_ARG, "a factored matrix would be %lld wide (at most 4096)", (long long)chol);
+    mp.gmax = std::max<int64_t>(1, chol * chol);
+    mp.q[0] = (int)ceil_pow2_log(mp.kA);
+    mp.q[1] = (int)ceil_pow2_log(mp.kB);
+    mp.q[2] = (int)ceil_pow2_log(mp.U * mp.Wd * mp.V);
+    if (mp.q[0] + mp.q[1] + mp.q[2] > 32)
+        return fail(TNSLQ_E_ARG, "the effective state would need %d qubits (at most 32)", mp.q[0] + mp.q[1] + mp.q[2]);
+    size_t o = 0;
+    auto take = [&](int64_t n) {
+        size_t r = o;
+        o += up((size_t)n * 16);
+        return r;
+    };
+    const int64_t e2 = mp.maxb * mp.maxb;
+    mp.off_El[0] = take(e2);
+    mp.off_El[1] = take(e2);
+    mp.off_Er[0] = take(e2);
+    mp.off_Er[1] = take(e2);
+    mp.off_S[0] = take(mp.smax);
+    mp.off_S[1] = take(mp.smax);
+    mp.off_S[2] = take(mp.smax);
+    mp.off_SA = take(mp.U * mp.pA * mp.Mb);
+    mp.off_SB = take(mp.Nb * mp.pB * mp.V);
+    mp.off_SG = take(mp.b0 > mp.a1 ? mp.Mb * mp.pG * mp.Nb : 1);
+    mp.off_G = take(mp.gmax);
+    mp.off_RA = take(mp.kA * mp.U * mp.Mb);
+    mp.off_RB = take(mp.kB * mp.Nb * mp.V);
+    mp.off_RBp = take(mp.kB * mp.Nb * mp.V);
+    mp.off_W = take(mp.Mb * mp.Nb * mp.Wd);
+    mp.off_T1 = take(mp.kA * mp.U * mp.Nb * mp.Wd);
+    mp.off_T = take(mp.kA * mp.U * mp.Wd * mp.kB * mp.V);
+    mp.off_part = o;
+    o += up(257 * 8);
+    mp.off_fail = o;
+    o += up(4 * 4);
+    mp.total = o;
+    return TNSLQ_OK;
+}
+
+// Contract the sites [i0, i1) onto the running section S (rows r = left bond
+// x physical so far, columns = bond), starting from S0 (rows0 x bond[i0]);
+// the result lands in `out`.
+int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t rows0, int i0, int i1, double2 *out,
+                double2 *scratch0, double2 *scratch1, hipStream_t st) {
+    const double2 *cur = S0;
+    int64_t rows = rows0;
+    for (int i = i0; i < i1; ++i) {
+        const int64_t z = mp.bond[i], py = (int64_t)mp.p[i] * mp.bond[i + 1];
+        double2 *dst = i + 1 == i1 ? out : ((i - i0) % 2 ? scratch1 : scratch0);
+        TNSLQ_HIP(launch_zgemm(0, 0, cur, T + mp.off[i], dst, (int)rows, (int)py, (int)z, z, py, py, 1, 0, 0, 0, st));
+        cur = dst;
+        rows *= mp.p[i];
+    }
+    return TNSLQ_OK;
+}
+
+// R[k][(l, r)] for a section S[l][phys][r]: S itself with its first two axes
+// exchanged, or (compressed) R = L^dagger with L L^dagger = S^dagger S over
+// the physical index.
+int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, double2 *R, double2 *tmp, double2 *G,
+                 int *failp, hipStream_t st) {
+    if (!comp) {
+        TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, R, st));
+        return TNSLQ_OK;
+    }
+    const int64_t n = l * r;
+    TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, tmp, st));   // [phys][(l r)]
+    TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
+    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, st));
+    TNSLQ_HIP(launch_swap01(G, 1, n, n, 1, 1, R, st));
+    return TNSLQ_OK;
+}
+}  // namespace
+
+int tnslq_mps_effective_state_size(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, int *q, size_t *ws_bytes) {
+    int rc;
+    g_err.clear();
+    if (!q || !ws_bytes) return fail(TNSLQ_E_ARG, "NULL output");
+    MpsPlan mp;
+    if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp))) return rc;
+    for (int i = 0; i < 3; ++i) q[i] = mp.q[i];
+    *ws_bytes = mp.total;
+    return TNSLQ_OK;
+}
+
+int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, void *psi_dev, void *ws_dev,
+                              size_t ws_bytes, void *stream) {
+    int rc;
+    g_err.clear();
+    MpsPlan mp;
+    if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp))) return rc;
+    if (!mps->tensors || !psi_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < mp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, mp.total);
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)ws_dev;
+    auto buf = [&](size_t off) { return (double2 *)(ws + off); };
+    const double2 *T = (const double2 *)mps->tensors;
+    int *failp = (int *)(ws + mp.off_fail);
+    TNSLQ_HIP(hipMemsetAsync(failp, 0, 16, st));
+    static const double2 one = {1.0, 0.0};
+    // traced environments: E_L on the bond entering A, E_R on the bond leaving B
+    double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
+    TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
+    for (int i = 0; i < mp.a0; ++i) {
+        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, st));
+        std::swap(El, Eln);
+    }
+    double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
+    TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
+    for (int i = mp.L - 1; i >= mp.b1; --i) {
+        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, st));
+        std::swap(Er, Ern);
+    }
+    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, st));       // X[x][u]
+    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, st));   // Y[y][v]
+    double2 *s0 = buf(mp.off_S[0]), *s1 = buf(mp.off_S[1]), *s2 = buf(mp.off_S[2]);
+    // block A with X absorbed: S_A[u][a][m], from X^T (rows u, columns x)
+    TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Eln, st));
+    if ((rc = mps_section(mp, T, Eln, mp.U, mp.a0, mp.a1, buf(mp.off_SA), s0, s1, st))) return rc;
+    // block B, then Y absorbed: S_B[n][b][v]
+    if ((rc = mps_section(mp, T, T + mp.off[mp.b0], mp.Nb * mp.p[mp.b0], mp.b0 + 1, mp.b1, s2, s0, s1, st))) return rc;
+    const double2 *SBy = mp.b1 - mp.b0 > 1 ? s2 : T + mp.off[mp.b0];
+    TNSLQ_HIP(launch_zgemm(0, 0, SBy, Er, buf(mp.off_SB), (int)(mp.Nb * mp.pB), (int)mp.V, mp.bond[mp.b1],
+                           mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
+    // vertical decompositions
+    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), failp + 2,
+                           st)))
+        return rc;
+    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), failp + 3,
+                           st)))
+        return rc;
+    TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
+    const int64_t nrow = mp.kA * mp.U, ncol = mp.kB * mp.V;
+    double2 *Tout = buf(mp.off_T);
+    if (mp.b0 == mp.a1) {
+        // adjacent blocks: psi[(kA, u)][(kB, v)] = sum_m R_A[(kA, u)][m] R_B[m][(kB, v)]
+        TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_RBp), Tout, (int)nrow, (int)ncol, (int)mp.Mb, mp.Mb,
+                               ncol, ncol, 1, 0, 0, 0, st));
+    } else {
+        // the gap section S_G[m][g][n] and its tensor W[m][n][w]
+        if ((rc = mps_section(mp, T, T + mp.off[mp.a1], mp.Mb * mp.p[mp.a1], mp.a1 + 1, mp.b0, buf(mp.off_SG), s0, s1,
+                              st)))
+            return rc;
+        const double2 *SG = mp.b0 - mp.a1 > 1 ? buf(mp.off_SG) : T + mp.off[mp.a1];
+        TNSLQ_HIP(launch_swap01(SG, mp.Mb, mp.pG, mp.Nb, 1, 0, buf(mp.off_W), st));   // [m][n][g]
+        if (mp.compG) {
+            const int64_t n = mp.Mb * mp.Nb;
+            TNSLQ_HIP(launch_zgemm(0, 2, buf(mp.off_W), buf(mp.off_W), buf(mp.off_G), (int)n, (int)n, (int)mp.pG, mp.pG,
+                                   mp.pG, n, 1, 0, 0, 0, st));
+            TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, st));
+            TNSLQ_HIP(hipMemcpyAsync(buf(mp.off_W), buf(mp.off_G), (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
+        }
+        // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)]
+        TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_W), buf(mp.off_T1), (int)nrow, (int)(mp.Nb * mp.Wd),
+                               (int)mp.Mb, mp.Mb, mp.Nb * mp.Wd, mp.Nb * mp.Wd, 1, 0, 0, 0, st));
+        // psi[(kA, u)][w][(kB, v)] = sum_n T1[(kA, u)][n][w] R_B[n][(kB, v)], batched over (kA, u)
+        for (int64_t b0c = 0; b0c < nrow; b0c += 65535) {
+            const int nb = (int)std::min<int64_t>(65535, nrow - b0c);
+            TNSLQ_HIP(launch_zgemm(1, 0, buf(mp.off_T1) + b0c * mp.Nb * mp.Wd, buf(mp.off_RBp),
+                                   Tout + b0c * mp.Wd * ncol, (int)mp.Wd, (int)ncol, (int)mp.Nb, mp.Wd, ncol, ncol, nb,
+                                   mp.Nb * mp.Wd, 0, mp.Wd * ncol, st));
+        }
+    }
+    double *part = (double *)(ws + mp.off_part);
+    TNSLQ_HIP(launch_sumsq(Tout, nrow * mp.Wd * ncol, part, st));
+    TNSLQ_HIP(launch_assemble(Tout, mp.kA, mp.U, mp.Wd, mp.kB, mp.V, int64_t(1) << mp.q[0], int64_t(1) << mp.q[1],
+                              int64_t(1) << mp.q[2], part + 256, (double2 *)psi_dev, st));
+    int hf[4] = {0, 0, 0, 0};
+    TNSLQ_HIP(hipMemcpyAsync(hf, failp, sizeof hf, hipMemcpyDeviceToHost, st));
+    TNSLQ_HIP(hipStreamSynchronize(st));
+    static const char *what[4] = {"left environment", "right environment", "block A", "block B or the gap"};
+    for (int i = 0; i < 4; ++i)
+        if (hf[i]) return fail(TNSLQ_E_NONFINITE, "%s: matrix to factor is not finite", what[i]);
+    return TNSLQ_OK;
+}
+
 int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev, int n_probes, int n_steps,
                      double *F_dev, void *stream) {
     g_err.clear();

@@ -1,0 +1,291 @@
+// Contiguous blocks of an open-boundary matrix product state (Sec. VI): the
+// compressed form of rho_AB^{T_B}, reduced to an effective dense state whose
+// partially transposed density matrix has the same nonzero spectrum.
+//
+// All of it is small FP64 linear algebra on tensors of bond dimension chi:
+//   * transfer sweeps for the traced environments left of A and right of B,
+//     E <- sum_s M_s^T E conj(M_s) (one thread per output entry);
+//   * Cholesky factors of positive matrices (environments, Gram matrices of
+//     the blocks and of the gap), column by column in one block;
+//   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
+//     (16 x 16 output tiles staged through LDS), for the block sections, their
+//     Gram matrices and the effective state;
+//   * an axis exchange, and the final scatter of the effective state into a
+//     zero-padded power-of-two layout, normalised.
+// The host side (api.hip) plans the sizes and sequences these launches.
+#include "tnslq_internal.h"
+
+namespace tnslq {
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// E_new[y][y'] = sum_{x, x', s} E[x][x'] M[x][s][y] conj(M[x'][s][y']) (left),
+// E_new[x][x'] = sum_{y, y', s} M[x][s][y] conj(M[x'][s][y']) E[y][y'] (right).
+template <bool LEFT>
+__global__ void __launch_bounds__(256) k_transfer(const double2 *__restrict__ E, const double2 *__restrict__ M, int cx,
+                                                  int p, int cy, double2 *__restrict__ Enew) {
+    const int nout = LEFT ? cy : cx;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nout * nout) return;
+    const int r = t / nout, c = t % nout;
+    double2 acc = make_double2(0.0, 0.0);
+    if (LEFT) {
+        for (int x = 0; x < cx; ++x)
+            for (int xp = 0; xp < cx; ++xp) {
+                const double2 e = E[x * cx + xp];
+                for (int s = 0; s < p; ++s) {
+                    const double2 v = cmul(e, cmul(M[(x * p + s) * cy + r], cconj(M[(xp * p + s) * cy + c])));
+                    acc = make_double2(acc.x + v.x, acc.y + v.y);
+                }
+            }
+    } else {
+        for (int y = 0; y < cy; ++y)
+            for (int yp = 0; yp < cy; ++yp) {
+                const double2 e = E[y * cy + yp];
+                for (int s = 0; s < p; ++s) {
+                    const double2 v = cmul(cmul(M[(r * p + s) * cy + y], cconj(M[(c * p + s) * cy + yp])), e);
+                    acc = make_double2(acc.x + v.x, acc.y + v.y);
+                }
+            }
+    }
+    Enew[t] = acc;
+}
+
+// Normalise a small positive matrix by its trace (one block): keeps long
+// sweeps in range; the effective state is normalised at the end.
+__global__ void __launch_bounds__(256) k_scale_by_trace(double2 *__restrict__ E, int n) {
+    __shared__ double tr;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += E[i * n + i].x;
+        tr = s > 0.0 ? s : 1.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n * n; i += blockDim.x) E[i] = make_double2(E[i].x / tr, E[i].y / tr);
+}
+
+// In-place lower Cholesky factor of a Hermitian positive semidefinite n x n
+// matrix (row-major): A = L L^dagger, L lower triangular with a real
+// non-negative diagonal; the strict upper triangle is zeroed.  One block walks
+// the columns.  A pivot not above 1e-13 of the largest diagonal entry (the
+// matrix is rank deficient there; Gram and transfer matrices are positive
+// semidefinite by construction) leaves its column zero: L L^dagger is still
+// the matrix, and the zero columns only add zero padding downstream.
+// *fail is set when a pivot is not finite.
+__global__ void __launch_bounds__(1024) k_cholesky(double2 *__restrict__ A, int n, int *__restrict__ fail) {
+    __shared__ double piv, dmax;
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, A[(int64_t)i * n + i].x);
+        dmax = m;
+        *fail = 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            double d = A[(int64_t)j * n + j].x;
+            for (int k = 0; k < j; ++k) {
+                const double2 l = A[(int64_t)j * n + k];
+                d -= l.x * l.x + l.y * l.y;
+            }
+            if (!isfinite(d)) *fail = 1;
+            d = d > 1e-13 * dmax ? sqrt(d) : 0.0;
+            A[(int64_t)j * n + j] = make_double2(d, 0.0);
+            piv = d;
+        }
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+            double2 v = A[(int64_t)i * n + j];
+            for (int k = 0; k < j; ++k) {
+                const double2 q = cmul(A[(int64_t)i * n + k], cconj(A[(int64_t)j * n + k]));
+                v = make_double2(v.x - q.x, v.y - q.y);
+            }
+            A[(int64_t)i * n + j] = piv > 0.0 ? make_double2(v.x / piv, v.y / piv) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x)
+        if (e % n > e / n) A[e] = make_double2(0.0, 0.0);
+}
+
+// C[b] = op(A[b]) op(B[b]) for complex row-major matrices: op(A) is M x K,
+// op(B) is K x N; OP = 0 (as stored), 1 (transpose), 2 (conjugate transpose);
+// lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.
+template <int OPA, int OPB>
+__global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, const double2 *__restrict__ B,
+                                               double2 *__restrict__ C, int M, int N, int K, int64_t lda,
+                                               int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc) {
+    constexpr int TS = 16;
+    __shared__ double2 As[TS][TS + 1], Bs[TS][TS + 1];
+    const int64_t b = blockIdx.z;
+    A += b * sa;
+    B += b * sb;
+    C += b * sc;
+    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+    const int row = blockIdx.y * TS + ty, col = blockIdx.x * TS + tx;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < K; k0 += TS) {
+        // op(A)[row][k0 + tx] and op(B)[k0 + ty][col]
+        {
+            const int r = blockIdx.y * TS + ty, k = k0 + tx;
+            double2 v = make_double2(0.0, 0.0);
+            if (r < M && k < K) {
+                v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
+                if (OPA == 2) v = cconj(v);
+            }
+            As[ty][tx] = v;
+        }
+        {
+            const int k = k0 + ty, c = blockIdx.x * TS + tx;
+            double2 v = make_double2(0.0, 0.0);
+            if (k < K && c < N) {
+                v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
+                if (OPB == 2) v = cconj(v);
+            }
+            Bs[ty][tx] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TS; ++kk) {
+            const double2 q = cmul(As[ty][kk], Bs[kk][tx]);
+            acc = make_double2(acc.x + q.x, acc.y + q.y);
+        }
+        __syncthreads();
+    }
+    if (row < M && col < N) C[(int64_t)row * ldc + col] = acc;
+}
+
+// out[b][j][i][k] = in[b][i][j][k] for nb tensors of shape (n0, n1, n2)
+// (exchange of their first two axes), conjugated if asked.
+__global__ void __launch_bounds__(256) k_swap01(const double2 *__restrict__ in, int64_t nb, int64_t n0, int64_t n1,
+                                                int64_t n2, int conj, double2 *__restrict__ out) {
+    const int64_t per = n0 * n1 * n2, total = nb * per;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t b = e / per, r = e % per;
+        const int64_t k = r % n2, j = (r / n2) % n1, i = r / (n1 * n2);
+        double2 v = in[e];
+        if (conj) v.y = -v.y;
+        out[b * per + (j * n0 + i) * n2 + k] = v;
+    }
+}
+
+// Partial sums of |x|^2 (one per block) and their total in one thread.
+__global__ void __launch_bounds__(256) k_sumsq(const double2 *__restrict__ x, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        s += x[e].x * x[e].x + x[e].y * x[e].y;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_sum_parts(double *__restrict__ part, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    part[n] = s;
+}
+
+// The effective state: from T[(kA, u)][w][(kB, v)] into psi[(a, b, e)] with
+// zero padding to dA2 x dB2 x dE2 (powers of two), e = (u W + w) V + v, all
+// scaled by 1 / sqrt(sumsq).
+__global__ void __launch_bounds__(256) k_assemble(const double2 *__restrict__ T, int64_t kA, int64_t U, int64_t W,
+                                                  int64_t kB, int64_t V, int64_t dB2, int64_t dE2, int64_t total,
+                                                  const double *__restrict__ sumsq, double2 *__restrict__ psi) {
+    const double sc = 1.0 / sqrt(*sumsq);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += stride) {
+        const int64_t e = o % dE2, b = (o / dE2) % dB2, a = o / (dE2 * dB2);
+        double2 v = make_double2(0.0, 0.0);
+        if (a < kA && b < kB && e < U * W * V) {
+            const int64_t vv = e % V, w = (e / V) % W, u = e / (V * W);
+            v = T[((a * U + u) * W + w) * (kB * V) + b * V + vv];
+            v = make_double2(v.x * sc, v.y * sc);
+        }
+        psi[o] = v;
+    }
+}
+
+unsigned blocks_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65535 * 8) g = 65535 * 8;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx, int p, int cy, double2 *Enew,
+                           hipStream_t st) {
+    const int nout = left ? cy : cx;
+    if (left)
+        hipLaunchKernelGGL(k_transfer<true>, dim3(blocks_for((int64_t)nout * nout)), dim3(256), 0, st, E, M, cx, p, cy,
+                           Enew);
+    else
+        hipLaunchKernelGGL(k_transfer<false>, dim3(blocks_for((int64_t)nout * nout)), dim3(256), 0, st, E, M, cx, p,
+                           cy, Enew);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scale_by_trace, dim3(1), dim3(256), 0, st, Enew, nout);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double2 *A, int n, int *fail, hipStream_t st) {
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, n, fail);
+    return hipGetLastError();
+}
+
+hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
+                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
+                        hipStream_t st) {
+    if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
+    // rows in chunks of 65535 tiles (the grid's y limit)
+    constexpr int64_t RCH = 65535 * 16;
+    for (int64_t r0 = 0; r0 < M; r0 += RCH) {
+        const int m = (int)(M - r0 < RCH ? M - r0 : RCH);
+        const double2 *Ac = opa == 0 ? A + r0 * lda : A + r0;
+        double2 *Cc = C + r0 * ldc;
+        dim3 grid((unsigned)((N + 15) / 16), (unsigned)((m + 15) / 16), (unsigned)batch), block(256);
+#define TNSLQ_ZG(OA, OB) \
+    hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc)
+        if (opa == 0 && opb == 0) TNSLQ_ZG(0, 0);
+        else if (opa == 1 && opb == 0) TNSLQ_ZG(1, 0);
+        else if (opa == 2 && opb == 0) TNSLQ_ZG(2, 0);
+        else if (opa == 0 && opb == 2) TNSLQ_ZG(0, 2);
+        else return hipErrorInvalidValue;
+#undef TNSLQ_ZG
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_swap01, dim3(blocks_for(nb * n0 * n1 * n2)), dim3(256), 0, st, in, nb, n0, n1, n2, conj, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double2 *x, int64_t n, double *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_sumsq, dim3(256), dim3(256), 0, st, x, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1), 0, st, part, 256);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const double2 *T, int64_t kA, int64_t U, int64_t W, int64_t kB, int64_t V, int64_t dA2,
+                           int64_t dB2, int64_t dE2, const double *sumsq, double2 *psi, hipStream_t st) {
+    const int64_t total = dA2 * dB2 * dE2;
+    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(total)), dim3(256), 0, st, T, kA, U, W, kB, V, dB2, dE2, total, sumsq,
+                       psi);
+    return hipGetLastError();
+}
+
+}  // namespace tnslq

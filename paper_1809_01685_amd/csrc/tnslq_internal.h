@@ -181,6 +181,32 @@ hipError_t launch_sum_transpose_y(const double2 *Yt, int S, int K, int64_t dA, i
 hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, int K, int swapped, double2 *Xs,
                                      hipStream_t st);
 
+// ------------------------------------------------------------ MPS blocks
+// Small FP64 complex linear algebra for the matrix-product-state reduction
+// (Sec. VI); all matrices row-major, interleaved complex.
+// One transfer step of a traced environment through the site tensor
+// M[x][s][y] (cx x p x cy): left, E[x][x'] -> [y][y']; right, E[y][y'] ->
+// [x][x']; the result scaled to unit trace.
+hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx, int p, int cy, double2 *Enew,
+                           hipStream_t st);
+// In-place lower Cholesky factor (A = L L^dagger) of an n x n positive matrix;
+// *fail (device) is set if a pivot is not positive.
+hipError_t launch_cholesky(double2 *A, int n, int *fail, hipStream_t st);
+// C[b] = op(A[b]) op(B[b]), op 0 = as stored, 1 = transpose, 2 = conjugate
+// transpose (supported pairs: (0,0), (1,0), (2,0), (0,2)); op(A) is M x K.
+hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
+                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
+                        hipStream_t st);
+// out[b][j][i][k] = (conj) in[b][i][j][k], nb tensors of shape (n0, n1, n2).
+hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,
+                         hipStream_t st);
+// part[256] = sum of |x|^2 over all n entries (partials in part[0..255]).
+hipError_t launch_sumsq(const double2 *x, int64_t n, double *part, hipStream_t st);
+// psi[(a, b, e)] (dA2 x dB2 x dE2, zero padded) = T[(a, u)][w][(b, v)] /
+// sqrt(*sumsq), e = (u W + w) V + v.
+hipError_t launch_assemble(const double2 *T, int64_t kA, int64_t U, int64_t W, int64_t kB, int64_t V, int64_t dA2,
+                           int64_t dB2, int64_t dE2, const double *sumsq, double2 *psi, hipStream_t st);
+
 // ------------------------------------------------------------ MLP
 size_t mlp_ws_bytes(int batch);
 hipError_t mlp_forward(const float *params, const float *norm, const float *x, int batch, float *out,

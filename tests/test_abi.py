@@ -157,7 +157,8 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"tnslq_partition": T.Partition, "tnslq_options": T.Options, "tnslq_result": T.Result,
-               "tnslq_spectral_result": T.SpectralResult, "tnslq_partition_dims": T.PartitionDims}
+               "tnslq_spectral_result": T.SpectralResult, "tnslq_partition_dims": T.PartitionDims,
+               "tnslq_mps": T.Mps}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tnslq.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -224,3 +225,27 @@ def test_dims_entry_points_validate_without_device(L):
     with pytest.raises(T.TnslqError, match="exceeds"):
         T.tnslq_workspace_bytes_dims(T.TNSLQ_C64, [3] * 10, list(range(5)), list(range(5, 9)), o)
     assert T.tnslq_workspace_bytes_dims(T.TNSLQ_C64, [3, 3], [0], [], o) == 0
+
+
+def test_mps_sizes_and_validation_without_device(L):
+    import ctypes as C
+
+    def desc(phys, bond):
+        pp = (C.c_int * len(phys))(*phys)
+        bb = (C.c_int * len(bond))(*bond)
+        m = T.Mps(len(phys), pp, bb, None)
+        m._keep = (pp, bb)
+        return m
+    # 12 qubits, bond 4: A = [2, 6) (2^4 = 16 = 4 x 4, not compressed), B = [6, 10)
+    phys, bond = [2] * 12, [1, 2, 4, 4, 4, 4, 4, 4, 4, 4, 4, 2, 1]
+    q = (C.c_int * 3)()
+    n = C.c_size_t(0)
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond)), 2, 4, 6, 4, q, C.byref(n)) == 0
+    assert list(q) == [4, 4, 4] and n.value > 0          # d_E' = bond[2] bond[10] = 16
+    # blocks out of order, or past the chain
+    for a0, na, b0, nb in ((6, 4, 2, 4), (2, 5, 6, 4), (2, 4, 10, 3)):
+        assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond)), a0, na, b0, nb, q, C.byref(n)) == -2
+    bad = list(bond)
+    bad[0] = 2
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bad)), 2, 4, 6, 4, q, C.byref(n)) == -1
+    assert L.tnslq_mps_effective_state(C.byref(desc(phys, bond)), 2, 4, 6, 4, None, None, 0, None) == -1

@@ -54,3 +54,23 @@ def test_bell_pair_mps_has_one_bit_and_product_state_none():
     assert mps.logneg_mps_exact(ts, 1, 7, 8, 2) == pytest.approx(0.0, abs=1e-12)
     ts = ti.random_mps(10, 2, 1, 0)      # bond dimension 1: a product state
     assert mps.logneg_mps_exact(ts, 1, 3, 5, 4) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_semidefinite_cholesky():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+    G = A @ A.conj().T
+    # positive definite: the ordinary factor
+    assert np.allclose(mps.psd_cholesky(G), np.linalg.cholesky(G), atol=1e-12)
+    # rank 3 of 6: still G = L L^dagger, with zero columns
+    B = A[:, :3]
+    G3 = B @ B.conj().T
+    Lr = mps.psd_cholesky(G3)
+    assert np.allclose(Lr @ Lr.conj().T, G3, atol=1e-12)
+    assert np.sum(np.any(np.abs(Lr) > 1e-9, axis=0)) == 3
+
+
+def test_rank_deficient_gap_is_handled():
+    # a Bell pair across a long gap: the gap's transfer matrix has rank 1
+    ts = ti.bell_pair_mps(12, 2, 9)
+    assert mps.logneg_mps_exact(ts, 1, 3, 7, 4) == pytest.approx(1.0, abs=1e-12)
