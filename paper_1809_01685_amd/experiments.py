@@ -38,6 +38,13 @@
         over 8 GiB of float32 (vendor kernels, timed with events), beside the
         entropy passes over the 30-qubit state (8 GiB, complex64) at K = 1, 2, 4.
 
+    python -m paper_1809_01685_amd.experiments mps_blocks
+        Two contiguous blocks of a 100-site random open-boundary MPS (qubits,
+        complex Gaussian tensors, bond dimension chi): adjacent 16-site blocks
+        at chi = 16 and 32 (the geometry of Sec. VII.C) and 16-site blocks with
+        a 4-site gap at chi = 16; time to build the effective state (Sec. VI)
+        and to the +-1% estimate (split BF16, exponential-fit rule).
+
 All print one JSON object.  All arithmetic of the method runs in libtnslq
 (hbm_peak times torch's own copy and sum only as a reference).
 """
@@ -286,6 +293,39 @@ def run_hbm_peak(reps=10, seed=0):
     return {"workload": "HBM yardstick on one MI355X", "rows": out}
 
 
+def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3"):
+    import torch
+    import tnslq_inputs as ti
+    from . import tnslq_logneg, tnslq_mps_effective_state
+    dev = torch.device("cuda:0")
+    rows = []
+    for chi, a0, la, b0, lb in ((16, 34, 16, 50, 16), (32, 34, 16, 50, 16), (16, 32, 16, 52, 16)):
+        ts = ti.random_mps(100, 2, chi, seed)
+        tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        psi, q = tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)
+        torch.cuda.synchronize()
+        t_eff = time.perf_counter() - t0
+        qa, qb, qe = q
+        t0 = time.perf_counter()
+        r = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps,
+                         precision=precision, seed=seed, stop_tol=0.01, stop_rule="fit", want_arrays=False)
+        t_ln = time.perf_counter() - t0
+        row = {"n_sites": 100, "chi": chi, "A": [a0, a0 + la], "B": [b0, b0 + lb], "gap": b0 - a0 - la,
+               "effective_qubits": list(q), "t_effective_state_s": t_eff, "t_logneg_s": t_ln,
+               "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_err": r["lanczos_err"],
+               "steps": r["steps_done"], "explicit_operator": bool(r["explicit_operator"])}
+        rows.append(row)
+        print(f"[mps_blocks] chi {chi}, A {row['A']}, B {row['B']}: effective state {q} in {t_eff:.3f} s, "
+              f"E = {r['logneg']:.4f} +- {r['logneg_se']:.4f} after {r['steps_done']} steps in {t_ln:.3f} s",
+              file=sys.stderr, flush=True)
+        del psi
+        torch.cuda.empty_cache()
+    return {"workload": "100-site random open-boundary MPS (qubits), two 16-site blocks", "precision": precision,
+            "rows": rows}
+
+
 def _parse_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -303,11 +343,14 @@ def main(argv=None):
     sub.add_parser("hbm_sweep")
     sub.add_parser("operator_forms")
     sub.add_parser("hbm_peak")
+    sub.add_parser("mps_blocks")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
+    elif args.cmd == "mps_blocks":
+        out = run_mps_blocks()
     elif args.cmd == "hbm_peak":
         out = run_hbm_peak()
     elif args.cmd == "operator_forms":
