@@ -178,7 +178,7 @@ def run_entropy30(n_steps=20, seed=0):
     return {"workload": "30-qubit Haar state c64, S = first n qubits", "rows": rows}
 
 
-def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3"):
+def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3", b_qubits=(1, 2, 3), probes=(1, 2, 4)):
     import torch
     import tnslq_inputs as ti
     dev = torch.device("cuda:0")
@@ -187,9 +187,9 @@ def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3"):
     D = 1 << L
     rows = []
     a = list(range(4, 17))
-    for nb in (1, 2, 3):
+    for nb in b_qubits:
         b = list(range(17, 17 + nb))
-        for K in (1, 2, 4):
+        for K in probes:
             tnslq_logneg(psi, L, a, b, K, 2, precision=precision, seed=seed, want_arrays=False)   # warm-up
             r = tnslq_logneg(psi, L, a, b, K, n_steps, precision=precision, seed=seed, want_arrays=False)
             d_ab = 1 << (len(a) + nb)
@@ -340,7 +340,10 @@ def main(argv=None):
     sc.add_argument("--depths", default="1-12")
     sc.add_argument("--precision", default="bf16x3")
     sub.add_parser("heldout26")
-    sub.add_parser("hbm_sweep")
+    hs = sub.add_parser("hbm_sweep")
+    hs.add_argument("--b-qubits", default="1,2,3")
+    hs.add_argument("--probes", default="1,2,4")
+    hs.add_argument("--steps", type=int, default=10)
     sub.add_parser("operator_forms")
     sub.add_parser("hbm_peak")
     sub.add_parser("mps_blocks")
@@ -356,7 +359,7 @@ def main(argv=None):
     elif args.cmd == "operator_forms":
         out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
-        out = run_hbm_sweep()
+        out = run_hbm_sweep(n_steps=args.steps, b_qubits=_parse_range(args.b_qubits), probes=_parse_range(args.probes))
     elif args.cmd == "entropy30":
         out = run_entropy30(n_steps=args.steps)
     else:
