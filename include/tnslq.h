@@ -319,6 +319,30 @@ int tnslq_mps_effective_state_size(const tnslq_mps *mps, int a0, int n_a, int b0
 int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, void *psi_dev, void *ws_dev,
                               size_t ws_bytes, void *stream);
 
+/* Algorithm 1 on the same two blocks without forming psi_eff (Sec. VI: the
+ * operator as a small tensor network).  With the factors above, psi_eff has
+ * the form psi[a][b][(u', v)] = sum_m P[a][u'][m] Q[b][m][v] (adjacent
+ * blocks: P = R_A and m the bond between them; with a gap: P = R_A W, u' =
+ * (u, w), m the bond entering B), and each matvec is four complex products,
+ *   Z1 = P^dagger X,  Z2 = Z1 Q,  Z3 = P Z2 (m and m' exchanged),
+ *   Y[a][b] = sum_{m', v} Z3[a][(m', v)] conj Q[b][(m', v)],
+ * about 2 k chi^4 + 2 k^2 chi^2 complex multiply-adds per probe for
+ * k = d_A' = d_B' and bonds chi, against 2 k^3 chi^2 for the lazy form on
+ * psi_eff.  The Lanczos vectors run over (a, b), a d_B' + b, n = d_A' d_B'
+ * entries, unpadded; the estimate and every output are those of
+ * tnslq_logneg on psi_eff (same probes, same stopping rules, the loop over
+ * probes with max_probes).
+ *   opt->precision must be TNSLQ_FP64 (complex products in FP64) and
+ *   opt->operator_form TNSLQ_OPERATOR_AUTO; res->streamed and
+ *   res->explicit_operator are 0.  Probes are processed in chunks whose
+ *   intermediates fit 8 GiB.  Errors as tnslq_logneg, plus those of
+ *   tnslq_mps_effective_state; synchronises `stream`. */
+int tnslq_workspace_bytes_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt,
+                              size_t *bytes);
+int tnslq_logneg_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt, void *ws_dev,
+                     size_t ws_bytes, void *stream, tnslq_result *res, double *G_host, double *alpha_host,
+                     double *beta_host, double *F_host, int *steps_host);
+
 /* ------------------------------------------------ partial-transpose matvec */
 
 /* Workspace bytes for tnslq_ptmatvec with n_vectors vectors. */

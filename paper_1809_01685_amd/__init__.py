@@ -103,6 +103,10 @@ _SIGS = {
     "tnslq_mps_effective_state_size": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, ctypes.POINTER(_I),
                                             ctypes.POINTER(_SZ)]),
     "tnslq_mps_effective_state": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
+    "tnslq_workspace_bytes_mps": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, ctypes.POINTER(Options),
+                                       ctypes.POINTER(_SZ)]),
+    "tnslq_logneg_mps": (_I, [ctypes.POINTER(Mps), _I, _I, _I, _I, ctypes.POINTER(Options), _VP, _SZ, _VP,
+                              ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
     "tnslq_rho_pt_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(_SZ)]),
     "tnslq_rho_pt": (_I, [_VP, _I, ctypes.POINTER(Partition), _VP, _VP, _SZ, _VP]),
     "tnslq_quadrature": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
@@ -377,19 +381,26 @@ def tnslq_rho_pt_dims(psi, dims, a, b, workspace=None, stream=None, out=None):
 
 
 # ------------------------------------------------- matrix product states
-def _mps(tensors, device):
-    """Upload an open-boundary MPS (a list of (chi_l, p, chi_r) arrays) and
-    describe it for the library."""
-    import numpy as np
-    import torch
+def _mps_desc(tensors, tensors_ptr=None):
+    """The library's description of an open-boundary MPS (a list of
+    (chi_l, p, chi_r) arrays) with its tensors at ``tensors_ptr``."""
     phys = [int(t.shape[1]) for t in tensors]
     bond = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
-    flat = np.concatenate([np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).ravel() for t in tensors])
-    dev = torch.from_numpy(flat).to(device)
     pp = (ctypes.c_int * len(phys))(*phys)
     bb = (ctypes.c_int * len(bond))(*bond)
-    m = Mps(len(tensors), pp, bb, _ptr(dev))
-    m._keep = (pp, bb, dev)
+    m = Mps(len(tensors), pp, bb, tensors_ptr)
+    m._keep = (pp, bb)
+    return m
+
+
+def _mps(tensors, device):
+    """Upload an open-boundary MPS and describe it for the library."""
+    import numpy as np
+    import torch
+    flat = np.concatenate([np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).ravel() for t in tensors])
+    dev = torch.from_numpy(flat).to(device)
+    m = _mps_desc(tensors, _ptr(dev))
+    m._keep = m._keep + (dev,)
     return m
 
 
@@ -412,14 +423,61 @@ def tnslq_mps_effective_state(tensors, a0: int, n_a: int, b0: int, n_b: int, dev
     return psi, (q[0], q[1], q[2])
 
 
+def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opts: Options) -> int:
+    m = _mps_desc(tensors)
+    n = ctypes.c_size_t(0)
+    _check(lib().tnslq_workspace_bytes_mps(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), ctypes.byref(opts),
+                                           ctypes.byref(n)), "tnslq_workspace_bytes_mps")
+    return n.value
+
+
 def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: int, n_steps: int, device="cuda",
-                     **kw) -> Dict[str, object]:
-    """E(rho_AB) of two contiguous blocks of an open-boundary MPS: the
-    effective state of tnslq_mps_effective_state through tnslq_logneg."""
-    psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device)
-    qa, qb, qe = q
-    out = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps, **kw)
-    out["effective_qubits"] = q
+                     route="factored", reorth: bool = False, seed: int = 0, probe_offset: int = 0,
+                     stop_tol: float = 0.0, stop_rule="diff", max_probes: int = 0, workspace=None, stream=None,
+                     want_arrays: bool = True, **kw) -> Dict[str, object]:
+    """E(rho_AB) of two contiguous blocks of an open-boundary MPS (Sec. VI).
+
+    route="factored": Algorithm 1 on the two-block operator in factorised form
+    (tnslq_logneg_mps, FP64, nothing of the effective state's size formed);
+    route="dense": the effective state of tnslq_mps_effective_state through
+    tnslq_logneg (further keywords, e.g. precision, go to tnslq_logneg)."""
+    import numpy as np
+    import torch
+    if route == "dense":
+        psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device)
+        qa, qb, qe = q
+        out = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps,
+                           reorth=reorth, seed=seed, probe_offset=probe_offset, stop_tol=stop_tol,
+                           stop_rule=stop_rule, max_probes=max_probes, want_arrays=want_arrays, **kw)
+        out["effective_qubits"] = q
+        return out
+    if route != "factored":
+        raise ValueError(f"route must be 'factored' or 'dense', not {route!r}")
+    if kw:
+        raise TypeError(f"unexpected keywords for the factored route: {sorted(kw)}")
+    opts = make_options(n_probes, n_steps, reorth, "fp64", seed, probe_offset, stop_tol, stop_rule, "auto",
+                        max_probes)
+    m = _mps(tensors, device)
+    need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts)
+    ws = _workspace(need, torch.device(device), workspace)
+    res = Result()
+    loop = max_probes > n_probes
+    K, s = n_probes, n_steps
+    G = np.zeros(max_probes if loop else K)
+    al, be, F = np.zeros((K, s)), np.zeros((K, s + 1)), np.zeros((K, s))
+    st = np.zeros(K, dtype=np.int32)
+    host = (lambda x: x.ctypes.data_as(ctypes.c_void_p)) if want_arrays and not loop else \
+        (lambda x: ctypes.c_void_p(0))
+    rc = lib().tnslq_logneg_mps(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), ctypes.byref(opts), _ptr(ws),
+                                ws.numel(), _stream(stream), ctypes.byref(res), G.ctypes.data_as(ctypes.c_void_p),
+                                host(al), host(be), host(F), host(st))
+    _check(rc, "tnslq_logneg_mps")
+    out: Dict[str, object] = res.as_dict()
+    if loop:
+        out["G"] = G[:res.n_probes_used].copy()
+    elif want_arrays:
+        out.update({"G": G, "alpha": al, "beta": be, "F": F, "steps": st})
+    out["workspace_bytes"] = need
     return out
 
 

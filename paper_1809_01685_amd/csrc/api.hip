@@ -57,6 +57,8 @@ int reduction_blocks(int64_t n, int K) {
 // operator and of its dense FP32/FP64 precursor.
 constexpr int64_t EXPLICIT_MAX_N = 16384;
 constexpr size_t EXPLICIT_BUDGET = size_t(4) << 30;
+// intermediates of the factorised MPS operator (probes are chunked to fit)
+constexpr size_t MPS_BUDGET = size_t(8) << 30;
 
 int check_partition(const tnslq_partition *p) {
     if (!p) return fail(TNSLQ_E_ARG, "partition is NULL");
@@ -194,7 +196,7 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     // multiply-adds per element of psi and the 128 x 128 matrix-core tiles
     // would be mostly padding; they run instead as two streaming passes over
     // psi in its own dtype with FP64 products and sums.
-    pl.stream = !pl.expl && (int64_t)K * pl.dB <= 4;
+    pl.stream = !pl.expl && !pl.mpsf && (int64_t)K * pl.dB <= 4;
     if (pl.expl) {
         // one dense product per matvec: rho^{T_B} (n rows, reduction n) with
         // the K vectors (rows k, reduction n), split-K to fill the chip
@@ -219,13 +221,30 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.S = pl.S2s;
     }
 
+    // factorised MPS operator: four complex products per probe, chunks of
+    // probes within a fixed budget of intermediates
+    const int64_t UpM = pl.mUp * pl.mM, MV = pl.mM * pl.mV;
+    if (pl.mpsf) {
+        const size_t per = 16 * (size_t)(UpM * pl.dB + 2 * UpM * MV + pl.dA * MV + n);
+        pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(MPS_BUDGET / per)));
+        pl.S = pl.S1 = 1;
+    }
+
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
         o += up(bytes);
         return r;
     };
-    if (pl.expl) {
+    if (pl.mpsf) {
+        pl.off_mps = take(pl.mps_bytes);
+        pl.off_Z1 = take((size_t)pl.kc * UpM * pl.dB * 16);
+        pl.off_Z2 = take((size_t)pl.kc * UpM * MV * 16);
+        pl.off_Z2p = take((size_t)pl.kc * UpM * MV * 16);
+        pl.off_Z3 = take((size_t)pl.kc * pl.dA * MV * 16);
+        pl.off_Ypart = take((size_t)pl.kc * n * 16);
+        pl.off_nrm = take((size_t)2 * pl.mM * pl.mM * 16 + 64);
+    } else if (pl.expl) {
         pl.off_Pabe = take(brick_bytes(prec, n, pl.dE));
         pl.off_Pabc = take(brick_bytes(prec, n, pl.dE));
         pl.off_Cd = take((size_t)(n * n) * acc);
@@ -402,6 +421,264 @@ ColmacDesc plain_colmac(const void *M, int64_t R, int64_t C, const double2 *V, i
     return g;
 }
 
+// ------------------------------------------------------------ MPS blocks
+int64_t ceil_pow2_log(int64_t x) {
+    int q = 0;
+    while ((int64_t(1) << q) < x) ++q;
+    return q;
+}
+
+// Sizes and workspace of the effective state of two contiguous blocks of an
+// open-boundary MPS (Sec. VI); see tnslq_mps_effective_state.
+struct MpsPlan {
+    int L = 0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    std::vector<int> p, bond;
+    std::vector<int64_t> off;          // element offset of each site's tensor
+    int64_t U = 1, Mb = 1, Nb = 1, V = 1, pA = 1, pB = 1, pG = 1;
+    int compA = 0, compB = 0, compG = 0;
+    int64_t kA = 1, kB = 1, Wd = 1;
+    int q[3] = {0, 0, 0};
+    int64_t smax = 1, gmax = 1, maxb = 1;
+    size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_G, off_RA, off_RB, off_RBp, off_W, off_T1,
+        off_T, off_P, off_part, off_fail, total = 0;
+};
+
+// dense: room for the effective state itself (the dense route); without it
+// only the factors are built.
+int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bool dense = true) {
+    if (!m) return fail(TNSLQ_E_ARG, "mps is NULL");
+    const int L = m->n_sites;
+    if (L < 2 || L > 100000) return fail(TNSLQ_E_ARG, "n_sites %d outside [2, 100000]", L);
+    if (!m->phys || !m->bond) return fail(TNSLQ_E_ARG, "phys or bond is NULL");
+    if (m->bond[0] != 1 || m->bond[L] != 1) return fail(TNSLQ_E_ARG, "open boundaries need bond[0] = bond[n] = 1");
+    if (a0 < 0 || na < 1 || nb < 1 || a0 + na > b0 || b0 + nb > L)
+        return fail(TNSLQ_E_PARTITION, "blocks [%d, %d) and [%d, %d) not ordered inside the chain", a0, a0 + na, b0,
+                    b0 + nb);
+    mp = MpsPlan();
+    mp.L = L;
+    mp.a0 = a0;
+    mp.a1 = a0 + na;
+    mp.b0 = b0;
+    mp.b1 = b0 + nb;
+    mp.p.assign(m->phys, m->phys + L);
+    mp.bond.assign(m->bond, m->bond + L + 1);
+    mp.off.resize(L + 1);
+    mp.off[0] = 0;
+    for (int i = 0; i < L; ++i) {
+        if (mp.p[i] < 2 || mp.p[i] > 65536) return fail(TNSLQ_E_ARG, "site %d: phys %d outside [2, 65536]", i, mp.p[i]);
+        if (mp.bond[i + 1] < 1 || mp.bond[i + 1] > 4096)
+            return fail(TNSLQ_E_ARG, "bond %d: %d outside [1, 4096]", i + 1, mp.bond[i + 1]);
+        mp.off[i + 1] = mp.off[i] + (int64_t)mp.bond[i] * mp.p[i] * mp.bond[i + 1];
+        mp.maxb = std::max<int64_t>(mp.maxb, mp.bond[i + 1]);
+    }
+    const int64_t LIM = int64_t(1) << 40;
+    auto prod = [&](int i0, int i1, int64_t &out) {
+        out = 1;
+        for (int i = i0; i < i1; ++i) {
+            if (out > LIM / mp.p[i]) return false;
+            out *= mp.p[i];
+        }
+        return true;
+    };
+    if (!prod(mp.a0, mp.a1, mp.pA) || !prod(mp.b0, mp.b1, mp.pB) || !prod(mp.a1, mp.b0, mp.pG))
+        return fail(TNSLQ_E_ARG, "a block's physical dimension exceeds 2^40");
+    mp.U = mp.bond[mp.a0];
+    mp.Mb = mp.bond[mp.a1];
+    mp.Nb = mp.bond[mp.b0];
+    mp.V = mp.bond[mp.b1];
+    mp.compA = mp.pA > mp.U * mp.Mb;
+    mp.compB = mp.pB > mp.Nb * mp.V;
+    mp.kA = mp.compA ? mp.U * mp.Mb : mp.pA;
+    mp.kB = mp.compB ? mp.Nb * mp.V : mp.pB;
+    if (mp.b0 > mp.a1) {
+        mp.compG = mp.pG > mp.Mb * mp.Nb;
+        mp.Wd = mp.compG ? mp.Mb * mp.Nb : mp.pG;
+    }
+    // section sizes while they are built (left bond x physical so far x bond)
+    auto sec_max = [&](int i0, int i1, int64_t left) {
+        int64_t f = 1, mx = 0;
+        for (int i = i0; i < i1; ++i) {
+            f *= mp.p[i];
+            mx = std::max(mx, left * f * mp.bond[i + 1]);
+        }
+        return mx;
+    };
+    mp.smax = std::max({sec_max(mp.a0, mp.a1, mp.U), sec_max(mp.b0, mp.b1, mp.Nb), mp.Nb * mp.pB * mp.V,
+                        mp.b0 > mp.a1 ? sec_max(mp.a1, mp.b0, mp.Mb) : int64_t(1)});
+    if (mp.smax > (int64_t(1) << 31)) return fail(TNSLQ_E_ARG, "a block section has more than 2^31 entries");
+    const int64_t chol = std::max({mp.compA ? mp.U * mp.Mb : 0, mp.compB ? mp.Nb * mp.V : 0,
+                                   mp.compG ? mp.Mb * mp.Nb : 0, mp.U, mp.V});
+    if (chol > 4096) return fail(TNSLQ_E_ARG, "a factored matrix would be %lld wide (at most 4096)", (long long)chol);
+    mp.gmax = std::max<int64_t>(1, chol * chol);
+    mp.q[0] = (int)ceil_pow2_log(mp.kA);
+    mp.q[1] = (int)ceil_pow2_log(mp.kB);
+    mp.q[2] = (int)ceil_pow2_log(mp.U * mp.Wd * mp.V);
+    if (!dense) {
+        const int64_t Up = mp.U * mp.Wd, M = mp.b0 > mp.a1 ? mp.Nb : mp.Mb;
+        if (mp.kA * Up > INT32_MAX || mp.kB * mp.V > INT32_MAX || Up * M > INT32_MAX || M * mp.V > INT32_MAX ||
+            mp.kA * mp.kB > (int64_t(1) << 32))
+            return fail(TNSLQ_E_ARG, "the blocks' factors exceed 2^31 rows or columns");
+    } else if (mp.q[0] + mp.q[1] + mp.q[2] > 32)
+        return fail(TNSLQ_E_ARG, "the effective state would need %d qubits (at most 32)", mp.q[0] + mp.q[1] + mp.q[2]);
+    size_t o = 0;
+    auto take = [&](int64_t n) {
+        size_t r = o;
+        o += up((size_t)n * 16);
+        return r;
+    };
+    const int64_t e2 = mp.maxb * mp.maxb;
+    mp.off_El[0] = take(e2);
+    mp.off_El[1] = take(e2);
+    mp.off_Er[0] = take(e2);
+    mp.off_Er[1] = take(e2);
+    mp.off_S[0] = take(mp.smax);
+    mp.off_S[1] = take(mp.smax);
+    mp.off_S[2] = take(mp.smax);
+    mp.off_SA = take(mp.U * mp.pA * mp.Mb);
+    mp.off_SB = take(mp.Nb * mp.pB * mp.V);
+    mp.off_SG = take(mp.b0 > mp.a1 ? mp.Mb * mp.pG * mp.Nb : 1);
+    mp.off_G = take(mp.gmax);
+    mp.off_RA = take(mp.kA * mp.U * mp.Mb);
+    mp.off_RB = take(mp.kB * mp.Nb * mp.V);
+    mp.off_RBp = take(mp.kB * mp.Nb * mp.V);
+    mp.off_W = take(mp.Mb * mp.Nb * mp.Wd);
+    mp.off_T1 = take(mp.kA * mp.U * mp.Nb * mp.Wd);
+    mp.off_T = take(dense ? mp.kA * mp.U * mp.Wd * mp.kB * mp.V : 1);
+    mp.off_P = take(mp.b0 > mp.a1 ? mp.kA * mp.U * mp.Wd * mp.Nb : 1);
+    mp.off_part = o;
+    o += up(257 * 8);
+    mp.off_fail = o;
+    o += up(4 * 4);
+    mp.total = o;
+    return TNSLQ_OK;
+}
+
+// Contract the sites [i0, i1) onto the running section S (rows r = left bond
+// x physical so far, columns = bond), starting from S0 (rows0 x bond[i0]);
+// the result lands in `out`.
+int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t rows0, int i0, int i1, double2 *out,
+                double2 *scratch0, double2 *scratch1, hipStream_t st) {
+    const double2 *cur = S0;
+    int64_t rows = rows0;
+    for (int i = i0; i < i1; ++i) {
+        const int64_t z = mp.bond[i], py = (int64_t)mp.p[i] * mp.bond[i + 1];
+        double2 *dst = i + 1 == i1 ? out : ((i - i0) % 2 ? scratch1 : scratch0);
+        TNSLQ_HIP(launch_zgemm(0, 0, cur, T + mp.off[i], dst, (int)rows, (int)py, (int)z, z, py, py, 1, 0, 0, 0, st));
+        cur = dst;
+        rows *= mp.p[i];
+    }
+    return TNSLQ_OK;
+}
+
+// R[k][(l, r)] for a section S[l][phys][r]: S itself with its first two axes
+// exchanged, or (compressed) R = L^dagger with L L^dagger = S^dagger S over
+// the physical index.
+int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, double2 *R, double2 *tmp, double2 *G,
+                 int *failp, hipStream_t st) {
+    if (!comp) {
+        TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, R, st));
+        return TNSLQ_OK;
+    }
+    const int64_t n = l * r;
+    TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, tmp, st));   // [phys][(l r)]
+    TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
+    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, st));
+    TNSLQ_HIP(launch_swap01(G, 1, n, n, 1, 1, R, st));
+    return TNSLQ_OK;
+}
+
+// The factors of the effective state psi[a][b][(u', v)] = sum_m P[a][u'][m]
+// Q[b][m][v]: for adjacent blocks u' = u and m is the bond between them; with
+// a gap, P = sum_m R_A[a][u][m] W[m][n][w] with u' = (u, w) and m -> n.  Qp is
+// Q with its first two axes exchanged, [m][b][v].
+struct MpsFactors {
+    double2 *P;
+    const double2 *Q, *Qp;
+    int64_t kA, Up, M, kB, V;
+};
+
+int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, MpsFactors &f) {
+    int rc;
+    auto buf = [&](size_t off) { return (double2 *)(ws + off); };
+    int *failp = (int *)(ws + mp.off_fail);
+    TNSLQ_HIP(hipMemsetAsync(failp, 0, 16, st));
+    static const double2 one = {1.0, 0.0};
+    // traced environments: E_L on the bond entering A, E_R on the bond leaving B
+    double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
+    TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
+    for (int i = 0; i < mp.a0; ++i) {
+        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, st));
+        std::swap(El, Eln);
+    }
+    double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
+    TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
+    for (int i = mp.L - 1; i >= mp.b1; --i) {
+        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, st));
+        std::swap(Er, Ern);
+    }
+    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, st));       // X[x][u]
+    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, st));   // Y[y][v]
+    double2 *s0 = buf(mp.off_S[0]), *s1 = buf(mp.off_S[1]), *s2 = buf(mp.off_S[2]);
+    // block A with X absorbed: S_A[u][a][m], from X^T (rows u, columns x)
+    TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Eln, st));
+    if ((rc = mps_section(mp, T, Eln, mp.U, mp.a0, mp.a1, buf(mp.off_SA), s0, s1, st))) return rc;
+    // block B, then Y absorbed: S_B[n][b][v]
+    if ((rc = mps_section(mp, T, T + mp.off[mp.b0], mp.Nb * mp.p[mp.b0], mp.b0 + 1, mp.b1, s2, s0, s1, st))) return rc;
+    const double2 *SBy = mp.b1 - mp.b0 > 1 ? s2 : T + mp.off[mp.b0];
+    TNSLQ_HIP(launch_zgemm(0, 0, SBy, Er, buf(mp.off_SB), (int)(mp.Nb * mp.pB), (int)mp.V, mp.bond[mp.b1],
+                           mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
+    // vertical decompositions
+    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), failp + 2,
+                           st)))
+        return rc;
+    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), failp + 3,
+                           st)))
+        return rc;
+    TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
+    f.Q = buf(mp.off_RB);
+    f.Qp = buf(mp.off_RBp);
+    f.kA = mp.kA;
+    f.kB = mp.kB;
+    f.V = mp.V;
+    f.M = mp.Nb;
+    if (mp.b0 == mp.a1) {
+        f.P = buf(mp.off_RA);
+        f.Up = mp.U;
+        return TNSLQ_OK;
+    }
+    // the gap section S_G[m][g][n] and its tensor W[m][n][w]
+    if ((rc = mps_section(mp, T, T + mp.off[mp.a1], mp.Mb * mp.p[mp.a1], mp.a1 + 1, mp.b0, buf(mp.off_SG), s0, s1, st)))
+        return rc;
+    const double2 *SG = mp.b0 - mp.a1 > 1 ? buf(mp.off_SG) : T + mp.off[mp.a1];
+    TNSLQ_HIP(launch_swap01(SG, mp.Mb, mp.pG, mp.Nb, 1, 0, buf(mp.off_W), st));   // [m][n][g]
+    if (mp.compG) {
+        const int64_t n = mp.Mb * mp.Nb;
+        TNSLQ_HIP(launch_zgemm(0, 2, buf(mp.off_W), buf(mp.off_W), buf(mp.off_G), (int)n, (int)n, (int)mp.pG, mp.pG,
+                               mp.pG, n, 1, 0, 0, 0, st));
+        TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, st));
+        TNSLQ_HIP(hipMemcpyAsync(buf(mp.off_W), buf(mp.off_G), (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
+    }
+    // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)], then P[(kA, u)][w][n]
+    const int64_t nrow = mp.kA * mp.U;
+    TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_W), buf(mp.off_T1), (int)nrow, (int)(mp.Nb * mp.Wd),
+                           (int)mp.Mb, mp.Mb, mp.Nb * mp.Wd, mp.Nb * mp.Wd, 1, 0, 0, 0, st));
+    TNSLQ_HIP(launch_swap01(buf(mp.off_T1), nrow, mp.Nb, mp.Wd, 1, 0, buf(mp.off_P), st));
+    f.P = buf(mp.off_P);
+    f.Up = mp.U * mp.Wd;
+    return TNSLQ_OK;
+}
+
+// Read the factorisations' outcome (synchronises).
+int mps_check(const MpsPlan &mp, char *ws, hipStream_t st) {
+    int hf[4] = {0, 0, 0, 0};
+    TNSLQ_HIP(hipMemcpyAsync(hf, ws + mp.off_fail, sizeof hf, hipMemcpyDeviceToHost, st));
+    TNSLQ_HIP(hipStreamSynchronize(st));
+    static const char *what[4] = {"left environment", "right environment", "block A", "block B or the gap"};
+    for (int i = 0; i < 4; ++i)
+        if (hf[i]) return fail(TNSLQ_E_NONFINITE, "%s: matrix to factor is not finite", what[i]);
+    return TNSLQ_OK;
+}
+
 struct Ctx {
     Plan pl;
     char *ws;
@@ -411,6 +688,9 @@ struct Ctx {
     void *P1s, *P2s;
     void *Pabe, *Pabc, *Cd, *rho;
     double2 *Up, *U2, *Xs, *Xq, *Ym;
+    const MpsPlan *mp = nullptr;     // factorised MPS operator: its factor construction
+    MpsFactors mf{};
+    double2 *Z1, *Z2, *Z2p, *Z3;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -454,6 +734,11 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Cd = pl.expl ? c.ws + pl.off_Cd : nullptr;
     c.rho = pl.expl ? c.ws + pl.off_rho : nullptr;
     if (pl.expl) c.Paeb = c.Pbea = c.Ups = nullptr;
+    c.Z1 = (double2 *)(c.ws + pl.off_Z1);
+    c.Z2 = (double2 *)(c.ws + pl.off_Z2);
+    c.Z2p = (double2 *)(c.ws + pl.off_Z2p);
+    c.Z3 = (double2 *)(c.ws + pl.off_Z3);
+    if (pl.mpsf) c.Paeb = c.Pbea = c.Xt = c.Ups = nullptr;
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
     c.alpha = (double *)(c.ws + pl.off_alpha);
@@ -513,6 +798,25 @@ int form_rho(const Plan &pl, int prec, const void *psi, void *Pabe, void *Pabc, 
 
 int do_layout(Ctx &c, const void *psi) {
     const Plan &pl = c.pl;
+    if (pl.mpsf) {
+        // the factors P and Q of the two blocks (psi is the chain's tensors),
+        // then psi = P Q normalised through P: ||psi||^2 = Re sum Ahat conj(C)
+        // with Ahat = P^dagger P and C = Qp Qp^dagger over the bond index m
+        int rc;
+        char *mws = c.ws + pl.off_mps;
+        if ((rc = mps_build(*c.mp, (const double2 *)psi, mws, c.st, c.mf))) return rc;
+        MpsFactors &f = c.mf;
+        if (f.kA != pl.dA || f.kB != pl.dB || f.Up != pl.mUp || f.M != pl.mM || f.V != pl.mV)
+            return fail(TNSLQ_E_ARG, "factor shapes differ from the plan");
+        double2 *Ah = (double2 *)(c.ws + pl.off_nrm), *Cq = Ah + pl.mM * pl.mM;
+        double *nrm = (double *)(Cq + pl.mM * pl.mM);
+        const int M = (int)f.M;
+        const int64_t rowsP = f.kA * f.Up, colsQ = f.kB * f.V;
+        TNSLQ_HIP(launch_zgemm(2, 0, f.P, f.P, Ah, M, M, (int)rowsP, M, M, M, 1, 0, 0, 0, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 2, f.Qp, f.Qp, Cq, M, M, (int)colsQ, colsQ, colsQ, M, 1, 0, 0, 0, c.st));
+        TNSLQ_HIP(launch_normalise_factor(Ah, Cq, (int64_t)M * M, nrm, f.P, rowsP * M, c.st));
+        return mps_check(*c.mp, mws, c.st);
+    }
     if (pl.expl) {
         // intermediary (iii): rho^{T_B} formed once, as the brick operand of
         // every later matvec
@@ -655,6 +959,33 @@ int explicit_matvec(Ctx &c, hipEvent_t e1, hipEvent_t e2) {
     return TNSLQ_OK;
 }
 
+// rho^{T_B} of the two-block state psi[a][b][(u', v)] = sum_m P[a][u'][m]
+// Q[b][m][v] (Sec. VI) applied to probes [k0, k0 + kcur) without forming psi:
+//   Z1[k][(u', m')][b']     = sum_a' conj P[a'][(u', m')] X[k][a'][b']
+//   Z2[k][(u', m')][(m, v)] = sum_b' Z1[k][(u', m')][b'] Q[b'][(m, v)]
+//   Z2p[k][(u', m)][(m', v)]  (axes m and m' exchanged)
+//   Z3[k][a][(m', v)]       = sum_(u', m) P[a][(u', m)] Z2p[k][(u', m)][(m', v)]
+//   Y[k][a][b]              = sum_(m', v) Z3[k][a][(m', v)] conj Q[b][(m', v)]
+// i.e. Y[a][b] = sum_{a', b', e} psi[a][b'][e] conj psi[a'][b][e] X[a'][b'].
+int mps_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2) {
+    const Plan &pl = c.pl;
+    const MpsFactors &f = c.mf;
+    const int64_t n = pl.dAB, UpM = f.Up * f.M, MV = f.M * f.V;
+    const int kA = (int)f.kA, kB = (int)f.kB;
+    TNSLQ_HIP(launch_zgemm(2, 0, f.P, x, c.Z1, (int)UpM, kB, kA, UpM, kB, kB, kcur, 0, n, UpM * kB, c.st));
+    TNSLQ_HIP(launch_zgemm(0, 0, c.Z1, f.Q, c.Z2, (int)UpM, (int)MV, kB, kB, MV, MV, kcur, UpM * kB, 0, UpM * MV,
+                           c.st));
+    if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+    TNSLQ_HIP(launch_swap01(c.Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, 0, c.Z2p, c.st));
+    TNSLQ_HIP(launch_zgemm(0, 0, f.P, c.Z2p, c.Z3, kA, (int)MV, (int)UpM, UpM, MV, MV, kcur, 0, UpM * MV, kA * MV,
+                           c.st));
+    TNSLQ_HIP(launch_zgemm(0, 2, c.Z3, f.Q, (double2 *)c.Ypart, kA, kB, (int)MV, MV, MV, kB, kcur, kA * MV, 0, n,
+                           c.st));
+    if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+    c.n_launch++;
+    return TNSLQ_OK;
+}
+
 // Events of one Lanczos step: mv0, then per probe chunk (after contraction 1,
 // after contraction 2, after the merge), then mv1 (matvec done), lz1.
 struct StepEvents {
@@ -681,7 +1012,9 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     TNSLQ_HIP(hipEventRecord(se->mv0(), c.st));
     for (int k0 = 0, ch = 0; k0 < pl.K; k0 += pl.kc, ++ch) {
         const int kcur = std::min(pl.kc, pl.K - k0);
-        if (pl.expl) {
+        if (pl.mpsf) {
+            if ((rc = mps_matvec(c, q_cur + (int64_t)k0 * n, kcur, se->c1(ch), se->c2(ch)))) return rc;
+        } else if (pl.expl) {
             if ((rc = explicit_matvec(c, se->c1(ch), se->c2(ch)))) return rc;
         } else if (pl.stream) {
             if ((rc = stream_contract(c, q_cur, se->c1(ch), se->c2(ch)))) return rc;
@@ -1567,165 +1900,6 @@ int tnslq_rho_pt_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
 }
 
 // ------------------------------------------------------------ MPS blocks
-namespace {
-int64_t ceil_pow2_log(int64_t x) {
-    int q = 0;
-    while ((int64_t(1) << q) < x) ++q;
-    return q;
-}
-
-// Sizes and workspace of the effective state of two contiguous blocks of an
-// open-boundary MPS (Sec. VI); see tnslq_mps_effective_state.
-struct MpsPlan {
-    int L = 0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-    std::vector<int> p, bond;
-    std::vector<int64_t> off;          // element offset of each site's tensor
-    int64_t U = 1, Mb = 1, Nb = 1, V = 1, pA = 1, pB = 1, pG = 1;
-    int compA = 0, compB = 0, compG = 0;
-    int64_t kA = 1, kB = 1, Wd = 1;
-    int q[3] = {0, 0, 0};
-    int64_t smax = 1, gmax = 1, maxb = 1;
-    size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_G, off_RA, off_RB, off_RBp, off_W, off_T1,
-        off_T, off_part, off_fail, total = 0;
-};
-
-int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp) {
-    if (!m) return fail(TNSLQ_E_ARG, "mps is NULL");
-    const int L = m->n_sites;
-    if (L < 2 || L > 100000) return fail(TNSLQ_E_ARG, "n_sites %d outside [2, 100000]", L);
-    if (!m->phys || !m->bond) return fail(TNSLQ_E_ARG, "phys or bond is NULL");
-    if (m->bond[0] != 1 || m->bond[L] != 1) return fail(TNSLQ_E_ARG, "open boundaries need bond[0] = bond[n] = 1");
-    if (a0 < 0 || na < 1 || nb < 1 || a0 + na > b0 || b0 + nb > L)
-        return fail(TNSLQ_E_PARTITION, "blocks [%d, %d) and [%d, %d) not ordered inside the chain", a0, a0 + na, b0,
-                    b0 + nb);
-    mp = MpsPlan();
-    mp.L = L;
-    mp.a0 = a0;
-    mp.a1 = a0 + na;
-    mp.b0 = b0;
-    mp.b1 = b0 + nb;
-    mp.p.assign(m->phys, m->phys + L);
-    mp.bond.assign(m->bond, m->bond + L + 1);
-    mp.off.resize(L + 1);
-    mp.off[0] = 0;
-    for (int i = 0; i < L; ++i) {
-        if (mp.p[i] < 2 || mp.p[i] > 65536) return fail(TNSLQ_E_ARG, "site %d: phys %d outside [2, 65536]", i, mp.p[i]);
-        if (mp.bond[i + 1] < 1 || mp.bond[i + 1] > 4096)
-            return fail(TNSLQ_E_ARG, "bond %d: %d outside [1, 4096]", i + 1, mp.bond[i + 1]);
-        mp.off[i + 1] = mp.off[i] + (int64_t)mp.bond[i] * mp.p[i] * mp.bond[i + 1];
-        mp.maxb = std::max<int64_t>(mp.maxb, mp.bond[i + 1]);
-    }
-    const int64_t LIM = int64_t(1) << 40;
-    auto prod = [&](int i0, int i1, int64_t &out) {
-        out = 1;
-        for (int i = i0; i < i1; ++i) {
-            if (out > LIM / mp.p[i]) return false;
-            out *= mp.p[i];
-        }
-        return true;
-    };
-    if (!prod(mp.a0, mp.a1, mp.pA) || !prod(mp.b0, mp.b1, mp.pB) || !prod(mp.a1, mp.b0, mp.pG))
-        return fail(TNSLQ_E_ARG, "a block's physical dimension exceeds 2^40");
-    mp.U = mp.bond[mp.a0];
-    mp.Mb = mp.bond[mp.a1];
-    mp.Nb = mp.bond[mp.b0];
-    mp.V = mp.bond[mp.b1];
-    mp.compA = mp.pA > mp.U * mp.Mb;
-    mp.compB = mp.pB > mp.Nb * mp.V;
-    mp.kA = mp.compA ? mp.U * mp.Mb : mp.pA;
-    mp.kB = mp.compB ? mp.Nb * mp.V : mp.pB;
-    if (mp.b0 > mp.a1) {
-        mp.compG = mp.pG > mp.Mb * mp.Nb;
-        mp.Wd = mp.compG ? mp.Mb * mp.Nb : mp.pG;
-    }
-    // section sizes while they are built (left bond x physical so far x bond)
-    auto sec_max = [&](int i0, int i1, int64_t left) {
-        int64_t f = 1, mx = 0;
-        for (int i = i0; i < i1; ++i) {
-            f *= mp.p[i];
-            mx = std::max(mx, left * f * mp.bond[i + 1]);
-        }
-        return mx;
-    };
-    mp.smax = std::max({sec_max(mp.a0, mp.a1, mp.U), sec_max(mp.b0, mp.b1, mp.Nb), mp.Nb * mp.pB * mp.V,
-                        mp.b0 > mp.a1 ? sec_max(mp.a1, mp.b0, mp.Mb) : int64_t(1)});
-    if (mp.smax > (int64_t(1) << 31)) return fail(TNSLQ_E_ARG, "a block section has more than 2^31 entries");
-    const int64_t chol = std::max({mp.compA ? mp.U * mp.Mb : 0, mp.compB ? mp.Nb * mp.V : 0,
-                                   mp.compG ? mp.Mb * mp.Nb : 0, mp.U, mp.V});
-    if (chol > 4096) return fail(TNSLQ_E_ARG, "a factored matrix would be %lld wide (at most 4096)", (long long)chol);
-    mp.gmax = std::max<int64_t>(1, chol * chol);
-    mp.q[0] = (int)ceil_pow2_log(mp.kA);
-    mp.q[1] = (int)ceil_pow2_log(mp.kB);
-    mp.q[2] = (int)ceil_pow2_log(mp.U * mp.Wd * mp.V);
-    if (mp.q[0] + mp.q[1] + mp.q[2] > 32)
-        return fail(TNSLQ_E_ARG, "the effective state would need %d qubits (at most 32)", mp.q[0] + mp.q[1] + mp.q[2]);
-    size_t o = 0;
-    auto take = [&](int64_t n) {
-        size_t r = o;
-        o += up((size_t)n * 16);
-        return r;
-    };
-    const int64_t e2 = mp.maxb * mp.maxb;
-    mp.off_El[0] = take(e2);
-    mp.off_El[1] = take(e2);
-    mp.off_Er[0] = take(e2);
-    mp.off_Er[1] = take(e2);
-    mp.off_S[0] = take(mp.smax);
-    mp.off_S[1] = take(mp.smax);
-    mp.off_S[2] = take(mp.smax);
-    mp.off_SA = take(mp.U * mp.pA * mp.Mb);
-    mp.off_SB = take(mp.Nb * mp.pB * mp.V);
-    mp.off_SG = take(mp.b0 > mp.a1 ? mp.Mb * mp.pG * mp.Nb : 1);
-    mp.off_G = take(mp.gmax);
-    mp.off_RA = take(mp.kA * mp.U * mp.Mb);
-    mp.off_RB = take(mp.kB * mp.Nb * mp.V);
-    mp.off_RBp = take(mp.kB * mp.Nb * mp.V);
-    mp.off_W = take(mp.Mb * mp.Nb * mp.Wd);
-    mp.off_T1 = take(mp.kA * mp.U * mp.Nb * mp.Wd);
-    mp.off_T = take(mp.kA * mp.U * mp.Wd * mp.kB * mp.V);
-    mp.off_part = o;
-    o += up(257 * 8);
-    mp.off_fail = o;
-    o += up(4 * 4);
-    mp.total = o;
-    return TNSLQ_OK;
-}
-
-// Contract the sites [i0, i1) onto the running section S (rows r = left bond
-// x physical so far, columns = bond), starting from S0 (rows0 x bond[i0]);
-// the result lands in `out`.
-int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t rows0, int i0, int i1, double2 *out,
-                double2 *scratch0, double2 *scratch1, hipStream_t st) {
-    const double2 *cur = S0;
-    int64_t rows = rows0;
-    for (int i = i0; i < i1; ++i) {
-        const int64_t z = mp.bond[i], py = (int64_t)mp.p[i] * mp.bond[i + 1];
-        double2 *dst = i + 1 == i1 ? out : ((i - i0) % 2 ? scratch1 : scratch0);
-        TNSLQ_HIP(launch_zgemm(0, 0, cur, T + mp.off[i], dst, (int)rows, (int)py, (int)z, z, py, py, 1, 0, 0, 0, st));
-        cur = dst;
-        rows *= mp.p[i];
-    }
-    return TNSLQ_OK;
-}
-
-// R[k][(l, r)] for a section S[l][phys][r]: S itself with its first two axes
-// exchanged, or (compressed) R = L^dagger with L L^dagger = S^dagger S over
-// the physical index.
-int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, double2 *R, double2 *tmp, double2 *G,
-                 int *failp, hipStream_t st) {
-    if (!comp) {
-        TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, R, st));
-        return TNSLQ_OK;
-    }
-    const int64_t n = l * r;
-    TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, tmp, st));   // [phys][(l r)]
-    TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
-    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, st));
-    TNSLQ_HIP(launch_swap01(G, 1, n, n, 1, 1, R, st));
-    return TNSLQ_OK;
-}
-}  // namespace
-
 int tnslq_mps_effective_state_size(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, int *q, size_t *ws_bytes) {
     int rc;
     g_err.clear();
@@ -1748,85 +1922,81 @@ int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int
     if (ws_bytes < mp.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, mp.total);
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)ws_dev;
-    auto buf = [&](size_t off) { return (double2 *)(ws + off); };
-    const double2 *T = (const double2 *)mps->tensors;
-    int *failp = (int *)(ws + mp.off_fail);
-    TNSLQ_HIP(hipMemsetAsync(failp, 0, 16, st));
-    static const double2 one = {1.0, 0.0};
-    // traced environments: E_L on the bond entering A, E_R on the bond leaving B
-    double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
-    TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
-    for (int i = 0; i < mp.a0; ++i) {
-        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, st));
-        std::swap(El, Eln);
-    }
-    double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
-    TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
-    for (int i = mp.L - 1; i >= mp.b1; --i) {
-        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, st));
-        std::swap(Er, Ern);
-    }
-    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, st));       // X[x][u]
-    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, st));   // Y[y][v]
-    double2 *s0 = buf(mp.off_S[0]), *s1 = buf(mp.off_S[1]), *s2 = buf(mp.off_S[2]);
-    // block A with X absorbed: S_A[u][a][m], from X^T (rows u, columns x)
-    TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Eln, st));
-    if ((rc = mps_section(mp, T, Eln, mp.U, mp.a0, mp.a1, buf(mp.off_SA), s0, s1, st))) return rc;
-    // block B, then Y absorbed: S_B[n][b][v]
-    if ((rc = mps_section(mp, T, T + mp.off[mp.b0], mp.Nb * mp.p[mp.b0], mp.b0 + 1, mp.b1, s2, s0, s1, st))) return rc;
-    const double2 *SBy = mp.b1 - mp.b0 > 1 ? s2 : T + mp.off[mp.b0];
-    TNSLQ_HIP(launch_zgemm(0, 0, SBy, Er, buf(mp.off_SB), (int)(mp.Nb * mp.pB), (int)mp.V, mp.bond[mp.b1],
-                           mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
-    // vertical decompositions
-    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), failp + 2,
-                           st)))
-        return rc;
-    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), failp + 3,
-                           st)))
-        return rc;
-    TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
-    const int64_t nrow = mp.kA * mp.U, ncol = mp.kB * mp.V;
-    double2 *Tout = buf(mp.off_T);
-    if (mp.b0 == mp.a1) {
-        // adjacent blocks: psi[(kA, u)][(kB, v)] = sum_m R_A[(kA, u)][m] R_B[m][(kB, v)]
-        TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_RBp), Tout, (int)nrow, (int)ncol, (int)mp.Mb, mp.Mb,
-                               ncol, ncol, 1, 0, 0, 0, st));
-    } else {
-        // the gap section S_G[m][g][n] and its tensor W[m][n][w]
-        if ((rc = mps_section(mp, T, T + mp.off[mp.a1], mp.Mb * mp.p[mp.a1], mp.a1 + 1, mp.b0, buf(mp.off_SG), s0, s1,
-                              st)))
-            return rc;
-        const double2 *SG = mp.b0 - mp.a1 > 1 ? buf(mp.off_SG) : T + mp.off[mp.a1];
-        TNSLQ_HIP(launch_swap01(SG, mp.Mb, mp.pG, mp.Nb, 1, 0, buf(mp.off_W), st));   // [m][n][g]
-        if (mp.compG) {
-            const int64_t n = mp.Mb * mp.Nb;
-            TNSLQ_HIP(launch_zgemm(0, 2, buf(mp.off_W), buf(mp.off_W), buf(mp.off_G), (int)n, (int)n, (int)mp.pG, mp.pG,
-                                   mp.pG, n, 1, 0, 0, 0, st));
-            TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, st));
-            TNSLQ_HIP(hipMemcpyAsync(buf(mp.off_W), buf(mp.off_G), (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
-        }
-        // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)]
-        TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_W), buf(mp.off_T1), (int)nrow, (int)(mp.Nb * mp.Wd),
-                               (int)mp.Mb, mp.Mb, mp.Nb * mp.Wd, mp.Nb * mp.Wd, 1, 0, 0, 0, st));
-        // psi[(kA, u)][w][(kB, v)] = sum_n T1[(kA, u)][n][w] R_B[n][(kB, v)], batched over (kA, u)
-        for (int64_t b0c = 0; b0c < nrow; b0c += 65535) {
-            const int nb = (int)std::min<int64_t>(65535, nrow - b0c);
-            TNSLQ_HIP(launch_zgemm(1, 0, buf(mp.off_T1) + b0c * mp.Nb * mp.Wd, buf(mp.off_RBp),
-                                   Tout + b0c * mp.Wd * ncol, (int)mp.Wd, (int)ncol, (int)mp.Nb, mp.Wd, ncol, ncol, nb,
-                                   mp.Nb * mp.Wd, 0, mp.Wd * ncol, st));
-        }
-    }
+    MpsFactors f;
+    if ((rc = mps_build(mp, (const double2 *)mps->tensors, ws, st, f))) return rc;
+    // psi[(kA, u')][(kB, v)] = sum_m P[(kA, u')][m] Qp[m][(kB, v)]
+    const int64_t nrow = f.kA * f.Up, ncol = f.kB * f.V;
+    double2 *Tout = (double2 *)(ws + mp.off_T);
+    TNSLQ_HIP(launch_zgemm(0, 0, f.P, f.Qp, Tout, (int)nrow, (int)ncol, (int)f.M, f.M, ncol, ncol, 1, 0, 0, 0, st));
     double *part = (double *)(ws + mp.off_part);
-    TNSLQ_HIP(launch_sumsq(Tout, nrow * mp.Wd * ncol, part, st));
+    TNSLQ_HIP(launch_sumsq(Tout, nrow * ncol, part, st));
     TNSLQ_HIP(launch_assemble(Tout, mp.kA, mp.U, mp.Wd, mp.kB, mp.V, int64_t(1) << mp.q[0], int64_t(1) << mp.q[1],
                               int64_t(1) << mp.q[2], part + 256, (double2 *)psi_dev, st));
-    int hf[4] = {0, 0, 0, 0};
-    TNSLQ_HIP(hipMemcpyAsync(hf, failp, sizeof hf, hipMemcpyDeviceToHost, st));
-    TNSLQ_HIP(hipStreamSynchronize(st));
-    static const char *what[4] = {"left environment", "right environment", "block A", "block B or the gap"};
-    for (int i = 0; i < 4; ++i)
-        if (hf[i]) return fail(TNSLQ_E_NONFINITE, "%s: matrix to factor is not finite", what[i]);
+    return mps_check(mp, ws, st);
+}
+
+// Plan of Algorithm 1 on the two-block operator in factorised form: the
+// Lanczos vectors run over (a, b) of the blocks' compressed physical indices.
+static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt, MpsPlan &mp,
+                   Plan &pl) {
+    int rc;
+    if ((rc = check_options(opt))) return rc;
+    if (opt->precision != TNSLQ_FP64)
+        return fail(TNSLQ_E_ARG, "the factorised MPS operator computes in FP64: precision must be TNSLQ_FP64");
+    if (opt->operator_form != TNSLQ_OPERATOR_AUTO)
+        return fail(TNSLQ_E_ARG, "operator_form must be TNSLQ_OPERATOR_AUTO for MPS blocks");
+    if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp, false))) return rc;
+    pl = Plan();
+    pl.mpsf = 1;
+    pl.dtype = TNSLQ_C128;
+    pl.prec = TNSLQ_FP64;
+    pl.K = opt->n_probes;
+    pl.m = opt->n_steps;
+    pl.reorth = opt->reorth;
+    const bool gap = mp.b0 > mp.a1;
+    pl.dA = mp.kA;
+    pl.dB = mp.kB;
+    pl.dAB = mp.kA * mp.kB;
+    pl.mUp = gap ? mp.U * mp.Wd : mp.U;
+    pl.mM = gap ? mp.Nb : mp.Mb;
+    pl.mV = mp.V;
+    pl.dE = pl.mUp * pl.mV;
+    pl.D = pl.dAB * pl.dE;
+    pl.mps_bytes = mp.total;
+    return plan_rest(pl, TNSLQ_C128, TNSLQ_FP64, pl.K, 1);
+}
+
+int tnslq_workspace_bytes_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt,
+                              size_t *bytes) {
+    int rc;
+    g_err.clear();
+    if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
+    MpsPlan mp;
+    Plan pl;
+    if ((rc = make_plan_mpsf(mps, a0, n_a, b0, n_b, opt, mp, pl))) return rc;
+    *bytes = pl.total;
     return TNSLQ_OK;
+}
+
+int tnslq_logneg_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt, void *ws_dev,
+                     size_t ws_bytes, void *stream, tnslq_result *res, double *G_host, double *alpha_host,
+                     double *beta_host, double *F_host, int *steps_host) {
+    Timer tm;
+    int rc;
+    g_err.clear();
+    if (!res) return fail(TNSLQ_E_ARG, "result is NULL");
+    MpsPlan mp;
+    Run r;
+    if ((rc = make_plan_mpsf(mps, a0, n_a, b0, n_b, opt, mp, r.c.pl))) return rc;
+    if (!mps->tensors) return fail(TNSLQ_E_ARG, "tensors is NULL");
+    const bool loop = opt->max_probes > opt->n_probes;
+    if (loop && (alpha_host || beta_host || F_host || steps_host))
+        return fail(TNSLQ_E_ARG, "with max_probes > n_probes only G_host may be requested");
+    r.c.mp = &mp;
+    if ((rc = run_start(r, opt, mps->tensors, ws_dev, ws_bytes, stream))) return rc;
+    if (loop) return run_probe_loop(r, opt, res, G_host, tm);
+    if ((rc = run_steps(r, opt->n_steps, opt->stop_tol))) return rc;
+    return run_finish(r, res, G_host, alpha_host, beta_host, F_host, steps_host, tm);
 }
 
 int tnslq_quadrature(const double *alpha_dev, const double *beta_dev, const int *steps_dev, int n_probes, int n_steps,

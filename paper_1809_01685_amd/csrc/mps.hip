@@ -8,8 +8,8 @@
 //   * Cholesky factors of positive matrices (environments, Gram matrices of
 //     the blocks and of the gap), column by column in one block;
 //   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
-//     (16 x 16 output tiles staged through LDS), for the block sections, their
-//     Gram matrices and the effective state;
+//     (64 x 64 output tiles staged through LDS), for the block sections, their
+//     Gram matrices, the effective state and the factorised operator;
 //   * an axis exchange, and the final scatter of the effective state into a
 //     zero-padded power-of-two layout, normalised.
 // The host side (api.hip) plans the sizes and sequences these launches.
@@ -112,49 +112,79 @@ __global__ void __launch_bounds__(1024) k_cholesky(double2 *__restrict__ A, int 
 
 // C[b] = op(A[b]) op(B[b]) for complex row-major matrices: op(A) is M x K,
 // op(B) is K x N; OP = 0 (as stored), 1 (transpose), 2 (conjugate transpose);
-// lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.
+// lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.  A block
+// of 256 threads computes a 64 x 64 tile, 4 x 4 outputs per thread, staging
+// 64 x 8 slices of op(A) and 8 x 64 of op(B) through LDS.
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, const double2 *__restrict__ B,
                                                double2 *__restrict__ C, int M, int N, int K, int64_t lda,
                                                int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc) {
-    constexpr int TS = 16;
-    __shared__ double2 As[TS][TS + 1], Bs[TS][TS + 1];
+    constexpr int TM = 64, TN = 64, TK = 8;
+    __shared__ double2 As[TK][TM + 1], Bs[TK][TN + 1];
     const int64_t b = blockIdx.z;
     A += b * sa;
     B += b * sb;
     C += b * sc;
-    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    const int row = blockIdx.y * TS + ty, col = blockIdx.x * TS + tx;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int k0 = 0; k0 < K; k0 += TS) {
-        // op(A)[row][k0 + tx] and op(B)[k0 + ty][col]
-        {
-            const int r = blockIdx.y * TS + ty, k = k0 + tx;
-            double2 v = make_double2(0.0, 0.0);
-            if (r < M && k < K) {
-                v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
-                if (OPA == 2) v = cconj(v);
+    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+    const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        // 512 entries of each slice, two per thread
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = t + 256 * q;
+            {
+                // op(A)[r0 + rr][k0 + kk]
+                const int rr = OPA == 0 ? e / TK : e % TM, kk = OPA == 0 ? e % TK : e / TM;
+                const int r = r0 + rr, k = k0 + kk;
+                double2 v = make_double2(0.0, 0.0);
+                if (r < M && k < K) {
+                    v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
+                    if (OPA == 2) v = cconj(v);
+                }
+                As[kk][rr] = v;
             }
-            As[ty][tx] = v;
-        }
-        {
-            const int k = k0 + ty, c = blockIdx.x * TS + tx;
-            double2 v = make_double2(0.0, 0.0);
-            if (k < K && c < N) {
-                v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
-                if (OPB == 2) v = cconj(v);
+            {
+                // op(B)[k0 + kk][c0 + cc]
+                const int cc = OPB == 0 ? e % TN : e / TK, kk = OPB == 0 ? e / TN : e % TK;
+                const int c = c0 + cc, k = k0 + kk;
+                double2 v = make_double2(0.0, 0.0);
+                if (c < N && k < K) {
+                    v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
+                    if (OPB == 2) v = cconj(v);
+                }
+                Bs[kk][cc] = v;
             }
-            Bs[ty][tx] = v;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < TS; ++kk) {
-            const double2 q = cmul(As[ty][kk], Bs[kk][tx]);
-            acc = make_double2(acc.x + q.x, acc.y + q.y);
+        for (int kk = 0; kk < TK; ++kk) {
+            double2 av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
+                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
+                }
         }
         __syncthreads();
     }
-    if (row < M && col < N) C[(int64_t)row * ldc + col] = acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+            if (r < M && c < N) C[(int64_t)r * ldc + c] = acc[i][j];
+        }
 }
 
 // out[b][j][i][k] = in[b][i][j][k] for nb tensors of shape (n0, n1, n2)
@@ -195,6 +225,30 @@ __global__ void k_sum_parts(double *__restrict__ part, int n) {
 // The effective state: from T[(kA, u)][w][(kB, v)] into psi[(a, b, e)] with
 // zero padding to dA2 x dB2 x dE2 (powers of two), e = (u W + w) V + v, all
 // scaled by 1 / sqrt(sumsq).
+// s = Re sum_i A[i] conj(C[i]) over n entries (one block), written to out[0].
+__global__ void __launch_bounds__(256) k_dot_re(const double2 *__restrict__ A, const double2 *__restrict__ C,
+                                                int64_t n, double *__restrict__ out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 256) s += A[e].x * C[e].x + A[e].y * C[e].y;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// x *= 1 / sqrt(s[0])
+__global__ void __launch_bounds__(256) k_scale_rsqrt(double2 *__restrict__ x, int64_t n, const double *__restrict__ s) {
+    const double f = 1.0 / sqrt(s[0]);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        x[e].x *= f;
+        x[e].y *= f;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_assemble(const double2 *__restrict__ T, int64_t kA, int64_t U, int64_t W,
                                                   int64_t kB, int64_t V, int64_t dB2, int64_t dE2, int64_t total,
                                                   const double *__restrict__ sumsq, double2 *__restrict__ psi) {
@@ -246,12 +300,12 @@ hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, do
                         hipStream_t st) {
     if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
     // rows in chunks of 65535 tiles (the grid's y limit)
-    constexpr int64_t RCH = 65535 * 16;
+    constexpr int64_t RCH = 65535 * 64;
     for (int64_t r0 = 0; r0 < M; r0 += RCH) {
         const int m = (int)(M - r0 < RCH ? M - r0 : RCH);
         const double2 *Ac = opa == 0 ? A + r0 * lda : A + r0;
         double2 *Cc = C + r0 * ldc;
-        dim3 grid((unsigned)((N + 15) / 16), (unsigned)((m + 15) / 16), (unsigned)batch), block(256);
+        dim3 grid((unsigned)((N + 63) / 64), (unsigned)((m + 63) / 64), (unsigned)batch), block(256);
 #define TNSLQ_ZG(OA, OB) \
     hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc)
         if (opa == 0 && opb == 0) TNSLQ_ZG(0, 0);
@@ -277,6 +331,15 @@ hipError_t launch_sumsq(const double2 *x, int64_t n, double *part, hipStream_t s
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1), 0, st, part, 256);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalise_factor(const double2 *Ahat, const double2 *C, int64_t mm, double *nrm, double2 *P,
+                                   int64_t np, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_re, dim3(1), dim3(256), 0, st, Ahat, C, mm, nrm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scale_rsqrt, dim3(blocks_for(np)), dim3(256), 0, st, P, np, nrm);
     return hipGetLastError();
 }
 

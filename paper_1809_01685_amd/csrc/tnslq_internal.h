@@ -52,6 +52,9 @@ struct Plan {
     int expl = 0;                    // rho^{T_B} formed explicitly (intermediary (iii))
     int64_t nst_rho = 1;             // bricks along the reduction index of the explicit matvec
     int64_t nst_e = 1;               // bricks along E of the forming product
+    int mpsf = 0;                    // two-block MPS operator in factorised form (Sec. VI)
+    int64_t mUp = 1, mM = 1, mV = 1; // its factors P[a][u'][m], Q[b][m][v]
+    size_t mps_bytes = 0;            // workspace of the factor construction
     int mixed = 0;                   // sites of general local dimension (explicit form only)
     MixedDesc md;                    // their regrouping
     int nblk = 1;                    // reduction blocks per probe vector
@@ -61,6 +64,7 @@ struct Plan {
     size_t off_P1s = 0, off_P2s = 0, off_Up = 0, off_U2 = 0, off_Xs = 0;
     size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, off_rho = 0;
     size_t off_Xq = 0, off_Ym = 0;
+    size_t off_mps = 0, off_Z1 = 0, off_Z2 = 0, off_Z2p = 0, off_Z3 = 0, off_nrm = 0;
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -204,6 +208,12 @@ hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, 
 hipError_t launch_sumsq(const double2 *x, int64_t n, double *part, hipStream_t st);
 // psi[(a, b, e)] (dA2 x dB2 x dE2, zero padded) = T[(a, u)][w][(b, v)] /
 // sqrt(*sumsq), e = (u W + w) V + v.
+// Normalisation of a two-factor state psi = P Q: with Ahat = P^dagger P and
+// C = Q Q^dagger (both mm entries, the same index order), nrm[0] =
+// Re sum Ahat conj(C) = ||psi||^2, and the np entries of P are divided by its
+// square root.
+hipError_t launch_normalise_factor(const double2 *Ahat, const double2 *C, int64_t mm, double *nrm, double2 *P,
+                                   int64_t np, hipStream_t st);
 hipError_t launch_assemble(const double2 *T, int64_t kA, int64_t U, int64_t W, int64_t kB, int64_t V, int64_t dA2,
                            int64_t dB2, int64_t dE2, const double *sumsq, double2 *psi, hipStream_t st);
 

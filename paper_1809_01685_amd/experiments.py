@@ -293,37 +293,59 @@ def run_hbm_peak(reps=10, seed=0):
     return {"workload": "HBM yardstick on one MI355X", "rows": out}
 
 
-def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3"):
+def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("dense", "factored")):
+    """Two blocks of a 100-site random MPS: the dense route (effective state,
+    then tnslq_logneg in `precision`) against the factorised operator (FP64),
+    both with the fit rule and a 1% target."""
     import torch
     import tnslq_inputs as ti
-    from . import tnslq_logneg, tnslq_mps_effective_state
+    from . import tnslq_logneg, tnslq_logneg_mps, tnslq_mps_effective_state
     dev = torch.device("cuda:0")
     rows = []
-    for chi, a0, la, b0, lb in ((16, 34, 16, 50, 16), (32, 34, 16, 50, 16), (16, 32, 16, 52, 16)):
+    # the last flag: the dense route as well (the gap rows' effective states
+    # would need 2^32 amplitudes or more)
+    for chi, a0, la, b0, lb, dense in ((16, 34, 16, 50, 16, True), (32, 34, 16, 50, 16, True),
+                                       (16, 32, 16, 52, 16, True), (32, 33, 16, 50, 16, False),
+                                       (64, 42, 8, 50, 8, True), (64, 41, 8, 50, 8, False)):
         ts = ti.random_mps(100, 2, chi, seed)
-        tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)      # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        psi, q = tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)
-        torch.cuda.synchronize()
-        t_eff = time.perf_counter() - t0
-        qa, qb, qe = q
-        t0 = time.perf_counter()
-        r = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps,
-                         precision=precision, seed=seed, stop_tol=0.01, stop_rule="fit", want_arrays=False)
-        t_ln = time.perf_counter() - t0
-        row = {"n_sites": 100, "chi": chi, "A": [a0, a0 + la], "B": [b0, b0 + lb], "gap": b0 - a0 - la,
-               "effective_qubits": list(q), "t_effective_state_s": t_eff, "t_logneg_s": t_ln,
-               "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_err": r["lanczos_err"],
-               "steps": r["steps_done"], "explicit_operator": bool(r["explicit_operator"])}
+        row = {"n_sites": 100, "chi": chi, "A": [a0, a0 + la], "B": [b0, b0 + lb], "gap": b0 - a0 - la}
+        if "dense" in routes and dense:
+            tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psi, q = tnslq_mps_effective_state(ts, a0, la, b0, lb, device=dev)
+            torch.cuda.synchronize()
+            t_eff = time.perf_counter() - t0
+            qa, qb, qe = q
+            t0 = time.perf_counter()
+            r = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps,
+                             precision=precision, seed=seed, stop_tol=0.01, stop_rule="fit", want_arrays=False)
+            t_ln = time.perf_counter() - t0
+            row.update({"effective_qubits": list(q), "t_effective_state_s": t_eff, "t_logneg_s": t_ln,
+                        "logneg": r["logneg"], "logneg_se": r["logneg_se"], "lanczos_err": r["lanczos_err"],
+                        "steps": r["steps_done"], "explicit_operator": bool(r["explicit_operator"])})
+            print(f"[mps_blocks] chi {chi}, A {row['A']}, B {row['B']}: dense: effective state {q} in "
+                  f"{t_eff:.3f} s, E = {r['logneg']:.4f} +- {r['logneg_se']:.4f} after {r['steps_done']} steps "
+                  f"in {t_ln:.3f} s", file=sys.stderr, flush=True)
+            del psi
+            torch.cuda.empty_cache()
+        if "factored" in routes:
+            tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, 10, device=dev, seed=seed, want_arrays=False)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, n_steps, device=dev, seed=seed, stop_tol=0.01,
+                                 stop_rule="fit", want_arrays=False)
+            t_f = time.perf_counter() - t0
+            row["factored"] = {"t_total_s": t_f, "t_layout_ms": f["t_layout_ms"], "t_matvec_ms": f["t_matvec_ms"],
+                               "steps": f["steps_done"], "logneg": f["logneg"], "logneg_se": f["logneg_se"],
+                               "lanczos_err": f["lanczos_err"], "workspace_bytes": f["workspace_bytes"]}
+            print(f"[mps_blocks] chi {chi}, A {row['A']}, B {row['B']}: factored: E = {f['logneg']:.4f} +- "
+                  f"{f['logneg_se']:.4f} after {f['steps_done']} steps in {t_f:.3f} s (factors "
+                  f"{f['t_layout_ms']:.1f} ms, matvecs {f['t_matvec_ms']:.1f} ms)", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
         rows.append(row)
-        print(f"[mps_blocks] chi {chi}, A {row['A']}, B {row['B']}: effective state {q} in {t_eff:.3f} s, "
-              f"E = {r['logneg']:.4f} +- {r['logneg_se']:.4f} after {r['steps_done']} steps in {t_ln:.3f} s",
-              file=sys.stderr, flush=True)
-        del psi
-        torch.cuda.empty_cache()
-    return {"workload": "100-site random open-boundary MPS (qubits), two 16-site blocks", "precision": precision,
-            "rows": rows}
+    return {"workload": "100-site random open-boundary MPS (qubits), two blocks of 8 or 16 sites",
+            "precision_dense": precision, "precision_factored": "fp64", "rows": rows}
 
 
 def _parse_range(s):
@@ -346,14 +368,15 @@ def main(argv=None):
     hs.add_argument("--steps", type=int, default=10)
     sub.add_parser("operator_forms")
     sub.add_parser("hbm_peak")
-    sub.add_parser("mps_blocks")
+    sp = sub.add_parser("mps_blocks")
+    sp.add_argument("--routes", default="dense,factored")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
     elif args.cmd == "mps_blocks":
-        out = run_mps_blocks()
+        out = run_mps_blocks(routes=tuple(args.routes.split(",")))
     elif args.cmd == "hbm_peak":
         out = run_hbm_peak()
     elif args.cmd == "operator_forms":

@@ -249,3 +249,28 @@ def test_mps_sizes_and_validation_without_device(L):
     bad[0] = 2
     assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bad)), 2, 4, 6, 4, q, C.byref(n)) == -1
     assert L.tnslq_mps_effective_state(C.byref(desc(phys, bond)), 2, 4, 6, 4, None, None, 0, None) == -1
+
+
+def test_factored_mps_workspace_and_validation_without_device(L):
+    import ctypes as C
+    # the same chain: the factorised route needs no room for the dense state
+    phys, bond = [2] * 12, [1, 2, 4, 4, 4, 4, 4, 4, 4, 4, 4, 2, 1]
+    tensors = [np.zeros((bond[i], 2, bond[i + 1])) for i in range(12)]
+    o = T.make_options(8, 20, precision="fp64")
+    n = T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, o)
+    # Lanczos vectors of d_A' d_B' = 256 entries: three slots of 8 probes at least
+    assert n >= 3 * 8 * 256 * 16
+    # more probes need more room; reorthogonalisation keeps every vector
+    assert T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, T.make_options(16, 20, precision="fp64")) > n
+    assert T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, T.make_options(8, 20, True, precision="fp64")) > n
+    for bad in (T.make_options(8, 20, precision="fp32"), T.make_options(8, 20, precision="fp64", operator="lazy")):
+        with pytest.raises(T.TnslqError):
+            T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, bad)
+    with pytest.raises(T.TnslqError):
+        T.tnslq_workspace_bytes_mps(tensors, 6, 4, 2, 4, o)
+    desc = T._mps_desc(tensors)
+    res = T.Result()
+    assert L.tnslq_logneg_mps(C.byref(desc), 2, 4, 6, 4, C.byref(o), None, 0, None, C.byref(res), None, None, None,
+                              None, None) == -1         # tensors NULL
+    assert L.tnslq_logneg_mps(C.byref(desc), 2, 4, 6, 4, C.byref(o), None, 0, None, None, None, None, None, None,
+                              None) == -1               # result NULL

@@ -7,6 +7,11 @@ the device's matches the oracle's entry by entry: 1e-11 of its largest entry
 factors of matrices up to 256 wide).  Its padding holds zeros.  The estimate
 then runs through tnslq_logneg on the padded state; in FP64 its Lanczos
 coefficients match the oracle's on the same padded state and probes to 1e-10.
+
+The factorised route (tnslq_logneg_mps) applies the same operator without
+forming the state: on the unpadded effective state and the same probes its
+Lanczos coefficients, per-probe estimates and stopping steps match the
+oracle's (explicit rho^{T_B} of that state) to 1e-10 relative.
 """
 import numpy as np
 import pytest
@@ -49,7 +54,8 @@ def test_effective_state_matches_oracle(dev, L, chi, a0, LA, b0, LB):
 @pytest.mark.parametrize("L,chi,a0,LA,b0,LB", [GEOMETRIES[0], GEOMETRIES[3], GEOMETRIES[6]])
 def test_logneg_of_blocks_matches_oracle(dev, L, chi, a0, LA, b0, LB):
     ts = ti.random_mps(L, 2, chi, L + chi)
-    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 8, 16, device=dev, precision="fp64", seed=2, reorth=True)
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 8, 16, device=dev, route="dense", precision="fp64", seed=2,
+                           reorth=True)
     qa, qb, qe = g["effective_qubits"]
     Pp = _padded(mps.effective_state(ts, a0, LA, b0, LB), (qa, qb, qe))
     o = slq.slq_logneg(Pp.reshape(-1), qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), 8, 16, seed=2,
@@ -65,5 +71,93 @@ def test_logneg_of_blocks_matches_oracle(dev, L, chi, a0, LA, b0, LB):
 
 def test_bell_pair_blocks_give_one_bit(dev):
     ts = ti.bell_pair_mps(12, 2, 9)
-    r = T.tnslq_logneg_mps(ts, 1, 3, 7, 4, 4, 10, device=dev, precision="fp64", seed=0)
+    r = T.tnslq_logneg_mps(ts, 1, 3, 7, 4, 4, 10, device=dev, route="dense", precision="fp64", seed=0)
     assert r["logneg"] == pytest.approx(1.0, abs=1e-12)
+    r = T.tnslq_logneg_mps(ts, 1, 3, 7, 4, 4, 10, device=dev, seed=0)
+    assert r["logneg"] == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("L,chi,a0,LA,b0,LB", GEOMETRIES)
+@pytest.mark.parametrize("reorth", [False, True])
+def test_factored_logneg_matches_oracle(dev, L, chi, a0, LA, b0, LB, reorth):
+    ts = ti.random_mps(L, 2, chi, L + chi)
+    K, m = 6, 14
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=5, reorth=reorth)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=5, reorth=reorth)
+    print(L, chi, a0, LA, b0, LB, Pe.shape, g["logneg"], o["logneg"])
+    assert g["streamed"] == 0 and g["explicit_operator"] == 0 and g["swapped_ab"] == 0
+    # Unique are the coefficients up to the first near-breakdown of each
+    # probe: past a beta below 1e-6 of the largest (a nearly invariant Krylov
+    # space, e.g. one exhausted at step n = d_A' d_B' <= m, or the few distinct
+    # eigenvalues of a bond-2 chain) both sides continue from rounding noise,
+    # with weights of that size in the estimate.  Without reorthogonalisation
+    # the recurrence also amplifies differences of summation order once Ritz
+    # values converge: a 1e-16 perturbation of the operator reaches 1e-12 at
+    # step 7 and 0.3 at step 9 on the (4, 4, 16) state (the spectrum spans
+    # 1e-6 to 0.86), while each probe's quadrature moves by at most 5e-8 of
+    # itself (replayed on the CPU); there the first 6 steps and G to 1e-6.
+    jm, tol = (m, 1e-10) if reorth else (6, 1e-6)
+    ascale, bscale = np.max(np.abs(o["alpha"])), np.max(np.abs(o["beta"][:, 1:]))
+    for k in range(K):
+        small = np.nonzero(o["beta"][k, 1:] < 1e-6 * bscale)[0]
+        jk = min(jm, small[0] + 1) if small.size else jm
+        if jk == jm == m:
+            assert g["steps"][k] == o["steps"][k]
+        else:
+            assert min(g["steps"][k], jk) == min(o["steps"][k], jk)
+        assert np.max(np.abs(g["alpha"][k, :jk] - o["alpha"][k, :jk])) <= 1e-10 * ascale
+        assert np.max(np.abs(g["beta"][k, :jk + 1] - o["beta"][k, :jk + 1])) <= 1e-10 * bscale
+    assert np.allclose(g["G"], o["G"], rtol=tol, atol=1e-14)
+    assert g["logneg"] == pytest.approx(o["logneg"], abs=tol * max(abs(o["logneg"]), 1.0))
+
+
+def test_factored_probe_loop_matches_oracle(dev):
+    # the loop over probe blocks (fit rule, target 0.01): the same blocks,
+    # per-probe estimates and stopping steps as the oracle replaying the rule
+    # on the unpadded effective state and the same probes
+    from oracle import lanczos_fit, probes
+    L, chi, a0, LA, b0, LB = GEOMETRIES[3]
+    ts = ti.random_mps(L, 2, chi, L + chi)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    R = exact.rho_pt(Pe)
+    n = Pe.shape[0] * Pe.shape[1]
+    K, m = 8, 30
+
+    def block(bi):
+        o = slq.slq(lambda v: R @ v, probes.rademacher_probes(7, K, n, bi * K), m)
+        return o["F"], o["alpha"], o["beta"]
+    o = lanczos_fit.probe_loop(block, K, 128, 0.01)
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=7, stop_tol=0.01, stop_rule="fit",
+                           max_probes=128)
+    assert g["n_probes_used"] == o["n_probes_used"]
+    assert np.allclose(g["G"], o["G"], rtol=1e-7, atol=0)
+    assert g["logneg"] == pytest.approx(o["logneg"], rel=1e-7)
+    assert g["steps_done"] == max(o["stops"])
+
+
+def test_factored_route_rejects_reduced_precision(dev):
+    ts = ti.random_mps(8, 2, 4, 1)
+    with pytest.raises(TypeError, match="precision"):
+        T.tnslq_logneg_mps(ts, 1, 2, 4, 2, 2, 10, device=dev, precision="fp32")
+
+
+def test_factored_probes_in_chunks(dev):
+    # bonds of 32 around blocks of 5 sites: per probe the intermediates
+    # Z1..Z3 take 16 (U'M d_B' + 2 U'M MV + d_A' MV) bytes, about 33 MiB, so
+    # 300 probes run in two chunks under the 8 GiB budget; every probe's
+    # coefficients still match the oracle's
+    L, chi, a0, LA, b0, LB = 24, 32, 5, 5, 10, 5
+    ts = ti.random_mps(L, 2, chi, 3)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    K, m = 300, 8
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=4)
+    dA, dB = Pe.shape[0], Pe.shape[1]
+    U, M, V = 32, 32, 32                 # bonds entering A, between the blocks, leaving B
+    assert (dA, dB) == (32, 32)
+    per = 16 * (U * M * dB + 2 * U * M * M * V + dA * M * V)
+    assert K * per > 8 << 30 and g["workspace_bytes"] < K * per
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=4)
+    assert np.max(np.abs(g["alpha"] - o["alpha"])) <= 1e-10 * np.max(np.abs(o["alpha"]))
+    assert np.max(np.abs(g["beta"] - o["beta"])) <= 1e-10 * np.max(np.abs(o["beta"]))
+    assert np.allclose(g["G"], o["G"], rtol=1e-10, atol=1e-14)
