@@ -41,9 +41,17 @@
     python -m paper_1809_01685_amd.experiments mps_blocks
         Two contiguous blocks of a 100-site random open-boundary MPS (qubits,
         complex Gaussian tensors, bond dimension chi): adjacent 16-site blocks
-        at chi = 16 and 32 (the geometry of Sec. VII.C) and 16-site blocks with
-        a 4-site gap at chi = 16; time to build the effective state (Sec. VI)
-        and to the +-1% estimate (split BF16, exponential-fit rule).
+        at chi = 16 and 32 (the geometry of Sec. VII.C), 8-site blocks at
+        chi = 64, and blocks 1 or 4 sites apart; the dense route (effective
+        state, then the split-BF16 estimate) against the factorised operator
+        (FP64), both to +-1% by the exponential-fit rule.
+
+    python -m paper_1809_01685_amd.experiments arith_peaks
+        Achievable arithmetic rates of this GPU (libtnslq_peak): dependent
+        loops of the BF16, FP32 and FP64 matrix instructions the contractions
+        use, and of FP64 and FP32 vector FMAs, each over 2048 workgroups of
+        four waves with eight (sixteen) independent chains per wave; best and
+        median of 5 launches of about 50 ms, against the published peaks.
 
 All print one JSON object.  All arithmetic of the method runs in libtnslq
 (hbm_peak times torch's own copy and sum only as a reference).
@@ -293,6 +301,57 @@ def run_hbm_peak(reps=10, seed=0):
     return {"workload": "HBM yardstick on one MI355X", "rows": out}
 
 
+def run_arith_peaks(reps=5, blocks=2048, target_ms=50.0):
+    import ctypes
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnslq_peak.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_1809_01685_amd.build")
+    lib = ctypes.CDLL(path)
+    lib.tnslq_peak_flops_per_round.restype = ctypes.c_double
+    lib.tnslq_peak_flops_per_round.argtypes = [ctypes.c_int]
+    lib.tnslq_peak_launch.restype = ctypes.c_int
+    lib.tnslq_peak_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_void_p,
+                                      ctypes.c_void_p]
+    dev = torch.device("cuda:0")
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream(dev)
+    # (kind, name, published dense peak in TFLOP/s)
+    kinds = [(0, "mfma_bf16_16x16x32", 2500.0), (5, "mfma_bf16_32x32x16", 2500.0), (1, "mfma_f32_16x16x4", 157.3),
+             (2, "mfma_f64_16x16x4", 78.6), (3, "valu_fma_f64", 78.6), (4, "valu_fma_f32", 157.3)]
+    rows = {}
+    for kind, name, peak in kinds:
+        per_round = lib.tnslq_peak_flops_per_round(kind) * blocks * 4
+        iters = max(1, int(peak * 1e12 * target_ms * 1e-3 / per_round))     # target_ms at the published peak
+
+        def launch():
+            rc = lib.tnslq_peak_launch(kind, blocks, iters, ctypes.c_float(1e-3), ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"tnslq_peak_launch({kind}) returned {rc}")
+        launch()
+        torch.cuda.synchronize()
+        rates = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            launch()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rates.append(per_round * iters / (ms * 1e-3) / 1e12)
+        rates.sort()
+        rows[name] = {"iters": iters, "blocks": blocks, "flops_per_launch": per_round * iters,
+                      "best_tflops": rates[-1], "median_tflops": rates[len(rates) // 2],
+                      "published_tflops": peak, "best_frac_of_published": rates[-1] / peak,
+                      "finite": bool(torch.isfinite(out).all().item())}
+        print(f"[arith_peaks] {name}: best {rates[-1]:.1f} TFLOP/s, median {rates[len(rates) // 2]:.1f} "
+              f"({100 * rates[-1] / peak:.1f}% of the published {peak})", file=sys.stderr, flush=True)
+    return {"workload": f"dependent instruction loops, {blocks} workgroups x 4 waves, ~{target_ms} ms each",
+            "rows": rows}
+
+
 def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("dense", "factored")):
     """Two blocks of a 100-site random MPS: the dense route (effective state,
     then tnslq_logneg in `precision`) against the factorised operator (FP64),
@@ -368,6 +427,9 @@ def main(argv=None):
     hs.add_argument("--steps", type=int, default=10)
     sub.add_parser("operator_forms")
     sub.add_parser("hbm_peak")
+    sp = sub.add_parser("arith_peaks")
+    sp.add_argument("--blocks", type=int, default=2048)
+    sp.add_argument("--ms", type=float, default=50.0)
     sp = sub.add_parser("mps_blocks")
     sp.add_argument("--routes", default="dense,factored")
     en = sub.add_parser("entropy30")
@@ -379,6 +441,8 @@ def main(argv=None):
         out = run_mps_blocks(routes=tuple(args.routes.split(",")))
     elif args.cmd == "hbm_peak":
         out = run_hbm_peak()
+    elif args.cmd == "arith_peaks":
+        out = run_arith_peaks(blocks=args.blocks, target_ms=args.ms)
     elif args.cmd == "operator_forms":
         out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
