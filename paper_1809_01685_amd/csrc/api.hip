@@ -440,7 +440,7 @@ struct MpsPlan {
     int q[3] = {0, 0, 0};
     int64_t smax = 1, gmax = 1, maxb = 1;
     size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_G, off_RA, off_RB, off_RBp, off_W, off_T1,
-        off_T, off_P, off_part, off_fail, total = 0;
+        off_T, off_P, off_TT, off_part, off_fail, total = 0;
 };
 
 // dense: room for the effective state itself (the dense route); without it
@@ -545,10 +545,14 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     mp.off_T1 = take(mp.kA * mp.U * mp.Nb * mp.Wd);
     mp.off_T = take(dense ? mp.kA * mp.U * mp.Wd * mp.kB * mp.V : 1);
     mp.off_P = take(mp.b0 > mp.a1 ? mp.kA * mp.U * mp.Wd * mp.Nb : 1);
+    int64_t tmax = 0;   // the transfer steps' scratch: one site tensor and one environment
+    for (int i = 0; i < L; ++i)
+        if (i < mp.a0 || i >= mp.b1) tmax = std::max<int64_t>(tmax, (mp.off[i + 1] - mp.off[i]) + e2);
+    mp.off_TT = take(std::max<int64_t>(tmax, 1));
     mp.off_part = o;
     o += up(257 * 8);
-    mp.off_fail = o;
-    o += up(4 * 4);
+    mp.off_fail = o;   // four flags, then at byte 64 the factorisations' scratch double
+    o += up(64 + 8);
     mp.total = o;
     return TNSLQ_OK;
 }
@@ -574,7 +578,7 @@ int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t 
 // exchanged, or (compressed) R = L^dagger with L L^dagger = S^dagger S over
 // the physical index.
 int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, double2 *R, double2 *tmp, double2 *G,
-                 int *failp, hipStream_t st) {
+                 int *failp, double *dscr, hipStream_t st) {
     if (!comp) {
         TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, R, st));
         return TNSLQ_OK;
@@ -582,7 +586,7 @@ int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, d
     const int64_t n = l * r;
     TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, tmp, st));   // [phys][(l r)]
     TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
-    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, st));
+    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, dscr, st));
     TNSLQ_HIP(launch_swap01(G, 1, n, n, 1, 1, R, st));
     return TNSLQ_OK;
 }
@@ -601,23 +605,24 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
     int rc;
     auto buf = [&](size_t off) { return (double2 *)(ws + off); };
     int *failp = (int *)(ws + mp.off_fail);
+    double *dscr = (double *)(ws + mp.off_fail + 64);   // the factorisations' largest diagonal entry
     TNSLQ_HIP(hipMemsetAsync(failp, 0, 16, st));
     static const double2 one = {1.0, 0.0};
     // traced environments: E_L on the bond entering A, E_R on the bond leaving B
     double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
     TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
     for (int i = 0; i < mp.a0; ++i) {
-        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, st));
+        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, buf(mp.off_TT), st));
         std::swap(El, Eln);
     }
     double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
     TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
     for (int i = mp.L - 1; i >= mp.b1; --i) {
-        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, st));
+        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, buf(mp.off_TT), st));
         std::swap(Er, Ern);
     }
-    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, st));       // X[x][u]
-    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, st));   // Y[y][v]
+    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, dscr, st));       // X[x][u]
+    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, dscr, st));   // Y[y][v]
     double2 *s0 = buf(mp.off_S[0]), *s1 = buf(mp.off_S[1]), *s2 = buf(mp.off_S[2]);
     // block A with X absorbed: S_A[u][a][m], from X^T (rows u, columns x)
     TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Eln, st));
@@ -629,10 +634,10 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
                            mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
     // vertical decompositions
     if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), failp + 2,
-                           st)))
+                           dscr, st)))
         return rc;
     if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), failp + 3,
-                           st)))
+                           dscr, st)))
         return rc;
     TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
     f.Q = buf(mp.off_RB);
@@ -655,7 +660,7 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
         const int64_t n = mp.Mb * mp.Nb;
         TNSLQ_HIP(launch_zgemm(0, 2, buf(mp.off_W), buf(mp.off_W), buf(mp.off_G), (int)n, (int)n, (int)mp.pG, mp.pG,
                                mp.pG, n, 1, 0, 0, 0, st));
-        TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, st));
+        TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, dscr, st));
         TNSLQ_HIP(hipMemcpyAsync(buf(mp.off_W), buf(mp.off_G), (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
     }
     // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)], then P[(kA, u)][w][n]

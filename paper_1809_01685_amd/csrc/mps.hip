@@ -4,9 +4,11 @@
 //
 // All of it is small FP64 linear algebra on tensors of bond dimension chi:
 //   * transfer sweeps for the traced environments left of A and right of B,
-//     E <- sum_s M_s^T E conj(M_s) (one thread per output entry);
-//   * Cholesky factors of positive matrices (environments, Gram matrices of
-//     the blocks and of the gap), column by column in one block;
+//     E <- sum_s M_s^T E conj(M_s) (two complex products per site);
+//   * Cholesky factors of positive semidefinite matrices (environments, Gram
+//     matrices of the blocks and of the gap), blocked: panels of 32 columns
+//     in one workgroup, the solve below them and the trailing update across
+//     the GPU;
 //   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
 //     (64 x 64 output tiles staged through LDS), for the block sections, their
 //     Gram matrices, the effective state and the factorised operator;
@@ -20,38 +22,6 @@ namespace {
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-
-// E_new[y][y'] = sum_{x, x', s} E[x][x'] M[x][s][y] conj(M[x'][s][y']) (left),
-// E_new[x][x'] = sum_{y, y', s} M[x][s][y] conj(M[x'][s][y']) E[y][y'] (right).
-template <bool LEFT>
-__global__ void __launch_bounds__(256) k_transfer(const double2 *__restrict__ E, const double2 *__restrict__ M, int cx,
-                                                  int p, int cy, double2 *__restrict__ Enew) {
-    const int nout = LEFT ? cy : cx;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nout * nout) return;
-    const int r = t / nout, c = t % nout;
-    double2 acc = make_double2(0.0, 0.0);
-    if (LEFT) {
-        for (int x = 0; x < cx; ++x)
-            for (int xp = 0; xp < cx; ++xp) {
-                const double2 e = E[x * cx + xp];
-                for (int s = 0; s < p; ++s) {
-                    const double2 v = cmul(e, cmul(M[(x * p + s) * cy + r], cconj(M[(xp * p + s) * cy + c])));
-                    acc = make_double2(acc.x + v.x, acc.y + v.y);
-                }
-            }
-    } else {
-        for (int y = 0; y < cy; ++y)
-            for (int yp = 0; yp < cy; ++yp) {
-                const double2 e = E[y * cy + yp];
-                for (int s = 0; s < p; ++s) {
-                    const double2 v = cmul(cmul(M[(r * p + s) * cy + y], cconj(M[(c * p + s) * cy + yp])), e);
-                    acc = make_double2(acc.x + v.x, acc.y + v.y);
-                }
-            }
-    }
-    Enew[t] = acc;
-}
 
 // Normalise a small positive matrix by its trace (one block): keeps long
 // sweeps in range; the effective state is normalised at the end.
@@ -68,49 +38,112 @@ __global__ void __launch_bounds__(256) k_scale_by_trace(double2 *__restrict__ E,
 
 // In-place lower Cholesky factor of a Hermitian positive semidefinite n x n
 // matrix (row-major): A = L L^dagger, L lower triangular with a real
-// non-negative diagonal; the strict upper triangle is zeroed.  One block walks
-// the columns.  A pivot not above 1e-13 of the largest diagonal entry (the
-// matrix is rank deficient there; Gram and transfer matrices are positive
-// semidefinite by construction) leaves its column zero: L L^dagger is still
-// the matrix, and the zero columns only add zero padding downstream.
-// *fail is set when a pivot is not finite.
-__global__ void __launch_bounds__(1024) k_cholesky(double2 *__restrict__ A, int n, int *__restrict__ fail) {
-    __shared__ double piv, dmax;
-    if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < n; ++i) m = fmax(m, A[(int64_t)i * n + i].x);
-        dmax = m;
-        *fail = 0;
+// non-negative diagonal; the strict upper triangle is zeroed.  A pivot not
+// above 1e-13 of the largest diagonal entry of the input (the matrix is rank
+// deficient there; Gram and transfer matrices are positive semidefinite by
+// construction) leaves its column zero: L L^dagger is still the matrix, and
+// the zero columns only add zero padding downstream.  *fail is set when a
+// pivot is not finite (and never cleared here).
+//
+// Blocked, right-looking, in panels of CNB columns: the diagonal block is
+// factored in one workgroup (k_chol_panel), the rows below solve against it
+// (k_chol_trsm), and the trailing matrix takes the rank-CNB update
+// A22 -= L21 L21^dagger as a complex product (k_zgemm, subtracting).
+constexpr int CNB = 32;
+
+__global__ void __launch_bounds__(256) k_chol_init(const double2 *__restrict__ A, int n, double *__restrict__ dmax) {
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, A[(int64_t)i * n + i].x);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *dmax = sh[0];
+}
+
+// Factor the w x w diagonal block at (j0, j0), w = min(CNB, n - j0), whose
+// entries already hold every update from the columns before j0.
+__global__ void __launch_bounds__(256) k_chol_panel(double2 *__restrict__ A, int n, int j0,
+                                                    const double *__restrict__ dmax, int *__restrict__ fail) {
+    __shared__ double2 T[CNB][CNB + 1];
+    const int w = min(CNB, n - j0);
+    for (int e = threadIdx.x; e < CNB * CNB; e += 256) {
+        const int r = e / CNB, c = e % CNB;
+        T[r][c] = (r < w && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : make_double2(0.0, 0.0);
+    }
+    const double tol = 1e-13 * *dmax;
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = T[j][j].x;
+            if (!isfinite(d)) *fail = 1;
+            T[j][j] = make_double2(d > tol ? sqrt(d) : 0.0, 0.0);
+        }
+        __syncthreads();
+        const double piv = T[j][j].x;
+        for (int i = j + 1 + threadIdx.x; i < w; i += 256)
+            T[i][j] = piv > 0.0 ? make_double2(T[i][j].x / piv, T[i][j].y / piv) : make_double2(0.0, 0.0);
+        __syncthreads();
+        // rank-1 update of the block's remaining lower triangle
+        const int m = w - j - 1;
+        for (int e = threadIdx.x; e < m * m; e += 256) {
+            const int i = j + 1 + e / m, k = j + 1 + e % m;
+            if (k <= i) {
+                const double2 q = cmul(T[i][j], cconj(T[k][j]));
+                T[i][k] = make_double2(T[i][k].x - q.x, T[i][k].y - q.y);
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < w * w; e += 256) {
+        const int r = e / w, c = e % w;
+        if (c <= r) A[(int64_t)(j0 + r) * n + j0 + c] = T[r][c];
+    }
+}
+
+// Rows r >= j0 + w: L21[r][:] solves x L11^dagger = A[r][j0 .. j0 + w), one
+// row per thread (zero pivots give zero entries, as in the unblocked form).
+__global__ void __launch_bounds__(256) k_chol_trsm(double2 *__restrict__ A, int n, int j0) {
+    __shared__ double2 L[CNB][CNB + 1];
+    const int w = min(CNB, n - j0);
+    for (int e = threadIdx.x; e < CNB * CNB; e += 256) {
+        const int r = e / CNB, c = e % CNB;
+        L[r][c] = (r < w && c <= r) ? A[(int64_t)(j0 + r) * n + j0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        if (threadIdx.x == 0) {
-            double d = A[(int64_t)j * n + j].x;
-            for (int k = 0; k < j; ++k) {
-                const double2 l = A[(int64_t)j * n + k];
-                d -= l.x * l.x + l.y * l.y;
-            }
-            if (!isfinite(d)) *fail = 1;
-            d = d > 1e-13 * dmax ? sqrt(d) : 0.0;
-            A[(int64_t)j * n + j] = make_double2(d, 0.0);
-            piv = d;
-        }
-        __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-            double2 v = A[(int64_t)i * n + j];
-            for (int k = 0; k < j; ++k) {
-                const double2 q = cmul(A[(int64_t)i * n + k], cconj(A[(int64_t)j * n + k]));
+    const int64_t r = (int64_t)j0 + w + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    double2 *row = A + r * n + j0;
+    double2 x[CNB];
+#pragma unroll
+    for (int k = 0; k < CNB; ++k) {
+        if (k < w) {
+            double2 v = row[k];
+#pragma unroll
+            for (int m = 0; m < k; ++m) {
+                const double2 q = cmul(x[m], cconj(L[k][m]));
                 v = make_double2(v.x - q.x, v.y - q.y);
             }
-            A[(int64_t)i * n + j] = piv > 0.0 ? make_double2(v.x / piv, v.y / piv) : make_double2(0.0, 0.0);
+            const double piv = L[k][k].x;
+            x[k] = piv > 0.0 ? make_double2(v.x / piv, v.y / piv) : make_double2(0.0, 0.0);
+            row[k] = x[k];
+        } else {
+            x[k] = make_double2(0.0, 0.0);
         }
-        __syncthreads();
     }
-    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x)
+}
+
+__global__ void __launch_bounds__(256) k_zero_upper(double2 *__restrict__ A, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
         if (e % n > e / n) A[e] = make_double2(0.0, 0.0);
 }
 
-// C[b] = op(A[b]) op(B[b]) for complex row-major matrices: op(A) is M x K,
+// C[b] = op(A[b]) op(B[b]) (C[b] -= op(A[b]) op(B[b]) with sub) for complex
+// row-major matrices: op(A) is M x K,
 // op(B) is K x N; OP = 0 (as stored), 1 (transpose), 2 (conjugate transpose);
 // lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.  A block
 // of 256 threads computes a 64 x 64 tile, 4 x 4 outputs per thread, staging
@@ -118,7 +151,8 @@ __global__ void __launch_bounds__(1024) k_cholesky(double2 *__restrict__ A, int 
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, const double2 *__restrict__ B,
                                                double2 *__restrict__ C, int M, int N, int K, int64_t lda,
-                                               int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc) {
+                                               int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc,
+                                               int sub) {
     constexpr int TM = 64, TN = 64, TK = 8;
     __shared__ double2 As[TK][TM + 1], Bs[TK][TN + 1];
     const int64_t b = blockIdx.z;
@@ -183,7 +217,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-            if (r < M && c < N) C[(int64_t)r * ldc + c] = acc[i][j];
+            if (r < M && c < N) {
+                double2 &o = C[(int64_t)r * ldc + c];
+                o = sub ? make_double2(o.x - acc[i][j].x, o.y - acc[i][j].y) : acc[i][j];
+            }
         }
 }
 
@@ -275,29 +312,56 @@ unsigned blocks_for(int64_t n) {
 
 }  // namespace
 
+// Left: E_new[y][y'] = sum_{x, x', s} E[x][x'] M[x][s][y] conj(M[x'][s][y'])
+// as G[x][(s, y)] = sum_x' E[x'][x] M[x'][(s, y)], H = M^dagger G over (x, s),
+// E_new = H^T.  Right: E_new[x][x'] = sum_{y, y', s} M[x][s][y]
+// conj(M[x'][s][y']) E[y][y'] as G = M E over y, E_new = G conj(M)^T over
+// (s, y').  Two complex products of chi^3 p multiply-adds each.
 hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx, int p, int cy, double2 *Enew,
-                           hipStream_t st) {
+                           double2 *tmp, hipStream_t st) {
     const int nout = left ? cy : cx;
-    if (left)
-        hipLaunchKernelGGL(k_transfer<true>, dim3(blocks_for((int64_t)nout * nout)), dim3(256), 0, st, E, M, cx, p, cy,
-                           Enew);
-    else
-        hipLaunchKernelGGL(k_transfer<false>, dim3(blocks_for((int64_t)nout * nout)), dim3(256), 0, st, E, M, cx, p,
-                           cy, Enew);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t pcy = (int64_t)p * cy;
+    hipError_t e;
+    if (left) {
+        double2 *G = tmp, *H = tmp + (int64_t)cx * pcy;
+        if ((e = launch_zgemm(1, 0, E, M, G, cx, (int)pcy, cx, cx, pcy, pcy, 1, 0, 0, 0, st)) != hipSuccess) return e;
+        if ((e = launch_zgemm(2, 0, M, G, H, cy, cy, cx * p, cy, cy, cy, 1, 0, 0, 0, st)) != hipSuccess) return e;
+        if ((e = launch_swap01(H, 1, cy, cy, 1, 0, Enew, st)) != hipSuccess) return e;
+    } else {
+        double2 *G = tmp;
+        if ((e = launch_zgemm(0, 0, M, E, G, cx * p, cy, cy, cy, cy, cy, 1, 0, 0, 0, st)) != hipSuccess) return e;
+        if ((e = launch_zgemm(0, 2, G, M, Enew, cx, cx, (int)pcy, pcy, pcy, cx, 1, 0, 0, 0, st)) != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(k_scale_by_trace, dim3(1), dim3(256), 0, st, Enew, nout);
     return hipGetLastError();
 }
 
-hipError_t launch_cholesky(double2 *A, int n, int *fail, hipStream_t st) {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, n, fail);
+hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream_t st) {
+    if (n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chol_init, dim3(1), dim3(256), 0, st, A, n, dmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int j0 = 0; j0 < n; j0 += CNB) {
+        const int w = n - j0 < CNB ? n - j0 : CNB, rest = n - j0 - w;
+        hipLaunchKernelGGL(k_chol_panel, dim3(1), dim3(256), 0, st, A, n, j0, dmax, fail);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (rest == 0) break;
+        hipLaunchKernelGGL(k_chol_trsm, dim3((rest + 255) / 256), dim3(256), 0, st, A, n, j0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // A22 -= L21 L21^dagger (the full square; its upper part is zeroed last)
+        const double2 *L21 = A + (int64_t)(j0 + w) * n + j0;
+        if ((e = launch_zgemm(0, 2, L21, L21, A + (int64_t)(j0 + w) * n + j0 + w, rest, rest, w, n, n, n, 1, 0, 0, 0,
+                              st, 1)) != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_zero_upper, dim3(blocks_for((int64_t)n * n)), dim3(256), 0, st, A, n);
     return hipGetLastError();
 }
 
 hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st) {
+                        hipStream_t st, int sub) {
     if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
     // rows in chunks of 65535 tiles (the grid's y limit)
     constexpr int64_t RCH = 65535 * 64;
@@ -307,7 +371,7 @@ hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, do
         double2 *Cc = C + r0 * ldc;
         dim3 grid((unsigned)((N + 63) / 64), (unsigned)((m + 63) / 64), (unsigned)batch), block(256);
 #define TNSLQ_ZG(OA, OB) \
-    hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc)
+    hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc, sub)
         if (opa == 0 && opb == 0) TNSLQ_ZG(0, 0);
         else if (opa == 1 && opb == 0) TNSLQ_ZG(1, 0);
         else if (opa == 2 && opb == 0) TNSLQ_ZG(2, 0);

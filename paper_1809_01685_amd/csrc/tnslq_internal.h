@@ -190,17 +190,22 @@ hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, i
 // (Sec. VI); all matrices row-major, interleaved complex.
 // One transfer step of a traced environment through the site tensor
 // M[x][s][y] (cx x p x cy): left, E[x][x'] -> [y][y']; right, E[y][y'] ->
-// [x][x']; the result scaled to unit trace.
+// [x][x']; the result scaled to unit trace.  tmp: cx p cy + cy^2 entries of
+// scratch (device).
 hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx, int p, int cy, double2 *Enew,
-                           hipStream_t st);
-// In-place lower Cholesky factor (A = L L^dagger) of an n x n positive matrix;
-// *fail (device) is set if a pivot is not positive.
-hipError_t launch_cholesky(double2 *A, int n, int *fail, hipStream_t st);
-// C[b] = op(A[b]) op(B[b]), op 0 = as stored, 1 = transpose, 2 = conjugate
-// transpose (supported pairs: (0,0), (1,0), (2,0), (0,2)); op(A) is M x K.
+                           double2 *tmp, hipStream_t st);
+// In-place lower Cholesky factor (A = L L^dagger) of an n x n positive
+// semidefinite matrix; a pivot not above 1e-13 of the largest diagonal entry
+// leaves its column zero; *fail (device) is set if a pivot is not finite and
+// is never cleared here.  dmax: one device double of scratch (calls on one
+// stream may share it).
+hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream_t st);
+// C[b] = op(A[b]) op(B[b]) (with sub: C[b] -= op(A[b]) op(B[b])), op 0 = as
+// stored, 1 = transpose, 2 = conjugate transpose (supported pairs: (0,0),
+// (1,0), (2,0), (0,2)); op(A) is M x K.
 hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st);
+                        hipStream_t st, int sub = 0);
 // out[b][j][i][k] = (conj) in[b][i][j][k], nb tensors of shape (n0, n1, n2).
 hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,
                          hipStream_t st);
