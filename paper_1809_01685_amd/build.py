@@ -49,7 +49,10 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    extra = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] if src == PEAK_SRC else []
+    # loops that carry matrix-instruction accumulators from one iteration to
+    # the next: in the accumulator-register form the compiler copied them
+    # between register files every iteration
+    extra = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] if src in (PEAK_SRC, os.path.join(CSRC, "mps.hip")) else []
     cmd = [hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -10,7 +10,8 @@
 //     in one workgroup, the solve below them and the trailing update across
 //     the GPU;
 //   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
-//     (64 x 64 output tiles staged through LDS), for the block sections, their
+//     (64 x 64 output tiles staged through LDS, FP64 matrix instructions),
+//     for the block sections, their
 //     Gram matrices, the effective state and the factorised operator;
 //   * an axis exchange, and the final scatter of the effective state into a
 //     zero-padded power-of-two layout, normalised.
@@ -143,33 +144,43 @@ __global__ void __launch_bounds__(256) k_zero_upper(double2 *__restrict__ A, int
 }
 
 // C[b] = op(A[b]) op(B[b]) (C[b] -= op(A[b]) op(B[b]) with sub) for complex
-// row-major matrices: op(A) is M x K,
-// op(B) is K x N; OP = 0 (as stored), 1 (transpose), 2 (conjugate transpose);
-// lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.  A block
-// of 256 threads computes a 64 x 64 tile, 4 x 4 outputs per thread, staging
-// 64 x 8 slices of op(A) and 8 x 64 of op(B) through LDS.
+// row-major matrices: op(A) is M x K, op(B) is K x N; OP = 0 (as stored),
+// 1 (transpose), 2 (conjugate transpose); lda/ldb/ldc are the stored row
+// strides, sa/sb/sc the batch strides.  A block of 256 threads (4 waves)
+// computes a 64 x 64 tile, staging 64 x 16 slices of op(A) and 16 x 64 of
+// op(B) through LDS (zeros outside the matrices); each wave owns 32 x 32
+// outputs as 2 x 2 tiles of v_mfma_f64_16x16x4f64, four real products per
+// complex one (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Lane l supplies
+// A[l % 16][k] and B[k][l % 16] with k = l / 16 of each 4-term step, and
+// holds outputs (4 r + l / 16, l % 16) in its accumulator register r.
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, const double2 *__restrict__ B,
                                                double2 *__restrict__ C, int M, int N, int K, int64_t lda,
                                                int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc,
                                                int sub) {
-    constexpr int TM = 64, TN = 64, TK = 8;
+    constexpr int TM = 64, TN = 64, TK = 16;
     __shared__ double2 As[TK][TM + 1], Bs[TK][TN + 1];
     const int64_t b = blockIdx.z;
     A += b * sa;
     B += b * sb;
     C += b * sc;
-    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int fr = lane & 15, fk = lane >> 4;
     const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
-    double2 acc[4][4];
+    f64x4 accr[2][2], acci[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+            acci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
     for (int k0 = 0; k0 < K; k0 += TK) {
-        // 512 entries of each slice, two per thread
+        // 1024 entries of each slice, four per thread
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 4; ++q) {
             const int e = t + 256 * q;
             {
                 // op(A)[r0 + rr][k0 + kk]
@@ -196,32 +207,38 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            double2 av[4], bv[4];
+        for (int k4 = 0; k4 < TK / 4; ++k4) {
+            const int kk = 4 * k4 + fk;
+            double2 av[2], bv[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < 2; ++i) av[i] = As[kk][wm * 32 + i * 16 + fr];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[kk][wn * 32 + j * 16 + fr];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
-                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
+                for (int j = 0; j < 2; ++j) {
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, accr[i][j], 0, 0, 0);
+                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, accr[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, acci[i][j], 0, 0, 0);
+                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acci[i][j], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-            if (r < M && c < N) {
-                double2 &o = C[(int64_t)r * ldc + c];
-                o = sub ? make_double2(o.x - acc[i][j].x, o.y - acc[i][j].y) : acc[i][j];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + wm * 32 + i * 16 + 4 * q + fk, c = c0 + wn * 32 + j * 16 + fr;
+                if (r < M && c < N) {
+                    double2 &o = C[(int64_t)r * ldc + c];
+                    o = sub ? make_double2(o.x - accr[i][j][q], o.y - acci[i][j][q])
+                            : make_double2(accr[i][j][q], acci[i][j][q]);
+                }
             }
-        }
 }
 
 // out[b][j][i][k] = in[b][i][j][k] for nb tensors of shape (n0, n1, n2)
