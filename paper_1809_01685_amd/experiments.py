@@ -42,7 +42,8 @@
         Two contiguous blocks of a 100-site random open-boundary MPS (qubits,
         complex Gaussian tensors, bond dimension chi): adjacent 16-site blocks
         at chi = 16 and 32 (the geometry of Sec. VII.C), 8-site blocks at
-        chi = 64, and blocks 1 or 4 sites apart; the dense route (effective
+        chi = 64 and 180 (the paper's largest bond dimension), and blocks 1 or
+        4 sites apart; the dense route (effective
         state, then the split-BF16 estimate) against the factorised operator
         (FP64), both to +-1% by the exponential-fit rule.
 
@@ -362,10 +363,11 @@ def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("
     dev = torch.device("cuda:0")
     rows = []
     # the last flag: the dense route as well (the gap rows' effective states
-    # would need 2^32 amplitudes or more)
+    # would need 2^32 amplitudes or more; at chi = 180 it takes 2^31, 32 GiB)
     for chi, a0, la, b0, lb, dense in ((16, 34, 16, 50, 16, True), (32, 34, 16, 50, 16, True),
                                        (16, 32, 16, 52, 16, True), (32, 33, 16, 50, 16, False),
-                                       (64, 42, 8, 50, 8, True), (64, 41, 8, 50, 8, False)):
+                                       (64, 42, 8, 50, 8, True), (64, 41, 8, 50, 8, False),
+                                       (180, 42, 8, 50, 8, True)):
         ts = ti.random_mps(100, 2, chi, seed)
         row = {"n_sites": 100, "chi": chi, "A": [a0, a0 + la], "B": [b0, b0 + lb], "gap": b0 - a0 - la}
         if "dense" in routes and dense:
