@@ -1,8 +1,9 @@
 // Contiguous blocks of an open-boundary matrix product state (Sec. VI): the
-// compressed form of rho_AB^{T_B}, reduced to an effective dense state whose
-// partially transposed density matrix has the same nonzero spectrum.
+// compressed form of rho_AB^{T_B}, as two factors P, Q of an effective state
+// whose partially transposed density matrix has the same nonzero spectrum
+// (applied in factorised form, or contracted into that state).
 //
-// All of it is small FP64 linear algebra on tensors of bond dimension chi:
+// All of it is FP64 linear algebra on tensors of bond dimension chi:
 //   * transfer sweeps for the traced environments left of A and right of B,
 //     E <- sum_s M_s^T E conj(M_s) (two complex products per site);
 //   * Cholesky factors of positive semidefinite matrices (environments, Gram
@@ -11,8 +12,9 @@
 //     the GPU;
 //   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
 //     (64 x 64 output tiles staged through LDS, FP64 matrix instructions),
-//     for the block sections, their
-//     Gram matrices, the effective state and the factorised operator;
+//     for the block sections, their Gram matrices, the effective state and
+//     the factorised operator;
+//   * the factor normalisation Re sum Ahat conj(C);
 //   * an axis exchange, and the final scatter of the effective state into a
 //     zero-padded power-of-two layout, normalised.
 // The host side (api.hip) plans the sizes and sequences these launches.
