@@ -332,7 +332,9 @@ int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int
  * entries, unpadded; the estimate and every output are those of
  * tnslq_logneg on psi_eff (same probes, same stopping rules, the loop over
  * probes with max_probes).
- *   opt->precision must be TNSLQ_FP64 (complex products in FP64) and
+ *   opt->precision TNSLQ_FP64 (complex products in FP64) or TNSLQ_FP32
+ *   (complex64 factors and intermediates on the FP32 matrix instructions;
+ *   the Lanczos recurrence stays FP64), and
  *   opt->operator_form TNSLQ_OPERATOR_AUTO; res->streamed and
  *   res->explicit_operator are 0.  Probes are processed in chunks whose
  *   intermediates fit 8 GiB.  Errors as tnslq_logneg, plus those of

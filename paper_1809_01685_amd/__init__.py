@@ -433,19 +433,22 @@ def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opt
 
 def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: int, n_steps: int, device="cuda",
                      route="factored", reorth: bool = False, seed: int = 0, probe_offset: int = 0,
-                     stop_tol: float = 0.0, stop_rule="diff", max_probes: int = 0, workspace=None, stream=None,
-                     want_arrays: bool = True, **kw) -> Dict[str, object]:
+                     stop_tol: float = 0.0, stop_rule="diff", max_probes: int = 0, precision=None, workspace=None,
+                     stream=None, want_arrays: bool = True, **kw) -> Dict[str, object]:
     """E(rho_AB) of two contiguous blocks of an open-boundary MPS (Sec. VI).
 
     route="factored": Algorithm 1 on the two-block operator in factorised form
-    (tnslq_logneg_mps, FP64, nothing of the effective state's size formed);
-    route="dense": the effective state of tnslq_mps_effective_state through
-    tnslq_logneg (further keywords, e.g. precision, go to tnslq_logneg)."""
+    (tnslq_logneg_mps, precision "fp64" (default) or "fp32", nothing of the
+    effective state's size formed); route="dense": the effective state of
+    tnslq_mps_effective_state through tnslq_logneg in `precision` (its
+    default when None; further keywords go to tnslq_logneg)."""
     import numpy as np
     import torch
     if route == "dense":
         psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device)
         qa, qb, qe = q
+        if precision is not None:
+            kw["precision"] = precision
         out = tnslq_logneg(psi, qa + qb + qe, list(range(qa)), list(range(qa, qa + qb)), n_probes, n_steps,
                            reorth=reorth, seed=seed, probe_offset=probe_offset, stop_tol=stop_tol,
                            stop_rule=stop_rule, max_probes=max_probes, want_arrays=want_arrays, **kw)
@@ -455,8 +458,8 @@ def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: in
         raise ValueError(f"route must be 'factored' or 'dense', not {route!r}")
     if kw:
         raise TypeError(f"unexpected keywords for the factored route: {sorted(kw)}")
-    opts = make_options(n_probes, n_steps, reorth, "fp64", seed, probe_offset, stop_tol, stop_rule, "auto",
-                        max_probes)
+    opts = make_options(n_probes, n_steps, reorth, precision or "fp64", seed, probe_offset, stop_tol, stop_rule,
+                        "auto", max_probes)
     m = _mps(tensors, device)
     need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts)
     ws = _workspace(need, torch.device(device), workspace)

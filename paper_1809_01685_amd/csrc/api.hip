@@ -224,9 +224,10 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     // factorised MPS operator: four complex products per probe, chunks of
     // probes within a fixed budget of intermediates
     const int64_t UpM = pl.mUp * pl.mM, MV = pl.mM * pl.mV;
+    const size_t mes = prec == TNSLQ_FP32 ? 8 : 16;   // bytes per complex entry of its intermediates
     if (pl.mpsf) {
-        const size_t per = 16 * (size_t)(UpM * pl.dB + 2 * UpM * MV + pl.dA * MV + n);
-        pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(MPS_BUDGET / per)));
+        const size_t per = mes * (size_t)(UpM * pl.dB + 2 * UpM * MV + pl.dA * MV + 2 * n);
+        pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)K, (int64_t)(MPS_BUDGET / per), 65535}));
         pl.S = pl.S1 = 1;
     }
 
@@ -238,12 +239,17 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     };
     if (pl.mpsf) {
         pl.off_mps = take(pl.mps_bytes);
-        pl.off_Z1 = take((size_t)pl.kc * UpM * pl.dB * 16);
-        pl.off_Z2 = take((size_t)pl.kc * UpM * MV * 16);
-        pl.off_Z2p = take((size_t)pl.kc * UpM * MV * 16);
-        pl.off_Z3 = take((size_t)pl.kc * pl.dA * MV * 16);
-        pl.off_Ypart = take((size_t)pl.kc * n * 16);
+        pl.off_Z1 = take((size_t)pl.kc * UpM * pl.dB * mes);
+        pl.off_Z2 = take((size_t)pl.kc * UpM * MV * mes);
+        pl.off_Z2p = take((size_t)pl.kc * UpM * MV * mes);
+        pl.off_Z3 = take((size_t)pl.kc * pl.dA * MV * mes);
+        pl.off_Ypart = take((size_t)pl.kc * n * mes);
         pl.off_nrm = take((size_t)2 * pl.mM * pl.mM * 16 + 64);
+        if (prec == TNSLQ_FP32) {
+            pl.off_P32 = take((size_t)pl.dA * UpM * 8);
+            pl.off_Q32 = take((size_t)pl.dB * MV * 8);
+            pl.off_X32 = take((size_t)pl.kc * n * 8);
+        }
     } else if (pl.expl) {
         pl.off_Pabe = take(brick_bytes(prec, n, pl.dE));
         pl.off_Pabc = take(brick_bytes(prec, n, pl.dE));
@@ -695,7 +701,8 @@ struct Ctx {
     double2 *Up, *U2, *Xs, *Xq, *Ym;
     const MpsPlan *mp = nullptr;     // factorised MPS operator: its factor construction
     MpsFactors mf{};
-    double2 *Z1, *Z2, *Z2p, *Z3;
+    double2 *Z1, *Z2, *Z2p, *Z3;     // complex64 in FP32
+    float2 *P32, *Q32, *X32;
     double2 *Q, *w;
     double *alpha, *beta, *F, *G, *stats, *dotpart, *nrmpart, *hpart;
     double2 *h;
@@ -743,6 +750,9 @@ void bind(Ctx &c, void *ws, hipStream_t st) {
     c.Z2 = (double2 *)(c.ws + pl.off_Z2);
     c.Z2p = (double2 *)(c.ws + pl.off_Z2p);
     c.Z3 = (double2 *)(c.ws + pl.off_Z3);
+    c.P32 = (float2 *)(c.ws + pl.off_P32);
+    c.Q32 = (float2 *)(c.ws + pl.off_Q32);
+    c.X32 = (float2 *)(c.ws + pl.off_X32);
     if (pl.mpsf) c.Paeb = c.Pbea = c.Xt = c.Ups = nullptr;
     c.Q = (double2 *)(c.ws + pl.off_Q);
     c.w = (double2 *)(c.ws + pl.off_w);
@@ -820,6 +830,10 @@ int do_layout(Ctx &c, const void *psi) {
         TNSLQ_HIP(launch_zgemm(2, 0, f.P, f.P, Ah, M, M, (int)rowsP, M, M, M, 1, 0, 0, 0, c.st));
         TNSLQ_HIP(launch_zgemm(0, 2, f.Qp, f.Qp, Cq, M, M, (int)colsQ, colsQ, colsQ, M, 1, 0, 0, 0, c.st));
         TNSLQ_HIP(launch_normalise_factor(Ah, Cq, (int64_t)M * M, nrm, f.P, rowsP * M, c.st));
+        if (pl.prec == TNSLQ_FP32) {
+            TNSLQ_HIP(launch_to_c64(f.P, rowsP * M, c.P32, c.st));
+            TNSLQ_HIP(launch_to_c64(f.Q, f.kB * M * f.V, c.Q32, c.st));
+        }
         return mps_check(*c.mp, mws, c.st);
     }
     if (pl.expl) {
@@ -977,15 +991,26 @@ int mps_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2)
     const MpsFactors &f = c.mf;
     const int64_t n = pl.dAB, UpM = f.Up * f.M, MV = f.M * f.V;
     const int kA = (int)f.kA, kB = (int)f.kB;
-    TNSLQ_HIP(launch_zgemm(2, 0, f.P, x, c.Z1, (int)UpM, kB, kA, UpM, kB, kB, kcur, 0, n, UpM * kB, c.st));
-    TNSLQ_HIP(launch_zgemm(0, 0, c.Z1, f.Q, c.Z2, (int)UpM, (int)MV, kB, kB, MV, MV, kcur, UpM * kB, 0, UpM * MV,
-                           c.st));
-    if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
-    TNSLQ_HIP(launch_swap01(c.Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, 0, c.Z2p, c.st));
-    TNSLQ_HIP(launch_zgemm(0, 0, f.P, c.Z2p, c.Z3, kA, (int)MV, (int)UpM, UpM, MV, MV, kcur, 0, UpM * MV, kA * MV,
-                           c.st));
-    TNSLQ_HIP(launch_zgemm(0, 2, c.Z3, f.Q, (double2 *)c.Ypart, kA, kB, (int)MV, MV, MV, kB, kcur, kA * MV, 0, n,
-                           c.st));
+    auto chain = [&](auto *P, auto *Q, auto *X, auto *Z1, auto *Z2, auto *Z2p, auto *Z3, auto *Y) -> int {
+        TNSLQ_HIP(launch_zgemm(2, 0, P, X, Z1, (int)UpM, kB, kA, UpM, kB, kB, kcur, 0, n, UpM * kB, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 0, Z1, Q, Z2, (int)UpM, (int)MV, kB, kB, MV, MV, kcur, UpM * kB, 0, UpM * MV,
+                               c.st));
+        if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+        TNSLQ_HIP(launch_swap01(Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, Z2p, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 0, P, Z2p, Z3, kA, (int)MV, (int)UpM, UpM, MV, MV, kcur, 0, UpM * MV, kA * MV,
+                               c.st));
+        TNSLQ_HIP(launch_zgemm(0, 2, Z3, Q, Y, kA, kB, (int)MV, MV, MV, kB, kcur, kA * MV, 0, n, c.st));
+        return TNSLQ_OK;
+    };
+    int rc;
+    if (pl.prec == TNSLQ_FP32) {
+        TNSLQ_HIP(launch_to_c64(x, (int64_t)kcur * n, c.X32, c.st));
+        rc = chain((const float2 *)c.P32, (const float2 *)c.Q32, (const float2 *)c.X32, (float2 *)c.Z1,
+                   (float2 *)c.Z2, (float2 *)c.Z2p, (float2 *)c.Z3, (float2 *)c.Ypart);
+    } else {
+        rc = chain((const double2 *)f.P, f.Q, x, c.Z1, c.Z2, c.Z2p, c.Z3, (double2 *)c.Ypart);
+    }
+    if (rc) return rc;
     if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
     c.n_launch++;
     return TNSLQ_OK;
@@ -1946,15 +1971,16 @@ static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b
                    Plan &pl) {
     int rc;
     if ((rc = check_options(opt))) return rc;
-    if (opt->precision != TNSLQ_FP64)
-        return fail(TNSLQ_E_ARG, "the factorised MPS operator computes in FP64: precision must be TNSLQ_FP64");
+    if (opt->precision != TNSLQ_FP64 && opt->precision != TNSLQ_FP32)
+        return fail(TNSLQ_E_ARG, "the factorised MPS operator computes in FP64 or FP32 (precision %d)",
+                    opt->precision);
     if (opt->operator_form != TNSLQ_OPERATOR_AUTO)
         return fail(TNSLQ_E_ARG, "operator_form must be TNSLQ_OPERATOR_AUTO for MPS blocks");
     if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp, false))) return rc;
     pl = Plan();
     pl.mpsf = 1;
     pl.dtype = TNSLQ_C128;
-    pl.prec = TNSLQ_FP64;
+    pl.prec = opt->precision;
     pl.K = opt->n_probes;
     pl.m = opt->n_steps;
     pl.reorth = opt->reorth;
@@ -1968,7 +1994,7 @@ static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b
     pl.dE = pl.mUp * pl.mV;
     pl.D = pl.dAB * pl.dE;
     pl.mps_bytes = mp.total;
-    return plan_rest(pl, TNSLQ_C128, TNSLQ_FP64, pl.K, 1);
+    return plan_rest(pl, TNSLQ_C128, pl.prec, pl.K, 1);
 }
 
 int tnslq_workspace_bytes_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, const tnslq_options *opt,

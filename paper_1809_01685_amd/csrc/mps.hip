@@ -146,24 +146,44 @@ __global__ void __launch_bounds__(256) k_zero_upper(double2 *__restrict__ A, int
 }
 
 // C[b] = op(A[b]) op(B[b]) (C[b] -= op(A[b]) op(B[b]) with sub) for complex
-// row-major matrices: op(A) is M x K, op(B) is K x N; OP = 0 (as stored),
-// 1 (transpose), 2 (conjugate transpose); lda/ldb/ldc are the stored row
-// strides, sa/sb/sc the batch strides.  A block of 256 threads (4 waves)
-// computes a 64 x 64 tile, staging 64 x 16 slices of op(A) and 16 x 64 of
-// op(B) through LDS (zeros outside the matrices); each wave owns 32 x 32
-// outputs as 2 x 2 tiles of v_mfma_f64_16x16x4f64, four real products per
+// row-major matrices, in FP64 (double2) or FP32 (float2): op(A) is M x K,
+// op(B) is K x N; OP = 0 (as stored), 1 (transpose), 2 (conjugate transpose);
+// lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.  A
+// block of 256 threads (4 waves) computes a 64 x 64 tile, staging 64 x 16
+// slices of op(A) and 16 x 64 of op(B) through LDS (zeros outside the
+// matrices); each wave owns 32 x 32 outputs as 2 x 2 tiles of
+// v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32), four real products per
 // complex one (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Lane l supplies
-// A[l % 16][k] and B[k][l % 16] with k = l / 16 of each 4-term step, and
-// holds outputs (4 r + l / 16, l % 16) in its accumulator register r.
+// A[l % 16][k] and B[k][l % 16] with k = l / 16 of each 4-term step; its
+// accumulator register r holds output row 4 r + l / 16 (FP64) or
+// 4 (l / 16) + r (FP32), column l % 16.
 typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-template <int OPA, int OPB>
-__global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, const double2 *__restrict__ B,
-                                               double2 *__restrict__ C, int M, int N, int K, int64_t lda,
+template <typename T> struct ZT;
+template <> struct ZT<double> {
+    using C2 = double2;
+    using V = f64x4;
+    static __device__ V mfma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ int row(int r, int fk) { return 4 * r + fk; }
+};
+template <> struct ZT<float> {
+    using C2 = float2;
+    using V = f32x4;
+    static __device__ V mfma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ int row(int r, int fk) { return 4 * fk + r; }
+};
+
+template <int OPA, int OPB, typename T>
+__global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restrict__ A,
+                                               const typename ZT<T>::C2 *__restrict__ B,
+                                               typename ZT<T>::C2 *__restrict__ C, int M, int N, int K, int64_t lda,
                                                int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc,
                                                int sub) {
+    using C2 = typename ZT<T>::C2;
+    using V = typename ZT<T>::V;
     constexpr int TM = 64, TN = 64, TK = 16;
-    __shared__ double2 As[TK][TM + 1], Bs[TK][TN + 1];
+    __shared__ C2 As[TK][TM + 1], Bs[TK][TN + 1];
     const int64_t b = blockIdx.z;
     A += b * sa;
     B += b * sb;
@@ -171,13 +191,13 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
     const int fr = lane & 15, fk = lane >> 4;
     const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
-    f64x4 accr[2][2], acci[2][2];
+    V accr[2][2], acci[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            accr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-            acci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+            accr[i][j] = V{0, 0, 0, 0};
+            acci[i][j] = V{0, 0, 0, 0};
         }
     for (int k0 = 0; k0 < K; k0 += TK) {
         // 1024 entries of each slice, four per thread
@@ -188,10 +208,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
                 // op(A)[r0 + rr][k0 + kk]
                 const int rr = OPA == 0 ? e / TK : e % TM, kk = OPA == 0 ? e % TK : e / TM;
                 const int r = r0 + rr, k = k0 + kk;
-                double2 v = make_double2(0.0, 0.0);
+                C2 v = {0, 0};
                 if (r < M && k < K) {
                     v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
-                    if (OPA == 2) v = cconj(v);
+                    if (OPA == 2) v.y = -v.y;
                 }
                 As[kk][rr] = v;
             }
@@ -199,10 +219,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
                 // op(B)[k0 + kk][c0 + cc]
                 const int cc = OPB == 0 ? e % TN : e / TK, kk = OPB == 0 ? e / TN : e % TK;
                 const int c = c0 + cc, k = k0 + kk;
-                double2 v = make_double2(0.0, 0.0);
+                C2 v = {0, 0};
                 if (c < N && k < K) {
                     v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
-                    if (OPB == 2) v = cconj(v);
+                    if (OPB == 2) v.y = -v.y;
                 }
                 Bs[kk][cc] = v;
             }
@@ -211,7 +231,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
 #pragma unroll
         for (int k4 = 0; k4 < TK / 4; ++k4) {
             const int kk = 4 * k4 + fk;
-            double2 av[2], bv[2];
+            C2 av[2], bv[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) av[i] = As[kk][wm * 32 + i * 16 + fr];
 #pragma unroll
@@ -220,10 +240,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, accr[i][j], 0, 0, 0);
-                    accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, accr[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, acci[i][j], 0, 0, 0);
-                    acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acci[i][j], 0, 0, 0);
+                    accr[i][j] = ZT<T>::mfma(av[i].x, bv[j].x, accr[i][j]);
+                    accr[i][j] = ZT<T>::mfma(-av[i].y, bv[j].y, accr[i][j]);
+                    acci[i][j] = ZT<T>::mfma(av[i].x, bv[j].y, acci[i][j]);
+                    acci[i][j] = ZT<T>::mfma(av[i].y, bv[j].x, acci[i][j]);
                 }
         }
         __syncthreads();
@@ -234,13 +254,37 @@ __global__ void __launch_bounds__(256) k_zgemm(const double2 *__restrict__ A, co
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wm * 32 + i * 16 + 4 * q + fk, c = c0 + wn * 32 + j * 16 + fr;
+                const int r = r0 + wm * 32 + i * 16 + ZT<T>::row(q, fk), c = c0 + wn * 32 + j * 16 + fr;
                 if (r < M && c < N) {
-                    double2 &o = C[(int64_t)r * ldc + c];
-                    o = sub ? make_double2(o.x - accr[i][j][q], o.y - acci[i][j][q])
-                            : make_double2(accr[i][j][q], acci[i][j][q]);
+                    C2 &o = C[(int64_t)r * ldc + c];
+                    if (sub) {
+                        o.x -= accr[i][j][q];
+                        o.y -= acci[i][j][q];
+                    } else {
+                        o.x = accr[i][j][q];
+                        o.y = acci[i][j][q];
+                    }
                 }
             }
+}
+
+// out[i] = (float2) in[i]
+__global__ void __launch_bounds__(256) k_to_c64(const double2 *__restrict__ in, int64_t n, float2 *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = make_float2((float)in[e].x, (float)in[e].y);
+}
+
+// out[b][j][i][k] = in[b][i][j][k] for float2 tensors (the FP32 factorised
+// operator's axis exchange)
+__global__ void __launch_bounds__(256) k_swap01_c64(const float2 *__restrict__ in, int64_t nb, int64_t n0, int64_t n1,
+                                                    int64_t n2, float2 *__restrict__ out) {
+    const int64_t per = n0 * n1 * n2, total = nb * per;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t bb = e / per, r = e % per;
+        const int64_t k = r % n2, j = (r / n2) % n1, i = r / (n1 * n2);
+        out[bb * per + (j * n0 + i) * n2 + k] = in[e];
+    }
 }
 
 // out[b][j][i][k] = in[b][i][j][k] for nb tensors of shape (n0, n1, n2)
@@ -378,19 +422,20 @@ hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
-                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st, int sub) {
+template <typename T>
+hipError_t zgemm_t(int opa, int opb, const typename ZT<T>::C2 *A, const typename ZT<T>::C2 *B, typename ZT<T>::C2 *C,
+                   int M, int N, int K, int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb,
+                   int64_t sc, hipStream_t st, int sub) {
     if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
     // rows in chunks of 65535 tiles (the grid's y limit)
     constexpr int64_t RCH = 65535 * 64;
     for (int64_t r0 = 0; r0 < M; r0 += RCH) {
         const int m = (int)(M - r0 < RCH ? M - r0 : RCH);
-        const double2 *Ac = opa == 0 ? A + r0 * lda : A + r0;
-        double2 *Cc = C + r0 * ldc;
+        const typename ZT<T>::C2 *Ac = opa == 0 ? A + r0 * lda : A + r0;
+        typename ZT<T>::C2 *Cc = C + r0 * ldc;
         dim3 grid((unsigned)((N + 63) / 64), (unsigned)((m + 63) / 64), (unsigned)batch), block(256);
 #define TNSLQ_ZG(OA, OB) \
-    hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc, sub)
+    hipLaunchKernelGGL((k_zgemm<OA, OB, T>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc, sub)
         if (opa == 0 && opb == 0) TNSLQ_ZG(0, 0);
         else if (opa == 1 && opb == 0) TNSLQ_ZG(1, 0);
         else if (opa == 2 && opb == 0) TNSLQ_ZG(2, 0);
@@ -401,6 +446,29 @@ hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, do
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
+                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
+                        hipStream_t st, int sub) {
+    return zgemm_t<double>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub);
+}
+
+hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, float2 *C, int M, int N, int K,
+                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
+                        hipStream_t st, int sub) {
+    return zgemm_t<float>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub);
+}
+
+hipError_t launch_to_c64(const double2 *in, int64_t n, float2 *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_c64, dim3(blocks_for(n)), dim3(256), 0, st, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_swap01(const float2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, float2 *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_swap01_c64, dim3(blocks_for(nb * n0 * n1 * n2)), dim3(256), 0, st, in, nb, n0, n1, n2, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,

@@ -65,6 +65,7 @@ struct Plan {
     size_t off_Pabe = 0, off_Pabc = 0, off_Cd = 0, off_rho = 0;
     size_t off_Xq = 0, off_Ym = 0;
     size_t off_mps = 0, off_Z1 = 0, off_Z2 = 0, off_Z2p = 0, off_Z3 = 0, off_nrm = 0;
+    size_t off_P32 = 0, off_Q32 = 0, off_X32 = 0;   // complex64 copies (FP32 factorised operator)
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
     size_t total = 0;
@@ -206,19 +207,32 @@ hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream
 hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
                         hipStream_t st, int sub = 0);
+// The same in FP32 (complex64 operands, FP32 matrix instructions).
+hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, float2 *C, int M, int N, int K,
+                        int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
+                        hipStream_t st, int sub = 0);
+// out[i] = complex64(in[i]), n entries.
+hipError_t launch_to_c64(const double2 *in, int64_t n, float2 *out, hipStream_t st);
 // out[b][j][i][k] = (conj) in[b][i][j][k], nb tensors of shape (n0, n1, n2).
 hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,
                          hipStream_t st);
+// launch_swap01 without conjugation, and for complex64 tensors.
+inline hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, double2 *out,
+                                hipStream_t st) {
+    return launch_swap01(in, nb, n0, n1, n2, 0, out, st);
+}
+hipError_t launch_swap01(const float2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, float2 *out,
+                         hipStream_t st);
 // part[256] = sum of |x|^2 over all n entries (partials in part[0..255]).
 hipError_t launch_sumsq(const double2 *x, int64_t n, double *part, hipStream_t st);
-// psi[(a, b, e)] (dA2 x dB2 x dE2, zero padded) = T[(a, u)][w][(b, v)] /
-// sqrt(*sumsq), e = (u W + w) V + v.
 // Normalisation of a two-factor state psi = P Q: with Ahat = P^dagger P and
 // C = Q Q^dagger (both mm entries, the same index order), nrm[0] =
 // Re sum Ahat conj(C) = ||psi||^2, and the np entries of P are divided by its
 // square root.
 hipError_t launch_normalise_factor(const double2 *Ahat, const double2 *C, int64_t mm, double *nrm, double2 *P,
                                    int64_t np, hipStream_t st);
+// psi[(a, b, e)] (dA2 x dB2 x dE2, zero padded) = T[(a, u)][w][(b, v)] /
+// sqrt(*sumsq), e = (u W + w) V + v.
 hipError_t launch_assemble(const double2 *T, int64_t kA, int64_t U, int64_t W, int64_t kB, int64_t V, int64_t dA2,
                            int64_t dB2, int64_t dE2, const double *sumsq, double2 *psi, hipStream_t st);
 

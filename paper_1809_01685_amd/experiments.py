@@ -404,6 +404,21 @@ def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("
                   f"{f['logneg_se']:.4f} after {f['steps_done']} steps in {t_f:.3f} s (factors "
                   f"{f['t_layout_ms']:.1f} ms, matvecs {f['t_matvec_ms']:.1f} ms)", file=sys.stderr, flush=True)
             torch.cuda.empty_cache()
+            # the same in FP32 (complex64 intermediates, FP32 matrix instructions)
+            tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, 10, device=dev, seed=seed, want_arrays=False,
+                             precision="fp32")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, n_steps, device=dev, seed=seed, stop_tol=0.01,
+                                 stop_rule="fit", want_arrays=False, precision="fp32")
+            t_f = time.perf_counter() - t0
+            row["factored_fp32"] = {"t_total_s": t_f, "t_layout_ms": f["t_layout_ms"],
+                                    "t_matvec_ms": f["t_matvec_ms"], "steps": f["steps_done"],
+                                    "logneg": f["logneg"], "logneg_se": f["logneg_se"]}
+            print(f"[mps_blocks] chi {chi}, A {row['A']}, B {row['B']}: factored FP32: E = {f['logneg']:.4f} +- "
+                  f"{f['logneg_se']:.4f} after {f['steps_done']} steps in {t_f:.3f} s (matvecs "
+                  f"{f['t_matvec_ms']:.1f} ms)", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
         rows.append(row)
     return {"workload": "100-site random open-boundary MPS (qubits), two blocks of 8 or 16 sites",
             "precision_dense": precision, "precision_factored": "fp64", "rows": rows}

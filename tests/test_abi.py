@@ -263,7 +263,10 @@ def test_factored_mps_workspace_and_validation_without_device(L):
     # more probes need more room; reorthogonalisation keeps every vector
     assert T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, T.make_options(16, 20, precision="fp64")) > n
     assert T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, T.make_options(8, 20, True, precision="fp64")) > n
-    for bad in (T.make_options(8, 20, precision="fp32"), T.make_options(8, 20, precision="fp64", operator="lazy")):
+    # FP32 halves the intermediates and adds complex64 copies of the factors
+    n32 = T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, T.make_options(8, 20, precision="fp32"))
+    assert 0 < n32
+    for bad in (T.make_options(8, 20, precision="bf16x3"), T.make_options(8, 20, precision="fp64", operator="lazy")):
         with pytest.raises(T.TnslqError):
             T.tnslq_workspace_bytes_mps(tensors, 2, 4, 6, 4, bad)
     with pytest.raises(T.TnslqError):
