@@ -38,3 +38,26 @@ def test_contraction_kernels_use_no_scratch(tmp_path):
     gemms = {k: v for k, v in usage.items() if "k_cgemm_nt_mfma" in k}
     assert len(gemms) == 3, usage
     assert all(v == 0 for v in gemms.values()), gemms
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+def test_mps_products_keep_accumulators_in_vgprs(tmp_path):
+    # the MPS complex products carry matrix-instruction accumulators across
+    # their reduction loop; built as the library builds them (VGPR form) they
+    # use no accumulation registers, hence no copies between register files,
+    # and no scratch
+    from paper_1809_01685_amd import build as b
+    out = tmp_path / "m.s"
+    cmd = [_hipcc(), *[f for f in b.FLAGS if f != "-fPIC"], "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+           "--cuda-device-only", "-S", os.path.join(CSRC, "mps.hip"), "-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    asm = out.read_text()
+    assert "v_mfma_f64_16x16x4" in asm and "v_mfma_f32_16x16x4" in asm
+    assert "v_accvgpr" not in asm
+    spills = [int(x) for x in re.findall(r"\.(?:vgpr|sgpr)_spill_count:\s+(\d+)", asm)]
+    assert spills and max(spills) == 0
+    scratch = [int(x) for x in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", asm)]
+    assert scratch and max(scratch) == 0
+    # and the build applies that form to this file
+    assert "-amdgpu-mfma-vgpr-form=1" in open(b.__file__).read()
