@@ -228,7 +228,13 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     if (pl.mpsf) {
         const size_t per = mes * (size_t)(UpM * pl.dB + 2 * UpM * MV + pl.dA * MV + 2 * n);
         pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)K, (int64_t)(MPS_BUDGET / per), 65535}));
-        pl.S = pl.S1 = 1;
+        pl.S1 = 1;
+        // the last product (d_A' x d_B' outputs, a sum over MV terms) has few
+        // output tiles: split its reduction until the chunk fills the chip,
+        // at least 256 terms per split; passA sums the splits
+        const int64_t ytiles = ((pl.dA + 63) / 64) * ((pl.dB + 63) / 64) * pl.kc;
+        pl.S = 1;
+        while (ytiles * pl.S < 1024 && MV / (2 * pl.S) >= 256 && (int64_t)pl.kc * 2 * pl.S <= 65535) pl.S *= 2;
     }
 
     size_t o = 0;
@@ -243,7 +249,7 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.off_Z2 = take((size_t)pl.kc * UpM * MV * mes);
         pl.off_Z2p = take((size_t)pl.kc * UpM * MV * mes);
         pl.off_Z3 = take((size_t)pl.kc * pl.dA * MV * mes);
-        pl.off_Ypart = take((size_t)pl.kc * n * mes);
+        pl.off_Ypart = take((size_t)pl.S * pl.kc * n * mes);
         pl.off_nrm = take((size_t)2 * pl.mM * pl.mM * 16 + 64);
         if (prec == TNSLQ_FP32) {
             pl.off_P32 = take((size_t)pl.dA * UpM * 8);
@@ -999,7 +1005,9 @@ int mps_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2)
         TNSLQ_HIP(launch_swap01(Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, Z2p, c.st));
         TNSLQ_HIP(launch_zgemm(0, 0, P, Z2p, Z3, kA, (int)MV, (int)UpM, UpM, MV, MV, kcur, 0, UpM * MV, kA * MV,
                                c.st));
-        TNSLQ_HIP(launch_zgemm(0, 2, Z3, Q, Y, kA, kB, (int)MV, MV, MV, kB, kcur, kA * MV, 0, n, c.st));
+        // split s of the reduction at Y + s kc n (passA sums the splits)
+        TNSLQ_HIP(launch_zgemm(0, 2, Z3, Q, Y, kA, kB, (int)MV, MV, MV, kB, kcur, kA * MV, 0, n, c.st, 0, pl.S,
+                               (int64_t)pl.kc * n));
         return TNSLQ_OK;
     };
     int rc;

@@ -179,15 +179,20 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
                                                const typename ZT<T>::C2 *__restrict__ B,
                                                typename ZT<T>::C2 *__restrict__ C, int M, int N, int K, int64_t lda,
                                                int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc,
-                                               int sub) {
+                                               int sub, int ks, int64_t csk) {
     using C2 = typename ZT<T>::C2;
     using V = typename ZT<T>::V;
     constexpr int TM = 64, TN = 64, TK = 16;
     __shared__ C2 As[TK][TM + 1], Bs[TK][TN + 1];
-    const int64_t b = blockIdx.z;
+    // grid z = (batch entry b, reduction split s): split s sums terms
+    // [kbeg, kend) into C + b sc + s csk
+    const int64_t b = blockIdx.z / ks;
+    const int sp = (int)(blockIdx.z % ks);
+    const int Kc = ((K + ks - 1) / ks + TK - 1) / TK * TK;
+    const int kbeg = sp * Kc, kend = min(K, kbeg + Kc);
     A += b * sa;
     B += b * sb;
-    C += b * sc;
+    C += b * sc + sp * csk;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
     const int fr = lane & 15, fk = lane >> 4;
     const int r0 = blockIdx.y * TM, c0 = blockIdx.x * TN;
@@ -199,7 +204,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
             accr[i][j] = V{0, 0, 0, 0};
             acci[i][j] = V{0, 0, 0, 0};
         }
-    for (int k0 = 0; k0 < K; k0 += TK) {
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         // 1024 entries of each slice, four per thread
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -209,7 +214,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
                 const int rr = OPA == 0 ? e / TK : e % TM, kk = OPA == 0 ? e % TK : e / TM;
                 const int r = r0 + rr, k = k0 + kk;
                 C2 v = {0, 0};
-                if (r < M && k < K) {
+                if (r < M && k < kend) {
                     v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
                     if (OPA == 2) v.y = -v.y;
                 }
@@ -220,7 +225,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
                 const int cc = OPB == 0 ? e % TN : e / TK, kk = OPB == 0 ? e / TN : e % TK;
                 const int c = c0 + cc, k = k0 + kk;
                 C2 v = {0, 0};
-                if (c < N && k < K) {
+                if (c < N && k < kend) {
                     v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
                     if (OPB == 2) v.y = -v.y;
                 }
@@ -425,17 +430,18 @@ hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream
 template <typename T>
 hipError_t zgemm_t(int opa, int opb, const typename ZT<T>::C2 *A, const typename ZT<T>::C2 *B, typename ZT<T>::C2 *C,
                    int M, int N, int K, int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb,
-                   int64_t sc, hipStream_t st, int sub) {
-    if (batch < 1 || batch > 65535) return hipErrorInvalidValue;
+                   int64_t sc, hipStream_t st, int sub, int ks, int64_t csk) {
+    if (batch < 1 || ks < 1 || (int64_t)batch * ks > 65535 || (sub && ks > 1)) return hipErrorInvalidValue;
     // rows in chunks of 65535 tiles (the grid's y limit)
     constexpr int64_t RCH = 65535 * 64;
     for (int64_t r0 = 0; r0 < M; r0 += RCH) {
         const int m = (int)(M - r0 < RCH ? M - r0 : RCH);
         const typename ZT<T>::C2 *Ac = opa == 0 ? A + r0 * lda : A + r0;
         typename ZT<T>::C2 *Cc = C + r0 * ldc;
-        dim3 grid((unsigned)((N + 63) / 64), (unsigned)((m + 63) / 64), (unsigned)batch), block(256);
-#define TNSLQ_ZG(OA, OB) \
-    hipLaunchKernelGGL((k_zgemm<OA, OB, T>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc, sub)
+        dim3 grid((unsigned)((N + 63) / 64), (unsigned)((m + 63) / 64), (unsigned)(batch * ks)), block(256);
+#define TNSLQ_ZG(OA, OB)                                                                                       \
+    hipLaunchKernelGGL((k_zgemm<OA, OB, T>), grid, block, 0, st, Ac, B, Cc, m, N, K, lda, ldb, ldc, sa, sb, sc, sub, \
+                       ks, csk)
         if (opa == 0 && opb == 0) TNSLQ_ZG(0, 0);
         else if (opa == 1 && opb == 0) TNSLQ_ZG(1, 0);
         else if (opa == 2 && opb == 0) TNSLQ_ZG(2, 0);
@@ -450,14 +456,14 @@ hipError_t zgemm_t(int opa, int opb, const typename ZT<T>::C2 *A, const typename
 
 hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st, int sub) {
-    return zgemm_t<double>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub);
+                        hipStream_t st, int sub, int ks, int64_t csk) {
+    return zgemm_t<double>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub, ks, csk);
 }
 
 hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, float2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st, int sub) {
-    return zgemm_t<float>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub);
+                        hipStream_t st, int sub, int ks, int64_t csk) {
+    return zgemm_t<float>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub, ks, csk);
 }
 
 hipError_t launch_to_c64(const double2 *in, int64_t n, float2 *out, hipStream_t st) {

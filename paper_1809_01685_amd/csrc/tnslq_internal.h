@@ -203,14 +203,16 @@ hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx,
 hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream_t st);
 // C[b] = op(A[b]) op(B[b]) (with sub: C[b] -= op(A[b]) op(B[b])), op 0 = as
 // stored, 1 = transpose, 2 = conjugate transpose (supported pairs: (0,0),
-// (1,0), (2,0), (0,2)); op(A) is M x K.
+// (1,0), (2,0), (0,2)); op(A) is M x K.  With ks > 1 the reduction is split
+// in ks ranges and split s writes its partial product to C[b] + s csk (not
+// with sub); batch * ks <= 65535.
 hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st, int sub = 0);
+                        hipStream_t st, int sub = 0, int ks = 1, int64_t csk = 0);
 // The same in FP32 (complex64 operands, FP32 matrix instructions).
 hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, float2 *C, int M, int N, int K,
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
-                        hipStream_t st, int sub = 0);
+                        hipStream_t st, int sub = 0, int ks = 1, int64_t csk = 0);
 // out[i] = complex64(in[i]), n entries.
 hipError_t launch_to_c64(const double2 *in, int64_t n, float2 *out, hipStream_t st);
 // out[b][j][i][k] = (conj) in[b][i][j][k], nb tensors of shape (n0, n1, n2).

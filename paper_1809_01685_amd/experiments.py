@@ -353,7 +353,7 @@ def run_arith_peaks(reps=5, blocks=2048, target_ms=50.0):
             "rows": rows}
 
 
-def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("dense", "factored")):
+def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("dense", "factored"), chis=None):
     """Two blocks of a 100-site random MPS: the dense route (effective state,
     then tnslq_logneg in `precision`) against the factorised operator (FP64),
     both with the fit rule and a 1% target."""
@@ -368,6 +368,8 @@ def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("
                                        (16, 32, 16, 52, 16, True), (32, 33, 16, 50, 16, False),
                                        (64, 42, 8, 50, 8, True), (64, 41, 8, 50, 8, False),
                                        (180, 42, 8, 50, 8, True)):
+        if chis and chi not in chis:
+            continue
         ts = ti.random_mps(100, 2, chi, seed)
         row = {"n_sites": 100, "chi": chi, "A": [a0, a0 + la], "B": [b0, b0 + lb], "gap": b0 - a0 - la}
         if "dense" in routes and dense:
@@ -449,13 +451,15 @@ def main(argv=None):
     sp.add_argument("--ms", type=float, default=50.0)
     sp = sub.add_parser("mps_blocks")
     sp.add_argument("--routes", default="dense,factored")
+    sp.add_argument("--chi", default="", help="comma list: only the rows of these bond dimensions")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
     if args.cmd == "scrambling":
         out = run_scrambling(_parse_range(args.depths), precision=args.precision)
     elif args.cmd == "mps_blocks":
-        out = run_mps_blocks(routes=tuple(args.routes.split(",")))
+        out = run_mps_blocks(routes=tuple(args.routes.split(",")),
+                             chis=[int(x) for x in args.chi.split(",") if x] or None)
     elif args.cmd == "hbm_peak":
         out = run_hbm_peak()
     elif args.cmd == "arith_peaks":
