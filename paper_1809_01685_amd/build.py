@@ -24,6 +24,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libtnslq.so")
 PEAK_SRC = os.path.join(PKG, "peak", "peak.hip")
 PEAK_OUT = os.path.join(PKG, "libtnslq_peak.so")
+# sources built with the matrix instructions' VGPR form (see _compile)
+VGPR_FORM = ("peak.hip", "mps.hip", "entropy.hip")
 BUILD = os.path.join(PKG, "_build")
 
 ARCH = "gfx950"
@@ -52,7 +54,7 @@ def _compile(src: str) -> str:
     # loops that carry matrix-instruction accumulators from one iteration to
     # the next: in the accumulator-register form the compiler copied them
     # between register files every iteration
-    extra = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] if src in (PEAK_SRC, os.path.join(CSRC, "mps.hip")) else []
+    extra = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] if os.path.basename(src) in VGPR_FORM else []
     cmd = [hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -304,6 +304,95 @@ __global__ void __launch_bounds__(CM_THREADS) k_colmac_plain(ColmacDesc g) {
         }
 }
 
+// The plain column MAC for groups of 8 (NVG = 1) or 16 (NVG = 2) vectors on
+// the FP64 matrix instructions (full 512-column panels, rows per split a
+// multiple of 4).  Per 4 rows, each 16-column tile of M takes per group of 8
+// vectors two v_mfma_f64_16x16x4f64 into one accumulator:
+//   D = Mr [Vr | Vi] + Mi [-Vi | Vr]        (M V)
+//   D = Mr [Vr | Vi] + Mi [Vi | -Vr]        (conj(M) V)
+// (16 x 4 blocks of M's real and imaginary parts against 4 x 16 blocks of the
+// eight vectors' real and imaginary parts), so that D's column j < 8 is the
+// real and j >= 8 the imaginary part of vector j % 8.  A wave owns NQ runs of
+// 32 columns, each the even and the odd columns' tiles (NQ = 2 / NVG: 32
+// accumulator registers, four waves per SIMD; a block covers 128 NQ columns
+// of a panel).  Lane l loads the column pair 2 (l % 16), 2 (l % 16) + 1 of a
+// run in row l / 16 of the 4 (the A operand: row l % 16 of a tile, term
+// l / 16), reads vector entry (l % 8, row l / 16) of each group from LDS (the
+// B operand: term l / 16, column l % 16), and holds D's rows 4 r + l / 16,
+// column l % 16, in register r.
+template <int DTYPE, bool CONJ, int NVG>
+__global__ void __launch_bounds__(CM_THREADS) k_colmac_mfma(ColmacDesc g) {
+    typedef __attribute__((ext_vector_type(4))) double f64x4;
+    constexpr int KG = 8 * NVG, CH = 64;        // vectors per group, vector rows staged per chunk
+    constexpr int NQ = 2 / NVG;                 // 32-column runs per wave
+    constexpr int BPP = CM_COLS / (128 * NQ);   // blocks per panel
+    __shared__ double2 vs[KG][CH];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int fr = lane & 15, fk = lane >> 4;
+    const int s = blockIdx.y;
+    const int v0 = blockIdx.z * KG;
+    const int kn = g.NV - v0 < KG ? g.NV - v0 : KG;
+    const int64_t i0 = (int64_t)s * g.rows_per_split;
+    const int64_t i1 = i0 + g.rows_per_split;
+    const int64_t pc0 = (int64_t)(blockIdx.x % BPP) * 128 * NQ + (int64_t)w * 32 * NQ + 2 * fr;
+    const int64_t pbase = (int64_t)(blockIdx.x / BPP) * g.R * CM_COLS;   // the panel
+    f64x4 acc[NQ][2][NVG];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int h = 0; h < NVG; ++h) acc[q][0][h] = acc[q][1][h] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int vj = fr & 7;
+    const bool imag_col = fr >= 8;
+    for (int64_t ib = i0; ib < i1; ib += CH) {
+        const int nrow = (int)(i1 - ib < CH ? i1 - ib : CH);
+        __syncthreads();
+        for (int e = t; e < KG * CH; e += CM_THREADS) {
+            const int k = e / CH, ii = e % CH;
+            vs[k][ii] = (k < kn && ii < nrow) ? g.V[(int64_t)(v0 + k) * g.R + ib + ii] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int r0 = 0; r0 < nrow; r0 += 4) {
+            const int rr = r0 + fk;   // this lane's row of the step
+            double2 ma[NQ], mb[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (rr < nrow) {
+                    load_pair<DTYPE>(g.M, pbase + (ib + rr) * CM_COLS + pc0 + 32 * q, ma[q], mb[q]);
+                } else {
+                    ma[q] = make_double2(0.0, 0.0);
+                    mb[q] = ma[q];
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < NVG; ++h) {
+                const double2 v = vs[8 * h + vj][rr < CH ? rr : 0];
+                const double bp = imag_col ? v.y : v.x;
+                const double bq = CONJ ? (imag_col ? -v.x : v.y) : (imag_col ? v.x : -v.y);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    acc[q][0][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[q].x, bp, acc[q][0][h], 0, 0, 0);
+                    acc[q][0][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[q].y, bq, acc[q][0][h], 0, 0, 0);
+                    acc[q][1][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(mb[q].x, bp, acc[q][1][h], 0, 0, 0);
+                    acc[q][1][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(mb[q].y, bq, acc[q][1][h], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D row 4 r + fk of tile (q, e) is column 128 NQ blockIdx.x + 32 NQ w + 32 q + 2 (4 r + fk) + e
+    const int64_t cb = (int64_t)blockIdx.x * 128 * NQ + (int64_t)w * 32 * NQ;
+#pragma unroll
+    for (int h = 0; h < NVG; ++h) {
+        if (8 * h + vj >= kn) continue;
+        double *o = (double *)(g.out + s * g.osplit + (int64_t)(v0 + 8 * h + vj) * g.C) + (imag_col ? 1 : 0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[2 * (cb + 32 * q + 2 * (4 * r + fk) + e)] = acc[q][e][h][r];
+    }
+}
+
 // Z[k][i] = sum_s Zp[s][k][i], n = K x n_i elements.
 __global__ void __launch_bounds__(256) k_sum_splits(const double2 *__restrict__ part, int S, int64_t n,
                                                     double2 *__restrict__ Z) {
@@ -474,6 +563,36 @@ hipError_t launch_colmac(int dtype, int conj, ColmacDesc g, hipStream_t st) {
     if (g.C < CM_COLS && CM_COLS % g.C != 0) return hipErrorInvalidValue;   // narrow panels: C divides 512
     if (g.vsh < 0 || g.vsh > 30 || g.osh < 0 || g.osh > 30) return hipErrorInvalidValue;
     g.rows_per_split = g.R / g.S;
+    // more than 4 vectors over full panels in 4-row steps: the matrix
+    // instructions, 8 or 16 vectors per pass over M (16 and several passes
+    // beyond)
+    const bool plain = g.vsh == 0 && g.vs1 == g.R && g.vsi == 1 && g.osh == 0 && g.os1 == g.C && g.osc == 1;
+    if (g.NV > 4 && plain && g.C % CM_COLS == 0 && g.rows_per_split % 4 == 0) {
+        const int nvg = g.NV > 8 ? 2 : 1;
+        const int64_t gx = (g.C / CM_COLS) * (nvg == 1 ? 2 : 4), gz = (g.NV + 8 * nvg - 1) / (8 * nvg);
+        if (gx > 0x7fffffff || g.S > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
+        const dim3 grid((unsigned)gx, (unsigned)g.S, (unsigned)gz);
+#define TNSLQ_CMM(T, CJ, G) hipLaunchKernelGGL((k_colmac_mfma<T, CJ, G>), grid, dim3(CM_THREADS), 0, st, g)
+        if (dtype == TNSLQ_C128) {
+            if (conj) {
+                if (nvg == 1) TNSLQ_CMM(TNSLQ_C128, true, 1);
+                else TNSLQ_CMM(TNSLQ_C128, true, 2);
+            } else {
+                if (nvg == 1) TNSLQ_CMM(TNSLQ_C128, false, 1);
+                else TNSLQ_CMM(TNSLQ_C128, false, 2);
+            }
+        } else {
+            if (conj) {
+                if (nvg == 1) TNSLQ_CMM(TNSLQ_C64, true, 1);
+                else TNSLQ_CMM(TNSLQ_C64, true, 2);
+            } else {
+                if (nvg == 1) TNSLQ_CMM(TNSLQ_C64, false, 1);
+                else TNSLQ_CMM(TNSLQ_C64, false, 2);
+            }
+        }
+#undef TNSLQ_CMM
+        return hipGetLastError();
+    }
     // vectors per pass over M: the smallest of 1, 2, 4, 8 covering NV (8 and
     // several passes beyond)
     const int kg = g.NV <= 1 ? 1 : g.NV <= 2 ? 2 : g.NV <= 4 ? 4 : 8;

@@ -55,6 +55,24 @@ def test_spectral_sum_matches_oracle_on_same_probes(dev, L, s, m, fn, dtype):
     assert g["value_se"] == pytest.approx(o["value_se"], rel=1e-6)
 
 
+@pytest.mark.parametrize("K", [6, 8, 13])
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_full_panels_eight_vector_groups_match_oracle(dev, K, dtype):
+    # 20 qubits, S = 0-9 (d = d_R = 1024): both passes read full 512-column
+    # panels, so groups of 8 vectors (6 of 8, 8, 8 + 5) run on the FP64
+    # matrix instructions; the same coefficients as the oracle on the same
+    # probes, as for the vector-unit passes
+    L, s, m = 20, list(range(10)), 12
+    psi_t, psi_np = _dev(ti.haar_state(L, 7), dtype, dev)
+    for fn in ("entropy", "purity"):
+        g = T.tnslq_spectral_sum(psi_t, L, s, fn, K, m, seed=4)
+        o = en.slq_spectral_sum(psi_np, L, s, fn, K, m, seed=4)
+        assert np.allclose(g["alpha"], o["alpha"], rtol=1e-10, atol=1e-12 * np.abs(o["alpha"]).max())
+        assert np.allclose(g["beta"][:, 1:], o["beta"][:, 1:], rtol=1e-10, atol=0)
+        assert np.allclose(g["G"], o["G"], rtol=1e-9, atol=0)
+        assert g["value"] == pytest.approx(o["value"], rel=1e-9)
+
+
 def test_reorthogonalised_entropy_matches_oracle_and_exact(dev):
     import torch
     L, s = 12, list(range(5))

@@ -41,23 +41,25 @@ def test_contraction_kernels_use_no_scratch(tmp_path):
 
 
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
-def test_mps_products_keep_accumulators_in_vgprs(tmp_path):
-    # the MPS complex products carry matrix-instruction accumulators across
-    # their reduction loop; built as the library builds them (VGPR form) they
-    # use no accumulation registers, hence no copies between register files,
-    # and no scratch
+@pytest.mark.parametrize("src,instrs", [("mps.hip", ("v_mfma_f64_16x16x4", "v_mfma_f32_16x16x4")),
+                                        ("entropy.hip", ("v_mfma_f64_16x16x4",))])
+def test_matrix_loops_keep_accumulators_in_vgprs(tmp_path, src, instrs):
+    # the MPS complex products and the entropy's eight-vector column MAC carry
+    # matrix-instruction accumulators across their reduction loops; built as
+    # the library builds them (VGPR form) they use no accumulation registers,
+    # hence no copies between register files, and no scratch
     from paper_1809_01685_amd import build as b
     out = tmp_path / "m.s"
     cmd = [_hipcc(), *[f for f in b.FLAGS if f != "-fPIC"], "-mllvm", "-amdgpu-mfma-vgpr-form=1",
-           "--cuda-device-only", "-S", os.path.join(CSRC, "mps.hip"), "-o", str(out)]
+           "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", str(out)]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     asm = out.read_text()
-    assert "v_mfma_f64_16x16x4" in asm and "v_mfma_f32_16x16x4" in asm
+    assert all(i in asm for i in instrs)
     assert "v_accvgpr" not in asm
     spills = [int(x) for x in re.findall(r"\.(?:vgpr|sgpr)_spill_count:\s+(\d+)", asm)]
     assert spills and max(spills) == 0
     scratch = [int(x) for x in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", asm)]
     assert scratch and max(scratch) == 0
     # and the build applies that form to this file
-    assert "-amdgpu-mfma-vgpr-form=1" in open(b.__file__).read()
+    assert src in b.VGPR_FORM
