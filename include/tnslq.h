@@ -59,7 +59,7 @@ enum { TNSLQ_C64 = 0, TNSLQ_C128 = 1 };
 
 /* Arithmetic of the two contractions (Sec. V Eq. 4) on the matrix cores.  The
  * Lanczos recurrence, reorthogonalisation, tridiagonal eigensolve and
- * statistics are FP64 in every mode.  With K d_B <= 4 (d_B the smaller side)
+ * statistics are FP64 in every mode.  With K d_B <= 8 (d_B the smaller side)
  * the contractions are bound by HBM, not by arithmetic, and run instead as two
  * streaming passes over psi in its own dtype with FP64 products and sums,
  * whatever the precision (tnslq_result.streamed).
@@ -88,7 +88,7 @@ enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
  *                            (at most 4 GiB of it).
  *   TNSLQ_OPERATOR_AUTO      the explicit form when it fits and its padded
  *                            flop count over n_steps matvecs is the smaller,
- *                            else the lazy form (always lazy when K d_B <= 4,
+ *                            else the lazy form (always lazy when K d_B <= 8,
  *                            the streaming regime). */
 enum { TNSLQ_OPERATOR_AUTO = 0, TNSLQ_OPERATOR_LAZY = 1, TNSLQ_OPERATOR_EXPLICIT = 2 };
 
@@ -193,7 +193,7 @@ typedef struct {
                                |E_j - E_{j-5}| (TNSLQ_STOP_DIFF, NaN for j < 6)
                                or eps_L / (T ln 2) (TNSLQ_STOP_FIT)            */
     int streamed;           /* 1 if the contractions ran as two streaming
-                               passes over psi with FP64 arithmetic (K d_B <= 4
+                               passes over psi with FP64 arithmetic (K d_B <= 8
                                after the role choice), 0 on the matrix cores
                                in `precision`                                  */
     int explicit_operator;  /* 1 if rho^{T_B} was formed explicitly

@@ -57,6 +57,10 @@ int reduction_blocks(int64_t n, int K) {
 // operator and of its dense FP32/FP64 precursor.
 constexpr int64_t EXPLICIT_MAX_N = 16384;
 constexpr size_t EXPLICIT_BUDGET = size_t(4) << 30;
+// the streaming form of the lazy operator up to this many vectors K d_B (up
+// to 4 its passes run on the vector units, up to 8 on the FP64 matrix
+// instructions, both at the HBM rate; from 16 the split-BF16 bricks are faster)
+constexpr int64_t STREAM_MAX_VECTORS = 8;
 // intermediates of the factorised MPS operator (probes are chunked to fit)
 constexpr size_t MPS_BUDGET = size_t(8) << 30;
 
@@ -192,11 +196,11 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         while (tiles1 * pl.S1 < 2048 && pl.nst1 % (2 * pl.S1) == 0 && pl.nst1 / (2 * pl.S1) >= 8) pl.S1 *= 2;
     const int64_t n = pl.dAB;
     pl.nblk = reduction_blocks(n, K);
-    // HBM regime: with K d_B <= 4 vectors the contractions do at most 4 complex
-    // multiply-adds per element of psi and the 128 x 128 matrix-core tiles
-    // would be mostly padding; they run instead as two streaming passes over
-    // psi in its own dtype with FP64 products and sums.
-    pl.stream = !pl.expl && !pl.mpsf && (int64_t)K * pl.dB <= 4;
+    // HBM regime: with K d_B <= STREAM_MAX_VECTORS vectors the contractions do
+    // at most that many complex multiply-adds per element of psi and the
+    // 128 x 128 matrix-core tiles would be mostly padding; they run instead as
+    // two streaming passes over psi in its own dtype with FP64 products and sums.
+    pl.stream = !pl.expl && !pl.mpsf && (int64_t)K * pl.dB <= STREAM_MAX_VECTORS;
     if (pl.expl) {
         // one dense product per matvec: rho^{T_B} (n rows, reduction n) with
         // the K vectors (rows k, reduction n), split-K to fill the chip

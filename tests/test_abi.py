@@ -71,7 +71,7 @@ def test_operator_form_choice_and_limits(L):
     with pytest.raises(T.TnslqError, match="explicit operator"):
         T.tnslq_workspace_bytes(T.TNSLQ_C64, 30, a30, b30, T.make_options(8, 10, precision="bf16x3",
                                                                          operator="explicit"))
-    # K d_B <= 4 (streaming regime): auto stays lazy
+    # K d_B <= 8 (streaming regime): auto stays lazy
     o1 = T.make_options(1, 10, operator="auto")
     assert T.tnslq_workspace_bytes(T.TNSLQ_C64, 16, list(range(8)), [8, 9], o1) == T.tnslq_workspace_bytes(
         T.TNSLQ_C64, 16, list(range(8)), [8, 9], T.make_options(1, 10, operator="lazy"))

@@ -115,7 +115,7 @@ def test_auto_takes_the_cheaper_form(dev):
     r = T.tnslq_logneg(psi_t, 20, list(range(8)), list(range(8, 16)), 4, 6, precision="fp32", seed=0,
                        want_arrays=False)
     assert r["explicit_operator"] == 0
-    # K d_B <= 4: the streaming passes
+    # K d_B <= 8: the streaming passes
     r = T.tnslq_logneg(psi_t, 20, list(range(6)), [10], 2, 6, precision="fp32", seed=0, want_arrays=False)
     assert r["explicit_operator"] == 0 and r["streamed"] == 1
     del psi_t
