@@ -139,3 +139,15 @@ def test_30_qubit_half_chain_entropy_is_pages_value(dev):
     assert p["value"] == pytest.approx(en.haar_mean_purity(1 << 15, 1 << 15), rel=0.02)
     del psi
     torch.cuda.empty_cache()
+
+
+def test_matrix_instruction_passes_are_deterministic(dev):
+    # the 8- and 16-vector passes (FP64 matrix instructions) sum in a fixed
+    # order: reruns give bitwise identical coefficients
+    L, s = 20, list(range(10))
+    psi_t, _ = _dev(ti.haar_state(L, 2), np.complex64, dev)
+    for K in (8, 16):
+        r1 = T.tnslq_spectral_sum(psi_t, L, s, "entropy", K, 8, seed=1)
+        r2 = T.tnslq_spectral_sum(psi_t, L, s, "entropy", K, 8, seed=1)
+        assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
+        assert r1["value"] == r2["value"]

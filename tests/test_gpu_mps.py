@@ -180,3 +180,15 @@ def test_factored_probes_in_chunks(dev):
     assert np.max(np.abs(g["alpha"] - o["alpha"])) <= 1e-10 * np.max(np.abs(o["alpha"]))
     assert np.max(np.abs(g["beta"] - o["beta"])) <= 1e-10 * np.max(np.abs(o["beta"]))
     assert np.allclose(g["G"], o["G"], rtol=1e-10, atol=1e-14)
+
+
+def test_factored_route_is_deterministic(dev):
+    # factors, normalisation and the reduction splits of the last product
+    # are summed in a fixed order: reruns give bitwise identical coefficients
+    L, chi, a0, LA, b0, LB = GEOMETRIES[3]
+    ts = ti.random_mps(L, 2, chi, L + chi)
+    for prec in ("fp64", "fp32"):
+        r1 = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 4, 10, device=dev, seed=3, precision=prec)
+        r2 = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 4, 10, device=dev, seed=3, precision=prec)
+        assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
+        assert r1["logneg"] == r2["logneg"]
