@@ -592,16 +592,26 @@ int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t 
 
 // R[k][(l, r)] for a section S[l][phys][r]: S itself with its first two axes
 // exchanged, or (compressed) R = L^dagger with L L^dagger = S^dagger S over
-// the physical index.
+// the physical index.  The Gram product's reduction over the physical index
+// is split until it fills the chip (partials in `part`, part_cap entries),
+// then summed.
 int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, double2 *R, double2 *tmp, double2 *G,
-                 int *failp, double *dscr, hipStream_t st) {
+                 double2 *part, int64_t part_cap, int *failp, double *dscr, hipStream_t st) {
     if (!comp) {
         TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, R, st));
         return TNSLQ_OK;
     }
     const int64_t n = l * r;
     TNSLQ_HIP(launch_swap01(S, 1, l, ph, r, 0, tmp, st));   // [phys][(l r)]
-    TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
+    const int64_t tiles = ((n + 63) / 64) * ((n + 63) / 64);
+    int ks = 1;
+    while (tiles * ks < 1024 && ph / (2 * ks) >= 256 && 2 * ks * n * n <= part_cap && 2 * ks <= 64) ks *= 2;
+    if (ks > 1) {
+        TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, part, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st, 0, ks, n * n));
+        TNSLQ_HIP(launch_sum_splits(part, ks, n * n, G, st));
+    } else {
+        TNSLQ_HIP(launch_zgemm(2, 0, tmp, tmp, G, (int)n, (int)n, (int)ph, n, n, n, 1, 0, 0, 0, st));
+    }
     TNSLQ_HIP(launch_cholesky(G, (int)n, failp, dscr, st));
     TNSLQ_HIP(launch_swap01(G, 1, n, n, 1, 1, R, st));
     return TNSLQ_OK;
@@ -649,11 +659,12 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
     TNSLQ_HIP(launch_zgemm(0, 0, SBy, Er, buf(mp.off_SB), (int)(mp.Nb * mp.pB), (int)mp.V, mp.bond[mp.b1],
                            mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
     // vertical decompositions
-    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), failp + 2,
-                           dscr, st)))
+    // (the sections' scratch s1, s2 is free again: the Gram products' partials)
+    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), s1,
+                           mp.smax, failp + 2, dscr, st)))
         return rc;
-    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), failp + 3,
-                           dscr, st)))
+    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), s1,
+                           mp.smax, failp + 3, dscr, st)))
         return rc;
     TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
     f.Q = buf(mp.off_RB);
