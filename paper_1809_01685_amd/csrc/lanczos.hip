@@ -248,48 +248,53 @@ __global__ void k_steps(const double *__restrict__ alpha, const double *__restri
 // (d, e) by implicit QL with Wilkinson-type shifts (Bowdler, Martin, Reinsch
 // & Wilkinson 1968), accumulating only the first row of the eigenvector
 // matrix.  e[i] couples d[i] and d[i+1]; e[n-1] must be 0.  On return d holds
-// the eigenvalues and z the first components.
-__device__ void tridiag_ql_first_row(int n, double *d, double *e, double *z) {
-    for (int i = 0; i < n; ++i) z[i] = (i == 0) ? 1.0 : 0.0;
+// the eigenvalues and z the first components.  Entry i of each array sits at
+// index i * ST (the arrays of several threads interleaved in LDS).
+template <int ST>
+__device__ void tridiag_ql_first_row(int n, double *d_, double *e_, double *z_) {
+    auto d = [&](int i) -> double & { return d_[i * ST]; };
+    auto e = [&](int i) -> double & { return e_[i * ST]; };
+    auto z = [&](int i) -> double & { return z_[i * ST]; };
+    for (int i = 0; i < n; ++i) z(i) = (i == 0) ? 1.0 : 0.0;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         while (true) {
             int mm = l;
             for (; mm < n - 1; ++mm) {
-                const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-                if (fabs(e[mm]) <= DBL_EPSILON * dd) break;
+                const double dd = fabs(d(mm)) + fabs(d(mm + 1));
+                if (fabs(e(mm)) <= DBL_EPSILON * dd) break;
             }
             if (mm == l || ++iter > 64) break;
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double g = (d(l + 1) - d(l)) / (2.0 * e(l));
             double r = hypot(g, 1.0);
-            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+            g = d(mm) - d(l) + e(l) / (g + copysign(r, g));
             double s = 1.0, c = 1.0, p = 0.0;
             bool early = false;
             for (int i = mm - 1; i >= l; --i) {
-                const double f = s * e[i], bb = c * e[i];
+                const double f = s * e(i), bb = c * e(i);
                 r = hypot(f, g);
-                e[i + 1] = r;
+                e(i + 1) = r;
                 if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[mm] = 0.0;
+                    d(i + 1) -= p;
+                    e(mm) = 0.0;
                     early = true;
                     break;
                 }
                 s = f / r;
                 c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * bb;
+                g = d(i + 1) - p;
+                r = (d(i) - g) * s + 2.0 * c * bb;
                 p = s * r;
-                d[i + 1] = g + p;
+                d(i + 1) = g + p;
                 g = c * r - bb;
-                const double fz = z[i + 1];
-                z[i + 1] = s * z[i] + c * fz;
-                z[i] = c * z[i] - s * fz;
+                const double fz = z(i + 1);
+                z(i + 1) = s * z(i) + c * fz;
+                z(i) = c * z(i) - s * fz;
             }
             if (early) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[mm] = 0.0;
+            d(l) -= p;
+            e(l) = g;
+            e(mm) = 0.0;
         }
     }
 }
@@ -303,23 +308,32 @@ __device__ inline double quad_f(int fn, double x) {
     return fabs(x);
 }
 
-__global__ void k_quadrature(const double *__restrict__ alpha, const double *__restrict__ beta,
-                             const int *__restrict__ steps, int K, int m, int jlo, int jhi, int fn,
-                             double *__restrict__ F) {
+// One thread per (probe, step); the threads of a block keep their d, e, z in
+// LDS, entry i of thread t at [i][t] (consecutive threads, consecutive banks).
+constexpr int QD_THREADS = 32;
+__global__ void __launch_bounds__(QD_THREADS) k_quadrature(const double *__restrict__ alpha,
+                                                           const double *__restrict__ beta,
+                                                           const int *__restrict__ steps, int K, int m, int jlo,
+                                                           int jhi, int fn, double *__restrict__ F) {
+    __shared__ double sd[TNSLQ_MAX_STEPS * QD_THREADS], se[TNSLQ_MAX_STEPS * QD_THREADS],
+        sz[TNSLQ_MAX_STEPS * QD_THREADS];
     const int nj = jhi - jlo + 1;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= K * nj) return;
     const int k = t / nj, j = jlo + t % nj;
     int jj = j;
     if (steps && steps[k] < jj) jj = steps[k];
-    double d[TNSLQ_MAX_STEPS], e[TNSLQ_MAX_STEPS], z[TNSLQ_MAX_STEPS];
+    double *d = sd + threadIdx.x, *e = se + threadIdx.x, *z = sz + threadIdx.x;
     for (int i = 0; i < jj; ++i) {
-        d[i] = alpha[(int64_t)k * m + i];
-        e[i] = (i + 1 < jj) ? beta[(int64_t)k * (m + 1) + i + 1] : 0.0;
+        d[i * QD_THREADS] = alpha[(int64_t)k * m + i];
+        e[i * QD_THREADS] = (i + 1 < jj) ? beta[(int64_t)k * (m + 1) + i + 1] : 0.0;
     }
-    tridiag_ql_first_row(jj, d, e, z);
+    tridiag_ql_first_row<QD_THREADS>(jj, d, e, z);
     double f = 0.0;
-    for (int i = 0; i < jj; ++i) f += z[i] * z[i] * quad_f(fn, d[i]);
+    for (int i = 0; i < jj; ++i) {
+        const double zi = z[i * QD_THREADS];
+        f += zi * zi * quad_f(fn, d[i * QD_THREADS]);
+    }
     F[(int64_t)k * m + (j - 1)] = f;
 }
 
@@ -400,16 +414,21 @@ __device__ inline double fit_linear(const double *y, int n, double r, double &f,
 
 __device__ inline double fit_grid_r(int i) { return -FIT_R_MAX + (2.0 * FIT_R_MAX) * i / (FIT_GRID - 1); }
 
-// Per probe k (one thread each): F_inf and its uncertainty after step j >= FIT_MIN_POINTS + 1.
-__global__ void k_fit(const double *__restrict__ alpha, const double *__restrict__ beta, const double *__restrict__ F,
-                      int K, int m, int j, double *__restrict__ finf, double *__restrict__ fsig) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// Per probe k (one wave each): F_inf and its uncertainty after step
+// j >= FIT_MIN_POINTS + 1.  The lanes share the grid; the first grid point of
+// least RSS wins (as a scan in order would pick it), and lane 0 refines it.
+__global__ void __launch_bounds__(64) k_fit(const double *__restrict__ alpha, const double *__restrict__ beta,
+                                            const double *__restrict__ F, int K, int m, int j,
+                                            double *__restrict__ finf, double *__restrict__ fsig) {
+    const int k = blockIdx.x, lane = threadIdx.x;
     if (k >= K) return;
     const double *ak = alpha + (int64_t)k * m, *bk = beta + (int64_t)k * (m + 1), *Fk = F + (int64_t)k * m;
     const int s = first_break(ak, bk, j);
     if (s > 0) {
-        finf[k] = Fk[s - 1];
-        fsig[k] = 0.0;
+        if (lane == 0) {
+            finf[k] = Fk[s - 1];
+            fsig[k] = 0.0;
+        }
         return;
     }
     const int lo = j - FIT_WINDOW > 1 ? j - FIT_WINDOW : 1;   // F_1 is never fitted
@@ -417,14 +436,24 @@ __global__ void k_fit(const double *__restrict__ alpha, const double *__restrict
     double y[FIT_WINDOW];
     for (int t = 0; t < n; ++t) y[t] = Fk[lo + t];
     double f, a, best = INFINITY;
-    int ib = 0;
-    for (int i = 0; i < FIT_GRID; ++i) {
+    int ib = FIT_GRID;   // none yet
+    for (int i = lane; i < FIT_GRID; i += 64) {
         const double rss = fit_linear(y, n, fit_grid_r(i), f, a);
         if (rss < best) {
             best = rss;
             ib = i;
         }
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(ib, off, 64);
+        if (ob < best || (ob == best && oi < ib)) {
+            best = ob;
+            ib = oi;
+        }
+    }
+    if (lane != 0) return;
+    if (ib == FIT_GRID) ib = 0;
     double lo_r = fit_grid_r(ib > 0 ? ib - 1 : 0), hi_r = fit_grid_r(ib < FIT_GRID - 1 ? ib + 1 : FIT_GRID - 1);
     const double g = 0.61803398874989484820;   // (sqrt(5) - 1) / 2
     double x1 = hi_r - g * (hi_r - lo_r), x2 = lo_r + g * (hi_r - lo_r);
@@ -599,7 +628,7 @@ hipError_t launch_steps(const double *alpha, const double *beta, int K, int m, i
 hipError_t launch_quadrature(const double *alpha, const double *beta, const int *steps, int K, int m, int jlo,
                              int jhi, int fn, double *F, hipStream_t st) {
     const int64_t nt = (int64_t)K * (jhi - jlo + 1);
-    hipLaunchKernelGGL(k_quadrature, dim3(cdiv(nt, 64)), dim3(64), 0, st, alpha, beta, steps, K, m, jlo, jhi, fn, F);
+    hipLaunchKernelGGL(k_quadrature, dim3(cdiv(nt, QD_THREADS)), dim3(QD_THREADS), 0, st, alpha, beta, steps, K, m, jlo, jhi, fn, F);
     return hipGetLastError();
 }
 
@@ -612,7 +641,7 @@ hipError_t launch_stats(const double *beta, const double *F, int K, int m, int j
 hipError_t launch_fit(const double *alpha, const double *beta, const double *F, int K, int m, int j, double *finf,
                       double *fsig, double *G, double *out, hipStream_t st) {
     if (j < FIT_MIN_POINTS + 1 || j > m) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fit, dim3((K + 63) / 64), dim3(64), 0, st, alpha, beta, F, K, m, j, finf, fsig);
+    hipLaunchKernelGGL(k_fit, dim3(K), dim3(64), 0, st, alpha, beta, F, K, m, j, finf, fsig);
     hipLaunchKernelGGL(k_fit_stats, dim3(1), dim3(256), 0, st, beta, (const double *)finf, (const double *)fsig, K, m,
                        G, out);
     return hipGetLastError();
