@@ -242,7 +242,7 @@ def main():
                     help="first copy MIB MiB device-to-device (a known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this library runs on one GPU only; --gpus must be 1 "
                                    "(probe-sharded multi-GPU execution is designed but not built)"}))
         sys.exit(2)
 

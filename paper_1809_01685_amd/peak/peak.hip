@@ -10,7 +10,7 @@
 // kind 2: v_mfma_f64_16x16x4_f64      2048
 // kind 3: v_fma_f64 (vector ALU)      2 per lane, 128 per wave
 // kind 4: v_fma_f32 (vector ALU)      2 per lane, 128 per wave (packed forms
-//         are disabled for this build, so this is the unpacked rate)
+//         are disabled in this library's compile flags, so this is the unpacked rate)
 // kind 5: v_mfma_f32_32x32x16_bf16   32768 (four accumulator chains of 16)
 //
 // Built with the matrix instructions' VGPR form (-amdgpu-mfma-vgpr-form): in

@@ -1,7 +1,7 @@
 """The learned early stop: what the trained network gains over the method
 without it, and that its run-time entry point behaves as specified.
 
-Gain is measured against full SLQ (40 steps, 32 probes) as the judge, on
+Gain is measured against full SLQ (40 steps, 32 probes) as the reference, on
 instances the network never saw:
   * the held-out 10% of the method-generated training set (split by instance);
   * freshly drawn instances from the same family with new seeds.
