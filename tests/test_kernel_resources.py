@@ -63,3 +63,31 @@ def test_matrix_loops_keep_accumulators_in_vgprs(tmp_path, src, instrs):
     assert scratch and max(scratch) == 0
     # and the build applies that form to this file
     assert src in b.VGPR_FORM
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+def test_quadrature_and_fit_use_no_scratch(tmp_path):
+    # the quadrature keeps each thread's tridiagonal and first-row arrays in
+    # LDS (per-lane scratch made it 1.7x slower), and the fit's per-lane state
+    # stays in registers
+    from paper_1809_01685_amd import build as b
+    cmd = [_hipcc(), *[f for f in b.FLAGS if f != "-fPIC"], "--cuda-device-only", "-c",
+           "-Rpass-analysis=kernel-resource-usage", os.path.join(CSRC, "lanczos.hip"), "-o", str(tmp_path / "l.o")]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    usage, lds, name = {}, {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name:
+            usage[name] = int(m.group(1))
+        m = re.search(r"LDS Size \[bytes/block\]: (\d+)", line)
+        if m and name:
+            lds[name] = int(m.group(1))
+    quad = [k for k in usage if "k_quadrature" in k]
+    fit = [k for k in usage if re.search(r"5k_fitE", k)]
+    assert len(quad) == 1 and len(fit) == 1, usage
+    assert usage[quad[0]] == 0 and usage[fit[0]] == 0
+    assert 0 < lds[quad[0]] <= 160 * 1024
