@@ -19,14 +19,15 @@
 // plane: 32 BF16, 16 FP32 or 8 FP64 reduction terms) in LDS: thread t copies
 // bytes [16 t, 16 t + 16) of every plane, so each load instruction of the
 // block reads 8 KiB of contiguous memory and lands at the same offset in LDS.
-// Double buffered: while the waves multiply step i out of one buffer, step
-// i+1 (loaded from global memory one step earlier) is written to the other
-// and step i+2 is loaded into registers, one barrier per step.  For BF16 the
-// LDS writes and global loads of a step are placed between its matrix
-// instructions (scheduling groups: the 24 fragment reads, then two MFMAs per
-// LDS write and per global load, then the remaining MFMAs) and the barrier is
-// pinned after the last MFMA, so that the two waves of a SIMD do not idle
-// together on LDS.  Bricks store the four 16-byte units of a row XOR-swizzled
+// Double buffered, one barrier per step.  For BF16 the copy goes straight
+// from global memory into LDS (global_load_lds_dwordx4: 16 bytes per lane,
+// each wave 1 KiB of every plane tile): while the waves multiply step i out
+// of one buffer, step i+1 is copied into the other, issued after the step's
+// fragment reads and waited for before the barrier.  Against staging through
+// registers this frees the staging registers and the LDS write instructions
+// (about 2% faster on both contractions).  FP32 and FP64 stage through
+// registers: step i+1 (loaded one step earlier) is written to the other
+// buffer and step i+2 is loaded into registers.  Bricks store the four 16-byte units of a row XOR-swizzled
 // by ((row >> 1) ^ (row >> 2)) & 3, so the fragment reads of 8 or 16
 // consecutive rows hit distinct banks.  Rows past the edge of C come from the
 // bricks' row padding and their results are dropped; the reduction padding
@@ -238,6 +239,57 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
     zero();
 
     const int frow = lane & 15, fk = lane >> 4;   // fragment row within a 16-row tile, k-unit
+    if constexpr (PREC == TNSLQ_BF16X3) {
+        typedef __attribute__((address_space(3))) void lds_void;
+        typedef __attribute__((address_space(1))) const void gbl_void;
+        const int wofs = 1024 * wid;   // this wave's 1 KiB of every plane tile
+        auto dma = [&](int64_t st, int buf) __attribute__((always_inline)) {
+            const char *pa = ga + st * BRICKB, *pb = gb + st * BRICKB;
+            char *As = lds + buf * STAGEB + wofs, *Bs = As + NPL * TILEB;
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                __builtin_amdgcn_global_load_lds((gbl_void *)(pa + p * TILEB), (lds_void *)(As + p * TILEB), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((gbl_void *)(pb + p * TILEB), (lds_void *)(Bs + p * TILEB), 16, 0, 0);
+            }
+        };
+        dma(sbeg, 0);
+        __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copies have landed
+        __syncthreads();
+        int buf = 0;
+        for (int64_t st = sbeg; st < send; ++st, buf ^= 1) {
+            const char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
+            uint4 fa[TM][NPL], fb[TN][NPL];
+#pragma unroll
+            for (int x = 0; x < TM; ++x) {
+                const int oa = loff(wm * TM * 16 + x * 16 + frow, fk);
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) fa[x][p] = *(const uint4 *)(As + p * TILEB + oa);
+            }
+#pragma unroll
+            for (int x = 0; x < TN; ++x) {
+                const int ob = loff(wn * TN * 16 + x * 16 + frow, fk);
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
+            }
+            // every fragment read of the stage is issued before the copy into
+            // the other buffer (the wait counters do not tell buffers apart)
+            __builtin_amdgcn_sched_barrier(0);
+            dma(st + 1 < send ? st + 1 : send - 1, buf ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+            stage_mfma<PREC>(fa, fb, accr, acci);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(0x0f70);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                outr[a][b] = accr[a][b];
+                outi[a][b] = acci[a][b];
+            }
+        return;
+    }
     gload(sbeg);
     lstore(0);
     if (sbeg + 1 < send) gload(sbeg + 1);
@@ -258,30 +310,11 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
 #pragma unroll
             for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
         }
-        if constexpr (PREC == TNSLQ_BF16X3) {
-            // unconditional (clamped) so that the stage is one basic block;
-            // the extra store and load of the last step are never read
-            lstore(buf ^ 1);
-            gload(st + 2 < send ? st + 2 : send - 1);
-        } else if (st + 1 < send) {
+        if (st + 1 < send) {
             lstore(buf ^ 1);
             if (st + 2 < send) gload(st + 2);
         }
         stage_mfma<PREC>(fa, fb, accr, acci);
-        if constexpr (PREC == TNSLQ_BF16X3) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 24, 0);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
-        }
         if constexpr (TWO_LEVEL) {
             if (++nstage == FLUSH) {
                 flush();
