@@ -157,6 +157,15 @@ typedef struct {
  *                pass max_probes.  psi is regrouped once.  Only G_host (room
  *                for max_probes values, filled for the probes used) may be
  *                non-NULL among the optional outputs.
+ *   chunk_probes 0: the lazy form on the matrix cores contracts as many
+ *                probes per launch as fit a 16 GiB intermediary (Sec. V
+ *                Eq. 4, intermediary (i): d_B x d_E d_B values per probe).
+ *                > 0: at most this many probes per launch.  Either way the
+ *                count is rounded up so that every chunk starts on a block of
+ *                128 rows (k, b') (a multiple of 128 / d_B when d_B < 128) and
+ *                capped at n_probes; the last chunk takes the remainder.  The
+ *                estimate does not depend on it; the workspace shrinks with
+ *                it.  Ignored by the streaming, explicit and MPS forms.
  */
 typedef struct {
     int n_probes;
@@ -169,6 +178,7 @@ typedef struct {
     int stop_rule;
     int operator_form;      /* TNSLQ_OPERATOR_AUTO / _LAZY / _EXPLICIT        */
     int max_probes;         /* > n_probes: Algorithm 1's loop over probes     */
+    int chunk_probes;       /* 0, or the most probes per contraction launch   */
 } tnslq_options;
 
 typedef struct {
@@ -209,7 +219,7 @@ typedef struct {
 const char *tnslq_status_str(int status);
 /* Description of the last failure on the calling thread ("" if none). */
 const char *tnslq_last_error(void);
-/* ABI version, currently 3. */
+/* ABI version, currently 4. */
 int tnslq_version(void);
 
 /* -------------------------------------------------- logarithmic negativity */
@@ -349,17 +359,20 @@ int tnslq_logneg_mps(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b, con
 
 /* Workspace bytes for tnslq_ptmatvec with n_vectors vectors. */
 int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n_vectors,
-                                   int precision, size_t *bytes);
+                                   int precision, int chunk_vectors, size_t *bytes);
 
 /* Y = rho_AB^{T_B} X for a block of n_vectors vectors (Sec. V Eq. 4:
  * (rho^{T_B} phi)_{ab} = sum_{a',b',c} psi_{ab'c} psi*_{a'bc} phi_{a'b'}),
  * contracted lazily through intermediary (i) in the given precision.
  *   X_dev  device, n_vectors x (d_A d_B) complex128, row n = vector n.
  *   Y_dev  device, same shape, overwritten (must not alias X_dev).
+ *   chunk_vectors  0 or the most vectors per contraction launch on the
+ *          matrix cores, rounded as tnslq_options.chunk_probes (the result
+ *          does not depend on it).
  * Does not synchronise. */
 int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors,
-                   const void *X_dev, void *Y_dev, int precision, void *ws_dev, size_t ws_bytes,
-                   void *stream);
+                   const void *X_dev, void *Y_dev, int precision, int chunk_vectors, void *ws_dev,
+                   size_t ws_bytes, void *stream);
 
 /* ------------------------------------------- explicit partial transpose */
 

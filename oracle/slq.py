@@ -3,33 +3,33 @@
 
 Oracle, test infrastructure only.
 
-Steps, in Algorithm 1's order and notation, per probe n:
-  phi <- random probe;  beta_1 = ||phi||;  phi_0 = 0;  phi_1 = phi / beta_1
-  for k = 1..K_max:
-      v       = X phi_k - beta_k phi_{k-1}
-      alpha_k = Re <phi_k | v>          (the operator is Hermitian)
-      v       = v - alpha_k phi_k
-      [optional: full reorthogonalisation against phi_1..phi_k, twice]
-      beta_{k+1} = ||v||
-      phi_{k+1}  = v / beta_{k+1}
-      T_k = tridiag(alpha_1..alpha_k; beta_2..beta_k)
-      (theta_j, w_j) = eig(T_k);  tau_j = <e_1|w_j>
-      F_k = sum_j tau_j^2 f(theta_j)
-  G_n = ||phi||^2 F_m
-then mean, standard error sqrt(Var/N), and E = log2(mean G).
+What is computed, per probe vector phi: the Lanczos process on the Hermitian
+operator started from phi / ||phi|| builds, one matvec per step, the
+tridiagonal matrix T_k of the operator restricted to the Krylov space (its
+diagonal alpha from the Rayleigh quotients of the basis vectors, its
+off-diagonal beta from the norms of the orthogonalised remainders).  The
+Gauss quadrature of f on the probe's spectral measure is then the sum over
+the eigenpairs of T_k of f(eigenvalue) weighted by the squared first
+component of the eigenvector.  Hutchinson's estimator averages
+||phi||^2 times that quadrature over independent probes; E = log2 of the
+mean for f = |x| (Eq. 1-2), with the error on the mean of Sec. VIII.
 
 Readings where the paper is silent (each also listed in the design notes):
-  * Algorithm 1's F_k estimates <phi_1|f|phi_1> for the *normalised* start
-    vector; Hutchinson's sum needs <phi|f|phi>, hence the factor
-    beta_1^2 = ||phi||^2 in G_n.
-  * lanczos_estimate is F_m after a fixed number m of steps (no early exit).
-  * Breakdown: a probe stops when beta_{k+1} <= 1e-12 * s_k with
+  * the quadrature estimates the bilinear form for the *normalised* start
+    vector; Hutchinson's sum needs <phi|f|phi>, hence the factor ||phi||^2
+    (= beta_1^2) in G_n;
+  * the diagonal coefficient is the real part of <q_k | X q_k> (the operator
+    is Hermitian);
+  * lanczos_estimate is the quadrature after a fixed number m of steps (no
+    early exit);
+  * breakdown: a probe stops when beta_{k+1} <= 1e-12 * s_k with
     s_k = max_{i<=k} |alpha_i| + max_{2<=i<=k} beta_i; the quadrature of
-    T_k is then exact and later F values repeat F_k.
-  * Reorthogonalisation (when asked for) is classical Gram-Schmidt applied
-    twice against every earlier Lanczos vector of the same probe.
-  * Error on the mean uses the sample variance with N-1 in the denominator;
-    the error of E follows by the delta method, dE = SE / (mean * ln 2).
+    T_k is then exact and later quadrature values repeat it;
+  * reorthogonalisation (when asked for) is classical Gram-Schmidt applied
+    twice against every earlier Lanczos vector of the same probe;
+  * the error on the mean uses the sample variance with N-1 in the
+    denominator; the error of E follows by the delta method,
+    dE = SE / (mean * ln 2).
 """
 from __future__ import annotations
 
@@ -157,13 +157,3 @@ def slq_logneg_dims(psi: np.ndarray, dims, a, b, n_probes: int, n_steps: int, se
     R = exact.rho_pt(P)
     X = probes.rademacher_probes(seed, n_probes, P.shape[0] * P.shape[1], probe_offset)
     return slq(lambda v: R @ v, X, n_steps, reorth)
-
-
-def lanczos_block_features(alpha: np.ndarray, beta: np.ndarray, d_a: int, d_b: int, d_e: int,
-                           n_early: int = 8) -> np.ndarray:
-    """The surrogate's 19 inputs: probe means of N*alpha_1..8 and
-    N*beta_2..9 (N = d_A d_B), then log2 d_A, log2 d_B, log2 d_E."""
-    n = float(d_a * d_b)
-    fa = n * np.mean(alpha[:, :n_early], axis=0)
-    fb = n * np.mean(beta[:, 1:n_early + 1], axis=0)
-    return np.concatenate([fa, fb, [np.log2(d_a), np.log2(d_b), np.log2(d_e)]])

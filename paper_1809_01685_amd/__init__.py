@@ -55,7 +55,7 @@ class Options(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int), ("n_steps", ctypes.c_int), ("reorth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("seed", ctypes.c_uint64), ("probe_offset", ctypes.c_uint64),
                 ("stop_tol", ctypes.c_double), ("stop_rule", ctypes.c_int), ("operator_form", ctypes.c_int),
-                ("max_probes", ctypes.c_int)]
+                ("max_probes", ctypes.c_int), ("chunk_probes", ctypes.c_int)]
 
 
 class SpectralResult(ctypes.Structure):
@@ -92,8 +92,8 @@ _SIGS = {
     "tnslq_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), ctypes.POINTER(Options), ctypes.POINTER(_SZ)]),
     "tnslq_logneg": (_I, [_VP, _I, ctypes.POINTER(Partition), ctypes.POINTER(Options), _VP, _SZ, _VP,
                           ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
-    "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, ctypes.POINTER(_SZ)]),
-    "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _VP, _SZ, _VP]),
+    "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, _I, ctypes.POINTER(_SZ)]),
+    "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _I, _VP, _SZ, _VP]),
     "tnslq_workspace_bytes_dims": (_I, [_I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options),
                                         ctypes.POINTER(_SZ)]),
     "tnslq_logneg_dims": (_I, [_VP, _I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options), _VP, _SZ, _VP,
@@ -230,9 +230,10 @@ def _operator(operator) -> int:
 
 def make_options(n_probes: int, n_steps: int, reorth: bool = False, precision="fp32", seed: int = 0,
                  probe_offset: int = 0, stop_tol: float = 0.0, stop_rule="diff", operator="auto",
-                 max_probes: int = 0) -> Options:
+                 max_probes: int = 0, chunk_probes: int = 0) -> Options:
     return Options(int(n_probes), int(n_steps), int(bool(reorth)), _prec(precision), int(seed) & (2**64 - 1),
-                   int(probe_offset), float(stop_tol), _rule(stop_rule), _operator(operator), int(max_probes))
+                   int(probe_offset), float(stop_tol), _rule(stop_rule), _operator(operator), int(max_probes),
+                   int(chunk_probes))
 
 
 def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int:
@@ -246,7 +247,8 @@ def tnslq_workspace_bytes(dtype: int, n_qubits: int, a, b, opts: Options) -> int
 # ------------------------------------------------------------- logneg
 def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: bool = False, precision="fp32",
                  seed: int = 0, probe_offset: int = 0, stop_tol: float = 0.0, workspace=None, stream=None,
-                 want_arrays: bool = True, stop_rule="diff", operator="auto", max_probes: int = 0) -> Dict[str, object]:
+                 want_arrays: bool = True, stop_rule="diff", operator="auto", max_probes: int = 0,
+                 chunk_probes: int = 0) -> Dict[str, object]:
     """SLQ estimate of log2 Tr|rho_AB^{T_B}| of the device state ``psi``.
 
     With ``max_probes`` > ``n_probes`` (fit rule, ``stop_tol`` > 0) blocks of
@@ -258,7 +260,7 @@ def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: 
         raise ValueError("psi has the wrong length")
     dt = _dtype_code(psi)
     opts = make_options(n_probes, n_steps, reorth, precision, seed, probe_offset, stop_tol, stop_rule, operator,
-                        max_probes)
+                        max_probes, chunk_probes)
     if max_probes > n_probes:
         p = _partition(n_qubits, a, b)
         ws = _workspace(tnslq_workspace_bytes(dt, n_qubits, a, b, opts), psi.device, workspace)
@@ -294,15 +296,17 @@ def tnslq_logneg(psi, n_qubits: int, a, b, n_probes: int, n_steps: int, reorth: 
 
 
 # ------------------------------------------------------------- matvec
-def tnslq_ptmatvec_workspace_bytes(dtype: int, n_qubits: int, a, b, n_vectors: int, precision="fp32") -> int:
+def tnslq_ptmatvec_workspace_bytes(dtype: int, n_qubits: int, a, b, n_vectors: int, precision="fp32",
+                                   chunk_vectors: int = 0) -> int:
     n = ctypes.c_size_t(0)
     p = _partition(n_qubits, a, b)
     _check(lib().tnslq_ptmatvec_workspace_bytes(int(dtype), ctypes.byref(p), int(n_vectors), _prec(precision),
-                                                ctypes.byref(n)), "tnslq_ptmatvec_workspace_bytes")
+                                                int(chunk_vectors), ctypes.byref(n)), "tnslq_ptmatvec_workspace_bytes")
     return n.value
 
 
-def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None, stream=None, Y=None):
+def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None, stream=None, Y=None,
+                   chunk_vectors: int = 0):
     """Y = rho_AB^{T_B} X for device complex128 X of shape (K, d_A d_B)."""
     import torch
     _check_device_tensor(psi, "psi")
@@ -311,13 +315,13 @@ def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None
         raise TypeError("X must be a 2-D complex128 device tensor")
     dt = _dtype_code(psi)
     K = X.shape[0]
-    need = tnslq_ptmatvec_workspace_bytes(dt, n_qubits, a, b, K, precision)
+    need = tnslq_ptmatvec_workspace_bytes(dt, n_qubits, a, b, K, precision, chunk_vectors)
     ws = _workspace(need, psi.device, workspace)
     if Y is None:
         Y = torch.empty_like(X)
     p = _partition(n_qubits, a, b)
-    _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision), _ptr(ws),
-                                ws.numel(), _stream(stream)), "tnslq_ptmatvec")
+    _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision),
+                                int(chunk_vectors), _ptr(ws), ws.numel(), _stream(stream)), "tnslq_ptmatvec")
     return Y
 
 

@@ -114,7 +114,7 @@ size_t explicit_bytes(int prec, int64_t n) {
 // cost D * min(d_A, d_B) per probe is the smaller one), chunking and the
 // workspace carve-up.  `lanczos` = 0 plans a bare lazy matvec.
 int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int prec, int lanczos, int opform,
-              Plan &pl) {
+              Plan &pl, int chunk = 0) {
     int rc;
     if ((rc = check_dtype(dtype)) || (rc = check_partition(p)) || (rc = check_prec(prec))) return rc;
     if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_EXPLICIT)
@@ -123,6 +123,7 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
         return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
     pl = Plan();
+    pl.kc_cap = std::max(0, chunk);
     pl.L = p->n_qubits;
     pl.dtype = dtype;
     pl.prec = prec;
@@ -143,7 +144,7 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
         } else if (lanczos && opform == TNSLQ_OPERATOR_AUTO && fits) {
             // cost of the lazy plan (roles as above, chunking as below)
             Plan lz;
-            if ((rc = make_plan(dtype, p, K, m, reorth, prec, lanczos, TNSLQ_OPERATOR_LAZY, lz))) return rc;
+            if ((rc = make_plan(dtype, p, K, m, reorth, prec, lanczos, TNSLQ_OPERATOR_LAZY, lz, chunk))) return rc;
             if (!lz.stream && explicit_macs(n0, dE0, K, lz.m) < lz.m * lazy_macs(lz)) pl.expl = 1;
         }
         if (pl.expl) pl.swapped = 0;
@@ -177,6 +178,7 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     // intermediary per probe: d_B rows (b) by d_E d_B reduction terms (c, b')
     const size_t ups_bytes_per = brick_bytes(prec, pl.dB, pl.dE * pl.dB);
     pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
+    if (pl.kc_cap > 0) pl.kc = std::min(pl.kc, pl.kc_cap);
     // every chunk must start on a block of 128 rows (k, b') of Xt (lazy form:
     // d_B is then a power of two)
     if (!pl.expl && pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
@@ -1149,6 +1151,7 @@ int check_options(const tnslq_options *opt) {
     if (opt->operator_form < TNSLQ_OPERATOR_AUTO || opt->operator_form > TNSLQ_OPERATOR_EXPLICIT)
         return fail(TNSLQ_E_ARG, "operator_form %d unknown", opt->operator_form);
     if (opt->max_probes < 0) return fail(TNSLQ_E_ARG, "max_probes must be >= 0");
+    if (opt->chunk_probes < 0) return fail(TNSLQ_E_ARG, "chunk_probes must be >= 0");
     if (opt->max_probes > opt->n_probes && (opt->stop_rule != TNSLQ_STOP_FIT || !(opt->stop_tol > 0.0)))
         return fail(TNSLQ_E_ARG, "the loop over probes (max_probes > n_probes) needs the fit rule and stop_tol > 0");
     if (opt->stop_rule == TNSLQ_STOP_FIT && opt->n_steps < TNSLQ_FIT_MIN_POINTS + 1)
@@ -1179,7 +1182,7 @@ int run_begin(Run &r, int dtype, const tnslq_partition *part, const tnslq_option
               size_t ws_bytes, void *stream) {
     int rc;
     if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
-                         opt->operator_form, r.c.pl)))
+                         opt->operator_form, r.c.pl, opt->chunk_probes)))
         return rc;
     return run_start(r, opt, psi, ws, ws_bytes, stream);
 }
@@ -1582,7 +1585,7 @@ const char *tnslq_status_str(int s) {
 
 const char *tnslq_last_error(void) { return g_err.c_str(); }
 
-int tnslq_version(void) { return 3; }
+int tnslq_version(void) { return 4; }
 
 int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_options *opt, size_t *bytes) {
     int rc;
@@ -1595,7 +1598,7 @@ int tnslq_workspace_bytes(int dtype, const tnslq_partition *part, const tnslq_op
     }
     Plan pl;
     if ((rc = make_plan(dtype, part, opt->n_probes, opt->n_steps, opt->reorth, opt->precision, 1,
-                         opt->operator_form, pl)))
+                         opt->operator_form, pl, opt->chunk_probes)))
         return rc;
     *bytes = pl.total;
     return TNSLQ_OK;
@@ -1759,25 +1762,28 @@ int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
 }
 
 int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n_vectors, int precision,
-                                   size_t *bytes) {
+                                   int chunk_vectors, size_t *bytes) {
     int rc;
     if (!bytes) return fail(TNSLQ_E_ARG, "bytes is NULL");
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
     if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
     Plan pl;
-    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, pl))) return rc;
+    if (chunk_vectors < 0) return fail(TNSLQ_E_ARG, "chunk_vectors must be >= 0");
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, pl, chunk_vectors))) return rc;
     *bytes = pl.total;
     return TNSLQ_OK;
 }
 
 int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors, const void *X_dev,
-                   void *Y_dev, int precision, void *ws_dev, size_t ws_bytes, void *stream) {
+                   void *Y_dev, int precision, int chunk_vectors, void *ws_dev, size_t ws_bytes, void *stream) {
     int rc;
     g_err.clear();
     if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
     if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
     Ctx c;
-    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, c.pl))) return rc;
+    if (chunk_vectors < 0) return fail(TNSLQ_E_ARG, "chunk_vectors must be >= 0");
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, c.pl, chunk_vectors)))
+        return rc;
     if (!psi_dev || !X_dev || !Y_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
     if (X_dev == Y_dev) return fail(TNSLQ_E_ARG, "X and Y alias");
     if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");

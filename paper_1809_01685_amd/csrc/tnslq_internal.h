@@ -45,9 +45,10 @@ struct Plan {
     int prec = TNSLQ_FP32;
     int K = 1, m = 1, reorth = 0;
     int kc = 1;                      // probes per contraction chunk
+    int kc_cap = 0;                  // caller's cap on kc (0: from the budget alone)
     int S = 1;                       // split-K factor of the second contraction
     int S1 = 1;                      // split-K factor of the first contraction
-    int stream = 0;                  // contractions as two streaming passes over psi (K d_B <= 4)
+    int stream = 0;                  // contractions as two streaming passes over psi (K d_B <= 8)
     int S1s = 1, S2s = 1;            // row splits of the two streaming passes
     int expl = 0;                    // rho^{T_B} formed explicitly (intermediary (iii))
     int64_t nst_rho = 1;             // bricks along the reduction index of the explicit matvec

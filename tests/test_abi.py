@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert T.tnslq_version() == 3
+    assert T.tnslq_version() == 4
     assert T.tnslq_status_str(0) == "ok"
     assert T.tnslq_status_str(-2) == "invalid partition"
     assert T.tnslq_status_str(-4) == "workspace too small"
@@ -81,6 +81,26 @@ def test_operator_form_choice_and_limits(L):
                                    ctypes.byref(n)) == -1
 
 
+def test_chunk_cap_sets_the_intermediary_size(L):
+    # the intermediary of the lazy form holds d_B x d_E d_B values per probe
+    # of a chunk: the workspace shrinks with the cap, by whole chunks
+    a30, b30 = list(range(4, 17)), list(range(17, 30))
+    ws = {c: T.tnslq_workspace_bytes(T.TNSLQ_C64, 30, a30, b30,
+                                     T.make_options(8, 10, precision="bf16x3", chunk_probes=c)) for c in (0, 1, 2, 8)}
+    ups = 8192 * 16 * 8192 * 8          # one probe's intermediary, split BF16 (8 B per complex value)
+    ypart = 8192 * 8192 * 8             # and its FP32 partial result
+    assert ws[0] == ws[2]               # the 16 GiB budget holds two probes
+    assert ws[2] - ws[1] == ups + ypart and ws[8] == ws[0]
+    # d_B = 64 < 128: a cap of 3 probes is rounded up to 4 (chunks start on
+    # 128-row blocks), so caps 3 and 4 plan alike and 1 becomes 2
+    a16, b16 = list(range(0, 8)), list(range(10, 16))
+    f = lambda c: T.tnslq_ptmatvec_workspace_bytes(T.TNSLQ_C64, 16, a16, b16, 10, "fp32", c)  # noqa: E731
+    assert f(3) == f(4) < f(5) <= f(0) and f(1) == f(2) < f(3)
+    with pytest.raises(T.TnslqError) as ei:
+        f(-1)
+    assert ei.value.status == -1
+
+
 def test_rho_pt_validates_without_device(L):
     assert T.tnslq_rho_pt_workspace_bytes(T.TNSLQ_C128, 10, [0, 1, 2], [5, 6, 7]) >= 64 * 64 * 16
     with pytest.raises(T.TnslqError) as ei:
@@ -112,7 +132,8 @@ def test_bad_options_rejected(L):
               T.make_options(4, 4, stop_rule=7), T.make_options(4, 5, stop_rule="fit"),
               T.make_options(4, 8, stop_tol=0.01, max_probes=-1),
               T.make_options(4, 8, stop_tol=0.01, stop_rule="diff", max_probes=16),
-              T.make_options(4, 8, stop_tol=0.0, stop_rule="fit", max_probes=16)):
+              T.make_options(4, 8, stop_tol=0.0, stop_rule="fit", max_probes=16),
+              T.make_options(4, 4, chunk_probes=-1)):
         rc = L.tnslq_workspace_bytes(0, ctypes.byref(p), ctypes.byref(o), ctypes.byref(n))
         assert rc == -1
     assert L.tnslq_workspace_bytes(7, ctypes.byref(p), ctypes.byref(T.make_options(4, 4)), ctypes.byref(n)) == -3

@@ -1,0 +1,145 @@
+"""The lazy operator in probe chunks, as the 26-qubit rho_AB workload runs it
+(Sec. V, Eq. 4, intermediary (i): the intermediary of a chunk of probes is
+formed and consumed before the next chunk), against the oracle.
+
+* Small states (14-15 qubits) with the chunk capped below the block: a cap
+  that divides the block, one that leaves a short last chunk, one rounded up
+  to whole 128-row blocks (d_B = 64), and the role exchange, in FP64, FP32
+  and split BF16; every output entry against the explicit operator (or the
+  lazy oracle where d_A d_B = 16384), max-abs relative to the largest.
+* The Lanczos recurrence over chunks: alpha and beta of a chunked FP64 run
+  against the oracle's on the same probes.
+* The 26-qubit rho_AB itself (30-qubit Haar state, E = 0-3, A = 4-16,
+  B = 17-29), 8 vectors in 4 chunks of 2 (the benchmark's plan): four whole
+  output columns of every vector, against the oracle's column formula.
+* The 24-qubit brickwork workload (depth 12, A = 4-11, B = 13-20): every
+  output entry of a split-BF16 and an FP32 block matvec against the lazy
+  oracle, and the depth-1 estimate, exactly 0 for this partition, within its
+  stated error.
+"""
+import numpy as np
+import pytest
+
+import tnslq_inputs as ti
+from oracle import exact, probes, slq
+
+pytestmark = pytest.mark.gpu
+T = pytest.importorskip("paper_1809_01685_amd")
+
+# element-wise bars, relative to the largest output entry
+ELEM_TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
+
+
+def _max_rel(got, want):
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("L,a,b,K,chunk", [
+    (14, list(range(0, 6)), list(range(8, 14)), 10, 4),   # d_B = 64: chunks 4, 4, 2
+    (14, list(range(0, 6)), list(range(8, 14)), 10, 3),   # 3 rounds up to 4
+    (14, list(range(0, 6)), list(range(8, 14)), 7, 1),    # 1 rounds up to 2: 2, 2, 2, 1
+    (14, list(range(8, 14)), [0, 1, 2, 3, 4, 5, 6], 6, 2),   # |B| > |A|: roles exchanged, d_B = 64
+    (15, list(range(0, 7)), list(range(8, 15)), 5, 2),    # d_B = 128: chunks 2, 2, 1 without rounding
+])
+def test_chunked_matvec_matches_oracle_entrywise(dev, prec, L, a, b, K, chunk):
+    import torch
+    dtype = np.complex128 if prec == "fp64" else np.complex64
+    psi = ti.haar_state(L, 3).astype(dtype)
+    n = 1 << (len(a) + len(b))
+    X = ti.random_vectors(K, n, seed=L + K)
+    psi_t = torch.from_numpy(psi).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    assert (T.tnslq_ptmatvec_workspace_bytes(0 if prec != "fp64" else 1, L, a, b, K, prec, chunk)
+            < T.tnslq_ptmatvec_workspace_bytes(0 if prec != "fp64" else 1, L, a, b, K, prec, 0))
+    Y = T.tnslq_ptmatvec(psi_t, L, a, b, Xd, precision=prec, chunk_vectors=chunk).cpu().numpy()
+    P = exact.regroup(psi.astype(np.complex128), L, a, b)
+    ref = exact.pt_matvec_explicit(P, X) if n <= 4096 else exact.pt_matvec_lazy(P, X)
+    err = _max_rel(Y, ref)
+    print(f"L={L} K={K} chunk={chunk} {prec}: max-abs error / max |Y| = {err:.2e}")
+    assert err <= ELEM_TOL[prec]
+    # the same vectors without a cap (one launch for all) agree to the same bar
+    Y1 = T.tnslq_ptmatvec(psi_t, L, a, b, Xd, precision=prec).cpu().numpy()
+    assert _max_rel(Y1, ref) <= ELEM_TOL[prec]
+
+
+@pytest.mark.parametrize("chunk", [2, 3])
+def test_chunked_lanczos_matches_oracle(dev, chunk):
+    # 10 probes in chunks of 4, 4, 2 (3 rounds up to 4 at d_B = 64): the
+    # recurrence reads each chunk's result at its probe offset
+    import torch
+    L, a, b, K, m = 14, list(range(0, 6)), list(range(8, 14)), 10, 12
+    psi = ti.haar_state(L, 8)
+    g = T.tnslq_logneg(torch.from_numpy(psi).to(dev), L, a, b, K, m, precision="fp64", seed=4, operator="lazy",
+                       chunk_probes=chunk)
+    assert not g["explicit_operator"] and not g["streamed"]
+    assert g["n_contract_launches"] == m * (3 if chunk == 3 else 5)
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    o = slq.slq(lambda v: R @ v, probes.rademacher_probes(4, K, 1 << 12), m)
+    scale = np.max(np.abs(o["alpha"]))
+    assert np.max(np.abs(g["alpha"] - o["alpha"])) <= 1e-10 * scale
+    assert np.max(np.abs(g["beta"] - o["beta"])) <= 1e-10 * np.max(o["beta"])
+    assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-10 * max(1.0, abs(o["logneg"])))
+
+
+L30, A30, B30 = 30, list(range(4, 17)), list(range(17, 30))
+
+
+def test_haar30_whole_columns_in_four_chunks(dev):
+    # the benchmark's plan: 8 vectors, 2 per launch (the 16 GiB intermediary
+    # budget), so 4 launches of each contraction; columns b spread over the
+    # 128 x 128 output tiles, every row a and every vector
+    import torch
+    psi_t = ti.haar_state_torch(L30, 0, dev, torch.complex64)
+    K, d = 8, 1 << 13
+    Xd = ti.random_vectors_torch(K, d * d, 21, dev)
+    Y = T.tnslq_ptmatvec(psi_t, L30, A30, B30, Xd, precision="bf16x3")
+    cols = [5, 2900, 6143, 8191]
+    got = Y.view(K, d, d)[:, :, cols].cpu().numpy()        # (K, a, col)
+    del Y
+    X = Xd.cpu().numpy().reshape(K, d, d)
+    del Xd
+    psi = psi_t.cpu().numpy()
+    del psi_t
+    torch.cuda.empty_cache()
+    # oracle: for slab c (d_A x d_B, E the leading qubits) and column b,
+    # u[b'] = sum_a' conj M_c[a', b] x[a', b'] and y[a, b] = sum_b' M_c[a, b'] u[b']
+    want = np.zeros((K, d, len(cols)), dtype=np.complex128)
+    for c in range(16):
+        m_c = psi[c * d * d:(c + 1) * d * d].reshape(d, d).astype(np.complex128)
+        mcols = np.conj(m_c[:, cols]).T                     # (col, a')
+        for k in range(K):
+            u = mcols @ X[k]                                # (col, b')
+            want[k] += m_c @ u.T                            # (a, col)
+    rms = np.sqrt(np.mean(np.abs(want) ** 2))
+    err = np.abs(got - want)
+    rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    print(f"26-qubit rho_AB, 4 columns x 8 vectors: norm-wise {rel:.2e}, max {err.max() / rms:.2e} of the RMS")
+    assert rel <= 3e-5                                       # the split-BF16 norm-wise bar
+    assert err.max() <= 1.5e-4 * rms                         # 5x that per entry, relative to the RMS output
+
+
+LB, AB_, BB_ = 24, list(range(4, 12)), list(range(13, 21))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_brick24_matvec_matches_lazy_oracle(dev, prec):
+    import torch
+    psi_t = ti.brickwork_state_torch(LB, 12, 0, dev, torch.complex64)
+    X = ti.random_vectors(4, 1 << 16, seed=13)
+    Y = T.tnslq_ptmatvec(psi_t, LB, AB_, BB_, torch.from_numpy(X).to(dev), precision=prec).cpu().numpy()
+    psi = psi_t.cpu().numpy()
+    P = exact.regroup(psi.astype(np.complex128), LB, AB_, BB_)
+    ref = exact.pt_matvec_lazy(P, X)
+    err = _max_rel(Y, ref)
+    print(f"24-qubit brickwork {prec}: max-abs error / max |Y| = {err:.2e}")
+    assert err <= ELEM_TOL[prec]
+
+
+def test_brick24_depth_one_is_zero_within_its_error(dev):
+    # at depth 1 no gate joins A and B, so rho_AB is a product and E = 0
+    import torch
+    psi = ti.brickwork_state_torch(LB, 1, 0, dev, torch.complex64)
+    g = T.tnslq_logneg(psi, LB, AB_, BB_, 32, 40, reorth=True, precision="bf16x3", seed=0)
+    assert abs(g["logneg"]) <= 3.0 * g["logneg_se"]

@@ -166,6 +166,33 @@ def test_stop_tolerance_stops_early_and_agrees(dev):
     assert abs(early["logneg"] - full["logneg"]) <= 0.01 * max(abs(full["logneg"]), 1.0)
 
 
+@pytest.mark.parametrize("tol", [0.02, 0.01, 0.003])
+def test_difference_rule_matches_oracle(dev, tol):
+    # the step-difference stop (stop_rule TNSLQ_STOP_DIFF) in FP64 against
+    # the oracle's rule replayed on its own trajectories for the same probes:
+    # the same stop step, estimate and Lanczos proxy
+    import torch
+    from oracle import step_difference
+    L, a, b, K, m = 14, list(range(5)), list(range(5, 10)), 16, 40
+    psi = ti.haar_state(L, 2)
+    g = T.tnslq_logneg(torch.from_numpy(psi).to(dev), L, a, b, K, m, precision="fp64", seed=1, stop_tol=tol,
+                       stop_rule="diff", operator="lazy")
+    R = exact.rho_pt(exact.regroup(psi, L, a, b))
+    o = slq.slq(lambda v: R @ v, probes.rademacher_probes(1, K, 1 << 10), m)
+    want = step_difference.run(o["beta"], o["F"], tol)
+    # no step's error sits within rounding of its threshold, so the stop step
+    # is decided the same way on both sides
+    for j in range(6, want["steps"] + 1):
+        c = step_difference.combined_error(o["beta"], o["F"], j)
+        thr = tol * max(abs(c["logneg"]), 1.0)
+        assert abs(c["err"] - thr) > 1e-9 * thr
+    assert 6 <= want["steps"] < m
+    assert g["steps_done"] == want["steps"]
+    assert g["logneg"] == pytest.approx(want["logneg"], abs=1e-10 * max(1.0, abs(want["logneg"])))
+    assert g["lanczos_err"] == pytest.approx(want["lanczos_err"], abs=1e-10)
+    assert g["logneg_se"] == pytest.approx(want["logneg_se"], rel=1e-9)
+
+
 def test_probe_offset_merges_as_independent_samples(dev):
     import torch
     L, a, b = 10, [0, 1, 2], [3, 4, 5]

@@ -1,5 +1,6 @@
 """The learned early stop: what the trained network gains over the method
-without it, and that its run-time entry point behaves as specified.
+without it, and that its run-time entry point (features, network, head and
+accept rule after eight Lanczos steps) matches the oracle's decision.
 
 Gain is measured against full SLQ (40 steps, 32 probes) as the reference, on
 instances the network never saw:
@@ -62,23 +63,42 @@ def test_network_gain_on_fresh_instances(dev, model):
     assert acc.sum() >= 10 and np.mean(err_m[acc] <= tol[acc]) >= 0.9
 
 
-def test_surrogate_entry_point_matches_host_prediction(dev, model):
+def _decision_margin_ok(d, tol):
+    # the accept decision compares sigma with tol max(|mu|, 1); both sides
+    # compute it in double from FP32 network outputs, so only a margin below
+    # the network's rounding leaves the flag open
+    thr = tol * max(abs(d["mu"]), 1.0)
+    return abs(d["sigma"] - thr) > 1e-4 * thr
+
+
+@pytest.mark.parametrize("tol", [0.01, 1e9, 1e-12])
+def test_surrogate_entry_point_matches_oracle_decision(dev, model, tol):
+    # the run-time path (8 FP64 Lanczos steps, the feature kernel, the
+    # network, mu = E_8 + y_scale u0, sigma = y_scale exp(u1 / 2) and the
+    # accept rule) against the oracle's decision on the oracle's own
+    # coefficients for the same probes
     import torch
     import tnslq_inputs as ti
-    L, a, b = 18, list(range(2, 9)), list(range(9, 16))
-    psi = ti.haar_state_torch(L, 5, dev, torch.complex64)
-    full = T.tnslq_logneg(psi, L, a, b, 32, 40, precision="bf16x3", seed=3)
-    x = S.features_from_coefficients(full["alpha"], full["beta"], 1 << 7, 1 << 7, 1 << 4)
-    e8 = S.estimate_at(full["beta"], full["F"], 8)
-    mu, sigma = S.predict(model, x[None], np.array([e8]), dev)
-    r = S.surrogate_logneg(model, psi, L, a, b, 32, 40, tol=0.01, precision="bf16x3", seed=3)
-    assert r["e_early"] == pytest.approx(e8, abs=1e-12)
-    assert r["mu"] == pytest.approx(mu[0], abs=1e-5 * max(1.0, abs(mu[0])))
-    assert r["sigma"] == pytest.approx(sigma[0], rel=1e-4)
+    from oracle import exact, probes, slq, surrogate as osur
+    L, a, b, K, m = 12, list(range(2, 7)), list(range(7, 12)), 16, 24
+    psi = ti.haar_state(L, 5)
+    r = S.surrogate_logneg(model, torch.from_numpy(psi).to(dev), L, a, b, K, m, tol=tol, precision="fp64", seed=3,
+                           operator="lazy")
+    R = exact.rho_pt(exact.regroup(psi, L, a, b))
+    o = slq.slq(lambda v: R @ v, probes.rademacher_probes(3, K, 1 << 10), m)
+    d = osur.decision(model.params, model.norm, model.y_scale, o["alpha"], o["beta"], o["F"], 1 << 5, 1 << 5,
+                      1 << 2, tol)
+    assert r["e_early"] == pytest.approx(d["e_early"], abs=1e-10)
+    assert r["mu"] == pytest.approx(d["mu"], abs=1e-5 * max(1.0, abs(d["mu"])))
+    assert r["sigma"] == pytest.approx(d["sigma"], rel=1e-5)
+    if _decision_margin_ok(d, tol):
+        assert r["used_fallback"] == (not d["accept"])
     if r["used_fallback"]:
-        assert r["logneg"] == pytest.approx(full["logneg"], abs=1e-12)
+        # the fallback is full SLQ: the oracle's estimate after m steps
+        assert r["steps_done"] == m
+        assert r["logneg"] == pytest.approx(o["logneg"], abs=1e-10 * max(1.0, abs(o["logneg"])))
     else:
-        assert r["logneg"] == pytest.approx(r["mu"]) and r["steps_done"] == 8
+        assert r["steps_done"] == 8 and r["logneg"] == r["mu"] and r["logneg_se"] == r["sigma"]
 
 
 def test_fallback_runs_full_slq(dev, model):

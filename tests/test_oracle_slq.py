@@ -122,9 +122,10 @@ def test_hutchinson_stats_definitions():
 
 
 def test_surrogate_features():
+    from oracle import surrogate
     psi = ti.haar_state(10, 0)
     out = slq.slq_logneg(psi, 10, [0, 1, 2], [3, 4, 5], 16, 10, seed=0)
-    f = slq.lanczos_block_features(out["alpha"], out["beta"], 8, 8, 16)
+    f = surrogate.block_features(out["alpha"], out["beta"], 8, 8, 16)
     assert f.shape == (19,)
     # N alpha_1 = phi^H X phi averaged over probes, whose expectation is Tr X = 1
     assert abs(f[0] - 1.0) < 0.2

@@ -38,6 +38,7 @@ __all__ = [
     "bell_pair_mps",
     "Workload",
     "WORKLOADS",
+    "random_vectors_torch",
 ]
 
 
@@ -277,6 +278,19 @@ def random_vectors(n_vectors: int, dim: int, seed: int) -> np.ndarray:
     imaginary parts, from ``default_rng(seed)``."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n_vectors, dim)) + 1j * rng.standard_normal((n_vectors, dim))
+
+
+def random_vectors_torch(n_vectors: int, dim: int, seed: int, device):
+    """(n_vectors, dim) complex128 vectors with i.i.d. N(0,1) real and
+    imaginary parts drawn on a torch device (for blocks too large to draw on
+    the host quickly), torch's generator seeded with ``seed``."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty((n_vectors, dim), dtype=torch.complex128, device=device)
+    torch.view_as_real(out).normal_(generator=g)
+    return out
 
 
 # --------------------------------------------------------------------------
