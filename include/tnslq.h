@@ -374,6 +374,24 @@ int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, 
                    const void *X_dev, void *Y_dev, int precision, int chunk_vectors, void *ws_dev,
                    size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): tnslq_ptmatvec
+ * with the workspace taken from a fixed scratch array the library holds on
+ * each GPU (TNSLQ_STATIC_SCRATCH_BYTES, kept from the library's load until
+ * the process ends) instead of a caller's buffer.  Arguments, results and
+ * errors as tnslq_ptmatvec; the problem must fit the scratch:
+ * tnslq_ptmatvec_workspace_bytes() <= TNSLQ_STATIC_SCRATCH_BYTES (a smaller
+ * chunk_vectors shrinks it), else TNSLQ_E_WORKSPACE before any device work.
+ * The scratch is that of the calling thread's current device, and `stream`
+ * must belong to that device.  Calls no allocating routine.  Every call on a
+ * GPU uses the same scratch, which keeps the last call's contents (nothing
+ * is assumed about them on entry): calls on one GPU whose device work
+ * overlaps in time (different streams or threads without ordering between
+ * them) race and give undefined results.  Does not synchronise. */
+#define TNSLQ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int tnslq_ptmatvec_static(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors,
+                          const void *X_dev, void *Y_dev, int precision, int chunk_vectors, void *stream);
+
 /* ------------------------------------------- explicit partial transpose */
 
 /* Workspace bytes for tnslq_rho_pt. */

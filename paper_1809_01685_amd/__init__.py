@@ -94,6 +94,7 @@ _SIGS = {
                           ctypes.POINTER(Result), _VP, _VP, _VP, _VP, _VP]),
     "tnslq_ptmatvec_workspace_bytes": (_I, [_I, ctypes.POINTER(Partition), _I, _I, _I, ctypes.POINTER(_SZ)]),
     "tnslq_ptmatvec": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _I, _VP, _SZ, _VP]),
+    "tnslq_ptmatvec_static": (_I, [_VP, _I, ctypes.POINTER(Partition), _I, _VP, _VP, _I, _I, _VP]),
     "tnslq_workspace_bytes_dims": (_I, [_I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options),
                                         ctypes.POINTER(_SZ)]),
     "tnslq_logneg_dims": (_I, [_VP, _I, ctypes.POINTER(PartitionDims), ctypes.POINTER(Options), _VP, _SZ, _VP,
@@ -322,6 +323,26 @@ def tnslq_ptmatvec(psi, n_qubits: int, a, b, X, precision="fp32", workspace=None
     p = _partition(n_qubits, a, b)
     _check(lib().tnslq_ptmatvec(_ptr(psi), dt, ctypes.byref(p), K, _ptr(X), _ptr(Y), _prec(precision),
                                 int(chunk_vectors), _ptr(ws), ws.numel(), _stream(stream)), "tnslq_ptmatvec")
+    return Y
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def tnslq_ptmatvec_static(psi, n_qubits: int, a, b, X, precision="fp32", stream=None, Y=None, chunk_vectors: int = 0):
+    """tnslq_ptmatvec on the library's fixed per-GPU scratch (no workspace,
+    nothing allocated by the library; ``Y`` is allocated here when not given)."""
+    import torch
+    _check_device_tensor(psi, "psi")
+    _check_device_tensor(X, "X")
+    if X.dtype != torch.complex128 or X.dim() != 2:
+        raise TypeError("X must be a 2-D complex128 device tensor")
+    if Y is None:
+        Y = torch.empty_like(X)
+    p = _partition(n_qubits, a, b)
+    _check(lib().tnslq_ptmatvec_static(_ptr(psi), _dtype_code(psi), ctypes.byref(p), X.shape[0], _ptr(X), _ptr(Y),
+                                       _prec(precision), int(chunk_vectors), _stream(stream)),
+           "tnslq_ptmatvec_static")
     return Y
 
 

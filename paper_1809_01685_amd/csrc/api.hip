@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1566,6 +1567,73 @@ int spectral_bytes(int dtype, int L, const int *s, int n_s, const tnslq_options 
     return TNSLQ_OK;
 }
 
+// ------------------------------------------------ block matvec entry points
+// Plan of tnslq_ptmatvec / tnslq_ptmatvec_static after the argument checks
+// (no device work).
+int ptmatvec_plan(int dtype, const tnslq_partition *part, int n_vectors, const void *X_dev, const void *Y_dev,
+                  int precision, int chunk_vectors, Plan &pl) {
+    int rc;
+    if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
+    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
+    if (chunk_vectors < 0) return fail(TNSLQ_E_ARG, "chunk_vectors must be >= 0");
+    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, pl, chunk_vectors)))
+        return rc;
+    if (!X_dev || !Y_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    if (X_dev == Y_dev) return fail(TNSLQ_E_ARG, "X and Y alias");
+    return TNSLQ_OK;
+}
+
+// Both contractions of Eq. 4 for the planned block on workspace `ws`
+// (regrouping psi, loading the vectors, every probe chunk).
+int ptmatvec_run(Ctx &c, const void *psi_dev, const void *X_dev, void *Y_dev, void *ws, hipStream_t st) {
+    if (!psi_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
+    bind(c, ws, st);
+    const Plan &pl = c.pl;
+    int rc;
+    if ((rc = do_layout(c, psi_dev))) return rc;
+    if (pl.stream) {
+        TNSLQ_HIP(launch_load_vectors_plain((const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xs, c.st));
+        if ((rc = stream_contract(c, c.Xs, nullptr, nullptr))) return rc;
+        TNSLQ_HIP(launch_reduce_partials(1, c.Ym, 1, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
+                                         (double2 *)Y_dev, c.st));
+        return TNSLQ_OK;
+    }
+    TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.pl.nst1, c.st));
+    for (int k0 = 0; k0 < pl.K; k0 += pl.kc) {
+        const int kcur = std::min(pl.kc, pl.K - k0);
+        if ((rc = contract_chunk(c, k0, kcur, nullptr, nullptr))) return rc;
+        TNSLQ_HIP(launch_reduce_partials(pl.prec == TNSLQ_FP64, c.Ypart, pl.S, (int64_t)pl.kc * pl.dAB, pl.dA, pl.dB,
+                                         kcur, pl.swapped, (double2 *)Y_dev + (size_t)k0 * pl.dAB, c.st));
+    }
+    return TNSLQ_OK;
+}
+
+// The fixed scratch of tnslq_ptmatvec_static: one copy per GPU, held from the
+// library's load until the process ends.  Host code never passes the array
+// itself to the device; it passes the device address hipGetSymbolAddress
+// returns for the current GPU, looked up once per GPU and kept.
+static __device__ __align__(256) unsigned char scratch[TNSLQ_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+int static_scratch(void **out) {
+    int dev = -1;
+    TNSLQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(TNSLQ_E_DEVICE, "device %d outside [0, %d)", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail(TNSLQ_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (!ptr || (uintptr_t)ptr % ALIGN) return fail(TNSLQ_E_DEVICE, "static scratch address %p unusable", ptr);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TNSLQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1776,36 +1844,28 @@ int tnslq_ptmatvec_workspace_bytes(int dtype, const tnslq_partition *part, int n
 
 int tnslq_ptmatvec(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors, const void *X_dev,
                    void *Y_dev, int precision, int chunk_vectors, void *ws_dev, size_t ws_bytes, void *stream) {
-    int rc;
     g_err.clear();
-    if ((rc = check_dtype(dtype)) || (rc = check_partition(part)) || (rc = check_prec(precision))) return rc;
-    if (part->n_a == 0 || part->n_b == 0) return fail(TNSLQ_E_PARTITION, "matvec needs non-empty A and B");
     Ctx c;
-    if (chunk_vectors < 0) return fail(TNSLQ_E_ARG, "chunk_vectors must be >= 0");
-    if ((rc = make_plan(dtype, part, n_vectors, 1, 0, precision, 0, TNSLQ_OPERATOR_LAZY, c.pl, chunk_vectors)))
-        return rc;
-    if (!psi_dev || !X_dev || !Y_dev || !ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
-    if (X_dev == Y_dev) return fail(TNSLQ_E_ARG, "X and Y alias");
+    int rc;
+    if ((rc = ptmatvec_plan(dtype, part, n_vectors, X_dev, Y_dev, precision, chunk_vectors, c.pl))) return rc;
+    if (!ws_dev) return fail(TNSLQ_E_ARG, "NULL device pointer");
     if ((uintptr_t)ws_dev % ALIGN) return fail(TNSLQ_E_ARG, "workspace not 256-byte aligned");
     if (ws_bytes < c.pl.total) return fail(TNSLQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, c.pl.total);
-    bind(c, ws_dev, (hipStream_t)stream);
-    const Plan &pl = c.pl;
-    if ((rc = do_layout(c, psi_dev))) return rc;
-    if (pl.stream) {
-        TNSLQ_HIP(launch_load_vectors_plain((const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xs, c.st));
-        if ((rc = stream_contract(c, c.Xs, nullptr, nullptr))) return rc;
-        TNSLQ_HIP(launch_reduce_partials(1, c.Ym, 1, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
-                                         (double2 *)Y_dev, c.st));
-        return TNSLQ_OK;
-    }
-    TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.pl.nst1, c.st));
-    for (int k0 = 0; k0 < pl.K; k0 += pl.kc) {
-        const int kcur = std::min(pl.kc, pl.K - k0);
-        if ((rc = contract_chunk(c, k0, kcur, nullptr, nullptr))) return rc;
-        TNSLQ_HIP(launch_reduce_partials(pl.prec == TNSLQ_FP64, c.Ypart, pl.S, (int64_t)pl.kc * pl.dAB, pl.dA, pl.dB,
-                                         kcur, pl.swapped, (double2 *)Y_dev + (size_t)k0 * pl.dAB, c.st));
-    }
-    return TNSLQ_OK;
+    return ptmatvec_run(c, psi_dev, X_dev, Y_dev, ws_dev, (hipStream_t)stream);
+}
+
+int tnslq_ptmatvec_static(const void *psi_dev, int dtype, const tnslq_partition *part, int n_vectors,
+                          const void *X_dev, void *Y_dev, int precision, int chunk_vectors, void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc;
+    if ((rc = ptmatvec_plan(dtype, part, n_vectors, X_dev, Y_dev, precision, chunk_vectors, c.pl))) return rc;
+    if (c.pl.total > TNSLQ_STATIC_SCRATCH_BYTES)
+        return fail(TNSLQ_E_WORKSPACE, "problem needs %zu bytes of scratch, the static scratch holds %zu", c.pl.total,
+                    (size_t)TNSLQ_STATIC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((rc = static_scratch(&ws))) return rc;
+    return ptmatvec_run(c, psi_dev, X_dev, Y_dev, ws, (hipStream_t)stream);
 }
 
 int tnslq_spectral_workspace_bytes(int dtype, int n_qubits, const int *s, int n_s, const tnslq_options *opt,

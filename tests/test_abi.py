@@ -101,6 +101,21 @@ def test_chunk_cap_sets_the_intermediary_size(L):
     assert ei.value.status == -1
 
 
+def test_static_scratch_entry_rejects_what_does_not_fit_before_device_work(L):
+    # the 30-qubit problem needs far more than the fixed scratch: a workspace
+    # error naming both sizes, with no device touched (none exists here)
+    a30, b30 = list(range(4, 17)), list(range(17, 30))
+    p = T._partition(30, a30, b30)
+    dummy = ctypes.c_void_p(256)
+    rc = L.tnslq_ptmatvec_static(dummy, 0, ctypes.byref(p), 8, dummy, ctypes.c_void_p(512), 2, 0, None)
+    assert rc == -4
+    assert "static scratch holds 67108864" in T.tnslq_last_error()
+    # argument errors come first
+    assert L.tnslq_ptmatvec_static(dummy, 0, ctypes.byref(p), 8, dummy, dummy, 2, 0, None) == -1
+    assert L.tnslq_ptmatvec_static(dummy, 0, ctypes.byref(p), 8, dummy, ctypes.c_void_p(512), 2, -1, None) == -1
+    assert T.STATIC_SCRATCH_BYTES == 64 << 20
+
+
 def test_rho_pt_validates_without_device(L):
     assert T.tnslq_rho_pt_workspace_bytes(T.TNSLQ_C128, 10, [0, 1, 2], [5, 6, 7]) >= 64 * 64 * 16
     with pytest.raises(T.TnslqError) as ei:
