@@ -230,6 +230,8 @@ def main():
     ap.add_argument("--check-steps", type=int, default=0, metavar="M",
                     help="also run M fixed steps on the same probes and report the estimate's error against "
                          "that run's value (post-hoc check of the +-tol target)")
+    ap.add_argument("--save-trajectory", default="", metavar="NPZ",
+                    help="with --check-steps: write that run's alpha, beta and quadrature values to NPZ")
     ap.add_argument("--max-steps", type=int, default=None)
     ap.add_argument("--probes", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
@@ -342,8 +344,11 @@ def main():
     if args.check_steps:
         # the plain M-step estimate (Gauss quadrature of T_M) on the same probes
         ref = T.tnslq_logneg(psi, L, a, b, w["n_probes"], args.check_steps, reorth=w["reorth"],
-                             precision=w["precision"], seed=args.seed, stop_tol=0.0, workspace=ws, want_arrays=False,
-                             stop_rule="diff")
+                             precision=w["precision"], seed=args.seed, stop_tol=0.0, workspace=ws,
+                             want_arrays=bool(args.save_trajectory), stop_rule="diff")
+        if args.save_trajectory:
+            import numpy as np
+            np.savez(args.save_trajectory, alpha=ref["alpha"], beta=ref["beta"], F=ref["F"])
         out["accuracy_check"] = {"reference_steps": args.check_steps, "reference_logneg": ref["logneg"],
                                  "error": last["logneg"] - ref["logneg"],
                                  "target": args.stop_tol * max(abs(ref["logneg"]), 1.0)}

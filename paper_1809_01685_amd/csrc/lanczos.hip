@@ -376,10 +376,14 @@ __global__ void __launch_bounds__(256) k_stats(const double *__restrict__ beta, 
 // of the |x| quadrature is an exponential too.  For fixed r the fit is the
 // linear regression of the values on r^t; r is chosen on an even grid of
 // FIT_GRID points and refined by golden-section search between the best grid
-// point's neighbours.  The uncertainty of F_inf is sqrt(C_00) of
+// point's neighbours.  The fit's own uncertainty of F_inf is sqrt(C_00) of
 // C = RSS / (n - 3) (J^T J)^-1, J the model's Jacobian in (F_inf, a, r); an
-// exact fit has uncertainty 0, a singular J^T J with RSS > 0 infinity.  A probe
-// whose recurrence broke down by step j is exact: F_s, uncertainty 0.
+// exact fit has uncertainty 0, a singular J^T J with RSS > 0 infinity.  To it
+// is added in quadrature the model error: the distance from F_inf to the limit
+// F_alg of the algebraic law F_j = F_alg + c (-1)^j / j^2 + d / j^2 (j the step
+// number) fitted to the same window by linear least squares, the way Gauss
+// quadrature of a function with a kink approaches its limit.  A probe whose
+// recurrence broke down by step j is exact: F_s, uncertainty 0.
 constexpr int FIT_WINDOW = TNSLQ_FIT_WINDOW;
 constexpr int FIT_MIN_POINTS = TNSLQ_FIT_MIN_POINTS;
 constexpr int FIT_GRID = 397;
@@ -413,6 +417,42 @@ __device__ inline double fit_linear(const double *y, int n, double r, double &f,
 }
 
 __device__ inline double fit_grid_r(int i) { return -FIT_R_MAX + (2.0 * FIT_R_MAX) * i / (FIT_GRID - 1); }
+
+// F_alg of the least-squares fit of F_alg + c (-1)^j / j^2 + d / j^2 to the n
+// values y of steps j0 .. j0 + n - 1: the two decaying columns are
+// orthonormalised (Gram-Schmidt, each projection applied twice) and F_alg is
+// the regression of y on the constant column's remainder.
+__device__ inline double fit_algebraic(const double *y, int n, int j0) {
+    double q[2][FIT_WINDOW], one[FIT_WINDOW], yr[FIT_WINDOW];
+    for (int t = 0; t < n; ++t) {
+        const double jj = (double)(j0 + t), w = 1.0 / (jj * jj);
+        q[0][t] = ((j0 + t) & 1) ? -w : w;
+        q[1][t] = w;
+        one[t] = 1.0;
+        yr[t] = y[t];
+    }
+    auto dot = [&](const double *u, const double *v) {
+        double s = 0.0;
+        for (int t = 0; t < n; ++t) s += u[t] * v[t];
+        return s;
+    };
+    auto remove = [&](double *v, const double *u) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const double c = dot(u, v);
+            for (int t = 0; t < n; ++t) v[t] -= c * u[t];
+        }
+    };
+    for (int c = 0; c < 2; ++c) {
+        if (c == 1) remove(q[1], q[0]);
+        const double nr = sqrt(dot(q[c], q[c]));
+        for (int t = 0; t < n; ++t) q[c][t] /= nr;
+    }
+    for (int c = 0; c < 2; ++c) {
+        remove(one, q[c]);
+        remove(yr, q[c]);
+    }
+    return dot(one, yr) / dot(one, one);
+}
 
 // Per probe k (one wave each): F_inf and its uncertainty after step
 // j >= FIT_MIN_POINTS + 1.  The lanes share the grid; the first grid point of
@@ -502,8 +542,9 @@ __global__ void __launch_bounds__(64) k_fit(const double *__restrict__ alpha, co
         const double c00 = rss / (n - 3) * cof00 / det;
         sig = (det > 0.0 && isfinite(c00) && c00 >= 0.0) ? sqrt(c00) : INFINITY;
     }
+    const double dm = f - fit_algebraic(y, n, lo + 1);
     finf[k] = f;
-    fsig[k] = sig;
+    fsig[k] = isfinite(sig) ? sqrt(sig * sig + dm * dm) : sig;
 }
 
 // Block statistics of the fitted estimates: G_n = beta_1^2 F_inf,n;

@@ -209,3 +209,62 @@ def test_probe_loop_respects_the_probe_budget():
     r = lf.probe_loop(block, 4, 11, 1e-6)   # unreachable target: 2 blocks fit in 11 probes
     assert r["n_probes_used"] == 8 and len(r["stops"]) == 2
     assert r["logneg_err"] > 1e-6
+
+
+# ------------------------------------------------------------ model term
+@pytest.mark.parametrize("j_end,n", [(6, 5), (9, 8), (17, 8)])
+def test_algebraic_law_is_recovered_exactly(j_end, n):
+    # noise-free F_j = 0.81 + 0.37 (-1)^j / j^2 - 0.05 / j^2 over steps
+    # j_end - n + 1 .. j_end: the algebraic fit returns the limit
+    j = np.arange(j_end - n + 1, j_end + 1, dtype=float)
+    y = 0.81 + 0.37 * (-1.0) ** j / j ** 2 - 0.05 / j ** 2
+    assert lf.algebraic_fit(y, j_end) == pytest.approx(0.81, abs=1e-13)
+
+
+def test_model_term_is_the_distance_between_the_two_limits():
+    # on an algebraic trajectory the model term is exactly how far the
+    # exponential's limit lies from the true one; a constant trajectory has
+    # no model error and no fit error
+    j = np.arange(1, 13, dtype=float)
+    F = 0.5 + 0.3 * (-1.0) ** j / j ** 2 + 0.02 / j ** 2
+    for k in (6, 9, 12):
+        est = lf.lanczos_estimate(F, k)
+        assert est["model"] == pytest.approx(abs(est["f_inf"] - 0.5), abs=1e-13)
+        assert est["sigma"] == pytest.approx(np.hypot(est["sigma_fit"], est["model"]), rel=1e-15)
+        assert est["sigma"] >= abs(est["f_inf"] - 0.5)
+    c = lf.lanczos_estimate(np.full(10, 0.25), 10)
+    assert c["f_inf"] == pytest.approx(0.25, rel=1e-15) and c["sigma"] < 1e-14
+
+
+def _coverage_cases():
+    # 21 Haar states of 12-14 qubits with small environments (d_E = 4-16, the
+    # regime of the 26-qubit rho_AB: the spectrum straddles 0) and three cuts
+    out = []
+    for L, a, b in ((12, list(range(2, 7)), list(range(7, 12))), (13, list(range(3, 8)), list(range(8, 13))),
+                    (14, list(range(0, 4)), list(range(4, 10)))):
+        for s in range(7):
+            out.append((L, a, b, 40 + 7 * L + s))
+    return out
+
+
+def test_stated_lanczos_error_covers_the_long_run():
+    # at the fit rule's +-1% stop, the stated Lanczos error (in bits) must
+    # cover the distance to the converged value on the same probes on at least
+    # 68% of the states (a one-sigma bar); the converged value is the mean of
+    # the plain quadrature estimates over steps 71-80, which averages the last
+    # alternation of the quadrature
+    cover, steps = [], []
+    for L, a, b, seed in _coverage_cases():
+        P = exact.regroup(ti.haar_state(L, seed), L, a, b)
+        R = exact.rho_pt(P)
+        X = probes.rademacher_probes(seed, 8, R.shape[0], 0)
+        r = slq.slq(lambda v: R @ v, X, 80)
+        e_long = np.mean([np.log2(np.mean(r["beta"][:, 0] ** 2 * r["F"][:, j])) for j in range(70, 80)])
+        k = lf.fit_stop_step(r["F"], r["alpha"], r["beta"], 0.01)
+        st = lf.fit_stats(r["F"], r["alpha"], r["beta"], k)
+        stated = st["lanczos_err"] / (st["trace_norm"] * np.log(2.0))
+        cover.append(abs(st["logneg"] - e_long) <= stated)
+        steps.append(k)
+    assert len(cover) >= 20
+    assert np.mean(cover) >= 0.68, (np.mean(cover), steps)
+    assert max(steps) < 20        # and the rule still stops early
