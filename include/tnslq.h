@@ -51,8 +51,22 @@ enum {
     TNSLQ_E_DTYPE = -3,      /* unknown storage type                           */
     TNSLQ_E_WORKSPACE = -4,  /* workspace smaller than the query returned      */
     TNSLQ_E_DEVICE = -5,     /* a HIP runtime call failed                      */
-    TNSLQ_E_NONFINITE = -6   /* the estimate came out NaN or infinite          */
+    TNSLQ_E_NONFINITE = -6,  /* psi holds a NaN or infinite amplitude, or the
+                                estimate came out NaN or infinite              */
+    TNSLQ_E_STATE = -7       /* psi is not normalised: | ||psi||^2 - 1 | above
+                                TNSLQ_NORM_TOL_C64 / _C128 for its dtype       */
 };
+
+/* The estimates assume a normalised state (Tr rho = 1, Sec. II Eq. 1); a state
+ * is checked, never silently renormalised.  tnslq_logneg, tnslq_logneg_dims,
+ * tnslq_logneg_surrogate, tnslq_spectral_sum and tnslq_mutual_information
+ * read psi once before the Lanczos steps (one synchronisation of the stream)
+ * and return TNSLQ_E_NONFINITE for a non-finite amplitude and TNSLQ_E_STATE
+ * for a squared norm outside 1 +- the tolerance of its dtype (a complex64
+ * state normalised in FP64 and rounded is within 1e-6 of 1).  The block
+ * matvecs (tnslq_ptmatvec*) apply Eq. 4 to any psi without a check. */
+#define TNSLQ_NORM_TOL_C64 1e-4
+#define TNSLQ_NORM_TOL_C128 1e-9
 
 /* State storage. */
 enum { TNSLQ_C64 = 0, TNSLQ_C128 = 1 };

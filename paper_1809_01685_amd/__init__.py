@@ -17,6 +17,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtnslq.so")
 
 TNSLQ_OK = 0
+TNSLQ_E_ARG, TNSLQ_E_PARTITION, TNSLQ_E_DTYPE, TNSLQ_E_WORKSPACE = -1, -2, -3, -4
+TNSLQ_E_DEVICE, TNSLQ_E_NONFINITE, TNSLQ_E_STATE = -5, -6, -7
 TNSLQ_C64, TNSLQ_C128 = 0, 1
 TNSLQ_FP64, TNSLQ_FP32, TNSLQ_BF16X3, TNSLQ_BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "bf16x6": TNSLQ_BF16X6}
@@ -191,8 +193,10 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def _workspace(nbytes: int, device, ws=None):
+    """The caller's workspace as given (the library checks its size), else a
+    new one of nbytes."""
     import torch
-    if ws is not None and ws.numel() >= nbytes:
+    if ws is not None:
         return ws
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 

@@ -66,9 +66,9 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _link(objs, out: str) -> None:
+def _link(objs, out: str, extra=()) -> None:
     tmp = out + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *extra]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
@@ -80,7 +80,8 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [PEAK_SRC]
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(_compile, srcs))
-    _link(objs[:-1], OUT)
+    # roctx ranges mark the phases of an estimate for rocprofv3 --marker-trace
+    _link(objs[:-1], OUT, ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     _link(objs[-1:], PEAK_OUT)
     if verbose:
         print(f"built {OUT}")

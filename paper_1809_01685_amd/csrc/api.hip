@@ -16,6 +16,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "tnslq_internal.h"
 
 using namespace tnslq;
@@ -304,6 +306,7 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.off_fit = take((size_t)2 * K * 8 + 8 * 8);
         pl.off_feat = take(64 * 4);
         pl.off_mlp = take(mlp_ws_bytes(1) + 64);
+        pl.off_chk = take(STATE_CHECK_BYTES);
     }
     pl.total = o;
     return TNSLQ_OK;
@@ -635,7 +638,7 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
     auto buf = [&](size_t off) { return (double2 *)(ws + off); };
     int *failp = (int *)(ws + mp.off_fail);
     double *dscr = (double *)(ws + mp.off_fail + 64);   // the factorisations' largest diagonal entry
-    TNSLQ_HIP(hipMemsetAsync(failp, 0, 16, st));
+    TNSLQ_HIP(launch_zero(failp, 16, st));
     static const double2 one = {1.0, 0.0};
     // traced environments: E_L on the bond entering A, E_R on the bond leaving B
     double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
@@ -867,7 +870,7 @@ int do_layout(Ctx &c, const void *psi) {
         if ((rc = form_rho(pl, pl.prec, psi, c.Pabe, c.Pabc, c.Cd, c.st))) return rc;
         TNSLQ_HIP(launch_pt_bricks(pl.prec, pl.prec == TNSLQ_FP64, c.Cd, pl.dAB, pl.dB, c.rho, pl.nst_rho, c.st));
         if (pl.dAB % brick_epr(pl.prec))
-            TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, pl.K, pl.dAB), c.st));
+            TNSLQ_HIP(launch_zero(c.Xt, brick_bytes(pl.prec, pl.K, pl.dAB), c.st));
         return TNSLQ_OK;
     }
     if (pl.stream) {
@@ -887,9 +890,9 @@ int do_layout(Ctx &c, const void *psi) {
     TNSLQ_HIP(launch_permute(pl.prec, pl.dtype, psi, c.Pbea, pl.dB * pl.dE, pl.dA, bea, 1, c.st));
     const int64_t epr = brick_epr(pl.prec);
     if (pl.dA % epr)
-        TNSLQ_HIP(hipMemsetAsync(c.Xt, 0, brick_bytes(pl.prec, (int64_t)pl.K * pl.dB, pl.dA), c.st));
+        TNSLQ_HIP(launch_zero(c.Xt, brick_bytes(pl.prec, (int64_t)pl.K * pl.dB, pl.dA), c.st));
     if ((pl.dE * pl.dB) % epr)
-        TNSLQ_HIP(hipMemsetAsync(c.Ups, 0, brick_bytes(pl.prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB), c.st));
+        TNSLQ_HIP(launch_zero(c.Ups, brick_bytes(pl.prec, (int64_t)pl.kc * pl.dB, pl.dE * pl.dB), c.st));
     return TNSLQ_OK;
 }
 
@@ -1097,9 +1100,9 @@ int slq_setup(Ctx &c, const void *psi, uint64_t seed, uint64_t offset) {
     const Plan &pl = c.pl;
     int rc;
     if ((rc = do_layout(c, psi))) return rc;
-    TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)pl.K * pl.m * 8, c.st));
-    TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)pl.K * (pl.m + 1) * 8, c.st));
-    TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)pl.K * pl.m * 8, c.st));
+    TNSLQ_HIP(launch_zero(c.alpha, (size_t)pl.K * pl.m * 8, c.st));
+    TNSLQ_HIP(launch_zero(c.beta, (size_t)pl.K * (pl.m + 1) * 8, c.st));
+    TNSLQ_HIP(launch_zero(c.F, (size_t)pl.K * pl.m * 8, c.st));
     TNSLQ_HIP(launch_probe_init(pl.prec, c.z, seed, offset, pl.swapped, c.Q, pl.stream ? nullptr : c.Xt, pl.nst1,
                                 c.alpha, c.beta, c.st));
     return TNSLQ_OK;
@@ -1137,6 +1140,21 @@ int trivial(const tnslq_options *opt, tnslq_result *res, double *G, double *alph
     if (beta) std::fill(beta, beta + (size_t)K * (m + 1), 0.0);
     if (F) std::fill(F, F + (size_t)K * m, 1.0);
     if (steps) std::fill(steps, steps + K, 0);
+    return TNSLQ_OK;
+}
+
+// The estimate needs a normalised state (Tr rho_AB = 1, Eq. 1); psi is
+// checked, not silently renormalised: its non-finite amplitudes and its
+// squared norm are read back once before the Lanczos steps.  Synchronises.
+int check_state(int dtype, const void *psi, int64_t D, double *scratch, hipStream_t st) {
+    TNSLQ_HIP(launch_state_check(dtype, psi, D, scratch, st));
+    double h[2];
+    TNSLQ_HIP(hipMemcpyAsync(h, scratch + 2 * STATE_CHECK_BLOCKS, sizeof h, hipMemcpyDeviceToHost, st));
+    TNSLQ_HIP(hipStreamSynchronize(st));
+    if (h[1] > 0.0) return fail(TNSLQ_E_NONFINITE, "psi holds %.0f non-finite amplitudes", h[1]);
+    const double tol = dtype == TNSLQ_C128 ? TNSLQ_NORM_TOL_C128 : TNSLQ_NORM_TOL_C64;
+    if (!(std::fabs(h[0] - 1.0) <= tol))
+        return fail(TNSLQ_E_STATE, "psi is not normalised: ||psi||^2 = %.10g (tolerance %g)", h[0], tol);
     return TNSLQ_OK;
 }
 
@@ -1209,7 +1227,12 @@ int run_start(Run &r, const tnslq_options *opt, const void *psi, void *ws, size_
             if (!(e = r.c.event())) return fail(TNSLQ_E_DEVICE, "hipEventCreate failed");
     }
     TNSLQ_HIP(hipEventRecord(r.e_start, r.c.st));
-    if ((rc = slq_setup(r.c, psi, opt->seed, opt->probe_offset))) return rc;
+    if (!r.c.pl.mpsf && (rc = check_state(r.c.pl.dtype, psi, r.c.pl.D, (double *)(r.c.ws + r.c.pl.off_chk), r.c.st)))
+        return rc;
+    roctxRangePush("tnslq layout");
+    rc = slq_setup(r.c, psi, opt->seed, opt->probe_offset);
+    roctxRangePop();
+    if (rc) return rc;
     TNSLQ_HIP(hipEventRecord(r.e_layout, r.c.st));
     return TNSLQ_OK;
 }
@@ -1231,7 +1254,10 @@ int fit_step(Run &r, int j, double *G) {
 int run_steps(Run &r, int jmax, double stop_tol, bool lanczos_only = false) {
     int rc;
     for (int j = r.jdone + 1; j <= jmax; ++j) {
-        if ((rc = lanczos_step(r.c, j, &r.se[j]))) return rc;
+        roctxRangePush("tnslq lanczos step");
+        rc = lanczos_step(r.c, j, &r.se[j]);
+        roctxRangePop();
+        if (rc) return rc;
         r.jdone = j;
         if (stop_tol <= 0.0) continue;
         if (r.rule == TNSLQ_STOP_FIT && j >= TNSLQ_FIT_MIN_POINTS + 1) {
@@ -1338,7 +1364,7 @@ struct SPlan {
     int K = 1, m = 1, reorth = 0;
     int S1 = 1, S2 = 1, nblk = 1, nQ = 3;
     size_t off_P1 = 0, off_P2 = 0, off_Zp = 0, off_Z = 0, off_Yp = 0, off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0;
-    size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, total = 0;
+    size_t off_F = 0, off_G = 0, off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_chk = 0, total = 0;
 };
 
 int check_subsystem(int L, const int *s, int n_s) {
@@ -1418,6 +1444,7 @@ int make_splan(int dtype, int L, const int *s, int n_s, const tnslq_options *opt
     sp.off_red = take((size_t)2 * K * sp.nblk * 8);
     sp.off_h = take((size_t)K * (m + 1) * sp.nblk * 16 + (size_t)K * (m + 1) * 16);
     sp.off_steps = take((size_t)K * 4);
+    sp.off_chk = take(STATE_CHECK_BYTES);
     sp.total = o;
     return TNSLQ_OK;
 }
@@ -1474,14 +1501,16 @@ int spectral_run(const SPlan &sp, const void *psi, const tnslq_options *opt, uin
         lz1[j] = event();
     }
     if ((int)ev.size() != 2 + 3 * sp.m) return fail(TNSLQ_E_DEVICE, "hipEventCreate failed");
+    int rc0;
+    if ((rc0 = check_state(sp.dtype, psi, sp.D, (double *)(base + sp.off_chk), st))) return rc0;
     TNSLQ_HIP(hipEventRecord(e0, st));
     const PermDesc p1 = perm_two(sp.L, sp.side, sp.n_side, sp.rest, sp.n_rest);
     const PermDesc p2 = perm_two(sp.L, sp.rest, sp.n_rest, sp.side, sp.n_side);
     TNSLQ_HIP(launch_regroup(sp.dtype, psi, P1, sp.d, sp.dR, p1, st));
     TNSLQ_HIP(launch_regroup(sp.dtype, psi, P2, sp.dR, sp.d, p2, st));
-    TNSLQ_HIP(hipMemsetAsync(alpha, 0, (size_t)sp.K * sp.m * 8, st));
-    TNSLQ_HIP(hipMemsetAsync(beta, 0, (size_t)sp.K * (sp.m + 1) * 8, st));
-    TNSLQ_HIP(hipMemsetAsync(F, 0, (size_t)sp.K * sp.m * 8, st));
+    TNSLQ_HIP(launch_zero(alpha, (size_t)sp.K * sp.m * 8, st));
+    TNSLQ_HIP(launch_zero(beta, (size_t)sp.K * (sp.m + 1) * 8, st));
+    TNSLQ_HIP(launch_zero(F, (size_t)sp.K * sp.m * 8, st));
     TNSLQ_HIP(launch_probe_init(TNSLQ_FP64, z, opt->seed, offset, 0, Q, nullptr, 0, alpha, beta, st));
     TNSLQ_HIP(hipEventRecord(e1, st));
     auto slot_of = [&](int jj) { return sp.reorth ? jj : jj % 3; };
@@ -1646,7 +1675,8 @@ const char *tnslq_status_str(int s) {
         case TNSLQ_E_DTYPE: return "invalid dtype";
         case TNSLQ_E_WORKSPACE: return "workspace too small";
         case TNSLQ_E_DEVICE: return "device error";
-        case TNSLQ_E_NONFINITE: return "non-finite result";
+        case TNSLQ_E_NONFINITE: return "non-finite value";
+        case TNSLQ_E_STATE: return "state not normalised";
         default: return "unknown status";
     }
 }
@@ -1695,9 +1725,9 @@ int run_probe_loop(Run &r, const tnslq_options *opt, tnslq_result *res, double *
     for (int b = 0;; ++b) {
         if (b > 0) {
             // the next block: fresh probes on the same regrouped psi
-            TNSLQ_HIP(hipMemsetAsync(c.alpha, 0, (size_t)K * pl.m * 8, c.st));
-            TNSLQ_HIP(hipMemsetAsync(c.beta, 0, (size_t)K * (pl.m + 1) * 8, c.st));
-            TNSLQ_HIP(hipMemsetAsync(c.F, 0, (size_t)K * pl.m * 8, c.st));
+            TNSLQ_HIP(launch_zero(c.alpha, (size_t)K * pl.m * 8, c.st));
+            TNSLQ_HIP(launch_zero(c.beta, (size_t)K * (pl.m + 1) * 8, c.st));
+            TNSLQ_HIP(launch_zero(c.F, (size_t)K * pl.m * 8, c.st));
             TNSLQ_HIP(launch_probe_init(pl.prec, c.z, opt->seed, opt->probe_offset + (uint64_t)b * K, pl.swapped,
                                         c.Q, pl.stream ? nullptr : c.Xt, pl.nst1, c.alpha, c.beta, c.st));
             r.jdone = 0;

@@ -3,6 +3,8 @@
 // psi_{1..L} -> psi_{abc}), the Hutchinson probe block (Sec. III,
 // Algorithm 1), and the conversions between caller vectors and the
 // contraction operands.
+#include <algorithm>
+
 #include "tnslq_internal.h"
 
 namespace tnslq {
@@ -291,7 +293,81 @@ inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
     return (unsigned)g;
 }
 
+// Zero n16 16-byte units and then `tail` single bytes (a fill kernel rather
+// than a memset node, so that work a caller captures into a HIP graph replays
+// correctly).
+__global__ void k_zero(uint4 *__restrict__ p, int64_t n16, unsigned char *__restrict__ tailp, int tail) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n16; k += stride) p[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < tail) tailp[i] = 0;
+}
+
+// ||psi||^2 and the number of non-finite amplitudes: per-block partial sums
+// (grid-stride, FP64), then one thread adds the blocks in order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_state_partial(const T *__restrict__ psi, int64_t D,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[2][256];
+    double s = 0.0, bad = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < D; i += stride) {
+        const double re = psi[i].x, im = psi[i].y;
+        if (isfinite(re) && isfinite(im))
+            s += re * re + im * im;
+        else
+            bad += 1.0;
+    }
+    sh[0][threadIdx.x] = s;
+    sh[1][threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+__global__ void k_state_sum(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, bad = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        s += part[2 * b];
+        bad += part[2 * b + 1];
+    }
+    out[0] = s;
+    out[1] = bad;
+}
+
 }  // namespace
+
+hipError_t launch_state_check(int dtype, const void *psi, int64_t D, double *scratch, hipStream_t st) {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(STATE_CHECK_BLOCKS, (D + 4095) / 4096));
+    double *out = scratch + 2 * STATE_CHECK_BLOCKS;
+    if (dtype == TNSLQ_C128)
+        hipLaunchKernelGGL(k_state_partial<double2>, dim3(nb), dim3(256), 0, st, (const double2 *)psi, D, scratch);
+    else
+        hipLaunchKernelGGL(k_state_partial<float2>, dim3(nb), dim3(256), 0, st, (const float2 *)psi, D, scratch);
+    hipLaunchKernelGGL(k_state_sum, dim3(1), dim3(64), 0, st, (const double *)scratch, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (!p || (uintptr_t)p % 16) return hipErrorInvalidValue;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int tail = (int)(bytes % 16);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(4096, (n16 + 255) / 256));
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4 *)p, n16,
+                       (unsigned char *)p + n16 * 16, tail);
+    return hipGetLastError();
+}
 
 hipError_t launch_permute(int prec, int dtype, const void *psi, void *out, int64_t R, int64_t Kr,
                           const PermDesc &pd, int conj, hipStream_t st) {

@@ -69,11 +69,22 @@ struct Plan {
     size_t off_P32 = 0, off_Q32 = 0, off_X32 = 0;   // complex64 copies (FP32 factorised operator)
     size_t off_Q = 0, off_w = 0, off_alpha = 0, off_beta = 0, off_F = 0, off_G = 0;
     size_t off_stats = 0, off_red = 0, off_h = 0, off_steps = 0, off_fit = 0, off_feat = 0, off_mlp = 0;
+    size_t off_chk = 0;              // the state check's partial sums
     size_t total = 0;
     int nQ = 3;                      // Lanczos vector slots
 };
 
 // ------------------------------------------------------------ layout
+// Zero `bytes` bytes at p (16-byte aligned) with a fill kernel on st.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// ||psi||^2 and the count of non-finite amplitudes of the D-element state, at
+// scratch[2 STATE_CHECK_BLOCKS] and scratch[2 STATE_CHECK_BLOCKS + 1]
+// (scratch: STATE_CHECK_BYTES of device memory).
+constexpr int STATE_CHECK_BLOCKS = 1024;
+constexpr size_t STATE_CHECK_BYTES = (2 * STATE_CHECK_BLOCKS + 2) * sizeof(double);
+hipError_t launch_state_check(int dtype, const void *psi, int64_t D, double *scratch, hipStream_t st);
+
 struct PermDesc {
     int L;
     int map[TNSLQ_MAX_QUBITS];   // output bit t <- input bit map[t]

@@ -165,6 +165,21 @@ def test_logneg_validates_before_device_work(L):
     assert "NULL" in T.tnslq_last_error()
 
 
+def test_status_codes_and_small_workspace_without_device(L):
+    assert [T.tnslq_status_str(c) for c in (-6, -7)] == ["non-finite value", "state not normalised"]
+    # a workspace smaller than the plan is refused before psi or the
+    # workspace is touched (the pointers here are not device memory)
+    p = T._partition(6, [0], [1, 2])
+    o = T.make_options(4, 4)
+    res = T.Result()
+    fake = ctypes.c_void_p(1 << 20)
+    rc = L.tnslq_logneg(fake, 0, ctypes.byref(p), ctypes.byref(o), fake, 256, None, ctypes.byref(res),
+                        None, None, None, None, None)
+    assert rc == T.TNSLQ_E_WORKSPACE and "workspace 256 bytes" in T.tnslq_last_error()
+    rc = L.tnslq_ptmatvec(fake, 0, ctypes.byref(p), 2, fake, ctypes.c_void_p(1 << 21), 1, 0, fake, 256, None)
+    assert rc == T.TNSLQ_E_WORKSPACE
+
+
 def test_empty_subsystem_is_exactly_zero_without_device(L):
     p = T._partition(6, [0, 1], [])
     o = T.make_options(3, 5)
