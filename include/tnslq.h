@@ -103,8 +103,16 @@ enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
  *   TNSLQ_OPERATOR_AUTO      the explicit form when it fits and its padded
  *                            flop count over n_steps matvecs is the smaller,
  *                            else the lazy form (always lazy when K d_B <= 8,
- *                            the streaming regime). */
-enum { TNSLQ_OPERATOR_AUTO = 0, TNSLQ_OPERATOR_LAZY = 1, TNSLQ_OPERATOR_EXPLICIT = 2 };
+ *                            the streaming regime).
+ * In the streaming regime the lazy form reads psi once per matvec where that
+ * is faster (complex64 psi, at least 256 environment slabs, one vector,
+ * d_B = 2 and d_A = 2048 or 4096: each block keeps its share of the result on
+ * chip), else in two passes.
+ *   TNSLQ_OPERATOR_LAZY_TWO_PASS  the lazy form with the two-pass streaming
+ *                            form always (for comparison; the results agree
+ *                            to FP64 rounding). */
+enum { TNSLQ_OPERATOR_AUTO = 0, TNSLQ_OPERATOR_LAZY = 1, TNSLQ_OPERATOR_EXPLICIT = 2,
+       TNSLQ_OPERATOR_LAZY_TWO_PASS = 3 };
 
 /* Stopping rules of tnslq_options.stop_rule. */
 enum { TNSLQ_STOP_DIFF = 0, TNSLQ_STOP_FIT = 1 };
@@ -216,10 +224,10 @@ typedef struct {
     double lanczos_err;     /* Lanczos part of the error of logneg, in bits:
                                |E_j - E_{j-5}| (TNSLQ_STOP_DIFF, NaN for j < 6)
                                or eps_L / (T ln 2) (TNSLQ_STOP_FIT)            */
-    int streamed;           /* 1 if the contractions ran as two streaming
-                               passes over psi with FP64 arithmetic (K d_B <= 8
-                               after the role choice), 0 on the matrix cores
-                               in `precision`                                  */
+    int streamed;           /* 0 if the contractions ran on the matrix cores
+                               in `precision`; in the streaming regime (K d_B
+                               <= 8 after the role choice, FP64 arithmetic) 1
+                               for two passes over psi, 2 for one read        */
     int explicit_operator;  /* 1 if rho^{T_B} was formed explicitly
                                (intermediary (iii)); the roles of A and B are
                                then never exchanged, t_contract1_ms is 0 and

@@ -24,8 +24,9 @@ TNSLQ_FP64, TNSLQ_FP32, TNSLQ_BF16X3, TNSLQ_BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": TNSLQ_FP64, "fp32": TNSLQ_FP32, "bf16x3": TNSLQ_BF16X3, "bf16x6": TNSLQ_BF16X6}
 TNSLQ_STOP_DIFF, TNSLQ_STOP_FIT = 0, 1
 STOP_RULES = {"diff": TNSLQ_STOP_DIFF, "fit": TNSLQ_STOP_FIT}
-TNSLQ_OPERATOR_AUTO, TNSLQ_OPERATOR_LAZY, TNSLQ_OPERATOR_EXPLICIT = 0, 1, 2
-OPERATORS = {"auto": TNSLQ_OPERATOR_AUTO, "lazy": TNSLQ_OPERATOR_LAZY, "explicit": TNSLQ_OPERATOR_EXPLICIT}
+TNSLQ_OPERATOR_AUTO, TNSLQ_OPERATOR_LAZY, TNSLQ_OPERATOR_EXPLICIT, TNSLQ_OPERATOR_LAZY_TWO_PASS = 0, 1, 2, 3
+OPERATORS = {"auto": TNSLQ_OPERATOR_AUTO, "lazy": TNSLQ_OPERATOR_LAZY, "explicit": TNSLQ_OPERATOR_EXPLICIT,
+             "lazy_two_pass": TNSLQ_OPERATOR_LAZY_TWO_PASS}
 TNSLQ_FIT_WINDOW, TNSLQ_FIT_MIN_POINTS = 8, 5
 TNSLQ_F_ABS, TNSLQ_F_ENTROPY, TNSLQ_F_PURITY = 0, 1, 2
 FUNCTIONS = {"entropy": TNSLQ_F_ENTROPY, "purity": TNSLQ_F_PURITY}

@@ -120,13 +120,14 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
               Plan &pl, int chunk = 0) {
     int rc;
     if ((rc = check_dtype(dtype)) || (rc = check_partition(p)) || (rc = check_prec(prec))) return rc;
-    if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_EXPLICIT)
+    if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_LAZY_TWO_PASS)
         return fail(TNSLQ_E_ARG, "operator_form %d unknown", opform);
     if (K < 1 || K > 65535) return fail(TNSLQ_E_ARG, "n_probes %d outside [1, 65535]", K);
     if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
         return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
     pl = Plan();
     pl.kc_cap = std::max(0, chunk);
+    pl.two_pass = opform == TNSLQ_OPERATOR_LAZY_TWO_PASS;
     pl.L = p->n_qubits;
     pl.dtype = dtype;
     pl.prec = prec;
@@ -228,6 +229,10 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.S2s = 1;
         while (gx2 * pl.S2s < 2048 && pl.dE * pl.dB / (2 * pl.S2s) >= 64) pl.S2s *= 2;
         pl.S = pl.S2s;
+        // one read of psi where the shape has an instance and every CU gets a
+        // slab range (fused.hip)
+        pl.fused = !pl.two_pass && pl.dE >= FUSED_BLOCKS && pt_fused_supported(dtype, pl.dA, pl.dB, K, pl.dE);
+        if (pl.fused) pl.S = FUSED_BLOCKS;
     }
 
     // factorised MPS operator: four complex products per probe, chunks of
@@ -272,6 +277,10 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.off_rho = take(brick_bytes(prec, n, n));
         pl.off_Xt = take(brick_bytes(prec, K, n));
         pl.off_Ypart = take((size_t)pl.S * K * n * acc);
+    } else if (pl.stream && pl.fused) {
+        pl.off_P1s = take((size_t)8 * pl.D);                        // psi as P[c][a][b]
+        pl.off_Ypart = take((size_t)FUSED_BLOCKS * K * n * 16);     // the blocks' partial Y
+        if (!lanczos) pl.off_Xs = take((size_t)K * n * 16);
     } else if (pl.stream) {
         const size_t esz = dtype == TNSLQ_C128 ? 16 : 8;
         const int64_t nv = (int64_t)K * pl.dB, ncol = pl.dE * pl.dB;
@@ -352,7 +361,7 @@ int make_plan_dims(int dtype, const tnslq_partition_dims *p, int K, int m, int r
     if (K < 1 || K > 65535) return fail(TNSLQ_E_ARG, "n_probes %d outside [1, 65535]", K);
     if (lanczos && (m < 1 || m > TNSLQ_MAX_STEPS))
         return fail(TNSLQ_E_ARG, "n_steps %d outside [1, %d]", m, TNSLQ_MAX_STEPS);
-    if (opform == TNSLQ_OPERATOR_LAZY)
+    if (opform == TNSLQ_OPERATOR_LAZY || opform == TNSLQ_OPERATOR_LAZY_TWO_PASS)
         return fail(TNSLQ_E_ARG, "sites of general dimension take the explicit operator only");
     if (opform < TNSLQ_OPERATOR_AUTO || opform > TNSLQ_OPERATOR_EXPLICIT)
         return fail(TNSLQ_E_ARG, "operator_form %d unknown", opform);
@@ -873,6 +882,13 @@ int do_layout(Ctx &c, const void *psi) {
             TNSLQ_HIP(launch_zero(c.Xt, brick_bytes(pl.prec, pl.K, pl.dAB), c.st));
         return TNSLQ_OK;
     }
+    if (pl.stream && pl.fused) {
+        // (E, A, B), B fastest: environment slab c is a contiguous d_A x d_B
+        // matrix (the panel layout with 512 columns is row-major)
+        const PermDesc eab = perm_for(pl, pl.qe, pl.nE, pl.qa, pl.nA, pl.qb, pl.nB);
+        TNSLQ_HIP(launch_regroup(pl.dtype, psi, c.P1s, pl.D / 512, 512, eab, c.st));
+        return TNSLQ_OK;
+    }
     if (pl.stream) {
         // (A; E, B): rows a', columns (c, b); (E, B; A): rows (c, b'), columns a
         int eb[TNSLQ_MAX_QUBITS];
@@ -907,6 +923,15 @@ int do_layout(Ctx &c, const void *psi) {
 // column MAC's plain form.
 int stream_contract(Ctx &c, const double2 *xq, hipEvent_t e1, hipEvent_t e2) {
     const Plan &pl = c.pl;
+    if (pl.fused) {
+        // both contractions in one read of psi; the Lanczos pass (or the
+        // matvec's reduction) sums the blocks' partials
+        if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+        TNSLQ_HIP(launch_pt_fused(c.P1s, xq, pl.dA, pl.dB, pl.K, pl.dE, FUSED_BLOCKS, (double2 *)c.Ypart, c.st));
+        if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+        c.n_launch++;
+        return TNSLQ_OK;
+    }
     const int64_t ncol = pl.dE * pl.dB;
     const int nv = pl.K * (int)pl.dB;
     TNSLQ_HIP(launch_vectors_by_b(xq, pl.K, pl.dA, pl.nB, c.Xq, c.st));
@@ -1081,7 +1106,8 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
             return rc;
         }
         // the streaming passes leave Y already summed over their splits
-        TNSLQ_HIP(launch_passA(accfp64, c.z, pl.stream ? (const void *)c.Ym : c.Ypart, pl.stream ? 1 : pl.S,
+        TNSLQ_HIP(launch_passA(accfp64, c.z, pl.stream && !pl.fused ? (const void *)c.Ym : c.Ypart,
+                               pl.stream && !pl.fused ? 1 : pl.S,
                                (int64_t)pl.kc * n, k0, kcur, q_prev, q_cur, c.w, c.alpha, c.beta, j, c.dotpart,
                                c.st));
         TNSLQ_HIP(hipEventRecord(se->pa(ch), c.st));
@@ -1167,7 +1193,7 @@ int check_options(const tnslq_options *opt) {
     if (!(opt->stop_tol >= 0.0)) return fail(TNSLQ_E_ARG, "stop_tol must be >= 0");
     if (opt->stop_rule != TNSLQ_STOP_DIFF && opt->stop_rule != TNSLQ_STOP_FIT)
         return fail(TNSLQ_E_ARG, "stop_rule %d unknown", opt->stop_rule);
-    if (opt->operator_form < TNSLQ_OPERATOR_AUTO || opt->operator_form > TNSLQ_OPERATOR_EXPLICIT)
+    if (opt->operator_form < TNSLQ_OPERATOR_AUTO || opt->operator_form > TNSLQ_OPERATOR_LAZY_TWO_PASS)
         return fail(TNSLQ_E_ARG, "operator_form %d unknown", opt->operator_form);
     if (opt->max_probes < 0) return fail(TNSLQ_E_ARG, "max_probes must be >= 0");
     if (opt->chunk_probes < 0) return fail(TNSLQ_E_ARG, "chunk_probes must be >= 0");
@@ -1331,7 +1357,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     res->steps_done = r.jdone;
     res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
     res->swapped_ab = pl.swapped;
-    res->streamed = pl.stream;
+    res->streamed = pl.stream ? (pl.fused ? 2 : 1) : 0;
     res->explicit_operator = pl.expl;
     res->n_probes_used = pl.K;
     res->n_matvecs = r.jdone;
@@ -1623,8 +1649,9 @@ int ptmatvec_run(Ctx &c, const void *psi_dev, const void *X_dev, void *Y_dev, vo
     if (pl.stream) {
         TNSLQ_HIP(launch_load_vectors_plain((const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xs, c.st));
         if ((rc = stream_contract(c, c.Xs, nullptr, nullptr))) return rc;
-        TNSLQ_HIP(launch_reduce_partials(1, c.Ym, 1, (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped,
-                                         (double2 *)Y_dev, c.st));
+        TNSLQ_HIP(launch_reduce_partials(1, pl.fused ? c.Ypart : (const void *)c.Ym, pl.fused ? pl.S : 1,
+                                         (int64_t)pl.K * pl.dAB, pl.dA, pl.dB, pl.K, pl.swapped, (double2 *)Y_dev,
+                                         c.st));
         return TNSLQ_OK;
     }
     TNSLQ_HIP(launch_load_vectors(pl.prec, (const double2 *)X_dev, pl.dA, pl.dB, pl.K, pl.swapped, c.Xt, c.pl.nst1, c.st));
@@ -1782,7 +1809,7 @@ int run_probe_loop(Run &r, const tnslq_options *opt, tnslq_result *res, double *
     res->steps_done = jmax;
     res->steps_min = steps_min;
     res->swapped_ab = pl.swapped;
-    res->streamed = pl.stream;
+    res->streamed = pl.stream ? (pl.fused ? 2 : 1) : 0;
     res->explicit_operator = pl.expl;
     res->n_probes_used = (int)Gall.size();
     res->n_matvecs = nmv;

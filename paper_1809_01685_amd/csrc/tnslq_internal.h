@@ -50,6 +50,8 @@ struct Plan {
     int S1 = 1;                      // split-K factor of the first contraction
     int stream = 0;                  // contractions as two streaming passes over psi (K d_B <= 8)
     int S1s = 1, S2s = 1;            // row splits of the two streaming passes
+    int fused = 0;                   // streaming regime in one read of psi (fused.hip)
+    int two_pass = 0;                // caller asked for the two-pass streaming form
     int expl = 0;                    // rho^{T_B} formed explicitly (intermediary (iii))
     int64_t nst_rho = 1;             // bricks along the reduction index of the explicit matvec
     int64_t nst_e = 1;               // bricks along E of the forming product
@@ -197,6 +199,16 @@ hipError_t launch_sum_transpose_y(const double2 *Yt, int S, int K, int64_t dA, i
 // Caller vectors into FP64 layout order Xs[k][a dB + b].
 hipError_t launch_load_vectors_plain(const double2 *X, int64_t dA, int64_t dB, int K, int swapped, double2 *Xs,
                                      hipStream_t st);
+
+// ------------------------------------------------------------ one-read streaming matvec
+// Both contractions over psi regrouped as P[c][a][b] (complex64, E slowest)
+// for vectors X[k][a d_B + b] (FP64): nblk partial sums Ypart[s][k][a d_B + b],
+// s < nblk, each over a contiguous range of the d_E slabs.  Shapes: d_B = 2,
+// K = 1, d_A = 2048 or 4096.
+constexpr int FUSED_BLOCKS = 256;
+bool pt_fused_supported(int dtype, int64_t dA, int64_t dB, int K, int64_t dE);
+hipError_t launch_pt_fused(const void *P, const double2 *X, int64_t dA, int64_t dB, int K, int64_t dE, int nblk,
+                           double2 *Ypart, hipStream_t st);
 
 // ------------------------------------------------------------ MPS blocks
 // Small FP64 complex linear algebra for the matrix-product-state reduction

@@ -18,10 +18,11 @@
         per Lanczos step and the HBM throughput of the two streaming passes
         over psi that apply the reduced density matrix.
 
-    python -m paper_1809_01685_amd.experiments hbm_sweep
+    python -m paper_1809_01685_amd.experiments hbm_sweep [--cases 13:1:1,...]
         The HBM-bound end of the negativity: the 30-qubit Haar state with
-        A = 4-16 and |B| = 1, 2, 3 qubits (B = 17, 18, 19 ...), K = 1, 2, 4
-        probes, 10 Lanczos steps; time per block matvec against the minimum
+        A = 4.. (|A| = 10, 12, 13 qubits) and B the next 1-3 qubits, K = 1, 2, 4
+        probes, 10 Lanczos steps, in the one-read form where the shape has it
+        and in the two-pass form; time per block matvec against the minimum
         bytes (psi once, the probe block in and out) at 8 TB/s.
 
     python -m paper_1809_01685_amd.experiments operator_forms
@@ -187,7 +188,13 @@ def run_entropy30(n_steps=20, seed=0):
     return {"workload": "30-qubit Haar state c64, S = first n qubits", "rows": rows}
 
 
-def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3", b_qubits=(1, 2, 3), probes=(1, 2, 4)):
+def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3",
+                  cases=((13, 1, 1), (13, 1, 2), (13, 1, 4), (13, 2, 1), (13, 2, 2), (13, 3, 1),
+                         (13, 2, 4), (13, 3, 2), (13, 3, 4), (12, 1, 1), (12, 1, 2), (11, 1, 1), (10, 1, 1)),
+                  forms=("lazy", "lazy_two_pass")):
+    """(|A|, |B|, K) cases on the 30-qubit state, A = 4.., B right after A;
+    each in the one-read form where the shape has it (operator "lazy") and in
+    the two-pass form."""
     import torch
     import tnslq_inputs as ti
     dev = torch.device("cuda:0")
@@ -195,26 +202,30 @@ def run_hbm_sweep(n_steps=10, seed=0, precision="bf16x3", b_qubits=(1, 2, 3), pr
     psi = ti.haar_state_torch(L, seed, dev, torch.complex64)
     D = 1 << L
     rows = []
-    a = list(range(4, 17))
-    for nb in b_qubits:
-        b = list(range(17, 17 + nb))
-        for K in probes:
-            tnslq_logneg(psi, L, a, b, K, 2, precision=precision, seed=seed, want_arrays=False)   # warm-up
-            r = tnslq_logneg(psi, L, a, b, K, n_steps, precision=precision, seed=seed, want_arrays=False)
-            d_ab = 1 << (len(a) + nb)
+    for na, nb, K in cases:
+        a = list(range(4, 4 + na))
+        b = list(range(4 + na, 4 + na + nb))
+        for form in forms:
+            tnslq_logneg(psi, L, a, b, K, 2, precision=precision, seed=seed, want_arrays=False, operator=form)
+            r = tnslq_logneg(psi, L, a, b, K, n_steps, precision=precision, seed=seed, want_arrays=False,
+                             operator=form)
+            d_ab = 1 << (na + nb)
             ms = r["t_matvec_ms"] / r["steps_done"]
             min_bytes = 8 * D + 2 * 8 * d_ab * K
-            rows.append({"b_qubits": nb, "probes": K, "streamed": bool(r["streamed"]), "logneg": r["logneg"],
-                         "logneg_se": None if K == 1 else r["logneg_se"], "matvec_ms": ms, "min_bytes": min_bytes,
+            rows.append({"a_qubits": na, "b_qubits": nb, "probes": K, "operator": form,
+                         "path": {0: "split-BF16 MFMA", 1: "two passes", 2: "one read"}[r["streamed"]],
+                         "logneg": r["logneg"], "logneg_se": None if K == 1 else r["logneg_se"],
+                         "matvec_ms": ms, "min_bytes": min_bytes,
                          "algorithmic_GBps": min_bytes / (ms * 1e-3) / 1e9,
-                         "frac_of_8TBps": min_bytes / (ms * 1e-3) / 8e12,
-                         "two_pass_frac_of_8TBps": 2 * 8 * D / (ms * 1e-3) / 8e12 if r["streamed"] else None})
-            print(f"[hbm_sweep] |B| = {nb}, K = {K}: {'stream' if r['streamed'] else 'mfma'} {ms:.3f} ms per matvec, "
+                         "frac_of_8TBps": min_bytes / (ms * 1e-3) / 8e12})
+            print(f"[hbm_sweep] |A| = {na}, |B| = {nb}, K = {K}, {form}: {rows[-1]['path']} {ms:.3f} ms per matvec, "
                   f"{rows[-1]['algorithmic_GBps']:.0f} GB/s of minimum bytes, E = {r['logneg']:.4f}",
                   file=sys.stderr, flush=True)
+            if not r["streamed"]:
+                break
     del psi
     torch.cuda.empty_cache()
-    return {"workload": "30-qubit Haar state c64, A = 4-16, B = 17.. (1-3 qubits)", "precision": precision,
+    return {"workload": "30-qubit Haar state c64, A = 4.. (|A| qubits), B the next |B| qubits", "precision": precision,
             "steps": n_steps, "rows": rows}
 
 
@@ -441,8 +452,8 @@ def main(argv=None):
     sc.add_argument("--precision", default="bf16x3")
     sub.add_parser("heldout26")
     hs = sub.add_parser("hbm_sweep")
-    hs.add_argument("--b-qubits", default="1,2,3")
-    hs.add_argument("--probes", default="1,2,4")
+    hs.add_argument("--cases", default="", help="comma list of |A|:|B|:K (default: the whole sweep)")
+    hs.add_argument("--forms", default="lazy,lazy_two_pass")
     hs.add_argument("--steps", type=int, default=10)
     sub.add_parser("operator_forms")
     sub.add_parser("hbm_peak")
@@ -467,7 +478,10 @@ def main(argv=None):
     elif args.cmd == "operator_forms":
         out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
-        out = run_hbm_sweep(n_steps=args.steps, b_qubits=_parse_range(args.b_qubits), probes=_parse_range(args.probes))
+        kw = {"forms": tuple(f for f in args.forms.split(",") if f)}
+        if args.cases:
+            kw["cases"] = tuple(tuple(int(x) for x in c.split(":")) for c in args.cases.split(","))
+        out = run_hbm_sweep(n_steps=args.steps, **kw)
     elif args.cmd == "entropy30":
         out = run_entropy30(n_steps=args.steps)
     else:

@@ -236,6 +236,6 @@ def test_streaming_passes_match_oracle(dev, a, b, dtype):
     for K in (2, 4):
         g = T.tnslq_logneg(psi_t, L, a, b, K, 10, precision="bf16x3", seed=4, operator="lazy")
         o = slq.slq_logneg(psi_np, L, a, b, K, 10, seed=4)
-        assert g["streamed"] == 1
+        assert g["streamed"] == 1       # d_A = 1024: the two passes
         assert np.max(np.abs(g["alpha"] - o["alpha"])) <= 1e-10 * np.max(np.abs(o["alpha"]))
         assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-10 * max(abs(o["logneg"]), 1.0))

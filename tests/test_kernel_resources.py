@@ -91,3 +91,26 @@ def test_quadrature_and_fit_use_no_scratch(tmp_path):
     assert len(quad) == 1 and len(fit) == 1, usage
     assert usage[quad[0]] == 0 and usage[fit[0]] == 0
     assert 0 < lds[quad[0]] <= 160 * 1024
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+def test_one_read_kernel_keeps_partial_y_in_registers(tmp_path):
+    # the one-read matvec holds its rows of the partial Y and of the probe in
+    # registers across every slab it streams; a spill would put them in
+    # per-lane scratch memory, i.e. back in HBM
+    from paper_1809_01685_amd import build as b
+    cmd = [_hipcc(), *[f for f in b.FLAGS if f != "-fPIC"], "--cuda-device-only", "-c",
+           "-Rpass-analysis=kernel-resource-usage", os.path.join(CSRC, "fused.hip"), "-o", str(tmp_path / "f.o")]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    usage, name = {}, None
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name:
+            usage[name] = int(m.group(1))
+    fused = {k: v for k, v in usage.items() if "k_pt_fused" in k}
+    assert len(fused) == 2, usage
+    assert all(v == 0 for v in fused.values()), fused
