@@ -19,16 +19,15 @@
 // plane: 32 BF16, 16 FP32 or 8 FP64 reduction terms) in LDS: thread t copies
 // bytes [16 t, 16 t + 16) of every plane, so each load instruction of the
 // block reads 8 KiB of contiguous memory and lands at the same offset in LDS.
-// Double buffered, one barrier per step.  For BF16 the copy goes straight
-// from global memory into LDS (global_load_lds_dwordx4: 16 bytes per lane,
-// each wave 1 KiB of every plane tile): while the waves multiply step i out
-// of one buffer, step i+1 is copied into the other, issued after the step's
-// fragment reads and waited for before the barrier.  Against staging through
-// registers this frees the staging registers and the LDS write instructions
-// (about 2% faster on both contractions).  FP32 and FP64 stage through
+// Double buffered, one barrier per step.  For BF16 (k_cgemm_bf16x3_ra) the
+// copy goes straight from global memory into LDS (global_load_lds_dwordx4:
+// 16 bytes per lane, each wave 1 KiB of every plane tile), and a wave reads
+// the next step's fragments while its matrix instructions run on the current
+// ones; see the comment at that kernel.  FP32 and FP64 stage through
 // registers: step i+1 (loaded one step earlier) is written to the other
-// buffer and step i+2 is loaded into registers.  Bricks store the four 16-byte units of a row XOR-swizzled
-// by ((row >> 1) ^ (row >> 2)) & 3, so the fragment reads of 8 or 16
+// buffer and step i+2 is loaded into registers.  Bricks store the four
+// 16-byte units of a row XOR-swizzled by ((row >> 1) ^ (row >> 2)) & 3, so
+// the fragment reads of 8 or 16
 // consecutive rows hit distinct banks.  Rows past the edge of C come from the
 // bricks' row padding and their results are dropped; the reduction padding
 // holds zeros.  Each lane's 16-byte fragment
@@ -42,6 +41,8 @@
 // cover a compact 4 x 8 patch of tiles and share their A and B tiles in that
 // XCD's L2.
 #include "operands.h"
+
+#include <type_traits>
 
 namespace tnslq {
 namespace {
@@ -107,38 +108,8 @@ template <int PREC>
 __device__ __forceinline__ void stage_mfma(const uint4 (&fa)[TM][MP<PREC>::NPL], const uint4 (&fb)[TN][MP<PREC>::NPL],
                                            typename MP<PREC>::acc (&accr)[TM][TN],
                                            typename MP<PREC>::acc (&acci)[TM][TN]) {
-    if constexpr (PREC == TNSLQ_BF16X3) {
-        uint4 nai[TM][2];
-#pragma unroll
-        for (int x = 0; x < TM; ++x) {
-            nai[x][0] = neg_bf16x8(fa[x][2]);
-            nai[x][1] = neg_bf16x8(fa[x][3]);
-        }
-        // split terms (p, q) in {(hi,hi), (hi,lo), (lo,hi)}
-#pragma unroll
-        for (int term = 0; term < 3; ++term) {
-            const int p = term == 2 ? 1 : 0;
-            const int q = term == 1 ? 1 : 0;
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b) {
-                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]), as_bf16x8(fb[b][q]),
-                                                                          accr[a][b], 0, 0, 0);
-                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]),
-                                                                          as_bf16x8(fb[b][2 + q]), acci[a][b], 0, 0, 0);
-                }
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b) {
-                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(nai[a][p]),
-                                                                          as_bf16x8(fb[b][2 + q]), accr[a][b], 0, 0, 0);
-                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][2 + p]),
-                                                                          as_bf16x8(fb[b][q]), acci[a][b], 0, 0, 0);
-                }
-        }
-    } else if constexpr (PREC == TNSLQ_FP32) {
+    static_assert(PREC != TNSLQ_BF16X3, "split BF16 runs in k_cgemm_bf16x3_ra");
+    if constexpr (PREC == TNSLQ_FP32) {
         uint4 nai[TM];
 #pragma unroll
         for (int x = 0; x < TM; ++x) nai[x] = neg_f32x4(fa[x][1]);
@@ -239,57 +210,6 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
     zero();
 
     const int frow = lane & 15, fk = lane >> 4;   // fragment row within a 16-row tile, k-unit
-    if constexpr (PREC == TNSLQ_BF16X3) {
-        typedef __attribute__((address_space(3))) void lds_void;
-        typedef __attribute__((address_space(1))) const void gbl_void;
-        const int wofs = 1024 * wid;   // this wave's 1 KiB of every plane tile
-        auto dma = [&](int64_t st, int buf) __attribute__((always_inline)) {
-            const char *pa = ga + st * BRICKB, *pb = gb + st * BRICKB;
-            char *As = lds + buf * STAGEB + wofs, *Bs = As + NPL * TILEB;
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                __builtin_amdgcn_global_load_lds((gbl_void *)(pa + p * TILEB), (lds_void *)(As + p * TILEB), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((gbl_void *)(pb + p * TILEB), (lds_void *)(Bs + p * TILEB), 16, 0, 0);
-            }
-        };
-        dma(sbeg, 0);
-        __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0): this wave's copies have landed
-        __syncthreads();
-        int buf = 0;
-        for (int64_t st = sbeg; st < send; ++st, buf ^= 1) {
-            const char *As = lds + buf * STAGEB, *Bs = As + NPL * TILEB;
-            uint4 fa[TM][NPL], fb[TN][NPL];
-#pragma unroll
-            for (int x = 0; x < TM; ++x) {
-                const int oa = loff(wm * TM * 16 + x * 16 + frow, fk);
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) fa[x][p] = *(const uint4 *)(As + p * TILEB + oa);
-            }
-#pragma unroll
-            for (int x = 0; x < TN; ++x) {
-                const int ob = loff(wn * TN * 16 + x * 16 + frow, fk);
-#pragma unroll
-                for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * TILEB + ob);
-            }
-            // every fragment read of the stage is issued before the copy into
-            // the other buffer (the wait counters do not tell buffers apart)
-            __builtin_amdgcn_sched_barrier(0);
-            dma(st + 1 < send ? st + 1 : send - 1, buf ^ 1);
-            __builtin_amdgcn_sched_barrier(0);
-            stage_mfma<PREC>(fa, fb, accr, acci);
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_waitcnt(0x0f70);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b) {
-                outr[a][b] = accr[a][b];
-                outi[a][b] = acci[a][b];
-            }
-        return;
-    }
     gload(sbeg);
     lstore(0);
     if (sbeg + 1 < send) gload(sbeg + 1);
@@ -338,52 +258,50 @@ __device__ __forceinline__ void mainloop(const GemmDesc &g, char *lds, int64_t i
     }
 }
 
-template <int PREC>
-__global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
-    using Acc = typename MP<PREC>::acc;
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int wm = wid / WAVES_N, wn = wid % WAVES_N;
-
+// Output tile (i0, j0) and reduction split s of block blockIdx.x: the
+// hardware deals blocks to the XCDs round robin, so block b is renumbered to
+// give XCD b % 8 a contiguous range, walked in groups of GROUP_M tile rows.
+struct TileAt {
+    int64_t i0, j0, sbeg, send;
+    int s;
+};
+__device__ inline TileAt tile_of(const GemmDesc &g) {
     const int64_t ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
     const int64_t per_split = ntm * ntn;
     int64_t bid = blockIdx.x;
     if (gridDim.x % 8 == 0) bid = (bid % 8) * (gridDim.x / 8) + bid / 8;
-    const int s = (int)(bid / per_split);
+    TileAt r;
+    r.s = (int)(bid / per_split);
     const int64_t t = bid % per_split;
     const int64_t group = t / (GROUP_M * ntn);
     const int64_t first_m = group * GROUP_M;
     const int64_t gsize = (ntm - first_m) < GROUP_M ? (ntm - first_m) : GROUP_M;
-    const int64_t tm = first_m + (t % (GROUP_M * ntn)) % gsize;
-    const int64_t tn = (t % (GROUP_M * ntn)) / gsize;
-    const int64_t i0 = tm * BM, j0 = tn * BN;
-
+    r.i0 = (first_m + (t % (GROUP_M * ntn)) % gsize) * BM;
+    r.j0 = ((t % (GROUP_M * ntn)) / gsize) * BN;
     const int64_t per = g.nst / g.S;
-    const int64_t sbeg = (int64_t)s * per, send = sbeg + per;
+    r.sbeg = (int64_t)r.s * per;
+    r.send = r.sbeg + per;
+    return r;
+}
 
-    Acc accr[TM][TN], acci[TM][TN];
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-            accr[a][b] = Acc{0, 0, 0, 0};
-            acci[a][b] = Acc{0, 0, 0, 0};
-        }
-    mainloop<PREC>(g, lds, i0, j0, sbeg, send, accr, acci);
-
-    // epilogue: output register r of lane l holds column l % 16 and row
-    // 4 * (l / 16) + r (FP32 accumulators) or row 4 * r + l / 16 (FP64)
+// Epilogue of a wave's WTM x WTN tiles of 16 x 16 whose first output row and
+// column are (wi0, wj0): output register r of lane l holds column l % 16 and
+// row 4 (l / 16) + r (FP32 accumulators) or row 4 r + l / 16 (FP64).
+template <int PREC, int WTM, int WTN>
+__device__ __forceinline__ void store_tiles(const GemmDesc &g, int s, int64_t wi0, int64_t wj0, int lane,
+                                            const typename MP<PREC>::acc (&accr)[WTM][WTN],
+                                            const typename MP<PREC>::acc (&acci)[WTM][WTN]) {
     const int frow = lane & 15, fk = lane >> 4;
     const int64_t cnb_mask = ((int64_t)1 << g.cnb_log2) - 1, cni_mask = ((int64_t)1 << g.cni_log2) - 1;
 #pragma unroll
-    for (int a = 0; a < TM; ++a)
+    for (int a = 0; a < WTM; ++a)
 #pragma unroll
-        for (int b = 0; b < TN; ++b)
+        for (int b = 0; b < WTN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int orow = PREC == TNSLQ_FP64 ? 4 * r + fk : 4 * fk + r;
-                const int64_t i = i0 + wm * TM * 16 + a * 16 + orow;
-                const int64_t j = j0 + wn * TN * 16 + b * 16 + frow;
+                const int64_t i = wi0 + a * 16 + orow;
+                const int64_t j = wj0 + b * 16 + frow;
                 if (i >= g.M || j >= g.N) continue;
                 const int64_t jq = j >> g.cnb_log2, jr = j & cnb_mask;
                 const auto vr = accr[a][b][r], vi = acci[a][b][r];
@@ -406,18 +324,194 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
 }
 
 template <int PREC>
-hipError_t launch(const GemmDesc &g, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_cgemm_nt_mfma<PREC>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
-        if (e != hipSuccess) return e;
-        attr_set = true;
+__global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
+    using Acc = typename MP<PREC>::acc;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wm = wid / WAVES_N, wn = wid % WAVES_N;
+    const TileAt tl = tile_of(g);
+
+    Acc accr[TM][TN], acci[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            accr[a][b] = Acc{0, 0, 0, 0};
+            acci[a][b] = Acc{0, 0, 0, 0};
+        }
+    mainloop<PREC>(g, lds, tl.i0, tl.j0, tl.sbeg, tl.send, accr, acci);
+    store_tiles<PREC, TM, TN>(g, tl.s, tl.i0 + wm * TM * 16, tl.j0 + wn * TN * 16, lane, accr, acci);
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3: the same block, waves and LDS stages as k_cgemm_nt_mfma, with the
+// next stage's fragments read while the current stage's matrix instructions
+// run.  B's fragments (32 registers per stage) are kept in two sets; A's are
+// read one row of tiles at a time, each into the registers that row has just
+// released, so that a wave waits for LDS only for A's last row.  The copy of
+// the stage after next goes into the LDS buffer the current stage has left,
+// right after the barrier that ends the previous stage; one barrier per
+// stage, after which every wave's copy has landed and every wave holds its
+// fragments.  The LDS buffers are four arrays (A and B of two stages), so
+// that the compiler can tell a fragment read of one buffer from a copy into
+// the other and does not make the read wait for the copy.  Reading ahead
+// keeps the matrix cores 70-77% busy on the 30-qubit contractions, 2-3
+// points more than reading each stage's fragments before its instructions;
+// the clock, held by the chip's power limit, gives back most of that.
+
+// the 24 matrix instructions of one row of tiles: A's fragment (re_hi,
+// re_lo, im_hi, im_lo) against the TN B fragments.  Each accumulator takes,
+// for the split terms (hi, hi), (hi, lo), (lo, hi) in turn, Re A Re B then
+// (-Im A) Im B (real part), or Re A Im B then Im A Re B (imaginary part).
+__device__ __forceinline__ void row_bf16x3(const uint4 (&fa)[4], const uint4 (&fb)[TN][4], f32x4 (&ar)[TN],
+                                           f32x4 (&ai)[TN]) {
+    const uint4 n0 = neg_bf16x8(fa[2]), n1 = neg_bf16x8(fa[3]);
+#pragma unroll
+    for (int term = 0; term < 3; ++term) {
+        const int p = term == 2 ? 1 : 0;
+        const int q = term == 1 ? 1 : 0;
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            ar[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[p]), as_bf16x8(fb[b][q]), ar[b], 0, 0, 0);
+            ai[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[p]), as_bf16x8(fb[b][2 + q]), ai[b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            ar[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(p ? n1 : n0), as_bf16x8(fb[b][2 + q]), ar[b], 0,
+                                                            0, 0);
+            ai[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[2 + p]), as_bf16x8(fb[b][q]), ai[b], 0, 0, 0);
+        }
     }
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+__global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3_ra(GemmDesc g) {
+    constexpr int NPL = 4;
+    constexpr int BRICKB = NPL * TILEB;   // one brick, all planes: 32 KiB
+    __shared__ __attribute__((aligned(16))) char ldsA0[BRICKB], ldsA1[BRICKB], ldsB0[BRICKB], ldsB1[BRICKB];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WAVES_N, wn = wid % WAVES_N;
+    const TileAt tl = tile_of(g);
+    const int64_t sbeg = tl.sbeg, send = tl.send;
+
+    // thread t copies bytes [16 t, 16 t + 16) of every plane tile; each
+    // wave's load fills 1 KiB of LDS at the same offset.  Block-uniform
+    // bases (scalar registers) plus one per-lane offset.
+    const size_t blk = brick_block_bytes(TNSLQ_BF16X3, g.nst);
+    const char *gA = (const char *)g.A + (size_t)(tl.i0 / BM) * blk;
+    const char *gB = (const char *)g.B + (size_t)(tl.j0 / BN) * blk;
+    const uint32_t toff = 16u * (uint32_t)tid;
+    const int wofs = 1024 * __builtin_amdgcn_readfirstlane(wid);
+    auto dma = [&](int64_t st, int buf) __attribute__((always_inline)) {
+        const char *pa = gA + st * BRICKB, *pb = gB + st * BRICKB;
+        char *As = (buf ? ldsA1 : ldsA0) + wofs, *Bs = (buf ? ldsB1 : ldsB0) + wofs;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            __builtin_amdgcn_global_load_lds((gbl_void_t *)(pa + p * TILEB + toff), (lds_void_t *)(As + p * TILEB), 16,
+                                             0, 0);
+            __builtin_amdgcn_global_load_lds((gbl_void_t *)(pb + p * TILEB + toff), (lds_void_t *)(Bs + p * TILEB), 16,
+                                             0, 0);
+        }
+    };
+    const int frow = lane & 15, fk = lane >> 4;
+    int oa[TM], ob[TN];
+#pragma unroll
+    for (int x = 0; x < TM; ++x) oa[x] = loff(wm * TM * 16 + x * 16 + frow, fk);
+#pragma unroll
+    for (int x = 0; x < TN; ++x) ob[x] = loff(wn * TN * 16 + x * 16 + frow, fk);
+    auto read_a = [&](int buf, int x, uint4 (&f)[NPL]) __attribute__((always_inline)) {
+        const char *As = (buf ? ldsA1 : ldsA0) + oa[x];
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) f[p] = *(const uint4 *)(As + p * TILEB);
+    };
+    auto read_b = [&](int buf, uint4 (&f)[TN][NPL]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int x = 0; x < TN; ++x) {
+            const char *Bs = (buf ? ldsB1 : ldsB0) + ob[x];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) f[x][p] = *(const uint4 *)(Bs + p * TILEB);
+        }
+    };
+
+    f32x4 accr[TM][TN], acci[TM][TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            accr[a][b] = f32x4{0, 0, 0, 0};
+            acci[a][b] = f32x4{0, 0, 0, 0};
+        }
+    uint4 fa[2][TM][NPL], fb[2][TN][NPL];
+
+    // stages sbeg and sbeg + 1 into the two buffers, stage sbeg's fragments
+    // into registers
+    const int64_t last = send - 1;
+    dma(sbeg, 0);
+    dma(sbeg + 1 <= last ? sbeg + 1 : last, 1);
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+    __syncthreads();
+    read_b(0, fb[0]);
+#pragma unroll
+    for (int x = 0; x < TM; ++x) read_a(0, x, fa[0][x]);
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): buffer 0 may be refilled
+    __syncthreads();
+
+    // stage st (its fragments in set C, its operands in buffer C): stage
+    // st + 1's fragments from buffer C ^ 1 into set C ^ 1, stage st + 2's
+    // operands into buffer C (the last stage again at the end of the run)
+    auto body = [&](auto cc, int64_t st) __attribute__((always_inline)) {
+        constexpr int C = decltype(cc)::value, N = C ^ 1;
+        read_b(N, fb[N]);
+        __builtin_amdgcn_sched_barrier(0);
+        dma(st + 2 <= last ? st + 2 : last, C);
+        __builtin_amdgcn_sched_barrier(0);
+        // A's row a of the next stage into the registers row a has just
+        // released
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+            row_bf16x3(fa[C][a], fb[C], accr[a], acci[a]);
+            __builtin_amdgcn_sched_barrier(0);
+            read_a(N, a, fa[N][a]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) and lgkmcnt(0)
+        __syncthreads();
+    };
+    int64_t st = sbeg;
+    for (; st + 1 < send; st += 2) {
+        body(std::integral_constant<int, 0>{}, st);
+        body(std::integral_constant<int, 1>{}, st + 1);
+    }
+    if (st < send) body(std::integral_constant<int, 0>{}, st);
+    store_tiles<TNSLQ_BF16X3, TM, TN>(g, tl.s, tl.i0 + wm * TM * 16, tl.j0 + wn * TN * 16, lane, accr, acci);
+}
+
+hipError_t launch_bf16x3_ra(const GemmDesc &g, hipStream_t st) {
     const int64_t nblocks = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.S;
     if (nblocks < 1 || nblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_cgemm_nt_mfma<PREC>, dim3((unsigned)nblocks), dim3(NT), lds_bytes<PREC>(), st, g);
+    hipLaunchKernelGGL(k_cgemm_bf16x3_ra, dim3((unsigned)nblocks), dim3(NT), 0, st, g);
     return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch(const GemmDesc &g, hipStream_t st) {
+    if constexpr (PREC == TNSLQ_BF16X3) {
+        return launch_bf16x3_ra(g, st);
+    } else {
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_cgemm_nt_mfma<PREC>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        const int64_t nblocks = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.S;
+        if (nblocks < 1 || nblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(k_cgemm_nt_mfma<PREC>, dim3((unsigned)nblocks), dim3(NT), lds_bytes<PREC>(), st, g);
+        return hipGetLastError();
+    }
 }
 
 template <int PREC>
