@@ -161,7 +161,10 @@ typedef struct {
  *                with SE the Hutchinson error of the mean T and eps_L the mean
  *                of ||phi_n||^2 sigma_n.  The result is the fitted estimate,
  *                also with stop_tol = 0 (then after n_steps steps, which must
- *                be > TNSLQ_FIT_MIN_POINTS).
+ *                be > TNSLQ_FIT_MIN_POINTS).  With stop_tol > 0 and no step
+ *                meeting the target, the result is the plain estimate of the
+ *                last step (G_n = ||phi_n||^2 F_{n_steps},n), lanczos_err the
+ *                fit's eps_L / (T ln 2) at that step.
  *   operator_form
  *                how rho^{T_B} is applied (TNSLQ_OPERATOR_*, above).
  *   max_probes   0 or <= n_probes: one block of n_probes probes, as above.
@@ -207,7 +210,8 @@ typedef struct {
     double logneg;          /* log2 of the mean of G_n                        */
     double logneg_se;       /* trace_norm_se / (trace_norm ln 2); NaN if N = 1 */
     double trace_norm;      /* mean of G_n = ||phi_n||^2 F_{m} (TNSLQ_STOP_FIT:
-                               ||phi_n||^2 F_inf,n)                           */
+                               ||phi_n||^2 F_inf,n, unless a target was set and
+                               never met)                                     */
     double trace_norm_se;   /* sqrt(Var(G) / N), sample variance (N - 1)       */
     int steps_done;         /* Lanczos steps run on the probe block            */
     int steps_min;          /* fewest steps of any probe (breakdown stops one) */
@@ -524,6 +528,9 @@ int tnslq_probes(uint64_t seed, uint64_t probe_offset, int n_probes, int64_t d, 
  * features and the identity for the three log2 sizes.  Output row = (u0, u1):
  * predicted residual mean and log variance. */
 #define TNSLQ_MLP_NIN 19
+/* Lanczos steps the surrogate may read before deciding. */
+#define TNSLQ_SURROGATE_MIN_EARLY 4
+#define TNSLQ_SURROGATE_MAX_EARLY 8
 #define TNSLQ_MLP_NHID 256
 #define TNSLQ_MLP_NOUT 2
 #define TNSLQ_MLP_NPARAMS 71426
@@ -561,13 +568,17 @@ int tnslq_mlp_train(float *params_dev, float *m_dev, float *v_dev, const float *
                     size_t ws_bytes, void *stream);
 
 /* Early-stopping surrogate run.  Runs `early_steps` Lanczos steps of
- * tnslq_logneg, forms the 19 features (probe means of d_A d_B alpha_1..8 and
- * d_A d_B beta_2..9, then log2 d_A, log2 d_B, log2 d_E), and evaluates the
- * network: mu = E_early + y_scale * u0, sigma = y_scale * exp(u1 / 2), with
- * E_early the SLQ estimate from T_{early_steps}.  If sigma <= tol *
- * max(|mu|, 1) the result is (mu, sigma); otherwise the same Lanczos state
- * continues to opt->n_steps (the fallback) and the result is full SLQ's.
- *   early_steps  8 (the network's input width fixes it).
+ * tnslq_logneg, forms the 19 features (slots 0..7: probe means of d_A d_B
+ * alpha_1..early_steps; slots 8..15: probe means of d_A d_B
+ * beta_2..early_steps+1; slots past early_steps hold zero; then log2 d_A,
+ * log2 d_B, log2 d_E), and evaluates the network: mu = E_early + y_scale *
+ * u0, sigma = y_scale * exp(u1 / 2), with E_early the SLQ estimate from
+ * T_{early_steps}.  If sigma <= tol * max(|mu|, 1) the result is (mu,
+ * sigma); otherwise the same Lanczos state continues to opt->n_steps (the
+ * fallback) and the result is full SLQ's.
+ *   early_steps  TNSLQ_SURROGATE_MIN_EARLY..TNSLQ_SURROGATE_MAX_EARLY, the
+ *                value the network was trained with (its checkpoint records
+ *                it).
  *   res          as tnslq_logneg; when the surrogate is accepted, logneg =
  *                mu and logneg_se = sigma.
  *   info_host    host, 5 doubles: mu, sigma, E_early, used_fallback (0/1),

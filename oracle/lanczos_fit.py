@@ -35,7 +35,13 @@ the readings taken here (each also listed in the design notes):
     error against long runs on 42% of a set of Haar states (the exponential
     extrapolation falls short of the limit on every one of them);
   * a probe whose Lanczos recurrence broke down at step s <= k is exact:
-    estimate F_s, uncertainty 0.
+    estimate F_s, uncertainty 0;
+  * a run with a target that no step up to the last one meets reports the
+    plain quadrature estimate of its last step (Algorithm 1's estimate
+    without the extrapolation), with the fit's Lanczos error at that step:
+    the fitted limit of a trajectory that has not settled can be several bits
+    off where the plain estimate is not (brickwork states with many small
+    eigenvalues of rho^{T_B}).
 
 Fitting method (the definition is the least-squares optimum; this is how it
 is found): for fixed r the model is linear in (F_inf, a) and solved by linear
@@ -50,6 +56,7 @@ from typing import Dict
 import numpy as np
 import scipy.optimize
 
+from . import step_difference
 from .slq import BREAKDOWN_TOL
 
 FIT_WINDOW = 8
@@ -171,6 +178,23 @@ def fit_stop_step(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float
         if np.isfinite(s["logneg_err"]) and s["logneg_err"] <= tol * max(abs(s["logneg"]), 1.0):
             return k
     return m
+
+
+def fit_rule_result(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float) -> Dict[str, object]:
+    """What a run under the fit rule with target tol > 0 reports: the fitted
+    block estimate at the first step meeting the target, else the plain
+    estimate of the last step with the fit's Lanczos error there (in bits)."""
+    m = F.shape[1]
+    k = fit_stop_step(F, alpha, beta, tol)
+    st = fit_stats(F, alpha, beta, k)
+    lanczos_bits = st["lanczos_err"] / (st["trace_norm"] * np.log(2.0))
+    if np.isfinite(st["logneg_err"]) and st["logneg_err"] <= tol * max(abs(st["logneg"]), 1.0):
+        return {"step": k, "met": True, "logneg": st["logneg"], "trace_norm": st["trace_norm"],
+                "trace_norm_se": st["trace_norm_se"], "G": st["G"], "lanczos_err": lanczos_bits}
+    plain = step_difference.block_estimate(beta, F, m)
+    return {"step": m, "met": False, "logneg": plain["logneg"], "trace_norm": plain["trace_norm"],
+            "trace_norm_se": plain["trace_norm_se"], "G": np.asarray(beta)[:, 0] ** 2 * np.asarray(F)[:, m - 1],
+            "lanczos_err": lanczos_bits}
 
 
 def block_lanczos_stop_step(F: np.ndarray, alpha: np.ndarray, beta: np.ndarray, tol: float) -> int:

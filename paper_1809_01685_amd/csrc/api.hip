@@ -1219,6 +1219,8 @@ struct Run {
     int jdone = 0;
     int rule = TNSLQ_STOP_DIFF;
     double lanczos_err = 0.0;   // of the last stop check
+    bool target = false;        // the last run_steps had a target (stop_tol > 0)
+    bool met = false;           // and stopped because it was met
 };
 
 int run_start(Run &r, const tnslq_options *opt, const void *psi, void *ws, size_t ws_bytes, void *stream);
@@ -1279,6 +1281,8 @@ int fit_step(Run &r, int j, double *G) {
 // lanczos_only, on the Lanczos part of the error alone).
 int run_steps(Run &r, int jmax, double stop_tol, bool lanczos_only = false) {
     int rc;
+    r.target = stop_tol > 0.0;
+    r.met = false;
     for (int j = r.jdone + 1; j <= jmax; ++j) {
         roctxRangePush("tnslq lanczos step");
         rc = lanczos_step(r.c, j, &r.se[j]);
@@ -1293,7 +1297,10 @@ int run_steps(Run &r, int jmax, double stop_tol, bool lanczos_only = false) {
             TNSLQ_HIP(hipStreamSynchronize(r.c.st));
             // lanczos_only: the block's Lanczos error alone, eps_L / (T ln 2)
             const double err = lanczos_only ? o[2] / (o[0] * std::log(2.0)) : o[4];
-            if (std::isfinite(o[3]) && std::isfinite(err) && err <= stop_tol * std::max(std::fabs(o[3]), 1.0)) break;
+            if (std::isfinite(o[3]) && std::isfinite(err) && err <= stop_tol * std::max(std::fabs(o[3]), 1.0)) {
+                r.met = true;
+                break;
+            }
         } else if (r.rule == TNSLQ_STOP_DIFF && j >= 6) {
             if ((rc = quad_stats(r.c, j, j - 5, j, j - 5, nullptr))) return rc;
             TNSLQ_HIP(launch_stats(r.c.beta, r.c.F, r.c.pl.K, r.c.pl.m, j, nullptr, r.c.stats, r.c.st));
@@ -1306,7 +1313,10 @@ int run_steps(Run &r, int jmax, double stop_tol, bool lanczos_only = false) {
             const double e_now = s[6], de = s[7], e_old = s[2];
             const double dl = e_now - e_old;
             const double err = std::sqrt((std::isnan(de) ? 0.0 : de * de) + dl * dl);
-            if (std::isfinite(e_now) && err <= stop_tol * std::max(std::fabs(e_now), 1.0)) break;
+            if (std::isfinite(e_now) && err <= stop_tol * std::max(std::fabs(e_now), 1.0)) {
+                r.met = true;
+                break;
+            }
         }
     }
     return TNSLQ_OK;
@@ -1318,10 +1328,15 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     const Plan &pl = c.pl;
     int rc;
     const bool fit = r.rule == TNSLQ_STOP_FIT && r.jdone >= TNSLQ_FIT_MIN_POINTS + 1;
+    // A fit-rule run that had a target and ran out of steps without meeting
+    // it reports the plain estimate of its last step (the fitted limit of a
+    // trajectory that has not settled can be far off), with the fit's
+    // Lanczos error as the measure of how far it is from converged.
+    const bool plain = !fit || (r.target && !r.met);
     // quadrature of every step and the plain statistics of each step (G at the
     // last step unless the fit supplies it)
-    if ((rc = quad_stats(c, r.jdone, 1, r.jdone, r.jdone, fit ? nullptr : c.G))) return rc;
-    if (fit && (rc = fit_step(r, r.jdone, c.G))) return rc;
+    if ((rc = quad_stats(c, r.jdone, 1, r.jdone, r.jdone, plain ? c.G : nullptr))) return rc;
+    if (fit && (rc = fit_step(r, r.jdone, plain ? nullptr : c.G))) return rc;
     double s[4], o[6], e_old = std::nan("");
     TNSLQ_HIP(hipMemcpyAsync(s, c.stats + (size_t)(r.jdone - 1) * 4, sizeof s, hipMemcpyDeviceToHost, c.st));
     if (fit) TNSLQ_HIP(hipMemcpyAsync(o, c.fitout, sizeof o, hipMemcpyDeviceToHost, c.st));
@@ -1340,7 +1355,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     TNSLQ_HIP(hipStreamSynchronize(c.st));
     if (steps) std::copy(hsteps.begin(), hsteps.end(), steps);
     zero_result(res);
-    if (fit) {
+    if (!plain) {
         const double ln2 = std::log(2.0);
         res->trace_norm = o[0];
         res->trace_norm_se = pl.K > 1 ? o[1] : std::nan("");
@@ -1352,7 +1367,10 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
         res->trace_norm_se = s[1];
         res->logneg = s[2];
         res->logneg_se = s[3];
-        res->lanczos_err = r.jdone >= 6 ? std::fabs(s[2] - e_old) : std::nan("");
+        if (fit)
+            res->lanczos_err = o[2] / (o[0] * std::log(2.0));
+        else
+            res->lanczos_err = r.jdone >= 6 ? std::fabs(s[2] - e_old) : std::nan("");
     }
     res->steps_done = r.jdone;
     res->steps_min = *std::min_element(hsteps.begin(), hsteps.end());
@@ -2255,7 +2273,9 @@ int tnslq_logneg_surrogate(const void *psi_dev, int dtype, const tnslq_partition
     g_err.clear();
     if (!res || !info || !params || !norm) return fail(TNSLQ_E_ARG, "NULL pointer");
     if ((rc = check_options(opt))) return rc;
-    if (early_steps != 8) return fail(TNSLQ_E_ARG, "early_steps must be 8 (network input width)");
+    if (early_steps < TNSLQ_SURROGATE_MIN_EARLY || early_steps > TNSLQ_SURROGATE_MAX_EARLY)
+        return fail(TNSLQ_E_ARG, "early_steps %d outside [%d, %d]", early_steps, TNSLQ_SURROGATE_MIN_EARLY,
+                    TNSLQ_SURROGATE_MAX_EARLY);
     if (opt->max_probes > opt->n_probes) return fail(TNSLQ_E_ARG, "the surrogate runs one block of probes");
     if (opt->n_steps < early_steps) return fail(TNSLQ_E_ARG, "n_steps must be >= early_steps");
     if (!(tol > 0.0)) return fail(TNSLQ_E_ARG, "tol must be > 0");

@@ -583,20 +583,22 @@ __global__ void __launch_bounds__(256) k_fit_stats(const double *__restrict__ be
     }
 }
 
-// Surrogate inputs: probe means of dAB alpha_1..n_early and dAB beta_2..n_early+1,
-// then log2 dA, log2 dB, log2 dE.
+// Surrogate inputs: probe means of dAB alpha_1..n_early in slots 0..7 and of
+// dAB beta_2..n_early+1 in slots 8..15 (slots past n_early hold zero), then
+// log2 dA, log2 dB, log2 dE.
 __global__ void k_features(const double *__restrict__ alpha, const double *__restrict__ beta, int K, int m,
                            int n_early, double dAB, double dA, double dB, double dE, float *__restrict__ feat) {
     const int t = threadIdx.x;
-    if (t < 2 * n_early) {
-        const bool is_a = t < n_early;
-        const int i = is_a ? t : t - n_early;
+    if (t < 2 * TNSLQ_SURROGATE_MAX_EARLY) {
+        const bool is_a = t < TNSLQ_SURROGATE_MAX_EARLY;
+        const int i = is_a ? t : t - TNSLQ_SURROGATE_MAX_EARLY;
         double s = 0.0;
-        for (int k = 0; k < K; ++k)
-            s += is_a ? alpha[(int64_t)k * m + i] : beta[(int64_t)k * (m + 1) + i + 1];
+        if (i < n_early)
+            for (int k = 0; k < K; ++k)
+                s += is_a ? alpha[(int64_t)k * m + i] : beta[(int64_t)k * (m + 1) + i + 1];
         feat[t] = (float)(dAB * s / K);
-    } else if (t < 2 * n_early + 3) {
-        const int i = t - 2 * n_early;
+    } else if (t < 2 * TNSLQ_SURROGATE_MAX_EARLY + 3) {
+        const int i = t - 2 * TNSLQ_SURROGATE_MAX_EARLY;
         feat[t] = (float)log2(i == 0 ? dA : (i == 1 ? dB : dE));
     }
 }

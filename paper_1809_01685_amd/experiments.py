@@ -5,12 +5,16 @@
         B = 13-20, E = rest: logarithmic negativity against circuit depth
         (a seeded stand-in for the quench of Sec. VII.B).
 
-    python -m paper_1809_01685_amd.experiments heldout26
+    python -m paper_1809_01685_amd.experiments heldout26 [--models DIR,...]
         The early-stopping surrogate on 26-qubit rho_AB it never saw: the
         30-qubit Haar state (E = 0-3) and 28-qubit brickwork states (A = 1-13,
         B = 14-26, E = {0, 27}) at depths 4, 8, 12.  Each is judged against
-        50-step split-BF16 SLQ on the same probes; the +-1% adaptive stop is
-        read off the same run's trajectory.
+        50-step split-BF16 SLQ on the same probes, beside the +-1% stop of the
+        exponential-fit rule, with the time of each.
+
+    python -m paper_1809_01685_amd.experiments surrogate_latency [--model DIR]
+        The learned stop's inference latency: the network on one feature row,
+        and the whole decision inside the surrogate run on a 20-qubit state.
 
     python -m paper_1809_01685_amd.experiments entropy30
         Von Neumann entropy of the 30-qubit Haar state (complex64) for cuts of
@@ -68,7 +72,7 @@ import time
 
 import numpy as np
 
-from . import tnslq_logneg
+from . import MLP_NIN, tnslq_logneg
 
 
 def _trajectory(r):
@@ -108,12 +112,71 @@ def run_scrambling(depths, seed=0, n_probes=32, n_steps=40, precision="bf16x3"):
             "precision": precision, "rows": rows}
 
 
-def run_heldout26(n_probes=8, n_steps=50, precision="bf16x3", seed=0, tol=0.01):
+def run_surrogate_latency(reps=200, model_dir=None):
+    """Inference latency of the learned stop: the network on one feature row
+    (device time between events, and host time of a forward plus a
+    synchronisation), and the whole decision inside tnslq_logneg_surrogate
+    (features, network, read-back) as the difference against tnslq_logneg
+    running the same early steps, on a 20-qubit state."""
+    import torch
+    import tnslq_inputs as ti
+    from . import tnslq_mlp_forward
+    from .surrogate import Model, surrogate_logneg
+    dev = torch.device("cuda:0")
+    model = Model.load(model_dir) if model_dir else Model.load()
+    p, nd = model.device_tensors(dev)
+    x = torch.randn(1, MLP_NIN, dtype=torch.float32, device=dev)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
+    for _ in range(10):
+        tnslq_mlp_forward(p, nd, x, workspace=ws)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    dev_us, host_us = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(st)
+        tnslq_mlp_forward(p, nd, x, workspace=ws)
+        e1.record(st)
+        torch.cuda.synchronize()
+        host_us.append((time.perf_counter() - t0) * 1e6)
+        dev_us.append(e0.elapsed_time(e1) * 1e3)
+    L, a, b, K = 20, list(range(2, 11)), list(range(11, 20)), 8
+    psi = ti.haar_state_torch(L, 3, dev, torch.complex64)
+    n_early = model.feature_steps
+    t_plain, t_sur = [], []
+    for _ in range(12):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tnslq_logneg(psi, L, a, b, K, n_early, precision="bf16x3", seed=1, want_arrays=False)
+        t_plain.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        r = surrogate_logneg(model, psi, L, a, b, K, 40, tol=1e9, precision="bf16x3", seed=1)
+        t_sur.append(time.perf_counter() - t0)
+        assert not r["used_fallback"] and r["steps_done"] == n_early
+    t_plain, t_sur = np.median(t_plain[2:]), np.median(t_sur[2:])
+    out = {"n_early": n_early, "forward_device_us_median": float(np.median(dev_us)),
+           "forward_host_us_median": float(np.median(host_us)),
+           "decision_state": "20-qubit Haar, A = 2-10, B = 11-19, K = 8, split BF16",
+           "t_plain_early_steps_ms": 1e3 * float(t_plain), "t_surrogate_accepted_ms": 1e3 * float(t_sur),
+           "decision_overhead_ms": 1e3 * float(t_sur - t_plain)}
+    print(f"[surrogate_latency] forward {out['forward_device_us_median']:.1f} us on the device, "
+          f"{out['forward_host_us_median']:.1f} us with the synchronisation; decision overhead "
+          f"{out['decision_overhead_ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def run_heldout26(n_probes=8, n_steps=50, precision="bf16x3", seed=0, tol=0.01, models=None):
+    """The surrogate on rho_AB of 26 qubits it never saw, against the
+    exponential-fit stop at the same target and 50-step SLQ on the same
+    probes; `models` are checkpoint directories (default: the committed
+    one)."""
     import torch
     import tnslq_inputs as ti
     from .surrogate import Model, surrogate_logneg
     dev = torch.device("cuda:0")
-    model = Model.load()
+    models = models or [None]
+    loaded = [(m or "committed", Model.load(m) if m else Model.load()) for m in models]
     cases = [("haar30", 30, list(range(4, 17)), list(range(17, 30)), "haar", 0)]
     for depth in (4, 8, 12):
         cases.append((f"brick28_d{depth}", 28, list(range(1, 14)), list(range(14, 27)), "brickwork", depth))
@@ -125,25 +188,32 @@ def run_heldout26(n_probes=8, n_steps=50, precision="bf16x3", seed=0, tol=0.01):
             psi = ti.brickwork_state_torch(L, depth, seed, dev, torch.complex64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        full = tnslq_logneg(psi, L, a, b, n_probes, n_steps, precision=precision, seed=seed)
+        full = tnslq_logneg(psi, L, a, b, n_probes, n_steps, precision=precision, seed=seed, want_arrays=False)
         t_full = time.perf_counter() - t0
-        E, dE = _trajectory(full)
-        j_stop = _adaptive_stop(E, dE, tol)
-        t0 = time.perf_counter()
-        s = surrogate_logneg(model, psi, L, a, b, n_probes, n_steps, tol=tol, precision=precision, seed=seed)
-        t_sur = time.perf_counter() - t0
         ref = full["logneg"]
+        t0 = time.perf_counter()
+        fit = tnslq_logneg(psi, L, a, b, n_probes, n_steps, precision=precision, seed=seed, stop_tol=tol,
+                           stop_rule="fit", want_arrays=False)
+        t_fit = time.perf_counter() - t0
         row = {"case": name, "E_full": ref, "E_full_se": full["logneg_se"], "t_full_s": t_full,
-               "steps_full": full["steps_done"], "E8": float(E[7]), "err_E8": float(E[7] - ref),
-               "adaptive_stop_step": j_stop, "E_adaptive": float(E[j_stop - 1]),
-               "err_adaptive": float(E[j_stop - 1] - ref),
-               "t_adaptive_s_est": t_full * j_stop / full["steps_done"],
-               "mu": s["mu"], "sigma": s["sigma"], "accepted": not s["used_fallback"],
-               "E_surrogate": s["logneg"], "err_surrogate": s["logneg"] - ref, "t_surrogate_s": t_sur}
+               "steps_full": full["steps_done"], "fit_steps": fit["steps_done"], "E_fit": fit["logneg"],
+               "err_fit": fit["logneg"] - ref, "fit_lanczos_err": fit["lanczos_err"], "t_fit_s": t_fit,
+               "surrogates": []}
+        for label, model in loaded:
+            t0 = time.perf_counter()
+            s = surrogate_logneg(model, psi, L, a, b, n_probes, n_steps, tol=tol, precision=precision, seed=seed,
+                                 stop_tol=tol, stop_rule="fit")
+            t_sur = time.perf_counter() - t0
+            row["surrogates"].append({"model": label, "n_early": model.feature_steps, "mu": s["mu"],
+                                      "sigma": s["sigma"], "accepted": not s["used_fallback"],
+                                      "steps": s["steps_done"], "E_surrogate": s["logneg"],
+                                      "err_surrogate": s["logneg"] - ref, "t_surrogate_s": t_sur})
+            print(f"[heldout26] {name} ({label}, {model.feature_steps} steps): surrogate {s['logneg']:.5f} "
+                  f"(sigma {s['sigma']:.4f}, accepted {not s['used_fallback']}, {s['steps_done']} steps, "
+                  f"{t_sur:.2f} s)", file=sys.stderr, flush=True)
         rows.append(row)
-        print(f"[heldout26] {name}: full {ref:.5f}, E8 {E[7]:.5f}, adaptive@{j_stop} {E[j_stop - 1]:.5f}, "
-              f"surrogate {s['logneg']:.5f} (sigma {s['sigma']:.4f}, accepted {not s['used_fallback']})",
-              file=sys.stderr, flush=True)
+        print(f"[heldout26] {name}: full {ref:.5f} ({t_full:.2f} s), fit rule {fit['logneg']:.5f} at step "
+              f"{fit['steps_done']} ({t_fit:.2f} s)", file=sys.stderr, flush=True)
         del psi
         torch.cuda.empty_cache()
     return {"probes": n_probes, "steps": n_steps, "precision": precision, "tol": tol, "rows": rows}
@@ -450,12 +520,15 @@ def main(argv=None):
     sc = sub.add_parser("scrambling")
     sc.add_argument("--depths", default="1-12")
     sc.add_argument("--precision", default="bf16x3")
-    sub.add_parser("heldout26")
+    ho = sub.add_parser("heldout26")
+    ho.add_argument("--models", default="", help="comma list of checkpoint directories (default: the committed one)")
     hs = sub.add_parser("hbm_sweep")
     hs.add_argument("--cases", default="", help="comma list of |A|:|B|:K (default: the whole sweep)")
     hs.add_argument("--forms", default="lazy,lazy_two_pass")
     hs.add_argument("--steps", type=int, default=10)
     sub.add_parser("operator_forms")
+    sl = sub.add_parser("surrogate_latency")
+    sl.add_argument("--model", default="")
     sub.add_parser("hbm_peak")
     sp = sub.add_parser("arith_peaks")
     sp.add_argument("--blocks", type=int, default=2048)
@@ -475,6 +548,8 @@ def main(argv=None):
         out = run_hbm_peak()
     elif args.cmd == "arith_peaks":
         out = run_arith_peaks(blocks=args.blocks, target_ms=args.ms)
+    elif args.cmd == "surrogate_latency":
+        out = run_surrogate_latency(model_dir=args.model or None)
     elif args.cmd == "operator_forms":
         out = run_operator_forms()
     elif args.cmd == "hbm_sweep":
@@ -485,7 +560,7 @@ def main(argv=None):
     elif args.cmd == "entropy30":
         out = run_entropy30(n_steps=args.steps)
     else:
-        out = run_heldout26()
+        out = run_heldout26(models=[m for m in args.models.split(",") if m] or None)
     print(json.dumps(out))
 
 

@@ -64,6 +64,29 @@ def test_fit_stop_step_matches_oracle_and_meets_target(dev):
     assert abs(g["logneg"] - o["logneg"]) <= 0.01 * max(abs(o["logneg"]), 1.0)
 
 
+def test_unmet_target_reports_the_plain_estimate_like_the_oracle(dev):
+    # a brickwork state that does not settle within 20 steps under a 1e-6
+    # target: the device reports the plain 20-step estimate and the fit's
+    # Lanczos error, as the oracle's result rule does.  Both sides
+    # reorthogonalise: without it the recurrence on this spectrum (many
+    # eigenvalues near 0) amplifies rounding differences past step 10
+    import torch
+    L, a, b = 12, list(range(1, 6)), list(range(6, 11))
+    psi = ti.brickwork_state(L, 3, 0)
+    K, m = 8, 20
+    g = T.tnslq_logneg(torch.from_numpy(psi).to(dev), L, a, b, K, m, precision="fp64", seed=2, stop_tol=1e-6,
+                       stop_rule="fit", reorth=True)
+    P = exact.regroup(psi, L, a, b)
+    R = exact.rho_pt(P)
+    X = probes.rademacher_probes(2, K, P.shape[0] * P.shape[1], 0)
+    o = slq.slq(lambda v: R @ v, X, m, reorth=True)
+    want = lf.fit_rule_result(o["F"], o["alpha"], o["beta"], 1e-6)
+    assert not want["met"] and g["steps_done"] == m
+    assert g["logneg"] == pytest.approx(want["logneg"], abs=1e-10)
+    assert np.allclose(g["G"], want["G"], rtol=1e-10, atol=0)
+    assert g["lanczos_err"] == pytest.approx(want["lanczos_err"], rel=1e-4)
+
+
 def test_fit_rule_stops_no_later_than_the_difference_rule(dev):
     import torch
     L, a, b = 14, list(range(4, 9)), list(range(9, 14))

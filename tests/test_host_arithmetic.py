@@ -1,5 +1,5 @@
 """The package's host-side arithmetic outside the run-time path (the
-surrogate's training features and E_8 labels, and the replay of the
+surrogate's training features and early-estimate labels, and the replay of the
 step-difference rule in the experiment drivers) against the oracle's
 definitions, on trajectories from the oracle's SLQ."""
 import numpy as np
@@ -26,8 +26,10 @@ def runs():
 def test_training_features_and_labels_match_the_oracle(runs):
     for r in runs:
         d_a, d_b, d_e = r["dims"]
-        f = psur.features_from_coefficients(r["alpha"], r["beta"], d_a, d_b, d_e)
-        assert np.allclose(f, osur.block_features(r["alpha"], r["beta"], d_a, d_b, d_e), rtol=1e-15, atol=0)
+        for n_early in (4, 5, 8):
+            f = psur.features_from_coefficients(r["alpha"], r["beta"], d_a, d_b, d_e, n_early)
+            assert np.allclose(f, osur.block_features(r["alpha"], r["beta"], d_a, d_b, d_e, n_early), rtol=1e-15,
+                               atol=0)
         for j in (6, 8, 24):
             assert psur.estimate_at(r["beta"], r["F"], j) == pytest.approx(
                 step_difference.block_estimate(r["beta"], r["F"], j)["logneg"], abs=1e-14)

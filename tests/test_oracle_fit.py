@@ -268,3 +268,25 @@ def test_stated_lanczos_error_covers_the_long_run():
     assert len(cover) >= 20
     assert np.mean(cover) >= 0.68, (np.mean(cover), steps)
     assert max(steps) < 20        # and the rule still stops early
+
+
+def test_unmet_target_reports_the_plain_estimate_of_the_last_step():
+    # a 12-qubit brickwork state of depth 3 does not meet a 1e-6 target in
+    # 20 steps: the run reports what plain SLQ of 20 steps gives (the
+    # oracle's SLQ, pinned against exact spectra elsewhere), with the fit's
+    # Lanczos error; a 1% target on a Haar state is met and reports the fit
+    L, a, b = 12, list(range(1, 6)), list(range(6, 11))
+    psi = ti.brickwork_state(L, 3, 0)
+    r = slq.slq_logneg(psi, L, a, b, 8, 20, seed=2)
+    out = lf.fit_rule_result(r["F"], r["alpha"], r["beta"], 1e-6)
+    assert not out["met"] and out["step"] == 20
+    assert out["logneg"] == pytest.approx(r["logneg"], abs=1e-12)
+    st = lf.fit_stats(r["F"], r["alpha"], r["beta"], 20)
+    assert out["lanczos_err"] == pytest.approx(st["lanczos_err"] / (st["trace_norm"] * np.log(2.0)), rel=1e-12)
+    assert out["lanczos_err"] > 1e-6 * max(abs(out["logneg"]), 1.0)
+    psi = ti.haar_state(L, 4)
+    r = slq.slq_logneg(psi, L, a, b, 8, 20, seed=2)
+    out = lf.fit_rule_result(r["F"], r["alpha"], r["beta"], 0.01)
+    k = lf.fit_stop_step(r["F"], r["alpha"], r["beta"], 0.01)
+    assert out["met"] and out["step"] == k < 20
+    assert out["logneg"] == lf.fit_stats(r["F"], r["alpha"], r["beta"], k)["logneg"]

@@ -30,6 +30,12 @@ def test_features_of_a_jacobi_matrix_are_its_entries():
     assert np.allclose(f[:8], n * diag[:8], rtol=0, atol=1e-12)
     assert np.allclose(f[8:16], n * off[:8], rtol=0, atol=1e-12)
     assert list(f[16:]) == [2.0, 2.0, 1.0]
+    # a network trained on fewer early steps reads them in the same slots,
+    # the later slots of each kind left zero
+    f5 = surrogate.block_features(a[None, :], b[None, :], 4, 4, 2, n_early=5)
+    assert np.allclose(f5[:5], n * diag[:5], rtol=0, atol=1e-12) and not f5[5:8].any()
+    assert np.allclose(f5[8:13], n * off[:5], rtol=0, atol=1e-12) and not f5[13:16].any()
+    assert list(f5[16:]) == [2.0, 2.0, 1.0]
 
 
 def test_features_of_a_bell_pair_in_closed_form():
