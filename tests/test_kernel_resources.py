@@ -95,9 +95,9 @@ def test_quadrature_and_fit_use_no_scratch(tmp_path):
 
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
 def test_one_read_kernel_keeps_partial_y_in_registers(tmp_path):
-    # the one-read matvec holds its rows of the partial Y and of the probe in
-    # registers across every slab it streams; a spill would put them in
-    # per-lane scratch memory, i.e. back in HBM
+    # the one-read matvec holds its rows of the partial Y, of the probe and of
+    # the slabs in flight in registers across every slab it streams; a spill
+    # would put them in per-lane scratch memory, i.e. back in HBM
     from paper_1809_01685_amd import build as b
     cmd = [_hipcc(), *[f for f in b.FLAGS if f != "-fPIC"], "--cuda-device-only", "-c",
            "-Rpass-analysis=kernel-resource-usage", os.path.join(CSRC, "fused.hip"), "-o", str(tmp_path / "f.o")]
@@ -111,6 +111,6 @@ def test_one_read_kernel_keeps_partial_y_in_registers(tmp_path):
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
         if m and name:
             usage[name] = int(m.group(1))
-    fused = {k: v for k, v in usage.items() if "k_pt_fused" in k}
+    fused = {k: v for k, v in usage.items() if "k_pt_rows" in k}
     assert len(fused) == 2, usage
     assert all(v == 0 for v in fused.values()), fused
