@@ -104,10 +104,17 @@ def run_scrambling(depths, seed=0, n_probes=32, n_steps=40, precision="bf16x3"):
         t0 = time.perf_counter()
         r = tnslq_logneg(psi, w.n_qubits, list(w.a), list(w.b), n_probes, n_steps, reorth=w.reorth,
                          precision=precision, seed=seed)
+        sec = time.perf_counter() - t0
+        # the same probes under the fit rule without a target: the fitted
+        # limit at the last step and the fit's Lanczos error
+        f = tnslq_logneg(psi, w.n_qubits, list(w.a), list(w.b), n_probes, n_steps, reorth=w.reorth,
+                         precision=precision, seed=seed, stop_rule="fit", want_arrays=False)
         rows.append({"depth": depth, "logneg": r["logneg"], "logneg_se": r["logneg_se"],
-                     "steps_min": r["steps_min"], "seconds": time.perf_counter() - t0})
-        print(f"[scrambling] depth {depth}: E = {r['logneg']:.4f} +- {r['logneg_se']:.4f}", file=sys.stderr,
-              flush=True)
+                     "lanczos_err_step_difference": r["lanczos_err"], "logneg_fit": f["logneg"],
+                     "lanczos_err_fit": f["lanczos_err"], "steps_min": r["steps_min"], "seconds": sec})
+        print(f"[scrambling] depth {depth}: E = {r['logneg']:.4f} +- {r['logneg_se']:.4f} (Hutchinson), "
+              f"|E_40 - E_35| = {r['lanczos_err']:.4f}, fit {f['logneg']:.4f} +- {f['lanczos_err']:.4f} (Lanczos)",
+              file=sys.stderr, flush=True)
     return {"workload": "brick24: 24-qubit brickwork, A = 4-11, B = 13-20", "probes": n_probes, "steps": n_steps,
             "precision": precision, "rows": rows}
 
