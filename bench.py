@@ -187,7 +187,7 @@ def run_forms(args, w, psi, L, a, b, m, ws):
                                    seed=args.seed, stop_tol=args.stop_tol, workspace=ws, stop_rule=rule)
         else:
             r = T.tnslq_logneg(psi, L, a, b, w["n_probes"], m, reorth=w["reorth"], precision=prec, seed=args.seed,
-                               stop_tol=args.stop_tol, workspace=None if prec in ("fp64", "fp32") else ws,
+                               stop_tol=args.stop_tol, workspace=None if prec in ("fp64", "fp32", "bf16x6") else ws,
                                stop_rule=rule)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -238,7 +238,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="",
                     help="comma list of extra forms to time on the same state and probes "
-                         "(fp64, fp32, bf16x3, surrogate); adds a 'forms' object with each form's "
+                         "(fp64, fp32, bf16x3, bf16x6, surrogate); adds a 'forms' object with each form's "
                          "time, estimate and error against the FP64 form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel for scaling HBM counters)")

@@ -3,6 +3,9 @@
 //   BF16X3  operands split as hi + lo BF16 pieces, three real products per
 //           real product (hi*hi + hi*lo + lo*hi), v_mfma_f32_16x16x32_bf16,
 //           FP32 accumulation;
+//   BF16X6  hi + mid + lo pieces, the six products of pieces (p, q) with
+//           p + q < 3, FP32 accumulation restarted every 64 terms
+//           (k_cgemm_bf16x6, 128 x 64 output tiles);
 //   FP32    v_mfma_f32_16x16x4_f32 with FP32 accumulation, the matrix-core
 //           sums flushed every 64 reduction terms into a second accumulator
 //           so that no FP32 running sum grows past 64 terms;
@@ -66,6 +69,10 @@ template <> struct MP<TNSLQ_BF16X3> {
     static constexpr int NPL = 4;        // re_hi, re_lo, im_hi, im_lo
     using acc = f32x4;
 };
+template <> struct MP<TNSLQ_BF16X6> {
+    static constexpr int NPL = 6;        // re_hi, re_mid, re_lo, im_hi, im_mid, im_lo
+    using acc = f32x4;
+};
 template <> struct MP<TNSLQ_FP32> {
     static constexpr int NPL = 2;
     using acc = f32x4;
@@ -78,8 +85,8 @@ template <> struct MP<TNSLQ_FP64> {
 // FP32 MFMAs or two 16x16x4 FP64 MFMAs per lane
 static_assert(brick_epr(TNSLQ_BF16X3) == 32 && brick_epr(TNSLQ_FP32) == 16 && brick_epr(TNSLQ_FP64) == 8,
               "brick rows of 64 bytes");
-static_assert(MP<TNSLQ_BF16X3>::NPL == planes_of(TNSLQ_BF16X3) && MP<TNSLQ_FP32>::NPL == planes_of(TNSLQ_FP32) &&
-                  MP<TNSLQ_FP64>::NPL == planes_of(TNSLQ_FP64),
+static_assert(MP<TNSLQ_BF16X3>::NPL == planes_of(TNSLQ_BF16X3) && MP<TNSLQ_BF16X6>::NPL == planes_of(TNSLQ_BF16X6) &&
+                  MP<TNSLQ_FP32>::NPL == planes_of(TNSLQ_FP32) && MP<TNSLQ_FP64>::NPL == planes_of(TNSLQ_FP64),
               "planes per brick");
 
 template <int PREC> constexpr int stage_bytes() { return 2 * MP<PREC>::NPL * TILEB; }
@@ -265,8 +272,9 @@ struct TileAt {
     int64_t i0, j0, sbeg, send;
     int s;
 };
+template <int TBN = BN>
 __device__ inline TileAt tile_of(const GemmDesc &g) {
-    const int64_t ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    const int64_t ntm = (g.M + BM - 1) / BM, ntn = (g.N + TBN - 1) / TBN;
     const int64_t per_split = ntm * ntn;
     int64_t bid = blockIdx.x;
     if (gridDim.x % 8 == 0) bid = (bid % 8) * (gridDim.x / 8) + bid / 8;
@@ -277,7 +285,7 @@ __device__ inline TileAt tile_of(const GemmDesc &g) {
     const int64_t first_m = group * GROUP_M;
     const int64_t gsize = (ntm - first_m) < GROUP_M ? (ntm - first_m) : GROUP_M;
     r.i0 = (first_m + (t % (GROUP_M * ntn)) % gsize) * BM;
-    r.j0 = ((t % (GROUP_M * ntn)) / gsize) * BN;
+    r.j0 = ((t % (GROUP_M * ntn)) / gsize) * TBN;
     const int64_t per = g.nst / g.S;
     r.sbeg = (int64_t)r.s * per;
     r.send = r.sbeg + per;
@@ -495,6 +503,150 @@ hipError_t launch_bf16x3_ra(const GemmDesc &g, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// BF16X6: operands split as hi + mid + lo BF16 pieces (six planes per
+// operand), the products of pieces (p, q) with p + q < 3, six per real
+// product, in FP32 on the matrix cores.  Six planes of a 128 x 128 tile would
+// take 96 KiB of LDS per step, so a block computes 128 x 64 outputs: A's
+// brick (48 KiB) and the half of B's brick that holds its 64 rows (24 KiB)
+// per step, double buffered in 144 KiB.  Eight waves (two per SIMD), each
+// 32 x 32 outputs (2 x 2 tiles of 16 x 16): per step a wave issues 96 MFMAs,
+// as in the three-piece kernel.  The matrix-core sums restart every two steps
+// (64 terms) and are added into a second FP32 accumulator, so that no FP32
+// running sum grows past 64 terms.
+constexpr int X6_BN = 64, X6_WAVES_M = 4, X6_WAVES_N = 2;
+constexpr int X6_TM = BM / (16 * X6_WAVES_M), X6_TN = X6_BN / (16 * X6_WAVES_N);
+constexpr int X6_NT = 64 * X6_WAVES_M * X6_WAVES_N;
+constexpr int X6_FLUSH = 2;
+static_assert(X6_TM == 2 && X6_TN == 2 && X6_NT == 512, "32 x 32 per wave");
+
+__global__ void __launch_bounds__(X6_NT, 1) k_cgemm_bf16x6(GemmDesc g) {
+    constexpr int NPL = 6;
+    constexpr int ABRICK = NPL * TILEB;        // A's brick, all planes: 48 KiB
+    constexpr int BHALF = TILEB / 2;           // 64 rows of one plane of B: 4 KiB
+    constexpr int BSTAGE = NPL * BHALF;        // 24 KiB
+    __shared__ __attribute__((aligned(16))) char ldsA0[ABRICK], ldsA1[ABRICK], ldsB0[BSTAGE], ldsB1[BSTAGE];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / X6_WAVES_N, wn = wid % X6_WAVES_N;
+    const TileAt tl = tile_of<X6_BN>(g);
+    const int64_t sbeg = tl.sbeg, send = tl.send;
+
+    const size_t blk = brick_block_bytes(TNSLQ_BF16X6, g.nst);
+    const char *gA = (const char *)g.A + (size_t)(tl.i0 / BM) * blk;
+    // B's rows j0 .. j0 + 63: the first or second half of every plane tile
+    const char *gB = (const char *)g.B + (size_t)(tl.j0 / BN) * blk + ((tl.j0 % BN) / X6_BN) * BHALF;
+    const int w = __builtin_amdgcn_readfirstlane(wid);
+    const uint32_t loff16 = 16u * (uint32_t)lane;
+    // A: thread t copies bytes [16 t, 16 t + 16) of each plane tile; B: wave
+    // w copies the 1 KiB pieces w, w + 8 and w + 16 of the 24 (plane piece / 4,
+    // quarter piece % 4 of its 4 KiB)
+    auto dma = [&](int64_t st, int buf) __attribute__((always_inline)) {
+        const char *pa = gA + st * ABRICK, *pb = gB + st * ABRICK;
+        char *As = (buf ? ldsA1 : ldsA0) + 1024 * w, *Bs = buf ? ldsB1 : ldsB0;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+            __builtin_amdgcn_global_load_lds((gbl_void_t *)(pa + p * TILEB + 1024 * w + loff16),
+                                             (lds_void_t *)(As + p * TILEB), 16, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int piece = w + 8 * i, plane = piece / 4, quarter = piece % 4;
+            __builtin_amdgcn_global_load_lds((gbl_void_t *)(pb + plane * TILEB + quarter * 1024 + loff16),
+                                             (lds_void_t *)(Bs + plane * BHALF + quarter * 1024), 16, 0, 0);
+        }
+    };
+    const int frow = lane & 15, fk = lane >> 4;
+    int oa[X6_TM], ob[X6_TN];
+#pragma unroll
+    for (int x = 0; x < X6_TM; ++x) oa[x] = loff(wm * X6_TM * 16 + x * 16 + frow, fk);
+#pragma unroll
+    for (int x = 0; x < X6_TN; ++x) ob[x] = loff(wn * X6_TN * 16 + x * 16 + frow, fk);
+
+    f32x4 accr[X6_TM][X6_TN], acci[X6_TM][X6_TN], outr[X6_TM][X6_TN], outi[X6_TM][X6_TN];
+#pragma unroll
+    for (int a = 0; a < X6_TM; ++a)
+#pragma unroll
+        for (int b = 0; b < X6_TN; ++b) {
+            accr[a][b] = acci[a][b] = outr[a][b] = outi[a][b] = f32x4{0, 0, 0, 0};
+        }
+    const int64_t last = send - 1;
+    dma(sbeg, 0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+    __syncthreads();
+    int nstage = 0;
+    for (int64_t st = sbeg; st < send; ++st) {
+        const int buf = (int)((st - sbeg) & 1);
+        const char *As = buf ? ldsA1 : ldsA0, *Bs = buf ? ldsB1 : ldsB0;
+        uint4 fa[X6_TM][NPL], fb[X6_TN][NPL];
+#pragma unroll
+        for (int x = 0; x < X6_TM; ++x)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) fa[x][p] = *(const uint4 *)(As + p * TILEB + oa[x]);
+#pragma unroll
+        for (int x = 0; x < X6_TN; ++x)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) fb[x][p] = *(const uint4 *)(Bs + p * BHALF + ob[x]);
+        // every fragment read of the step is issued before the copy into
+        // the other buffer
+        __builtin_amdgcn_sched_barrier(0);
+        dma(st + 1 <= last ? st + 1 : last, buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+        // pieces (p, q) with p + q < 3; Re C += Re A Re B + (-Im A) Im B,
+        // Im C += Re A Im B + Im A Re B
+#pragma unroll
+        for (int pq = 0; pq < 6; ++pq) {
+            const int p = pq < 3 ? 0 : (pq < 5 ? 1 : 2);
+            const int q = pq < 3 ? pq : (pq < 5 ? pq - 3 : 0);
+#pragma unroll
+            for (int a = 0; a < X6_TM; ++a) {
+                const uint4 na = neg_bf16x8(fa[a][3 + p]);
+#pragma unroll
+                for (int b = 0; b < X6_TN; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]), as_bf16x8(fb[b][q]),
+                                                                          accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][p]),
+                                                                          as_bf16x8(fb[b][3 + q]), acci[a][b], 0, 0, 0);
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(na), as_bf16x8(fb[b][3 + q]),
+                                                                          accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[a][3 + p]),
+                                                                          as_bf16x8(fb[b][q]), acci[a][b], 0, 0, 0);
+                }
+            }
+        }
+        if (++nstage == X6_FLUSH) {
+#pragma unroll
+            for (int a = 0; a < X6_TM; ++a)
+#pragma unroll
+                for (int b = 0; b < X6_TN; ++b) {
+                    outr[a][b] += accr[a][b];
+                    outi[a][b] += acci[a][b];
+                    accr[a][b] = acci[a][b] = f32x4{0, 0, 0, 0};
+                }
+            nstage = 0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) and lgkmcnt(0)
+        __syncthreads();
+    }
+    if (nstage) {
+#pragma unroll
+        for (int a = 0; a < X6_TM; ++a)
+#pragma unroll
+            for (int b = 0; b < X6_TN; ++b) {
+                outr[a][b] += accr[a][b];
+                outi[a][b] += acci[a][b];
+            }
+    }
+    store_tiles<TNSLQ_BF16X6, X6_TM, X6_TN>(g, tl.s, tl.i0 + wm * X6_TM * 16, tl.j0 + wn * X6_TN * 16, lane, outr,
+                                            outi);
+}
+
+hipError_t launch_bf16x6(const GemmDesc &g, hipStream_t st) {
+    const int64_t nblocks = ((g.M + BM - 1) / BM) * ((g.N + X6_BN - 1) / X6_BN) * g.S;
+    if (nblocks < 1 || nblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_cgemm_bf16x6, dim3((unsigned)nblocks), dim3(X6_NT), 0, st, g);
+    return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t launch(const GemmDesc &g, hipStream_t st) {
     if constexpr (PREC == TNSLQ_BF16X3) {
@@ -521,11 +673,12 @@ bool supported(const GemmDesc &g) {
 
 }  // namespace
 
-// Whether the matrix-core kernel takes this contraction: BF16X3, FP32 or FP64
-// bricks, the bricks divided evenly between the splits.
+// Whether the matrix-core kernel takes this contraction: BF16X3, BF16X6, FP32
+// or FP64 bricks, the bricks divided evenly between the splits.
 bool gemm_mfma_supported(int prec, const GemmDesc &g) {
     switch (prec) {
         case TNSLQ_BF16X3: return supported<TNSLQ_BF16X3>(g);
+        case TNSLQ_BF16X6: return supported<TNSLQ_BF16X6>(g);
         case TNSLQ_FP32: return supported<TNSLQ_FP32>(g);
         case TNSLQ_FP64: return supported<TNSLQ_FP64>(g);
         default: return false;
@@ -535,6 +688,7 @@ bool gemm_mfma_supported(int prec, const GemmDesc &g) {
 hipError_t launch_gemm_mfma(int prec, const GemmDesc &g, hipStream_t st) {
     switch (prec) {
         case TNSLQ_BF16X3: return launch<TNSLQ_BF16X3>(g, st);
+        case TNSLQ_BF16X6: return launch_bf16x6(g, st);
         case TNSLQ_FP32: return launch<TNSLQ_FP32>(g, st);
         case TNSLQ_FP64: return launch<TNSLQ_FP64>(g, st);
         default: return hipErrorInvalidValue;

@@ -1,9 +1,10 @@
 // Complex "NT" contraction C = A * B^T on the vector ALUs, over the same
 // brick operands as the matrix-core kernel.
 //
-// Serves the six-piece BF16 split (hi/mid/lo, the products with p + q < 3
-// formed in FP32), which has no matrix-core kernel, and works for every
-// precision.  Sums run in blocks of one LDS tile (16 terms), blocks added into
+// Serves shapes the matrix-core kernels do not take (bricks not divided
+// evenly between the splits, unaligned operands) and works for every
+// precision, including the six-piece BF16 split (hi/mid/lo, the products with
+// p + q < 3 formed in FP32).  Sums run in blocks of one LDS tile (16 terms), blocks added into
 // a second accumulator.
 #include "tnslq_internal.h"
 

@@ -35,8 +35,8 @@ def test_contraction_kernels_use_no_scratch(tmp_path):
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
         if m and name:
             usage[name] = int(m.group(1))
-    gemms = {k: v for k, v in usage.items() if "k_cgemm_nt_mfma" in k or "k_cgemm_bf16x3" in k}
-    assert len(gemms) == 3, usage
+    gemms = {k: v for k, v in usage.items() if "k_cgemm_" in k}
+    assert len(gemms) == 4, usage
     assert all(v == 0 for v in gemms.values()), gemms
 
 
