@@ -236,13 +236,18 @@ def main():
     ap.add_argument("--probes", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="",
+    ap.add_argument("--forms", default=None,
                     help="comma list of extra forms to time on the same state and probes "
                          "(fp64, fp32, bf16x3, bf16x6, surrogate); adds a 'forms' object with each form's "
-                         "time, estimate and error against the FP64 form")
+                         "time, estimate and error against the FP64 form (default: the learned stop, "
+                         "'surrogate', on the default haar30 run; '' for none)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
+    if args.forms is None:
+        # the metric asks for the split-precision and the learned-stop forms
+        # side by side; the default line carries the second as a form
+        args.forms = "surrogate" if (args.workload == "haar30" and not args.max_steps and not args.check_steps) else ""
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU only; --gpus must be 1 "
                                    "(probe-sharded multi-GPU execution is designed but not built)"}))
