@@ -79,6 +79,19 @@ EXTRA = {
 }
 
 
+def finite_or_none(v):
+    """The JSON line with every NaN or infinity as null (strict JSON has
+    neither)."""
+    import math
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    if isinstance(v, dict):
+        return {k: finite_or_none(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [finite_or_none(x) for x in v]
+    return v
+
+
 def workload(name):
     import tnslq_inputs as ti
     if name in ti.WORKLOADS:
@@ -364,7 +377,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(psi, w, last["steps_done"])
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite_or_none(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
