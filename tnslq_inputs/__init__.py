@@ -321,7 +321,8 @@ def max_entangled_pair_state_dims(dims: Sequence[int], i: int, j: int, dtype=np.
 
 
 # --------------------------------------------------------------------------
-# Open-boundary matrix product states (Sec. VI): tensors (chi_i, p, chi_{i+1})
+# Matrix product states (Sec. VI): tensors (chi_i, p, chi_{i+1}); open
+# boundaries have chi_0 = chi_L = 1, periodic ones chi_0 = chi_L > 1
 # --------------------------------------------------------------------------
 def random_mps(n_sites: int, p: int, chi: int, seed: int) -> List[np.ndarray]:
     """Complex Gaussian tensors with bond dimensions min(chi, p^i, p^(L-i))
@@ -352,5 +353,69 @@ def bell_pair_mps(n_sites: int, i: int, j: int) -> List[np.ndarray]:
             M[0, 0, 0] = M[1, 0, 1] = 1.0
         else:
             M[0, 0, 0] = 1.0
+        out.append(M)
+    return out
+
+
+def random_mps_periodic(n_sites: int, p: int, chi: int, seed: int) -> List[np.ndarray]:
+    """Complex Gaussian tensors of a ring: every bond chi, the closing bond
+    included, not normalised."""
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((chi, p, chi)) + 1j * rng.standard_normal((chi, p, chi)) for _ in range(n_sites)]
+
+
+def dimer_mps(n_sites: int, seed: int, offset: int = 0, periodic: bool = False):
+    """Qubit pairs (i, i+1) for i = offset, offset + 2, ... each in a random
+    pure two-qubit state c[s][t] (complex Gaussian, normalised); on a ring
+    (periodic) with an odd offset and an even n_sites the last pair closes
+    through the boundary, (n_sites - 1, 0).  Unpaired sites are |0>.  Returns
+    (tensors, pairs) with pairs a list of ((i, j), c).  Bond 2 inside a pair,
+    1 elsewhere."""
+    rng = np.random.default_rng(seed)
+    L = n_sites
+    pairs = []
+    i = offset % 2
+    while i + 1 < L:
+        pairs.append((i, i + 1))
+        i += 2
+    if periodic and i == L - 1 and offset % 2 == 1:
+        pairs.append((L - 1, 0))
+    coef = []
+    for _ in pairs:
+        c = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+        coef.append(c / np.linalg.norm(c))
+    first = {a: k for k, (a, _) in enumerate(pairs)}
+    second = {b: k for k, (_, b) in enumerate(pairs)}
+    bond = [1] * (L + 1)
+    for a, b in pairs:
+        if b == a + 1:
+            bond[a + 1] = 2
+        else:                      # the pair closing the ring
+            bond[0] = bond[L] = 2
+    out = []
+    for s in range(L):
+        M = np.zeros((bond[s], 2, bond[s + 1]), dtype=np.complex128)
+        if s in first:             # M[0][s][k] = c[s][k], the bond carries the partner's level
+            M[0, :, :] = coef[first[s]]
+        elif s in second:          # M[k][t][0] = delta(k, t)
+            M[0, 0, 0] = M[1, 1, 0] = 1.0
+        else:
+            M[0, 0, 0] = 1.0
+        out.append(M)
+    return out, [(pr, c) for pr, c in zip(pairs, coef)]
+
+
+def ghz_mps(n_sites: int, periodic: bool = True) -> List[np.ndarray]:
+    """(|0...0> + |1...1>) (not normalised) as bond-2 tensors: on a ring every
+    M[:, s, :] = |s><s|, so psi = Tr prod = [all s equal]; open boundaries cut
+    the first and last tensors to a row and a column of ones."""
+    out = []
+    for s in range(n_sites):
+        M = np.zeros((2, 2, 2), dtype=np.complex128)
+        M[0, 0, 0] = M[1, 1, 1] = 1.0
+        if not periodic and s == 0:
+            M = M.sum(axis=0, keepdims=True)
+        if not periodic and s == n_sites - 1:
+            M = M.sum(axis=2, keepdims=True)
         out.append(M)
     return out
