@@ -307,40 +307,69 @@ int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
 
 /* ----------------------------------------- matrix product states (Sec. VI) */
 
-/* An open-boundary matrix product state (Eq. 5 with boundary bonds of size
- * 1): site i holds a complex128 tensor M_i[x][s][y] of shape
- * (bond[i], phys[i], bond[i+1]), row-major, the sites' tensors one after the
- * other in `tensors` (device, read only).  psi_{s_0 .. s_{L-1}} =
- * M_0[0][s_0][:] M_1[:][s_1][:] ... M_{L-1}[:][s_{L-1}][0], site 0 most
- * significant.  The state need not be normalised. */
+/* A matrix product state (Eq. 5, Fig. 4): site i holds a complex128 tensor
+ * M_i[x][s][y] of shape (bond[i], phys[i], bond[i+1]), row-major, the sites'
+ * tensors one after the other in `tensors` (device, read only).
+ *   open boundaries (bond[0] = bond[n] = 1): psi_{s_0 .. s_{L-1}} =
+ *     M_0[0][s_0][:] M_1[:][s_1][:] ... M_{L-1}[:][s_{L-1}][0];
+ *   periodic boundaries (bond[0] = bond[n] > 1, a ring): psi_{s_0 .. s_{L-1}}
+ *     = Tr M_0[:][s_0][:] ... M_{L-1}[:][s_{L-1}][:] (the closing bond summed);
+ * site 0 most significant.  The state need not be normalised.
+ * `sections` chooses how the matrices of compressed sections (below) are
+ * formed:
+ *   TNSLQ_MPS_SECTIONS_EXPLICIT: the section is contracted over its whole
+ *     physical index (p^len x bond^2 entries, at most 2^31) and its Gram
+ *     matrix is a product over that index;
+ *   TNSLQ_MPS_SECTIONS_TRANSFER: its transfer matrix T[(x, x')][y'][y] =
+ *     sum_s S[x][s][y] conj(S[x'][s][y']) is built one site at a time (the
+ *     first step of Sec. VI's lateral compression; bond^4 entries, about
+ *     2 bond^5 p complex multiply-adds per site), so sections of any length
+ *     are reached; the Gram and trace matrices are T with its axes regrouped;
+ *   TNSLQ_MPS_SECTIONS_AUTO (0): per section, the cheaper of the two by that
+ *     count, the transfer route whenever the explicit section would exceed
+ *     2^26 entries.
+ * Both give the same effective state up to rounding. */
+#define TNSLQ_MPS_SECTIONS_AUTO 0
+#define TNSLQ_MPS_SECTIONS_EXPLICIT 1
+#define TNSLQ_MPS_SECTIONS_TRANSFER 2
 typedef struct {
     int n_sites;
-    const int *phys;        /* host, n_sites entries >= 2                      */
-    const int *bond;        /* host, n_sites + 1 entries, bond[0] = bond[n] = 1 */
-    const void *tensors;    /* device, complex128                              */
+    const int *phys;        /* host, n_sites entries >= 2                        */
+    const int *bond;        /* host, n_sites + 1 entries in [1, 4096],
+                               bond[0] = bond[n]                                 */
+    const void *tensors;    /* device, complex128                                */
+    int sections;           /* TNSLQ_MPS_SECTIONS_*                              */
 } tnslq_mps;
 
 /* Contiguous blocks A = sites [a0, a0 + n_a) and B = [b0, b0 + n_b), a0 + n_a
- * <= b0.  Sec. VI's compressed form of rho_AB^{T_B}, reduced to a dense
- * effective state psi_eff with the same nonzero spectrum of the partial
- * transpose (so the same trace norm), normalised:
- *   - the sites left of A and right of B are traced; their transfer products
- *     E_L, E_R (positive, on the bonds entering A and leaving B) are factored
+ * <= b0; bonds u enters A, m leaves it, n enters B, v leaves it.  Sec. VI's
+ * compressed form of rho_AB^{T_B}, reduced to a dense effective state psi_eff
+ * with the same nonzero spectrum of the partial transpose (so the same trace
+ * norm), normalised:
+ *   - open chain: the sites left of A and right of B are traced; their
+ *     transfer products E_L, E_R (positive, on u and v) are factored
  *     E = X X^dagger (Cholesky) and absorbed into A and B, whose outer bond
  *     indices u, v become traced environment indices;
+ *   - ring: the sites right of B and left of A form one outer section
+ *     O[v][o][u] through the closing bond (the identity delta(v, u) when the
+ *     blocks cover the ring); it is traced: Z[v][u][z] with Z Z^dagger its
+ *     transfer matrix grouped as (v, u) against (v', u') (Cholesky when its
+ *     physical space is larger than v u, else O itself), z joining the
+ *     environment;
  *   - vertical decomposition: a block whose physical space is larger than its
  *     two bonds' (p^{n_a} > bond[a0] bond[a0 + n_a]) is replaced by R with
  *     R^dagger R its Gram matrix over the physical index (Cholesky): an
  *     isometry on the block's space, which keeps the nonzero spectrum of the
  *     partial transpose; effective dimension <= bond^2;
- *   - the gap between A and B (if any) is traced: its transfer matrix,
- *     grouped as its two bonds against their conjugates, is factored W
- *     W^dagger when the gap's physical space is the larger, and W's column
- *     index joins the environment.
- * psi_eff's parts A', B', E' = (u, w, v) are each zero padded to a power of
- * two, 2^q_A, 2^q_B, 2^q_E, so that tnslq_logneg (qubits: A = [0, q_A),
- * B = [q_A, q_A + q_B)) applies to it unchanged; the padding adds only zero
- * eigenvalues.
+ *   - the gap between A and B (if any) is traced like the outer section:
+ *     W[m][n][w], W W^dagger its transfer matrix grouped as (m, n) against
+ *     (m', n').
+ * E' = (u, w, v) on an open chain, (w, z) on a ring.  psi_eff's parts A', B',
+ * E' are each zero padded to a power of two, 2^q_A, 2^q_B, 2^q_E, so that
+ * tnslq_logneg (qubits: A = [0, q_A), B = [q_A, q_A + q_B)) applies to it
+ * unchanged; the padding adds only zero eigenvalues.  Factored matrices are
+ * at most 16384 wide (bond[a0] bond[a0 + n_a] and its like for compressed
+ * sections).
  *   tnslq_mps_effective_state_size: q[3] = (q_A, q_B, q_E) and the workspace
  *     bytes (host only).
  *   tnslq_mps_effective_state: writes psi_eff, 2^(q_A + q_B + q_E) complex128
@@ -357,14 +386,15 @@ int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int
 
 /* Algorithm 1 on the same two blocks without forming psi_eff (Sec. VI: the
  * operator as a small tensor network).  With the factors above, psi_eff has
- * the form psi[a][b][(u', v)] = sum_m P[a][u'][m] Q[b][m][v] (adjacent
- * blocks: P = R_A and m the bond between them; with a gap: P = R_A W, u' =
- * (u, w), m the bond entering B), and each matvec is four complex products,
+ * the form psi[a][b][(u', v)] = sum_m P[a][u'][m] Q[b][m][v] (open chain,
+ * adjacent blocks: P = R_A and m the bond between them; with a gap: P = R_A W,
+ * u' = (u, w), m the bond entering B; ring: P = R_A W with u' = w and
+ * m = (n, u), Q = R_B Z with v = z), and each matvec is four complex products,
  *   Z1 = P^dagger X,  Z2 = Z1 Q,  Z3 = P Z2 (m and m' exchanged),
  *   Y[a][b] = sum_{m', v} Z3[a][(m', v)] conj Q[b][(m', v)],
  * about 2 k chi^4 + 2 k^2 chi^2 complex multiply-adds per probe for
- * k = d_A' = d_B' and bonds chi, against 2 k^3 chi^2 for the lazy form on
- * psi_eff.  The Lanczos vectors run over (a, b), a d_B' + b, n = d_A' d_B'
+ * k = d_A' = d_B' and bonds chi on an open chain (on a ring m is chi^2 wide),
+ * against 2 k^3 chi^2 for the lazy form on psi_eff.  The Lanczos vectors run over (a, b), a d_B' + b, n = d_A' d_B'
  * entries, unpadded; the estimate and every output are those of
  * tnslq_logneg on psi_eff (same probes, same stopping rules, the loop over
  * probes with max_probes).

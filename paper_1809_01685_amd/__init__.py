@@ -51,7 +51,10 @@ class PartitionDims(ctypes.Structure):
 
 class Mps(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int), ("phys", ctypes.POINTER(ctypes.c_int)), ("bond", ctypes.POINTER(ctypes.c_int)),
-                ("tensors", ctypes.c_void_p)]
+                ("tensors", ctypes.c_void_p), ("sections", ctypes.c_int)]
+
+
+MPS_SECTIONS = {"auto": 0, "explicit": 1, "transfer": 2}
 
 
 class Options(ctypes.Structure):
@@ -411,37 +414,41 @@ def tnslq_rho_pt_dims(psi, dims, a, b, workspace=None, stream=None, out=None):
 
 
 # ------------------------------------------------- matrix product states
-def _mps_desc(tensors, tensors_ptr=None):
-    """The library's description of an open-boundary MPS (a list of
-    (chi_l, p, chi_r) arrays) with its tensors at ``tensors_ptr``."""
+def _mps_desc(tensors, tensors_ptr=None, sections="auto"):
+    """The library's description of an MPS (a list of (chi_l, p, chi_r)
+    arrays; chi_l of the first = chi_r of the last, 1 for an open chain) with
+    its tensors at ``tensors_ptr``; ``sections`` "auto", "explicit" or
+    "transfer" (how compressed sections are formed)."""
+    if sections not in MPS_SECTIONS:
+        raise ValueError(f"sections must be one of {sorted(MPS_SECTIONS)}, not {sections!r}")
     phys = [int(t.shape[1]) for t in tensors]
     bond = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
     pp = (ctypes.c_int * len(phys))(*phys)
     bb = (ctypes.c_int * len(bond))(*bond)
-    m = Mps(len(tensors), pp, bb, tensors_ptr)
+    m = Mps(len(tensors), pp, bb, tensors_ptr, MPS_SECTIONS[sections])
     m._keep = (pp, bb)
     return m
 
 
-def _mps(tensors, device):
-    """Upload an open-boundary MPS and describe it for the library."""
+def _mps(tensors, device, sections="auto"):
+    """Upload an MPS and describe it for the library."""
     import numpy as np
     import torch
     flat = np.concatenate([np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).ravel() for t in tensors])
     dev = torch.from_numpy(flat).to(device)
-    m = _mps_desc(tensors, _ptr(dev))
+    m = _mps_desc(tensors, _ptr(dev), sections)
     m._keep = m._keep + (dev,)
     return m
 
 
 def tnslq_mps_effective_state(tensors, a0: int, n_a: int, b0: int, n_b: int, device="cuda", workspace=None,
-                              stream=None):
+                              stream=None, sections="auto"):
     """Sec. VI's compressed form of rho_AB^{T_B} for blocks A = [a0, a0 + n_a),
-    B = [b0, b0 + n_b) of an open-boundary MPS, as a dense effective state:
+    B = [b0, b0 + n_b) of an open or periodic MPS, as a dense effective state:
     returns (psi_eff, (q_A, q_B, q_E)); psi_eff is a device complex128 vector
     of 2^(q_A + q_B + q_E) amplitudes, A' the most significant qubits."""
     import torch
-    m = _mps(tensors, device)
+    m = _mps(tensors, device, sections)
     q = (ctypes.c_int * 3)()
     n = ctypes.c_size_t(0)
     _check(lib().tnslq_mps_effective_state_size(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), q,
@@ -453,8 +460,9 @@ def tnslq_mps_effective_state(tensors, a0: int, n_a: int, b0: int, n_b: int, dev
     return psi, (q[0], q[1], q[2])
 
 
-def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opts: Options) -> int:
-    m = _mps_desc(tensors)
+def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opts: Options,
+                              sections="auto") -> int:
+    m = _mps_desc(tensors, None, sections)
     n = ctypes.c_size_t(0)
     _check(lib().tnslq_workspace_bytes_mps(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), ctypes.byref(opts),
                                            ctypes.byref(n)), "tnslq_workspace_bytes_mps")
@@ -464,8 +472,8 @@ def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opt
 def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: int, n_steps: int, device="cuda",
                      route="factored", reorth: bool = False, seed: int = 0, probe_offset: int = 0,
                      stop_tol: float = 0.0, stop_rule="diff", max_probes: int = 0, precision=None, workspace=None,
-                     stream=None, want_arrays: bool = True, **kw) -> Dict[str, object]:
-    """E(rho_AB) of two contiguous blocks of an open-boundary MPS (Sec. VI).
+                     stream=None, want_arrays: bool = True, sections="auto", **kw) -> Dict[str, object]:
+    """E(rho_AB) of two contiguous blocks of an open or periodic MPS (Sec. VI).
 
     route="factored": Algorithm 1 on the two-block operator in factorised form
     (tnslq_logneg_mps, precision "fp64" (default) or "fp32", nothing of the
@@ -475,7 +483,7 @@ def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: in
     import numpy as np
     import torch
     if route == "dense":
-        psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device)
+        psi, q = tnslq_mps_effective_state(tensors, a0, n_a, b0, n_b, device, sections=sections)
         qa, qb, qe = q
         if precision is not None:
             kw["precision"] = precision
@@ -490,8 +498,8 @@ def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: in
         raise TypeError(f"unexpected keywords for the factored route: {sorted(kw)}")
     opts = make_options(n_probes, n_steps, reorth, precision or "fp64", seed, probe_offset, stop_tol, stop_rule,
                         "auto", max_probes)
-    m = _mps(tensors, device)
-    need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts)
+    m = _mps(tensors, device, sections)
+    need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts, sections)
     ws = _workspace(need, torch.device(device), workspace)
     res = Result()
     loop = max_probes > n_probes

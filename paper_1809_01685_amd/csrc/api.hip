@@ -460,19 +460,89 @@ int64_t ceil_pow2_log(int64_t x) {
 }
 
 // Sizes and workspace of the effective state of two contiguous blocks of an
-// open-boundary MPS (Sec. VI); see tnslq_mps_effective_state.
+// open or periodic MPS (Sec. VI); see tnslq_mps_effective_state.
+constexpr int64_t MPS_CHOL_MAX = 16384;           // widest factored matrix
+constexpr int64_t MPS_EXPLICIT_AUTO = int64_t(1) << 26;   // largest explicit section the automatic choice keeps
+
+// One section of the chain: its sites in order (consecutive along the ring),
+// the bonds x entering and y leaving it, its physical size p (saturated above
+// 2^40), whether it is compressed (p > x y), and if so whether its matrix
+// comes from the transfer sweep (tr) or from the explicit section.
+struct MpsSec {
+    std::vector<int> sites;
+    int64_t x = 1, y = 1, p = 1;
+    bool comp = false, tr = false;
+    int64_t smax = 0;             // explicit: the largest running section
+    int64_t tmax = 0, amax = 0;   // transfer: the largest T and step scratch
+};
+
 struct MpsPlan {
     int L = 0, a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    bool closed = false;
     std::vector<int> p, bond;
     std::vector<int64_t> off;          // element offset of each site's tensor
-    int64_t U = 1, Mb = 1, Nb = 1, V = 1, pA = 1, pB = 1, pG = 1;
-    int compA = 0, compB = 0, compG = 0;
-    int64_t kA = 1, kB = 1, Wd = 1;
+    MpsSec A, B, G, O;                 // blocks, gap (empty when adjacent), a ring's outer section
+    int64_t U = 1, Mb = 1, Nb = 1, V = 1;
+    int64_t kA = 1, kB = 1, Wd = 1, Zd = 1;
+    int64_t Up = 1, Mf = 1, Vf = 1;    // psi[a][b][(u', v')] = sum_m P[a][u'][m] Q[b][m][v']
     int q[3] = {0, 0, 0};
-    int64_t smax = 1, gmax = 1, maxb = 1;
-    size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_G, off_RA, off_RB, off_RBp, off_W, off_T1,
-        off_T, off_P, off_TT, off_part, off_fail, total = 0;
+    int64_t smax = 1, gmax = 1, maxb = 1, tmax = 1, amax = 1;
+    size_t off_El[2], off_Er[2], off_S[3], off_SA, off_SB, off_SG, off_SO, off_G, off_RA, off_RB, off_RBp, off_W,
+        off_Z, off_T1, off_T, off_P, off_Q2, off_Q2p, off_TT, off_Tt[2], off_At, off_part, off_fail, total = 0;
 };
+
+// Physical size, compression and route of a section: 0, or 1 when the
+// explicit section the route needs would exceed 2^31 entries, 2 when the
+// transfer sweep's buffers would exceed 2^32 entries.
+int plan_sec(const MpsPlan &mp, MpsSec &s, int route, bool absorb_right) {
+    const int64_t LIM = int64_t(1) << 40;
+    s.x = mp.bond[s.sites.front()];
+    s.y = mp.bond[s.sites.back() + 1];
+    s.p = 1;
+    for (int i : s.sites) s.p = s.p > LIM / mp.p[i] ? LIM + 1 : s.p * mp.p[i];
+    s.comp = s.p > s.x * s.y;
+    // explicit: running section x (physical so far) bond; transfer: x^2 bond^2
+    // and the step's x^2 bond p bond (complex multiply-adds as costs)
+    double ex = 0.0, tr = (double)s.x * s.x * s.x * s.x, f = 1.0;
+    int64_t rows = s.x;
+    bool fits = true;
+    s.smax = s.tmax = s.amax = 0;
+    s.tmax = s.x * s.x * s.x * s.x;
+    for (int i : s.sites) {
+        const int64_t z = mp.bond[i], y = mp.bond[(size_t)i + 1], pi = mp.p[i];
+        ex += (double)rows * z * pi * y;
+        f *= pi;
+        if (fits && (double)rows * pi * y <= (double)(int64_t(1) << 31)) {
+            rows *= pi;
+            s.smax = std::max(s.smax, rows * y);
+        } else {
+            fits = false;
+        }
+        tr += (double)s.x * s.x * pi * z * y * (double)(z + y);
+        s.tmax = std::max(s.tmax, s.x * s.x * y * y);
+        s.amax = std::max(s.amax, s.x * s.x * z * pi * y);
+    }
+    if (absorb_right) {
+        s.smax = std::max(s.smax, rows * s.y);
+        s.amax = std::max(s.amax, s.x * s.x * s.y * s.y);
+    }
+    ex += (double)s.x * s.y * s.x * s.y * f;   // the Gram product over the physical index
+    const bool tfits = std::max(s.tmax, s.amax) <= (int64_t(1) << 32);
+    if (!s.comp)
+        s.tr = false;
+    else if (route == TNSLQ_MPS_SECTIONS_TRANSFER)
+        s.tr = true;
+    else if (route == TNSLQ_MPS_SECTIONS_EXPLICIT)
+        s.tr = false;
+    else
+        s.tr = tfits && (!fits || s.smax > MPS_EXPLICIT_AUTO || tr < ex);
+    if (s.tr) {
+        s.smax = 0;
+        return tfits ? 0 : 2;
+    }
+    s.tmax = s.amax = 0;
+    return fits ? 0 : 1;
+}
 
 // dense: room for the effective state itself (the dense route); without it
 // only the factors are built.
@@ -481,7 +551,12 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     const int L = m->n_sites;
     if (L < 2 || L > 100000) return fail(TNSLQ_E_ARG, "n_sites %d outside [2, 100000]", L);
     if (!m->phys || !m->bond) return fail(TNSLQ_E_ARG, "phys or bond is NULL");
-    if (m->bond[0] != 1 || m->bond[L] != 1) return fail(TNSLQ_E_ARG, "open boundaries need bond[0] = bond[n] = 1");
+    if (m->sections < TNSLQ_MPS_SECTIONS_AUTO || m->sections > TNSLQ_MPS_SECTIONS_TRANSFER)
+        return fail(TNSLQ_E_ARG, "sections %d is not a TNSLQ_MPS_SECTIONS_ value", m->sections);
+    if (m->bond[0] != m->bond[L])
+        return fail(TNSLQ_E_ARG, "boundary bonds differ: bond[0] = %d, bond[n] = %d (open chains have 1, rings the "
+                                 "same closing bond)",
+                    m->bond[0], m->bond[L]);
     if (a0 < 0 || na < 1 || nb < 1 || a0 + na > b0 || b0 + nb > L)
         return fail(TNSLQ_E_PARTITION, "blocks [%d, %d) and [%d, %d) not ordered inside the chain", a0, a0 + na, b0,
                     b0 + nb);
@@ -495,69 +570,79 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     mp.bond.assign(m->bond, m->bond + L + 1);
     mp.off.resize(L + 1);
     mp.off[0] = 0;
+    for (int i = 0; i <= L; ++i)
+        if (mp.bond[i] < 1 || mp.bond[i] > 4096) return fail(TNSLQ_E_ARG, "bond %d: %d outside [1, 4096]", i, mp.bond[i]);
+    mp.closed = mp.bond[0] > 1;
     for (int i = 0; i < L; ++i) {
         if (mp.p[i] < 2 || mp.p[i] > 65536) return fail(TNSLQ_E_ARG, "site %d: phys %d outside [2, 65536]", i, mp.p[i]);
-        if (mp.bond[i + 1] < 1 || mp.bond[i + 1] > 4096)
-            return fail(TNSLQ_E_ARG, "bond %d: %d outside [1, 4096]", i + 1, mp.bond[i + 1]);
         mp.off[i + 1] = mp.off[i] + (int64_t)mp.bond[i] * mp.p[i] * mp.bond[i + 1];
         mp.maxb = std::max<int64_t>(mp.maxb, mp.bond[i + 1]);
     }
-    const int64_t LIM = int64_t(1) << 40;
-    auto prod = [&](int i0, int i1, int64_t &out) {
-        out = 1;
-        for (int i = i0; i < i1; ++i) {
-            if (out > LIM / mp.p[i]) return false;
-            out *= mp.p[i];
-        }
-        return true;
-    };
-    if (!prod(mp.a0, mp.a1, mp.pA) || !prod(mp.b0, mp.b1, mp.pB) || !prod(mp.a1, mp.b0, mp.pG))
-        return fail(TNSLQ_E_ARG, "a block's physical dimension exceeds 2^40");
+    const bool gap = mp.b0 > mp.a1;
+    for (int i = mp.a0; i < mp.a1; ++i) mp.A.sites.push_back(i);
+    for (int i = mp.b0; i < mp.b1; ++i) mp.B.sites.push_back(i);
+    for (int i = mp.a1; i < mp.b0; ++i) mp.G.sites.push_back(i);
+    if (mp.closed) {
+        for (int i = mp.b1; i < L; ++i) mp.O.sites.push_back(i);
+        for (int i = 0; i < mp.a0; ++i) mp.O.sites.push_back(i);
+    }
+    const int route = m->sections;
+    MpsSec *secs[4] = {&mp.A, &mp.B, gap ? &mp.G : nullptr, mp.O.sites.empty() ? nullptr : &mp.O};
+    static const char *sname[4] = {"block A", "block B", "the gap", "the outer section"};
+    int serr[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+        if (secs[k]) serr[k] = plan_sec(mp, *secs[k], route, k == 1 && !mp.closed);
     mp.U = mp.bond[mp.a0];
     mp.Mb = mp.bond[mp.a1];
     mp.Nb = mp.bond[mp.b0];
     mp.V = mp.bond[mp.b1];
-    mp.compA = mp.pA > mp.U * mp.Mb;
-    mp.compB = mp.pB > mp.Nb * mp.V;
-    mp.kA = mp.compA ? mp.U * mp.Mb : mp.pA;
-    mp.kB = mp.compB ? mp.Nb * mp.V : mp.pB;
-    if (mp.b0 > mp.a1) {
-        mp.compG = mp.pG > mp.Mb * mp.Nb;
-        mp.Wd = mp.compG ? mp.Mb * mp.Nb : mp.pG;
+    mp.kA = mp.A.comp ? mp.U * mp.Mb : mp.A.p;
+    mp.kB = mp.B.comp ? mp.Nb * mp.V : mp.B.p;
+    if (gap) mp.Wd = mp.G.comp ? mp.Mb * mp.Nb : mp.G.p;
+    if (mp.closed) mp.Zd = mp.O.sites.empty() ? 1 : (mp.O.comp ? mp.V * mp.U : mp.O.p);
+    if (mp.closed) {
+        mp.Up = gap ? mp.Wd : 1;
+        mp.Mf = (gap ? mp.Nb : mp.Mb) * mp.U;
+        mp.Vf = mp.Zd;
+    } else {
+        mp.Up = gap ? mp.U * mp.Wd : mp.U;
+        mp.Mf = gap ? mp.Nb : mp.Mb;
+        mp.Vf = mp.V;
     }
-    // section sizes while they are built (left bond x physical so far x bond)
-    auto sec_max = [&](int i0, int i1, int64_t left) {
-        int64_t f = 1, mx = 0;
-        for (int i = i0; i < i1; ++i) {
-            f *= mp.p[i];
-            mx = std::max(mx, left * f * mp.bond[i + 1]);
-        }
-        return mx;
-    };
-    mp.smax = std::max({sec_max(mp.a0, mp.a1, mp.U), sec_max(mp.b0, mp.b1, mp.Nb), mp.Nb * mp.pB * mp.V,
-                        mp.b0 > mp.a1 ? sec_max(mp.a1, mp.b0, mp.Mb) : int64_t(1)});
-    if (mp.smax > (int64_t(1) << 31)) return fail(TNSLQ_E_ARG, "a block section has more than 2^31 entries");
-    const int64_t chol = std::max({mp.compA ? mp.U * mp.Mb : 0, mp.compB ? mp.Nb * mp.V : 0,
-                                   mp.compG ? mp.Mb * mp.Nb : 0, mp.U, mp.V});
-    if (chol > 4096) return fail(TNSLQ_E_ARG, "a factored matrix would be %lld wide (at most 4096)", (long long)chol);
+    int64_t chol = std::max<int64_t>(mp.U, mp.V);
+    for (const MpsSec *s : {&mp.A, &mp.B, &mp.G, &mp.O})
+        if (s->comp) chol = std::max(chol, s->x * s->y);
+    if (chol > MPS_CHOL_MAX)
+        return fail(TNSLQ_E_ARG, "a factored matrix would be %lld wide (at most %lld)", (long long)chol,
+                    (long long)MPS_CHOL_MAX);
+    for (int k = 0; k < 4; ++k) {
+        if (serr[k] == 1)
+            return fail(TNSLQ_E_ARG, "%s: the explicit section would exceed 2^31 entries%s", sname[k],
+                        secs[k]->comp ? " (the transfer route reaches it)" : "");
+        if (serr[k] == 2) return fail(TNSLQ_E_ARG, "%s: the transfer sweep would exceed 2^32 entries", sname[k]);
+    }
     mp.gmax = std::max<int64_t>(1, chol * chol);
+    for (const MpsSec *s : {&mp.A, &mp.B, &mp.G, &mp.O}) {
+        mp.smax = std::max(mp.smax, s->smax);
+        mp.tmax = std::max(mp.tmax, s->tmax);
+        mp.amax = std::max(mp.amax, s->amax);
+    }
     mp.q[0] = (int)ceil_pow2_log(mp.kA);
     mp.q[1] = (int)ceil_pow2_log(mp.kB);
-    mp.q[2] = (int)ceil_pow2_log(mp.U * mp.Wd * mp.V);
+    mp.q[2] = (int)ceil_pow2_log(mp.Up * mp.Vf);
     if (!dense) {
-        const int64_t Up = mp.U * mp.Wd, M = mp.b0 > mp.a1 ? mp.Nb : mp.Mb;
-        if (mp.kA * Up > INT32_MAX || mp.kB * mp.V > INT32_MAX || Up * M > INT32_MAX || M * mp.V > INT32_MAX ||
-            mp.kA * mp.kB > (int64_t(1) << 32))
+        if (mp.kA * mp.Up > INT32_MAX || mp.kB * mp.Vf > INT32_MAX || mp.Up * mp.Mf > INT32_MAX ||
+            mp.Mf * mp.Vf > INT32_MAX || mp.kA * mp.kB > (int64_t(1) << 32) || mp.kB * mp.Mf > INT32_MAX)
             return fail(TNSLQ_E_ARG, "the blocks' factors exceed 2^31 rows or columns");
     } else if (mp.q[0] + mp.q[1] + mp.q[2] > 32)
         return fail(TNSLQ_E_ARG, "the effective state would need %d qubits (at most 32)", mp.q[0] + mp.q[1] + mp.q[2]);
     size_t o = 0;
     auto take = [&](int64_t n) {
         size_t r = o;
-        o += up((size_t)n * 16);
+        o += up((size_t)std::max<int64_t>(n, 1) * 16);
         return r;
     };
-    const int64_t e2 = mp.maxb * mp.maxb;
+    const int64_t e2 = mp.closed ? 1 : mp.maxb * mp.maxb;
     mp.off_El[0] = take(e2);
     mp.off_El[1] = take(e2);
     mp.off_Er[0] = take(e2);
@@ -565,44 +650,86 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     mp.off_S[0] = take(mp.smax);
     mp.off_S[1] = take(mp.smax);
     mp.off_S[2] = take(mp.smax);
-    mp.off_SA = take(mp.U * mp.pA * mp.Mb);
-    mp.off_SB = take(mp.Nb * mp.pB * mp.V);
-    mp.off_SG = take(mp.b0 > mp.a1 ? mp.Mb * mp.pG * mp.Nb : 1);
+    mp.off_SA = take(mp.A.tr ? 1 : mp.U * mp.A.p * mp.Mb);
+    mp.off_SB = take(mp.B.tr ? 1 : mp.Nb * mp.B.p * mp.V);
+    mp.off_SG = take(gap && !mp.G.tr ? mp.Mb * mp.G.p * mp.Nb : 1);
+    mp.off_SO = take(!mp.O.sites.empty() && !mp.O.tr ? mp.V * mp.O.p * mp.U : 1);
     mp.off_G = take(mp.gmax);
     mp.off_RA = take(mp.kA * mp.U * mp.Mb);
     mp.off_RB = take(mp.kB * mp.Nb * mp.V);
-    mp.off_RBp = take(mp.kB * mp.Nb * mp.V);
-    mp.off_W = take(mp.Mb * mp.Nb * mp.Wd);
-    mp.off_T1 = take(mp.kA * mp.U * mp.Nb * mp.Wd);
-    mp.off_T = take(dense ? mp.kA * mp.U * mp.Wd * mp.kB * mp.V : 1);
-    mp.off_P = take(mp.b0 > mp.a1 ? mp.kA * mp.U * mp.Wd * mp.Nb : 1);
-    int64_t tmax = 0;   // the transfer steps' scratch: one site tensor and one environment
-    for (int i = 0; i < L; ++i)
-        if (i < mp.a0 || i >= mp.b1) tmax = std::max<int64_t>(tmax, (mp.off[i + 1] - mp.off[i]) + e2);
-    mp.off_TT = take(std::max<int64_t>(tmax, 1));
+    mp.off_RBp = take(mp.closed ? 1 : mp.kB * mp.Nb * mp.V);
+    mp.off_W = take(gap ? mp.Mb * mp.Nb * mp.Wd : 1);
+    mp.off_Z = take(mp.closed ? mp.V * mp.U * mp.Zd : 1);
+    mp.off_T1 = take(gap ? mp.kA * mp.U * mp.Nb * mp.Wd : 1);
+    mp.off_T = take(dense ? mp.kA * mp.Up * mp.kB * mp.Vf : 1);
+    mp.off_P = take(gap || mp.closed ? mp.kA * mp.Up * mp.Mf : 1);
+    mp.off_Q2 = take(mp.closed ? mp.kB * mp.Mf * mp.Vf : 1);
+    mp.off_Q2p = take(mp.closed ? mp.kB * mp.Mf * mp.Vf : 1);
+    int64_t tenv = 0;   // the environment sweeps' scratch: one site tensor and one environment
+    if (!mp.closed)
+        for (int i = 0; i < L; ++i)
+            if (i < mp.a0 || i >= mp.b1) tenv = std::max<int64_t>(tenv, (mp.off[i + 1] - mp.off[i]) + e2);
+    mp.off_TT = take(tenv);
+    const bool sweep = mp.A.tr || mp.B.tr || mp.G.tr || mp.O.tr;
+    mp.off_Tt[0] = take(sweep ? mp.tmax : 1);
+    mp.off_Tt[1] = take(sweep ? mp.tmax : 1);
+    mp.off_At = take(sweep ? mp.amax : 1);
     mp.off_part = o;
     o += up(257 * 8);
-    mp.off_fail = o;   // four flags, then at byte 64 the factorisations' scratch double
-    o += up(64 + 8);
+    mp.off_fail = o;   // four flags, then at byte 64 the factorisations' scratch double, at 72 the sweeps'
+    o += up(64 + 16);
     mp.total = o;
     return TNSLQ_OK;
 }
 
-// Contract the sites [i0, i1) onto the running section S (rows r = left bond
-// x physical so far, columns = bond), starting from S0 (rows0 x bond[i0]);
-// the result lands in `out`.
-int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t rows0, int i0, int i1, double2 *out,
-                double2 *scratch0, double2 *scratch1, hipStream_t st) {
+// Contract the listed sites (consecutive along the ring) onto the running
+// section S (rows r = left bond x physical so far, columns = bond), starting
+// from S0 (rows0 x the first site's left bond); the result lands in `out`.
+int mps_section(const MpsPlan &mp, const double2 *T, const double2 *S0, int64_t rows0, const int *sites, int ns,
+                double2 *out, double2 *scratch0, double2 *scratch1, hipStream_t st) {
     const double2 *cur = S0;
     int64_t rows = rows0;
-    for (int i = i0; i < i1; ++i) {
+    for (int k = 0; k < ns; ++k) {
+        const int i = sites[k];
         const int64_t z = mp.bond[i], py = (int64_t)mp.p[i] * mp.bond[i + 1];
-        double2 *dst = i + 1 == i1 ? out : ((i - i0) % 2 ? scratch1 : scratch0);
+        double2 *dst = k + 1 == ns ? out : (k % 2 ? scratch1 : scratch0);
         TNSLQ_HIP(launch_zgemm(0, 0, cur, T + mp.off[i], dst, (int)rows, (int)py, (int)z, z, py, py, 1, 0, 0, 0, st));
         cur = dst;
         rows *= mp.p[i];
     }
     return TNSLQ_OK;
+}
+
+// The explicit section S[x][phys][y] of s (x = its left bond): the first
+// site's tensor itself when it is alone, else contracted into `out`.
+int mps_section_of(const MpsPlan &mp, const double2 *T, const MpsSec &s, double2 *out, double2 *scratch0,
+                   double2 *scratch1, hipStream_t st, const double2 **S) {
+    const int i0 = s.sites.front();
+    if (s.sites.size() == 1) {
+        *S = T + mp.off[i0];
+        return TNSLQ_OK;
+    }
+    *S = out;
+    return mps_section(mp, T, T + mp.off[i0], s.x * mp.p[i0], s.sites.data() + 1, (int)s.sites.size() - 1, out,
+                       scratch0, scratch1, st);
+}
+
+// The transfer matrix of the section s, T[(x, x')][y'][y], with X (x x x)
+// absorbed on its left bond when not null; returns the buffer holding it.
+double2 *mps_sweep(const MpsPlan &mp, const double2 *T, const MpsSec &s, const double2 *X, char *ws, hipStream_t st,
+                   int &rc) {
+    double2 *cur = (double2 *)(ws + mp.off_Tt[0]), *nxt = (double2 *)(ws + mp.off_Tt[1]);
+    double2 *A = (double2 *)(ws + mp.off_At);
+    double *tscr = (double *)(ws + mp.off_fail + 72);
+    rc = TNSLQ_OK;
+    hipError_t e = launch_transfer_start(X, s.x, cur, tscr, st);
+    for (size_t k = 0; e == hipSuccess && k < s.sites.size(); ++k) {
+        const int i = s.sites[k];
+        e = launch_transfer_step(cur, T + mp.off[i], s.x, mp.bond[i], mp.p[i], mp.bond[i + 1], nxt, A, tscr, st);
+        std::swap(cur, nxt);
+    }
+    if (e != hipSuccess) rc = fail(TNSLQ_E_DEVICE, "transfer sweep: %s", hipGetErrorString(e));
+    return cur;
 }
 
 // R[k][(l, r)] for a section S[l][phys][r]: S itself with its first two axes
@@ -632,10 +759,56 @@ int mps_vertical(const double2 *S, int64_t l, int64_t ph, int64_t r, int comp, d
     return TNSLQ_OK;
 }
 
-// The factors of the effective state psi[a][b][(u', v)] = sum_m P[a][u'][m]
-// Q[b][m][v]: for adjacent blocks u' = u and m is the bond between them; with
-// a gap, P = sum_m R_A[a][u][m] W[m][n][w] with u' = (u, w) and m -> n.  Qp is
-// Q with its first two axes exchanged, [m][b][v].
+// R[k][(x, y)] = L^dagger for the Gram matrix of a section given by its
+// transfer matrix Tr[x][x'][y'][y]: G[x][y][x'][y'] = Tr[x'][x][y][y'].
+int mps_vertical_transfer(const double2 *Tr, int64_t x, int64_t y, double2 *R, double2 *G, int *failp, double *dscr,
+                          hipStream_t st) {
+    const int64_t d[4] = {x, x, y, y};
+    const int perm[4] = {1, 2, 0, 3};
+    TNSLQ_HIP(launch_permute4(Tr, d, perm, G, st));
+    TNSLQ_HIP(launch_cholesky(G, (int)(x * y), failp, dscr, st));
+    TNSLQ_HIP(launch_swap01(G, 1, x * y, x * y, 1, 1, R, st));
+    return TNSLQ_OK;
+}
+
+// F[(x, y)][f] with F F^dagger = the section's matrix sum_s S[x][s][y]
+// conj(S[x'][s][y']) = Tr[x][x'][y'][y] (a traced gap or outer section), in
+// place in F (x y x y entries).
+int mps_trace_factor_transfer(const double2 *Tr, int64_t x, int64_t y, double2 *F, int *failp, double *dscr,
+                              hipStream_t st) {
+    const int64_t d[4] = {x, x, y, y};
+    const int perm[4] = {0, 3, 1, 2};
+    TNSLQ_HIP(launch_permute4(Tr, d, perm, F, st));
+    TNSLQ_HIP(launch_cholesky(F, (int)(x * y), failp, dscr, st));
+    return TNSLQ_OK;
+}
+
+// F[x][y][f] for an explicit traced section S[x][g][y]: S with its last two
+// axes exchanged when g <= x y (F holds x y g entries), else the Cholesky
+// factor of sum_g S[x][g][y] conj(S[x'][g][y']) (F holds (x y)^2 entries; the
+// exchanged section goes to tmp, x g y entries, the Gram matrix to G).
+int mps_trace_factor(const double2 *S, int64_t x, int64_t g, int64_t y, bool comp, double2 *F, double2 *tmp,
+                     double2 *G, int *failp, double *dscr, hipStream_t st) {
+    if (!comp) {
+        TNSLQ_HIP(launch_swap01(S, x, g, y, 1, 0, F, st));   // [x][y][g]
+        return TNSLQ_OK;
+    }
+    const int64_t n = x * y;
+    TNSLQ_HIP(launch_swap01(S, x, g, y, 1, 0, tmp, st));
+    TNSLQ_HIP(launch_zgemm(0, 2, tmp, tmp, G, (int)n, (int)n, (int)g, g, g, n, 1, 0, 0, 0, st));
+    TNSLQ_HIP(launch_cholesky(G, (int)n, failp, dscr, st));
+    TNSLQ_HIP(hipMemcpyAsync(F, G, (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
+    return TNSLQ_OK;
+}
+
+// The factors of the effective state psi[a][b][(u', v')] = sum_m P[a][u'][m]
+// Q[b][m][v']:
+//   open, adjacent:  P = R_A, u' = u, m the bond between the blocks, v' = v;
+//   open, gap:       P[a][(u, w)][n] = sum_m R_A[a][u][m] W[m][n][w];
+//   ring:            P[a][w][(n, u)] = sum_m R_A[a][u][m] W[m][n][w] (W the
+//                    identity when adjacent), Q[b][(n, u)][z] = sum_v
+//                    R_B[b][n][v] Z[v][u][z], v' = z.
+// Qp is Q with its first two axes exchanged, [m][b][v'].
 struct MpsFactors {
     double2 *P;
     const double2 *Q, *Qp;
@@ -649,69 +822,146 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
     double *dscr = (double *)(ws + mp.off_fail + 64);   // the factorisations' largest diagonal entry
     TNSLQ_HIP(launch_zero(failp, 16, st));
     static const double2 one = {1.0, 0.0};
-    // traced environments: E_L on the bond entering A, E_R on the bond leaving B
-    double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
-    TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
-    for (int i = 0; i < mp.a0; ++i) {
-        TNSLQ_HIP(launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, buf(mp.off_TT), st));
-        std::swap(El, Eln);
-    }
-    double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
-    TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
-    for (int i = mp.L - 1; i >= mp.b1; --i) {
-        TNSLQ_HIP(launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, buf(mp.off_TT), st));
-        std::swap(Er, Ern);
-    }
-    TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, dscr, st));       // X[x][u]
-    TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, dscr, st));   // Y[y][v]
     double2 *s0 = buf(mp.off_S[0]), *s1 = buf(mp.off_S[1]), *s2 = buf(mp.off_S[2]);
-    // block A with X absorbed: S_A[u][a][m], from X^T (rows u, columns x)
-    TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Eln, st));
-    if ((rc = mps_section(mp, T, Eln, mp.U, mp.a0, mp.a1, buf(mp.off_SA), s0, s1, st))) return rc;
-    // block B, then Y absorbed: S_B[n][b][v]
-    if ((rc = mps_section(mp, T, T + mp.off[mp.b0], mp.Nb * mp.p[mp.b0], mp.b0 + 1, mp.b1, s2, s0, s1, st))) return rc;
-    const double2 *SBy = mp.b1 - mp.b0 > 1 ? s2 : T + mp.off[mp.b0];
-    TNSLQ_HIP(launch_zgemm(0, 0, SBy, Er, buf(mp.off_SB), (int)(mp.Nb * mp.pB), (int)mp.V, mp.bond[mp.b1],
-                           mp.bond[mp.b1], mp.V, mp.V, 1, 0, 0, 0, st));
-    // vertical decompositions
-    // (the sections' scratch s1, s2 is free again: the Gram products' partials)
-    if ((rc = mps_vertical(buf(mp.off_SA), mp.U, mp.pA, mp.Mb, mp.compA, buf(mp.off_RA), s0, buf(mp.off_G), s1,
-                           mp.smax, failp + 2, dscr, st)))
-        return rc;
-    if ((rc = mps_vertical(buf(mp.off_SB), mp.Nb, mp.pB, mp.V, mp.compB, buf(mp.off_RB), s0, buf(mp.off_G), s1,
-                           mp.smax, failp + 3, dscr, st)))
-        return rc;
-    TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
-    f.Q = buf(mp.off_RB);
-    f.Qp = buf(mp.off_RBp);
+    const double2 *X = nullptr, *Y = nullptr;
+    double2 *Xt = nullptr;
+    if (!mp.closed) {
+        // traced environments: E_L on the bond entering A, E_R on the bond leaving B
+        double2 *El = buf(mp.off_El[0]), *Eln = buf(mp.off_El[1]);
+        TNSLQ_HIP(hipMemcpyAsync(El, &one, sizeof one, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < mp.a0; ++i) {
+            TNSLQ_HIP(
+                launch_transfer(1, El, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Eln, buf(mp.off_TT), st));
+            std::swap(El, Eln);
+        }
+        double2 *Er = buf(mp.off_Er[0]), *Ern = buf(mp.off_Er[1]);
+        TNSLQ_HIP(hipMemcpyAsync(Er, &one, sizeof one, hipMemcpyHostToDevice, st));
+        for (int i = mp.L - 1; i >= mp.b1; --i) {
+            TNSLQ_HIP(
+                launch_transfer(0, Er, T + mp.off[i], mp.bond[i], mp.p[i], mp.bond[i + 1], Ern, buf(mp.off_TT), st));
+            std::swap(Er, Ern);
+        }
+        TNSLQ_HIP(launch_cholesky(El, (int)mp.U, failp, dscr, st));       // X[x][u]
+        TNSLQ_HIP(launch_cholesky(Er, (int)mp.V, failp + 1, dscr, st));   // Y[y][v]
+        X = El;
+        Y = Er;
+        Xt = Eln;
+        TNSLQ_HIP(launch_swap01(El, 1, mp.U, mp.U, 1, 0, Xt, st));        // X^T (rows u, columns x)
+    }
+    // block A: R_A[kA][u][m]
+    if (mp.A.tr) {
+        double2 *Ta = mps_sweep(mp, T, mp.A, X, ws, st, rc);
+        if (rc) return rc;
+        if ((rc = mps_vertical_transfer(Ta, mp.U, mp.Mb, buf(mp.off_RA), buf(mp.off_G), failp + 2, dscr, st)))
+            return rc;
+    } else {
+        const double2 *SA;
+        if (X) {
+            if ((rc = mps_section(mp, T, Xt, mp.U, mp.A.sites.data(), (int)mp.A.sites.size(), buf(mp.off_SA), s0, s1,
+                                  st)))
+                return rc;
+            SA = buf(mp.off_SA);
+        } else if ((rc = mps_section_of(mp, T, mp.A, buf(mp.off_SA), s0, s1, st, &SA))) {
+            return rc;
+        }
+        if ((rc = mps_vertical(SA, mp.U, mp.A.p, mp.Mb, mp.A.comp, buf(mp.off_RA), s0, buf(mp.off_G), s1, mp.smax,
+                               failp + 2, dscr, st)))
+            return rc;
+    }
+    // block B: R_B[kB][n][v]
+    if (mp.B.tr) {
+        double2 *Tb = mps_sweep(mp, T, mp.B, nullptr, ws, st, rc);
+        if (rc) return rc;
+        if (Y) {
+            double2 *Tn = Tb == buf(mp.off_Tt[0]) ? buf(mp.off_Tt[1]) : buf(mp.off_Tt[0]);
+            TNSLQ_HIP(launch_transfer_absorb_right(Tb, Y, mp.Nb, mp.V, mp.V, Tn, buf(mp.off_At),
+                                                   (double *)(ws + mp.off_fail + 72), st));
+            Tb = Tn;
+        }
+        if ((rc = mps_vertical_transfer(Tb, mp.Nb, mp.V, buf(mp.off_RB), buf(mp.off_G), failp + 3, dscr, st)))
+            return rc;
+    } else {
+        const double2 *SB;
+        if ((rc = mps_section_of(mp, T, mp.B, s2, s0, s1, st, &SB))) return rc;
+        if (Y) {
+            TNSLQ_HIP(launch_zgemm(0, 0, SB, Y, buf(mp.off_SB), (int)(mp.Nb * mp.B.p), (int)mp.V, (int)mp.V, mp.V,
+                                   mp.V, mp.V, 1, 0, 0, 0, st));
+            SB = buf(mp.off_SB);
+        }
+        if ((rc = mps_vertical(SB, mp.Nb, mp.B.p, mp.V, mp.B.comp, buf(mp.off_RB), s0, buf(mp.off_G), s1, mp.smax,
+                               failp + 3, dscr, st)))
+            return rc;
+    }
+    const bool gap = mp.b0 > mp.a1;
+    // the gap: W[m][n][w]
+    if (gap) {
+        if (mp.G.tr) {
+            double2 *Tg = mps_sweep(mp, T, mp.G, nullptr, ws, st, rc);
+            if (rc) return rc;
+            if ((rc = mps_trace_factor_transfer(Tg, mp.Mb, mp.Nb, buf(mp.off_W), failp + 3, dscr, st))) return rc;
+        } else {
+            const double2 *SG;
+            if ((rc = mps_section_of(mp, T, mp.G, buf(mp.off_SG), s0, s1, st, &SG))) return rc;
+            if ((rc = mps_trace_factor(SG, mp.Mb, mp.G.p, mp.Nb, mp.G.comp, buf(mp.off_W), s2, buf(mp.off_G),
+                                       failp + 3, dscr, st)))
+                return rc;
+        }
+    }
+    // a ring's outer section: Z[v][u][z]
+    if (mp.closed) {
+        if (mp.O.sites.empty()) {
+            TNSLQ_HIP(launch_identity(buf(mp.off_Z), mp.V, st));
+        } else if (mp.O.tr) {
+            double2 *To = mps_sweep(mp, T, mp.O, nullptr, ws, st, rc);
+            if (rc) return rc;
+            if ((rc = mps_trace_factor_transfer(To, mp.V, mp.U, buf(mp.off_Z), failp + 3, dscr, st))) return rc;
+        } else {
+            const double2 *SO;
+            if ((rc = mps_section_of(mp, T, mp.O, buf(mp.off_SO), s0, s1, st, &SO))) return rc;
+            if ((rc = mps_trace_factor(SO, mp.V, mp.O.p, mp.U, mp.O.comp, buf(mp.off_Z), s2, buf(mp.off_G),
+                                       failp + 3, dscr, st)))
+                return rc;
+        }
+    }
     f.kA = mp.kA;
     f.kB = mp.kB;
-    f.V = mp.V;
-    f.M = mp.Nb;
-    if (mp.b0 == mp.a1) {
-        f.P = buf(mp.off_RA);
-        f.Up = mp.U;
+    f.Up = mp.Up;
+    f.M = mp.Mf;
+    f.V = mp.Vf;
+    // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)]
+    const int64_t nrow = mp.kA * mp.U;
+    if (gap)
+        TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_W), buf(mp.off_T1), (int)nrow, (int)(mp.Nb * mp.Wd),
+                               (int)mp.Mb, mp.Mb, mp.Nb * mp.Wd, mp.Nb * mp.Wd, 1, 0, 0, 0, st));
+    if (!mp.closed) {
+        TNSLQ_HIP(launch_swap01(buf(mp.off_RB), 1, mp.kB, mp.Nb, mp.V, 0, buf(mp.off_RBp), st));   // [n][kB][v]
+        f.Q = buf(mp.off_RB);
+        f.Qp = buf(mp.off_RBp);
+        if (!gap) {
+            f.P = buf(mp.off_RA);
+        } else {
+            TNSLQ_HIP(launch_swap01(buf(mp.off_T1), nrow, mp.Nb, mp.Wd, 1, 0, buf(mp.off_P), st));   // [(kA, u)][w][n]
+            f.P = buf(mp.off_P);
+        }
         return TNSLQ_OK;
     }
-    // the gap section S_G[m][g][n] and its tensor W[m][n][w]
-    if ((rc = mps_section(mp, T, T + mp.off[mp.a1], mp.Mb * mp.p[mp.a1], mp.a1 + 1, mp.b0, buf(mp.off_SG), s0, s1, st)))
-        return rc;
-    const double2 *SG = mp.b0 - mp.a1 > 1 ? buf(mp.off_SG) : T + mp.off[mp.a1];
-    TNSLQ_HIP(launch_swap01(SG, mp.Mb, mp.pG, mp.Nb, 1, 0, buf(mp.off_W), st));   // [m][n][g]
-    if (mp.compG) {
-        const int64_t n = mp.Mb * mp.Nb;
-        TNSLQ_HIP(launch_zgemm(0, 2, buf(mp.off_W), buf(mp.off_W), buf(mp.off_G), (int)n, (int)n, (int)mp.pG, mp.pG,
-                               mp.pG, n, 1, 0, 0, 0, st));
-        TNSLQ_HIP(launch_cholesky(buf(mp.off_G), (int)n, failp + 3, dscr, st));
-        TNSLQ_HIP(hipMemcpyAsync(buf(mp.off_W), buf(mp.off_G), (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
+    // ring: Q[(kB, n)][(u, z)] = sum_v R_B[(kB, n)][v] Z[v][(u, z)], Qp = [(n, u)][kB][z]
+    const int64_t uz = mp.U * mp.Zd;
+    TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RB), buf(mp.off_Z), buf(mp.off_Q2), (int)(mp.kB * mp.Nb), (int)uz,
+                           (int)mp.V, mp.V, uz, uz, 1, 0, 0, 0, st));
+    TNSLQ_HIP(launch_swap01(buf(mp.off_Q2), 1, mp.kB, mp.Mf, mp.Zd, 0, buf(mp.off_Q2p), st));
+    if (gap) {
+        // P[a][w][n][u] = T1[a][u][n][w]
+        const int64_t d[4] = {mp.kA, mp.U, mp.Nb, mp.Wd};
+        const int perm[4] = {0, 3, 2, 1};
+        TNSLQ_HIP(launch_permute4(buf(mp.off_T1), d, perm, buf(mp.off_P), st));
+    } else {
+        // P[a][m][u] = R_A[a][u][m] (w of size 1)
+        TNSLQ_HIP(launch_swap01(buf(mp.off_RA), mp.kA, mp.U, mp.Mb, 1, 0, buf(mp.off_P), st));
     }
-    // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)], then P[(kA, u)][w][n]
-    const int64_t nrow = mp.kA * mp.U;
-    TNSLQ_HIP(launch_zgemm(0, 0, buf(mp.off_RA), buf(mp.off_W), buf(mp.off_T1), (int)nrow, (int)(mp.Nb * mp.Wd),
-                           (int)mp.Mb, mp.Mb, mp.Nb * mp.Wd, mp.Nb * mp.Wd, 1, 0, 0, 0, st));
-    TNSLQ_HIP(launch_swap01(buf(mp.off_T1), nrow, mp.Nb, mp.Wd, 1, 0, buf(mp.off_P), st));
     f.P = buf(mp.off_P);
-    f.Up = mp.U * mp.Wd;
+    f.Q = buf(mp.off_Q2);
+    f.Qp = buf(mp.off_Q2p);
     return TNSLQ_OK;
 }
 
@@ -2124,7 +2374,7 @@ int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int
     TNSLQ_HIP(launch_zgemm(0, 0, f.P, f.Qp, Tout, (int)nrow, (int)ncol, (int)f.M, f.M, ncol, ncol, 1, 0, 0, 0, st));
     double *part = (double *)(ws + mp.off_part);
     TNSLQ_HIP(launch_sumsq(Tout, nrow * ncol, part, st));
-    TNSLQ_HIP(launch_assemble(Tout, mp.kA, mp.U, mp.Wd, mp.kB, mp.V, int64_t(1) << mp.q[0], int64_t(1) << mp.q[1],
+    TNSLQ_HIP(launch_assemble(Tout, mp.kA, 1, mp.Up, mp.kB, mp.Vf, int64_t(1) << mp.q[0], int64_t(1) << mp.q[1],
                               int64_t(1) << mp.q[2], part + 256, (double2 *)psi_dev, st));
     return mps_check(mp, ws, st);
 }
@@ -2148,13 +2398,12 @@ static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b
     pl.K = opt->n_probes;
     pl.m = opt->n_steps;
     pl.reorth = opt->reorth;
-    const bool gap = mp.b0 > mp.a1;
     pl.dA = mp.kA;
     pl.dB = mp.kB;
     pl.dAB = mp.kA * mp.kB;
-    pl.mUp = gap ? mp.U * mp.Wd : mp.U;
-    pl.mM = gap ? mp.Nb : mp.Mb;
-    pl.mV = mp.V;
+    pl.mUp = mp.Up;
+    pl.mM = mp.Mf;
+    pl.mV = mp.Vf;
     pl.dE = pl.mUp * pl.mV;
     pl.D = pl.dAB * pl.dE;
     pl.mps_bytes = mp.total;

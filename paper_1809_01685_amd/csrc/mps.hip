@@ -1,22 +1,28 @@
-// Contiguous blocks of an open-boundary matrix product state (Sec. VI): the
-// compressed form of rho_AB^{T_B}, as two factors P, Q of an effective state
-// whose partially transposed density matrix has the same nonzero spectrum
-// (applied in factorised form, or contracted into that state).
+// Contiguous blocks of a matrix product state, open or periodic (Sec. VI):
+// the compressed form of rho_AB^{T_B}, as two factors P, Q of an effective
+// state whose partially transposed density matrix has the same nonzero
+// spectrum (applied in factorised form, or contracted into that state).
 //
 // All of it is FP64 linear algebra on tensors of bond dimension chi:
-//   * transfer sweeps for the traced environments left of A and right of B,
-//     E <- sum_s M_s^T E conj(M_s) (two complex products per site);
+//   * transfer sweeps for the traced environments left of A and right of B
+//     of an open chain, E <- sum_s M_s^T E conj(M_s) (two complex products
+//     per site);
+//   * transfer matrices of whole sections, T[(x, x')][y'][y] (chi^4 entries),
+//     one site at a time (one complex product and chi^2 small batched ones per
+//     site), for blocks, gaps and the ring's outer section of any length:
+//     the Gram matrix of a block and the factored matrix of a traced section
+//     are T with its four axes regrouped;
 //   * Cholesky factors of positive semidefinite matrices (environments, Gram
-//     matrices of the blocks and of the gap), blocked: panels of 32 columns
-//     in one workgroup, the solve below them and the trailing update across
-//     the GPU;
+//     matrices of the blocks, of the gap and of a ring's outer section),
+//     blocked: panels of 32 columns in one workgroup, the solve below them
+//     and the trailing update across the GPU;
 //   * complex matrix products C = op(A) op(B), batched, op in {N, T, C}
 //     (64 x 64 output tiles staged through LDS, FP64 matrix instructions),
 //     for the block sections, their Gram matrices, the effective state and
 //     the factorised operator;
 //   * the factor normalisation Re sum Ahat conj(C);
-//   * an axis exchange, and the final scatter of the effective state into a
-//     zero-padded power-of-two layout, normalised.
+//   * axis exchanges and permutations, and the final scatter of the effective
+//     state into a zero-padded power-of-two layout, normalised.
 // The host side (api.hip) plans the sizes and sequences these launches.
 #include "tnslq_internal.h"
 
@@ -371,6 +377,86 @@ __global__ void __launch_bounds__(256) k_assemble(const double2 *__restrict__ T,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Transfer matrices of sections (the first step of Sec. VI's lateral
+// compression): T[(x, x')][y'][y] = sum_s S[x][s][y] conj(S[x'][s][y']) for a
+// section S with left bond x and right bond y, built one site at a time.
+
+// T0[(u, u')][z'][z] = X[z][u] conj(X[z'][u']) for an n x n factor X (the
+// identity when X is null): the transfer matrix of no sites with X absorbed
+// on the left bond.
+__global__ void __launch_bounds__(256) k_transfer_start(const double2 *__restrict__ X, int64_t n,
+                                                        double2 *__restrict__ T) {
+    const int64_t total = n * n * n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t z = e % n, zp = (e / n) % n, up = (e / (n * n)) % n, u = e / (n * n * n);
+        double2 v;
+        if (X) {
+            const double2 a = X[z * n + u], b = X[zp * n + up];
+            v = cmul(a, cconj(b));
+        } else {
+            v = make_double2(z == u && zp == up ? 1.0 : 0.0, 0.0);
+        }
+        T[e] = v;
+    }
+}
+
+// s = sum_{a < x, c < y} Re T[(a, a)][c][c] (one block; 256 partial sums
+// combined in a fixed order).
+__global__ void __launch_bounds__(256) k_transfer_trace(const double2 *__restrict__ T, int64_t x, int64_t y,
+                                                        double *__restrict__ s) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < x * y; e += 256) {
+        const int64_t a = e / y, c = e % y;
+        acc += T[((a * x + a) * y + c) * y + c].x;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s[0] = sh[0];
+}
+
+// x /= s[0] where s[0] > 0 (a zero or non-finite trace leaves x as it is; the
+// factorisation then reports what it finds)
+__global__ void __launch_bounds__(256) k_scale_inv(double2 *__restrict__ x, int64_t n, const double *__restrict__ s) {
+    const double t = s[0];
+    if (!(t > 0.0) || !isfinite(t)) return;
+    const double f = 1.0 / t;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        x[e].x *= f;
+        x[e].y *= f;
+    }
+}
+
+// out = in with its four axes permuted: in has shape d[0..3], out axis j is
+// in axis perm[j] (out shape d[perm[0]], ..., d[perm[3]]).
+struct Perm4 {
+    int64_t od[4];   // out shape
+    int64_t is[4];   // in stride of out axis j
+};
+__global__ void __launch_bounds__(256) k_permute4(const double2 *__restrict__ in, Perm4 p, int64_t total,
+                                                  double2 *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = e, off = 0;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            off += (r % p.od[j]) * p.is[j];
+            r /= p.od[j];
+        }
+        out[e] = in[off];
+    }
+}
+
+// out[i][j] = delta(i, j), n x n
+__global__ void __launch_bounds__(256) k_identity(double2 *__restrict__ out, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = make_double2(e / n == e % n ? 1.0 : 0.0, 0.0);
+}
+
 unsigned blocks_for(int64_t n) {
     int64_t g = (n + 255) / 256;
     if (g < 1) g = 1;
@@ -505,6 +591,84 @@ hipError_t launch_assemble(const double2 *T, int64_t kA, int64_t U, int64_t W, i
     const int64_t total = dA2 * dB2 * dE2;
     hipLaunchKernelGGL(k_assemble, dim3(blocks_for(total)), dim3(256), 0, st, T, kA, U, W, kB, V, dB2, dE2, total, sumsq,
                        psi);
+    return hipGetLastError();
+}
+
+// Batched C[b] = op(A) B[b] in chunks of at most 65535 batch entries (the
+// grid's z limit).
+static hipError_t zgemm_batches(int opa, const double2 *A, const double2 *B, double2 *C, int M, int N, int K,
+                                int64_t lda, int64_t ldb, int64_t ldc, int64_t batch, int64_t sb, int64_t sc,
+                                hipStream_t st) {
+    for (int64_t b0 = 0; b0 < batch; b0 += 65535) {
+        const int nb = (int)(batch - b0 < 65535 ? batch - b0 : 65535);
+        hipError_t e = launch_zgemm(opa, 0, A, B + b0 * sb, C + b0 * sc, M, N, K, lda, ldb, ldc, nb, 0, sb, sc, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t scale_by_transfer_trace(double2 *T, int64_t x, int64_t y, double *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_transfer_trace, dim3(1), dim3(256), 0, st, T, x, y, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = x * x * y * y;
+    hipLaunchKernelGGL(k_scale_inv, dim3(blocks_for(n)), dim3(256), 0, st, T, n, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_transfer_start(const double2 *X, int64_t n, double2 *T, double *s, hipStream_t st) {
+    const int64_t total = n * n * n * n;
+    hipLaunchKernelGGL(k_transfer_start, dim3(blocks_for(total)), dim3(256), 0, st, X, n, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scale_by_transfer_trace(T, n, n, s, st);
+}
+
+// One site M[z][s][y] (cz x p x cy) onto T[(x, x')][z'][z]:
+//   A[(r, z')][(s, y)] = sum_z T[(r, z')][z] M[z][(s, y)]          (one product)
+//   Tnew[r][y'][y]     = sum_(z', s) conj(M[(z', s)][y']) A[r][(z', s)][y]  (x^2 products)
+// then Tnew divided by its trace.  x^2 p cz cy (cz + cy) complex multiply-adds.
+hipError_t launch_transfer_step(const double2 *T, const double2 *M, int64_t x, int64_t cz, int64_t p, int64_t cy,
+                                double2 *Tnew, double2 *A, double *s, hipStream_t st) {
+    const int64_t r = x * x, pcy = p * cy;
+    hipError_t e = launch_zgemm(0, 0, T, M, A, (int)(r * cz), (int)pcy, (int)cz, cz, pcy, pcy, 1, 0, 0, 0, st);
+    if (e != hipSuccess) return e;
+    if ((e = zgemm_batches(2, M, A, Tnew, (int)cy, (int)cy, (int)(cz * p), cy, cy, cy, r, cz * pcy, cy * cy, st)) !=
+        hipSuccess)
+        return e;
+    return scale_by_transfer_trace(Tnew, x, cy, s, st);
+}
+
+// T -> T' of the section S Y (Y: cy x cv): H[(r, y')][v] = sum_y T[(r, y')][y]
+// Y[y][v], T'[r][v'][v] = sum_y' conj(Y[y'][v']) H[r][y'][v].
+hipError_t launch_transfer_absorb_right(const double2 *T, const double2 *Y, int64_t x, int64_t cy, int64_t cv,
+                                        double2 *Tnew, double2 *H, double *s, hipStream_t st) {
+    const int64_t r = x * x;
+    hipError_t e = launch_zgemm(0, 0, T, Y, H, (int)(r * cy), (int)cv, (int)cy, cy, cv, cv, 1, 0, 0, 0, st);
+    if (e != hipSuccess) return e;
+    if ((e = zgemm_batches(2, Y, H, Tnew, (int)cv, (int)cv, (int)cy, cv, cv, cv, r, cy * cv, cv * cv, st)) !=
+        hipSuccess)
+        return e;
+    return scale_by_transfer_trace(Tnew, x, cv, s, st);
+}
+
+hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st) {
+    Perm4 p;
+    int64_t stride[4];
+    stride[3] = 1;
+    for (int j = 2; j >= 0; --j) stride[j] = stride[j + 1] * d[j + 1];
+    for (int j = 0; j < 4; ++j) {
+        if (perm[j] < 0 || perm[j] > 3) return hipErrorInvalidValue;
+        p.od[j] = d[perm[j]];
+        p.is[j] = stride[perm[j]];
+    }
+    const int64_t total = d[0] * d[1] * d[2] * d[3];
+    hipLaunchKernelGGL(k_permute4, dim3(blocks_for(total)), dim3(256), 0, st, in, p, total, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(double2 *out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_identity, dim3(blocks_for(n * n)), dim3(256), 0, st, out, n);
     return hipGetLastError();
 }
 

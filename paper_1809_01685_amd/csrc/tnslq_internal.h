@@ -225,6 +225,22 @@ hipError_t launch_transfer(int left, const double2 *E, const double2 *M, int cx,
 // is never cleared here.  dmax: one device double of scratch (calls on one
 // stream may share it).
 hipError_t launch_cholesky(double2 *A, int n, int *fail, double *dmax, hipStream_t st);
+// Transfer matrices of MPS sections, T[(x, x')][y'][y] = sum_s S[x][s][y]
+// conj(S[x'][s][y']) (row-major, x^2 y^2 entries), each divided by its trace
+// sum_{a, c} T[(a, a)][c][c] (s: one device double of scratch):
+//   start: no sites, X (n x n, or the identity when null) absorbed on the
+//     left bond: T[(u, u')][z'][z] = X[z][u] conj(X[z'][u']);
+//   step: one site M (cz x p x cy) appended (A: x^2 cz p cy scratch entries);
+//   absorb_right: the section S Y for Y (cy x cv) (H: x^2 cy cv entries).
+hipError_t launch_transfer_start(const double2 *X, int64_t n, double2 *T, double *s, hipStream_t st);
+hipError_t launch_transfer_step(const double2 *T, const double2 *M, int64_t x, int64_t cz, int64_t p, int64_t cy,
+                                double2 *Tnew, double2 *A, double *s, hipStream_t st);
+hipError_t launch_transfer_absorb_right(const double2 *T, const double2 *Y, int64_t x, int64_t cy, int64_t cv,
+                                        double2 *Tnew, double2 *H, double *s, hipStream_t st);
+// out = in (shape d[0..3]) with out axis j = in axis perm[j].
+hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st);
+// out = the n x n identity.
+hipError_t launch_identity(double2 *out, int64_t n, hipStream_t st);
 // C[b] = op(A[b]) op(B[b]) (with sub: C[b] -= op(A[b]) op(B[b])), op 0 = as
 // stored, 1 = transpose, 2 = conjugate transpose (supported pairs: (0,0),
 // (1,0), (2,0), (0,2)); op(A) is M x K.  With ks > 1 the reduction is split

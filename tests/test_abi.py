@@ -302,6 +302,49 @@ def test_mps_sizes_and_validation_without_device(L):
     assert L.tnslq_mps_effective_state(C.byref(desc(phys, bond)), 2, 4, 6, 4, None, None, 0, None) == -1
 
 
+def test_mps_rings_and_section_routes_without_device(L):
+    import ctypes as C
+
+    def desc(phys, bond, sections=0):
+        pp = (C.c_int * len(phys))(*phys)
+        bb = (C.c_int * len(bond))(*bond)
+        m = T.Mps(len(phys), pp, bb, None, sections)
+        m._keep = (pp, bb)
+        return m
+    q = (C.c_int * 3)()
+    n = C.c_size_t(0)
+    # a ring of 10 qubits, every bond 3: A = [1, 4), B = [5, 8), outer
+    # section [8, 10) + [0, 1) (2^3 = 8 <= 9: kept whole, d_Z = 8), gap [4, 5)
+    # (2 <= 9, d_W = 2); A and B compressed (8 <= 9: no, kept whole)
+    phys, bond = [2] * 10, [3] * 11
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond)), 1, 3, 5, 3, q, C.byref(n)) == 0
+    assert list(q) == [3, 3, 4]                      # E' = (w, z) = 2 x 8
+    # blocks covering the ring: the outer section is the identity, E' = 1
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond)), 0, 5, 5, 5, q, C.byref(n)) == 0
+    assert list(q) == [4, 4, 0]                      # compressed blocks: 3 x 3 = 9 -> 16
+    # route values outside the enumeration
+    for bad in (-1, 3):
+        assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, bad)), 1, 3, 5, 3, q, C.byref(n)) == -1
+    # 200 qubits, bond 4: blocks of 80 sites reach only the transfer route
+    phys, bond = [2] * 200, [1, 2] + [4] * 197 + [2, 1]
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 0)), 10, 80, 90, 80, q, C.byref(n)) == 0
+    assert list(q) == [4, 4, 4]
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 2)), 10, 80, 90, 80, q, C.byref(n)) == 0
+    assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 1)), 10, 80, 90, 80, q, C.byref(n)) == -1
+    assert "transfer route" in T.tnslq_last_error()
+    # factored matrices up to 16384 wide: bond 128 around a compressed block
+    # of 17 sites (2^17 > 128 x 128; with bond 256, 2^17 > 256 x 256 too)
+    o = T.make_options(2, 4, precision="fp64")
+    for chi, ok in ((128, True), (256, False)):
+        bond = [1] + [min(2 ** min(i, 40 - i), chi) for i in range(1, 40)] + [1]
+        tensors = [np.zeros((bond[i], 2, bond[i + 1])) for i in range(40)]
+        if ok:
+            assert T.tnslq_workspace_bytes_mps(tensors, 8, 17, 25, 13, o) > 0
+        else:
+            with pytest.raises(T.TnslqError, match="16384"):
+                T.tnslq_workspace_bytes_mps(tensors, 8, 17, 25, 13, o)
+
+
 def test_factored_mps_workspace_and_validation_without_device(L):
     import ctypes as C
     # the same chain: the factorised route needs no room for the dense state

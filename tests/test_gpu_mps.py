@@ -195,3 +195,134 @@ def test_factored_route_is_deterministic(dev):
         r2 = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 4, 10, device=dev, seed=3, precision=prec)
         assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
         assert r1["logneg"] == r2["logneg"]
+
+
+# ------------------------------------------------------------------ rings
+PERIODIC = [
+    (8, 3, 0, 3, 3, 5),      # the blocks cover the ring: identity outer section
+    (8, 3, 1, 3, 4, 3),      # adjacent, outer section of 2 sites kept whole
+    (10, 2, 1, 3, 5, 3),     # gap 1, outer section of 3 sites compressed
+    (10, 3, 2, 2, 6, 2),     # gap 2, outer section of 4 sites compressed
+    (12, 2, 2, 4, 7, 4),     # both blocks compressed, gap 1, outer of 3 sites
+    (10, 2, 0, 4, 4, 6),     # blocks compressed, covering the ring
+]
+
+
+@pytest.mark.parametrize("L,chi,a0,LA,b0,LB", PERIODIC)
+@pytest.mark.parametrize("sections", ["explicit", "transfer", "auto"])
+def test_periodic_effective_state_matches_oracle(dev, L, chi, a0, LA, b0, LB, sections):
+    ts = ti.random_mps_periodic(L, 2, chi, 3 * L + chi)
+    print("ring", L, chi, a0, LA, b0, LB, sections, flush=True)
+    psi, q = T.tnslq_mps_effective_state(ts, a0, LA, b0, LB, device=dev, sections=sections)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB, transfer=sections == "transfer")
+    want = _padded(Pe, q)
+    got = psi.cpu().numpy().reshape(want.shape)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("L,chi,a0,LA,b0,LB", [PERIODIC[0], PERIODIC[2], PERIODIC[4]])
+def test_periodic_factored_logneg_matches_oracle(dev, L, chi, a0, LA, b0, LB):
+    # the ring's factors P[a][w][(n, u)], Q[b][(n, u)][z]: the same operator as
+    # the oracle's effective state, coefficients to 1e-10 (reorthogonalised,
+    # up to the first near-breakdown as in the open-chain test)
+    ts = ti.random_mps_periodic(L, 2, chi, 3 * L + chi)
+    K, m = 6, 14
+    print("ring factored", L, chi, a0, LA, b0, LB, flush=True)
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=9, reorth=True)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=9, reorth=True)
+    ascale, bscale = np.max(np.abs(o["alpha"])), np.max(np.abs(o["beta"][:, 1:]))
+    for k in range(K):
+        small = np.nonzero(o["beta"][k, 1:] < 1e-6 * bscale)[0]
+        jk = min(m, small[0] + 1) if small.size else m
+        assert np.max(np.abs(g["alpha"][k, :jk] - o["alpha"][k, :jk])) <= 1e-10 * ascale
+        assert np.max(np.abs(g["beta"][k, :jk + 1] - o["beta"][k, :jk + 1])) <= 1e-10 * bscale
+    assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-10 * max(abs(o["logneg"]), 1.0))
+    # and the estimate against the exact value of the dense ring
+    psi = mps.mps_to_dense(ts)
+    e = exact.logneg_exact(exact.regroup(psi / np.linalg.norm(psi), L, list(range(a0, a0 + LA)),
+                                         list(range(b0, b0 + LB))))
+    assert abs(g["logneg"] - e) <= 4 * g["logneg_se"] + 0.05 * max(abs(e), 1.0)
+
+
+# ------------------------------------------------- the transfer-matrix route
+@pytest.mark.parametrize("L,chi,a0,LA,b0,LB", GEOMETRIES)
+def test_transfer_route_matches_oracle(dev, L, chi, a0, LA, b0, LB):
+    ts = ti.random_mps(L, 2, chi, L + chi)
+    print("transfer", L, chi, a0, LA, b0, LB, flush=True)
+    psi, q = T.tnslq_mps_effective_state(ts, a0, LA, b0, LB, device=dev, sections="transfer")
+    want = _padded(mps.effective_state(ts, a0, LA, b0, LB, transfer=True), q)
+    got = psi.cpu().numpy().reshape(want.shape)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_long_random_blocks_match_oracle(dev, periodic):
+    # blocks of 40 sites (2^40 physical values: only the transfer route), an
+    # open chain of 120 sites with bond 8, and a ring of 60 sites with bond 4
+    # whose outer section has 15 sites
+    if periodic:
+        ts = ti.random_mps_periodic(60, 2, 4, 21)
+        a0, LA, b0, LB = 5, 20, 30, 20
+    else:
+        ts = ti.random_mps(120, 2, 8, 20)
+        a0, LA, b0, LB = 10, 40, 52, 40
+    print("long blocks", periodic, flush=True)
+    psi, q = T.tnslq_mps_effective_state(ts, a0, LA, b0, LB, device=dev)
+    Pe = mps.effective_state(ts, a0, LA, b0, LB, transfer=True)
+    want = _padded(Pe, q)
+    got = psi.cpu().numpy().reshape(want.shape)
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+    K, m = 6, 12
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=3, reorth=True)
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=3, reorth=True)
+    assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-8 * max(abs(o["logneg"]), 1.0))
+
+
+def _pair_logneg(c):
+    s = np.linalg.svd(c, compute_uv=False)
+    return 2.0 * np.log2(np.sum(s))
+
+
+def test_long_blocks_closed_forms(dev):
+    # qubit pairs: E is that of the pair the A|B boundary cuts (and, on a
+    # ring whose blocks cover it, of the pair closing it); a GHZ ring has one
+    # bit between blocks that cover it and none otherwise.  The device's
+    # effective state (blocks of 20 to 40 sites, the transfer route) carries
+    # that value exactly: its partial transpose's spectrum, summed
+    def e_dev(ts, a0, LA, b0, LB, sections="auto"):
+        psi, q = T.tnslq_mps_effective_state(ts, a0, LA, b0, LB, device=dev, sections=sections)
+        return exact.logneg_exact(psi.cpu().numpy().reshape(1 << q[0], 1 << q[1], 1 << q[2]))
+    ts, pairs = ti.dimer_mps(80, 11, offset=0)
+    c = dict(pairs)
+    assert e_dev(ts, 5, 30, 35, 34) == pytest.approx(_pair_logneg(c[(34, 35)]), abs=1e-12)
+    assert e_dev(ts, 5, 30, 36, 34) == pytest.approx(0.0, abs=1e-12)
+    ts, pairs = ti.dimer_mps(80, 12, offset=1, periodic=True)
+    c = dict(pairs)
+    for (a0, LA, b0, LB), want in (((0, 40, 40, 40), _pair_logneg(c[(39, 40)]) + _pair_logneg(c[(79, 0)])),
+                                   ((1, 39, 40, 39), _pair_logneg(c[(39, 40)]))):
+        for sections in ("auto", "transfer"):
+            assert e_dev(ts, a0, LA, b0, LB, sections) == pytest.approx(want, abs=1e-12)
+    ts = ti.ghz_mps(60, True)
+    for (a0, LA, b0, LB), want in (((0, 25, 25, 35), 1.0), ((0, 25, 26, 34), 0.0), ((3, 20, 23, 30), 0.0)):
+        assert e_dev(ts, a0, LA, b0, LB) == pytest.approx(want, abs=1e-12)
+
+
+def test_wide_bonds_agree_between_routes(dev):
+    # bond 64 around compressed blocks of 13 sites (Gram matrices 4096 wide,
+    # the explicit section 2^25 entries): the two routes give the same
+    # effective operator up to rounding (its Gram matrices summed in other
+    # orders, then factored), so the same Lanczos coefficients on the same
+    # probes to the factorisation's amplification of that rounding
+    ts = ti.random_mps(40, 2, 64, 5)
+    a0, LA, b0, LB = 8, 13, 21, 13
+    out = {}
+    for sections in ("explicit", "transfer"):
+        print("wide bonds", sections, flush=True)
+        out[sections] = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 2, 6, device=dev, seed=4, reorth=True,
+                                           sections=sections)
+    a, b = out["explicit"], out["transfer"]
+    print("wide bonds", a["logneg"], b["logneg"], np.max(np.abs(a["alpha"] - b["alpha"])), flush=True)
+    assert np.max(np.abs(a["alpha"] - b["alpha"])) <= 1e-7 * np.max(np.abs(a["alpha"]))
+    assert np.max(np.abs(a["beta"] - b["beta"])) <= 1e-7 * np.max(np.abs(a["beta"]))
+    assert a["logneg"] == pytest.approx(b["logneg"], rel=1e-7)
