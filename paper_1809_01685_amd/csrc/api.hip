@@ -184,8 +184,9 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
     if (pl.kc_cap > 0) pl.kc = std::min(pl.kc, pl.kc_cap);
     // every chunk must start on a block of 128 rows (k, b') of Xt (lazy form:
-    // d_B is then a power of two)
-    if (!pl.expl && pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
+    // d_B is then a power of two, so below 128 it divides 128; the factorised
+    // MPS operator chunks its probes on its own, below)
+    if (!pl.expl && !pl.mpsf && pl.kc < K && (pl.kc * pl.dB) % BRICK_ROWS != 0) {
         const int q = (int)(BRICK_ROWS / pl.dB);
         pl.kc = std::min(K, (pl.kc + q - 1) / q * q);
     }
@@ -1112,9 +1113,30 @@ int do_layout(Ctx &c, const void *psi) {
         double2 *Ah = (double2 *)(c.ws + pl.off_nrm), *Cq = Ah + pl.mM * pl.mM;
         double *nrm = (double *)(Cq + pl.mM * pl.mM);
         const int M = (int)f.M;
-        const int64_t rowsP = f.kA * f.Up, colsQ = f.kB * f.V;
-        TNSLQ_HIP(launch_zgemm(2, 0, f.P, f.P, Ah, M, M, (int)rowsP, M, M, M, 1, 0, 0, 0, c.st));
-        TNSLQ_HIP(launch_zgemm(0, 2, f.Qp, f.Qp, Cq, M, M, (int)colsQ, colsQ, colsQ, M, 1, 0, 0, 0, c.st));
+        const int64_t rowsP = f.kA * f.Up, colsQ = f.kB * f.V, mm = (int64_t)M * M;
+        // M x M outputs over long reductions (k^2 chi terms): split until the
+        // products fill the chip, partials in the still unused intermediate Z2
+        const int64_t tiles = ((M + 63) / 64) * ((M + 63) / 64);
+        const int64_t cap = (int64_t)(pl.kc * pl.mUp * pl.mM * pl.mM * pl.mV * (pl.prec == TNSLQ_FP32 ? 8 : 16) / 16);
+        auto splits = [&](int64_t K) {
+            int ks = 1;
+            while (tiles * ks < 1024 && K / (2 * ks) >= 256 && 2 * ks * mm <= cap && 2 * ks <= 1024) ks *= 2;
+            return ks;
+        };
+        const int ksA = splits(rowsP), ksC = splits(colsQ);
+        if (ksA > 1) {
+            TNSLQ_HIP(launch_zgemm(2, 0, f.P, f.P, c.Z2, M, M, (int)rowsP, M, M, M, 1, 0, 0, 0, c.st, 0, ksA, mm));
+            TNSLQ_HIP(launch_sum_splits(c.Z2, ksA, mm, Ah, c.st));
+        } else {
+            TNSLQ_HIP(launch_zgemm(2, 0, f.P, f.P, Ah, M, M, (int)rowsP, M, M, M, 1, 0, 0, 0, c.st));
+        }
+        if (ksC > 1) {
+            TNSLQ_HIP(
+                launch_zgemm(0, 2, f.Qp, f.Qp, c.Z2, M, M, (int)colsQ, colsQ, colsQ, M, 1, 0, 0, 0, c.st, 0, ksC, mm));
+            TNSLQ_HIP(launch_sum_splits(c.Z2, ksC, mm, Cq, c.st));
+        } else {
+            TNSLQ_HIP(launch_zgemm(0, 2, f.Qp, f.Qp, Cq, M, M, (int)colsQ, colsQ, colsQ, M, 1, 0, 0, 0, c.st));
+        }
         TNSLQ_HIP(launch_normalise_factor(Ah, Cq, (int64_t)M * M, nrm, f.P, rowsP * M, c.st));
         if (pl.prec == TNSLQ_FP32) {
             TNSLQ_HIP(launch_to_c64(f.P, rowsP * M, c.P32, c.st));

@@ -52,6 +52,14 @@
         state, then the split-BF16 estimate) against the factorised operator
         (FP64), both to +-1% by the exponential-fit rule.
 
+    python -m paper_1809_01685_amd.experiments mps_long
+        Long blocks at the size of Sec. VII.C's Heisenberg chain: a 1000-site
+        random open MPS with bond 32, 64 and 116, adjacent blocks of 20, 100
+        and 400 sites at its centre (their Gram matrices from transfer
+        sweeps), the factorised operator in FP32 to +-1% by the fit rule;
+        then rings of 200 sites, bond 8 and 12, blocks of 40 sites 10 apart
+        and a 110-site outer section.
+
     python -m paper_1809_01685_amd.experiments arith_peaks
         Achievable arithmetic rates of this GPU (libtnslq_peak): dependent
         loops of the BF16, FP32 and FP64 matrix instructions the contractions
@@ -514,6 +522,55 @@ def run_mps_blocks(seed=0, n_probes=8, n_steps=40, precision="bf16x3", routes=("
             "precision_dense": precision, "precision_factored": "fp64", "rows": rows}
 
 
+def run_mps_long(seed=0, n_probes=2, n_steps=10, chis=(32, 64, 116), lengths=(20, 100, 400), n_sites=1000,
+                 rings=True):
+    """Long blocks (Sec. VI at the size of its Heisenberg-chain study: 1000
+    sites, bonds up to 116, adjacent blocks): seeded random tensors stand in
+    for the DMRG ground state.  A = [L/2 - l, L/2), B = [L/2, L/2 + l); the
+    blocks' Gram matrices come from transfer sweeps (their explicit sections
+    would hold 2^l bond^2 entries).  The factorised operator in FP32, the
+    fit rule with a 1% target; t_layout_ms is the whole factor construction
+    (environment sweeps, block sweeps, Cholesky factors, normalisation).
+    Then rings of 200 sites (bond 8 and 12) with a gap and a 100-site outer
+    section."""
+    import torch
+    import tnslq_inputs as ti
+    from . import tnslq_logneg_mps
+    dev = torch.device("cuda:0")
+    rows = []
+
+    def one(ts, a0, la, b0, lb, row, prec):
+        t0 = time.perf_counter()
+        f = tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, n_steps, device=dev, seed=seed, stop_tol=0.01,
+                             stop_rule="fit", want_arrays=False, precision=prec)
+        torch.cuda.synchronize()
+        row.update({"precision": prec, "t_total_s": time.perf_counter() - t0, "t_layout_ms": f["t_layout_ms"],
+                    "t_matvec_ms": f["t_matvec_ms"], "steps": f["steps_done"],
+                    "ms_per_matvec": f["t_matvec_ms"] / max(f["steps_done"], 1), "logneg": f["logneg"],
+                    "logneg_se": f["logneg_se"], "lanczos_err": f["lanczos_err"],
+                    "workspace_bytes": f["workspace_bytes"]})
+        print(f"[mps_long] {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+        torch.cuda.empty_cache()
+
+    for chi in chis:
+        ts = ti.random_mps(n_sites, 2, chi, seed)
+        tnslq_logneg_mps(ts, n_sites // 2 - 20, 20, n_sites // 2, 20, n_probes, 2, device=dev, seed=seed,
+                         want_arrays=False, precision="fp32")   # warm-up
+        for la in lengths:
+            c = n_sites // 2
+            one(ts, c - la, la, c, la, {"chain": "open", "n_sites": n_sites, "chi": chi, "A": [c - la, c],
+                                       "B": [c, c + la]}, "fp32")
+    if rings:
+        for chi in (8, 12):
+            ts = ti.random_mps_periodic(200, 2, chi, seed + chi)
+            one(ts, 10, 40, 60, 40, {"chain": "ring", "n_sites": 200, "chi": chi, "A": [10, 50], "B": [60, 100],
+                                     "outer_sites": 110}, "fp64")
+    return {"workload": f"seeded random MPS of qubits: open chain of {n_sites} sites, adjacent blocks of "
+                        f"{list(lengths)} sites at its centre; rings of 200 sites",
+            "n_probes": n_probes, "n_steps": n_steps, "rows": rows}
+
+
 def _parse_range(s):
     if "-" in s:
         lo, hi = s.split("-")
@@ -543,6 +600,9 @@ def main(argv=None):
     sp = sub.add_parser("mps_blocks")
     sp.add_argument("--routes", default="dense,factored")
     sp.add_argument("--chi", default="", help="comma list: only the rows of these bond dimensions")
+    ml = sub.add_parser("mps_long")
+    ml.add_argument("--chi", default="32,64,116")
+    ml.add_argument("--lengths", default="20,100,400")
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
@@ -551,6 +611,9 @@ def main(argv=None):
     elif args.cmd == "mps_blocks":
         out = run_mps_blocks(routes=tuple(args.routes.split(",")),
                              chis=[int(x) for x in args.chi.split(",") if x] or None)
+    elif args.cmd == "mps_long":
+        out = run_mps_long(chis=[int(x) for x in args.chi.split(",")],
+                           lengths=[int(x) for x in args.lengths.split(",")])
     elif args.cmd == "hbm_peak":
         out = run_hbm_peak()
     elif args.cmd == "arith_peaks":

@@ -332,6 +332,11 @@ def test_mps_rings_and_section_routes_without_device(L):
     assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 2)), 10, 80, 90, 80, q, C.byref(n)) == 0
     assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 1)), 10, 80, 90, 80, q, C.byref(n)) == -1
     assert "transfer route" in T.tnslq_last_error()
+    # blocks whose compressed dimension is not a power of two and whose
+    # probes do not fit one chunk (d_A' = d_B' = 13456 at bond 116, 2 probes)
+    bond = [1] + [min(2 ** min(i, 60 - i), 116) for i in range(1, 60)] + [1]
+    tensors = [np.zeros((bond[i], 2, bond[i + 1])) for i in range(60)]
+    assert T.tnslq_workspace_bytes_mps(tensors, 10, 20, 30, 20, T.make_options(2, 4, precision="fp32")) > 0
     # factored matrices up to 16384 wide: bond 128 around a compressed block
     # of 17 sites (2^17 > 128 x 128; with bond 256, 2^17 > 256 x 256 too)
     o = T.make_options(2, 4, precision="fp64")
