@@ -239,6 +239,8 @@ typedef struct {
                                forming is part of t_layout_ms                  */
     int n_probes_used;      /* probes behind the estimate (n_probes, or a
                                multiple of it with max_probes)                 */
+    int mps_matvec;         /* tnslq_logneg_mps: the matvec that ran,
+                               TNSLQ_MPS_MATVEC_FACTORS or _NETWORK; else 0    */
 } tnslq_result;
 
 /* ------------------------------------------------------------ utilities */
@@ -332,6 +334,18 @@ int tnslq_logneg_dims(const void *psi_dev, int dtype, const tnslq_partition_dims
 #define TNSLQ_MPS_SECTIONS_AUTO 0
 #define TNSLQ_MPS_SECTIONS_EXPLICIT 1
 #define TNSLQ_MPS_SECTIONS_TRANSFER 2
+/* `matvec` chooses how tnslq_logneg_mps contracts a probe through the
+ * compressed operator (below); both apply the same operator:
+ *   TNSLQ_MPS_MATVEC_FACTORS: psi_eff's two factors P, Q (four products);
+ *   TNSLQ_MPS_MATVEC_NETWORK: the blocks' R_A, R_B and the traced gap's and
+ *     ring's matrices E_W, E_Z kept apart (six products, every intermediate
+ *     at most bond^4 per probe, as the network of Sec. VI);
+ *   TNSLQ_MPS_MATVEC_AUTO (0): the one with fewer multiply-adds per probe
+ *     (the factors on ties).
+ * tnslq_mps_effective_state ignores it. */
+#define TNSLQ_MPS_MATVEC_AUTO 0
+#define TNSLQ_MPS_MATVEC_FACTORS 1
+#define TNSLQ_MPS_MATVEC_NETWORK 2
 typedef struct {
     int n_sites;
     const int *phys;        /* host, n_sites entries >= 2                        */
@@ -339,6 +353,7 @@ typedef struct {
                                bond[0] = bond[n]                                 */
     const void *tensors;    /* device, complex128                                */
     int sections;           /* TNSLQ_MPS_SECTIONS_*                              */
+    int matvec;             /* TNSLQ_MPS_MATVEC_*                                */
 } tnslq_mps;
 
 /* Contiguous blocks A = sites [a0, a0 + n_a) and B = [b0, b0 + n_b), a0 + n_a
@@ -393,9 +408,18 @@ int tnslq_mps_effective_state(const tnslq_mps *mps, int a0, int n_a, int b0, int
  *   Z1 = P^dagger X,  Z2 = Z1 Q,  Z3 = P Z2 (m and m' exchanged),
  *   Y[a][b] = sum_{m', v} Z3[a][(m', v)] conj Q[b][(m', v)],
  * about 2 k chi^4 + 2 k^2 chi^2 complex multiply-adds per probe for
- * k = d_A' = d_B' and bonds chi on an open chain (on a ring m is chi^2 wide),
- * against 2 k^3 chi^2 for the lazy form on psi_eff.  The Lanczos vectors run over (a, b), a d_B' + b, n = d_A' d_B'
- * entries, unpadded; the estimate and every output are those of
+ * k = d_A' = d_B' and bonds chi on an open chain with adjacent blocks,
+ * against 2 k^3 chi^2 for the lazy form on psi_eff.  Across a gap (u' is
+ * chi w wide) and on a ring (m is chi^2 wide) the factors grow; the network
+ * form keeps E_W[(m, n), (m', n')] = sum_w W[m][n][w] conj W[m'][n'][w] and
+ * E_Z[(v, u), (v', u')] = sum_z Z[v][u][z] conj Z[v'][u'][z] apart:
+ *   T1 = R_A^dagger X, T2 = T1 R_B               (T2[u'][m'][n][v]),
+ *   T3[m][n'][u'][v] = sum_{m', n} E_W T2        (adjacent: T2 regrouped),
+ *   T4[u][v'][m][n'] = sum_{v, u'} E_Z T3        (open chain: T3 regrouped),
+ *   Y[a][b] = sum R_A[a][u][m] T4[u][v'][m][n'] conj R_B[b][n'][v'],
+ * about 4 k chi^4 + (chi^2)^3 per traced section, every intermediate at
+ * most chi^4 entries per probe.  The Lanczos vectors run over (a, b),
+ * a d_B' + b, n = d_A' d_B' entries, unpadded; the estimate and every output are those of
  * tnslq_logneg on psi_eff (same probes, same stopping rules, the loop over
  * probes with max_probes).
  *   opt->precision TNSLQ_FP64 (complex products in FP64) or TNSLQ_FP32

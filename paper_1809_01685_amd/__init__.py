@@ -51,10 +51,11 @@ class PartitionDims(ctypes.Structure):
 
 class Mps(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int), ("phys", ctypes.POINTER(ctypes.c_int)), ("bond", ctypes.POINTER(ctypes.c_int)),
-                ("tensors", ctypes.c_void_p), ("sections", ctypes.c_int)]
+                ("tensors", ctypes.c_void_p), ("sections", ctypes.c_int), ("matvec", ctypes.c_int)]
 
 
 MPS_SECTIONS = {"auto": 0, "explicit": 1, "transfer": 2}
+MPS_MATVEC = {"auto": 0, "factors": 1, "network": 2}
 
 
 class Options(ctypes.Structure):
@@ -82,7 +83,7 @@ class Result(ctypes.Structure):
                 ("t_contract1_ms", ctypes.c_double), ("t_contract2_ms", ctypes.c_double),
                 ("t_lanczos_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("lanczos_err", ctypes.c_double), ("streamed", ctypes.c_int), ("explicit_operator", ctypes.c_int),
-                ("n_probes_used", ctypes.c_int)]
+                ("n_probes_used", ctypes.c_int), ("mps_matvec", ctypes.c_int)]
 
     def as_dict(self) -> Dict[str, float]:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -414,29 +415,32 @@ def tnslq_rho_pt_dims(psi, dims, a, b, workspace=None, stream=None, out=None):
 
 
 # ------------------------------------------------- matrix product states
-def _mps_desc(tensors, tensors_ptr=None, sections="auto"):
+def _mps_desc(tensors, tensors_ptr=None, sections="auto", matvec="auto"):
     """The library's description of an MPS (a list of (chi_l, p, chi_r)
     arrays; chi_l of the first = chi_r of the last, 1 for an open chain) with
     its tensors at ``tensors_ptr``; ``sections`` "auto", "explicit" or
-    "transfer" (how compressed sections are formed)."""
+    "transfer" (how compressed sections are formed), ``matvec`` "auto",
+    "factors" or "network" (how the factorised route contracts a probe)."""
     if sections not in MPS_SECTIONS:
         raise ValueError(f"sections must be one of {sorted(MPS_SECTIONS)}, not {sections!r}")
+    if matvec not in MPS_MATVEC:
+        raise ValueError(f"matvec must be one of {sorted(MPS_MATVEC)}, not {matvec!r}")
     phys = [int(t.shape[1]) for t in tensors]
     bond = [int(tensors[0].shape[0])] + [int(t.shape[2]) for t in tensors]
     pp = (ctypes.c_int * len(phys))(*phys)
     bb = (ctypes.c_int * len(bond))(*bond)
-    m = Mps(len(tensors), pp, bb, tensors_ptr, MPS_SECTIONS[sections])
+    m = Mps(len(tensors), pp, bb, tensors_ptr, MPS_SECTIONS[sections], MPS_MATVEC[matvec])
     m._keep = (pp, bb)
     return m
 
 
-def _mps(tensors, device, sections="auto"):
+def _mps(tensors, device, sections="auto", matvec="auto"):
     """Upload an MPS and describe it for the library."""
     import numpy as np
     import torch
     flat = np.concatenate([np.ascontiguousarray(np.asarray(t, dtype=np.complex128)).ravel() for t in tensors])
     dev = torch.from_numpy(flat).to(device)
-    m = _mps_desc(tensors, _ptr(dev), sections)
+    m = _mps_desc(tensors, _ptr(dev), sections, matvec)
     m._keep = m._keep + (dev,)
     return m
 
@@ -461,8 +465,8 @@ def tnslq_mps_effective_state(tensors, a0: int, n_a: int, b0: int, n_b: int, dev
 
 
 def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opts: Options,
-                              sections="auto") -> int:
-    m = _mps_desc(tensors, None, sections)
+                              sections="auto", matvec="auto") -> int:
+    m = _mps_desc(tensors, None, sections, matvec)
     n = ctypes.c_size_t(0)
     _check(lib().tnslq_workspace_bytes_mps(ctypes.byref(m), int(a0), int(n_a), int(b0), int(n_b), ctypes.byref(opts),
                                            ctypes.byref(n)), "tnslq_workspace_bytes_mps")
@@ -472,7 +476,8 @@ def tnslq_workspace_bytes_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, opt
 def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: int, n_steps: int, device="cuda",
                      route="factored", reorth: bool = False, seed: int = 0, probe_offset: int = 0,
                      stop_tol: float = 0.0, stop_rule="diff", max_probes: int = 0, precision=None, workspace=None,
-                     stream=None, want_arrays: bool = True, sections="auto", **kw) -> Dict[str, object]:
+                     stream=None, want_arrays: bool = True, sections="auto", matvec="auto",
+                     **kw) -> Dict[str, object]:
     """E(rho_AB) of two contiguous blocks of an open or periodic MPS (Sec. VI).
 
     route="factored": Algorithm 1 on the two-block operator in factorised form
@@ -498,8 +503,8 @@ def tnslq_logneg_mps(tensors, a0: int, n_a: int, b0: int, n_b: int, n_probes: in
         raise TypeError(f"unexpected keywords for the factored route: {sorted(kw)}")
     opts = make_options(n_probes, n_steps, reorth, precision or "fp64", seed, probe_offset, stop_tol, stop_rule,
                         "auto", max_probes)
-    m = _mps(tensors, device, sections)
-    need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts, sections)
+    m = _mps(tensors, device, sections, matvec)
+    need = tnslq_workspace_bytes_mps(tensors, a0, n_a, b0, n_b, opts, sections, matvec)
     ws = _workspace(need, torch.device(device), workspace)
     res = Result()
     loop = max_probes > n_probes

@@ -173,6 +173,37 @@ int make_plan(int dtype, const tnslq_partition *p, int K, int m, int reorth, int
     return plan_rest(pl, dtype, prec, K, lanczos);
 }
 
+// The network form's tensors (offsets from pl.off_net): E_W regrouped
+// [(m, n')][(m', n)] (a gap), E_Z regrouped [(u, v')][(v, u')] (a ring),
+// their complex64 copies, and four scratch tensors of up to s4 entries for
+// the normalisation (Gram matrices of the blocks, E_W, E_Z and their
+// contractions, each at most (bond^2)^2).
+struct NetBufs {
+    size_t ewp, ezp, ew32, ez32, x[4], total;
+    int64_t s4;
+};
+NetBufs net_bufs(const Plan &pl) {
+    NetBufs b{};
+    const int64_t UM = pl.nU * pl.nM, NV = pl.nN * pl.nV, MN = pl.nM * pl.nN, UV = pl.nU * pl.nV,
+                  UN = pl.nU * pl.nN;
+    const int64_t w = std::max({UM, NV, MN, UV, UN});
+    b.s4 = w * w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += up(std::max<size_t>(bytes, 16));
+        return r;
+    };
+    b.ewp = take(pl.ngap ? (size_t)MN * MN * 16 : 16);
+    b.ezp = take(pl.nring ? (size_t)UV * UV * 16 : 16);
+    const bool f32 = pl.prec == TNSLQ_FP32;
+    b.ew32 = take(pl.ngap && f32 ? (size_t)MN * MN * 8 : 16);
+    b.ez32 = take(pl.nring && f32 ? (size_t)UV * UV * 8 : 16);
+    for (int i = 0; i < 4; ++i) b.x[i] = take((size_t)b.s4 * 16);
+    b.total = o;
+    return b;
+}
+
 // Chunking, splits and the workspace carve-up of a plan whose roles, sizes
 // and operator form are set.
 int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
@@ -238,7 +269,9 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
 
     // factorised MPS operator: four complex products per probe, chunks of
     // probes within a fixed budget of intermediates
-    const int64_t UpM = pl.mUp * pl.mM, MV = pl.mM * pl.mV;
+    // (network form: Z1 = T1, Z2 and Z2p = T2 .. T4, Z3 = T5, with U'M -> U M
+    // and MV -> N V)
+    const int64_t UpM = pl.mnet ? pl.nU * pl.nM : pl.mUp * pl.mM, MV = pl.mnet ? pl.nN * pl.nV : pl.mM * pl.mV;
     const size_t mes = prec == TNSLQ_FP32 ? 8 : 16;   // bytes per complex entry of its intermediates
     if (pl.mpsf) {
         const size_t per = mes * (size_t)(UpM * pl.dB + 2 * UpM * MV + pl.dA * MV + 2 * n);
@@ -265,10 +298,11 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
         pl.off_Z2p = take((size_t)pl.kc * UpM * MV * mes);
         pl.off_Z3 = take((size_t)pl.kc * pl.dA * MV * mes);
         pl.off_Ypart = take((size_t)pl.S * pl.kc * n * mes);
-        pl.off_nrm = take((size_t)2 * pl.mM * pl.mM * 16 + 64);
+        pl.off_nrm = take(pl.mnet ? 64 : (size_t)2 * pl.mM * pl.mM * 16 + 64);
+        if (pl.mnet) pl.off_net = take(net_bufs(pl).total);
         if (prec == TNSLQ_FP32) {
-            pl.off_P32 = take((size_t)pl.dA * UpM * 8);
-            pl.off_Q32 = take((size_t)pl.dB * MV * 8);
+            pl.off_P32 = take((size_t)pl.dA * UpM * 8);     // P or R_A
+            pl.off_Q32 = take((size_t)pl.dB * MV * 8);      // Q or R_B
             pl.off_X32 = take((size_t)pl.kc * n * 8);
         }
     } else if (pl.expl) {
@@ -546,8 +580,8 @@ int plan_sec(const MpsPlan &mp, MpsSec &s, int route, bool absorb_right) {
 }
 
 // dense: room for the effective state itself (the dense route); without it
-// only the factors are built.
-int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bool dense = true) {
+// only the factors are built, or with net only the network form's pieces.
+int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bool dense = true, bool net = false) {
     if (!m) return fail(TNSLQ_E_ARG, "mps is NULL");
     const int L = m->n_sites;
     if (L < 2 || L > 100000) return fail(TNSLQ_E_ARG, "n_sites %d outside [2, 100000]", L);
@@ -632,8 +666,10 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     mp.q[1] = (int)ceil_pow2_log(mp.kB);
     mp.q[2] = (int)ceil_pow2_log(mp.Up * mp.Vf);
     if (!dense) {
-        if (mp.kA * mp.Up > INT32_MAX || mp.kB * mp.Vf > INT32_MAX || mp.Up * mp.Mf > INT32_MAX ||
-            mp.Mf * mp.Vf > INT32_MAX || mp.kA * mp.kB > (int64_t(1) << 32) || mp.kB * mp.Mf > INT32_MAX)
+        if (mp.kA * mp.kB > (int64_t(1) << 32))
+            return fail(TNSLQ_E_ARG, "d_A' d_B' = %lld exceeds 2^32", (long long)(mp.kA * mp.kB));
+        if (!net && (mp.kA * mp.Up > INT32_MAX || mp.kB * mp.Vf > INT32_MAX || mp.Up * mp.Mf > INT32_MAX ||
+                     mp.Mf * mp.Vf > INT32_MAX || mp.kB * mp.Mf > INT32_MAX))
             return fail(TNSLQ_E_ARG, "the blocks' factors exceed 2^31 rows or columns");
     } else if (mp.q[0] + mp.q[1] + mp.q[2] > 32)
         return fail(TNSLQ_E_ARG, "the effective state would need %d qubits (at most 32)", mp.q[0] + mp.q[1] + mp.q[2]);
@@ -658,14 +694,15 @@ int plan_mps(const tnslq_mps *m, int a0, int na, int b0, int nb, MpsPlan &mp, bo
     mp.off_G = take(mp.gmax);
     mp.off_RA = take(mp.kA * mp.U * mp.Mb);
     mp.off_RB = take(mp.kB * mp.Nb * mp.V);
-    mp.off_RBp = take(mp.closed ? 1 : mp.kB * mp.Nb * mp.V);
+    const bool pq = dense || !net;   // the factors P, Q are built
+    mp.off_RBp = take(mp.closed || !pq ? 1 : mp.kB * mp.Nb * mp.V);
     mp.off_W = take(gap ? mp.Mb * mp.Nb * mp.Wd : 1);
     mp.off_Z = take(mp.closed ? mp.V * mp.U * mp.Zd : 1);
-    mp.off_T1 = take(gap ? mp.kA * mp.U * mp.Nb * mp.Wd : 1);
+    mp.off_T1 = take(gap && pq ? mp.kA * mp.U * mp.Nb * mp.Wd : 1);
     mp.off_T = take(dense ? mp.kA * mp.Up * mp.kB * mp.Vf : 1);
-    mp.off_P = take(gap || mp.closed ? mp.kA * mp.Up * mp.Mf : 1);
-    mp.off_Q2 = take(mp.closed ? mp.kB * mp.Mf * mp.Vf : 1);
-    mp.off_Q2p = take(mp.closed ? mp.kB * mp.Mf * mp.Vf : 1);
+    mp.off_P = take((gap || mp.closed) && pq ? mp.kA * mp.Up * mp.Mf : 1);
+    mp.off_Q2 = take(mp.closed && pq ? mp.kB * mp.Mf * mp.Vf : 1);
+    mp.off_Q2p = take(mp.closed && pq ? mp.kB * mp.Mf * mp.Vf : 1);
     int64_t tenv = 0;   // the environment sweeps' scratch: one site tensor and one environment
     if (!mp.closed)
         for (int i = 0; i < L; ++i)
@@ -809,14 +846,20 @@ int mps_trace_factor(const double2 *S, int64_t x, int64_t g, int64_t y, bool com
 //   ring:            P[a][w][(n, u)] = sum_m R_A[a][u][m] W[m][n][w] (W the
 //                    identity when adjacent), Q[b][(n, u)][z] = sum_v
 //                    R_B[b][n][v] Z[v][u][z], v' = z.
-// Qp is Q with its first two axes exchanged, [m][b][v'].
+// Qp is Q with its first two axes exchanged, [m][b][v'].  The network form
+// keeps the pieces: R_A[a][u][m], R_B[b][n][v], W[(m, n)][w] (a gap),
+// Z[(v, u)][z] (a ring).
 struct MpsFactors {
     double2 *P;
     const double2 *Q, *Qp;
     int64_t kA, Up, M, kB, V;
+    double2 *RA;
+    const double2 *RB, *W, *Z;
+    int64_t U, Mb, Nb, Vb, Wd, Zd;
 };
 
-int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, MpsFactors &f) {
+// net: stop once the pieces of the network form are built (no P, Q).
+int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, MpsFactors &f, bool net = false) {
     int rc;
     auto buf = [&](size_t off) { return (double2 *)(ws + off); };
     int *failp = (int *)(ws + mp.off_fail);
@@ -929,6 +972,21 @@ int mps_build(const MpsPlan &mp, const double2 *T, char *ws, hipStream_t st, Mps
     f.Up = mp.Up;
     f.M = mp.Mf;
     f.V = mp.Vf;
+    f.RA = buf(mp.off_RA);
+    f.RB = buf(mp.off_RB);
+    f.W = gap ? buf(mp.off_W) : nullptr;
+    f.Z = mp.closed ? buf(mp.off_Z) : nullptr;
+    f.U = mp.U;
+    f.Mb = mp.Mb;
+    f.Nb = mp.Nb;
+    f.Vb = mp.V;
+    f.Wd = mp.Wd;
+    f.Zd = mp.Zd;
+    if (net) {
+        f.P = nullptr;
+        f.Q = f.Qp = nullptr;
+        return TNSLQ_OK;
+    }
     // T1[(kA, u)][(n, w)] = sum_m R_A[(kA, u)][m] W[m][(n, w)]
     const int64_t nrow = mp.kA * mp.U;
     if (gap)
@@ -1098,8 +1156,94 @@ int form_rho(const Plan &pl, int prec, const void *psi, void *Pabe, void *Pabc, 
     return TNSLQ_OK;
 }
 
+// The network form (psi is the chain's tensors): R_A, R_B and the traced
+// sections' matrices E_W = W W^dagger, E_Z = Z Z^dagger regrouped for the
+// matvec, then R_A scaled so that the effective state has norm 1:
+//   ||psi||^2 = sum GA[u'][m'][u][m] E_W[m][n][m'][n'] HB[n'][v'][n][v]
+//               E_Z[v][u][v'][u']
+// with GA = R_A^dagger R_A, HB = R_B^dagger R_B (open chains: E_Z the
+// identity on (u, v); adjacent blocks: E_W the identity, n = m).
+int net_layout(Ctx &c, const void *psi) {
+    const Plan &pl = c.pl;
+    int rc;
+    char *mws = c.ws + pl.off_mps;
+    if ((rc = mps_build(*c.mp, (const double2 *)psi, mws, c.st, c.mf, true))) return rc;
+    const MpsFactors &f = c.mf;
+    if (f.kA != pl.dA || f.kB != pl.dB || f.U != pl.nU || f.Mb != pl.nM || f.Nb != pl.nN || f.Vb != pl.nV)
+        return fail(TNSLQ_E_ARG, "network shapes differ from the plan");
+    const int64_t U = pl.nU, M = pl.nM, N = pl.nN, V = pl.nV, UM = U * M, NV = N * V, MN = M * N, UV = U * V;
+    const NetBufs nb = net_bufs(pl);
+    char *base = c.ws + pl.off_net;
+    auto at = [&](size_t off) { return (double2 *)(base + off); };
+    double2 *x0 = at(nb.x[0]), *x1 = at(nb.x[1]), *x2 = at(nb.x[2]), *x3 = at(nb.x[3]);
+    double *nrm = (double *)(c.ws + pl.off_nrm);
+    const int kA = (int)f.kA, kB = (int)f.kB;
+    if (pl.ngap) {
+        // E_W[(m, n)][(m', n')] in x2, regrouped as [m][n'][m'][n]
+        TNSLQ_HIP(launch_zgemm(0, 2, f.W, f.W, x2, (int)MN, (int)MN, (int)f.Wd, f.Wd, f.Wd, MN, 1, 0, 0, 0, c.st));
+        const int64_t d[4] = {M, N, M, N};
+        const int perm[4] = {0, 3, 2, 1};
+        TNSLQ_HIP(launch_permute4(x2, d, perm, at(nb.ewp), c.st));
+    }
+    if (pl.nring) {
+        // E_Z[(v, u)][(v', u')] in x3, regrouped as [u][v'][v][u']
+        TNSLQ_HIP(launch_zgemm(0, 2, f.Z, f.Z, x3, (int)UV, (int)UV, (int)f.Zd, f.Zd, f.Zd, UV, 1, 0, 0, 0, c.st));
+        const int64_t d[4] = {V, U, V, U};
+        const int perm[4] = {1, 2, 0, 3};
+        TNSLQ_HIP(launch_permute4(x3, d, perm, at(nb.ezp), c.st));
+    }
+    // GA[(u', m')][(u, m)] in x0, as [(u', u)][(m, m')] in x1
+    TNSLQ_HIP(launch_zgemm(2, 0, f.RA, f.RA, x0, (int)UM, (int)UM, kA, UM, UM, UM, 1, 0, 0, 0, c.st));
+    {
+        const int64_t d[4] = {U, M, U, M};
+        const int perm[4] = {0, 2, 3, 1};
+        TNSLQ_HIP(launch_permute4(x0, d, perm, x1, c.st));
+    }
+    // F1[(u', u)][(n, n')] = sum_{m, m'} GA E_W
+    double2 *F1 = x1, *fr0 = x0, *fr1 = x2;
+    if (pl.ngap) {
+        const int64_t d[4] = {M, N, M, N};
+        const int perm[4] = {0, 2, 1, 3};   // E_W as [(m, m')][(n, n')]
+        TNSLQ_HIP(launch_permute4(x2, d, perm, x0, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 0, x1, x0, x2, (int)(U * U), (int)(N * N), (int)(M * M), M * M, N * N, N * N, 1, 0,
+                               0, 0, c.st));
+        F1 = x2;
+        fr0 = x0;
+        fr1 = x1;
+    }
+    // HB[(n', v')][(n, v)], as [(n, n')][(v', v)]; F2[(u', u)][(v', v)] = F1 HB
+    TNSLQ_HIP(launch_zgemm(2, 0, f.RB, f.RB, fr0, (int)NV, (int)NV, kB, NV, NV, NV, 1, 0, 0, 0, c.st));
+    {
+        const int64_t d[4] = {N, V, N, V};
+        const int perm[4] = {2, 0, 1, 3};
+        TNSLQ_HIP(launch_permute4(fr0, d, perm, fr1, c.st));
+    }
+    double2 *F2 = fr0;
+    TNSLQ_HIP(launch_zgemm(0, 0, F1, fr1, F2, (int)(U * U), (int)(V * V), (int)(N * N), N * N, V * V, V * V, 1, 0, 0,
+                           0, c.st));
+    if (pl.nring) {
+        // ||psi||^2 = Re sum F2[u'][u][v'][v] conj E_Z[v'][u'][v][u]
+        const int64_t d[4] = {V, U, V, U};
+        const int perm[4] = {1, 3, 0, 2};
+        TNSLQ_HIP(launch_permute4(x3, d, perm, fr1, c.st));
+        TNSLQ_HIP(launch_normalise_factor(F2, fr1, UV * UV, nrm, f.RA, f.kA * UM, c.st));
+    } else {
+        // ||psi||^2 = sum_{u, v} F2[u][u][v][v]
+        TNSLQ_HIP(launch_trace_pairs(F2, U, V, nrm, c.st));
+        TNSLQ_HIP(launch_scale_rsqrt(f.RA, f.kA * UM, nrm, c.st));
+    }
+    if (pl.prec == TNSLQ_FP32) {
+        TNSLQ_HIP(launch_to_c64(f.RA, f.kA * UM, c.P32, c.st));
+        TNSLQ_HIP(launch_to_c64(f.RB, f.kB * NV, c.Q32, c.st));
+        if (pl.ngap) TNSLQ_HIP(launch_to_c64(at(nb.ewp), MN * MN, (float2 *)(base + nb.ew32), c.st));
+        if (pl.nring) TNSLQ_HIP(launch_to_c64(at(nb.ezp), UV * UV, (float2 *)(base + nb.ez32), c.st));
+    }
+    return mps_check(*c.mp, mws, c.st);
+}
+
 int do_layout(Ctx &c, const void *psi) {
     const Plan &pl = c.pl;
+    if (pl.mpsf && pl.mnet) return net_layout(c, psi);
     if (pl.mpsf) {
         // the factors P and Q of the two blocks (psi is the chain's tensors),
         // then psi = P Q normalised through P: ||psi||^2 = Re sum Ahat conj(C)
@@ -1342,6 +1486,78 @@ int mps_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2)
     return TNSLQ_OK;
 }
 
+// The network form's matvec for kcur probes (x: [k][a'][b'], kA x kB each):
+//   T1[k][(u', m')][b']    = sum_a' conj R_A[a'][(u', m')] X[k][a'][b']
+//   T2[k][(u', m')][(n, v)] = sum_b' T1 R_B[b'][(n, v)]
+//   T3[k][m][n'][u'][v]    = sum_{m', n} E_W[m][n][m'][n'] T2[k][u'][m'][n][v]
+//                            (adjacent blocks: T2 regrouped, n = m, n' = m')
+//   T4[k][u][v'][m][n']    = sum_{v, u'} E_Z[v][u][v'][u'] T3[k][m][n'][u'][v]
+//                            (open chain: T3 regrouped, u' = u, v' = v)
+//   T5[k][a][(n', v')]     = sum_{u, m} R_A[a][(u, m)] T4[k][u][v'][m][n']
+//   Y[k][a][b]             = sum_{n', v'} T5[k][a][(n', v')] conj R_B[b][(n', v')]
+// (the last in reduction splits at Ypart, as for the factors).  Each product
+// is batched over the chunk; the regroupings are axis permutations.
+int net_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2) {
+    const Plan &pl = c.pl;
+    const int64_t n = pl.dAB, U = pl.nU, M = pl.nM, N = pl.nN, V = pl.nV, UM = U * M, NV = N * V, MN = M * N,
+                  UV = U * V, big = UM * NV;
+    const int kA = (int)pl.dA, kB = (int)pl.dB;
+    const NetBufs nb = net_bufs(pl);
+    char *base = c.ws + pl.off_net;
+    auto chain = [&](auto *RA, auto *RB, auto *EWp, auto *EZp, auto *X, auto *T1, auto *Ta, auto *Tb, auto *T5,
+                     auto *Y) -> int {
+        TNSLQ_HIP(launch_zgemm(2, 0, RA, X, T1, (int)UM, kB, kA, UM, kB, kB, kcur, 0, n, UM * kB, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 0, T1, RB, Ta, (int)UM, (int)NV, kB, kB, NV, NV, kcur, UM * kB, 0, big, c.st));
+        if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+        auto *T3 = Ta;   // [m][n'][u'][v]
+        if (pl.ngap) {
+            const int64_t d[4] = {U, M, N, V};
+            const int perm[4] = {1, 2, 0, 3};   // [m'][n][u'][v]
+            TNSLQ_HIP(launch_permute4(Ta, d, perm, Tb, c.st, kcur));
+            TNSLQ_HIP(launch_zgemm(0, 0, EWp, Tb, Ta, (int)MN, (int)UV, (int)MN, MN, UV, UV, kcur, 0, big, big, c.st));
+        } else {
+            const int64_t d[4] = {U, M, M, V};
+            const int perm[4] = {2, 1, 0, 3};
+            TNSLQ_HIP(launch_permute4(Ta, d, perm, Tb, c.st, kcur));
+            T3 = Tb;
+        }
+        auto *other = T3 == Ta ? Tb : Ta;
+        auto *T4p = other;   // [u][m][n'][v']
+        if (pl.nring) {
+            const int64_t d3[4] = {M, N, U, V};
+            const int perm3[4] = {3, 2, 0, 1};   // [v][u'][m][n']
+            TNSLQ_HIP(launch_permute4(T3, d3, perm3, other, c.st, kcur));
+            TNSLQ_HIP(launch_zgemm(0, 0, EZp, other, T3, (int)UV, (int)MN, (int)UV, UV, MN, MN, kcur, 0, big, big,
+                                   c.st));   // T4[u][v'][m][n']
+            const int64_t d4[4] = {U, V, M, N};
+            const int perm4[4] = {0, 2, 3, 1};
+            TNSLQ_HIP(launch_permute4(T3, d4, perm4, other, c.st, kcur));
+        } else {
+            const int64_t d3[4] = {M, N, U, V};
+            const int perm3[4] = {2, 0, 1, 3};
+            TNSLQ_HIP(launch_permute4(T3, d3, perm3, other, c.st, kcur));
+        }
+        TNSLQ_HIP(launch_zgemm(0, 0, RA, T4p, T5, kA, (int)NV, (int)UM, UM, NV, NV, kcur, 0, big, kA * NV, c.st));
+        TNSLQ_HIP(launch_zgemm(0, 2, T5, RB, Y, kA, kB, (int)NV, NV, NV, kB, kcur, kA * NV, 0, n, c.st, 0, pl.S,
+                               (int64_t)pl.kc * n));
+        return TNSLQ_OK;
+    };
+    int rc;
+    if (pl.prec == TNSLQ_FP32) {
+        TNSLQ_HIP(launch_to_c64(x, (int64_t)kcur * n, c.X32, c.st));
+        rc = chain((const float2 *)c.P32, (const float2 *)c.Q32, (const float2 *)(base + nb.ew32),
+                   (const float2 *)(base + nb.ez32), (const float2 *)c.X32, (float2 *)c.Z1, (float2 *)c.Z2,
+                   (float2 *)c.Z2p, (float2 *)c.Z3, (float2 *)c.Ypart);
+    } else {
+        rc = chain((const double2 *)c.mf.RA, c.mf.RB, (const double2 *)(base + nb.ewp),
+                   (const double2 *)(base + nb.ezp), x, c.Z1, c.Z2, c.Z2p, c.Z3, (double2 *)c.Ypart);
+    }
+    if (rc) return rc;
+    if (e2) TNSLQ_HIP(hipEventRecord(e2, c.st));
+    c.n_launch++;
+    return TNSLQ_OK;
+}
+
 // Events of one Lanczos step: mv0, then per probe chunk (after contraction 1,
 // after contraction 2, after the merge), then mv1 (matvec done), lz1.
 struct StepEvents {
@@ -1369,7 +1585,8 @@ int lanczos_step(Ctx &c, int j, StepEvents *se) {
     for (int k0 = 0, ch = 0; k0 < pl.K; k0 += pl.kc, ++ch) {
         const int kcur = std::min(pl.kc, pl.K - k0);
         if (pl.mpsf) {
-            if ((rc = mps_matvec(c, q_cur + (int64_t)k0 * n, kcur, se->c1(ch), se->c2(ch)))) return rc;
+            if ((rc = (pl.mnet ? net_matvec : mps_matvec)(c, q_cur + (int64_t)k0 * n, kcur, se->c1(ch), se->c2(ch))))
+                return rc;
         } else if (pl.expl) {
             if ((rc = explicit_matvec(c, se->c1(ch), se->c2(ch)))) return rc;
         } else if (pl.stream) {
@@ -1649,6 +1866,7 @@ int run_finish(Run &r, tnslq_result *res, double *G, double *alpha, double *beta
     res->swapped_ab = pl.swapped;
     res->streamed = pl.stream ? (pl.fused ? 2 : 1) : 0;
     res->explicit_operator = pl.expl;
+    res->mps_matvec = pl.mpsf ? (pl.mnet ? TNSLQ_MPS_MATVEC_NETWORK : TNSLQ_MPS_MATVEC_FACTORS) : 0;
     res->n_probes_used = pl.K;
     res->n_matvecs = r.jdone;
     res->n_contract_launches = c.n_launch;
@@ -2101,6 +2319,7 @@ int run_probe_loop(Run &r, const tnslq_options *opt, tnslq_result *res, double *
     res->swapped_ab = pl.swapped;
     res->streamed = pl.stream ? (pl.fused ? 2 : 1) : 0;
     res->explicit_operator = pl.expl;
+    res->mps_matvec = pl.mpsf ? (pl.mnet ? TNSLQ_MPS_MATVEC_NETWORK : TNSLQ_MPS_MATVEC_FACTORS) : 0;
     res->n_probes_used = (int)Gall.size();
     res->n_matvecs = nmv;
     res->n_contract_launches = c.n_launch;
@@ -2412,9 +2631,45 @@ static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b
                     opt->precision);
     if (opt->operator_form != TNSLQ_OPERATOR_AUTO)
         return fail(TNSLQ_E_ARG, "operator_form must be TNSLQ_OPERATOR_AUTO for MPS blocks");
-    if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp, false))) return rc;
+    if (!mps) return fail(TNSLQ_E_ARG, "mps is NULL");
+    if (mps->matvec < TNSLQ_MPS_MATVEC_AUTO || mps->matvec > TNSLQ_MPS_MATVEC_NETWORK)
+        return fail(TNSLQ_E_ARG, "matvec %d is not a TNSLQ_MPS_MATVEC_ value", mps->matvec);
+    if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mp, false, true))) return rc;
+    // complex multiply-adds per probe and matvec of the two forms
+    const bool gap = mp.b0 > mp.a1;
+    const double kA = (double)mp.kA, kB = (double)mp.kB;
+    const double UpM = (double)mp.Up * mp.Mf, MV = (double)mp.Mf * mp.Vf;
+    const double UM = (double)mp.U * mp.Mb, NV = (double)mp.Nb * mp.V, MN = (double)mp.Mb * mp.Nb,
+                 UV = (double)mp.U * mp.V;
+    const double c_pq = UpM * kB * kA + UpM * MV * kB + kA * MV * UpM + kA * kB * MV;
+    const double c_net = UM * kB * kA + UM * NV * kB + (gap ? MN * MN * UV : 0.0) + (mp.closed ? UV * UV * MN : 0.0) +
+                         kA * NV * UM + kA * kB * NV;
+    // the network's layout scratch: four tensors of (bond^2)^2 entries
+    const double wmax = std::max({UM, NV, MN, UV, (double)mp.U * mp.Nb});
+    const bool net_fits = 4.0 * wmax * wmax * 16.0 <= (double)(size_t(64) << 30);
+    if (mps->matvec == TNSLQ_MPS_MATVEC_NETWORK && !net_fits)
+        return fail(TNSLQ_E_ARG, "the network form's layout would need more than 64 GiB");
+    bool net = mps->matvec == TNSLQ_MPS_MATVEC_NETWORK ||
+               (mps->matvec == TNSLQ_MPS_MATVEC_AUTO && net_fits && c_net < c_pq);
+    if (!net) {
+        MpsPlan mq;
+        if ((rc = plan_mps(mps, a0, n_a, b0, n_b, mq, false, false))) {
+            if (mps->matvec == TNSLQ_MPS_MATVEC_FACTORS || !net_fits) return rc;
+            net = true;   // the factors would not fit the products' index range
+            g_err.clear();
+        } else {
+            mp = mq;
+        }
+    }
     pl = Plan();
     pl.mpsf = 1;
+    pl.mnet = net;
+    pl.ngap = gap;
+    pl.nring = mp.closed;
+    pl.nU = mp.U;
+    pl.nM = mp.Mb;
+    pl.nN = mp.Nb;
+    pl.nV = mp.V;
     pl.dtype = TNSLQ_C128;
     pl.prec = opt->precision;
     pl.K = opt->n_probes;
@@ -2426,7 +2681,7 @@ static int make_plan_mpsf(const tnslq_mps *mps, int a0, int n_a, int b0, int n_b
     pl.mUp = mp.Up;
     pl.mM = mp.Mf;
     pl.mV = mp.Vf;
-    pl.dE = pl.mUp * pl.mV;
+    pl.dE = mp.Up * mp.Vf;
     pl.D = pl.dAB * pl.dE;
     pl.mps_bytes = mp.total;
     return plan_rest(pl, TNSLQ_C128, pl.prec, pl.K, 1);

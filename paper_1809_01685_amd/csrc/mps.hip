@@ -432,16 +432,20 @@ __global__ void __launch_bounds__(256) k_scale_inv(double2 *__restrict__ x, int6
     }
 }
 
-// out = in with its four axes permuted: in has shape d[0..3], out axis j is
-// in axis perm[j] (out shape d[perm[0]], ..., d[perm[3]]).
+// out[b] = in[b] with its four axes permuted, for nb tensors one after the
+// other: in[b] has shape d[0..3], out axis j is in axis perm[j] (out shape
+// d[perm[0]], ..., d[perm[3]]).
 struct Perm4 {
     int64_t od[4];   // out shape
     int64_t is[4];   // in stride of out axis j
+    int64_t per;     // entries per tensor
 };
-__global__ void __launch_bounds__(256) k_permute4(const double2 *__restrict__ in, Perm4 p, int64_t total,
-                                                  double2 *__restrict__ out) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute4(const T *__restrict__ in, Perm4 p, int64_t total,
+                                                  T *__restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = e, off = 0;
+        const int64_t b = e / p.per;
+        int64_t r = e - b * p.per, off = b * p.per;
 #pragma unroll
         for (int j = 3; j >= 0; --j) {
             off += (r % p.od[j]) * p.is[j];
@@ -652,18 +656,43 @@ hipError_t launch_transfer_absorb_right(const double2 *T, const double2 *Y, int6
     return scale_by_transfer_trace(Tnew, x, cv, s, st);
 }
 
-hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st) {
+template <typename T>
+static hipError_t permute4_t(const T *in, const int64_t d[4], const int perm[4], T *out, hipStream_t st, int64_t nb) {
     Perm4 p;
     int64_t stride[4];
     stride[3] = 1;
     for (int j = 2; j >= 0; --j) stride[j] = stride[j + 1] * d[j + 1];
+    int seen = 0;
     for (int j = 0; j < 4; ++j) {
-        if (perm[j] < 0 || perm[j] > 3) return hipErrorInvalidValue;
+        if (perm[j] < 0 || perm[j] > 3 || (seen >> perm[j]) & 1) return hipErrorInvalidValue;
+        seen |= 1 << perm[j];
         p.od[j] = d[perm[j]];
         p.is[j] = stride[perm[j]];
     }
-    const int64_t total = d[0] * d[1] * d[2] * d[3];
-    hipLaunchKernelGGL(k_permute4, dim3(blocks_for(total)), dim3(256), 0, st, in, p, total, out);
+    p.per = d[0] * d[1] * d[2] * d[3];
+    const int64_t total = nb * p.per;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute4<T>, dim3(blocks_for(total)), dim3(256), 0, st, in, p, total, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st,
+                           int64_t nb) {
+    return permute4_t(in, d, perm, out, st, nb);
+}
+
+hipError_t launch_permute4(const float2 *in, const int64_t d[4], const int perm[4], float2 *out, hipStream_t st,
+                           int64_t nb) {
+    return permute4_t(in, d, perm, out, st, nb);
+}
+
+hipError_t launch_trace_pairs(const double2 *T, int64_t x, int64_t y, double *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_transfer_trace, dim3(1), dim3(256), 0, st, T, x, y, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_rsqrt(double2 *x, int64_t n, const double *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_rsqrt, dim3(blocks_for(n)), dim3(256), 0, st, x, n, s);
     return hipGetLastError();
 }
 

@@ -57,6 +57,10 @@ struct Plan {
     int64_t nst_e = 1;               // bricks along E of the forming product
     int mpsf = 0;                    // two-block MPS operator in factorised form (Sec. VI)
     int64_t mUp = 1, mM = 1, mV = 1; // its factors P[a][u'][m], Q[b][m][v]
+    int mnet = 0;                    // ... applied as the network R_A, E_W, E_Z, R_B instead
+    int ngap = 0, nring = 0;         // the network's traced gap and ring sections
+    int64_t nU = 1, nM = 1, nN = 1, nV = 1;   // its bonds u, m (A), n, v (B)
+    size_t off_net = 0;              // network tensors and layout scratch
     size_t mps_bytes = 0;            // workspace of the factor construction
     int mixed = 0;                   // sites of general local dimension (explicit form only)
     MixedDesc md;                    // their regrouping
@@ -237,10 +241,18 @@ hipError_t launch_transfer_step(const double2 *T, const double2 *M, int64_t x, i
                                 double2 *Tnew, double2 *A, double *s, hipStream_t st);
 hipError_t launch_transfer_absorb_right(const double2 *T, const double2 *Y, int64_t x, int64_t cy, int64_t cv,
                                         double2 *Tnew, double2 *H, double *s, hipStream_t st);
-// out = in (shape d[0..3]) with out axis j = in axis perm[j].
-hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st);
+// out[b] = in[b] (shape d[0..3]) with out axis j = in axis perm[j], for nb
+// tensors one after the other.
+hipError_t launch_permute4(const double2 *in, const int64_t d[4], const int perm[4], double2 *out, hipStream_t st,
+                           int64_t nb = 1);
+hipError_t launch_permute4(const float2 *in, const int64_t d[4], const int perm[4], float2 *out, hipStream_t st,
+                           int64_t nb = 1);
 // out = the n x n identity.
 hipError_t launch_identity(double2 *out, int64_t n, hipStream_t st);
+// s[0] = sum_{a < x, c < y} Re T[a][a][c][c] (T of shape x, x, y, y).
+hipError_t launch_trace_pairs(const double2 *T, int64_t x, int64_t y, double *s, hipStream_t st);
+// x *= 1 / sqrt(s[0]) (s on the device).
+hipError_t launch_scale_rsqrt(double2 *x, int64_t n, const double *s, hipStream_t st);
 // C[b] = op(A[b]) op(B[b]) (with sub: C[b] -= op(A[b]) op(B[b])), op 0 = as
 // stored, 1 = transpose, 2 = conjugate transpose (supported pairs: (0,0),
 // (1,0), (2,0), (0,2)); op(A) is M x K.  With ks > 1 the reduction is split

@@ -57,8 +57,9 @@
         random open MPS with bond 32, 64 and 116, adjacent blocks of 20, 100
         and 400 sites at its centre (their Gram matrices from transfer
         sweeps), the factorised operator in FP32 to +-1% by the fit rule;
-        then rings of 200 sites, bond 8 and 12, blocks of 40 sites 10 apart
-        and a 110-site outer section.
+        80-site blocks 40 sites apart (bond 16: both matvec forms; bond 64:
+        the network form); then rings of 200 sites, bond 8 to 32, blocks of
+        40 sites 10 apart and a 110-site outer section.
 
     python -m paper_1809_01685_amd.experiments arith_peaks
         Achievable arithmetic rates of this GPU (libtnslq_peak): dependent
@@ -539,12 +540,13 @@ def run_mps_long(seed=0, n_probes=2, n_steps=10, chis=(32, 64, 116), lengths=(20
     dev = torch.device("cuda:0")
     rows = []
 
-    def one(ts, a0, la, b0, lb, row, prec):
+    def one(ts, a0, la, b0, lb, row, prec, matvec="auto"):
         t0 = time.perf_counter()
         f = tnslq_logneg_mps(ts, a0, la, b0, lb, n_probes, n_steps, device=dev, seed=seed, stop_tol=0.01,
-                             stop_rule="fit", want_arrays=False, precision=prec)
+                             stop_rule="fit", want_arrays=False, precision=prec, matvec=matvec)
         torch.cuda.synchronize()
-        row.update({"precision": prec, "t_total_s": time.perf_counter() - t0, "t_layout_ms": f["t_layout_ms"],
+        row.update({"precision": prec, "matvec": {1: "factors", 2: "network"}[f["mps_matvec"]],
+                    "t_total_s": time.perf_counter() - t0, "t_layout_ms": f["t_layout_ms"],
                     "t_matvec_ms": f["t_matvec_ms"], "steps": f["steps_done"],
                     "ms_per_matvec": f["t_matvec_ms"] / max(f["steps_done"], 1), "logneg": f["logneg"],
                     "logneg_se": f["logneg_se"], "lanczos_err": f["lanczos_err"],
@@ -562,12 +564,23 @@ def run_mps_long(seed=0, n_probes=2, n_steps=10, chis=(32, 64, 116), lengths=(20
             one(ts, c - la, la, c, la, {"chain": "open", "n_sites": n_sites, "chi": chi, "A": [c - la, c],
                                        "B": [c, c + la]}, "fp32")
     if rings:
-        for chi in (8, 12):
+        # blocks 40 sites apart on the open chain: the factors' u' = (u, w)
+        # is chi^3 wide, the network form keeps E_W (chi^4) apart
+        for chi, forms in ((16, ("factors", "network")), (64, ("network",))):
+            ts = ti.random_mps(n_sites, 2, chi, seed)
+            c = n_sites // 2
+            for mv in forms:
+                one(ts, c - 100, 80, c + 20, 80, {"chain": "open", "n_sites": n_sites, "chi": chi,
+                                                  "A": [c - 100, c - 20], "B": [c + 20, c + 100]}, "fp64", mv)
+        for chi in (8, 12, 16, 32):
             ts = ti.random_mps_periodic(200, 2, chi, seed + chi)
-            one(ts, 10, 40, 60, 40, {"chain": "ring", "n_sites": 200, "chi": chi, "A": [10, 50], "B": [60, 100],
-                                     "outer_sites": 110}, "fp64")
+            forms = ("factors", "network") if chi == 8 else ("network",)
+            for mv in forms:
+                one(ts, 10, 40, 60, 40, {"chain": "ring", "n_sites": 200, "chi": chi, "A": [10, 50],
+                                         "B": [60, 100], "outer_sites": 110}, "fp64", mv)
     return {"workload": f"seeded random MPS of qubits: open chain of {n_sites} sites, adjacent blocks of "
-                        f"{list(lengths)} sites at its centre; rings of 200 sites",
+                        f"{list(lengths)} sites at its centre and 80-site blocks 40 sites apart; rings of 200 "
+                        f"sites",
             "n_probes": n_probes, "n_steps": n_steps, "rows": rows}
 
 

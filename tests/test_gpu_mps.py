@@ -326,3 +326,63 @@ def test_wide_bonds_agree_between_routes(dev):
     assert np.max(np.abs(a["alpha"] - b["alpha"])) <= 1e-7 * np.max(np.abs(a["alpha"]))
     assert np.max(np.abs(a["beta"] - b["beta"])) <= 1e-7 * np.max(np.abs(a["beta"]))
     assert a["logneg"] == pytest.approx(b["logneg"], rel=1e-7)
+
+
+# ------------------------------------------- the network form of the matvec
+def _compare_coefficients(g, o, K, m, tol=1e-10):
+    ascale, bscale = np.max(np.abs(o["alpha"])), np.max(np.abs(o["beta"][:, 1:]))
+    for k in range(K):
+        small = np.nonzero(o["beta"][k, 1:] < 1e-6 * bscale)[0]
+        jk = min(m, small[0] + 1) if small.size else m
+        assert np.max(np.abs(g["alpha"][k, :jk] - o["alpha"][k, :jk])) <= tol * ascale
+        assert np.max(np.abs(g["beta"][k, :jk + 1] - o["beta"][k, :jk + 1])) <= tol * bscale
+
+
+@pytest.mark.parametrize("geom", [("open",) + g for g in GEOMETRIES] + [("ring",) + g for g in PERIODIC])
+def test_network_matvec_matches_oracle(dev, geom):
+    # R_A, R_B and the traced sections' E_W, E_Z kept apart: the same
+    # operator, so the same coefficients as the oracle's explicit rho^{T_B}
+    # of its effective state on the same probes (reorthogonalised)
+    kind, L, chi, a0, LA, b0, LB = geom
+    ts = ti.random_mps(L, 2, chi, L + chi) if kind == "open" else ti.random_mps_periodic(L, 2, chi, 3 * L + chi)
+    K, m = 6, 14
+    print("network", geom, flush=True)
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=5, reorth=True, matvec="network")
+    assert g["mps_matvec"] == 2
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=5, reorth=True)
+    _compare_coefficients(g, o, K, m)
+    assert g["logneg"] == pytest.approx(o["logneg"], abs=1e-10 * max(abs(o["logneg"]), 1.0))
+
+
+@pytest.mark.parametrize("geom", [("open", 14, 4, 1, 5, 8, 6), ("ring", 12, 2, 2, 4, 7, 4)])
+def test_network_matvec_fp32(dev, geom):
+    kind, L, chi, a0, LA, b0, LB = geom
+    ts = ti.random_mps(L, 2, chi, L + chi) if kind == "open" else ti.random_mps_periodic(L, 2, chi, 3 * L + chi)
+    K, m = 8, 16
+    g = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, K, m, device=dev, seed=2, reorth=True, precision="fp32",
+                           matvec="network")
+    Pe = mps.effective_state(ts, a0, LA, b0, LB)
+    o = slq.slq_logneg_dims(Pe.reshape(-1), list(Pe.shape), [0], [1], K, m, seed=2, reorth=True)
+    assert abs(g["logneg"] - o["logneg"]) <= 1e-4 * max(abs(o["logneg"]), 1.0)
+    assert np.max(np.abs(g["alpha"][:, :4] - o["alpha"][:, :4])) <= 1e-5 * np.max(np.abs(o["alpha"]))
+
+
+def test_automatic_matvec_choice_and_agreement(dev):
+    # open chain, adjacent blocks: the factors (a tie, the factors' four
+    # products are the network's); a ring with a gap: the network (the
+    # factors' shared bond is chi^2 wide); a long gap at bond 16: the network.
+    # Where both run, both give the same coefficients on the same probes
+    cases = [("open", ti.random_mps(12, 2, 4, 16), (2, 4, 6, 4), 1),
+             ("ring", ti.random_mps_periodic(40, 2, 6, 9), (2, 10, 16, 10), 2),
+             ("open gap", ti.random_mps(60, 2, 16, 4), (10, 12, 30, 12), 2)]
+    for name, ts, (a0, LA, b0, LB), want in cases:
+        print("auto", name, flush=True)
+        r = {}
+        for mv in ("auto", "factors", "network"):
+            r[mv] = T.tnslq_logneg_mps(ts, a0, LA, b0, LB, 4, 10, device=dev, seed=8, reorth=True, matvec=mv)
+        assert r["auto"]["mps_matvec"] == want
+        assert r["factors"]["mps_matvec"] == 1 and r["network"]["mps_matvec"] == 2
+        a, b = r["factors"], r["network"]
+        assert np.max(np.abs(a["alpha"] - b["alpha"])) <= 1e-9 * np.max(np.abs(a["alpha"]))
+        assert a["logneg"] == pytest.approx(b["logneg"], abs=1e-9 * max(abs(a["logneg"]), 1.0))
