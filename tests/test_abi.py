@@ -332,6 +332,17 @@ def test_mps_rings_and_section_routes_without_device(L):
     assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 2)), 10, 80, 90, 80, q, C.byref(n)) == 0
     assert L.tnslq_mps_effective_state_size(C.byref(desc(phys, bond, 1)), 10, 80, 90, 80, q, C.byref(n)) == -1
     assert "transfer route" in T.tnslq_last_error()
+    # the matvec form: out-of-range values are argument errors; on a ring
+    # with a gap the network form needs far less room than the factors
+    ring = [np.zeros((8, 2, 8)) for _ in range(40)]
+    o = T.make_options(2, 4, precision="fp64")
+    for bad in (-1, 3):
+        m = T._mps_desc(ring)
+        m.matvec = bad
+        assert L.tnslq_workspace_bytes_mps(C.byref(m), 2, 10, 16, 10, C.byref(o), C.byref(n)) == -1
+    w_net = T.tnslq_workspace_bytes_mps(ring, 2, 10, 16, 10, o, matvec="network")
+    w_pq = T.tnslq_workspace_bytes_mps(ring, 2, 10, 16, 10, o, matvec="factors")
+    assert T.tnslq_workspace_bytes_mps(ring, 2, 10, 16, 10, o) == w_net < w_pq / 10
     # blocks whose compressed dimension is not a power of two and whose
     # probes do not fit one chunk (d_A' = d_B' = 13456 at bond 116, 2 probes)
     bond = [1] + [min(2 ** min(i, 60 - i), 116) for i in range(1, 60)] + [1]
