@@ -25,7 +25,7 @@ OUT = os.path.join(PKG, "libtnslq.so")
 PEAK_SRC = os.path.join(PKG, "peak", "peak.hip")
 PEAK_OUT = os.path.join(PKG, "libtnslq_peak.so")
 # sources built with the matrix instructions' VGPR form (see _compile)
-VGPR_FORM = ("peak.hip", "mps.hip", "entropy.hip")
+VGPR_FORM = ("peak.hip", "mps.hip", "entropy.hip", "mlp.hip")
 BUILD = os.path.join(PKG, "_build")
 
 ARCH = "gfx950"

@@ -42,10 +42,12 @@ def test_contraction_kernels_use_no_scratch(tmp_path):
 
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
 @pytest.mark.parametrize("src,instrs", [("mps.hip", ("v_mfma_f64_16x16x4", "v_mfma_f32_16x16x4")),
-                                        ("entropy.hip", ("v_mfma_f64_16x16x4",))])
+                                        ("entropy.hip", ("v_mfma_f64_16x16x4",)),
+                                        ("mlp.hip", ("v_mfma_f32_16x16x32_bf16",))])
 def test_matrix_loops_keep_accumulators_in_vgprs(tmp_path, src, instrs):
-    # the MPS complex products and the entropy's eight-vector column MAC carry
-    # matrix-instruction accumulators across their reduction loops; built as
+    # the MPS complex products, the entropy's eight-vector column MAC and the
+    # surrogate network's products carry matrix-instruction accumulators
+    # across their reduction loops; built as
     # the library builds them (VGPR form) they use no accumulation registers,
     # hence no copies between register files, and no scratch
     from paper_1809_01685_amd import build as b
