@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(256) k_zero_upper(double2 *__restrict__ A, int
 // lda/ldb/ldc are the stored row strides, sa/sb/sc the batch strides.  A
 // block of 256 threads (4 waves) computes a 64 x 64 tile, staging 64 x 16
 // slices of op(A) and 16 x 64 of op(B) through LDS (zeros outside the
-// matrices); each wave owns 32 x 32 outputs as 2 x 2 tiles of
+// matrices; each step's slices are loaded into registers during the
+// previous step's products); each wave owns 32 x 32 outputs as 2 x 2 tiles of
 // v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32), four real products per
 // complex one (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  Lane l supplies
 // A[l % 16][k] and B[k][l % 16] with k = l / 16 of each 4-term step; its
@@ -210,7 +211,11 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
             accr[i][j] = V{0, 0, 0, 0};
             acci[i][j] = V{0, 0, 0, 0};
         }
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    // The slices of k0 + TK are loaded into registers while the MFMAs of k0
+    // run (their global latency hidden behind the arithmetic), then stored
+    // to LDS between the two barriers of the next step.
+    C2 ra[4], rb[4];
+    auto load = [&](int k0) {
         // 1024 entries of each slice, four per thread
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -224,7 +229,7 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
                     v = OPA == 0 ? A[(int64_t)r * lda + k] : A[(int64_t)k * lda + r];
                     if (OPA == 2) v.y = -v.y;
                 }
-                As[kk][rr] = v;
+                ra[q] = v;
             }
             {
                 // op(B)[k0 + kk][c0 + cc]
@@ -235,10 +240,20 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
                     v = OPB == 0 ? B[(int64_t)k * ldb + c] : B[(int64_t)c * ldb + k];
                     if (OPB == 2) v.y = -v.y;
                 }
-                Bs[kk][cc] = v;
+                rb[q] = v;
             }
         }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = t + 256 * q;
+            As[OPA == 0 ? e % TK : e / TM][OPA == 0 ? e / TK : e % TM] = ra[q];
+            Bs[OPB == 0 ? e / TN : e % TK][OPB == 0 ? e % TN : e / TK] = rb[q];
+        }
         __syncthreads();
+        if (k0 + TK < kend) load(k0 + TK);
 #pragma unroll
         for (int k4 = 0; k4 < TK / 4; ++k4) {
             const int kk = 4 * k4 + fk;
