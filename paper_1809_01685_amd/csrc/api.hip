@@ -541,8 +541,8 @@ int plan_sec(const MpsPlan &mp, MpsSec &s, int route, bool absorb_right) {
     double ex = 0.0, tr = (double)s.x * s.x * s.x * s.x, f = 1.0;
     int64_t rows = s.x;
     bool fits = true;
-    s.smax = s.tmax = s.amax = 0;
-    s.tmax = s.x * s.x * s.x * s.x;
+    s.smax = s.amax = 0;
+    s.tmax = s.x * s.x * s.x * s.x;   // the sweep's start
     for (int i : s.sites) {
         const int64_t z = mp.bond[i], y = mp.bond[(size_t)i + 1], pi = mp.p[i];
         ex += (double)rows * z * pi * y;
