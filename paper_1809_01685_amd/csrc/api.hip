@@ -1450,7 +1450,8 @@ int explicit_matvec(Ctx &c, hipEvent_t e1, hipEvent_t e2) {
 // Q[b][m][v] (Sec. VI) applied to probes [k0, k0 + kcur) without forming psi:
 //   Z1[k][(u', m')][b']     = sum_a' conj P[a'][(u', m')] X[k][a'][b']
 //   Z2[k][(u', m')][(m, v)] = sum_b' Z1[k][(u', m')][b'] Q[b'][(m, v)]
-//   Z2p[k][(u', m)][(m', v)]  (axes m and m' exchanged)
+//   Z2p[k][(u', m)][(m', v)]  (axes m and m' exchanged: the product writes
+//                            its outputs there directly)
 //   Z3[k][a][(m', v)]       = sum_(u', m) P[a][(u', m)] Z2p[k][(u', m)][(m', v)]
 //   Y[k][a][b]              = sum_(m', v) Z3[k][a][(m', v)] conj Q[b][(m', v)]
 // i.e. Y[a][b] = sum_{a', b', e} psi[a][b'][e] conj psi[a'][b][e] X[a'][b'].
@@ -1461,10 +1462,17 @@ int mps_matvec(Ctx &c, const double2 *x, int kcur, hipEvent_t e1, hipEvent_t e2)
     const int kA = (int)f.kA, kB = (int)f.kB;
     auto chain = [&](auto *P, auto *Q, auto *X, auto *Z1, auto *Z2, auto *Z2p, auto *Z3, auto *Y) -> int {
         TNSLQ_HIP(launch_zgemm(2, 0, P, X, Z1, (int)UpM, kB, kA, UpM, kB, kB, kcur, 0, n, UpM * kB, c.st));
-        TNSLQ_HIP(launch_zgemm(0, 0, Z1, Q, Z2, (int)UpM, (int)MV, kB, kB, MV, MV, kcur, UpM * kB, 0, UpM * MV,
-                               c.st));
-        if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
-        TNSLQ_HIP(launch_swap01(Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, Z2p, c.st));
+        if (UpM <= 65535 * 64) {
+            // Z2 written straight into the exchanged order Z2p
+            TNSLQ_HIP(launch_zgemm_xc(Z1, Q, Z2p, (int)UpM, (int)MV, kB, kB, MV, kcur, UpM * kB, 0, UpM * MV, f.M,
+                                      f.V, c.st));
+            if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+        } else {
+            TNSLQ_HIP(launch_zgemm(0, 0, Z1, Q, Z2, (int)UpM, (int)MV, kB, kB, MV, MV, kcur, UpM * kB, 0, UpM * MV,
+                                   c.st));
+            if (e1) TNSLQ_HIP(hipEventRecord(e1, c.st));
+            TNSLQ_HIP(launch_swap01(Z2, (int64_t)kcur * f.Up, f.M, f.M, f.V, Z2p, c.st));
+        }
         TNSLQ_HIP(launch_zgemm(0, 0, P, Z2p, Z3, kA, (int)MV, (int)UpM, UpM, MV, MV, kcur, 0, UpM * MV, kA * MV,
                                c.st));
         // split s of the reduction at Y + s kc n (passA sums the splits)

@@ -181,12 +181,15 @@ template <> struct ZT<float> {
     static __device__ int row(int r, int fk) { return 4 * fk + r; }
 };
 
-template <int OPA, int OPB, typename T>
+// XC: output (r, c) with r = (r1, r2), r2 < xm, and c = (c1, c2), c2 < xv,
+// lands at ((r1 xm + c1) xm + r2) xv + c2 of its batch entry, i.e. the
+// result with r2 and c1 exchanged (ldc unused).
+template <int OPA, int OPB, typename T, bool XC = false>
 __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restrict__ A,
                                                const typename ZT<T>::C2 *__restrict__ B,
                                                typename ZT<T>::C2 *__restrict__ C, int M, int N, int K, int64_t lda,
                                                int64_t ldb, int64_t ldc, int64_t sa, int64_t sb, int64_t sc,
-                                               int sub, int ks, int64_t csk) {
+                                               int sub, int ks, int64_t csk, int64_t xm = 1, int64_t xv = 1) {
     using C2 = typename ZT<T>::C2;
     using V = typename ZT<T>::V;
     constexpr int TM = 64, TN = 64, TK = 16;
@@ -282,7 +285,14 @@ __global__ void __launch_bounds__(256) k_zgemm(const typename ZT<T>::C2 *__restr
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + wm * 32 + i * 16 + ZT<T>::row(q, fk), c = c0 + wn * 32 + j * 16 + fr;
                 if (r < M && c < N) {
-                    C2 &o = C[(int64_t)r * ldc + c];
+                    int64_t at;
+                    if constexpr (XC) {
+                        const int64_t r1 = r / xm, r2 = r - r1 * xm, c1 = c / xv, c2 = c - c1 * xv;
+                        at = ((r1 * xm + c1) * xm + r2) * xv + c2;
+                    } else {
+                        at = (int64_t)r * ldc + c;
+                    }
+                    C2 &o = C[at];
                     if (sub) {
                         o.x -= accr[i][j][q];
                         o.y -= acci[i][j][q];
@@ -563,6 +573,31 @@ hipError_t launch_zgemm(int opa, int opb, const double2 *A, const double2 *B, do
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
                         hipStream_t st, int sub, int ks, int64_t csk) {
     return zgemm_t<double>(opa, opb, A, B, C, M, N, K, lda, ldb, ldc, batch, sa, sb, sc, st, sub, ks, csk);
+}
+
+template <typename T>
+static hipError_t zgemm_xc_t(const typename ZT<T>::C2 *A, const typename ZT<T>::C2 *B, typename ZT<T>::C2 *C, int M,
+                             int N, int K, int64_t lda, int64_t ldb, int batch, int64_t sa, int64_t sb, int64_t sc,
+                             int64_t xm, int64_t xv, hipStream_t st) {
+    // one launch (rows within the grid's y limit), whole row and column groups
+    if (batch < 1 || batch > 65535 || (int64_t)M > 65535 * 64 || xm < 1 || xv < 1 || M % xm || N % xv)
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)batch), block(256);
+    hipLaunchKernelGGL((k_zgemm<0, 0, T, true>), grid, block, 0, st, A, B, C, M, N, K, lda, ldb, (int64_t)0, sa, sb,
+                       sc, 0, 1, (int64_t)0, xm, xv);
+    return hipGetLastError();
+}
+
+hipError_t launch_zgemm_xc(const double2 *A, const double2 *B, double2 *C, int M, int N, int K, int64_t lda,
+                           int64_t ldb, int batch, int64_t sa, int64_t sb, int64_t sc, int64_t xm, int64_t xv,
+                           hipStream_t st) {
+    return zgemm_xc_t<double>(A, B, C, M, N, K, lda, ldb, batch, sa, sb, sc, xm, xv, st);
+}
+
+hipError_t launch_zgemm_xc(const float2 *A, const float2 *B, float2 *C, int M, int N, int K, int64_t lda,
+                           int64_t ldb, int batch, int64_t sa, int64_t sb, int64_t sc, int64_t xm, int64_t xv,
+                           hipStream_t st) {
+    return zgemm_xc_t<float>(A, B, C, M, N, K, lda, ldb, batch, sa, sb, sc, xm, xv, st);
 }
 
 hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, float2 *C, int M, int N, int K,

@@ -266,6 +266,16 @@ hipError_t launch_zgemm(int opa, int opb, const float2 *A, const float2 *B, floa
                         int64_t lda, int64_t ldb, int64_t ldc, int batch, int64_t sa, int64_t sb, int64_t sc,
                         hipStream_t st, int sub = 0, int ks = 1, int64_t csk = 0);
 // out[i] = complex64(in[i]), n entries.
+// C[b] = A[b] B[b] (both as stored) written with an exchange: output (r, c),
+// r = (r1, r2) with r2 < xm and c = (c1, c2) with c2 < xv, lands at
+// ((r1 xm + c1) xm + r2) xv + c2 of C[b] (M a multiple of xm, N of xv,
+// M <= 65535 * 64 rows, batch <= 65535).
+hipError_t launch_zgemm_xc(const double2 *A, const double2 *B, double2 *C, int M, int N, int K, int64_t lda,
+                           int64_t ldb, int batch, int64_t sa, int64_t sb, int64_t sc, int64_t xm, int64_t xv,
+                           hipStream_t st);
+hipError_t launch_zgemm_xc(const float2 *A, const float2 *B, float2 *C, int M, int N, int K, int64_t lda,
+                           int64_t ldb, int batch, int64_t sa, int64_t sb, int64_t sc, int64_t xm, int64_t xv,
+                           hipStream_t st);
 hipError_t launch_to_c64(const double2 *in, int64_t n, float2 *out, hipStream_t st);
 // out[b][j][i][k] = (conj) in[b][i][j][k], nb tensors of shape (n0, n1, n2).
 hipError_t launch_swap01(const double2 *in, int64_t nb, int64_t n0, int64_t n1, int64_t n2, int conj, double2 *out,
