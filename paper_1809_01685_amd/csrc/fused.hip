@@ -75,6 +75,12 @@ __global__ void __launch_bounds__(FT, 1) k_pt_rows(const float4 *__restrict__ Pm
         for (int k = 0; k < KP; ++k)
 #pragma unroll
             for (int bp = 0; bp < DB; ++bp) x[r][k][bp] = X[(int64_t)k * N + ((int64_t)r * FT + t) * DB + bp];
+    // X complete before the slab loads start: the wait count the compiler
+    // places at the loop head merges the first entry with every later one,
+    // and with X's loads issued after the ring's it waits there for every
+    // load in flight (vmcnt(0)), draining the ring once per P slabs
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
     double yr[RPT][KP][DB], yi[RPT][KP][DB];
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
@@ -165,17 +171,24 @@ __global__ void __launch_bounds__(FT, 1) k_pt_rows(const float4 *__restrict__ Pm
 
     // slabs c0 .. c0 + P - 1 in flight, then each slab worked on and its
     // registers refilled with the slab P further on (the last slab again
-    // past the end of the range)
+    // past the end of the range, an L2 hit).  The compiler waits for every
+    // load in flight at the head of a loop whose iterations use registers
+    // loaded by the one before, so one iteration walks the ring UNR times:
+    // that drain comes once per UNR P slabs, and within an iteration each
+    // slab waits for its own loads only.  The refills are unconditional (a
+    // refill inside the tail test would make every head wait as well).
+    constexpr int UNR = 4;
 #pragma unroll
     for (int i = 0; i < P; ++i) load(c0 + i <= last ? c0 + i : last, ring[i]);
-    for (int64_t c = c0; c < c1; c += P) {
+    for (int64_t c = c0; c < c1; c += P * UNR) {
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-            if (c + i < c1) {
-                work(ring[i]);
-                load(c + i + P <= last ? c + i + P : last, ring[i]);
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int64_t cc = c + u * P + i;
+                if (cc < c1) work(ring[i]);
+                load(cc + P <= last ? cc + P : last, ring[i]);
             }
-        }
     }
     double2 *out = Ypart + (int64_t)blockIdx.x * KP * N;
 #pragma unroll
@@ -190,8 +203,8 @@ __global__ void __launch_bounds__(FT, 1) k_pt_rows(const float4 *__restrict__ Pm
 template <int DB, int KP, int FT, int RPT, int P>
 hipError_t launch_rows(const float2 *Pm, const double2 *X, int64_t dE, int nblk, double2 *Ypart, hipStream_t st) {
     const int64_t slabs = (dE + nblk - 1) / nblk;
-    hipLaunchKernelGGL((k_pt_rows<DB, KP, FT, RPT, P>), dim3(nblk), dim3(FT), 0, st, (const float4 *)Pm, X, dE, slabs,
-                       Ypart);
+    hipLaunchKernelGGL((k_pt_rows<DB, KP, FT, RPT, P>), dim3(nblk), dim3(FT), 0, st, (const float4 *)Pm, X, dE,
+                       slabs, Ypart);
     return hipGetLastError();
 }
 
