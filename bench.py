@@ -23,8 +23,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s per ±1% logneg estimate @26-qubit ρ_AB; ρ^T_B matvec GB/s or MFMA util"
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "fp32": 157.3, "fp64": 78.6}
-# real matrix-core products per complex product of each split
-MFMA_PER_ALGO = {"bf16x3": 3.0, "bf16x6": 6.0, "fp32": 1.0, "fp64": 1.0}
+# matrix-core products per real product of the algorithm (4 per complex
+# product): split BF16 takes 3 products of pieces per real product and 3 real
+# products per complex one (9 / 4); BF16X6 6 products of pieces, 4 real products
+MFMA_PER_ALGO = {"bf16x3": 2.25, "bf16x6": 6.0, "fp32": 1.0, "fp64": 1.0}
 # rocprofv3 counter summary of the split-BF16 contraction kernel at the default workload
 COUNTERS = os.path.join(ROOT, "profiles", "gemm_bf16x3_haar30_counters.txt")
 

@@ -183,8 +183,9 @@ typedef struct {
  *                for max_probes values, filled for the probes used) may be
  *                non-NULL among the optional outputs.
  *   chunk_probes 0: the lazy form on the matrix cores contracts as many
- *                probes per launch as fit a 16 GiB intermediary (Sec. V
- *                Eq. 4, intermediary (i): d_B x d_E d_B values per probe).
+ *                probes per launch as fit an intermediary of 2^31 values
+ *                (Sec. V Eq. 4, intermediary (i): d_B x d_E d_B values per
+ *                probe; 8, 12 or 16 bytes each in FP32, split BF16, FP64).
  *                > 0: at most this many probes per launch.  Either way the
  *                count is rounded up so that every chunk starts on a block of
  *                128 rows (k, b') (a multiple of 128 / d_B when d_B < 128) and

@@ -45,8 +45,9 @@ int fail(int code, const char *fmt, ...) {
 constexpr size_t ALIGN = 256;
 inline size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Largest intermediary (Ups) chunk the planner allows, in bytes.
-constexpr size_t UPS_BUDGET = size_t(16) << 30;
+// Largest intermediary (Ups) chunk the planner allows, in complex values
+// (16 GiB in FP32, 24 GiB in split BF16, 32 GiB in FP64 bricks).
+constexpr size_t UPS_BUDGET_VALUES = size_t(1) << 31;
 // Blocks per probe vector of the Lanczos kernels' two-stage reductions: at
 // least 4096 elements per block for long vectors, but enough blocks over the
 // K probes to fill the chip (about 2048) down to 128 elements per block.
@@ -211,8 +212,9 @@ int plan_rest(Plan &pl, int dtype, int prec, int K, int lanczos) {
     pl.nst1 = brick_stages(prec, pl.dA);
     pl.nst2 = brick_stages(prec, pl.dE * pl.dB);
     // intermediary per probe: d_B rows (b) by d_E d_B reduction terms (c, b')
-    const size_t ups_bytes_per = brick_bytes(prec, pl.dB, pl.dE * pl.dB);
-    pl.kc = (int)std::max<int64_t>(1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET / std::max<size_t>(ups_bytes_per, 1))));
+    const size_t ups_values_per = (size_t)brick_rows(pl.dB) * brick_stages(prec, pl.dE * pl.dB) * brick_epr(prec);
+    pl.kc = (int)std::max<int64_t>(
+        1, std::min<int64_t>(K, (int64_t)(UPS_BUDGET_VALUES / std::max<size_t>(ups_values_per, 1))));
     if (pl.kc_cap > 0) pl.kc = std::min(pl.kc, pl.kc_cap);
     // every chunk must start on a block of 128 rows (k, b') of Xt (lazy form:
     // d_B is then a power of two, so below 128 it divides 128; the factorised

@@ -1,7 +1,8 @@
 // Complex "NT" contraction C = A * B^T on the matrix cores (gfx950), for the
-// two contractions of Sec. V Eq. 4, in three arithmetics:
-//   BF16X3  operands split as hi + lo BF16 pieces, three real products per
-//           real product (hi*hi + hi*lo + lo*hi), v_mfma_f32_16x16x32_bf16,
+// two contractions of Sec. V Eq. 4, in these arithmetics:
+//   BF16X3  operands split as hi + lo BF16 pieces, three products of pieces
+//           per real product (hi*hi + hi*lo + lo*hi), three real products per
+//           complex product (see k_cgemm_bf16x3), v_mfma_f32_16x16x32_bf16,
 //           FP32 accumulation;
 //   BF16X6  hi + mid + lo pieces, the six products of pieces (p, q) with
 //           p + q < 3, FP32 accumulation restarted every 64 terms
@@ -11,7 +12,7 @@
 //           so that no FP32 running sum grows past 64 terms;
 //   FP64    v_mfma_f64_16x16x4_f64.
 //
-// Complex products use four real MFMA chains:
+// Complex products in BF16X6, FP32 and FP64 use four real MFMA chains:
 //   Re C += Re A Re B + (-Im A) Im B,   Im C += Re A Im B + Im A Re B,
 // the sign of Im A applied by flipping sign bits in registers.
 //
@@ -22,11 +23,12 @@
 // plane: 32 BF16, 16 FP32 or 8 FP64 reduction terms) in LDS: thread t copies
 // bytes [16 t, 16 t + 16) of every plane, so each load instruction of the
 // block reads 8 KiB of contiguous memory and lands at the same offset in LDS.
-// Double buffered, one barrier per step.  For BF16 (k_cgemm_bf16x3_ra) the
-// copy goes straight from global memory into LDS (global_load_lds_dwordx4:
-// 16 bytes per lane, each wave 1 KiB of every plane tile), and a wave reads
-// the next step's fragments while its matrix instructions run on the current
-// ones; see the comment at that kernel.  FP32 and FP64 stage through
+// Double buffered, one barrier per step.  For BF16 (k_cgemm_bf16x3,
+// k_cgemm_bf16x6) the copy goes straight from global memory into LDS
+// (global_load_lds_dwordx4: 16 bytes per lane, each wave 1 KiB of a plane
+// tile); k_cgemm_bf16x3 stages one pair of planes at a time and reads the next
+// pair's fragments while its matrix instructions run on the current ones; see
+// the comment at that kernel.  FP32 and FP64 stage through
 // registers: step i+1 (loaded one step earlier) is written to the other
 // buffer and step i+2 is loaded into registers.  Bricks store the four
 // 16-byte units of a row XOR-swizzled by ((row >> 1) ^ (row >> 2)) & 3, so
@@ -66,7 +68,7 @@ static_assert(BM * ROWB / 16 == NT, "one 16-byte unit of every brick plane per t
 
 template <int PREC> struct MP;
 template <> struct MP<TNSLQ_BF16X3> {
-    static constexpr int NPL = 4;        // re_hi, re_lo, im_hi, im_lo
+    static constexpr int NPL = 6;        // re_hi, re_lo, im_hi, im_lo, sum_hi, sum_lo
     using acc = f32x4;
 };
 template <> struct MP<TNSLQ_BF16X6> {
@@ -115,7 +117,7 @@ template <int PREC>
 __device__ __forceinline__ void stage_mfma(const uint4 (&fa)[TM][MP<PREC>::NPL], const uint4 (&fb)[TN][MP<PREC>::NPL],
                                            typename MP<PREC>::acc (&accr)[TM][TN],
                                            typename MP<PREC>::acc (&acci)[TM][TN]) {
-    static_assert(PREC != TNSLQ_BF16X3, "split BF16 runs in k_cgemm_bf16x3_ra");
+    static_assert(PREC != TNSLQ_BF16X3, "split BF16 runs in k_cgemm_bf16x3");
     if constexpr (PREC == TNSLQ_FP32) {
         uint4 nai[TM];
 #pragma unroll
@@ -352,71 +354,81 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16X3: the same block, waves and LDS stages as k_cgemm_nt_mfma, with the
-// next stage's fragments read while the current stage's matrix instructions
-// run.  B's fragments (32 registers per stage) are kept in two sets; A's are
-// read one row of tiles at a time, each into the registers that row has just
-// released, so that a wave waits for LDS only for A's last row.  The copy of
-// the stage after next goes into the LDS buffer the current stage has left,
-// right after the barrier that ends the previous stage; one barrier per
-// stage, after which every wave's copy has landed and every wave holds its
-// fragments.  The LDS buffers are four arrays (A and B of two stages), so
-// that the compiler can tell a fragment read of one buffer from a copy into
-// the other and does not make the read wait for the copy.  Reading ahead
-// keeps the matrix cores 70-77% busy on the 30-qubit contractions, 2-3
-// points more than reading each stage's fragments before its instructions;
-// the clock, held by the chip's power limit, gives back most of that.
-
-// the 24 matrix instructions of one row of tiles: A's fragment (re_hi,
-// re_lo, im_hi, im_lo) against the TN B fragments.  Each accumulator takes,
-// for the split terms (hi, hi), (hi, lo), (lo, hi) in turn, Re A Re B then
-// (-Im A) Im B (real part), or Re A Im B then Im A Re B (imaginary part).
-__device__ __forceinline__ void row_bf16x3(const uint4 (&fa)[4], const uint4 (&fb)[TN][4], f32x4 (&ar)[TN],
-                                           f32x4 (&ai)[TN]) {
-    const uint4 n0 = neg_bf16x8(fa[2]), n1 = neg_bf16x8(fa[3]);
-#pragma unroll
-    for (int term = 0; term < 3; ++term) {
-        const int p = term == 2 ? 1 : 0;
-        const int q = term == 1 ? 1 : 0;
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-            ar[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[p]), as_bf16x8(fb[b][q]), ar[b], 0, 0, 0);
-            ai[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[p]), as_bf16x8(fb[b][2 + q]), ai[b], 0, 0, 0);
-        }
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-            ar[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(p ? n1 : n0), as_bf16x8(fb[b][2 + q]), ar[b], 0,
-                                                            0, 0);
-            ai[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[2 + p]), as_bf16x8(fb[b][q]), ai[b], 0, 0, 0);
-        }
-    }
-}
-
+// BF16X3: three real products per complex product (Gauss's form),
+//   T1 = sum Re A Re B,  T2 = sum Im A Im B,  T3 = sum (Re A + Im A)(Re B + Im B),
+//   Re C = T1 - T2,      Im C = T3 - T1 - T2,
+// each real product split as hi*hi + hi*lo + lo*hi: 9 matrix instructions per
+// pair of 16 x 16 tiles and reduction step instead of 12.  The operands carry
+// Re + Im as a third pair of planes (operands.h), so a brick is three 16 KiB
+// pairs (re, im, sum; hi and lo of 128 rows each) in the order of the three
+// products.  Staging a whole brick of both operands twice would take 192 KiB
+// of LDS; the kernel stages instead one pair of planes of each operand per
+// "phase" (32 KiB), and the phases of a block's run of bricks are consecutive
+// 16 KiB pieces of its rows of A and of B.  Same block, waves and tiles as
+// k_cgemm_nt_mfma (128 x 128 outputs, 8 waves of 64 x 32); per phase a wave
+// issues 24 matrix instructions into the accumulators of that phase's product.
+// Pipeline over a ring of four LDS buffers (128 KiB): in phase ph a wave reads
+// phase ph + 1's fragments from its buffer into the second register set, the
+// block copies phase ph + 4 into the buffer phase ph has left (its fragments
+// are in registers), the matrix instructions run on phase ph's fragments,
+// and one barrier ends the phase once phase ph + 2 has landed (the copies of
+// ph + 3 and ph + 4 stay in flight).  The barrier is a bare s_barrier after
+// explicit wait counts: __syncthreads would add a fence that waits for every
+// copy in flight.  Buffers, register sets and accumulators are chosen at
+// compile time (the LDS buffers are eight arrays, so that the compiler tells a
+// fragment read of one buffer from a copy into another): the loop body is 12
+// phases (4 bricks), and a run whose phase count is not a multiple of 12
+// starts with the last 3, 6 or 9 phases of that body, so the loop itself has
+// no branch (a branch around each phase's instructions cost 8%).  Against the
+// four-product kernel on the 30-qubit contractions (launched alone: 256 / 262
+// ms against 286 / 287; chained as in a Lanczos step, sustained on one box:
+// 269 / 262 against 290 / 282): 7-10% rather than 25%, the rest taken by the
+// 1.5x bytes staged per step (with the copies left out the loop takes 189 ms)
+// and the power they cost under the chip's power limit.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 
-__global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3_ra(GemmDesc g) {
-    constexpr int NPL = 4;
-    constexpr int BRICKB = NPL * TILEB;   // one brick, all planes: 32 KiB
-    __shared__ __attribute__((aligned(16))) char ldsA0[BRICKB], ldsA1[BRICKB], ldsB0[BRICKB], ldsB1[BRICKB];
+constexpr int PHB = 2 * TILEB;    // one pair of planes of one operand: 16 KiB
+constexpr int X3_BODY = 12;       // phases per loop iteration: lcm(2 sets, 3 products, 4 buffers)
+
+template <int U, int END, typename F>
+__device__ __forceinline__ void unroll_from(F &f) {
+    if constexpr (U < END) {
+        f(std::integral_constant<int, U>{});
+        unroll_from<U + 1, END>(f);
+    }
+}
+
+__global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3(GemmDesc g) {
+    __shared__ __attribute__((aligned(16))) char lA0[PHB], lA1[PHB], lA2[PHB], lA3[PHB];
+    __shared__ __attribute__((aligned(16))) char lB0[PHB], lB1[PHB], lB2[PHB], lB3[PHB];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WAVES_N, wn = wid % WAVES_N;
     const TileAt tl = tile_of(g);
-    const int64_t sbeg = tl.sbeg, send = tl.send;
-
-    // thread t copies bytes [16 t, 16 t + 16) of every plane tile; each
-    // wave's load fills 1 KiB of LDS at the same offset.  Block-uniform
-    // bases (scalar registers) plus one per-lane offset.
+    // phases of this block's run of bricks (3 per brick)
+    const int64_t p0 = 3 * tl.sbeg, pend = 3 * tl.send, plast = pend - 1;
     const size_t blk = brick_block_bytes(TNSLQ_BF16X3, g.nst);
     const char *gA = (const char *)g.A + (size_t)(tl.i0 / BM) * blk;
     const char *gB = (const char *)g.B + (size_t)(tl.j0 / BN) * blk;
     const uint32_t toff = 16u * (uint32_t)tid;
     const int wofs = 1024 * __builtin_amdgcn_readfirstlane(wid);
-    auto dma = [&](int64_t st, int buf) __attribute__((always_inline)) {
-        const char *pa = gA + st * BRICKB, *pb = gB + st * BRICKB;
-        char *As = (buf ? ldsA1 : ldsA0) + wofs, *Bs = (buf ? ldsB1 : ldsB0) + wofs;
+    auto bufA = [&](auto bb) -> char * {
+        constexpr int B = decltype(bb)::value;
+        return B == 0 ? lA0 : (B == 1 ? lA1 : (B == 2 ? lA2 : lA3));
+    };
+    auto bufB = [&](auto bb) -> char * {
+        constexpr int B = decltype(bb)::value;
+        return B == 0 ? lB0 : (B == 1 ? lB1 : (B == 2 ? lB2 : lB3));
+    };
+    // copy phase ph (the last phase again past the end of the run) into
+    // buffer bb: thread t copies bytes [16 t, 16 t + 16) of both plane tiles
+    // of A and of B
+    auto dma = [&](int64_t ph, auto bb) __attribute__((always_inline)) {
+        const int64_t q = ph <= plast ? ph : plast;
+        const char *pa = gA + q * PHB, *pb = gB + q * PHB;
+        char *As = bufA(bb) + wofs, *Bs = bufB(bb) + wofs;
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) {
+        for (int p = 0; p < 2; ++p) {
             __builtin_amdgcn_global_load_lds((gbl_void_t *)(pa + p * TILEB + toff), (lds_void_t *)(As + p * TILEB), 16,
                                              0, 0);
             __builtin_amdgcn_global_load_lds((gbl_void_t *)(pb + p * TILEB + toff), (lds_void_t *)(Bs + p * TILEB), 16,
@@ -429,77 +441,99 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3_ra(GemmDesc g) {
     for (int x = 0; x < TM; ++x) oa[x] = loff(wm * TM * 16 + x * 16 + frow, fk);
 #pragma unroll
     for (int x = 0; x < TN; ++x) ob[x] = loff(wn * TN * 16 + x * 16 + frow, fk);
-    auto read_a = [&](int buf, int x, uint4 (&f)[NPL]) __attribute__((always_inline)) {
-        const char *As = (buf ? ldsA1 : ldsA0) + oa[x];
+    // fragments (hi, lo) of the wave's A and B tiles, two sets
+    uint4 fa[2][TM][2], fb[2][TN][2];
+    auto rd = [&](auto ss, auto bb) __attribute__((always_inline)) {
+        constexpr int S = decltype(ss)::value;
+        const char *As = bufA(bb), *Bs = bufB(bb);
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) f[p] = *(const uint4 *)(As + p * TILEB);
+        for (int x = 0; x < TM; ++x)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) fa[S][x][p] = *(const uint4 *)(As + p * TILEB + oa[x]);
+#pragma unroll
+        for (int x = 0; x < TN; ++x)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) fb[S][x][p] = *(const uint4 *)(Bs + p * TILEB + ob[x]);
     };
-    auto read_b = [&](int buf, uint4 (&f)[TN][NPL]) __attribute__((always_inline)) {
+    // T1, T2, T3
+    f32x4 t[3][TM][TN];
 #pragma unroll
-        for (int x = 0; x < TN; ++x) {
-            const char *Bs = (buf ? ldsB1 : ldsB0) + ob[x];
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
-            for (int p = 0; p < NPL; ++p) f[x][p] = *(const uint4 *)(Bs + p * TILEB);
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) t[q][a][b] = f32x4{0, 0, 0, 0};
+
+    // phase base + U of the loop body (U = 0 .. 11): fragments in set U % 2,
+    // operands in buffer U % 4, product U % 3
+    int64_t base = 0;
+    auto phase = [&](auto uu) __attribute__((always_inline)) {
+        constexpr int U = decltype(uu)::value;
+        constexpr int C = U % 2, Q = U % 3;
+        const int64_t ph = base + U;
+        rd(std::integral_constant<int, C ^ 1>{}, std::integral_constant<int, (U + 1) % 4>{});
+        __builtin_amdgcn_sched_barrier(0);
+        dma(ph + 4, std::integral_constant<int, U % 4>{});
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int term = 0; term < 3; ++term) {
+            const int p = term == 2 ? 1 : 0, q = term == 1 ? 1 : 0;
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    t[Q][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[C][a][p]), as_bf16x8(fb[C][b][q]),
+                                                                         t[Q][a][b], 0, 0, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0x0078);   // vmcnt(8): phase ph + 2 landed; lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
     };
+    // the run starts at body position U0 (0, 3, 6 or 9), so that it ends with
+    // a whole body: phases p0 .. p0 + 3 into buffers U0 .. U0 + 3 (mod 4),
+    // phase p0's fragments into set U0 % 2, then body positions U0 .. 11
+    auto start = [&](auto u0) __attribute__((always_inline)) {
+        constexpr int V = decltype(u0)::value;
+        dma(p0, std::integral_constant<int, V % 4>{});
+        dma(p0 + 1, std::integral_constant<int, (V + 1) % 4>{});
+        dma(p0 + 2, std::integral_constant<int, (V + 2) % 4>{});
+        dma(p0 + 3, std::integral_constant<int, (V + 3) % 4>{});
+        __builtin_amdgcn_s_waitcnt(0x0f7c);   // vmcnt(12): phase p0 landed
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        rd(std::integral_constant<int, V % 2>{}, std::integral_constant<int, V % 4>{});
+        __builtin_amdgcn_s_waitcnt(0x0078);   // vmcnt(8): phase p0 + 1 landed; lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        base = p0 - V;
+        unroll_from<V, X3_BODY>(phase);
+        base += X3_BODY;
+    };
+    const int u0 = (int)((X3_BODY - (pend - p0) % X3_BODY) % X3_BODY);
+    switch (u0) {
+        case 3: start(std::integral_constant<int, 3>{}); break;
+        case 6: start(std::integral_constant<int, 6>{}); break;
+        case 9: start(std::integral_constant<int, 9>{}); break;
+        default: start(std::integral_constant<int, 0>{}); break;
+    }
+    for (; base < pend; base += X3_BODY) unroll_from<0, X3_BODY>(phase);
 
     f32x4 accr[TM][TN], acci[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-            accr[a][b] = f32x4{0, 0, 0, 0};
-            acci[a][b] = f32x4{0, 0, 0, 0};
+            accr[a][b] = t[0][a][b] - t[1][a][b];
+            acci[a][b] = t[2][a][b] - t[0][a][b] - t[1][a][b];
         }
-    uint4 fa[2][TM][NPL], fb[2][TN][NPL];
-
-    // stages sbeg and sbeg + 1 into the two buffers, stage sbeg's fragments
-    // into registers
-    const int64_t last = send - 1;
-    dma(sbeg, 0);
-    dma(sbeg + 1 <= last ? sbeg + 1 : last, 1);
-    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
-    __syncthreads();
-    read_b(0, fb[0]);
-#pragma unroll
-    for (int x = 0; x < TM; ++x) read_a(0, x, fa[0][x]);
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): buffer 0 may be refilled
-    __syncthreads();
-
-    // stage st (its fragments in set C, its operands in buffer C): stage
-    // st + 1's fragments from buffer C ^ 1 into set C ^ 1, stage st + 2's
-    // operands into buffer C (the last stage again at the end of the run)
-    auto body = [&](auto cc, int64_t st) __attribute__((always_inline)) {
-        constexpr int C = decltype(cc)::value, N = C ^ 1;
-        read_b(N, fb[N]);
-        __builtin_amdgcn_sched_barrier(0);
-        dma(st + 2 <= last ? st + 2 : last, C);
-        __builtin_amdgcn_sched_barrier(0);
-        // A's row a of the next stage into the registers row a has just
-        // released
-#pragma unroll
-        for (int a = 0; a < TM; ++a) {
-            row_bf16x3(fa[C][a], fb[C], accr[a], acci[a]);
-            __builtin_amdgcn_sched_barrier(0);
-            read_a(N, a, fa[N][a]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) and lgkmcnt(0)
-        __syncthreads();
-    };
-    int64_t st = sbeg;
-    for (; st + 1 < send; st += 2) {
-        body(std::integral_constant<int, 0>{}, st);
-        body(std::integral_constant<int, 1>{}, st + 1);
-    }
-    if (st < send) body(std::integral_constant<int, 0>{}, st);
     store_tiles<TNSLQ_BF16X3, TM, TN>(g, tl.s, tl.i0 + wm * TM * 16, tl.j0 + wn * TN * 16, lane, accr, acci);
 }
 
-hipError_t launch_bf16x3_ra(const GemmDesc &g, hipStream_t st) {
+hipError_t launch_bf16x3(const GemmDesc &g, hipStream_t st) {
     const int64_t nblocks = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.S;
     if (nblocks < 1 || nblocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_cgemm_bf16x3_ra, dim3((unsigned)nblocks), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(k_cgemm_bf16x3, dim3((unsigned)nblocks), dim3(NT), 0, st, g);
     return hipGetLastError();
 }
 
@@ -650,7 +684,7 @@ hipError_t launch_bf16x6(const GemmDesc &g, hipStream_t st) {
 template <int PREC>
 hipError_t launch(const GemmDesc &g, hipStream_t st) {
     if constexpr (PREC == TNSLQ_BF16X3) {
-        return launch_bf16x3_ra(g, st);
+        return launch_bf16x3(g, st);
     } else {
         static bool attr_set = false;
         if (!attr_set) {

@@ -20,7 +20,11 @@ __host__ __device__ constexpr int pieces_of(int prec) {
 __host__ __device__ constexpr int piece_bytes(int prec) {
     return prec == TNSLQ_FP64 ? 8 : (prec == TNSLQ_FP32 ? 4 : 2);
 }
-__host__ __device__ constexpr int planes_of(int prec) { return 2 * pieces_of(prec); }
+// Planes per stored complex value: the pieces of the real part, then those of
+// the imaginary part; split BF16 (BF16X3) also stores the pieces of their sum
+// Re + Im, which its contraction needs for the three-product form of a complex
+// product (planes re_hi, re_lo, im_hi, im_lo, sum_hi, sum_lo).
+__host__ __device__ constexpr int planes_of(int prec) { return prec == TNSLQ_BF16X3 ? 6 : 2 * pieces_of(prec); }
 
 // ------------------------------------------------------------ BF16 helpers
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs; NaN stays NaN).
@@ -58,7 +62,8 @@ __device__ inline void split_bf16_d(double x, uint16_t *out) {
 }
 
 // Store one complex value (re, im) into plane arrays at element index `idx`.
-// `ps` is the plane stride in elements.  Accepts double inputs.
+// `ps` is the plane stride in elements.  Accepts double inputs.  BF16X3 also
+// stores the split of re + im (rounded once, from the inputs' precision).
 template <int PREC>
 __device__ inline void store_planes(void *base, int64_t ps, int64_t idx, double re, double im) {
     if constexpr (PREC == TNSLQ_FP64) {
@@ -79,6 +84,11 @@ __device__ inline void store_planes(void *base, int64_t ps, int64_t idx, double 
         split_bf16_d<NP>(im, h);
 #pragma unroll
         for (int q = 0; q < NP; ++q) p[(NP + q) * ps + idx] = h[q];
+        if constexpr (PREC == TNSLQ_BF16X3) {
+            split_bf16_d<NP>(re + im, h);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) p[(2 * NP + q) * ps + idx] = h[q];
+        }
     }
 }
 // Same for FP32 accumulator values (the first contraction's output).
@@ -102,20 +112,27 @@ __device__ inline void store_planes_f(void *base, int64_t ps, int64_t idx, float
         split_bf16<NP>(im, h);
 #pragma unroll
         for (int q = 0; q < NP; ++q) p[(NP + q) * ps + idx] = h[q];
+        if constexpr (PREC == TNSLQ_BF16X3) {
+            split_bf16<NP>(re + im, h);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) p[(2 * NP + q) * ps + idx] = h[q];
+        }
     }
 }
 
 // ------------------------------------------------------------ bricks
 // An R x Kr operand is cut into bricks of 128 rows by 64 bytes of the
 // reduction index (32 BF16, 16 FP32 or 8 FP64 terms) per plane; a brick holds
-// all planes of its piece of the matrix one after the other (8 KiB each), and
+// all planes of its piece of the matrix one after the other (8 KiB each, in
+// the order of planes_of), and
 // bricks run along the reduction index first, then over blocks of 128 rows.
 // Within a brick row the four 16-byte units are stored XOR-swizzled by
 // ((row >> 1) ^ (row >> 2)) & 3, the order in which the contraction kernel
 // keeps them in LDS.  Rows are padded to a multiple of 128 and the reduction
 // index to a whole brick; padding along the reduction index must hold zeros.
-// One brick is what the contraction kernel stages per reduction step, so its
-// loads are contiguous 8 KiB blocks.
+// One brick is what the contraction kernel stages per reduction step (split
+// BF16: one pair of planes at a time), so its loads are contiguous blocks of
+// 8 KiB or more.
 constexpr int BRICK_ROWS = 128;
 constexpr int BRICK_ROW_BYTES = 64;
 constexpr int BRICK_PLANE_BYTES = BRICK_ROWS * BRICK_ROW_BYTES;

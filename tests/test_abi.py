@@ -87,9 +87,10 @@ def test_chunk_cap_sets_the_intermediary_size(L):
     a30, b30 = list(range(4, 17)), list(range(17, 30))
     ws = {c: T.tnslq_workspace_bytes(T.TNSLQ_C64, 30, a30, b30,
                                      T.make_options(8, 10, precision="bf16x3", chunk_probes=c)) for c in (0, 1, 2, 8)}
-    ups = 8192 * 16 * 8192 * 8          # one probe's intermediary, split BF16 (8 B per complex value)
+    ups = 8192 * 16 * 8192 * 12         # one probe's intermediary, split BF16 (12 B per complex value:
+    #                                     re, im and re + im, hi and lo pieces each)
     ypart = 8192 * 8192 * 8             # and its FP32 partial result
-    assert ws[0] == ws[2]               # the 16 GiB budget holds two probes
+    assert ws[0] == ws[2]               # the budget of 2^31 values holds two probes
     assert ws[2] - ws[1] == ups + ypart and ws[8] == ws[0]
     # d_B = 64 < 128: a cap of 3 probes is rounded up to 4 (chunks start on
     # 128-row blocks), so caps 3 and 4 plan alike and 1 becomes 2

@@ -87,7 +87,7 @@ L30, A30, B30 = 30, list(range(4, 17)), list(range(17, 30))
 
 
 def test_haar30_whole_columns_in_four_chunks(dev):
-    # the benchmark's plan: 8 vectors, 2 per launch (the 16 GiB intermediary
+    # the benchmark's plan: 8 vectors, 2 per launch (the 2^31-value intermediary
     # budget), so 4 launches of each contraction; columns b spread over the
     # 128 x 128 output tiles, every row a and every vector
     import torch
