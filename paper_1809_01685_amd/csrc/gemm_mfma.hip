@@ -367,12 +367,14 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
 // 16 KiB pieces of its rows of A and of B.  Same block, waves and tiles as
 // k_cgemm_nt_mfma (128 x 128 outputs, 8 waves of 64 x 32); per phase a wave
 // issues 24 matrix instructions into the accumulators of that phase's product.
-// Pipeline over a ring of four LDS buffers (128 KiB): in phase ph a wave reads
-// phase ph + 1's fragments from its buffer into the second register set, the
-// block copies phase ph + 4 into the buffer phase ph has left (its fragments
-// are in registers), the matrix instructions run on phase ph's fragments,
-// and one barrier ends the phase once phase ph + 2 has landed (the copies of
-// ph + 3 and ph + 4 stay in flight).  The barrier is a bare s_barrier after
+// Pipeline over a ring of four LDS buffers (128 KiB): in phase ph the matrix
+// instructions run on phase ph's fragments while, issued between them, a wave
+// reads phase ph + 1's fragments from its buffer into the second register set
+// and the block copies phase ph + 4 into the buffer phase ph has left (its
+// fragments are in registers); one barrier ends the phase once phase ph + 2
+// has landed (the copies of ph + 3 and ph + 4 stay in flight).  Issuing the
+// reads and copies before the matrix instructions instead left the matrix
+// cores idle after every barrier: 254 / 270 ms per launch against 244 / 244.  The barrier is a bare s_barrier after
 // explicit wait counts: __syncthreads would add a fence that waits for every
 // copy in flight.  Buffers, register sets and accumulators are chosen at
 // compile time (the LDS buffers are eight arrays, so that the compiler tells a
@@ -380,11 +382,10 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
 // phases (4 bricks), and a run whose phase count is not a multiple of 12
 // starts with the last 3, 6 or 9 phases of that body, so the loop itself has
 // no branch (a branch around each phase's instructions cost 8%).  Against the
-// four-product kernel on the 30-qubit contractions (launched alone: 256 / 262
-// ms against 286 / 287; chained as in a Lanczos step, sustained on one box:
-// 269 / 262 against 290 / 282): 7-10% rather than 25%, the rest taken by the
-// 1.5x bytes staged per step (with the copies left out the loop takes 189 ms)
-// and the power they cost under the chip's power limit.
+// four-product kernel on the 30-qubit contractions, launched alone on one box:
+// 244 / 244 ms per launch against 283 / 282, 14% rather than 25%, the rest
+// taken by the 1.5x bytes staged per step (with the copies left out the loop
+// took 189 ms) and the power they cost under the chip's power limit.
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) const void gbl_void_t;
 
@@ -472,9 +473,7 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3(GemmDesc g) {
         constexpr int C = U % 2, Q = U % 3;
         const int64_t ph = base + U;
         rd(std::integral_constant<int, C ^ 1>{}, std::integral_constant<int, (U + 1) % 4>{});
-        __builtin_amdgcn_sched_barrier(0);
         dma(ph + 4, std::integral_constant<int, U % 4>{});
-        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int term = 0; term < 3; ++term) {
             const int p = term == 2 ? 1 : 0, q = term == 1 ? 1 : 0;
@@ -485,6 +484,21 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3(GemmDesc g) {
                     t[Q][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(fa[C][a][p]), as_bf16x8(fb[C][b][q]),
                                                                          t[Q][a][b], 0, 0, 0);
         }
+        // the matrix instructions start right after the barrier, the 12
+        // fragment reads and the 4 copies issued one between each pair
+        // (2 MFMA, then 12 x (LDS read, MFMA), 4 x (copy, MFMA), 6 MFMA)
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0x0078);   // vmcnt(8): phase ph + 2 landed; lgkmcnt(0)
         __builtin_amdgcn_s_barrier();
