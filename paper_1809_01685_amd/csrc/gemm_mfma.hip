@@ -541,7 +541,71 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_bf16x3(GemmDesc g) {
             accr[a][b] = t[0][a][b] - t[1][a][b];
             acci[a][b] = t[2][a][b] - t[0][a][b] - t[1][a][b];
         }
-    store_tiles<TNSLQ_BF16X3, TM, TN>(g, tl.s, tl.i0 + wm * TM * 16, tl.j0 + wn * TN * 16, lane, accr, acci);
+    if (g.out_mode != 0 || g.cnb_log2 < 3) {
+        store_tiles<TNSLQ_BF16X3, TM, TN>(g, tl.s, tl.i0 + wm * TM * 16, tl.j0 + wn * TN * 16, lane, accr, acci);
+        return;
+    }
+    // Output as bricks (the first contraction's intermediary), through LDS.
+    // Per element the MFMA layout gives a lane one column and scattered rows,
+    // so direct stores are 2-byte pieces (192 per lane; they cost 8% of the
+    // launch).  Instead, one pair of planes at a time (re, im, re + im; hi and
+    // lo) goes into LDS as [plane][row][column] and leaves in 16-byte units:
+    // 8 consecutive columns j are 8 consecutive reduction terms of one brick
+    // row when cnb >= 8.  Rows are taken in the order of their environment
+    // index i % cni, so that a wave writes consecutive brick rows.  Staging
+    // rows of 288 bytes (128 columns + 16 of padding) keep the 2-byte writes
+    // of a wave's 4 row groups in distinct banks; plane p's rows 32 m .. 32 m
+    // + 31 live in ring buffer 4 p + m (9 KiB of its 16).
+    __builtin_amdgcn_s_waitcnt(0x0070);   // every copy (the clamped ones past the end) landed
+    __syncthreads();
+    constexpr int SROW = 288;
+    auto sbase = [&](int pm) -> char * {
+        return pm == 0 ? lA0
+                       : (pm == 1 ? lA1
+                                  : (pm == 2 ? lA2
+                                             : (pm == 3 ? lA3 : (pm == 4 ? lB0 : (pm == 5 ? lB1 : (pm == 6 ? lB2 : lB3))))));
+    };
+    const int nB = g.cnb_log2, nE = g.cni_log2;
+    const int64_t cnb_mask = ((int64_t)1 << nB) - 1, cni_mask = ((int64_t)1 << nE) - 1;
+    const int G = nE < 7 ? (BM >> nE) : 1;   // rows of the tile per environment index
+    constexpr int64_t PS = brick_ps(TNSLQ_BF16X3);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+            const int il0 = wm * TM * 16 + a * 16;   // 32-row group (il0 >> 5) is uniform
+            char *s0 = sbase(il0 >> 5), *s1 = sbase(4 + (il0 >> 5));
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int il = il0 + 4 * fk + r, jl = wn * TN * 16 + b * 16 + frow;
+                    const float re = accr[a][b][r], im = acci[a][b][r];
+                    uint16_t h[2];
+                    split_bf16<2>(q == 0 ? re : (q == 1 ? im : re + im), h);
+                    const int off = (il & 31) * SROW + 2 * jl;
+                    *(uint16_t *)(s0 + off) = h[0];
+                    *(uint16_t *)(s1 + off) = h[1];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int R = tid + NT * x, ii = R >> 4;
+            const int il = (ii % G) * (BM / G) + ii / G, jl = 8 * (R & 15);
+            const int64_t i = tl.i0 + il, j = tl.j0 + jl;
+            if (i < g.M && j < g.N) {
+                const int64_t row = (j >> nB) * g.crs + (i >> nE);
+                const int64_t col = ((i & cni_mask) << nB) + (j & cnb_mask);
+                const int64_t idx = brick_index(TNSLQ_BF16X3, g.c_nst, row, col);
+                const int off = (il & 31) * SROW + 2 * jl;
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    *(uint4 *)((uint16_t *)g.C + idx + (2 * q + p) * PS) = *(const uint4 *)(sbase(4 * p + (il >> 5)) + off);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t launch_bf16x3(const GemmDesc &g, hipStream_t st) {
