@@ -50,6 +50,8 @@ PARTS = [
     (11, [0, 1, 2, 3, 4], [6, 7, 8, 9, 10]),
     (14, list(range(6)), list(range(8, 14))),
     (13, list(range(9)), [10, 11]),     # d_B d_E = 16: the first contraction splits along a'
+    (14, [0, 1, 2], [3, 4, 5]),         # d_B = 8, d_E = 256: the intermediary leaves the split
+                                        # contraction through LDS with one row per environment index
 ]
 
 
