@@ -80,7 +80,9 @@ enum { TNSLQ_C64 = 0, TNSLQ_C128 = 1 };
  *   FP64    complex FP64 products and sums.
  *   FP32    complex FP32 products, FP32 sums in blocks, blocks summed in FP64.
  *   BF16X3  each FP32 operand split as hi + lo (two BF16 values); products
- *           hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32 accumulation.
+ *           hi*hi + hi*lo + lo*hi on BF16 matrix cores with FP32 accumulation,
+ *           three real products per complex product (the operands also carry
+ *           the split of Re + Im, 12 bytes per complex value).
  *   BF16X6  hi + mid + lo split, six BF16 products per real product.        */
 enum { TNSLQ_FP64 = 0, TNSLQ_FP32 = 1, TNSLQ_BF16X3 = 2, TNSLQ_BF16X6 = 3 };
 
