@@ -374,9 +374,10 @@ __global__ void __launch_bounds__(NT, 1) k_cgemm_nt_mfma(GemmDesc g) {
 // fragments are in registers); one barrier ends the phase once phase ph + 2
 // has landed (the copies of ph + 3 and ph + 4 stay in flight).  Issuing the
 // reads and copies before the matrix instructions instead left the matrix
-// cores idle after every barrier: 254 / 270 ms per launch against 244 / 244.  The barrier is a bare s_barrier after
-// explicit wait counts: __syncthreads would add a fence that waits for every
-// copy in flight.  Buffers, register sets and accumulators are chosen at
+// cores idle after every barrier: 254 / 270 ms per launch against 244 / 244.
+// The barrier is a bare s_barrier after explicit wait counts: __syncthreads
+// would add a fence that waits for every copy in flight.  Buffers, register
+// sets and accumulators are chosen at
 // compile time (the LDS buffers are eight arrays, so that the compiler tells a
 // fragment read of one buffer from a copy into another): the loop body is 12
 // phases (4 bricks), and a run whose phase count is not a multiple of 12
