@@ -12,6 +12,11 @@
         50-step split-BF16 SLQ on the same probes, beside the +-1% stop of the
         exponential-fit rule, with the time of each.
 
+    python -m paper_1809_01685_amd.experiments rounding [--depth 8]
+        How far plain (not reorthogonalised) Lanczos moves with the matvec's
+        rounding: one 28-qubit brickwork state of the held-out set, the same 8
+        probes in split BF16 and in FP32, after 12 and after 50 steps.
+
     python -m paper_1809_01685_amd.experiments surrogate_latency [--model DIR]
         The learned stop's inference latency: the network on one feature row,
         and the whole decision inside the surrogate run on a 20-qubit state.
@@ -233,6 +238,31 @@ def run_heldout26(n_probes=8, n_steps=50, precision="bf16x3", seed=0, tol=0.01, 
         del psi
         torch.cuda.empty_cache()
     return {"probes": n_probes, "steps": n_steps, "precision": precision, "tol": tol, "rows": rows}
+
+
+def run_rounding(depth=8, seed=0, n_probes=8, steps=(12, 50), precisions=("bf16x3", "fp32")):
+    """The held-out brickwork state (28 qubits, A = 1-13, B = 14-26) through
+    the library in two precisions on the same probes, without
+    reorthogonalisation: the estimates agree while Lanczos keeps its basis
+    orthogonal and drift apart once it loses it (Algorithm 1 run as written)."""
+    import torch
+    import tnslq_inputs as ti
+    dev = torch.device("cuda:0")
+    L, a, b = 28, list(range(1, 14)), list(range(14, 27))
+    psi = ti.brickwork_state_torch(L, depth, seed, dev, torch.complex64)
+    rows = []
+    for m in steps:
+        for prec in precisions:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = tnslq_logneg(psi, L, a, b, n_probes, m, precision=prec, seed=seed, want_arrays=False)
+            t = time.perf_counter() - t0
+            rows.append({"steps": m, "precision": prec, "logneg": r["logneg"], "logneg_se": r["logneg_se"],
+                         "seconds": t})
+            print(f"[rounding] depth {depth}, {m} steps, {prec}: E = {r['logneg']:.6f} +- {r['logneg_se']:.4f} "
+                  f"({t:.1f} s)", file=sys.stderr, flush=True)
+    return {"workload": f"brick28_d{depth}: 28-qubit brickwork, A = 1-13, B = 14-26, {n_probes} probes, "
+                        "no reorthogonalisation", "rows": rows}
 
 
 def run_entropy30(n_steps=20, seed=0):
@@ -619,6 +649,8 @@ def main(argv=None):
     ml = sub.add_parser("mps_long")
     ml.add_argument("--chi", default="32,64,116")
     ml.add_argument("--lengths", default="20,100,400")
+    ro = sub.add_parser("rounding")
+    ro.add_argument("--depth", type=int, default=8)
     en = sub.add_parser("entropy30")
     en.add_argument("--steps", type=int, default=20)
     args = ap.parse_args(argv)
@@ -645,6 +677,8 @@ def main(argv=None):
         out = run_hbm_sweep(n_steps=args.steps, **kw)
     elif args.cmd == "entropy30":
         out = run_entropy30(n_steps=args.steps)
+    elif args.cmd == "rounding":
+        out = run_rounding(depth=args.depth)
     else:
         out = run_heldout26(models=[m for m in args.models.split(",") if m] or None)
     print(json.dumps(out))
